@@ -1,0 +1,96 @@
+"""Brute-force dense formulation for tiny networks (N <= 8) -- TEST INFRASTRUCTURE.
+
+A second, deliberately different way to evaluate the same model as
+``oracle.c``, used to pin it:
+
+* the delayed input of vertex j at step t is evaluated straight from the
+  definition, sum over k != j of w_kj * spd(V_k(t - tau_kj)) (Section 3.2,
+  Eq. izpsc, last term), reading a full spike-history matrix instead of an
+  event-driven inbox;
+* the refractory hold is expressed through the time since the last spike
+  (held while 1 <= t - t_last <= n_ref) rather than a countdown;
+* everything is pure-Python floats and ints, one loop per vertex.
+
+Philox4x32-10 (Salmon et al., SC'11) is re-implemented here in Python
+integers so the formulation is self-contained; both implementations are
+pinned by the published known-answer vectors.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Optional, Sequence
+
+M32 = 0xFFFFFFFF
+
+
+def philox4x32_10(ctr: Sequence[int], key: Sequence[int]) -> List[int]:
+    x0, x1, x2, x3 = (int(c) & M32 for c in ctr)
+    k0, k1 = int(key[0]) & M32, int(key[1]) & M32
+    for r in range(10):
+        if r:
+            k0 = (k0 + 0x9E3779B9) & M32
+            k1 = (k1 + 0xBB67AE85) & M32
+        p0 = 0xD2511F53 * x0
+        p1 = 0xCD9E8D57 * x2
+        x0, x1, x2, x3 = ((p1 >> 32) ^ x1 ^ k0) & M32, p1 & M32, ((p0 >> 32) ^ x3 ^ k1) & M32, p0 & M32
+    return [x0, x1, x2, x3]
+
+
+def gauss(a: int, b: int) -> float:
+    u1 = ((a >> 8) + 0.5) / 16777216.0
+    u2 = ((b >> 8) + 0.5) / 16777216.0
+    return math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2)
+
+
+def simulate(n: int, edges: Sequence, steps: int, *, dt: float = 0.1, tau: float = 20.0,
+             v_rest: float = 0.0, v_reset: float = 0.0, v_th: float = 1.0, n_ref: int = 20,
+             drive_thr: Optional[Sequence[int]] = None, drive_amp: float = 1.5,
+             i_ext: Optional[Sequence[float]] = None, sigma: float = 0.0, seed: int = 0,
+             v0: Optional[Sequence[float]] = None) -> Dict[str, list]:
+    """edges: iterable of (src, dst, weight, delay_steps)."""
+    assert n <= 8, "brute force is for tiny networks"
+    W = [[0.0] * n for _ in range(n)]
+    A = [[False] * n for _ in range(n)]
+    D = [[0] * n for _ in range(n)]
+    for (i, j, w, d) in edges:
+        assert i != j and not A[i][j]
+        A[i][j] = True
+        W[i][j] = float(w)
+        D[i][j] = int(d)
+    key = (seed & M32, (seed >> 32) & M32)
+    V = [float(v) for v in v0] if v0 is not None else [v_rest] * n
+    last = [None] * n
+    hist: List[List[int]] = []
+    rec_s, rec_v, rec_i = [], [], []
+    for t in range(steps):
+        s = [1 if V[j] >= v_th else 0 for j in range(n)]
+        hist.append(s)
+        rec_s.append(s)
+        rec_v.append(list(V))
+        I = []
+        for j in range(n):
+            tot = 0.0
+            for k in range(n):
+                if k == j or not A[k][j]:
+                    continue
+                tk = t - D[k][j]
+                if tk >= 0 and hist[tk][k]:
+                    tot += W[k][j]
+            I.append(tot)
+        rec_i.append(I)
+        newV = list(V)
+        for j in range(n):
+            if s[j]:
+                newV[j] = v_reset
+                last[j] = t
+                continue
+            if last[j] is not None and 1 <= t - last[j] <= n_ref:
+                newV[j] = v_reset
+                continue
+            r = philox4x32_10((j, t & M32, t >> 32, 0), key)
+            u = (float(i_ext[j]) if i_ext is not None else 0.0) + \
+                (drive_amp if (drive_thr is not None and r[0] < drive_thr[j]) else 0.0)
+            xi = gauss(r[1], r[2])
+            newV[j] = V[j] + (dt / tau) * (v_rest - V[j]) + I[j] + u + sigma * xi
+        V = newV
+    return {"raster": rec_s, "v": rec_v, "input": rec_i, "v_final": V}

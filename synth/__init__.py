@@ -1,0 +1,276 @@
+"""Seeded synthetic inputs for geometric-network simulations.
+
+This module is the only code shared by the GPU library and the CPU oracle.
+It decides *what is simulated*: vertex positions, which ordered pairs carry
+an edge, the (FP16-representable) edge weights, which vertices are driven or
+inhibitory, and the model constants.  It computes none of the simulated
+method itself (no delays, no dynamics, no delivery, no observation).
+
+Workloads (sizes follow the paper's framework, section "Standardized Tests"
+for the 2D/3D geometric placements, scaled to the sizes studied here):
+
+* ``config0``  256 vertices in a 1 mm x 1 mm square, ordered pair (i, j)
+  connected with probability 0.3 when closer than 150 um, weights
+  U[0.5, 1.5]*w0, 10 % of vertices Poisson-driven at 5 Hz, no noise.
+* ``config1``  65,536 vertices in a 1 mm cube, connection probability
+  p0*exp(-r/100 um) (about 100 in-edges per vertex), weights U[0.5,1.5]*w0/10,
+  Gaussian state noise sigma = 0.05 per step.
+* ``config2``  1,048,576 vertices in a cube scaled for the same density
+  (2.52 mm), same rule cut at 2 mm, 20 % inhibitory sources (negated weights).
+* ``config3``  an ensemble of 2D networks of config0 type whose sizes are
+  log-uniform in [64, 4096].
+* ``config4``  N = 1024 networks of config0 type with state noise
+  sigma = 0.05, observed through calcium.
+
+Vertices are numbered along a Morton (Z-order) curve of their position, so
+that consecutive indices are spatial neighbours (the paper likewise numbers
+vertices by position).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsynth.so")
+_lib = None
+
+# ----------------------------------------------------------------------------
+# Model constants shared by every workload (recorded once, used by both sides).
+# ----------------------------------------------------------------------------
+DT_MS = 0.1                 # time step
+V_UM_PER_MS = 100.0         # conduction speed 0.1 m/s
+TAU_MS = 20.0               # LIF membrane time constant
+V_REST = 0.0
+V_RESET = 0.0
+V_TH = 1.0
+N_REF = 20                  # 2 ms refractory period at dt = 0.1 ms
+DRIVE_RATE_HZ = 5.0
+DRIVE_AMP = 1.5             # one drive pulse lifts a resting vertex past threshold
+DRIVE_FRACTION = 0.1
+INHIB_FRACTION = 0.2
+NOISE_SIGMA = 0.05
+W0 = 0.05                   # weight scale (configs 0/3/4); configs 1/2 use W0/10
+TAU_C_MS = 500.0            # calcium removal time constant
+FRAME_NUM, FRAME_DEN = 3, 1000   # 30 Hz camera at dt = 0.1 ms: frame(t) = floor(3t/1000)
+
+C1_P0 = 0.100               # exp(-r/100um) amplitude giving ~100 in-edges in a 1 mm cube
+C2_P0 = 0.0715              # same for the 2.52 mm cube
+LAMBDA_UM = 100.0
+C2_RCUT_UM = 2000.0
+
+
+def build(force: bool = False) -> str:
+    """Compile the generator's C helper (gcc, OpenMP) in-tree."""
+    src = os.path.join(_HERE, "synth.c")
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+                               src, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        lib.syn_edges.restype = ctypes.c_void_p
+        lib.syn_edges.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_uint64]
+        lib.syn_edges_count.restype = ctypes.c_int64
+        lib.syn_edges_count.argtypes = [ctypes.c_void_p]
+        lib.syn_edges_copy.restype = None
+        lib.syn_edges_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        lib.syn_edges_free.restype = None
+        lib.syn_edges_free.argtypes = [ctypes.c_void_p]
+        _lib = lib
+    return _lib
+
+
+def config_seed(config: int, net: int = 0) -> int:
+    """Seed of network ``net`` of workload ``config``."""
+    return (0x9E3779B97F4A7C15 * (config + 1) + net) % (1 << 64)
+
+
+@dataclass
+class NetSpec:
+    """One network: geometry, edges and model constants (host arrays)."""
+    name: str
+    pos_um: np.ndarray                      # float64 [n, dims]
+    src: np.ndarray                         # int32 [E]
+    dst: np.ndarray                         # int32 [E]
+    weight: np.ndarray                      # float32 [E], exactly representable in FP16
+    delay_steps: Optional[np.ndarray] = None  # uint8 [E] explicit delays, else from geometry
+    dt_ms: float = DT_MS
+    v_um_per_ms: float = V_UM_PER_MS
+    tau_ms: float = TAU_MS
+    v_rest: float = V_REST
+    v_reset: float = V_RESET
+    v_th: float = V_TH
+    n_ref: int = N_REF
+    drive_rate_hz: Optional[np.ndarray] = None   # float32 [n]; 0 = not driven
+    drive_amp: float = DRIVE_AMP
+    i_ext: Optional[np.ndarray] = None           # float32 [n] constant input per step
+    noise_sigma: float = 0.0
+    seed: int = 0
+    v0: Optional[np.ndarray] = None              # float32 [n] initial state
+    tau_c_ms: float = TAU_C_MS
+    frame_num: int = FRAME_NUM
+    frame_den: int = FRAME_DEN
+    inhibitory: Optional[np.ndarray] = None      # bool [n] (informational)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.pos_um.shape[0])
+
+    @property
+    def dims(self) -> int:
+        return int(self.pos_um.shape[1])
+
+    @property
+    def n_edges(self) -> int:
+        return int(self.src.shape[0])
+
+
+def round_fp16(x: np.ndarray) -> np.ndarray:
+    """Round to the nearest FP16 value (ties to even), returned as float32."""
+    return np.asarray(x, dtype=np.float64).astype(np.float16).astype(np.float32)
+
+
+def morton_order(pos: np.ndarray, extent: np.ndarray) -> np.ndarray:
+    """Permutation sorting points along a Z-order curve."""
+    n, dims = pos.shape
+    bits = 21 if dims <= 3 else 16
+    q = np.clip((pos / np.asarray(extent, dtype=np.float64)) * (1 << bits), 0, (1 << bits) - 1).astype(np.uint64)
+    code = np.zeros(n, dtype=np.uint64)
+    for b in range(bits):
+        for k in range(dims):
+            code |= ((q[:, k] >> np.uint64(b)) & np.uint64(1)) << np.uint64(b * dims + k)
+    return np.argsort(code, kind="stable")
+
+
+def uniform_positions(n: int, extent, seed: int) -> np.ndarray:
+    extent = np.asarray(extent, dtype=np.float64)
+    rng = np.random.default_rng([seed & 0xFFFFFFFF, seed >> 32, 1])
+    pos = rng.random((n, extent.shape[0])) * extent
+    perm = morton_order(pos, extent)
+    return np.ascontiguousarray(pos[perm])
+
+
+def sample_edges(pos: np.ndarray, extent, kind: int, p0: float, lam: float, r_cut: float,
+                 cell_um: float, seed: int):
+    """Independent per-pair Bernoulli edges i->j (i != j) with a distance rule.
+
+    kind 0: p = p0 within r_cut; kind 1: p = p0*exp(-r/lam) within r_cut.
+    Returns (src, dst) int32 arrays sorted by (dst, src).
+    """
+    lib = _load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    n, dims = pos.shape
+    ext = np.zeros(3, dtype=np.float64)
+    ext[:dims] = np.asarray(extent, dtype=np.float64)
+    h = lib.syn_edges(n, dims, pos.ctypes.data, ext.ctypes.data, kind, p0, lam,
+                      r_cut if math.isfinite(r_cut) else 1e308, cell_um, seed)
+    if not h:
+        raise RuntimeError("syn_edges failed")
+    try:
+        m = lib.syn_edges_count(h)
+        src = np.empty(m, dtype=np.int32)
+        dst = np.empty(m, dtype=np.int32)
+        lib.syn_edges_copy(h, src.ctypes.data, dst.ctypes.data)
+    finally:
+        lib.syn_edges_free(h)
+    key = dst.astype(np.int64) * n + src
+    order = np.argsort(key, kind="stable")
+    return np.ascontiguousarray(src[order]), np.ascontiguousarray(dst[order])
+
+
+def _subset(n: int, frac: float, seed: int, tag: int) -> np.ndarray:
+    rng = np.random.default_rng([seed & 0xFFFFFFFF, seed >> 32, tag])
+    k = int(round(frac * n))
+    mask = np.zeros(n, dtype=bool)
+    mask[rng.permutation(n)[:k]] = True
+    return mask
+
+
+def _weights(m: int, scale: float, seed: int) -> np.ndarray:
+    rng = np.random.default_rng([seed & 0xFFFFFFFF, seed >> 32, 7])
+    return round_fp16((0.5 + rng.random(m)) * scale)
+
+
+def config0_like(n: int, seed: int, name: str = "config0", w0: float = W0) -> NetSpec:
+    """2D square 1 mm, p = 0.3 within 150 um, 10 % driven at 5 Hz, no noise."""
+    pos = uniform_positions(n, [1000.0, 1000.0], seed)
+    src, dst = sample_edges(pos, [1000.0, 1000.0], 0, 0.3, 1.0, 150.0, 150.0, seed ^ 0xE1)
+    w = _weights(src.shape[0], w0, seed)
+    driven = _subset(n, DRIVE_FRACTION, seed, 3)
+    rate = np.where(driven, DRIVE_RATE_HZ, 0.0).astype(np.float32)
+    return NetSpec(name=name, pos_um=pos, src=src, dst=dst, weight=w,
+                   drive_rate_hz=rate, seed=seed, noise_sigma=0.0,
+                   meta={"extent_um": [1000.0, 1000.0], "driven": driven})
+
+
+def config0(seed: Optional[int] = None) -> NetSpec:
+    return config0_like(256, config_seed(0) if seed is None else seed, "config0")
+
+
+def config1(seed: Optional[int] = None, n: int = 65536) -> NetSpec:
+    """3D cube of 1 mm at n = 65,536 (smaller n keeps the density)."""
+    seed = config_seed(1) if seed is None else seed
+    side = 1000.0 * (n / 65536.0) ** (1.0 / 3.0)
+    ext = [side] * 3
+    pos = uniform_positions(n, ext, seed)
+    src, dst = sample_edges(pos, ext, 1, C1_P0, LAMBDA_UM, float("inf"), LAMBDA_UM, seed ^ 0xE1)
+    w = _weights(src.shape[0], W0 / 10.0, seed)
+    return NetSpec(name="config1" if n == 65536 else "config1_n%d" % n, pos_um=pos, src=src, dst=dst,
+                   weight=w, seed=seed, noise_sigma=NOISE_SIGMA, meta={"extent_um": ext})
+
+
+def config2(seed: Optional[int] = None, n: int = 1 << 20) -> NetSpec:
+    """Constant-density cube (2.52 mm at n = 2^20), cut at 2 mm, 20 % inhibitory."""
+    seed = config_seed(2) if seed is None else seed
+    side = 1000.0 * (n / 65536.0) ** (1.0 / 3.0)
+    ext = [side] * 3
+    pos = uniform_positions(n, ext, seed)
+    src, dst = sample_edges(pos, ext, 1, C2_P0, LAMBDA_UM, C2_RCUT_UM, LAMBDA_UM, seed ^ 0xE1)
+    w = _weights(src.shape[0], W0 / 10.0, seed)
+    inh = _subset(n, INHIB_FRACTION, seed, 5)
+    w = np.where(inh[src], -w, w).astype(np.float32)
+    return NetSpec(name="config2" if n == (1 << 20) else "config2_n%d" % n, pos_um=pos, src=src, dst=dst,
+                   weight=w, seed=seed, noise_sigma=NOISE_SIGMA, inhibitory=inh,
+                   meta={"extent_um": ext})
+
+
+def config3_sizes(n_nets: int = 512, seed: Optional[int] = None) -> List[int]:
+    seed = config_seed(3) if seed is None else seed
+    rng = np.random.default_rng([seed & 0xFFFFFFFF, seed >> 32, 11])
+    return [int(round(math.exp(x))) for x in rng.uniform(math.log(64), math.log(4096), n_nets)]
+
+
+def config3(n_nets: int = 512, sizes: Optional[List[int]] = None) -> List[NetSpec]:
+    sizes = config3_sizes(n_nets) if sizes is None else sizes
+    return [config0_like(nm, config_seed(3, m + 1), "config3_net%d" % m) for m, nm in enumerate(sizes)]
+
+
+def config4_net(m: int, noise_sigma: float = NOISE_SIGMA) -> NetSpec:
+    """N = 1024 network built like config0, with state noise so that
+    undriven vertices fire (without it they stay silent and no edge into them
+    is observable)."""
+    spec = config0_like(1024, config_seed(4, m), "config4_net%d" % m)
+    spec.noise_sigma = noise_sigma
+    return spec
+
+
+def in_degree(spec: NetSpec) -> np.ndarray:
+    return np.bincount(spec.dst, minlength=spec.n)
