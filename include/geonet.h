@@ -1,0 +1,219 @@
+/*
+ * geonet: fixed-step simulation of dynamic geometric networks on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Model (Buibas & Silva, "A framework for simulating and estimating the
+ * state and functional topology of complex dynamic geometric networks"):
+ *   - every vertex j has a fixed position x_j and a state y_j(t) advanced in
+ *     steps of dt by a transition function (Section 2, Eq. Htrans); here the
+ *     leaky integrate-and-fire vertex of Section 3.1, Euler-integrated;
+ *   - a vertex signals when V >= threshold (Section 3.2, Eq. spd) and the
+ *     signal reaches target j after tau_ij = |x_i - x_j| / s (Eq. delaydist),
+ *     weighted by omega_ij: the input of j at step t is the sum over in-edges
+ *     i -> j of omega_ij * spd(V_i(t - tau_ij)) (Eq. izpsc, last term);
+ *   - control u_j(t) per vertex (Section 2): a constant input plus Poisson
+ *     pulses; state noise as allowed by the framework (Section 1);
+ *   - observation (Section 3.3): calcium c + dt*(-c/tau_c + spd), averaged
+ *     over the steps of one camera frame, fluorescence n*c + b + N(0, g^2).
+ *
+ * Step semantics, for t = 0, 1, ... (all vertices in parallel):
+ *   s_j(t)   = [V_j(t) >= v_th]
+ *   I_j(t)   = sum over edges (i -> j) of w_ij * s_i(t - d_ij),  d_ij >= 1
+ *   if s_j(t):                 V_j(t+1) = v_reset, hold for n_ref steps
+ *   else if held:              V_j(t+1) = v_reset  (input discarded)
+ *   else: V_j(t+1) = V_j + (dt/tau)(v_rest - V_j) + I_j + u_j + sigma*xi_j
+ *   c_j(t+1) = c_j + dt*(-c_j/tau_c + s_j)
+ * with d_ij = max(1, ceil(|x_i - x_j| / (s*dt))) unless given explicitly.
+ * The held steps after a spike at step t0 are t0+1 .. t0+n_ref.
+ *
+ * Random numbers are Philox4x32-10 (Salmon et al., SC'11) with key = seed
+ * (low word first) and counter (j, t_lo, t_hi, 0) for the step of vertex j;
+ * output 0 decides the Poisson pulse (pulse iff x0 < floor(rate*dt*2^32)),
+ * outputs 1 and 2 give xi by Box-Muller on 24-bit uniforms ((x>>8)+0.5)/2^24.
+ * Observation noise uses counter (j, frame_lo, frame_hi, 1), outputs 0, 1.
+ * j is the vertex index inside its own network.
+ *
+ * Conventions for every entry point:
+ *   - all calls return net_status; nothing throws across this boundary;
+ *     net_last_error() gives the text of the last non-OK status of the
+ *     calling thread;
+ *   - "host" pointers are read during the call only (the library copies
+ *     them); "device" pointers are caller-owned device memory written
+ *     asynchronously on `stream`;
+ *   - `stream` is a hipStream_t (NULL = the default stream); every device
+ *     operation of a call is ordered on it and the call does not wait for it
+ *     except where stated;
+ *   - a device fault seen by a call is returned as NET_E_DEVICE and leaves
+ *     the handle unusable (later calls return NET_E_STATE).
+ */
+#ifndef GEONET_H
+#define GEONET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct net net_t;
+
+typedef enum {
+    NET_OK = 0,
+    NET_W_INEXACT = 1,      /* build succeeded, but some row's weight sums are not
+                               provably exact in FP32 (see net_build) */
+    NET_E_ARG = -1,         /* invalid argument */
+    NET_E_RANGE = -2,       /* a delay above 255 steps, or a size overflow */
+    NET_E_OOM = -3,         /* device allocation failed */
+    NET_E_DEVICE = -4,      /* HIP runtime or kernel error */
+    NET_E_STATE = -5,       /* handle unusable after an earlier device error */
+    NET_E_UNSUPPORTED = -6  /* request outside what this build supports */
+} net_status;
+
+/*
+ * One network (Section 2: vertex set with positions, directed weighted
+ * edges, delays from geometry, per-vertex parameters Theta_j and control).
+ * An array of these is an ensemble of independent networks.
+ */
+typedef struct {
+    int32_t n_nodes;              /* J, >= 1 */
+    int32_t dims;                 /* dimension of x_j: 1, 2 or 3 */
+    const double* pos_um;         /* host [n_nodes*dims] row-major positions (um) */
+    int64_t n_edges;              /* >= 0 */
+    const int32_t* src;           /* host [n_edges] source i of edge i -> j */
+    const int32_t* dst;           /* host [n_edges] target j; i != j, no duplicates */
+    const float* weight;          /* host [n_edges] omega_ij; rounded to FP16 (ties to
+                                     even) when built; sign selects excitation/inhibition */
+    const uint8_t* delay_steps;   /* host [n_edges] explicit delays (values 0 are taken
+                                     as 1), or NULL to compute them from positions */
+    double v_um_per_ms;           /* conduction speed s (Eq. delaydist) */
+    double dt_ms;                 /* time step; equal for all networks of an ensemble */
+    float tau_ms;                 /* membrane time constant */
+    float v_rest, v_reset, v_th;  /* rest (decay target), reset value, threshold */
+    int32_t n_ref;                /* held steps after a spike, 0..250 */
+    const float* drive_rate_hz;   /* host [n_nodes] Poisson pulse rate, or NULL */
+    float drive_amp;              /* pulse amplitude A added to V */
+    const float* i_ext;           /* host [n_nodes] constant input per step, or NULL */
+    float noise_sigma;            /* sigma of the per-step Gaussian increment */
+    uint64_t seed;                /* Philox key */
+    const float* v0;              /* host [n_nodes] V(0), or NULL for v_rest */
+    float tau_c_ms;               /* calcium removal time constant */
+    int32_t frame_num, frame_den; /* frame(t) = floor(t*num/den); equal across an ensemble */
+} net_desc;
+
+/* Build options; a zeroed struct (or NULL) selects the defaults. */
+typedef struct {
+    int32_t frame_capacity;       /* frames kept per vertex; 0 disables calcium */
+    int32_t block_threads;        /* delivery workgroup size override (0 = auto) */
+    int32_t blocks_per_cu;        /* delivery workgroups per CU override (0 = auto) */
+    int32_t flags;                /* NET_BUILD_* */
+} net_build_opts;
+
+#define NET_BUILD_NO_LDS_SUMMARY 1   /* keep the recent-spike summary in global memory */
+
+/*
+ * Optional per-step records for net_step_n (device pointers, may be NULL).
+ * Row k holds step t0 + k where t0 is the step counter before the call.
+ * Vertices are numbered across the ensemble in net_desc order.
+ */
+typedef struct {
+    uint64_t* raster;   /* [n_steps][raster_words]: bit (j % 64) of word j / 64 = s_j(t) */
+    float* v;           /* [n_steps][n_total]: V_j(t) at the start of step t */
+    float* input;       /* [n_steps][n_total]: delivered input I_j(t) */
+} net_record;
+
+typedef struct {
+    int64_t n_total;        /* vertices over all networks */
+    int64_t n_edges;        /* edges over all networks (as given) */
+    int64_t n_edges_stored; /* stored edge slots incl. padding */
+    int32_t n_nets;
+    int32_t max_delay;      /* largest delay in steps */
+    int64_t raster_words;   /* 64-bit words per raster row */
+    int64_t t;              /* steps taken so far */
+    int64_t frames_done;    /* completed camera frames */
+    int32_t exact;          /* 1 if every FP32 delivery sum is provably exact */
+    int32_t lds_summary;    /* 1 if the delivery kernel stages the summary in LDS */
+    int32_t deliver_blocks, deliver_threads;
+    int64_t device_bytes;   /* device memory held by the handle */
+} net_info_t;
+
+/*
+ * Device-memory allocator used for every allocation made by net_build (the
+ * Python binding registers the PyTorch caching allocator).  alloc returns
+ * NULL on failure.  Passing NULL for both restores hipMalloc/hipFree.
+ * Affects handles built afterwards; not thread-safe against concurrent
+ * net_build calls.
+ */
+net_status net_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx),
+                             void (*release)(void* ptr, void* stream, void* ctx), void* ctx);
+
+/*
+ * Build n_nets >= 1 networks into one handle (Section 2 definitions; delays
+ * by Eq. delaydist).  Copies all host inputs.  Computes delays in double
+ * precision (R3 rule above), rounds weights to FP16, forms the edge list
+ * sorted by target (CSR by target), uploads on `stream` and waits for the
+ * upload.  Returns NET_E_RANGE for a delay above 255 steps, NET_E_ARG for an
+ * out-of-range index, a self-loop, a duplicate edge or inconsistent
+ * dt/frame settings, NET_W_INEXACT (with a valid handle) when, for some
+ * target, (sum of |w|) / (smallest FP16 ulp among its weights) > 2^24.
+ * *out receives the handle on NET_OK or NET_W_INEXACT, else NULL.
+ */
+net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts* opts,
+                     void* stream, net_t** out);
+
+/*
+ * Advance every network by n_steps >= 0 steps (semantics above), enqueued on
+ * `stream` without host synchronisation.  rec may be NULL; its buffers must
+ * hold n_steps rows.
+ */
+net_status net_step_n(net_t* h, int64_t n_steps, const net_record* rec, void* stream);
+
+/* What net_observe returns. */
+enum {
+    NET_OBS_V = 1,        /* float [n_total]  current V */
+    NET_OBS_REF = 2,      /* int32 [n_total]  remaining held steps */
+    NET_OBS_CALCIUM = 3,  /* float [n_total]  current c */
+    NET_OBS_FRAMES = 4,   /* float [F][n_total] mean c of frames 0..F-1, F = out_bytes/(4*n_total) */
+    NET_OBS_FLUOR = 5     /* float [F][n_total] n*cbar + b + gamma*xi, params = net_fluor_params */
+};
+
+typedef struct {
+    float gain, offset, gamma;  /* n, b, gamma of the observation function (Section 3.3) */
+    int32_t pad;
+} net_fluor_params;
+
+/*
+ * Observation z_j = F_j(y_j) (Section 2, Eq. obsfun; Section 3.3).  Writes
+ * `what` into device buffer `out` of out_bytes on `stream`.  Frame requests
+ * need frame_capacity > 0 at build and F <= min(frames_done, capacity).
+ */
+net_status net_observe(net_t* h, int32_t what, const void* params, void* out, int64_t out_bytes,
+                       void* stream);
+
+/*
+ * Kernel timing for measurement.  After net_timing_begin(h, max_steps), each
+ * of the next max_steps steps taken by net_step_n records HIP events around
+ * its delivery and vertex-update launches (on the call's stream).
+ * net_timing_end waits for those events, returns the summed durations in
+ * milliseconds and the number of timed steps, and stops recording.  Timing
+ * never changes results.
+ */
+net_status net_timing_begin(net_t* h, int64_t max_steps);
+net_status net_timing_end(net_t* h, double* deliver_ms, double* update_ms, int64_t* steps);
+
+/* Sizes and counters of a handle (host struct). */
+net_status net_info(const net_t* h, net_info_t* out);
+
+/* First vertex index of every network: host int64 [n_nets + 1]. */
+net_status net_node_offsets(const net_t* h, int64_t* out);
+
+/* Release the handle and its device memory (waits for the handle's stream). */
+void net_free(net_t* h);
+
+/* Text of the last non-OK status of the calling thread ("" if none). */
+const char* net_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GEONET_H */

@@ -1,0 +1,97 @@
+"""ctypes declarations mirroring include/geonet.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgeonet.so")
+
+NET_OK = 0
+NET_W_INEXACT = 1
+NET_E_ARG = -1
+NET_E_RANGE = -2
+NET_E_OOM = -3
+NET_E_DEVICE = -4
+NET_E_STATE = -5
+NET_E_UNSUPPORTED = -6
+
+NET_BUILD_NO_LDS_SUMMARY = 1
+
+NET_OBS_V = 1
+NET_OBS_REF = 2
+NET_OBS_CALCIUM = 3
+NET_OBS_FRAMES = 4
+NET_OBS_FLUOR = 5
+
+_vp = C.c_void_p
+
+
+class NetDesc(C.Structure):
+    _fields_ = [
+        ("n_nodes", C.c_int32), ("dims", C.c_int32), ("pos_um", _vp), ("n_edges", C.c_int64),
+        ("src", _vp), ("dst", _vp), ("weight", _vp), ("delay_steps", _vp),
+        ("v_um_per_ms", C.c_double), ("dt_ms", C.c_double), ("tau_ms", C.c_float),
+        ("v_rest", C.c_float), ("v_reset", C.c_float), ("v_th", C.c_float), ("n_ref", C.c_int32),
+        ("drive_rate_hz", _vp), ("drive_amp", C.c_float), ("i_ext", _vp), ("noise_sigma", C.c_float),
+        ("seed", C.c_uint64), ("v0", _vp), ("tau_c_ms", C.c_float), ("frame_num", C.c_int32),
+        ("frame_den", C.c_int32),
+    ]
+
+
+class BuildOpts(C.Structure):
+    _fields_ = [("frame_capacity", C.c_int32), ("block_threads", C.c_int32),
+                ("blocks_per_cu", C.c_int32), ("flags", C.c_int32)]
+
+
+class Record(C.Structure):
+    _fields_ = [("raster", _vp), ("v", _vp), ("input", _vp)]
+
+
+class Info(C.Structure):
+    _fields_ = [
+        ("n_total", C.c_int64), ("n_edges", C.c_int64), ("n_edges_stored", C.c_int64),
+        ("n_nets", C.c_int32), ("max_delay", C.c_int32), ("raster_words", C.c_int64), ("t", C.c_int64),
+        ("frames_done", C.c_int64), ("exact", C.c_int32), ("lds_summary", C.c_int32),
+        ("deliver_blocks", C.c_int32), ("deliver_threads", C.c_int32), ("device_bytes", C.c_int64),
+    ]
+
+
+class FluorParams(C.Structure):
+    _fields_ = [("gain", C.c_float), ("offset", C.c_float), ("gamma", C.c_float), ("pad", C.c_int32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(_vp, C.c_size_t, _vp, _vp)
+RELEASE_FN = C.CFUNCTYPE(None, _vp, _vp, _vp)
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "net_set_allocator": (C.c_int, [ALLOC_FN, RELEASE_FN, _vp]),
+    "net_build": (C.c_int, [C.POINTER(NetDesc), C.c_int32, C.POINTER(BuildOpts), _vp, C.POINTER(_vp)]),
+    "net_step_n": (C.c_int, [_vp, C.c_int64, C.POINTER(Record), _vp]),
+    "net_observe": (C.c_int, [_vp, C.c_int32, _vp, _vp, C.c_int64, _vp]),
+    "net_info": (C.c_int, [_vp, C.POINTER(Info)]),
+    "net_node_offsets": (C.c_int, [_vp, _vp]),
+    "net_timing_begin": (C.c_int, [_vp, C.c_int64]),
+    "net_timing_end": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "net_free": (None, [_vp]),
+    "net_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load the in-tree HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libgeonet.so is not built; run paper_0908_3934_amd/build.py "
+                               "(or __graft_entry__.build()) first")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib

@@ -1,0 +1,367 @@
+// C-ABI entry points of the geonet library (declared in include/geonet.h).
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace geonet;
+
+struct net {
+    DeviceGraph g{};
+    LaunchConfig lc{};
+    std::vector<void*> blocks;
+    std::vector<int64_t> node_off;
+    int64_t n_edges = 0;
+    int64_t t = 0;
+    int64_t frames_done = 0;
+    int64_t acc_steps = 0;
+    int64_t device_bytes = 0;
+    int32_t frame_num = 0, frame_den = 1;
+    bool exact = true;
+    bool broken = false;
+    void* (*alloc)(size_t, void*, void*) = nullptr;
+    void (*release)(void*, void*, void*) = nullptr;
+    void* alloc_ctx = nullptr;
+    hipStream_t last_stream = nullptr;
+    // kernel timing: events [4 * step] = deliver start/end, update start/end
+    std::vector<hipEvent_t> tev;
+    int64_t t_cap = 0, t_used = 0;
+};
+
+namespace {
+
+thread_local std::string t_error;
+
+struct AllocatorState {
+    void* (*alloc)(size_t, void*, void*) = nullptr;
+    void (*release)(void*, void*, void*) = nullptr;
+    void* ctx = nullptr;
+};
+AllocatorState g_alloc;
+std::mutex g_alloc_mu;
+
+net_status fail(net_status st, const std::string& msg) {
+    t_error = msg;
+    return st;
+}
+
+net_status device_fail(net* h, hipError_t e, const char* where) {
+    if (h) h->broken = true;
+    return fail(NET_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+void* dev_alloc(net* h, size_t bytes, hipStream_t s) {
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) / 256 * 256;
+    void* p = nullptr;
+    if (h->alloc) {
+        p = h->alloc(bytes, s, h->alloc_ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (p) {
+        h->blocks.push_back(p);
+        h->device_bytes += static_cast<int64_t>(bytes);
+    }
+    return p;
+}
+
+void release_all(net* h) {
+    for (void* p : h->blocks) {
+        if (h->release)
+            h->release(p, h->last_stream, h->alloc_ctx);
+        else
+            (void)hipFree(p);
+    }
+    h->blocks.clear();
+}
+
+template <typename T>
+net_status upload(net* h, T** dst, const std::vector<T>& src, size_t count, hipStream_t s, const char* what) {
+    void* p = dev_alloc(h, count * sizeof(T), s);
+    if (!p) return fail(NET_E_OOM, std::string("net_build: device allocation failed for ") + what);
+    *dst = static_cast<T*>(p);
+    if (!src.empty()) {
+        hipError_t e = hipMemcpyAsync(p, src.data(), std::min(src.size(), count) * sizeof(T), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return device_fail(h, e, "net_build: upload");
+    }
+    return NET_OK;
+}
+
+template <typename T>
+net_status zeros(net* h, T** dst, size_t count, hipStream_t s, const char* what, int byte = 0) {
+    void* p = dev_alloc(h, count * sizeof(T), s);
+    if (!p) return fail(NET_E_OOM, std::string("net_build: device allocation failed for ") + what);
+    *dst = static_cast<T*>(p);
+    hipError_t e = hipMemsetAsync(p, byte, count * sizeof(T), s);
+    if (e != hipSuccess) return device_fail(h, e, "net_build: clear");
+    return NET_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* net_last_error(void) { return t_error.c_str(); }
+
+net_status net_set_allocator(void* (*alloc)(size_t, void*, void*), void (*release)(void*, void*, void*), void* ctx) {
+    if ((alloc == nullptr) != (release == nullptr))
+        return fail(NET_E_ARG, "net_set_allocator: give both functions or neither");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc.alloc = alloc;
+    g_alloc.release = release;
+    g_alloc.ctx = ctx;
+    return NET_OK;
+}
+
+net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts* opts, void* stream, net_t** out) {
+    if (!out) return fail(NET_E_ARG, "net_build: out is NULL");
+    *out = nullptr;
+    if (opts && (opts->frame_capacity < 0 || opts->block_threads < 0 || opts->blocks_per_cu < 0 ||
+                 (opts->block_threads && (opts->block_threads % 64 || opts->block_threads > 1024))))
+        return fail(NET_E_ARG, "net_build: invalid options");
+    HostGraph hg;
+    std::string err;
+    net_status st = build_host_graph(descs, n_nets, hg, err);
+    if (st != NET_OK) return fail(st, err);
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    net* h = new net();
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        h->alloc = g_alloc.alloc;
+        h->release = g_alloc.release;
+        h->alloc_ctx = g_alloc.ctx;
+    }
+    h->last_stream = s;
+    h->node_off = hg.node_off;
+    h->n_edges = hg.n_edges;
+    h->exact = hg.exact;
+    h->frame_num = hg.frame_num;
+    h->frame_den = hg.frame_den;
+    DeviceGraph& g = h->g;
+    g.n_total = hg.n_total;
+    g.n_pad = hg.n_pad;
+    g.e_slots = hg.e_slots;
+    g.n_chunks = hg.n_chunks;
+    g.n_nets = n_nets;
+    g.max_delay = hg.max_delay;
+    g.d_sum = hg.max_delay;
+    g.p0 = hg.params[0];
+    const int32_t frame_cap = opts ? opts->frame_capacity : 0;
+    g.frame_cap = frame_cap;
+
+    auto bail = [&](net_status code) {
+        (void)hipStreamSynchronize(s);
+        release_all(h);
+        delete h;
+        return code;
+    };
+    const size_t np = static_cast<size_t>(g.n_pad);
+    int32_t* src = nullptr;
+    uint16_t* w = nullptr;
+    uint8_t *d = nullptr, *rs = nullptr;
+    int32_t* c0 = nullptr;
+    NetParams* params = nullptr;
+    if ((st = upload(h, &src, hg.src, hg.e_slots, s, "sources")) != NET_OK) return bail(st);
+    if ((st = upload(h, &w, hg.w, hg.e_slots, s, "weights")) != NET_OK) return bail(st);
+    if ((st = upload(h, &d, hg.d, hg.e_slots, s, "delays")) != NET_OK) return bail(st);
+    if ((st = upload(h, &rs, hg.rowstart, hg.rowstart.size(), s, "row starts")) != NET_OK) return bail(st);
+    if ((st = upload(h, &c0, hg.chunk_row0, hg.chunk_row0.size(), s, "chunk rows")) != NET_OK) return bail(st);
+    if ((st = upload(h, &params, hg.params, hg.params.size(), s, "parameters")) != NET_OK) return bail(st);
+    g.src = src;
+    g.w = w;
+    g.d = d;
+    g.rowstart = rs;
+    g.chunk_row0 = c0;
+    g.params = params;
+    if (n_nets > 1) {
+        int32_t* nid = nullptr;
+        if ((st = upload(h, &nid, hg.net_id, np, s, "network ids")) != NET_OK) return bail(st);
+        g.net_id = nid;
+    }
+    if (hg.any_drive) {
+        uint32_t* thr = nullptr;
+        if ((st = upload(h, &thr, hg.drive_thr, np, s, "drive thresholds")) != NET_OK) return bail(st);
+        g.drive_thr = thr;
+    }
+    if (hg.any_iext) {
+        float* ie = nullptr;
+        if ((st = upload(h, &ie, hg.i_ext, np, s, "constant inputs")) != NET_OK) return bail(st);
+        g.i_ext = ie;
+    }
+    if ((st = upload(h, &g.V, hg.v0, np, s, "V")) != NET_OK) return bail(st);
+    if ((st = zeros(h, &g.age, np, s, "age", kAgeNever)) != NET_OK) return bail(st);
+    if ((st = zeros(h, &g.I, np, s, "input")) != NET_OK) return bail(st);
+    if ((st = zeros(h, &g.ring, np * kRingWords, s, "history ring")) != NET_OK) return bail(st);
+    if ((st = zeros(h, &g.summary, np / 32, s, "summary")) != NET_OK) return bail(st);
+    if (frame_cap > 0) {
+        if ((st = zeros(h, &g.calcium, np, s, "calcium")) != NET_OK) return bail(st);
+        if ((st = zeros(h, &g.frame_acc, np, s, "frame accumulator")) != NET_OK) return bail(st);
+        if ((st = zeros(h, &g.frames, np * static_cast<size_t>(frame_cap), s, "frames")) != NET_OK) return bail(st);
+    }
+    hipError_t e = configure_deliver(g, opts, h->lc);
+    if (e != hipSuccess) {
+        device_fail(h, e, "net_build: configure");
+        return bail(NET_E_DEVICE);
+    }
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        device_fail(h, e, "net_build: upload");
+        return bail(NET_E_DEVICE);
+    }
+    *out = h;
+    if (!h->exact) {
+        t_error = "net_build: some target's weights may not sum exactly in FP32";
+        return NET_W_INEXACT;
+    }
+    return NET_OK;
+}
+
+net_status net_step_n(net_t* h, int64_t n_steps, const net_record* rec, void* stream) {
+    if (!h) return fail(NET_E_ARG, "net_step_n: handle is NULL");
+    if (h->broken) return fail(NET_E_STATE, "net_step_n: handle unusable after a device error");
+    if (n_steps < 0) return fail(NET_E_ARG, "net_step_n: n_steps < 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    h->last_stream = s;
+    const bool observe = h->g.frame_cap > 0 && h->frame_num > 0;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        const int64_t t = h->t + k;
+        hipEvent_t* ev = (h->t_used < h->t_cap) ? &h->tev[4 * h->t_used++] : nullptr;
+        if (ev) (void)hipEventRecord(ev[0], s);
+        hipError_t e = launch_deliver(h->g, h->lc, t, s);
+        if (ev) (void)hipEventRecord(ev[1], s);
+        if (e != hipSuccess) return device_fail(h, e, "net_step_n: delivery launch");
+        int32_t flush = 0, steps = 0;
+        int64_t frame = 0;
+        if (observe) {
+            frame = t * h->frame_num / h->frame_den;
+            const int64_t next = (t + 1) * h->frame_num / h->frame_den;
+            h->acc_steps += 1;
+            if (next != frame) {
+                flush = 1;
+                steps = static_cast<int32_t>(h->acc_steps);
+                h->acc_steps = 0;
+                h->frames_done = std::max(h->frames_done, frame + 1);
+            }
+        }
+        if (ev) (void)hipEventRecord(ev[2], s);
+        e = launch_node_update(h->g, t, k, rec, flush, frame, steps, s);
+        if (ev) (void)hipEventRecord(ev[3], s);
+        if (e != hipSuccess) return device_fail(h, e, "net_step_n: update launch");
+    }
+    h->t += n_steps;
+    return NET_OK;
+}
+
+net_status net_observe(net_t* h, int32_t what, const void* params, void* out, int64_t out_bytes, void* stream) {
+    if (!h) return fail(NET_E_ARG, "net_observe: handle is NULL");
+    if (h->broken) return fail(NET_E_STATE, "net_observe: handle unusable after a device error");
+    if (!out) return fail(NET_E_ARG, "net_observe: out is NULL");
+    const int64_t n = h->g.n_total;
+    int64_t frames = 0;
+    switch (what) {
+        case NET_OBS_V:
+        case NET_OBS_REF:
+            if (out_bytes < 4 * n) return fail(NET_E_ARG, "net_observe: out_bytes too small");
+            break;
+        case NET_OBS_CALCIUM:
+            if (h->g.frame_cap <= 0) return fail(NET_E_UNSUPPORTED, "net_observe: built without observation");
+            if (out_bytes < 4 * n) return fail(NET_E_ARG, "net_observe: out_bytes too small");
+            break;
+        case NET_OBS_FRAMES:
+        case NET_OBS_FLUOR: {
+            if (h->g.frame_cap <= 0) return fail(NET_E_UNSUPPORTED, "net_observe: built without observation");
+            if (out_bytes % (4 * n) != 0) return fail(NET_E_ARG, "net_observe: out_bytes must be F * 4 * n_total");
+            frames = out_bytes / (4 * n);
+            const int64_t avail = std::min<int64_t>(h->frames_done, h->g.frame_cap);
+            if (frames > avail) return fail(NET_E_RANGE, "net_observe: more frames requested than recorded");
+            if (what == NET_OBS_FLUOR && !params) return fail(NET_E_ARG, "net_observe: fluorescence needs parameters");
+            break;
+        }
+        default:
+            return fail(NET_E_ARG, "net_observe: unknown observable");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    h->last_stream = s;
+    hipError_t e = launch_observe(h->g, what, static_cast<const net_fluor_params*>(params), out, frames, s);
+    if (e != hipSuccess) return device_fail(h, e, "net_observe");
+    return NET_OK;
+}
+
+net_status net_info(const net_t* h, net_info_t* out) {
+    if (!h || !out) return fail(NET_E_ARG, "net_info: NULL argument");
+    std::memset(out, 0, sizeof(*out));
+    out->n_total = h->g.n_total;
+    out->n_edges = h->n_edges;
+    out->n_edges_stored = h->g.e_slots;
+    out->n_nets = h->g.n_nets;
+    out->max_delay = h->g.max_delay;
+    out->raster_words = (h->g.n_total + 63) / 64;
+    out->t = h->t;
+    out->frames_done = h->frames_done;
+    out->exact = h->exact ? 1 : 0;
+    out->lds_summary = h->lc.lds_summary ? 1 : 0;
+    out->deliver_blocks = h->lc.deliver_blocks;
+    out->deliver_threads = h->lc.deliver_threads;
+    out->device_bytes = h->device_bytes;
+    return NET_OK;
+}
+
+net_status net_node_offsets(const net_t* h, int64_t* out) {
+    if (!h || !out) return fail(NET_E_ARG, "net_node_offsets: NULL argument");
+    std::memcpy(out, h->node_off.data(), h->node_off.size() * sizeof(int64_t));
+    return NET_OK;
+}
+
+net_status net_timing_begin(net_t* h, int64_t max_steps) {
+    if (!h) return fail(NET_E_ARG, "net_timing_begin: handle is NULL");
+    if (max_steps < 0 || max_steps > (int64_t(1) << 22)) return fail(NET_E_ARG, "net_timing_begin: bad max_steps");
+    for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
+    h->tev.assign(static_cast<size_t>(4 * max_steps), nullptr);
+    for (auto& e : h->tev) {
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) {
+            h->t_cap = 0;
+            return device_fail(h, r, "net_timing_begin");
+        }
+    }
+    h->t_cap = max_steps;
+    h->t_used = 0;
+    return NET_OK;
+}
+
+net_status net_timing_end(net_t* h, double* deliver_ms, double* update_ms, int64_t* steps) {
+    if (!h || !deliver_ms || !update_ms || !steps) return fail(NET_E_ARG, "net_timing_end: NULL argument");
+    double dsum = 0.0, usum = 0.0;
+    for (int64_t k = 0; k < h->t_used; ++k) {
+        hipEvent_t* ev = &h->tev[4 * k];
+        float a = 0.0f, b = 0.0f;
+        hipError_t r = hipEventSynchronize(ev[3]);
+        if (r == hipSuccess) r = hipEventElapsedTime(&a, ev[0], ev[1]);
+        if (r == hipSuccess) r = hipEventElapsedTime(&b, ev[2], ev[3]);
+        if (r != hipSuccess) return device_fail(h, r, "net_timing_end");
+        dsum += a;
+        usum += b;
+    }
+    *deliver_ms = dsum;
+    *update_ms = usum;
+    *steps = h->t_used;
+    for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
+    h->tev.clear();
+    h->t_cap = h->t_used = 0;
+    return NET_OK;
+}
+
+void net_free(net_t* h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->last_stream);
+    for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
+    release_all(h);
+    delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,293 @@
+// Host-side graph construction: delays from geometry, FP16 weights and the
+// CSR-by-target edge layout consumed by the delivery kernel.
+//
+// Layout of the stored edge list (one entry per "slot"):
+//   rows are targets j in ensemble order; a row holds the in-edges of j
+//   sorted by source; a target with no in-edge gets one placeholder slot
+//   (weight 0, source j, delay 1) so that every row owns at least one slot;
+//   the list is padded with placeholders to a multiple of 512 slots.
+//   rowstart bit s is set iff slot s is the first slot of its row, and
+//   chunk_row0[c] is the row of slot 512*c.  Row of slot s is then
+//   chunk_row0[s/512] + (number of rowstart bits in (512*(s/512), s]).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+#include "internal.h"
+
+namespace geonet {
+namespace {
+
+uint16_t to_fp16_bits(float f) {
+    _Float16 h = static_cast<_Float16>(f);   // IEEE round-to-nearest-even
+    uint16_t b;
+    std::memcpy(&b, &h, sizeof(b));
+    return b;
+}
+
+// log2 of the spacing of FP16 values around |h| (h != 0, finite).
+int fp16_ulp_log2(uint16_t h) {
+    int e = (h >> 10) & 0x1F;
+    return e == 0 ? -24 : e - 25;
+}
+
+bool fp16_finite(uint16_t h) { return ((h >> 10) & 0x1F) != 0x1F; }
+
+double fp16_abs(uint16_t h) {
+    _Float16 v;
+    uint16_t a = h & 0x7FFF;
+    std::memcpy(&v, &a, sizeof(a));
+    return static_cast<double>(v);
+}
+
+// Delay rule of Eq. delaydist in steps: max(1, ceil(|xi - xj| / (s*dt))).
+int32_t delay_from_geometry(const double* xi, const double* xj, int dims, double step_len) {
+    double acc = 0.0;
+    for (int k = 0; k < dims; ++k) {
+        const double diff = xi[k] - xj[k];
+        acc = acc + diff * diff;
+    }
+    const double steps = std::ceil(std::sqrt(acc) / step_len);
+    if (!(steps <= 255.0)) return -1;
+    return steps < 1.0 ? 1 : static_cast<int32_t>(steps);
+}
+
+uint32_t pulse_threshold(double rate_hz, double dt_ms) {
+    const double thr = std::floor(rate_hz * (dt_ms * 1e-3) * 4294967296.0);
+    if (!(thr > 0.0)) return 0u;
+    if (thr >= 4294967295.0) return 0xFFFFFFFFu;
+    return static_cast<uint32_t>(thr);
+}
+
+}  // namespace
+
+net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g, std::string& err) {
+    if (!descs || n_nets < 1) {
+        err = "net_build: descs must hold n_nets >= 1 networks";
+        return NET_E_ARG;
+    }
+    g.node_off.assign(n_nets + 1, 0);
+    int64_t e_total = 0;
+    for (int m = 0; m < n_nets; ++m) {
+        const net_desc& d = descs[m];
+        if (d.n_nodes < 1 || d.dims < 1 || d.dims > 3 || d.n_edges < 0) {
+            err = "net_build: network " + std::to_string(m) + " needs n_nodes >= 1, dims in 1..3, n_edges >= 0";
+            return NET_E_ARG;
+        }
+        if (d.n_edges > 0 && (!d.src || !d.dst || !d.weight)) {
+            err = "net_build: network " + std::to_string(m) + " has edges but no src/dst/weight";
+            return NET_E_ARG;
+        }
+        if (!d.delay_steps && d.n_edges > 0 && !d.pos_um) {
+            err = "net_build: network " + std::to_string(m) + " needs positions or explicit delays";
+            return NET_E_ARG;
+        }
+        if (!(d.dt_ms > 0.0) || !(d.tau_ms > 0.0) || d.n_ref < 0 || d.n_ref > 250) {
+            err = "net_build: network " + std::to_string(m) + " needs dt > 0, tau > 0, 0 <= n_ref <= 250";
+            return NET_E_ARG;
+        }
+        if (!d.delay_steps && d.n_edges > 0 && !(d.v_um_per_ms > 0.0)) {
+            err = "net_build: network " + std::to_string(m) + " needs a positive conduction speed";
+            return NET_E_ARG;
+        }
+        if (m > 0 && (d.dt_ms != descs[0].dt_ms || d.frame_num != descs[0].frame_num ||
+                      d.frame_den != descs[0].frame_den)) {
+            err = "net_build: all networks of an ensemble must share dt and the frame rule";
+            return NET_E_ARG;
+        }
+        g.node_off[m + 1] = g.node_off[m] + d.n_nodes;
+        e_total += d.n_edges;
+    }
+    g.n_total = g.node_off[n_nets];
+    if (g.n_total > (int64_t(1) << 28)) {
+        err = "net_build: more than 2^28 vertices";
+        return NET_E_RANGE;
+    }
+    g.n_pad = (g.n_total + kNodeAlign - 1) / kNodeAlign * kNodeAlign;
+    g.n_edges = e_total;
+    g.dt_ms = descs[0].dt_ms;
+    g.frame_num = descs[0].frame_num;
+    g.frame_den = descs[0].frame_den > 0 ? descs[0].frame_den : 1;
+    if (g.frame_num < 0) {
+        err = "net_build: frame_num must be >= 0";
+        return NET_E_ARG;
+    }
+
+    // In-degree per target row.
+    const int64_t N = g.n_total;
+    std::vector<int64_t> indeg(N + 1, 0);
+    for (int m = 0; m < n_nets; ++m) {
+        const net_desc& d = descs[m];
+        for (int64_t e = 0; e < d.n_edges; ++e) {
+            const int32_t i = d.src[e], j = d.dst[e];
+            if (i < 0 || i >= d.n_nodes || j < 0 || j >= d.n_nodes) {
+                err = "net_build: network " + std::to_string(m) + " edge " + std::to_string(e) +
+                      " has a vertex index out of range";
+                return NET_E_ARG;
+            }
+            if (i == j) {
+                err = "net_build: network " + std::to_string(m) + " edge " + std::to_string(e) +
+                      " is a self-loop (the input set excludes i == j)";
+                return NET_E_ARG;
+            }
+            indeg[g.node_off[m] + j]++;
+        }
+    }
+    // Slot offsets: every row gets max(indeg, 1) slots.
+    std::vector<int64_t> row_ptr(N + 1, 0);
+    for (int64_t r = 0; r < N; ++r) row_ptr[r + 1] = row_ptr[r] + std::max<int64_t>(indeg[r], 1);
+    const int64_t used = row_ptr[N];
+    g.e_slots = (used + kChunkEdges - 1) / kChunkEdges * kChunkEdges;
+    if (g.e_slots == 0) g.e_slots = kChunkEdges;
+    if (g.e_slots > (int64_t(1) << 31) - kChunkEdges) {
+        err = "net_build: more than 2^31 edge slots";
+        return NET_E_RANGE;
+    }
+    g.n_chunks = g.e_slots / kChunkEdges;
+    g.src.assign(g.e_slots, 0);
+    g.w.assign(g.e_slots, 0);
+    g.d.assign(g.e_slots, 1);
+    g.rowstart.assign(g.e_slots / 8, 0);
+
+    // Scatter edges into their rows (stable in input order).
+    std::vector<int64_t> fill(row_ptr.begin(), row_ptr.end() - 1);
+    int32_t max_delay = 1;
+    for (int m = 0; m < n_nets; ++m) {
+        const net_desc& d = descs[m];
+        const int64_t off = g.node_off[m];
+        const double step_len = d.v_um_per_ms * d.dt_ms;
+        for (int64_t e = 0; e < d.n_edges; ++e) {
+            const int32_t i = d.src[e], j = d.dst[e];
+            int32_t dl;
+            if (d.delay_steps) {
+                dl = d.delay_steps[e] < 1 ? 1 : d.delay_steps[e];
+            } else {
+                dl = delay_from_geometry(d.pos_um + int64_t(i) * d.dims, d.pos_um + int64_t(j) * d.dims, d.dims,
+                                         step_len);
+                if (dl < 0) {
+                    err = "net_build: network " + std::to_string(m) + " edge " + std::to_string(e) +
+                          " needs a delay above 255 steps";
+                    return NET_E_RANGE;
+                }
+            }
+            const uint16_t wb = to_fp16_bits(d.weight[e]);
+            if (!fp16_finite(wb)) {
+                err = "net_build: network " + std::to_string(m) + " edge " + std::to_string(e) +
+                      " has a weight outside the FP16 range";
+                return NET_E_RANGE;
+            }
+            max_delay = std::max(max_delay, dl);
+            const int64_t s = fill[off + j]++;
+            g.src[s] = static_cast<int32_t>(off + i);
+            g.w[s] = wb;
+            g.d[s] = static_cast<uint8_t>(dl);
+        }
+    }
+    g.max_delay = max_delay;
+    // Placeholders for empty rows, row-start bits, per-row order and exactness.
+    const double two24 = 16777216.0;
+    for (int64_t r = 0; r < N; ++r) {
+        const int64_t a = row_ptr[r], b = row_ptr[r + 1];
+        g.rowstart[a >> 3] |= uint8_t(1u << (a & 7));
+        if (indeg[r] == 0) {
+            g.src[a] = static_cast<int32_t>(r);
+            g.w[a] = 0;
+            g.d[a] = 1;
+            continue;
+        }
+        bool sorted = true;
+        for (int64_t s = a + 1; s < b; ++s)
+            if (g.src[s] <= g.src[s - 1]) {
+                sorted = false;
+                break;
+            }
+        if (!sorted) {
+            std::vector<int64_t> idx(b - a);
+            for (int64_t s = a; s < b; ++s) idx[s - a] = s;
+            std::sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return g.src[x] < g.src[y]; });
+            std::vector<int32_t> ts(b - a);
+            std::vector<uint16_t> tw(b - a);
+            std::vector<uint8_t> td(b - a);
+            for (int64_t k = 0; k < b - a; ++k) {
+                ts[k] = g.src[idx[k]];
+                tw[k] = g.w[idx[k]];
+                td[k] = g.d[idx[k]];
+            }
+            for (int64_t k = 0; k < b - a; ++k) {
+                g.src[a + k] = ts[k];
+                g.w[a + k] = tw[k];
+                g.d[a + k] = td[k];
+            }
+            for (int64_t s = a + 1; s < b; ++s)
+                if (g.src[s] == g.src[s - 1]) {
+                    err = "net_build: duplicate edge into vertex " + std::to_string(r);
+                    return NET_E_ARG;
+                }
+        }
+        // FP32 exactness: every partial sum of the row is a multiple of the
+        // smallest FP16 spacing q present and bounded by sum |w|.
+        double sum_abs = 0.0;
+        int ulp_min = 1 << 20;
+        for (int64_t s = a; s < b; ++s) {
+            if ((g.w[s] & 0x7FFF) == 0) continue;
+            sum_abs += fp16_abs(g.w[s]);
+            ulp_min = std::min(ulp_min, fp16_ulp_log2(g.w[s]));
+        }
+        if (sum_abs > 0.0 && sum_abs > std::ldexp(two24, ulp_min)) g.exact = false;
+    }
+    // Trailing padding slots belong to the last row; their weight is 0.
+    for (int64_t s = used; s < g.e_slots; ++s) {
+        g.src[s] = 0;
+        g.w[s] = 0;
+        g.d[s] = 1;
+    }
+    g.chunk_row0.assign(g.n_chunks, 0);
+    {
+        int64_t r = 0;
+        for (int64_t c = 0; c < g.n_chunks; ++c) {
+            const int64_t s = c * kChunkEdges;
+            while (r + 1 < N && row_ptr[r + 1] <= s) ++r;
+            g.chunk_row0[c] = static_cast<int32_t>(r);
+        }
+    }
+
+    // Per-vertex arrays and per-network constants.
+    g.v0.assign(g.n_pad, 0.0f);
+    g.drive_thr.assign(g.n_pad, 0u);
+    g.i_ext.assign(g.n_pad, 0.0f);
+    g.net_id.assign(g.n_pad, n_nets - 1);
+    g.params.resize(n_nets);
+    for (int m = 0; m < n_nets; ++m) {
+        const net_desc& d = descs[m];
+        NetParams& p = g.params[m];
+        p.decay = static_cast<float>(d.dt_ms / static_cast<double>(d.tau_ms));
+        p.v_rest = d.v_rest;
+        p.v_reset = d.v_reset;
+        p.v_th = d.v_th;
+        p.sigma = d.noise_sigma;
+        p.drive_amp = d.drive_amp;
+        p.dt = static_cast<float>(d.dt_ms);
+        p.inv_tau_c = d.tau_c_ms > 0.0f ? 1.0f / d.tau_c_ms : 0.0f;
+        p.n_ref = d.n_ref;
+        p.key_lo = static_cast<uint32_t>(d.seed);
+        p.key_hi = static_cast<uint32_t>(d.seed >> 32);
+        p.node_off = static_cast<int32_t>(g.node_off[m]);
+        for (int32_t j = 0; j < d.n_nodes; ++j) {
+            const int64_t k = g.node_off[m] + j;
+            g.v0[k] = d.v0 ? d.v0[j] : d.v_rest;
+            if (d.drive_rate_hz) {
+                g.drive_thr[k] = pulse_threshold(d.drive_rate_hz[j], d.dt_ms);
+                g.any_drive |= g.drive_thr[k] != 0u;
+            }
+            if (d.i_ext) {
+                g.i_ext[k] = d.i_ext[j];
+                g.any_iext |= d.i_ext[j] != 0.0f;
+            }
+            g.net_id[k] = m;
+        }
+    }
+    return NET_OK;
+}
+
+}  // namespace geonet

@@ -1,0 +1,103 @@
+// Internal declarations of the geonet library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/geonet.h"
+
+namespace geonet {
+
+// Edges are processed in chunks of 512 slots: 64 lanes x 8 consecutive edges.
+constexpr int kEdgesPerLane = 8;
+constexpr int kChunkEdges = 64 * kEdgesPerLane;
+constexpr int kRingSlots = 256;       // spike history per vertex, bits
+constexpr int kRingWords = kRingSlots / 32;
+constexpr int kNodeAlign = 256;       // vertex arrays padded to this many entries (one update workgroup)
+constexpr uint8_t kAgeNever = 255;    // "no spike within the last 254 steps"
+
+// Per-network constants used by the vertex kernels.
+struct NetParams {
+    float decay;        // dt / tau
+    float v_rest, v_reset, v_th;
+    float sigma, drive_amp;
+    float dt, inv_tau_c;
+    int32_t n_ref;
+    uint32_t key_lo, key_hi;
+    int32_t node_off;   // first vertex of the network in the ensemble numbering
+};
+
+// Host-side result of graph construction (before upload).
+struct HostGraph {
+    int64_t n_total = 0, n_pad = 0;
+    int64_t n_edges = 0;          // real edges
+    int64_t e_slots = 0;          // stored slots incl. empty-row placeholders and padding
+    int64_t n_chunks = 0;
+    int32_t max_delay = 1;
+    bool exact = true;
+    std::vector<int32_t> src;     // [e_slots]
+    std::vector<uint16_t> w;      // [e_slots] FP16 bits
+    std::vector<uint8_t> d;       // [e_slots]
+    std::vector<uint8_t> rowstart;  // [e_slots / 8] bit k of byte b: slot 8b+k opens a row
+    std::vector<int32_t> chunk_row0;  // [n_chunks] row of each chunk's first slot
+    std::vector<int64_t> node_off;    // [n_nets + 1]
+    std::vector<NetParams> params;    // [n_nets]
+    // per-vertex arrays [n_pad]
+    std::vector<float> v0;
+    std::vector<uint32_t> drive_thr;
+    std::vector<float> i_ext;
+    std::vector<int32_t> net_id;
+    bool any_drive = false, any_iext = false;
+    double dt_ms = 0.0;
+    int32_t frame_num = 0, frame_den = 1;
+};
+
+// Builds the CSR-by-target edge list and per-vertex arrays.  Returns a
+// status and fills `err` on failure.
+net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g, std::string& err);
+
+// Device-side handle contents.
+struct DeviceGraph {
+    int64_t n_total, n_pad, e_slots, n_chunks;
+    int32_t n_nets, max_delay, d_sum;
+    const int32_t* src;
+    const uint16_t* w;
+    const uint8_t* d;
+    const uint8_t* rowstart;
+    const int32_t* chunk_row0;
+    const NetParams* params;
+    const int32_t* net_id;        // null for one network
+    const uint32_t* drive_thr;    // null when no vertex is driven
+    const float* i_ext;           // null when all zero
+    float* V;
+    uint8_t* age;
+    float* I;
+    uint32_t* ring;               // [n_pad * kRingWords]
+    uint32_t* summary;            // [n_pad / 32]
+    float* calcium;               // null when observation is off
+    float* frame_acc;
+    float* frames;                // [frame_cap][n_pad]
+    int32_t frame_cap;
+    NetParams p0;                 // parameters of network 0 (fast path)
+};
+
+struct LaunchConfig {
+    int deliver_blocks = 0;
+    int deliver_threads = 0;
+    bool lds_summary = false;
+    size_t lds_bytes = 0;
+};
+
+// Kernel launchers (kernels.hip).
+hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t t, hipStream_t s);
+hipError_t launch_node_update(const DeviceGraph& g, int64_t t, int64_t rec_row, const net_record* rec,
+                              int32_t frame_flush, int64_t frame_index, int32_t frame_steps,
+                              hipStream_t s);
+hipError_t launch_observe(const DeviceGraph& g, int32_t what, const net_fluor_params* fp, void* out,
+                          int64_t n_frames, hipStream_t s);
+hipError_t configure_deliver(const DeviceGraph& g, const net_build_opts* opts, LaunchConfig& lc);
+
+}  // namespace geonet

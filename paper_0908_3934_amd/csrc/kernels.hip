@@ -1,0 +1,405 @@
+// Device kernels of the geonet library (gfx950, wave64).
+//
+//   deliver_kernel      I_j(t) = sum over in-edges i -> j of w_ij * s_i(t - d_ij)
+//                       (Section 3.2, Eq. izpsc last term) over the CSR-by-target
+//                       slot list; a one-bit-per-vertex "fired within the last
+//                       D steps" summary, staged in LDS, filters the edges whose
+//                       exact history bit must be fetched.
+//   node_update_kernel  spike test (Eq. spd), LIF Euler transition with the
+//                       refractory hold (Section 3.1), control and noise
+//                       (Philox4x32-10 + Box-Muller), spike-history ring,
+//                       recent-spike summary, calcium and camera frames
+//                       (Section 3.3).
+//   observe_kernel      fluorescence n*cbar + b + gamma*xi (Section 3.3) and
+//                       state read-outs.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace geonet {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as
+// easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplies with the
+// Weyl key schedule.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox(uint4 x, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t a = x.x, c = x.z;
+        const uint32_t hi_a = __umulhi(0xD2511F53u, a), lo_a = 0xD2511F53u * a;
+        const uint32_t hi_c = __umulhi(0xCD9E8D57u, c), lo_c = 0xCD9E8D57u * c;
+        x = make_uint4(hi_c ^ x.y ^ k0, lo_c, hi_a ^ x.w ^ k1, lo_a);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return x;
+}
+
+// Standard normal from two 32-bit draws (Box-Muller on 24-bit uniforms).
+__device__ __forceinline__ float gaussian(uint32_t a, uint32_t b) {
+    const float u1 = (static_cast<float>(a >> 8) + 0.5f) * 0x1p-24f;
+    const float u2 = (static_cast<float>(b >> 8) + 0.5f) * 0x1p-24f;
+    return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+}
+
+__device__ __forceinline__ float half_bits_to_float(uint32_t bits) {
+    return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(bits)));
+}
+
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint32_t wave_exclusive_sum(uint32_t v, int lane) {
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x - v;
+}
+
+struct DeliverArgs {
+    const int32_t* __restrict__ src;
+    const uint16_t* __restrict__ w;
+    const uint8_t* __restrict__ d;
+    const uint8_t* __restrict__ rowstart;
+    const int32_t* __restrict__ chunk_row0;
+    const uint32_t* __restrict__ summary;
+    const uint32_t* __restrict__ ring;
+    float* __restrict__ I;
+    int64_t n_chunks;
+    int32_t summary_vec4;   // summary size in 16-byte units
+    uint32_t t;             // step index modulo 2^32 (only t mod 256 matters)
+};
+
+// One wave handles 512 consecutive slots per iteration: lane L owns slots
+// 8L .. 8L+7 of the chunk, loaded as 2x16 B (sources), 16 B (weights) and
+// 8 B (delays).  Workgroups take contiguous chunk ranges; ranges of the
+// workgroups that share an XCD (blockIdx % 8) are adjacent, so the history
+// words they gather for neighbouring targets meet in that XCD's L2.
+template <bool kLdsSummary>
+__global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
+    extern __shared__ uint4 lds_summary4[];
+    const uint32_t* lds_summary = reinterpret_cast<const uint32_t*>(lds_summary4);
+    if (kLdsSummary) {
+        const uint4* g = reinterpret_cast<const uint4*>(a.summary);
+        for (int i = threadIdx.x; i < a.summary_vec4; i += blockDim.x) lds_summary4[i] = g[i];
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int nb = gridDim.x;
+    const int b = blockIdx.x;
+    const int lb = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+    const int64_t c_begin = static_cast<int64_t>(lb) * a.n_chunks / nb;
+    const int64_t c_end = static_cast<int64_t>(lb + 1) * a.n_chunks / nb;
+    const uint32_t t = a.t;
+
+    for (int64_t c = c_begin + wave; c < c_end; c += nwaves) {
+        const int64_t e0 = c * kChunkEdges + lane * kEdgesPerLane;
+        const int4 s_lo = *reinterpret_cast<const int4*>(a.src + e0);
+        const int4 s_hi = *reinterpret_cast<const int4*>(a.src + e0 + 4);
+        const uint4 wq = *reinterpret_cast<const uint4*>(a.w + e0);
+        const uint2 dq = *reinterpret_cast<const uint2*>(a.d + e0);
+        const uint32_t rs = a.rowstart[c * 64 + lane];
+        const uint32_t sv[8] = {(uint32_t)s_lo.x, (uint32_t)s_lo.y, (uint32_t)s_lo.z, (uint32_t)s_lo.w,
+                                (uint32_t)s_hi.x, (uint32_t)s_hi.y, (uint32_t)s_hi.z, (uint32_t)s_hi.w};
+        uint32_t slot[8], word[8];
+        uint32_t cand = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t s = sv[k];
+            const uint32_t sw = kLdsSummary ? lds_summary[s >> 5] : a.summary[s >> 5];
+            const uint32_t hit = (sw >> (s & 31)) & 1u;
+            const uint32_t dk = ((k < 4 ? dq.x : dq.y) >> (8 * (k & 3))) & 0xFFu;
+            slot[k] = (t - dk) & 0xFFu;
+            const uint32_t widx = hit ? s * kRingWords + (slot[k] >> 5) : 0u;
+            word[k] = a.ring[widx];
+            cand |= hit << k;
+        }
+        uint32_t fired = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) fired |= (((cand >> k) & (word[k] >> (slot[k] & 31))) & 1u) << k;
+        if (wave_ballot(fired != 0)) {
+            // Row of each slot from the row-start bits (position 0 of the
+            // chunk belongs to chunk_row0 whether or not it opens a row).
+            const uint32_t bits = lane == 0 ? (rs & ~1u) : rs;
+            const uint32_t before = wave_exclusive_sum(__popc(bits), lane);
+            const int32_t row0 = a.chunk_row0[c] + static_cast<int32_t>(before);
+            const uint32_t wv[4] = {wq.x, wq.y, wq.z, wq.w};
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if ((fired >> k) & 1u) {
+                    const int32_t row = row0 + __popc(bits & ((2u << k) - 1u));
+                    const float wf = half_bits_to_float((wv[k >> 1] >> (16 * (k & 1))) & 0xFFFFu);
+                    // All partial sums of a row are exact in FP32, so the
+                    // order of these additions does not change the result.
+                    unsafeAtomicAdd(a.I + row, wf);
+                }
+            }
+        }
+    }
+}
+
+struct NodeArgs {
+    float* __restrict__ V;
+    uint8_t* __restrict__ age;
+    float* __restrict__ I;
+    uint32_t* __restrict__ ring;
+    uint32_t* __restrict__ summary;
+    const NetParams* __restrict__ params;
+    const int32_t* __restrict__ net_id;
+    const uint32_t* __restrict__ drive_thr;
+    const float* __restrict__ i_ext;
+    float* __restrict__ calcium;
+    float* __restrict__ frame_acc;
+    float* __restrict__ frames;
+    uint64_t* __restrict__ rec_raster;
+    float* __restrict__ rec_v;
+    float* __restrict__ rec_input;
+    int64_t n_total, n_pad, rec_row, raster_words, frame_index;
+    uint32_t t_lo, t_hi;
+    int32_t d_sum, frame_flush, frame_steps, frame_cap;
+    NetParams p0;
+};
+
+template <bool kMulti>
+__global__ void __launch_bounds__(256) node_update_kernel(NodeArgs a) {
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool valid = j < a.n_total;
+    const int64_t jj = valid ? j : 0;
+    const NetParams p = kMulti ? a.params[a.net_id[jj]] : a.p0;
+    const float v = a.V[jj];
+    const uint32_t age = a.age[jj];
+    const float in = a.I[jj];
+    const bool spike = valid && v >= p.v_th;
+
+    const uint64_t spikes = wave_ballot(spike);
+    if (a.rec_raster && lane == 0 && j < a.n_total) a.rec_raster[a.rec_row * a.raster_words + (j >> 6)] = spikes;
+    if (valid) {
+        if (a.rec_v) a.rec_v[a.rec_row * a.n_total + j] = v;
+        if (a.rec_input) a.rec_input[a.rec_row * a.n_total + j] = in;
+        a.I[j] = 0.0f;
+        // spike-history ring: bit (t mod 256) of vertex j
+        const uint32_t slot = a.t_lo & 0xFFu;
+        uint32_t* wp = a.ring + j * kRingWords + (slot >> 5);
+        const uint32_t m = 1u << (slot & 31);
+        *wp = spike ? (*wp | m) : (*wp & ~m);
+    }
+
+    float vn;
+    uint32_t age_n;
+    const bool held = age >= 1u && age <= static_cast<uint32_t>(p.n_ref);
+    if (spike) {
+        vn = p.v_reset;
+        age_n = 1u;
+    } else {
+        age_n = age >= static_cast<uint32_t>(kAgeNever) ? kAgeNever : age + 1u;
+        if (held) {
+            vn = p.v_reset;
+        } else {
+            float u = a.i_ext ? a.i_ext[jj] : 0.0f;
+            float noise = 0.0f;
+            const uint32_t thr = a.drive_thr ? a.drive_thr[jj] : 0u;
+            if (thr != 0u || p.sigma != 0.0f) {
+                const uint32_t jl = static_cast<uint32_t>(jj - p.node_off);
+                const uint4 r = philox(make_uint4(jl, a.t_lo, a.t_hi, 0u), p.key_lo, p.key_hi);
+                if (r.x < thr) u += p.drive_amp;
+                if (p.sigma != 0.0f) noise = p.sigma * gaussian(r.y, r.z);
+            }
+            vn = v + p.decay * (p.v_rest - v) + in + u + noise;
+        }
+    }
+    // recent-spike summary for the next step: last spike within d_sum steps
+    const uint64_t recent = wave_ballot(valid && age_n <= static_cast<uint32_t>(a.d_sum));
+    if (lane == 0 && j < a.n_pad) reinterpret_cast<uint64_t*>(a.summary)[j >> 6] = recent;
+
+    if (valid) {
+        a.V[j] = vn;
+        a.age[j] = static_cast<uint8_t>(age_n);
+        if (a.calcium) {
+            const float c = a.calcium[j];
+            float acc = a.frame_acc[j] + c;
+            if (a.frame_flush) {
+                if (a.frame_index < a.frame_cap) a.frames[a.frame_index * a.n_pad + j] = acc / static_cast<float>(a.frame_steps);
+                acc = 0.0f;
+            }
+            a.frame_acc[j] = acc;
+            a.calcium[j] = c + p.dt * (-c * p.inv_tau_c + (spike ? 1.0f : 0.0f));
+        }
+    }
+}
+
+struct ObserveArgs {
+    const float* __restrict__ V;
+    const uint8_t* __restrict__ age;
+    const float* __restrict__ calcium;
+    const float* __restrict__ frames;
+    const NetParams* __restrict__ params;
+    const int32_t* __restrict__ net_id;
+    void* out;
+    int64_t n_total, n_pad, n_frames;
+    int32_t what, multi;
+    float gain, offset, gamma;
+};
+
+__global__ void __launch_bounds__(256) observe_kernel(ObserveArgs a) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t rows = (a.what == NET_OBS_FRAMES || a.what == NET_OBS_FLUOR) ? a.n_frames : 1;
+    if (idx >= rows * a.n_total) return;
+    const int64_t f = idx / a.n_total, j = idx - f * a.n_total;
+    const NetParams& p = a.params[a.multi ? a.net_id[j] : 0];
+    switch (a.what) {
+        case NET_OBS_V:
+            static_cast<float*>(a.out)[j] = a.V[j];
+            break;
+        case NET_OBS_REF: {
+            const int32_t age = a.age[j];
+            static_cast<int32_t*>(a.out)[j] = (age >= 1 && age <= p.n_ref) ? p.n_ref + 1 - age : 0;
+            break;
+        }
+        case NET_OBS_CALCIUM:
+            static_cast<float*>(a.out)[j] = a.calcium[j];
+            break;
+        case NET_OBS_FRAMES:
+            static_cast<float*>(a.out)[idx] = a.frames[f * a.n_pad + j];
+            break;
+        case NET_OBS_FLUOR: {
+            const uint32_t jl = static_cast<uint32_t>(j - p.node_off);
+            const uint4 r = philox(make_uint4(jl, static_cast<uint32_t>(f), static_cast<uint32_t>(f >> 32), 1u),
+                                   p.key_lo, p.key_hi);
+            static_cast<float*>(a.out)[idx] = a.gain * a.frames[f * a.n_pad + j] + a.offset + a.gamma * gaussian(r.x, r.y);
+            break;
+        }
+        default:
+            break;
+    }
+}
+
+}  // namespace
+
+hipError_t configure_deliver(const DeviceGraph& g, const net_build_opts* opts, LaunchConfig& lc) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    int n_cu = 0, lds_max = 0;
+    if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
+    const size_t summary_bytes = static_cast<size_t>(g.n_pad / 8);
+    const bool want_lds = !(opts && (opts->flags & NET_BUILD_NO_LDS_SUMMARY));
+    lc.lds_summary = want_lds && summary_bytes <= static_cast<size_t>(lds_max);
+    lc.lds_bytes = lc.lds_summary ? summary_bytes : 0;
+    if (lc.lds_summary) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&deliver_kernel<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(summary_bytes));
+        if (e != hipSuccess) return e;
+    }
+    // Workgroups per CU limited by the summary held in LDS (160 KiB per CU).
+    int per_cu = 8;
+    if (lc.lds_summary && summary_bytes > 0) {
+        per_cu = static_cast<int>((160 * 1024) / summary_bytes);
+        per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
+    }
+    int threads = per_cu <= 1 ? 1024 : (per_cu <= 2 ? 512 : 256);
+    if (opts && opts->block_threads) threads = opts->block_threads;
+    if (opts && opts->blocks_per_cu) per_cu = opts->blocks_per_cu;
+    int64_t blocks = static_cast<int64_t>(n_cu) * per_cu;
+    const int64_t waves_needed = g.n_chunks;                 // at least one chunk per wave
+    const int64_t max_blocks = (waves_needed + (threads / 64) - 1) / (threads / 64);
+    if (blocks > max_blocks) blocks = max_blocks < 1 ? 1 : max_blocks;
+    if (blocks >= 8) blocks = blocks / 8 * 8;
+    lc.deliver_blocks = static_cast<int>(blocks);
+    lc.deliver_threads = threads;
+    return hipSuccess;
+}
+
+hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t t, hipStream_t s) {
+    DeliverArgs a;
+    a.src = g.src;
+    a.w = g.w;
+    a.d = g.d;
+    a.rowstart = g.rowstart;
+    a.chunk_row0 = g.chunk_row0;
+    a.summary = g.summary;
+    a.ring = g.ring;
+    a.I = g.I;
+    a.n_chunks = g.n_chunks;
+    a.summary_vec4 = static_cast<int32_t>(g.n_pad / 128);
+    a.t = static_cast<uint32_t>(t);
+    if (lc.lds_summary)
+        hipLaunchKernelGGL(deliver_kernel<true>, dim3(lc.deliver_blocks), dim3(lc.deliver_threads), lc.lds_bytes, s, a);
+    else
+        hipLaunchKernelGGL(deliver_kernel<false>, dim3(lc.deliver_blocks), dim3(lc.deliver_threads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_update(const DeviceGraph& g, int64_t t, int64_t rec_row, const net_record* rec,
+                              int32_t frame_flush, int64_t frame_index, int32_t frame_steps, hipStream_t s) {
+    NodeArgs a;
+    a.V = g.V;
+    a.age = g.age;
+    a.I = g.I;
+    a.ring = g.ring;
+    a.summary = g.summary;
+    a.params = g.params;
+    a.net_id = g.net_id;
+    a.drive_thr = g.drive_thr;
+    a.i_ext = g.i_ext;
+    a.calcium = g.calcium;
+    a.frame_acc = g.frame_acc;
+    a.frames = g.frames;
+    a.rec_raster = rec ? rec->raster : nullptr;
+    a.rec_v = rec ? rec->v : nullptr;
+    a.rec_input = rec ? rec->input : nullptr;
+    a.n_total = g.n_total;
+    a.n_pad = g.n_pad;
+    a.rec_row = rec_row;
+    a.raster_words = (g.n_total + 63) / 64;
+    a.frame_index = frame_index;
+    a.t_lo = static_cast<uint32_t>(t);
+    a.t_hi = static_cast<uint32_t>(static_cast<uint64_t>(t) >> 32);
+    a.d_sum = g.d_sum;
+    a.frame_flush = frame_flush;
+    a.frame_steps = frame_steps;
+    a.frame_cap = g.frame_cap;
+    a.p0 = g.p0;
+    const int threads = 256;
+    const int64_t blocks = g.n_pad / threads + ((g.n_pad % threads) ? 1 : 0);
+    if (g.n_nets > 1)
+        hipLaunchKernelGGL(node_update_kernel<true>, dim3(blocks), dim3(threads), 0, s, a);
+    else
+        hipLaunchKernelGGL(node_update_kernel<false>, dim3(blocks), dim3(threads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_observe(const DeviceGraph& g, int32_t what, const net_fluor_params* fp, void* out, int64_t n_frames,
+                          hipStream_t s) {
+    ObserveArgs a;
+    a.V = g.V;
+    a.age = g.age;
+    a.calcium = g.calcium;
+    a.frames = g.frames;
+    a.params = g.params;
+    a.net_id = g.net_id;
+    a.out = out;
+    a.n_total = g.n_total;
+    a.n_pad = g.n_pad;
+    a.n_frames = n_frames;
+    a.what = what;
+    a.multi = g.n_nets > 1 ? 1 : 0;
+    a.gain = fp ? fp->gain : 1.0f;
+    a.offset = fp ? fp->offset : 0.0f;
+    a.gamma = fp ? fp->gamma : 0.0f;
+    const int64_t rows = (what == NET_OBS_FRAMES || what == NET_OBS_FLUOR) ? n_frames : 1;
+    const int64_t total = rows * g.n_total;
+    if (total == 0) return hipSuccess;
+    const int threads = 256;
+    hipLaunchKernelGGL(observe_kernel, dim3((total + threads - 1) / threads), dim3(threads), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace geonet

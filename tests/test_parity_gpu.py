@@ -1,0 +1,173 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle.
+
+Bars: spike delivery and delays bit-exact; V within 1e-4 (max abs) over
+the first 1000 steps; spike rasters agreeing on >= 99.5 % of events
+(Jaccard over (vertex, step) pairs) over the whole run.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import fixtures as fx
+
+pytestmark = pytest.mark.gpu
+
+V_TOL = 1e-4
+JACCARD_MIN = 0.995
+
+
+def _gn():
+    import torch
+    import paper_0908_3934_amd as gn
+    assert torch.cuda.is_available(), "GPU tests need the MI355X"
+    return gn, torch
+
+
+def run_gpu(spec_or_specs, T, frame_capacity=0, **kw):
+    gn, torch = _gn()
+    net = gn.Net(spec_or_specs, frame_capacity=frame_capacity, **kw)
+    out = net.step(T, raster=True, v=True, inp=True)
+    torch.cuda.synchronize()
+    n = net.n_total
+    res = {
+        "raster": gn.unpack_raster(out["raster"], n),
+        "v": out["v"].cpu().numpy().astype(np.float64),
+        "input": out["input"].cpu().numpy().astype(np.float64),
+        "net": net,
+    }
+    return res
+
+
+def jaccard(a, b):
+    inter = np.logical_and(a, b).sum()
+    union = np.logical_or(a, b).sum()
+    return 1.0 if union == 0 else inter / union
+
+
+def check_parity(g, o, v_steps=1000, exact_raster=False):
+    J = jaccard(g["raster"].astype(bool), o["raster"].astype(bool))
+    dv = np.abs(g["v"][:v_steps] - o["v"][:v_steps]).max()
+    assert dv <= V_TOL, "max |dV| over the first %d steps = %g" % (v_steps, dv)
+    assert J >= JACCARD_MIN, "raster Jaccard %.6f" % J
+    if exact_raster:
+        assert np.array_equal(g["raster"], o["raster"])
+    # delivery is exact wherever both sides saw the same past spikes:
+    # compare inputs up to the first step whose raster differs
+    diff_rows = np.nonzero((g["raster"] != o["raster"]).any(1))[0]
+    upto = diff_rows[0] + 1 if diff_rows.size else g["raster"].shape[0]
+    assert np.array_equal(g["input"][:upto], o["input"][:upto])
+    return J, dv
+
+
+@pytest.mark.parametrize("scenario", ["A", "B"])
+def test_fig2_golden_gpu(scenario):
+    spec = fx.fig2_spec(scenario)
+    g = run_gpu(spec, spec.meta["steps"])
+    assert fx.raster_events(g["raster"]) == sorted(spec.meta["spikes"])
+    nz = [(int(j), int(t), float(g["input"][t, j])) for t, j in zip(*np.nonzero(g["input"]))]
+    assert sorted(nz) == sorted(spec.meta["inputs"])
+
+
+@pytest.mark.parametrize("dist,w", [(150.0, 1.0), (73.2, 1.0), (1234.5, 1.0), (150.0, 0.75)])
+def test_two_vertex_chain_gpu(dist, w):
+    d = math.ceil(dist / (synth.V_UM_PER_MS * synth.DT_MS))
+    spec = fx.two_vertex_chain(dist, w)
+    g = run_gpu(spec, d + 5)
+    assert np.nonzero(g["input"][:, 1])[0].tolist() == [d]
+    fires = np.nonzero(g["raster"][:, 1])[0].tolist()
+    assert fires == ([d + 1] if w >= 1.0 else [])
+
+
+@pytest.mark.parametrize("i0,n_star,period", [(1.5, 220, 241), (2.0, 139, 160)])
+def test_lif_period_gpu(i0, n_star, period):
+    spec = fx.single_vertex(i0)
+    g = run_gpu(spec, n_star + 4 * period + 2)
+    s = np.nonzero(g["raster"][:, 0])[0].tolist()
+    assert s == [n_star + m * period for m in range(5)]
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_tiny_networks_gpu(seed):
+    n = 2 + seed % 7
+    spec = fx.random_tiny(n, 0.5, seed, sigma=0.05 if seed % 2 else 0.0)
+    T = 1500
+    g = run_gpu(spec, T)
+    o = oracle.OracleNet(spec).step(T, v=True, inp=True)
+    check_parity(g, o)
+
+
+def test_config0_full_run():
+    spec = synth.config0()
+    T = 10000
+    g = run_gpu(spec, T)
+    o = oracle.OracleNet(spec).step(T, v=True, inp=True)
+    J, dv = check_parity(g, o)
+    assert o["raster"].sum() > 100
+
+
+def test_config0_recurrent_with_noise():
+    spec = synth.config0_like(256, synth.config_seed(0), w0=0.36)
+    spec.noise_sigma = 0.05
+    T = 10000
+    g = run_gpu(spec, T)
+    o = oracle.OracleNet(spec).step(T, v=True, inp=True)
+    J, dv = check_parity(g, o)
+    assert o["raster"].sum() > 1000
+
+
+def test_config1_reduced():
+    spec = synth.config1(n=8192)
+    T = 3000
+    g = run_gpu(spec, T)
+    o = oracle.OracleNet(spec).step(T, v=True, inp=True)
+    J, dv = check_parity(g, o)
+    assert o["raster"].sum() > 1000
+
+
+def test_ensemble_matches_independent_runs():
+    sizes = [64, 100, 257, 300, 513, 97]
+    specs = [synth.config0_like(n, synth.config_seed(3, k + 1), w0=0.36) for k, n in enumerate(sizes)]
+    for s in specs:
+        s.noise_sigma = 0.05
+    T = 2000
+    g = run_gpu(specs, T)
+    offs = g["net"].node_offsets()
+    for k, s in enumerate(specs):
+        a, b = offs[k], offs[k + 1]
+        o = oracle.OracleNet(s).step(T, v=True, inp=True)
+        sub = {"raster": g["raster"][:, a:b], "v": g["v"][:, a:b], "input": g["input"][:, a:b]}
+        check_parity(sub, o)
+
+
+def test_lds_and_global_summary_agree():
+    spec = synth.config1(n=4096)
+    T = 800
+    a = run_gpu(spec, T)
+    gn, _ = _gn()
+    b = run_gpu(spec, T, flags=gn.NET_BUILD_NO_LDS_SUMMARY)
+    assert a["net"].info()["lds_summary"] == 1 and b["net"].info()["lds_summary"] == 0
+    assert np.array_equal(a["raster"], b["raster"])
+    assert np.array_equal(a["input"], b["input"])
+    assert np.array_equal(a["v"], b["v"])
+
+
+def test_run_twice_bit_identical():
+    spec = synth.config1(n=4096)
+    a = run_gpu(spec, 600)
+    b = run_gpu(spec, 600)
+    assert np.array_equal(a["v"], b["v"]) and np.array_equal(a["raster"], b["raster"])
+
+
+def test_split_steps_equal_one_call():
+    gn, torch = _gn()
+    spec = synth.config1(n=4096)
+    net1 = gn.Net(spec)
+    whole = net1.step(700, v=True)["v"]
+    net2 = gn.Net(spec)
+    p1 = net2.step(300, v=True)["v"]
+    p2 = net2.step(400, v=True)["v"]
+    torch.cuda.synchronize()
+    assert torch.equal(whole, torch.cat([p1, p2]))
