@@ -55,6 +55,8 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy three times (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the simulator is built and measured on a single "
@@ -66,6 +68,13 @@ def main():
     import paper_0908_3934_amd as gn
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     t0 = time.perf_counter()
     spec = synth.config2(n=args.n)
     log("generated N=%d E=%d in %.1f s" % (spec.n, spec.n_edges, time.perf_counter() - t0))

@@ -231,9 +231,7 @@ net_status net_step_n(net_t* h, int64_t n_steps, const net_record* rec, void* st
     for (int64_t k = 0; k < n_steps; ++k) {
         const int64_t t = h->t + k;
         hipEvent_t* ev = (h->t_used < h->t_cap) ? &h->tev[4 * h->t_used++] : nullptr;
-        if (ev) (void)hipEventRecord(ev[0], s);
-        hipError_t e = launch_deliver(h->g, h->lc, t, s);
-        if (ev) (void)hipEventRecord(ev[1], s);
+        hipError_t e = launch_deliver(h->g, h->lc, t, s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
         if (e != hipSuccess) return device_fail(h, e, "net_step_n: delivery launch");
         int32_t flush = 0, steps = 0;
         int64_t frame = 0;
@@ -248,9 +246,8 @@ net_status net_step_n(net_t* h, int64_t n_steps, const net_record* rec, void* st
                 h->frames_done = std::max(h->frames_done, frame + 1);
             }
         }
-        if (ev) (void)hipEventRecord(ev[2], s);
-        e = launch_node_update(h->g, t, k, rec, flush, frame, steps, s);
-        if (ev) (void)hipEventRecord(ev[3], s);
+        e = launch_node_update(h->g, t, k, rec, flush, frame, steps, s, ev ? ev[2] : nullptr,
+                               ev ? ev[3] : nullptr);
         if (e != hipSuccess) return device_fail(h, e, "net_step_n: update launch");
     }
     h->t += n_steps;

@@ -92,10 +92,12 @@ struct LaunchConfig {
 };
 
 // Kernel launchers (kernels.hip).
-hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t t, hipStream_t s);
+// ev0/ev1: optional events bound to the kernel's start and end (timing).
+hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t t, hipStream_t s,
+                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_node_update(const DeviceGraph& g, int64_t t, int64_t rec_row, const net_record* rec,
                               int32_t frame_flush, int64_t frame_index, int32_t frame_steps,
-                              hipStream_t s);
+                              hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_observe(const DeviceGraph& g, int32_t what, const net_fluor_params* fp, void* out,
                           int64_t n_frames, hipStream_t s);
 hipError_t configure_deliver(const DeviceGraph& g, const net_build_opts* opts, LaunchConfig& lc);

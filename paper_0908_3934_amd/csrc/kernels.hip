@@ -12,6 +12,7 @@
 //                       (Section 3.3).
 //   observe_kernel      fluorescence n*cbar + b + gamma*xi (Section 3.3) and
 //                       state read-outs.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -79,17 +80,36 @@ struct DeliverArgs {
 // 8 B (delays).  Workgroups take contiguous chunk ranges; ranges of the
 // workgroups that share an XCD (blockIdx % 8) are adjacent, so the history
 // words they gather for neighbouring targets meet in that XCD's L2.
+// The next chunk's stream loads are issued right after the current chunk's
+// history gathers, so they are in flight while the gathers are consumed.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+struct ChunkRegs {
+    u32x4 s_lo, s_hi;
+    u32x4 wq;
+    u32x2 dq;
+    uint32_t rs;
+};
+
+// Stream loads of one chunk.  The edge list is read once per step and is
+// larger than the last-level cache, so it is loaded non-temporally to leave
+// the caches to the history ring and the summary.
+__device__ __forceinline__ void load_chunk(ChunkRegs& x, const DeliverArgs& a, int64_t c, int lane) {
+    const int64_t e0 = c * kChunkEdges + lane * kEdgesPerLane;
+    x.s_lo = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(a.src + e0));
+    x.s_hi = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(a.src + e0 + 4));
+    x.wq = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(a.w + e0));
+    x.dq = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(a.d + e0));
+    x.rs = a.rowstart[c * 64 + lane];
+}
+
 template <bool kLdsSummary>
 __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
     extern __shared__ uint4 lds_summary4[];
     const uint32_t* lds_summary = reinterpret_cast<const uint32_t*>(lds_summary4);
-    if (kLdsSummary) {
-        const uint4* g = reinterpret_cast<const uint4*>(a.summary);
-        for (int i = threadIdx.x; i < a.summary_vec4; i += blockDim.x) lds_summary4[i] = g[i];
-        __syncthreads();
-    }
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform chunk index
     const int nwaves = blockDim.x >> 6;
     const int nb = gridDim.x;
     const int b = blockIdx.x;
@@ -98,15 +118,18 @@ __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
     const int64_t c_end = static_cast<int64_t>(lb + 1) * a.n_chunks / nb;
     const uint32_t t = a.t;
 
-    for (int64_t c = c_begin + wave; c < c_end; c += nwaves) {
-        const int64_t e0 = c * kChunkEdges + lane * kEdgesPerLane;
-        const int4 s_lo = *reinterpret_cast<const int4*>(a.src + e0);
-        const int4 s_hi = *reinterpret_cast<const int4*>(a.src + e0 + 4);
-        const uint4 wq = *reinterpret_cast<const uint4*>(a.w + e0);
-        const uint2 dq = *reinterpret_cast<const uint2*>(a.d + e0);
-        const uint32_t rs = a.rowstart[c * 64 + lane];
-        const uint32_t sv[8] = {(uint32_t)s_lo.x, (uint32_t)s_lo.y, (uint32_t)s_lo.z, (uint32_t)s_lo.w,
-                                (uint32_t)s_hi.x, (uint32_t)s_hi.y, (uint32_t)s_hi.z, (uint32_t)s_hi.w};
+    int64_t c = c_begin + wave;
+    ChunkRegs cur;
+    if (c < c_end) load_chunk(cur, a, c, lane);
+    if (kLdsSummary) {
+        const uint4* g = reinterpret_cast<const uint4*>(a.summary);
+        for (int i = threadIdx.x; i < a.summary_vec4; i += blockDim.x) lds_summary4[i] = g[i];
+        __syncthreads();
+    }
+
+    for (; c < c_end; c += nwaves) {
+        const uint32_t sv[8] = {cur.s_lo.x, cur.s_lo.y, cur.s_lo.z, cur.s_lo.w,
+                                cur.s_hi.x, cur.s_hi.y, cur.s_hi.z, cur.s_hi.w};
         uint32_t slot[8], word[8];
         uint32_t cand = 0;
 #pragma unroll
@@ -114,12 +137,19 @@ __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
             const uint32_t s = sv[k];
             const uint32_t sw = kLdsSummary ? lds_summary[s >> 5] : a.summary[s >> 5];
             const uint32_t hit = (sw >> (s & 31)) & 1u;
-            const uint32_t dk = ((k < 4 ? dq.x : dq.y) >> (8 * (k & 3))) & 0xFFu;
+            const uint32_t dk = ((k < 4 ? cur.dq.x : cur.dq.y) >> (8 * (k & 3))) & 0xFFu;
             slot[k] = (t - dk) & 0xFFu;
             const uint32_t widx = hit ? s * kRingWords + (slot[k] >> 5) : 0u;
             word[k] = a.ring[widx];
             cand |= hit << k;
         }
+        const u32x4 wq = cur.wq;
+        const uint32_t rs = cur.rs;
+        // Unconditional (the last iteration reloads its own chunk) so that
+        // consuming the gathers never has to wait for these loads.
+        const int64_t cn = (c + nwaves < c_end) ? c + nwaves : c;
+        load_chunk(cur, a, cn, lane);
+
         uint32_t fired = 0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) fired |= (((cand >> k) & (word[k] >> (slot[k] & 31))) & 1u) << k;
@@ -317,7 +347,8 @@ hipError_t configure_deliver(const DeviceGraph& g, const net_build_opts* opts, L
     return hipSuccess;
 }
 
-hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t t, hipStream_t s) {
+hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t t, hipStream_t s, hipEvent_t ev0,
+                          hipEvent_t ev1) {
     DeliverArgs a;
     a.src = g.src;
     a.w = g.w;
@@ -330,15 +361,17 @@ hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t 
     a.n_chunks = g.n_chunks;
     a.summary_vec4 = static_cast<int32_t>(g.n_pad / 128);
     a.t = static_cast<uint32_t>(t);
+    const dim3 grid(lc.deliver_blocks), block(lc.deliver_threads);
     if (lc.lds_summary)
-        hipLaunchKernelGGL(deliver_kernel<true>, dim3(lc.deliver_blocks), dim3(lc.deliver_threads), lc.lds_bytes, s, a);
+        hipExtLaunchKernelGGL(deliver_kernel<true>, grid, block, lc.lds_bytes, s, ev0, ev1, 0, a);
     else
-        hipLaunchKernelGGL(deliver_kernel<false>, dim3(lc.deliver_blocks), dim3(lc.deliver_threads), 0, s, a);
+        hipExtLaunchKernelGGL(deliver_kernel<false>, grid, block, 0, s, ev0, ev1, 0, a);
     return hipGetLastError();
 }
 
 hipError_t launch_node_update(const DeviceGraph& g, int64_t t, int64_t rec_row, const net_record* rec,
-                              int32_t frame_flush, int64_t frame_index, int32_t frame_steps, hipStream_t s) {
+                              int32_t frame_flush, int64_t frame_index, int32_t frame_steps, hipStream_t s,
+                              hipEvent_t ev0, hipEvent_t ev1) {
     NodeArgs a;
     a.V = g.V;
     a.age = g.age;
@@ -370,9 +403,9 @@ hipError_t launch_node_update(const DeviceGraph& g, int64_t t, int64_t rec_row, 
     const int threads = 256;
     const int64_t blocks = g.n_pad / threads + ((g.n_pad % threads) ? 1 : 0);
     if (g.n_nets > 1)
-        hipLaunchKernelGGL(node_update_kernel<true>, dim3(blocks), dim3(threads), 0, s, a);
+        hipExtLaunchKernelGGL(node_update_kernel<true>, dim3(blocks), dim3(threads), 0, s, ev0, ev1, 0, a);
     else
-        hipLaunchKernelGGL(node_update_kernel<false>, dim3(blocks), dim3(threads), 0, s, a);
+        hipExtLaunchKernelGGL(node_update_kernel<false>, dim3(blocks), dim3(threads), 0, s, ev0, ev1, 0, a);
     return hipGetLastError();
 }
 
