@@ -85,7 +85,7 @@ def main():
 
     net.step(args.warmup)
     torch.cuda.synchronize()
-    net.timing_begin(args.steps)
+    net.timing_begin(2 * args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     net.step(args.steps)
@@ -97,7 +97,7 @@ def main():
 
     E = spec.n_edges
     value = E * args.steps / wall
-    avg_deliver_s = tm["deliver_ms"] / tm["steps"] / 1e3
+    avg_deliver_s = tm["deliver_ms"] / tm["deliver_launches"] / 1e3
     achieved = BYTES_PER_EDGE * E / avg_deliver_s / 1e9
     v_now = net.observe(gn.NET_OBS_V)
     torch.cuda.synchronize()
@@ -135,7 +135,7 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
             "avg_launch_us": avg_deliver_s * 1e6,
-            "update_avg_launch_us": tm["update_ms"] / tm["steps"] * 1e3,
+            "update_avg_launch_us": tm["update_ms"] / tm["update_launches"] * 1e3,
         },
     }
     net.close()

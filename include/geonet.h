@@ -109,7 +109,12 @@ typedef struct {
     int32_t flags;                /* NET_BUILD_* */
 } net_build_opts;
 
-#define NET_BUILD_NO_LDS_SUMMARY 1   /* keep the recent-spike summary in global memory */
+/* Build flags (variants that compute the same result; for tuning/measurement). */
+#define NET_BUILD_NO_LDS_SUMMARY 1        /* keep the recent-spike summary in global memory */
+#define NET_BUILD_DELIVER_NO_PREFETCH 2   /* delivery: no prefetch of the next edge chunk */
+#define NET_BUILD_DELIVER_CACHED 4        /* delivery: ordinary (not non-temporal) edge loads */
+#define NET_BUILD_PER_STEP 8              /* ensembles: per-step kernels instead of the
+                                             single-launch ensemble kernel */
 
 /*
  * Optional per-step records for net_step_n (device pointers, may be NULL).
@@ -191,15 +196,21 @@ net_status net_observe(net_t* h, int32_t what, const void* params, void* out, in
                        void* stream);
 
 /*
- * Kernel timing for measurement.  After net_timing_begin(h, max_steps), each
- * of the next max_steps steps taken by net_step_n records HIP events around
- * its delivery and vertex-update launches (on the call's stream).
- * net_timing_end waits for those events, returns the summed durations in
- * milliseconds and the number of timed steps, and stops recording.  Timing
+ * Kernel timing for measurement.  After net_timing_begin(h, max_launches),
+ * the next max_launches kernel launches made by net_step_n are bound to HIP
+ * events (start and end of the kernel itself, on the call's stream).
+ * net_timing_end waits for them, fills *out with the summed durations per
+ * kernel kind and the launch and step counts, and stops recording.  Timing
  * never changes results.
  */
-net_status net_timing_begin(net_t* h, int64_t max_steps);
-net_status net_timing_end(net_t* h, double* deliver_ms, double* update_ms, int64_t* steps);
+typedef struct {
+    double deliver_ms, update_ms, ensemble_ms;         /* summed kernel durations */
+    int64_t deliver_launches, update_launches, ensemble_launches;
+    int64_t steps;                                     /* steps covered by timed launches */
+} net_timing_t;
+
+net_status net_timing_begin(net_t* h, int64_t max_launches);
+net_status net_timing_end(net_t* h, net_timing_t* out);
 
 /* Sizes and counters of a handle (host struct). */
 net_status net_info(const net_t* h, net_info_t* out);

@@ -16,11 +16,13 @@ from typing import Iterable, List, Optional, Sequence
 import numpy as np
 
 from . import _abi
-from ._abi import (NET_BUILD_NO_LDS_SUMMARY, NET_OBS_CALCIUM, NET_OBS_FLUOR, NET_OBS_FRAMES, NET_OBS_REF,
+from ._abi import (NET_BUILD_DELIVER_CACHED, NET_BUILD_DELIVER_NO_PREFETCH, NET_BUILD_NO_LDS_SUMMARY,
+                   NET_BUILD_PER_STEP, NET_OBS_CALCIUM, NET_OBS_FLUOR, NET_OBS_FRAMES, NET_OBS_REF,
                    NET_OBS_V, NET_OK, NET_W_INEXACT)
 
 __all__ = ["Net", "GeonetError", "NET_OBS_V", "NET_OBS_REF", "NET_OBS_CALCIUM", "NET_OBS_FRAMES",
-           "NET_OBS_FLUOR", "NET_BUILD_NO_LDS_SUMMARY", "library"]
+           "NET_OBS_FLUOR", "NET_BUILD_NO_LDS_SUMMARY", "NET_BUILD_DELIVER_NO_PREFETCH",
+           "NET_BUILD_DELIVER_CACHED", "NET_BUILD_PER_STEP", "library"]
 
 
 class GeonetError(RuntimeError):
@@ -191,13 +193,13 @@ class Net:
         _check(library().net_step_n(self.h, n_steps, C.byref(rec), s), "net_step_n")
         return {"raster": r, "v": vv, "input": ii}
 
-    def timing_begin(self, max_steps: int):
-        _check(library().net_timing_begin(self.h, max_steps), "net_timing_begin")
+    def timing_begin(self, max_launches: int):
+        _check(library().net_timing_begin(self.h, max_launches), "net_timing_begin")
 
-    def timing_end(self):
-        d, u, n = C.c_double(), C.c_double(), C.c_int64()
-        _check(library().net_timing_end(self.h, C.byref(d), C.byref(u), C.byref(n)), "net_timing_end")
-        return {"deliver_ms": d.value, "update_ms": u.value, "steps": n.value}
+    def timing_end(self) -> dict:
+        out = _abi.Timing()
+        _check(library().net_timing_end(self.h, C.byref(out)), "net_timing_end")
+        return {name: getattr(out, name) for name, _ in _abi.Timing._fields_}
 
     def observe(self, what: int, frames: int = 0, gain: float = 1.0, offset: float = 0.0, gamma: float = 0.0,
                 stream=None):

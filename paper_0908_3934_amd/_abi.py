@@ -17,6 +17,9 @@ NET_E_STATE = -5
 NET_E_UNSUPPORTED = -6
 
 NET_BUILD_NO_LDS_SUMMARY = 1
+NET_BUILD_DELIVER_NO_PREFETCH = 2
+NET_BUILD_DELIVER_CACHED = 4
+NET_BUILD_PER_STEP = 8
 
 NET_OBS_V = 1
 NET_OBS_REF = 2
@@ -57,6 +60,12 @@ class Info(C.Structure):
     ]
 
 
+class Timing(C.Structure):
+    _fields_ = [("deliver_ms", C.c_double), ("update_ms", C.c_double), ("ensemble_ms", C.c_double),
+                ("deliver_launches", C.c_int64), ("update_launches", C.c_int64),
+                ("ensemble_launches", C.c_int64), ("steps", C.c_int64)]
+
+
 class FluorParams(C.Structure):
     _fields_ = [("gain", C.c_float), ("offset", C.c_float), ("gamma", C.c_float), ("pad", C.c_int32)]
 
@@ -73,7 +82,7 @@ SIGNATURES = {
     "net_info": (C.c_int, [_vp, C.POINTER(Info)]),
     "net_node_offsets": (C.c_int, [_vp, _vp]),
     "net_timing_begin": (C.c_int, [_vp, C.c_int64]),
-    "net_timing_end": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "net_timing_end": (C.c_int, [_vp, C.POINTER(Timing)]),
     "net_free": (None, [_vp]),
     "net_last_error": (C.c_char_p, []),
 }

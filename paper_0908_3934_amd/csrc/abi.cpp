@@ -26,9 +26,12 @@ struct net {
     void (*release)(void*, void*, void*) = nullptr;
     void* alloc_ctx = nullptr;
     hipStream_t last_stream = nullptr;
-    // kernel timing: events [4 * step] = deliver start/end, update start/end
+    // kernel timing: events [2 * launch] = start/end; kind 0 deliver, 1 update, 2 ensemble
     std::vector<hipEvent_t> tev;
+    std::vector<int32_t> tkind;
+    std::vector<int64_t> tsteps;
     int64_t t_cap = 0, t_used = 0;
+    EnsemblePlan plan;
 };
 
 namespace {
@@ -99,6 +102,69 @@ net_status zeros(net* h, T** dst, size_t count, hipStream_t s, const char* what,
     hipError_t e = hipMemsetAsync(p, byte, count * sizeof(T), s);
     if (e != hipSuccess) return device_fail(h, e, "net_build: clear");
     return NET_OK;
+}
+
+// Next pair of timing events (or nulls when not timing).
+void next_events(net* h, int32_t kind, int64_t steps, hipEvent_t* e0, hipEvent_t* e1) {
+    *e0 = *e1 = nullptr;
+    if (h->t_used >= h->t_cap) return;
+    const int64_t k = h->t_used++;
+    *e0 = h->tev[2 * k];
+    *e1 = h->tev[2 * k + 1];
+    h->tkind[k] = kind;
+    h->tsteps[k] = steps;
+}
+
+// Longest-processing-time packing of networks onto workgroups under an LDS
+// budget per workgroup.  Returns false if some network does not fit.
+bool plan_ensemble(net* h, const HostGraph& hg, int n_cu, int wgs_per_cu, int threads, bool observe,
+                   std::vector<NetMeta>& meta, std::vector<int32_t>& wg_nets, std::vector<int32_t>& wg_off,
+                   size_t& lds_max) {
+    const int n_nets = h->g.n_nets;
+    const size_t budget = (160u * 1024u) / static_cast<size_t>(wgs_per_cu);
+    meta.resize(n_nets);
+    std::vector<int64_t> cost(n_nets);
+    std::vector<size_t> need(n_nets);
+    for (int m = 0; m < n_nets; ++m) {
+        NetMeta& nm = meta[m];
+        nm.node_off = static_cast<int32_t>(hg.node_off[m]);
+        nm.n_nodes = static_cast<int32_t>(hg.node_off[m + 1] - hg.node_off[m]);
+        nm.chunk_begin = static_cast<int32_t>(hg.net_chunk_begin[m]);
+        nm.chunk_end = static_cast<int32_t>(hg.net_chunk_end[m]);
+        nm.words = hg.net_max_delay[m] <= 31 ? 1 : kRingWords;
+        need[m] = ensemble_lds_bytes(nm.n_nodes, nm.words, observe);
+        if (need[m] > budget) return false;
+        // per-step cost model: edge slots + vertices + a fixed share of the barriers
+        cost[m] = int64_t(nm.chunk_end - nm.chunk_begin) * kChunkEdges + 8 * int64_t(nm.n_nodes) + 2048;
+    }
+    const int n_wg = std::max(1, std::min(n_nets, n_cu * wgs_per_cu));
+    std::vector<int> order(n_nets);
+    for (int m = 0; m < n_nets; ++m) order[m] = m;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] != cost[y] ? cost[x] > cost[y] : x < y; });
+    std::vector<int64_t> load(n_wg, 0);
+    std::vector<size_t> used(n_wg, 0);
+    std::vector<std::vector<int32_t>> lists(n_wg);
+    for (int m : order) {
+        int best = -1;
+        for (int b = 0; b < n_wg; ++b)
+            if (used[b] + need[m] <= budget && (best < 0 || load[b] < load[best])) best = b;
+        if (best < 0) return false;
+        meta[m].lds_off = static_cast<int32_t>(used[best]);
+        used[best] += need[m];
+        load[best] += cost[m];
+        lists[best].push_back(m);
+    }
+    wg_off.assign(n_wg + 1, 0);
+    wg_nets.clear();
+    lds_max = 16;
+    for (int b = 0; b < n_wg; ++b) {
+        wg_off[b] = static_cast<int32_t>(wg_nets.size());
+        for (int32_t m : lists[b]) wg_nets.push_back(m);
+        lds_max = std::max(lds_max, used[b]);
+    }
+    wg_off[n_wg] = static_cast<int32_t>(wg_nets.size());
+    (void)threads;
+    return true;
 }
 
 }  // namespace
@@ -208,6 +274,40 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
         device_fail(h, e, "net_build: configure");
         return bail(NET_E_DEVICE);
     }
+    if (n_nets > 1 && !(opts && (opts->flags & NET_BUILD_PER_STEP))) {
+        int dev = 0, n_cu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
+            std::vector<NetMeta> meta;
+            std::vector<int32_t> wg_nets, wg_off;
+            size_t lds_max = 0;
+            const bool observe = frame_cap > 0 && hg.frame_num > 0;
+            int per_cu = (opts && opts->blocks_per_cu) ? opts->blocks_per_cu : 2;
+            int threads = (opts && opts->block_threads) ? opts->block_threads : (per_cu >= 2 ? 512 : 1024);
+            bool ok = plan_ensemble(h, hg, n_cu, per_cu, threads, observe, meta, wg_nets, wg_off, lds_max);
+            if (!ok && per_cu > 1 && !(opts && opts->blocks_per_cu)) {
+                per_cu = 1;
+                threads = (opts && opts->block_threads) ? opts->block_threads : 1024;
+                ok = plan_ensemble(h, hg, n_cu, per_cu, threads, observe, meta, wg_nets, wg_off, lds_max);
+            }
+            if (ok) {
+                EnsemblePlan& pl = h->plan;
+                std::vector<NetMeta> mv(meta.begin(), meta.end());
+                if ((st = upload(h, &pl.meta, mv, mv.size(), s, "ensemble plan")) != NET_OK) return bail(st);
+                if ((st = upload(h, &pl.wg_nets, wg_nets, wg_nets.size(), s, "ensemble plan")) != NET_OK) return bail(st);
+                if ((st = upload(h, &pl.wg_off, wg_off, wg_off.size(), s, "ensemble plan")) != NET_OK) return bail(st);
+                pl.blocks = static_cast<int>(wg_off.size()) - 1;
+                pl.threads = threads;
+                pl.lds_bytes = lds_max;
+                e = enable_ensemble_lds(lds_max);
+                if (e != hipSuccess) {
+                    device_fail(h, e, "net_build: ensemble LDS");
+                    return bail(NET_E_DEVICE);
+                }
+                pl.enabled = true;
+            }
+        }
+    }
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         device_fail(h, e, "net_build: upload");
@@ -228,10 +328,44 @@ net_status net_step_n(net_t* h, int64_t n_steps, const net_record* rec, void* st
     hipStream_t s = static_cast<hipStream_t>(stream);
     h->last_stream = s;
     const bool observe = h->g.frame_cap > 0 && h->frame_num > 0;
+    if (h->plan.enabled) {
+        // one launch per (at most 2^30) steps for the whole ensemble
+        int64_t done = 0;
+        while (done < n_steps) {
+            const int32_t chunk = static_cast<int32_t>(std::min<int64_t>(n_steps - done, int64_t(1) << 30));
+            net_record sub{};
+            if (rec) {
+                const int64_t words = (h->g.n_total + 63) / 64;
+                sub.raster = rec->raster ? rec->raster + done * words : nullptr;
+                sub.v = rec->v ? rec->v + done * h->g.n_total : nullptr;
+                sub.input = rec->input ? rec->input + done * h->g.n_total : nullptr;
+            }
+            hipEvent_t e0, e1;
+            next_events(h, 2, chunk, &e0, &e1);
+            hipError_t e = launch_ensemble(h->g, h->plan, h->t + done, chunk, rec ? &sub : nullptr, h->frame_num,
+                                           h->frame_den, s, e0, e1);
+            if (e != hipSuccess) return device_fail(h, e, "net_step_n: ensemble launch");
+            done += chunk;
+        }
+        if (observe) {
+            for (int64_t t = h->t; t < h->t + n_steps; ++t) {
+                const int64_t frame = t * h->frame_num / h->frame_den;
+                const int64_t next = (t + 1) * h->frame_num / h->frame_den;
+                h->acc_steps += 1;
+                if (next != frame) {
+                    h->acc_steps = 0;
+                    h->frames_done = std::max(h->frames_done, frame + 1);
+                }
+            }
+        }
+        h->t += n_steps;
+        return NET_OK;
+    }
     for (int64_t k = 0; k < n_steps; ++k) {
         const int64_t t = h->t + k;
-        hipEvent_t* ev = (h->t_used < h->t_cap) ? &h->tev[4 * h->t_used++] : nullptr;
-        hipError_t e = launch_deliver(h->g, h->lc, t, s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
+        hipEvent_t d0, d1, u0, u1;
+        next_events(h, 0, 1, &d0, &d1);
+        hipError_t e = launch_deliver(h->g, h->lc, t, s, d0, d1);
         if (e != hipSuccess) return device_fail(h, e, "net_step_n: delivery launch");
         int32_t flush = 0, steps = 0;
         int64_t frame = 0;
@@ -246,8 +380,8 @@ net_status net_step_n(net_t* h, int64_t n_steps, const net_record* rec, void* st
                 h->frames_done = std::max(h->frames_done, frame + 1);
             }
         }
-        e = launch_node_update(h->g, t, k, rec, flush, frame, steps, s, ev ? ev[2] : nullptr,
-                               ev ? ev[3] : nullptr);
+        next_events(h, 1, 0, &u0, &u1);
+        e = launch_node_update(h->g, t, k, rec, flush, frame, steps, s, u0, u1);
         if (e != hipSuccess) return device_fail(h, e, "net_step_n: update launch");
     }
     h->t += n_steps;
@@ -314,39 +448,39 @@ net_status net_node_offsets(const net_t* h, int64_t* out) {
     return NET_OK;
 }
 
-net_status net_timing_begin(net_t* h, int64_t max_steps) {
+net_status net_timing_begin(net_t* h, int64_t max_launches) {
     if (!h) return fail(NET_E_ARG, "net_timing_begin: handle is NULL");
-    if (max_steps < 0 || max_steps > (int64_t(1) << 22)) return fail(NET_E_ARG, "net_timing_begin: bad max_steps");
+    if (max_launches < 0 || max_launches > (int64_t(1) << 22))
+        return fail(NET_E_ARG, "net_timing_begin: bad max_launches");
     for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
-    h->tev.assign(static_cast<size_t>(4 * max_steps), nullptr);
+    h->tev.assign(static_cast<size_t>(2 * max_launches), nullptr);
+    h->tkind.assign(static_cast<size_t>(max_launches), 0);
+    h->tsteps.assign(static_cast<size_t>(max_launches), 0);
+    h->t_cap = 0;
+    h->t_used = 0;
     for (auto& e : h->tev) {
         hipError_t r = hipEventCreate(&e);
-        if (r != hipSuccess) {
-            h->t_cap = 0;
-            return device_fail(h, r, "net_timing_begin");
-        }
+        if (r != hipSuccess) return device_fail(h, r, "net_timing_begin");
     }
-    h->t_cap = max_steps;
-    h->t_used = 0;
+    h->t_cap = max_launches;
     return NET_OK;
 }
 
-net_status net_timing_end(net_t* h, double* deliver_ms, double* update_ms, int64_t* steps) {
-    if (!h || !deliver_ms || !update_ms || !steps) return fail(NET_E_ARG, "net_timing_end: NULL argument");
-    double dsum = 0.0, usum = 0.0;
+net_status net_timing_end(net_t* h, net_timing_t* out) {
+    if (!h || !out) return fail(NET_E_ARG, "net_timing_end: NULL argument");
+    std::memset(out, 0, sizeof(*out));
     for (int64_t k = 0; k < h->t_used; ++k) {
-        hipEvent_t* ev = &h->tev[4 * k];
-        float a = 0.0f, b = 0.0f;
-        hipError_t r = hipEventSynchronize(ev[3]);
-        if (r == hipSuccess) r = hipEventElapsedTime(&a, ev[0], ev[1]);
-        if (r == hipSuccess) r = hipEventElapsedTime(&b, ev[2], ev[3]);
+        float ms = 0.0f;
+        hipError_t r = hipEventSynchronize(h->tev[2 * k + 1]);
+        if (r == hipSuccess) r = hipEventElapsedTime(&ms, h->tev[2 * k], h->tev[2 * k + 1]);
         if (r != hipSuccess) return device_fail(h, r, "net_timing_end");
-        dsum += a;
-        usum += b;
+        switch (h->tkind[k]) {
+            case 0: out->deliver_ms += ms; out->deliver_launches++; break;
+            case 1: out->update_ms += ms; out->update_launches++; break;
+            default: out->ensemble_ms += ms; out->ensemble_launches++; break;
+        }
+        out->steps += h->tsteps[k];
     }
-    *deliver_ms = dsum;
-    *update_ms = usum;
-    *steps = h->t_used;
     for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
     h->tev.clear();
     h->t_cap = h->t_used = 0;

@@ -134,10 +134,23 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
             indeg[g.node_off[m] + j]++;
         }
     }
-    // Slot offsets: every row gets max(indeg, 1) slots.
-    std::vector<int64_t> row_ptr(N + 1, 0);
-    for (int64_t r = 0; r < N; ++r) row_ptr[r + 1] = row_ptr[r] + std::max<int64_t>(indeg[r], 1);
-    const int64_t used = row_ptr[N];
+    // Slot offsets: every row gets max(indeg, 1) slots.  In an ensemble each
+    // network's slot range starts on a chunk boundary, so a chunk never mixes
+    // networks (the ensemble kernel walks each network's chunks on its own).
+    std::vector<int64_t> row_ptr(N + 1, 0);   // row_ptr[r] = first slot of row r
+    g.net_chunk_begin.assign(n_nets, 0);
+    g.net_chunk_end.assign(n_nets, 0);
+    int64_t used = 0;
+    for (int m = 0; m < n_nets; ++m) {
+        if (n_nets > 1) used = (used + kChunkEdges - 1) / kChunkEdges * kChunkEdges;
+        g.net_chunk_begin[m] = used / kChunkEdges;
+        for (int64_t r = g.node_off[m]; r < g.node_off[m + 1]; ++r) {
+            row_ptr[r] = used;
+            used += std::max<int64_t>(indeg[r], 1);
+        }
+        g.net_chunk_end[m] = (used + kChunkEdges - 1) / kChunkEdges;
+    }
+    row_ptr[N] = used;
     g.e_slots = (used + kChunkEdges - 1) / kChunkEdges * kChunkEdges;
     if (g.e_slots == 0) g.e_slots = kChunkEdges;
     if (g.e_slots > (int64_t(1) << 31) - kChunkEdges) {
@@ -145,14 +158,22 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
         return NET_E_RANGE;
     }
     g.n_chunks = g.e_slots / kChunkEdges;
+    // Every slot starts as a zero-weight placeholder owned by the preceding row
+    // (its source is that row's own vertex, so it stays inside its network).
     g.src.assign(g.e_slots, 0);
     g.w.assign(g.e_slots, 0);
     g.d.assign(g.e_slots, 1);
     g.rowstart.assign(g.e_slots / 8, 0);
+    for (int64_t r = 0; r < N; ++r) {
+        const int64_t a = row_ptr[r];
+        const int64_t b = (r + 1 < N) ? row_ptr[r + 1] : g.e_slots;
+        for (int64_t s = a; s < b; ++s) g.src[s] = static_cast<int32_t>(r);
+    }
 
     // Scatter edges into their rows (stable in input order).
     std::vector<int64_t> fill(row_ptr.begin(), row_ptr.end() - 1);
     int32_t max_delay = 1;
+    g.net_max_delay.assign(n_nets, 1);
     for (int m = 0; m < n_nets; ++m) {
         const net_desc& d = descs[m];
         const int64_t off = g.node_off[m];
@@ -178,6 +199,7 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
                 return NET_E_RANGE;
             }
             max_delay = std::max(max_delay, dl);
+            g.net_max_delay[m] = std::max(g.net_max_delay[m], dl);
             const int64_t s = fill[off + j]++;
             g.src[s] = static_cast<int32_t>(off + i);
             g.w[s] = wb;
@@ -188,7 +210,7 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
     // Placeholders for empty rows, row-start bits, per-row order and exactness.
     const double two24 = 16777216.0;
     for (int64_t r = 0; r < N; ++r) {
-        const int64_t a = row_ptr[r], b = row_ptr[r + 1];
+        const int64_t a = row_ptr[r], b = a + std::max<int64_t>(indeg[r], 1);
         g.rowstart[a >> 3] |= uint8_t(1u << (a & 7));
         if (indeg[r] == 0) {
             g.src[a] = static_cast<int32_t>(r);
@@ -235,12 +257,6 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
             ulp_min = std::min(ulp_min, fp16_ulp_log2(g.w[s]));
         }
         if (sum_abs > 0.0 && sum_abs > std::ldexp(two24, ulp_min)) g.exact = false;
-    }
-    // Trailing padding slots belong to the last row; their weight is 0.
-    for (int64_t s = used; s < g.e_slots; ++s) {
-        g.src[s] = 0;
-        g.w[s] = 0;
-        g.d[s] = 1;
     }
     g.chunk_row0.assign(g.n_chunks, 0);
     {

@@ -30,6 +30,14 @@ struct NetParams {
     int32_t node_off;   // first vertex of the network in the ensemble numbering
 };
 
+// Per-network description used by the ensemble kernel.
+struct NetMeta {
+    int32_t node_off, n_nodes;
+    int32_t chunk_begin, chunk_end;
+    int32_t words;      // history words per vertex in LDS: 1 (32 steps) or 8 (256 steps)
+    int32_t lds_off;    // byte offset of the network's state in its workgroup's LDS
+};
+
 // Host-side result of graph construction (before upload).
 struct HostGraph {
     int64_t n_total = 0, n_pad = 0;
@@ -44,6 +52,8 @@ struct HostGraph {
     std::vector<uint8_t> rowstart;  // [e_slots / 8] bit k of byte b: slot 8b+k opens a row
     std::vector<int32_t> chunk_row0;  // [n_chunks] row of each chunk's first slot
     std::vector<int64_t> node_off;    // [n_nets + 1]
+    std::vector<int64_t> net_chunk_begin, net_chunk_end;  // [n_nets] chunk range of each network
+    std::vector<int32_t> net_max_delay;                   // [n_nets]
     std::vector<NetParams> params;    // [n_nets]
     // per-vertex arrays [n_pad]
     std::vector<float> v0;
@@ -88,8 +98,26 @@ struct LaunchConfig {
     int deliver_blocks = 0;
     int deliver_threads = 0;
     bool lds_summary = false;
+    bool prefetch = true;
+    bool nontemporal = true;
     size_t lds_bytes = 0;
 };
+
+// Plan of the ensemble kernel: networks packed onto workgroups.
+struct EnsemblePlan {
+    bool enabled = false;
+    int blocks = 0, threads = 0;
+    size_t lds_bytes = 0;           // per workgroup (max over workgroups)
+    NetMeta* meta = nullptr;        // device [n_nets] (lds_off filled per network)
+    int32_t* wg_nets = nullptr;     // device: networks of workgroup b at [wg_off[b], wg_off[b+1])
+    int32_t* wg_off = nullptr;      // device [blocks + 1]
+};
+
+// LDS bytes one network needs in the ensemble kernel.
+inline size_t ensemble_lds_bytes(int64_t n_nodes, int words, bool observe) {
+    const size_t per = 4 * 3 + 4 * static_cast<size_t>(words) + (observe ? 8 : 0);   // V, I, age, ring, c, acc
+    return (static_cast<size_t>(n_nodes) * per + 15) / 16 * 16;
+}
 
 // Kernel launchers (kernels.hip).
 // ev0/ev1: optional events bound to the kernel's start and end (timing).
@@ -101,5 +129,9 @@ hipError_t launch_node_update(const DeviceGraph& g, int64_t t, int64_t rec_row, 
 hipError_t launch_observe(const DeviceGraph& g, int32_t what, const net_fluor_params* fp, void* out,
                           int64_t n_frames, hipStream_t s);
 hipError_t configure_deliver(const DeviceGraph& g, const net_build_opts* opts, LaunchConfig& lc);
+hipError_t enable_ensemble_lds(size_t bytes);
+hipError_t launch_ensemble(const DeviceGraph& g, const EnsemblePlan& plan, int64_t t0, int32_t n_steps,
+                           const net_record* rec, int32_t frame_num, int32_t frame_den, hipStream_t s,
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 }  // namespace geonet

@@ -95,16 +95,24 @@ struct ChunkRegs {
 // Stream loads of one chunk.  The edge list is read once per step and is
 // larger than the last-level cache, so it is loaded non-temporally to leave
 // the caches to the history ring and the summary.
+template <bool kNT>
 __device__ __forceinline__ void load_chunk(ChunkRegs& x, const DeliverArgs& a, int64_t c, int lane) {
     const int64_t e0 = c * kChunkEdges + lane * kEdgesPerLane;
-    x.s_lo = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(a.src + e0));
-    x.s_hi = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(a.src + e0 + 4));
-    x.wq = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(a.w + e0));
-    x.dq = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(a.d + e0));
+    if (kNT) {
+        x.s_lo = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(a.src + e0));
+        x.s_hi = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(a.src + e0 + 4));
+        x.wq = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(a.w + e0));
+        x.dq = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(a.d + e0));
+    } else {
+        x.s_lo = *reinterpret_cast<const u32x4*>(a.src + e0);
+        x.s_hi = *reinterpret_cast<const u32x4*>(a.src + e0 + 4);
+        x.wq = *reinterpret_cast<const u32x4*>(a.w + e0);
+        x.dq = *reinterpret_cast<const u32x2*>(a.d + e0);
+    }
     x.rs = a.rowstart[c * 64 + lane];
 }
 
-template <bool kLdsSummary>
+template <bool kLdsSummary, bool kPrefetch, bool kNT>
 __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
     extern __shared__ uint4 lds_summary4[];
     const uint32_t* lds_summary = reinterpret_cast<const uint32_t*>(lds_summary4);
@@ -120,7 +128,7 @@ __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
 
     int64_t c = c_begin + wave;
     ChunkRegs cur;
-    if (c < c_end) load_chunk(cur, a, c, lane);
+    if (kPrefetch && c < c_end) load_chunk<kNT>(cur, a, c, lane);
     if (kLdsSummary) {
         const uint4* g = reinterpret_cast<const uint4*>(a.summary);
         for (int i = threadIdx.x; i < a.summary_vec4; i += blockDim.x) lds_summary4[i] = g[i];
@@ -128,6 +136,7 @@ __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
     }
 
     for (; c < c_end; c += nwaves) {
+        if (!kPrefetch) load_chunk<kNT>(cur, a, c, lane);
         const uint32_t sv[8] = {cur.s_lo.x, cur.s_lo.y, cur.s_lo.z, cur.s_lo.w,
                                 cur.s_hi.x, cur.s_hi.y, cur.s_hi.z, cur.s_hi.w};
         uint32_t slot[8], word[8];
@@ -147,8 +156,10 @@ __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
         const uint32_t rs = cur.rs;
         // Unconditional (the last iteration reloads its own chunk) so that
         // consuming the gathers never has to wait for these loads.
-        const int64_t cn = (c + nwaves < c_end) ? c + nwaves : c;
-        load_chunk(cur, a, cn, lane);
+        if (kPrefetch) {
+            const int64_t cn = (c + nwaves < c_end) ? c + nwaves : c;
+            load_chunk<kNT>(cur, a, cn, lane);
+        }
 
         uint32_t fired = 0;
 #pragma unroll
@@ -264,6 +275,274 @@ __global__ void __launch_bounds__(256) node_update_kernel(NodeArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Ensemble kernel: one launch advances every network of an ensemble by
+// n_steps.  Each workgroup owns a packed set of networks and keeps their whole
+// state in LDS (V, input accumulator, age, a 32- or 256-step history ring,
+// calcium); per step it runs the delivery of all its networks, one barrier,
+// the vertex update of all its networks, one barrier.  Networks never share a
+// workgroup's data with other workgroups, so no grid-wide synchronisation is
+// needed.  Edges stream from global memory (L2/MALL resident for ensembles).
+// The arithmetic per vertex and per edge is the same as in node_update_kernel
+// and deliver_kernel.
+// ---------------------------------------------------------------------------
+struct EnsembleArgs {
+    const int32_t* __restrict__ src;
+    const uint16_t* __restrict__ w;
+    const uint8_t* __restrict__ d;
+    const uint8_t* __restrict__ rowstart;
+    const int32_t* __restrict__ chunk_row0;
+    const NetMeta* __restrict__ meta;
+    const int32_t* __restrict__ wg_nets;
+    const int32_t* __restrict__ wg_off;
+    const NetParams* __restrict__ params;
+    const uint32_t* __restrict__ drive_thr;
+    const float* __restrict__ i_ext;
+    float* __restrict__ V;
+    uint8_t* __restrict__ age;
+    uint32_t* __restrict__ ring;
+    uint32_t* __restrict__ summary;
+    float* __restrict__ calcium;
+    float* __restrict__ frame_acc;
+    float* __restrict__ frames;
+    uint64_t* __restrict__ rec_raster;
+    float* __restrict__ rec_v;
+    float* __restrict__ rec_input;
+    int64_t t0, n_total, n_pad, raster_words;
+    int32_t n_steps, frame_cap, frame_num, frame_den, d_sum;
+};
+
+struct NetLds {
+    float* V;
+    float* I;
+    uint32_t* age;
+    uint32_t* ring;
+    float* c;
+    float* acc;
+};
+
+__device__ __forceinline__ NetLds carve(uint8_t* base, const NetMeta& nm, bool obs) {
+    NetLds L;
+    const int n = nm.n_nodes;
+    L.V = reinterpret_cast<float*>(base + nm.lds_off);
+    L.I = L.V + n;
+    L.age = reinterpret_cast<uint32_t*>(L.I + n);
+    L.ring = L.age + n;
+    L.c = reinterpret_cast<float*>(L.ring + static_cast<int64_t>(n) * nm.words);
+    L.acc = obs ? L.c + n : L.c;
+    return L;
+}
+
+// Write the 64 bits `bits` of local vertices [u0, u0+64) (union numbering
+// u0 = first vertex) into a bit array of 64-bit words shared with other
+// networks: clear this network's positions (mask), then set its bits.
+__device__ __forceinline__ void put_bits_shared(uint64_t* words, int64_t u0, uint64_t bits, uint64_t mask) {
+    const int64_t w0 = u0 >> 6;
+    const int sh = static_cast<int>(u0 & 63);
+    atomicAnd(reinterpret_cast<unsigned long long*>(words + w0), ~(mask << sh));
+    atomicOr(reinterpret_cast<unsigned long long*>(words + w0), (bits & mask) << sh);
+    if (sh != 0 && (mask >> (64 - sh)) != 0) {
+        atomicAnd(reinterpret_cast<unsigned long long*>(words + w0 + 1), ~(mask >> (64 - sh)));
+        atomicOr(reinterpret_cast<unsigned long long*>(words + w0 + 1), (bits & mask) >> (64 - sh));
+    }
+}
+
+__global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
+    extern __shared__ uint4 lds4[];
+    uint8_t* lds = reinterpret_cast<uint8_t*>(lds4);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nwaves = blockDim.x >> 6;
+    const int q_begin = a.wg_off[blockIdx.x], q_end = a.wg_off[blockIdx.x + 1];
+    const bool obs = a.calcium != nullptr;
+
+    // ---- load the state of every network of this workgroup into LDS
+    for (int q = q_begin; q < q_end; ++q) {
+        const NetMeta nm = a.meta[a.wg_nets[q]];
+        const NetLds L = carve(lds, nm, obs);
+        for (int j = tid; j < nm.n_nodes; j += blockDim.x) {
+            const int64_t u = nm.node_off + j;
+            L.V[j] = a.V[u];
+            L.I[j] = 0.0f;
+            L.age[j] = a.age[u];
+            if (obs) {
+                L.c[j] = a.calcium[u];
+                L.acc[j] = a.frame_acc[u];
+            }
+            const uint32_t* gr = a.ring + u * kRingWords;
+            if (nm.words == kRingWords) {
+#pragma unroll
+                for (int k = 0; k < kRingWords; ++k) L.ring[j * kRingWords + k] = gr[k];
+            } else {
+                // steps t0-32 .. t0-1 into one word, bit = step mod 32
+                const uint32_t q32 = static_cast<uint32_t>(a.t0) & 31u;
+                const uint32_t hi = gr[(static_cast<uint32_t>(a.t0 - 1) & 255u) >> 5];
+                const uint32_t lo = gr[(static_cast<uint32_t>(a.t0 - 32) & 255u) >> 5];
+                const uint32_t m = (1u << q32) - 1u;
+                L.ring[j] = q32 == 0 ? hi : ((hi & m) | (lo & ~m));
+            }
+        }
+    }
+    __syncthreads();
+
+    for (int s = 0; s < a.n_steps; ++s) {
+        const int64_t t = a.t0 + s;
+        // ---- delivery: I_j(t) = sum of w over in-edges whose source fired at t - d
+        for (int q = q_begin; q < q_end; ++q) {
+            const NetMeta nm = a.meta[a.wg_nets[q]];
+            const NetLds L = carve(lds, nm, obs);
+            const uint32_t rmask = 32u * static_cast<uint32_t>(nm.words) - 1u;
+            for (int c = nm.chunk_begin + wave; c < nm.chunk_end; c += nwaves) {
+                const int64_t e0 = static_cast<int64_t>(c) * kChunkEdges + lane * kEdgesPerLane;
+                const u32x4 s_lo = *reinterpret_cast<const u32x4*>(a.src + e0);
+                const u32x4 s_hi = *reinterpret_cast<const u32x4*>(a.src + e0 + 4);
+                const u32x4 wq = *reinterpret_cast<const u32x4*>(a.w + e0);
+                const u32x2 dq = *reinterpret_cast<const u32x2*>(a.d + e0);
+                const uint32_t sv[8] = {s_lo.x, s_lo.y, s_lo.z, s_lo.w, s_hi.x, s_hi.y, s_hi.z, s_hi.w};
+                uint32_t fired = 0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const uint32_t sl = sv[k] - static_cast<uint32_t>(nm.node_off);
+                    const uint32_t dk = ((k < 4 ? dq.x : dq.y) >> (8 * (k & 3))) & 0xFFu;
+                    const uint32_t slot = (static_cast<uint32_t>(t) - dk) & rmask;
+                    const uint32_t word = L.ring[sl * static_cast<uint32_t>(nm.words) + (slot >> 5)];
+                    fired |= ((word >> (slot & 31u)) & 1u) << k;
+                }
+                if (wave_ballot(fired != 0)) {
+                    const uint32_t rs = a.rowstart[static_cast<int64_t>(c) * 64 + lane];
+                    const uint32_t bits = lane == 0 ? (rs & ~1u) : rs;
+                    const uint32_t before = wave_exclusive_sum(__popc(bits), lane);
+                    const int32_t row0 = a.chunk_row0[c] - nm.node_off + static_cast<int32_t>(before);
+                    const uint32_t wv[4] = {wq.x, wq.y, wq.z, wq.w};
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        if ((fired >> k) & 1u) {
+                            const int32_t row = row0 + __popc(bits & ((2u << k) - 1u));
+                            atomicAdd(L.I + row, half_bits_to_float((wv[k >> 1] >> (16 * (k & 1))) & 0xFFFFu));
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // ---- vertex update (same rules as node_update_kernel)
+        for (int q = q_begin; q < q_end; ++q) {
+            const int m = a.wg_nets[q];
+            const NetMeta nm = a.meta[m];
+            const NetParams p = a.params[m];
+            const NetLds L = carve(lds, nm, obs);
+            const uint32_t rmask = 32u * static_cast<uint32_t>(nm.words) - 1u;
+            for (int base = 0; base < nm.n_nodes; base += blockDim.x) {
+                const int j = base + tid;
+                const bool valid = j < nm.n_nodes;
+                const int jj = valid ? j : 0;
+                const int64_t u = nm.node_off + jj;
+                const float v = L.V[jj];
+                const uint32_t age = L.age[jj];
+                const float in = L.I[jj];
+                const bool spike = valid && v >= p.v_th;
+                const uint64_t spikes = wave_ballot(spike);
+                const uint64_t alive = wave_ballot(valid);
+                if (a.rec_raster && lane == 0 && alive != 0)
+                    put_bits_shared(a.rec_raster + s * a.raster_words, nm.node_off + base + wave * 64, spikes, alive);
+                float vn;
+                uint32_t age_n;
+                const bool held = age >= 1u && age <= static_cast<uint32_t>(p.n_ref);
+                if (spike) {
+                    vn = p.v_reset;
+                    age_n = 1u;
+                } else {
+                    age_n = age >= static_cast<uint32_t>(kAgeNever) ? kAgeNever : age + 1u;
+                    if (held) {
+                        vn = p.v_reset;
+                    } else {
+                        float uu = a.i_ext ? a.i_ext[u] : 0.0f;
+                        float noise = 0.0f;
+                        const uint32_t thr = a.drive_thr ? a.drive_thr[u] : 0u;
+                        if (thr != 0u || p.sigma != 0.0f) {
+                            const uint4 r = philox(make_uint4(static_cast<uint32_t>(jj), static_cast<uint32_t>(t),
+                                                              static_cast<uint32_t>(static_cast<uint64_t>(t) >> 32), 0u),
+                                                   p.key_lo, p.key_hi);
+                            if (r.x < thr) uu += p.drive_amp;
+                            if (p.sigma != 0.0f) noise = p.sigma * gaussian(r.y, r.z);
+                        }
+                        vn = v + p.decay * (p.v_rest - v) + in + uu + noise;
+                    }
+                }
+                if (valid) {
+                    if (a.rec_v) a.rec_v[s * a.n_total + u] = v;
+                    if (a.rec_input) a.rec_input[s * a.n_total + u] = in;
+                    L.I[j] = 0.0f;
+                    const uint32_t slot = static_cast<uint32_t>(t) & rmask;
+                    uint32_t* wp = L.ring + j * nm.words + (slot >> 5);
+                    const uint32_t mb = 1u << (slot & 31u);
+                    *wp = spike ? (*wp | mb) : (*wp & ~mb);
+                    L.V[j] = vn;
+                    L.age[j] = age_n;
+                    if (obs) {
+                        const float c = L.c[j];
+                        float acc = L.acc[j] + c;
+                        const int64_t f_now = t * a.frame_num / a.frame_den;
+                        const int64_t f_next = (t + 1) * a.frame_num / a.frame_den;
+                        if (f_next != f_now) {
+                            const int64_t first = (f_now * a.frame_den + a.frame_num - 1) / a.frame_num;
+                            const int64_t next = ((f_now + 1) * a.frame_den + a.frame_num - 1) / a.frame_num;
+                            if (f_now < a.frame_cap)
+                                a.frames[f_now * a.n_pad + u] = acc / static_cast<float>(next - first);
+                            acc = 0.0f;
+                        }
+                        L.acc[j] = acc;
+                        L.c[j] = c + p.dt * (-c * p.inv_tau_c + (spike ? 1.0f : 0.0f));
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- write the state back (global ring in the 256-step layout, summary)
+    const int64_t t1 = a.t0 + a.n_steps;
+    for (int q = q_begin; q < q_end; ++q) {
+        const NetMeta nm = a.meta[a.wg_nets[q]];
+        const NetLds L = carve(lds, nm, obs);
+        for (int base = 0; base < nm.n_nodes; base += blockDim.x) {
+            const int j = base + tid;
+            const bool valid = j < nm.n_nodes;
+            const int64_t u = nm.node_off + (valid ? j : 0);
+            const uint32_t age = valid ? L.age[j] : 255u;
+            const uint64_t recent = wave_ballot(valid && age <= static_cast<uint32_t>(a.d_sum));
+            const uint64_t alive = wave_ballot(valid);
+            if (lane == 0 && alive != 0)
+                put_bits_shared(reinterpret_cast<uint64_t*>(a.summary), nm.node_off + base + wave * 64, recent, alive);
+            if (!valid) continue;
+            a.V[u] = L.V[j];
+            a.age[u] = static_cast<uint8_t>(age);
+            if (obs) {
+                a.calcium[u] = L.c[j];
+                a.frame_acc[u] = L.acc[j];
+            }
+            uint32_t* gr = a.ring + u * kRingWords;
+            if (nm.words == kRingWords) {
+#pragma unroll
+                for (int k = 0; k < kRingWords; ++k) gr[k] = L.ring[j * kRingWords + k];
+            } else {
+                const uint32_t q32 = static_cast<uint32_t>(t1) & 31u;
+                const uint32_t r = L.ring[j];
+                const uint32_t ihi = (static_cast<uint32_t>(t1 - 1) & 255u) >> 5;
+                const uint32_t ilo = (static_cast<uint32_t>(t1 - 32) & 255u) >> 5;
+                if (q32 == 0) {
+                    gr[ihi] = r;
+                } else {
+                    const uint32_t m = (1u << q32) - 1u;
+                    gr[ihi] = (gr[ihi] & ~m) | (r & m);
+                    gr[ilo] = (gr[ilo] & m) | (r & ~m);
+                }
+            }
+        }
+    }
+}
+
 struct ObserveArgs {
     const float* __restrict__ V;
     const uint8_t* __restrict__ age;
@@ -320,13 +599,21 @@ hipError_t configure_deliver(const DeviceGraph& g, const net_build_opts* opts, L
     if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
     const size_t summary_bytes = static_cast<size_t>(g.n_pad / 8);
-    const bool want_lds = !(opts && (opts->flags & NET_BUILD_NO_LDS_SUMMARY));
+    const int flags = opts ? opts->flags : 0;
+    const bool want_lds = !(flags & NET_BUILD_NO_LDS_SUMMARY);
     lc.lds_summary = want_lds && summary_bytes <= static_cast<size_t>(lds_max);
     lc.lds_bytes = lc.lds_summary ? summary_bytes : 0;
+    lc.prefetch = !(flags & NET_BUILD_DELIVER_NO_PREFETCH);
+    lc.nontemporal = !(flags & NET_BUILD_DELIVER_CACHED);
     if (lc.lds_summary) {
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&deliver_kernel<true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(summary_bytes));
-        if (e != hipSuccess) return e;
+        const void* fns[4] = {reinterpret_cast<const void*>(&deliver_kernel<true, false, false>),
+                              reinterpret_cast<const void*>(&deliver_kernel<true, false, true>),
+                              reinterpret_cast<const void*>(&deliver_kernel<true, true, false>),
+                              reinterpret_cast<const void*>(&deliver_kernel<true, true, true>)};
+        for (const void* f : fns) {
+            e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(summary_bytes));
+            if (e != hipSuccess) return e;
+        }
     }
     // Workgroups per CU limited by the summary held in LDS (160 KiB per CU).
     int per_cu = 8;
@@ -362,10 +649,22 @@ hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t 
     a.summary_vec4 = static_cast<int32_t>(g.n_pad / 128);
     a.t = static_cast<uint32_t>(t);
     const dim3 grid(lc.deliver_blocks), block(lc.deliver_threads);
-    if (lc.lds_summary)
-        hipExtLaunchKernelGGL(deliver_kernel<true>, grid, block, lc.lds_bytes, s, ev0, ev1, 0, a);
-    else
-        hipExtLaunchKernelGGL(deliver_kernel<false>, grid, block, 0, s, ev0, ev1, 0, a);
+    const int v = (lc.lds_summary ? 4 : 0) | (lc.prefetch ? 2 : 0) | (lc.nontemporal ? 1 : 0);
+    switch (v) {
+#define GEONET_DELIVER_CASE(L, P, N)                                                                        \
+    case (L ? 4 : 0) | (P ? 2 : 0) | (N ? 1 : 0):                                                           \
+        hipExtLaunchKernelGGL((deliver_kernel<L, P, N>), grid, block, L ? lc.lds_bytes : 0, s, ev0, ev1, 0, a); \
+        break;
+        GEONET_DELIVER_CASE(false, false, false)
+        GEONET_DELIVER_CASE(false, false, true)
+        GEONET_DELIVER_CASE(false, true, false)
+        GEONET_DELIVER_CASE(false, true, true)
+        GEONET_DELIVER_CASE(true, false, false)
+        GEONET_DELIVER_CASE(true, false, true)
+        GEONET_DELIVER_CASE(true, true, false)
+        GEONET_DELIVER_CASE(true, true, true)
+#undef GEONET_DELIVER_CASE
+    }
     return hipGetLastError();
 }
 
@@ -433,6 +732,50 @@ hipError_t launch_observe(const DeviceGraph& g, int32_t what, const net_fluor_pa
     const int threads = 256;
     hipLaunchKernelGGL(observe_kernel, dim3((total + threads - 1) / threads), dim3(threads), 0, s, a);
     return hipGetLastError();
+}
+
+
+hipError_t launch_ensemble(const DeviceGraph& g, const EnsemblePlan& plan, int64_t t0, int32_t n_steps,
+                           const net_record* rec, int32_t frame_num, int32_t frame_den, hipStream_t s,
+                           hipEvent_t ev0, hipEvent_t ev1) {
+    EnsembleArgs a;
+    a.src = g.src;
+    a.w = g.w;
+    a.d = g.d;
+    a.rowstart = g.rowstart;
+    a.chunk_row0 = g.chunk_row0;
+    a.meta = plan.meta;
+    a.wg_nets = plan.wg_nets;
+    a.wg_off = plan.wg_off;
+    a.params = g.params;
+    a.drive_thr = g.drive_thr;
+    a.i_ext = g.i_ext;
+    a.V = g.V;
+    a.age = g.age;
+    a.ring = g.ring;
+    a.summary = g.summary;
+    a.calcium = (g.calcium && frame_num > 0) ? g.calcium : nullptr;
+    a.frame_acc = g.frame_acc;
+    a.frames = g.frames;
+    a.rec_raster = rec ? rec->raster : nullptr;
+    a.rec_v = rec ? rec->v : nullptr;
+    a.rec_input = rec ? rec->input : nullptr;
+    a.t0 = t0;
+    a.n_total = g.n_total;
+    a.n_pad = g.n_pad;
+    a.raster_words = (g.n_total + 63) / 64;
+    a.n_steps = n_steps;
+    a.frame_cap = g.frame_cap;
+    a.frame_num = frame_num > 0 ? frame_num : 1;
+    a.frame_den = frame_den > 0 ? frame_den : 1;
+    a.d_sum = g.d_sum;
+    hipExtLaunchKernelGGL(ensemble_kernel, dim3(plan.blocks), dim3(plan.threads), plan.lds_bytes, s, ev0, ev1, 0, a);
+    return hipGetLastError();
+}
+
+hipError_t enable_ensemble_lds(size_t bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&ensemble_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
 }
 
 }  // namespace geonet

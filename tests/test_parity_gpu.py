@@ -171,3 +171,82 @@ def test_split_steps_equal_one_call():
     p2 = net2.step(400, v=True)["v"]
     torch.cuda.synchronize()
     assert torch.equal(whole, torch.cat([p1, p2]))
+
+
+def _ensemble_specs(sizes, seed_base=1, w0=0.36, sigma=0.05, three_d=False):
+    specs = []
+    for k, n in enumerate(sizes):
+        if three_d:
+            s = synth.config1(seed=synth.config_seed(1, 100 + k), n=n)
+        else:
+            s = synth.config0_like(n, synth.config_seed(3, seed_base + k), w0=w0)
+            s.noise_sigma = sigma
+        specs.append(s)
+    return specs
+
+
+def test_ensemble_kernel_equals_per_step():
+    gn, torch = _gn()
+    specs = _ensemble_specs([64, 90, 1500, 300, 2048, 700, 128, 77, 1024, 400])
+    T = 1500
+    a = run_gpu(specs, T)
+    b = run_gpu(specs, T, flags=gn.NET_BUILD_PER_STEP)
+    assert a["net"].info()["n_nets"] == len(specs)
+    for key in ("raster", "v", "input"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_ensemble_kernel_long_delays_and_split_calls():
+    gn, torch = _gn()
+    specs = _ensemble_specs([512, 700, 300], three_d=True)      # delays above 31 steps
+    net1 = gn.Net(specs)
+    whole = net1.step(900, raster=True, v=True)
+    net2 = gn.Net(specs)
+    parts = [net2.step(k, raster=True, v=True) for k in (37, 300, 563)]   # boundaries off the 32-step grid
+    torch.cuda.synchronize()
+    assert torch.equal(whole["v"], torch.cat([p["v"] for p in parts]))
+    assert torch.equal(whole["raster"], torch.cat([p["raster"] for p in parts]))
+    o = [oracle.OracleNet(s).step(900, v=True, inp=False) for s in specs]
+    offs = net1.node_offsets()
+    r = gn.unpack_raster(whole["raster"], net1.n_total)
+    v = whole["v"].cpu().numpy()
+    for k, s in enumerate(specs):
+        sl = slice(offs[k], offs[k + 1])
+        assert jaccard(r[:, sl].astype(bool), o[k]["raster"].astype(bool)) >= JACCARD_MIN
+        assert np.abs(v[:900, sl] - o[k]["v"]).max() <= V_TOL
+
+
+def test_observation_frames_and_fluorescence():
+    gn, torch = _gn()
+    spec = synth.config0_like(256, synth.config_seed(4, 0), w0=0.36)
+    spec.noise_sigma = 0.05
+    T = 3400                                  # 10 complete frames at 30 Hz
+    net = gn.Net(spec, frame_capacity=16)
+    net.step(T)
+    nf = net.info()["frames_done"]
+    assert nf == 10
+    fr = net.observe(gn.NET_OBS_FRAMES, frames=nf).cpu().numpy().astype(np.float64)
+    F = net.observe(gn.NET_OBS_FLUOR, frames=nf, gain=2.0, offset=0.5, gamma=0.01).cpu().numpy()
+    ca = net.observe(gn.NET_OBS_CALCIUM).cpu().numpy()
+    o = oracle.OracleNet(spec, frames_cap=16)
+    o.step(T)
+    ofr = o.frames()
+    assert ofr.shape == fr.shape
+    assert np.abs(fr - ofr).max() <= 1e-6 * max(1.0, np.abs(ofr).max())
+    assert np.abs(ca - o.calcium()).max() <= 1e-6
+    oF = oracle.fluorescence(ofr, 2.0, 0.5, 0.01, spec.seed)
+    assert np.abs(F - oF).max() <= 1e-5
+    assert ofr.max() > 0.0
+
+
+def test_ensemble_observation_matches_per_step():
+    gn, torch = _gn()
+    specs = _ensemble_specs([256, 600, 90])
+    outs = []
+    for flags in (0, gn.NET_BUILD_PER_STEP):
+        net = gn.Net(specs, frame_capacity=8, flags=flags)
+        net.step(2100)
+        nf = net.info()["frames_done"]
+        outs.append(net.observe(gn.NET_OBS_FRAMES, frames=nf).cpu().numpy())
+    assert outs[0].shape[0] == 6
+    assert np.array_equal(outs[0], outs[1])
