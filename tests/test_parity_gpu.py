@@ -196,9 +196,11 @@ def test_ensemble_kernel_equals_per_step():
         assert np.array_equal(a[key], b[key]), key
 
 
-def test_ensemble_kernel_long_delays_and_split_calls():
+@pytest.mark.parametrize("three_d", [False, True])
+def test_ensemble_kernel_split_calls(three_d):
     gn, torch = _gn()
-    specs = _ensemble_specs([512, 700, 300], three_d=True)      # delays above 31 steps
+    # 2D: delays <= 15 steps (32-step LDS ring); 3D: delays above 31 (256-step ring)
+    specs = _ensemble_specs([512, 700, 300], three_d=three_d)
     net1 = gn.Net(specs)
     whole = net1.step(900, raster=True, v=True)
     net2 = gn.Net(specs)
