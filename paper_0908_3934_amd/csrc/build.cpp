@@ -283,8 +283,8 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
         p.v_th = d.v_th;
         p.sigma = d.noise_sigma;
         p.drive_amp = d.drive_amp;
-        p.dt = static_cast<float>(d.dt_ms);
-        p.inv_tau_c = d.tau_c_ms > 0.0f ? 1.0f / d.tau_c_ms : 0.0f;
+        p.dt_d = d.dt_ms;
+        p.tau_c_d = d.tau_c_ms > 0.0f ? static_cast<double>(d.tau_c_ms) : 1e300;
         p.n_ref = d.n_ref;
         p.key_lo = static_cast<uint32_t>(d.seed);
         p.key_hi = static_cast<uint32_t>(d.seed >> 32);

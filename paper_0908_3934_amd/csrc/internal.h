@@ -24,10 +24,10 @@ struct NetParams {
     float decay;        // dt / tau
     float v_rest, v_reset, v_th;
     float sigma, drive_amp;
-    float dt, inv_tau_c;
     int32_t n_ref;
     uint32_t key_lo, key_hi;
     int32_t node_off;   // first vertex of the network in the ensemble numbering
+    double dt_d, tau_c_d;   // calcium transition in double precision
 };
 
 // Per-network description used by the ensemble kernel.
@@ -87,8 +87,8 @@ struct DeviceGraph {
     float* I;
     uint32_t* ring;               // [n_pad * kRingWords]
     uint32_t* summary;            // [n_pad / 32]
-    float* calcium;               // null when observation is off
-    float* frame_acc;
+    double* calcium;              // null when observation is off
+    double* frame_acc;
     float* frames;                // [frame_cap][n_pad]
     int32_t frame_cap;
     NetParams p0;                 // parameters of network 0 (fast path)
@@ -115,7 +115,7 @@ struct EnsemblePlan {
 
 // LDS bytes one network needs in the ensemble kernel.
 inline size_t ensemble_lds_bytes(int64_t n_nodes, int words, bool observe) {
-    const size_t per = 4 * 3 + 4 * static_cast<size_t>(words) + (observe ? 8 : 0);   // V, I, age, ring, c, acc
+    const size_t per = 4 * 3 + 4 * static_cast<size_t>(words) + (observe ? 16 : 0);   // V, I, age, ring, c, acc
     return (static_cast<size_t>(n_nodes) * per + 15) / 16 * 16;
 }
 

@@ -195,8 +195,8 @@ struct NodeArgs {
     const int32_t* __restrict__ net_id;
     const uint32_t* __restrict__ drive_thr;
     const float* __restrict__ i_ext;
-    float* __restrict__ calcium;
-    float* __restrict__ frame_acc;
+    double* __restrict__ calcium;
+    double* __restrict__ frame_acc;
     float* __restrict__ frames;
     uint64_t* __restrict__ rec_raster;
     float* __restrict__ rec_v;
@@ -263,14 +263,16 @@ __global__ void __launch_bounds__(256) node_update_kernel(NodeArgs a) {
         a.V[j] = vn;
         a.age[j] = static_cast<uint8_t>(age_n);
         if (a.calcium) {
-            const float c = a.calcium[j];
-            float acc = a.frame_acc[j] + c;
+            // calcium and its frame sum in FP64: tau_c / dt is thousands of steps
+            const double c = a.calcium[j];
+            double acc = a.frame_acc[j] + c;
             if (a.frame_flush) {
-                if (a.frame_index < a.frame_cap) a.frames[a.frame_index * a.n_pad + j] = acc / static_cast<float>(a.frame_steps);
-                acc = 0.0f;
+                if (a.frame_index < a.frame_cap)
+                    a.frames[a.frame_index * a.n_pad + j] = static_cast<float>(acc / static_cast<double>(a.frame_steps));
+                acc = 0.0;
             }
             a.frame_acc[j] = acc;
-            a.calcium[j] = c + p.dt * (-c * p.inv_tau_c + (spike ? 1.0f : 0.0f));
+            a.calcium[j] = c + p.dt_d * (-c / p.tau_c_d + (spike ? 1.0 : 0.0));
         }
     }
 }
@@ -302,8 +304,8 @@ struct EnsembleArgs {
     uint8_t* __restrict__ age;
     uint32_t* __restrict__ ring;
     uint32_t* __restrict__ summary;
-    float* __restrict__ calcium;
-    float* __restrict__ frame_acc;
+    double* __restrict__ calcium;
+    double* __restrict__ frame_acc;
     float* __restrict__ frames;
     uint64_t* __restrict__ rec_raster;
     float* __restrict__ rec_v;
@@ -313,23 +315,23 @@ struct EnsembleArgs {
 };
 
 struct NetLds {
+    double* c;      // first: 8-byte aligned (lds_off is a multiple of 16)
+    double* acc;
     float* V;
     float* I;
     uint32_t* age;
     uint32_t* ring;
-    float* c;
-    float* acc;
 };
 
 __device__ __forceinline__ NetLds carve(uint8_t* base, const NetMeta& nm, bool obs) {
     NetLds L;
     const int n = nm.n_nodes;
-    L.V = reinterpret_cast<float*>(base + nm.lds_off);
+    L.c = reinterpret_cast<double*>(base + nm.lds_off);
+    L.acc = obs ? L.c + n : L.c;
+    L.V = reinterpret_cast<float*>(obs ? L.acc + n : L.c);
     L.I = L.V + n;
     L.age = reinterpret_cast<uint32_t*>(L.I + n);
     L.ring = L.age + n;
-    L.c = reinterpret_cast<float*>(L.ring + static_cast<int64_t>(n) * nm.words);
-    L.acc = obs ? L.c + n : L.c;
     return L;
 }
 
@@ -481,19 +483,19 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
                     L.V[j] = vn;
                     L.age[j] = age_n;
                     if (obs) {
-                        const float c = L.c[j];
-                        float acc = L.acc[j] + c;
+                        const double c = L.c[j];
+                        double acc = L.acc[j] + c;
                         const int64_t f_now = t * a.frame_num / a.frame_den;
                         const int64_t f_next = (t + 1) * a.frame_num / a.frame_den;
                         if (f_next != f_now) {
                             const int64_t first = (f_now * a.frame_den + a.frame_num - 1) / a.frame_num;
                             const int64_t next = ((f_now + 1) * a.frame_den + a.frame_num - 1) / a.frame_num;
                             if (f_now < a.frame_cap)
-                                a.frames[f_now * a.n_pad + u] = acc / static_cast<float>(next - first);
-                            acc = 0.0f;
+                                a.frames[f_now * a.n_pad + u] = static_cast<float>(acc / static_cast<double>(next - first));
+                            acc = 0.0;
                         }
                         L.acc[j] = acc;
-                        L.c[j] = c + p.dt * (-c * p.inv_tau_c + (spike ? 1.0f : 0.0f));
+                        L.c[j] = c + p.dt_d * (-c / p.tau_c_d + (spike ? 1.0 : 0.0));
                     }
                 }
             }
@@ -546,7 +548,7 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
 struct ObserveArgs {
     const float* __restrict__ V;
     const uint8_t* __restrict__ age;
-    const float* __restrict__ calcium;
+    const double* __restrict__ calcium;
     const float* __restrict__ frames;
     const NetParams* __restrict__ params;
     const int32_t* __restrict__ net_id;
@@ -572,7 +574,7 @@ __global__ void __launch_bounds__(256) observe_kernel(ObserveArgs a) {
             break;
         }
         case NET_OBS_CALCIUM:
-            static_cast<float*>(a.out)[j] = a.calcium[j];
+            static_cast<float*>(a.out)[j] = static_cast<float>(a.calcium[j]);
             break;
         case NET_OBS_FRAMES:
             static_cast<float*>(a.out)[idx] = a.frames[f * a.n_pad + j];
@@ -581,7 +583,9 @@ __global__ void __launch_bounds__(256) observe_kernel(ObserveArgs a) {
             const uint32_t jl = static_cast<uint32_t>(j - p.node_off);
             const uint4 r = philox(make_uint4(jl, static_cast<uint32_t>(f), static_cast<uint32_t>(f >> 32), 1u),
                                    p.key_lo, p.key_hi);
-            static_cast<float*>(a.out)[idx] = a.gain * a.frames[f * a.n_pad + j] + a.offset + a.gamma * gaussian(r.x, r.y);
+            const double F = static_cast<double>(a.gain) * a.frames[f * a.n_pad + j] + static_cast<double>(a.offset) +
+                             static_cast<double>(a.gamma) * static_cast<double>(gaussian(r.x, r.y));
+            static_cast<float*>(a.out)[idx] = static_cast<float>(F);
             break;
         }
         default:
