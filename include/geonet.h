@@ -111,10 +111,12 @@ typedef struct {
 
 /* Build flags (variants that compute the same result; for tuning/measurement). */
 #define NET_BUILD_NO_LDS_SUMMARY 1        /* keep the recent-spike summary in global memory */
-#define NET_BUILD_DELIVER_NO_PREFETCH 2   /* delivery: no prefetch of the next edge chunk */
-#define NET_BUILD_DELIVER_CACHED 4        /* delivery: ordinary (not non-temporal) edge loads */
+#define NET_BUILD_DELIVER_PREFETCH 2      /* delivery: prefetch the next edge chunks */
+#define NET_BUILD_DELIVER_NONTEMPORAL 4   /* delivery: non-temporal edge loads */
 #define NET_BUILD_PER_STEP 8              /* ensembles: per-step kernels instead of the
                                              single-launch ensemble kernel */
+#define NET_BUILD_DELIVER_UNROLL1 16      /* delivery: one 512-edge chunk per wave iteration
+                                             (default two) */
 
 /*
  * Optional per-step records for net_step_n (device pointers, may be NULL).

@@ -17,9 +17,10 @@ NET_E_STATE = -5
 NET_E_UNSUPPORTED = -6
 
 NET_BUILD_NO_LDS_SUMMARY = 1
-NET_BUILD_DELIVER_NO_PREFETCH = 2
-NET_BUILD_DELIVER_CACHED = 4
+NET_BUILD_DELIVER_PREFETCH = 2
+NET_BUILD_DELIVER_NONTEMPORAL = 4
 NET_BUILD_PER_STEP = 8
+NET_BUILD_DELIVER_UNROLL1 = 16
 
 NET_OBS_V = 1
 NET_OBS_REF = 2

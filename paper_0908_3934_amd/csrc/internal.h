@@ -98,8 +98,9 @@ struct LaunchConfig {
     int deliver_blocks = 0;
     int deliver_threads = 0;
     bool lds_summary = false;
-    bool prefetch = true;
-    bool nontemporal = true;
+    bool prefetch = false;
+    bool nontemporal = false;
+    int unroll = 2;
     size_t lds_bytes = 0;
 };
 

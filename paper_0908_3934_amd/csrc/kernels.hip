@@ -112,7 +112,29 @@ __device__ __forceinline__ void load_chunk(ChunkRegs& x, const DeliverArgs& a, i
     x.rs = a.rowstart[c * 64 + lane];
 }
 
-template <bool kLdsSummary, bool kPrefetch, bool kNT>
+// Row of each fired slot from the row-start bits (position 0 of the chunk
+// belongs to chunk_row0 whether or not it opens a row), then one exact FP32
+// atomic add per arrival.  All partial sums of a row are exact in FP32, so
+// the order of these additions does not change the result.
+__device__ __forceinline__ void deliver_fired(const DeliverArgs& a, int64_t c, int lane, uint32_t fired, uint32_t rs,
+                                              const u32x4& wq) {
+    const uint32_t bits = lane == 0 ? (rs & ~1u) : rs;
+    const uint32_t before = wave_exclusive_sum(__popc(bits), lane);
+    const int32_t row0 = a.chunk_row0[c] + static_cast<int32_t>(before);
+    const uint32_t wv[4] = {wq.x, wq.y, wq.z, wq.w};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if ((fired >> k) & 1u) {
+            const int32_t row = row0 + __popc(bits & ((2u << k) - 1u));
+            unsafeAtomicAdd(a.I + row, half_bits_to_float((wv[k >> 1] >> (16 * (k & 1))) & 0xFFFFu));
+        }
+    }
+}
+
+// kUnroll chunks per wave iteration: all their stream loads are issued
+// before the first wait, and all their history gathers before the second,
+// so a wave keeps kUnroll chunks of loads in flight.
+template <bool kLdsSummary, bool kPrefetch, bool kNT, int kUnroll>
 __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
     extern __shared__ uint4 lds_summary4[];
     const uint32_t* lds_summary = reinterpret_cast<const uint32_t*>(lds_summary4);
@@ -125,62 +147,69 @@ __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
     const int64_t c_begin = static_cast<int64_t>(lb) * a.n_chunks / nb;
     const int64_t c_end = static_cast<int64_t>(lb + 1) * a.n_chunks / nb;
     const uint32_t t = a.t;
+    const int64_t stride = static_cast<int64_t>(nwaves) * kUnroll;
 
-    int64_t c = c_begin + wave;
-    ChunkRegs cur;
-    if (kPrefetch && c < c_end) load_chunk<kNT>(cur, a, c, lane);
+    int64_t c = c_begin + static_cast<int64_t>(wave) * kUnroll;
+    ChunkRegs cur[kUnroll];
+    if (kPrefetch) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t cu = c + u < c_end ? c + u : c_end - 1;
+            if (c < c_end) load_chunk<kNT>(cur[u], a, cu, lane);
+        }
+    }
     if (kLdsSummary) {
         const uint4* g = reinterpret_cast<const uint4*>(a.summary);
         for (int i = threadIdx.x; i < a.summary_vec4; i += blockDim.x) lds_summary4[i] = g[i];
         __syncthreads();
     }
 
-    for (; c < c_end; c += nwaves) {
-        if (!kPrefetch) load_chunk<kNT>(cur, a, c, lane);
-        const uint32_t sv[8] = {cur.s_lo.x, cur.s_lo.y, cur.s_lo.z, cur.s_lo.w,
-                                cur.s_hi.x, cur.s_hi.y, cur.s_hi.z, cur.s_hi.w};
-        uint32_t slot[8], word[8];
-        uint32_t cand = 0;
+    for (; c < c_end; c += stride) {
+        // chunks beyond the range repeat the last one and are masked below
+        if (!kPrefetch) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const uint32_t s = sv[k];
-            const uint32_t sw = kLdsSummary ? lds_summary[s >> 5] : a.summary[s >> 5];
-            const uint32_t hit = (sw >> (s & 31)) & 1u;
-            const uint32_t dk = ((k < 4 ? cur.dq.x : cur.dq.y) >> (8 * (k & 3))) & 0xFFu;
-            slot[k] = (t - dk) & 0xFFu;
-            const uint32_t widx = hit ? s * kRingWords + (slot[k] >> 5) : 0u;
-            word[k] = a.ring[widx];
-            cand |= hit << k;
+            for (int u = 0; u < kUnroll; ++u) load_chunk<kNT>(cur[u], a, c + u < c_end ? c + u : c_end - 1, lane);
         }
-        const u32x4 wq = cur.wq;
-        const uint32_t rs = cur.rs;
-        // Unconditional (the last iteration reloads its own chunk) so that
-        // consuming the gathers never has to wait for these loads.
-        if (kPrefetch) {
-            const int64_t cn = (c + nwaves < c_end) ? c + nwaves : c;
-            load_chunk<kNT>(cur, a, cn, lane);
-        }
-
-        uint32_t fired = 0;
+        uint32_t slot[kUnroll][8], word[kUnroll][8], cand[kUnroll];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) fired |= (((cand >> k) & (word[k] >> (slot[k] & 31))) & 1u) << k;
-        if (wave_ballot(fired != 0)) {
-            // Row of each slot from the row-start bits (position 0 of the
-            // chunk belongs to chunk_row0 whether or not it opens a row).
-            const uint32_t bits = lane == 0 ? (rs & ~1u) : rs;
-            const uint32_t before = wave_exclusive_sum(__popc(bits), lane);
-            const int32_t row0 = a.chunk_row0[c] + static_cast<int32_t>(before);
-            const uint32_t wv[4] = {wq.x, wq.y, wq.z, wq.w};
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint32_t sv[8] = {cur[u].s_lo.x, cur[u].s_lo.y, cur[u].s_lo.z, cur[u].s_lo.w,
+                                    cur[u].s_hi.x, cur[u].s_hi.y, cur[u].s_hi.z, cur[u].s_hi.w};
+            cand[u] = 0;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                if ((fired >> k) & 1u) {
-                    const int32_t row = row0 + __popc(bits & ((2u << k) - 1u));
-                    const float wf = half_bits_to_float((wv[k >> 1] >> (16 * (k & 1))) & 0xFFFFu);
-                    // All partial sums of a row are exact in FP32, so the
-                    // order of these additions does not change the result.
-                    unsafeAtomicAdd(a.I + row, wf);
-                }
+                const uint32_t s = sv[k];
+                const uint32_t sw = kLdsSummary ? lds_summary[s >> 5] : a.summary[s >> 5];
+                const uint32_t hit = (sw >> (s & 31)) & 1u;
+                const uint32_t dk = ((k < 4 ? cur[u].dq.x : cur[u].dq.y) >> (8 * (k & 3))) & 0xFFu;
+                slot[u][k] = (t - dk) & 0xFFu;
+                const uint32_t widx = hit ? s * kRingWords + (slot[u][k] >> 5) : 0u;
+                word[u][k] = a.ring[widx];
+                cand[u] |= hit << k;
             }
+        }
+        u32x4 wq[kUnroll];
+        uint32_t rs[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            wq[u] = cur[u].wq;
+            rs[u] = cur[u].rs;
+        }
+        if (kPrefetch) {
+            // unconditional, so consuming the gathers never waits for these loads
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int64_t cn = c + stride + u;
+                load_chunk<kNT>(cur[u], a, cn < c_end ? cn : c_end - 1, lane);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            uint32_t fired = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) fired |= (((cand[u] >> k) & (word[u][k] >> (slot[u][k] & 31))) & 1u) << k;
+            if (c + u >= c_end) fired = 0;
+            if (wave_ballot(fired != 0)) deliver_fired(a, c + u, lane, fired, rs[u], wq[u]);
         }
     }
 }
@@ -607,13 +636,18 @@ hipError_t configure_deliver(const DeviceGraph& g, const net_build_opts* opts, L
     const bool want_lds = !(flags & NET_BUILD_NO_LDS_SUMMARY);
     lc.lds_summary = want_lds && summary_bytes <= static_cast<size_t>(lds_max);
     lc.lds_bytes = lc.lds_summary ? summary_bytes : 0;
-    lc.prefetch = !(flags & NET_BUILD_DELIVER_NO_PREFETCH);
-    lc.nontemporal = !(flags & NET_BUILD_DELIVER_CACHED);
+    lc.prefetch = (flags & NET_BUILD_DELIVER_PREFETCH) != 0;
+    lc.nontemporal = (flags & NET_BUILD_DELIVER_NONTEMPORAL) != 0;
+    lc.unroll = (flags & NET_BUILD_DELIVER_UNROLL1) ? 1 : 2;
     if (lc.lds_summary) {
-        const void* fns[4] = {reinterpret_cast<const void*>(&deliver_kernel<true, false, false>),
-                              reinterpret_cast<const void*>(&deliver_kernel<true, false, true>),
-                              reinterpret_cast<const void*>(&deliver_kernel<true, true, false>),
-                              reinterpret_cast<const void*>(&deliver_kernel<true, true, true>)};
+        const void* fns[8] = {reinterpret_cast<const void*>(&deliver_kernel<true, false, false, 1>),
+                              reinterpret_cast<const void*>(&deliver_kernel<true, false, true, 1>),
+                              reinterpret_cast<const void*>(&deliver_kernel<true, true, false, 1>),
+                              reinterpret_cast<const void*>(&deliver_kernel<true, true, true, 1>),
+                              reinterpret_cast<const void*>(&deliver_kernel<true, false, false, 2>),
+                              reinterpret_cast<const void*>(&deliver_kernel<true, false, true, 2>),
+                              reinterpret_cast<const void*>(&deliver_kernel<true, true, false, 2>),
+                              reinterpret_cast<const void*>(&deliver_kernel<true, true, true, 2>)};
         for (const void* f : fns) {
             e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(summary_bytes));
             if (e != hipSuccess) return e;
@@ -653,20 +687,25 @@ hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t 
     a.summary_vec4 = static_cast<int32_t>(g.n_pad / 128);
     a.t = static_cast<uint32_t>(t);
     const dim3 grid(lc.deliver_blocks), block(lc.deliver_threads);
-    const int v = (lc.lds_summary ? 4 : 0) | (lc.prefetch ? 2 : 0) | (lc.nontemporal ? 1 : 0);
+    const int v = (lc.unroll == 2 ? 8 : 0) | (lc.lds_summary ? 4 : 0) | (lc.prefetch ? 2 : 0) | (lc.nontemporal ? 1 : 0);
     switch (v) {
-#define GEONET_DELIVER_CASE(L, P, N)                                                                        \
-    case (L ? 4 : 0) | (P ? 2 : 0) | (N ? 1 : 0):                                                           \
-        hipExtLaunchKernelGGL((deliver_kernel<L, P, N>), grid, block, L ? lc.lds_bytes : 0, s, ev0, ev1, 0, a); \
+#define GEONET_DELIVER_CASE(U, L, P, N)                                                            \
+    case (U == 2 ? 8 : 0) | (L ? 4 : 0) | (P ? 2 : 0) | (N ? 1 : 0):                               \
+        hipExtLaunchKernelGGL((deliver_kernel<L, P, N, U>), grid, block, L ? lc.lds_bytes : 0, s, ev0, ev1, 0, \
+                              a);                                                                  \
         break;
-        GEONET_DELIVER_CASE(false, false, false)
-        GEONET_DELIVER_CASE(false, false, true)
-        GEONET_DELIVER_CASE(false, true, false)
-        GEONET_DELIVER_CASE(false, true, true)
-        GEONET_DELIVER_CASE(true, false, false)
-        GEONET_DELIVER_CASE(true, false, true)
-        GEONET_DELIVER_CASE(true, true, false)
-        GEONET_DELIVER_CASE(true, true, true)
+#define GEONET_DELIVER_CASES(U)              \
+    GEONET_DELIVER_CASE(U, false, false, false) \
+    GEONET_DELIVER_CASE(U, false, false, true)  \
+    GEONET_DELIVER_CASE(U, false, true, false)  \
+    GEONET_DELIVER_CASE(U, false, true, true)   \
+    GEONET_DELIVER_CASE(U, true, false, false)  \
+    GEONET_DELIVER_CASE(U, true, false, true)   \
+    GEONET_DELIVER_CASE(U, true, true, false)   \
+    GEONET_DELIVER_CASE(U, true, true, true)
+        GEONET_DELIVER_CASES(1)
+        GEONET_DELIVER_CASES(2)
+#undef GEONET_DELIVER_CASES
 #undef GEONET_DELIVER_CASE
     }
     return hipGetLastError();
