@@ -115,8 +115,8 @@ typedef struct {
 #define NET_BUILD_DELIVER_NONTEMPORAL 4   /* delivery: non-temporal edge loads */
 #define NET_BUILD_PER_STEP 8              /* ensembles: per-step kernels instead of the
                                              single-launch ensemble kernel */
-#define NET_BUILD_DELIVER_UNROLL1 16      /* delivery: one 512-edge chunk per wave iteration
-                                             (default two) */
+#define NET_BUILD_DELIVER_UNROLL2 16      /* delivery: two 512-edge chunks per wave iteration
+                                             (default one) */
 
 /*
  * Optional per-step records for net_step_n (device pointers, may be NULL).
@@ -139,6 +139,7 @@ typedef struct {
     int64_t t;              /* steps taken so far */
     int64_t frames_done;    /* completed camera frames */
     int32_t exact;          /* 1 if every FP32 delivery sum is provably exact */
+    int32_t summary_window; /* steps covered by the recent-spike filter */
     int32_t lds_summary;    /* 1 if the delivery kernel stages the summary in LDS */
     int32_t deliver_blocks, deliver_threads;
     int64_t device_bytes;   /* device memory held by the handle */

@@ -20,7 +20,7 @@ NET_BUILD_NO_LDS_SUMMARY = 1
 NET_BUILD_DELIVER_PREFETCH = 2
 NET_BUILD_DELIVER_NONTEMPORAL = 4
 NET_BUILD_PER_STEP = 8
-NET_BUILD_DELIVER_UNROLL1 = 16
+NET_BUILD_DELIVER_UNROLL2 = 16
 
 NET_OBS_V = 1
 NET_OBS_REF = 2
@@ -56,7 +56,7 @@ class Info(C.Structure):
     _fields_ = [
         ("n_total", C.c_int64), ("n_edges", C.c_int64), ("n_edges_stored", C.c_int64),
         ("n_nets", C.c_int32), ("max_delay", C.c_int32), ("raster_words", C.c_int64), ("t", C.c_int64),
-        ("frames_done", C.c_int64), ("exact", C.c_int32), ("lds_summary", C.c_int32),
+        ("frames_done", C.c_int64), ("exact", C.c_int32), ("summary_window", C.c_int32), ("lds_summary", C.c_int32),
         ("deliver_blocks", C.c_int32), ("deliver_threads", C.c_int32), ("device_bytes", C.c_int64),
     ]
 

@@ -215,7 +215,7 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
     g.n_chunks = hg.n_chunks;
     g.n_nets = n_nets;
     g.max_delay = hg.max_delay;
-    g.d_sum = hg.max_delay;
+    g.d_sum = hg.window;
     g.p0 = hg.params[0];
     const int32_t frame_cap = opts ? opts->frame_capacity : 0;
     g.frame_cap = frame_cap;
@@ -431,6 +431,7 @@ net_status net_info(const net_t* h, net_info_t* out) {
     out->n_edges_stored = h->g.e_slots;
     out->n_nets = h->g.n_nets;
     out->max_delay = h->g.max_delay;
+    out->summary_window = h->g.d_sum;
     out->raster_words = (h->g.n_total + 63) / 64;
     out->t = h->t;
     out->frames_done = h->frames_done;

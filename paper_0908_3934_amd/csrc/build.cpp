@@ -207,6 +207,21 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
         }
     }
     g.max_delay = max_delay;
+    // Summary window: the smallest W with at most 0.5 % of the edges longer
+    // than W (those edges bypass the recent-spike filter).
+    {
+        std::vector<int64_t> hist(256, 0);
+        for (int64_t s = 0; s < g.e_slots; ++s) hist[g.d[s]]++;
+        const int64_t allow = g.e_slots / 200;
+        int64_t above = 0;
+        int32_t w = max_delay;
+        for (int32_t d = max_delay; d >= 1; --d) {
+            if (above + hist[d] > allow) break;
+            above += hist[d];
+            w = d - 1;
+        }
+        g.window = std::max(w, 1);
+    }
     // Placeholders for empty rows, row-start bits, per-row order and exactness.
     const double two24 = 16777216.0;
     for (int64_t r = 0; r < N; ++r) {

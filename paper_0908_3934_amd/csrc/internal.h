@@ -45,6 +45,7 @@ struct HostGraph {
     int64_t e_slots = 0;          // stored slots incl. empty-row placeholders and padding
     int64_t n_chunks = 0;
     int32_t max_delay = 1;
+    int32_t window = 1;           // recent-spike summary window (steps)
     bool exact = true;
     std::vector<int32_t> src;     // [e_slots]
     std::vector<uint16_t> w;      // [e_slots] FP16 bits
@@ -72,7 +73,7 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
 // Device-side handle contents.
 struct DeviceGraph {
     int64_t n_total, n_pad, e_slots, n_chunks;
-    int32_t n_nets, max_delay, d_sum;
+    int32_t n_nets, max_delay, d_sum;   // d_sum: summary window W <= max_delay
     const int32_t* src;
     const uint16_t* w;
     const uint8_t* d;
@@ -85,7 +86,7 @@ struct DeviceGraph {
     float* V;
     uint8_t* age;
     float* I;
-    uint32_t* ring;               // [n_pad * kRingWords]
+    uint32_t* ring;               // [kRingWords][n_pad]: bit (s mod 32) of word (s mod 256)/32 = spike at step s
     uint32_t* summary;            // [n_pad / 32]
     double* calcium;              // null when observation is off
     double* frame_acc;

@@ -73,6 +73,8 @@ struct DeliverArgs {
     int64_t n_chunks;
     int32_t summary_vec4;   // summary size in 16-byte units
     uint32_t t;             // step index modulo 2^32 (only t mod 256 matters)
+    uint32_t n_pad;         // ring row length: word (slot/32, vertex) is at slot/32*n_pad + vertex
+    uint32_t window;        // summary window W: bit set iff the vertex fired in the last W steps
 };
 
 // One wave handles 512 consecutive slots per iteration: lane L owns slots
@@ -180,10 +182,11 @@ __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
             for (int k = 0; k < 8; ++k) {
                 const uint32_t s = sv[k];
                 const uint32_t sw = kLdsSummary ? lds_summary[s >> 5] : a.summary[s >> 5];
-                const uint32_t hit = (sw >> (s & 31)) & 1u;
                 const uint32_t dk = ((k < 4 ? cur[u].dq.x : cur[u].dq.y) >> (8 * (k & 3))) & 0xFFu;
+                // edges longer than the summary window always look at the history
+                const uint32_t hit = ((sw >> (s & 31)) & 1u) | (dk > a.window ? 1u : 0u);
                 slot[u][k] = (t - dk) & 0xFFu;
-                const uint32_t widx = hit ? s * kRingWords + (slot[u][k] >> 5) : 0u;
+                const uint32_t widx = hit ? (slot[u][k] >> 5) * a.n_pad + s : 0u;
                 word[u][k] = a.ring[widx];
                 cand[u] |= hit << k;
             }
@@ -256,7 +259,7 @@ __global__ void __launch_bounds__(256) node_update_kernel(NodeArgs a) {
         a.I[j] = 0.0f;
         // spike-history ring: bit (t mod 256) of vertex j
         const uint32_t slot = a.t_lo & 0xFFu;
-        uint32_t* wp = a.ring + j * kRingWords + (slot >> 5);
+        uint32_t* wp = a.ring + (slot >> 5) * a.n_pad + j;
         const uint32_t m = 1u << (slot & 31);
         *wp = spike ? (*wp | m) : (*wp & ~m);
     }
@@ -401,15 +404,15 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
                 L.c[j] = a.calcium[u];
                 L.acc[j] = a.frame_acc[u];
             }
-            const uint32_t* gr = a.ring + u * kRingWords;
+            const uint32_t* gr = a.ring + u;          // word b of vertex u at gr[b * n_pad]
             if (nm.words == kRingWords) {
 #pragma unroll
-                for (int k = 0; k < kRingWords; ++k) L.ring[j * kRingWords + k] = gr[k];
+                for (int k = 0; k < kRingWords; ++k) L.ring[j * kRingWords + k] = gr[k * a.n_pad];
             } else {
                 // steps t0-32 .. t0-1 into one word, bit = step mod 32
                 const uint32_t q32 = static_cast<uint32_t>(a.t0) & 31u;
-                const uint32_t hi = gr[(static_cast<uint32_t>(a.t0 - 1) & 255u) >> 5];
-                const uint32_t lo = gr[(static_cast<uint32_t>(a.t0 - 32) & 255u) >> 5];
+                const uint32_t hi = gr[((static_cast<uint32_t>(a.t0 - 1) & 255u) >> 5) * a.n_pad];
+                const uint32_t lo = gr[((static_cast<uint32_t>(a.t0 - 32) & 255u) >> 5) * a.n_pad];
                 const uint32_t m = (1u << q32) - 1u;
                 L.ring[j] = q32 == 0 ? hi : ((hi & m) | (lo & ~m));
             }
@@ -553,15 +556,15 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
                 a.calcium[u] = L.c[j];
                 a.frame_acc[u] = L.acc[j];
             }
-            uint32_t* gr = a.ring + u * kRingWords;
+            uint32_t* gr = a.ring + u;
             if (nm.words == kRingWords) {
 #pragma unroll
-                for (int k = 0; k < kRingWords; ++k) gr[k] = L.ring[j * kRingWords + k];
+                for (int k = 0; k < kRingWords; ++k) gr[k * a.n_pad] = L.ring[j * kRingWords + k];
             } else {
                 const uint32_t q32 = static_cast<uint32_t>(t1) & 31u;
                 const uint32_t r = L.ring[j];
-                const uint32_t ihi = (static_cast<uint32_t>(t1 - 1) & 255u) >> 5;
-                const uint32_t ilo = (static_cast<uint32_t>(t1 - 32) & 255u) >> 5;
+                const int64_t ihi = ((static_cast<uint32_t>(t1 - 1) & 255u) >> 5) * a.n_pad;
+                const int64_t ilo = ((static_cast<uint32_t>(t1 - 32) & 255u) >> 5) * a.n_pad;
                 if (q32 == 0) {
                     gr[ihi] = r;
                 } else {
@@ -638,7 +641,7 @@ hipError_t configure_deliver(const DeviceGraph& g, const net_build_opts* opts, L
     lc.lds_bytes = lc.lds_summary ? summary_bytes : 0;
     lc.prefetch = (flags & NET_BUILD_DELIVER_PREFETCH) != 0;
     lc.nontemporal = (flags & NET_BUILD_DELIVER_NONTEMPORAL) != 0;
-    lc.unroll = (flags & NET_BUILD_DELIVER_UNROLL1) ? 1 : 2;
+    lc.unroll = (flags & NET_BUILD_DELIVER_UNROLL2) ? 2 : 1;
     if (lc.lds_summary) {
         const void* fns[8] = {reinterpret_cast<const void*>(&deliver_kernel<true, false, false, 1>),
                               reinterpret_cast<const void*>(&deliver_kernel<true, false, true, 1>),
@@ -686,6 +689,8 @@ hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t 
     a.n_chunks = g.n_chunks;
     a.summary_vec4 = static_cast<int32_t>(g.n_pad / 128);
     a.t = static_cast<uint32_t>(t);
+    a.n_pad = static_cast<uint32_t>(g.n_pad);
+    a.window = static_cast<uint32_t>(g.d_sum);
     const dim3 grid(lc.deliver_blocks), block(lc.deliver_threads);
     const int v = (lc.unroll == 2 ? 8 : 0) | (lc.lds_summary ? 4 : 0) | (lc.prefetch ? 2 : 0) | (lc.nontemporal ? 1 : 0);
     switch (v) {
