@@ -25,6 +25,23 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_EDGE = 7      # int32 source + FP16 weight + uint8 delay, read once per step
 
 
+def measured_traffic():
+    """HBM bytes per delivery launch from the committed rocprofv3 counter
+    summary, if it was taken on the kernel source as it is now (else None)."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "deliver_config2.md")
+    src = os.path.join(ROOT, "paper_0908_3934_amd", "csrc", "kernels.hip")
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines()
+                      if line.startswith(("traffic_bytes_per_launch:", "kernels_hip_sha256_16:")))
+        if fields.get("kernels_hip_sha256_16", "").strip() != sha:
+            return None
+        return int(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -133,7 +150,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "avg_launch_us": avg_deliver_s * 1e6,
             "update_avg_launch_us": tm["update_ms"] / tm["update_launches"] * 1e3,
         },
