@@ -221,6 +221,38 @@ net_status net_info(const net_t* h, net_info_t* out);
 /* First vertex index of every network: host int64 [n_nets + 1]. */
 net_status net_node_offsets(const net_t* h, int64_t* out);
 
+/* ------------------------------------------------------------------------
+ * Learned edge scorer: an MLP 64 -> 256 -> 256 -> 1 (ReLU) on pair
+ * features, trained with binary cross-entropy on simulated networks whose
+ * edges are known; it proposes functional edges i -> j from observations
+ * (the inverse problem of Sections 1 and 4).  BF16 operands on the matrix
+ * cores, FP32 accumulation and master weights.  Rounding points: features,
+ * W1 and W2 to BF16; H1, H2 to BF16 after bias + ReLU; dH2, dH1 to BF16
+ * before they enter a matrix product; head, loss and gradients in FP32.
+ *
+ * Parameters are one flat FP32 vector of 82,689 values:
+ *   W1[64][256] | b1[256] | W2[256][256] | b2[256] | w3[256] | b3
+ * (W[k][n] row-major: input k, output n).  Features are FP32 [rows][64]
+ * row-major in device memory; labels FP32 0/1 [rows].  All calls run on
+ * `stream`; the activation workspace grows (with a stream synchronisation)
+ * when a call needs more rows than any earlier one.
+ * ------------------------------------------------------------------------ */
+typedef struct net_mlp net_mlp_t;
+
+net_status net_mlp_create(net_mlp_t** out);                 /* parameters zero */
+net_status net_mlp_set_params(net_mlp_t* m, const float* host_params, int64_t n);   /* resets Adam */
+net_status net_mlp_get_params(const net_mlp_t* m, float* host_params, int64_t n);
+/* logits_dev[r] = MLP(x_dev[r]) */
+net_status net_mlp_forward(net_mlp_t* m, const float* x_dev, int64_t rows, float* logits_dev, void* stream);
+/* gradient of the mean BCE over the rows into grad_dev [82,689] and loss_dev [1] (either may be NULL) */
+net_status net_mlp_grad(net_mlp_t* m, const float* x_dev, const float* y_dev, int64_t rows, float* grad_dev,
+                        float* loss_dev, void* stream);
+/* one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the mean BCE of the rows */
+net_status net_mlp_train_step(net_mlp_t* m, const float* x_dev, const float* y_dev, int64_t rows, float lr,
+                              float* loss_dev, void* stream);
+void net_mlp_free(net_mlp_t* m);
+const char* net_mlp_last_error(void);
+
 /* Release the handle and its device memory (waits for the handle's stream). */
 void net_free(net_t* h);
 

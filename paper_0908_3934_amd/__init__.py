@@ -20,7 +20,7 @@ from ._abi import (NET_BUILD_DELIVER_NONTEMPORAL, NET_BUILD_DELIVER_PREFETCH, NE
                    NET_BUILD_NO_LDS_SUMMARY, NET_BUILD_PER_STEP, NET_OBS_CALCIUM, NET_OBS_FLUOR, NET_OBS_FRAMES, NET_OBS_REF,
                    NET_OBS_V, NET_OK, NET_W_INEXACT)
 
-__all__ = ["Net", "GeonetError", "NET_OBS_V", "NET_OBS_REF", "NET_OBS_CALCIUM", "NET_OBS_FRAMES",
+__all__ = ["Net", "Mlp", "GeonetError", "NET_OBS_V", "NET_OBS_REF", "NET_OBS_CALCIUM", "NET_OBS_FRAMES",
            "NET_OBS_FLUOR", "NET_BUILD_NO_LDS_SUMMARY", "NET_BUILD_DELIVER_PREFETCH",
            "NET_BUILD_DELIVER_NONTEMPORAL", "NET_BUILD_DELIVER_UNROLL2", "NET_BUILD_PER_STEP", "library"]
 
@@ -218,6 +218,78 @@ class Net:
         _check(library().net_observe(self.h, what, C.byref(params) if params is not None else None,
                                      out.data_ptr(), out.numel() * 4, s), "net_observe")
         return out
+
+
+class Mlp:
+    """Edge-scoring MLP 64 -> 256 -> 256 -> 1 on the GPU (see include/geonet.h)."""
+
+    N_PARAMS = _abi.MLP_PARAMS
+
+    def __init__(self, params: Optional[np.ndarray] = None):
+        lib = library()
+        h = C.c_void_p()
+        self._check(lib.net_mlp_create(C.byref(h)), "net_mlp_create")
+        self.h = h
+        if params is not None:
+            self.set_params(params)
+
+    @staticmethod
+    def _check(st, where):
+        if st != NET_OK:
+            raise GeonetError(st, where, library().net_mlp_last_error().decode())
+
+    @staticmethod
+    def init_params(seed: int = 0) -> np.ndarray:
+        """He-uniform initial weights, zero biases."""
+        rng = np.random.default_rng(seed)
+        p = np.zeros(_abi.MLP_PARAMS, dtype=np.float32)
+        i, h = _abi.MLP_IN, _abi.MLP_H
+        o = 0
+        p[o:o + i * h] = rng.uniform(-1, 1, i * h) * np.sqrt(6.0 / i); o += i * h + h
+        p[o:o + h * h] = rng.uniform(-1, 1, h * h) * np.sqrt(6.0 / h); o += h * h + h
+        p[o:o + h] = rng.uniform(-1, 1, h) * np.sqrt(3.0 / h)
+        return p
+
+    def set_params(self, params: np.ndarray):
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(library().net_mlp_set_params(self.h, a.ctypes.data, a.size), "net_mlp_set_params")
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(_abi.MLP_PARAMS, dtype=np.float32)
+        self._check(library().net_mlp_get_params(self.h, out.ctypes.data, out.size), "net_mlp_get_params")
+        return out
+
+    def forward(self, x, stream=None):
+        import torch
+        assert x.is_cuda and x.dtype == torch.float32 and x.shape[1] == _abi.MLP_IN and x.is_contiguous()
+        out = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        self._check(library().net_mlp_forward(self.h, x.data_ptr(), x.shape[0], out.data_ptr(),
+                                              _stream_handle(stream)), "net_mlp_forward")
+        return out
+
+    def grad(self, x, y, stream=None):
+        import torch
+        g = torch.empty(_abi.MLP_PARAMS, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        self._check(library().net_mlp_grad(self.h, x.data_ptr(), y.data_ptr(), x.shape[0], g.data_ptr(),
+                                           loss.data_ptr(), _stream_handle(stream)), "net_mlp_grad")
+        return g, loss
+
+    def train_step(self, x, y, lr: float, loss=None, stream=None):
+        self._check(library().net_mlp_train_step(self.h, x.data_ptr(), y.data_ptr(), x.shape[0], float(lr),
+                                                 loss.data_ptr() if loss is not None else None,
+                                                 _stream_handle(stream)), "net_mlp_train_step")
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            library().net_mlp_free(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def unpack_raster(words, n: int) -> np.ndarray:

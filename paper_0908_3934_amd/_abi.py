@@ -86,7 +86,18 @@ SIGNATURES = {
     "net_timing_end": (C.c_int, [_vp, C.POINTER(Timing)]),
     "net_free": (None, [_vp]),
     "net_last_error": (C.c_char_p, []),
+    "net_mlp_create": (C.c_int, [C.POINTER(_vp)]),
+    "net_mlp_set_params": (C.c_int, [_vp, _vp, C.c_int64]),
+    "net_mlp_get_params": (C.c_int, [_vp, _vp, C.c_int64]),
+    "net_mlp_forward": (C.c_int, [_vp, _vp, C.c_int64, _vp, _vp]),
+    "net_mlp_grad": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, _vp, _vp]),
+    "net_mlp_train_step": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_float, _vp, _vp]),
+    "net_mlp_free": (None, [_vp]),
+    "net_mlp_last_error": (C.c_char_p, []),
 }
+
+MLP_PARAMS = 82689
+MLP_IN, MLP_H = 64, 256
 
 _lib = None
 

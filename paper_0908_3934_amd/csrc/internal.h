@@ -136,4 +136,37 @@ hipError_t launch_ensemble(const DeviceGraph& g, const EnsemblePlan& plan, int64
                            const net_record* rec, int32_t frame_num, int32_t frame_den, hipStream_t s,
                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
+// ---------------------------------------------------------------------------
+// Edge-scoring MLP 64 -> 256 -> 256 -> 1: flat FP32 parameter layout.
+// ---------------------------------------------------------------------------
+constexpr int kMlpIn = 64, kMlpH = 256;
+constexpr int kMlpW1Off = 0, kMlpW1 = kMlpIn * kMlpH;          // W1[k][n]
+constexpr int kMlpB1Off = kMlpW1Off + kMlpW1;                   // b1[256]
+constexpr int kMlpW2Off = kMlpB1Off + kMlpH, kMlpW2 = kMlpH * kMlpH;   // W2[k][n]
+constexpr int kMlpB2Off = kMlpW2Off + kMlpW2;                   // b2[256]
+constexpr int kMlpW3Off = kMlpB2Off + kMlpH;                    // w3[256]
+constexpr int kMlpB3Off = kMlpW3Off + kMlpH;                    // b3
+constexpr int kMlpParams = kMlpB3Off + 1;                        // 82,689
+
+struct MlpDevice {
+    float* params = nullptr;      // FP32 master weights
+    float* adam_m = nullptr;
+    float* adam_v = nullptr;
+    float* grad = nullptr;
+    uint16_t* w1b = nullptr;      // BF16 copies
+    uint16_t* w2b = nullptr;
+    uint16_t* H1 = nullptr;       // [cap x 256] BF16 activations and gradients
+    uint16_t* H2 = nullptr;
+    uint16_t* dH1 = nullptr;
+    uint16_t* dH2 = nullptr;
+    float* logits = nullptr;      // [cap]
+    float* loss = nullptr;        // [1]
+    int64_t cap = 0;
+};
+
+hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const float* y, bool backward, hipStream_t s);
+hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, hipStream_t s);
+hipError_t mlp_adam(const MlpDevice& d, float lr, float beta1, float beta2, float eps, int64_t t, hipStream_t s);
+hipError_t mlp_refresh_bf16(const MlpDevice& d, hipStream_t s);
+
 }  // namespace geonet

@@ -1,0 +1,342 @@
+// Edge-scoring MLP (64 -> 256 -> 256 -> 1) on gfx950 matrix cores.
+//
+// BF16 operands, FP32 accumulation (v_mfma_f32_32x32x16_bf16), FP32 master
+// weights and Adam state.  Rounding points (mirrored by the CPU reference):
+// the input features, W1 and W2 are rounded to BF16; H1 and H2 are rounded
+// to BF16 after bias + ReLU; in the backward pass dH2 and dH1 are rounded to
+// BF16 before they enter a matrix product.  The head (H2 . w3 + b3), the
+// binary cross-entropy with logits and all gradients are FP32.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "internal.h"
+
+namespace geonet {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float x) {
+    uint32_t u = __builtin_bit_cast(uint32_t, x);
+    if ((u & 0x7F800000u) == 0x7F800000u) return static_cast<uint16_t>((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+    u += 0x7FFFu + ((u >> 16) & 1u);          // round to nearest, ties to even
+    return static_cast<uint16_t>(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
+    return __builtin_bit_cast(float, static_cast<uint32_t>(b) << 16);
+}
+
+// ---------------------------------------------------------------------------
+// C[M x N] = op(A)[M x K] * op(B)[K x N], FP32 accumulation.
+// A element (m, k) at A[m*a_rs + k*a_cs]; B element (k, n) at B[k*b_rs + n*b_cs].
+// A is FP32 (rounded to BF16 when staged) or BF16 bits; B is BF16 bits.
+// Block tile 64 x 64, four waves (2 x 2) of one 32 x 32 MFMA tile each,
+// K staged through LDS 32 at a time.  Split-K: blockIdx.z takes
+// K range [z*k_chunk, min(K, (z+1)*k_chunk)).
+// ---------------------------------------------------------------------------
+enum Epilogue { kBiasReluBf16 = 0, kMaskBf16 = 1, kAtomicF32 = 2 };
+
+struct GemmArgs {
+    const void* A;
+    const uint16_t* B;
+    int64_t M, N, K, k_chunk;
+    int64_t a_rs, a_cs, b_rs, b_cs;
+    const float* bias;        // kBiasReluBf16: [N]
+    const uint16_t* mask;     // kMaskBf16: BF16 [M x N] row-major; keep where > 0
+    uint16_t* out_bf16;       // [M x N] row-major
+    float* out_f32;           // [M x N] row-major (atomic add)
+};
+
+constexpr int kTile = 64, kKs = 32, kLdsK = kKs + 8;   // padded rows against bank conflicts
+
+template <bool kAF32, int kEpi>
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
+    __shared__ uint16_t As[kTile][kLdsK];   // [m][k]
+    __shared__ uint16_t Bs[kTile][kLdsK];   // [n][k] (transposed so fragments are contiguous)
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t m0 = static_cast<int64_t>(blockIdx.y) * kTile, n0 = static_cast<int64_t>(blockIdx.x) * kTile;
+    const int64_t k_lo = static_cast<int64_t>(blockIdx.z) * g.k_chunk;
+    const int64_t k_hi = k_lo + g.k_chunk < g.K ? k_lo + g.k_chunk : g.K;
+    f32x16 acc = {};
+    for (int64_t k0 = k_lo; k0 < k_hi; k0 += kKs) {
+        // stage 64 x 32 of A and 32 x 64 of B: 8 elements of each per thread
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int e = tid + r * 256;            // 0 .. 2047
+            const int i = e / kKs, kk = e % kKs;    // A: row i, column kk
+            const int64_t m = m0 + i, k = k0 + kk;
+            uint16_t av = 0;
+            if (m < g.M && k < k_hi) {
+                const int64_t off = m * g.a_rs + k * g.a_cs;
+                av = kAF32 ? f32_to_bf16_bits(static_cast<const float*>(g.A)[off])
+                           : static_cast<const uint16_t*>(g.A)[off];
+            }
+            As[i][kk] = av;
+            const int jn = e % kTile, kb = e / kTile;   // B: column jn, row kb
+            const int64_t n = n0 + jn, kr = k0 + kb;
+            Bs[jn][kb] = (n < g.N && kr < k_hi) ? g.B[kr * g.b_rs + n * g.b_cs] : static_cast<uint16_t>(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kKs; ks += 16) {
+            // lane supplies row (lane % 32) and k = ks + 8*(lane / 32) .. +7
+            const int r = lane & 31, kq = ks + 8 * (lane >> 5);
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + r][kq]);
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn * 32 + r][kq]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // acc[i] holds C[m][n]: n = lane % 32, m = 8*(i/4) + 4*(lane/32) + i%4
+    const int64_t n = n0 + wn * 32 + (lane & 31);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int64_t m = m0 + wm * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+        if (m >= g.M || n >= g.N) continue;
+        const float v = acc[i];
+        if (kEpi == kBiasReluBf16) {
+            const float h = v + g.bias[n];
+            g.out_bf16[m * g.N + n] = f32_to_bf16_bits(h > 0.0f ? h : 0.0f);
+        } else if (kEpi == kMaskBf16) {
+            const float keep = bf16_bits_to_f32(g.mask[m * g.N + n]) > 0.0f ? 1.0f : 0.0f;
+            g.out_bf16[m * g.N + n] = f32_to_bf16_bits(v * keep);
+        } else {
+            atomicAdd(g.out_f32 + m * g.N + n, v);
+        }
+    }
+}
+
+// Head: logit = H2 . w3 + b3; BCE with logits; dlogit = (sigmoid - y)/B;
+// dH2 = BF16(dlogit * w3 * [H2 > 0]); dw3 += dlogit * H2; db3 += dlogit.
+// One wave per row (256 columns, 4 per lane).
+struct HeadArgs {
+    const uint16_t* H2;
+    const float* w3;
+    const float* b3;
+    const float* y;          // null for inference
+    float* logits;
+    uint16_t* dH2;
+    float* dw3;
+    float* db3;
+    float* loss;             // sum of per-row losses / B (atomic)
+    int64_t B;
+};
+
+__global__ void __launch_bounds__(256) head_kernel(HeadArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    if (row >= a.B) return;
+    float h[4], s = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        h[q] = bf16_bits_to_f32(a.H2[row * 256 + q * 64 + lane]);
+        s += h[q] * a.w3[q * 64 + lane];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    const float logit = s + a.b3[0];
+    if (lane == 0) a.logits[row] = logit;
+    if (!a.y) return;
+    const float y = a.y[row];
+    const float p = 1.0f / (1.0f + expf(-logit));
+    const float inv_b = 1.0f / static_cast<float>(a.B);
+    const float dl = (p - y) * inv_b;
+    if (lane == 0) {
+        // log(1 + exp(-|z|)) + max(z, 0) - z*y
+        const float l = log1pf(expf(-fabsf(logit))) + fmaxf(logit, 0.0f) - logit * y;
+        atomicAdd(a.loss, l * inv_b);
+        atomicAdd(a.db3, dl);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int n = q * 64 + lane;
+        a.dH2[row * 256 + n] = f32_to_bf16_bits(h[q] > 0.0f ? dl * a.w3[n] : 0.0f);
+        atomicAdd(a.dw3 + n, dl * h[q]);
+    }
+}
+
+// Column sums of a BF16 [B x 256] matrix into FP32 (bias gradients).
+__global__ void __launch_bounds__(256) colsum_kernel(const uint16_t* X, int64_t B, float* out) {
+    const int n = threadIdx.x;
+    const int64_t rows_per = (B + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rows_per;
+    const int64_t r1 = r0 + rows_per < B ? r0 + rows_per : B;
+    float s = 0.0f;
+    for (int64_t r = r0; r < r1; ++r) s += bf16_bits_to_f32(X[r * 256 + n]);
+    if (r1 > r0) atomicAdd(out + n, s);
+}
+
+// Adam on the flat FP32 parameter vector; refreshes the BF16 copies of W1, W2.
+struct AdamArgs {
+    float* p;
+    float* m;
+    float* v;
+    const float* g;
+    uint16_t* w1b;
+    uint16_t* w2b;
+    int64_t n;
+    float lr, b1, b2, eps, c1, c2;   // c1 = 1 - b1^t, c2 = 1 - b2^t
+};
+
+__global__ void __launch_bounds__(256) adam_kernel(AdamArgs a) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const float gi = a.g[i];
+    const float m = a.b1 * a.m[i] + (1.0f - a.b1) * gi;
+    const float v = a.b2 * a.v[i] + (1.0f - a.b2) * gi * gi;
+    a.m[i] = m;
+    a.v[i] = v;
+    const float p = a.p[i] - a.lr * (m / a.c1) / (sqrtf(v / a.c2) + a.eps);
+    a.p[i] = p;
+    if (i < kMlpW1) a.w1b[i] = f32_to_bf16_bits(p);
+    else if (i >= kMlpW2Off && i < kMlpW2Off + kMlpW2) a.w2b[i - kMlpW2Off] = f32_to_bf16_bits(p);
+}
+
+__global__ void __launch_bounds__(256) to_bf16_kernel(const float* x, uint16_t* y, int64_t n) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f32_to_bf16_bits(x[i]);
+}
+
+template <bool kAF32, int kEpi>
+hipError_t gemm(const GemmArgs& g, int split, hipStream_t s) {
+    dim3 grid(static_cast<unsigned>((g.N + kTile - 1) / kTile), static_cast<unsigned>((g.M + kTile - 1) / kTile),
+              static_cast<unsigned>(split));
+    hipLaunchKernelGGL((gemm_kernel<kAF32, kEpi>), grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Forward pass for B rows of features X (FP32 [B x 64]); fills H1, H2 and logits.
+hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const float* y, bool backward,
+                       hipStream_t s) {
+    const float* p = d.params;
+    GemmArgs g1{};
+    g1.A = X;
+    g1.B = d.w1b;
+    g1.M = B;
+    g1.N = kMlpH;
+    g1.K = kMlpIn;
+    g1.k_chunk = kMlpIn;
+    g1.a_rs = kMlpIn;
+    g1.a_cs = 1;
+    g1.b_rs = kMlpH;
+    g1.b_cs = 1;
+    g1.bias = p + kMlpB1Off;
+    g1.out_bf16 = d.H1;
+    hipError_t e = gemm<true, kBiasReluBf16>(g1, 1, s);
+    if (e != hipSuccess) return e;
+    GemmArgs g2 = g1;
+    g2.A = d.H1;
+    g2.B = d.w2b;
+    g2.K = kMlpH;
+    g2.k_chunk = kMlpH;
+    g2.a_rs = kMlpH;
+    g2.bias = p + kMlpB2Off;
+    g2.out_bf16 = d.H2;
+    e = gemm<false, kBiasReluBf16>(g2, 1, s);
+    if (e != hipSuccess) return e;
+    HeadArgs h{};
+    h.H2 = d.H2;
+    h.w3 = p + kMlpW3Off;
+    h.b3 = p + kMlpB3Off;
+    h.y = backward ? y : nullptr;
+    h.logits = d.logits;
+    h.dH2 = d.dH2;
+    h.dw3 = d.grad + kMlpW3Off;
+    h.db3 = d.grad + kMlpB3Off;
+    h.loss = d.loss;
+    h.B = B;
+    const int64_t threads = B * 64;
+    hipLaunchKernelGGL(head_kernel, dim3(static_cast<unsigned>((threads + 255) / 256)), dim3(256), 0, s, h);
+    return hipGetLastError();
+}
+
+// Backward pass after mlp_forward(..., backward = true): accumulates the
+// gradient of the mean BCE into d.grad (which the caller zeroed).
+hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, hipStream_t s) {
+    const int split = B >= 4096 ? static_cast<int>((B + 2047) / 2048) : 1;
+    const int64_t k_chunk = ((B + split - 1) / split + kKs - 1) / kKs * kKs;
+    // dW2 = H1^T dH2  (M = 256, N = 256, K = B)
+    GemmArgs w2{};
+    w2.A = d.H1;
+    w2.B = d.dH2;
+    w2.M = kMlpH;
+    w2.N = kMlpH;
+    w2.K = B;
+    w2.k_chunk = k_chunk;
+    w2.a_rs = 1;
+    w2.a_cs = kMlpH;
+    w2.b_rs = kMlpH;
+    w2.b_cs = 1;
+    w2.out_f32 = d.grad + kMlpW2Off;
+    hipError_t e = gemm<false, kAtomicF32>(w2, split, s);
+    if (e != hipSuccess) return e;
+    // dH1 = BF16((dH2 W2^T) * [H1 > 0])  (M = B, N = 256, K = 256)
+    GemmArgs h1{};
+    h1.A = d.dH2;
+    h1.B = d.w2b;
+    h1.M = B;
+    h1.N = kMlpH;
+    h1.K = kMlpH;
+    h1.k_chunk = kMlpH;
+    h1.a_rs = kMlpH;
+    h1.a_cs = 1;
+    h1.b_rs = 1;          // B(k, n) = W2(n, k)
+    h1.b_cs = kMlpH;
+    h1.mask = d.H1;
+    h1.out_bf16 = d.dH1;
+    if ((e = gemm<false, kMaskBf16>(h1, 1, s)) != hipSuccess) return e;
+    // dW1 = X^T dH1  (M = 64, N = 256, K = B), X rounded to BF16 on staging
+    GemmArgs w1{};
+    w1.A = X;
+    w1.B = d.dH1;
+    w1.M = kMlpIn;
+    w1.N = kMlpH;
+    w1.K = B;
+    w1.k_chunk = k_chunk;
+    w1.a_rs = 1;
+    w1.a_cs = kMlpIn;
+    w1.b_rs = kMlpH;
+    w1.b_cs = 1;
+    w1.out_f32 = d.grad + kMlpW1Off;
+    if ((e = gemm<true, kAtomicF32>(w1, split, s)) != hipSuccess) return e;
+    const unsigned cs_blocks = static_cast<unsigned>(B < 1024 ? 1 : (B + 1023) / 1024);
+    hipLaunchKernelGGL(colsum_kernel, dim3(cs_blocks), dim3(256), 0, s, d.dH2, B, d.grad + kMlpB2Off);
+    hipLaunchKernelGGL(colsum_kernel, dim3(cs_blocks), dim3(256), 0, s, d.dH1, B, d.grad + kMlpB1Off);
+    return hipGetLastError();
+}
+
+hipError_t mlp_adam(const MlpDevice& d, float lr, float beta1, float beta2, float eps, int64_t t, hipStream_t s) {
+    AdamArgs a;
+    a.p = d.params;
+    a.m = d.adam_m;
+    a.v = d.adam_v;
+    a.g = d.grad;
+    a.w1b = d.w1b;
+    a.w2b = d.w2b;
+    a.n = kMlpParams;
+    a.lr = lr;
+    a.b1 = beta1;
+    a.b2 = beta2;
+    a.eps = eps;
+    a.c1 = static_cast<float>(1.0 - std::pow(static_cast<double>(beta1), static_cast<double>(t)));
+    a.c2 = static_cast<float>(1.0 - std::pow(static_cast<double>(beta2), static_cast<double>(t)));
+    hipLaunchKernelGGL(adam_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t mlp_refresh_bf16(const MlpDevice& d, hipStream_t s) {
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((kMlpW1 + 255) / 256), dim3(256), 0, s, d.params + kMlpW1Off, d.w1b,
+                       static_cast<int64_t>(kMlpW1));
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((kMlpW2 + 255) / 256), dim3(256), 0, s, d.params + kMlpW2Off, d.w2b,
+                       static_cast<int64_t>(kMlpW2));
+    return hipGetLastError();
+}
+
+}  // namespace geonet

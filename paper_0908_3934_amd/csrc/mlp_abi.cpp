@@ -1,0 +1,180 @@
+// C-ABI entry points of the edge-scoring MLP (declared in include/geonet.h).
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace geonet;
+
+struct net_mlp {
+    MlpDevice d;
+    int64_t adam_t = 0;
+    bool broken = false;
+};
+
+namespace {
+
+thread_local std::string m_error;
+
+net_status mfail(net_status st, const std::string& msg) {
+    m_error = msg;
+    return st;
+}
+
+net_status mdev(net_mlp* m, hipError_t e, const char* where) {
+    if (m) m->broken = true;
+    return mfail(NET_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+hipError_t alloc(T** p, size_t n) {
+    return hipMalloc(reinterpret_cast<void**>(p), (n ? n : 1) * sizeof(T));
+}
+
+void release(MlpDevice& d) {
+    void* ps[] = {d.params, d.adam_m, d.adam_v, d.grad, d.w1b, d.w2b, d.H1, d.H2, d.dH1, d.dH2, d.logits, d.loss};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    d = MlpDevice{};
+}
+
+// Grow the activation workspace to hold `rows` rows (waits for the stream).
+net_status reserve(net_mlp* m, int64_t rows, hipStream_t s) {
+    if (rows <= m->d.cap) return NET_OK;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return mdev(m, e, "net_mlp: workspace");
+    uint16_t** bufs[] = {&m->d.H1, &m->d.H2, &m->d.dH1, &m->d.dH2};
+    for (uint16_t** b : bufs) {
+        if (*b) (void)hipFree(*b);
+        *b = nullptr;
+        if (alloc(b, static_cast<size_t>(rows) * kMlpH) != hipSuccess) return mfail(NET_E_OOM, "net_mlp: workspace");
+    }
+    if (m->d.logits) (void)hipFree(m->d.logits);
+    m->d.logits = nullptr;
+    if (alloc(&m->d.logits, static_cast<size_t>(rows)) != hipSuccess) return mfail(NET_E_OOM, "net_mlp: workspace");
+    m->d.cap = rows;
+    return NET_OK;
+}
+
+net_status check(const net_mlp* m, int64_t rows, const void* x) {
+    if (!m) return mfail(NET_E_ARG, "net_mlp: handle is NULL");
+    if (m->broken) return mfail(NET_E_STATE, "net_mlp: handle unusable after a device error");
+    if (rows < 1 || rows > (int64_t(1) << 26)) return mfail(NET_E_ARG, "net_mlp: rows must be in 1 .. 2^26");
+    if (!x) return mfail(NET_E_ARG, "net_mlp: features are NULL");
+    return NET_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* net_mlp_last_error(void) { return m_error.c_str(); }
+
+net_status net_mlp_create(net_mlp_t** out) {
+    if (!out) return mfail(NET_E_ARG, "net_mlp_create: out is NULL");
+    *out = nullptr;
+    net_mlp* m = new net_mlp();
+    MlpDevice& d = m->d;
+    if (alloc(&d.params, kMlpParams) != hipSuccess || alloc(&d.adam_m, kMlpParams) != hipSuccess ||
+        alloc(&d.adam_v, kMlpParams) != hipSuccess || alloc(&d.grad, kMlpParams) != hipSuccess ||
+        alloc(&d.w1b, kMlpW1) != hipSuccess || alloc(&d.w2b, kMlpW2) != hipSuccess || alloc(&d.loss, 1) != hipSuccess) {
+        release(d);
+        delete m;
+        return mfail(NET_E_OOM, "net_mlp_create: device allocation failed");
+    }
+    hipError_t e = hipMemset(d.params, 0, kMlpParams * sizeof(float));
+    if (e == hipSuccess) e = hipMemset(d.adam_m, 0, kMlpParams * sizeof(float));
+    if (e == hipSuccess) e = hipMemset(d.adam_v, 0, kMlpParams * sizeof(float));
+    if (e == hipSuccess) e = mlp_refresh_bf16(d, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        release(d);
+        delete m;
+        return mfail(NET_E_DEVICE, std::string("net_mlp_create: ") + hipGetErrorString(e));
+    }
+    *out = m;
+    return NET_OK;
+}
+
+net_status net_mlp_set_params(net_mlp_t* m, const float* host_params, int64_t n) {
+    if (!m || !host_params) return mfail(NET_E_ARG, "net_mlp_set_params: NULL argument");
+    if (n != kMlpParams) return mfail(NET_E_ARG, "net_mlp_set_params: expected 82689 parameters");
+    if (m->broken) return mfail(NET_E_STATE, "net_mlp_set_params: handle unusable");
+    hipError_t e = hipMemcpy(m->d.params, host_params, kMlpParams * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(m->d.adam_m, 0, kMlpParams * sizeof(float));
+    if (e == hipSuccess) e = hipMemset(m->d.adam_v, 0, kMlpParams * sizeof(float));
+    if (e == hipSuccess) e = mlp_refresh_bf16(m->d, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return mdev(m, e, "net_mlp_set_params");
+    m->adam_t = 0;
+    return NET_OK;
+}
+
+net_status net_mlp_get_params(const net_mlp_t* m, float* host_params, int64_t n) {
+    if (!m || !host_params) return mfail(NET_E_ARG, "net_mlp_get_params: NULL argument");
+    if (n != kMlpParams) return mfail(NET_E_ARG, "net_mlp_get_params: expected 82689 parameters");
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(host_params, m->d.params, kMlpParams * sizeof(float), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return mfail(NET_E_DEVICE, std::string("net_mlp_get_params: ") + hipGetErrorString(e));
+    return NET_OK;
+}
+
+net_status net_mlp_forward(net_mlp_t* m, const float* x_dev, int64_t rows, float* logits_dev, void* stream) {
+    net_status st = check(m, rows, x_dev);
+    if (st != NET_OK) return st;
+    if (!logits_dev) return mfail(NET_E_ARG, "net_mlp_forward: logits are NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = reserve(m, rows, s)) != NET_OK) return st;
+    hipError_t e = mlp_forward(m->d, x_dev, rows, nullptr, false, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(logits_dev, m->d.logits, rows * sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return mdev(m, e, "net_mlp_forward");
+    return NET_OK;
+}
+
+static net_status grad_impl(net_mlp* m, const float* x, const float* y, int64_t rows, hipStream_t s) {
+    net_status st = check(m, rows, x);
+    if (st != NET_OK) return st;
+    if (!y) return mfail(NET_E_ARG, "net_mlp: labels are NULL");
+    if ((st = reserve(m, rows, s)) != NET_OK) return st;
+    hipError_t e = hipMemsetAsync(m->d.grad, 0, kMlpParams * sizeof(float), s);
+    if (e == hipSuccess) e = hipMemsetAsync(m->d.loss, 0, sizeof(float), s);
+    if (e == hipSuccess) e = mlp_forward(m->d, x, rows, y, true, s);
+    if (e == hipSuccess) e = mlp_backward(m->d, x, rows, s);
+    if (e != hipSuccess) return mdev(m, e, "net_mlp: gradient");
+    return NET_OK;
+}
+
+net_status net_mlp_grad(net_mlp_t* m, const float* x_dev, const float* y_dev, int64_t rows, float* grad_dev,
+                        float* loss_dev, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    net_status st = grad_impl(m, x_dev, y_dev, rows, s);
+    if (st != NET_OK) return st;
+    hipError_t e = hipSuccess;
+    if (grad_dev) e = hipMemcpyAsync(grad_dev, m->d.grad, kMlpParams * sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && loss_dev) e = hipMemcpyAsync(loss_dev, m->d.loss, sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return mdev(m, e, "net_mlp_grad");
+    return NET_OK;
+}
+
+net_status net_mlp_train_step(net_mlp_t* m, const float* x_dev, const float* y_dev, int64_t rows, float lr,
+                              float* loss_dev, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!(lr > 0.0f)) return mfail(NET_E_ARG, "net_mlp_train_step: lr must be > 0");
+    net_status st = grad_impl(m, x_dev, y_dev, rows, s);
+    if (st != NET_OK) return st;
+    m->adam_t += 1;
+    hipError_t e = mlp_adam(m->d, lr, 0.9f, 0.999f, 1e-8f, m->adam_t, s);
+    if (e == hipSuccess && loss_dev) e = hipMemcpyAsync(loss_dev, m->d.loss, sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return mdev(m, e, "net_mlp_train_step");
+    return NET_OK;
+}
+
+void net_mlp_free(net_mlp_t* m) {
+    if (!m) return;
+    (void)hipDeviceSynchronize();
+    release(m->d);
+    delete m;
+}
+
+}  // extern "C"
