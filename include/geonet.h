@@ -242,6 +242,9 @@ typedef struct net_mlp net_mlp_t;
 net_status net_mlp_create(net_mlp_t** out);                 /* parameters zero */
 net_status net_mlp_set_params(net_mlp_t* m, const float* host_params, int64_t n);   /* resets Adam */
 net_status net_mlp_get_params(const net_mlp_t* m, float* host_params, int64_t n);
+/* Input standardisation applied before the first layer: x'_k = (x_k - shift[k]) * scale[k]
+   (host [64] each; default shift 0, scale 1). */
+net_status net_mlp_set_input_norm(net_mlp_t* m, const float* shift, const float* scale);
 /* logits_dev[r] = MLP(x_dev[r]) */
 net_status net_mlp_forward(net_mlp_t* m, const float* x_dev, int64_t rows, float* logits_dev, void* stream);
 /* gradient of the mean BCE over the rows into grad_dev [82,689] and loss_dev [1] (either may be NULL) */
@@ -252,6 +255,40 @@ net_status net_mlp_train_step(net_mlp_t* m, const float* x_dev, const float* y_d
                               float* loss_dev, void* stream);
 void net_mlp_free(net_mlp_t* m);
 const char* net_mlp_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Observations of one network for the inverse problem: what an experiment
+ * provides (fluorescence of every vertex per camera frame, positions, the
+ * experimenter's own control schedule) plus the candidate pairs to score.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_nodes, n_frames;
+    const float* fluor;          /* device [n_frames][n_nodes] fluorescence F_j(f) */
+    int64_t n_pairs;
+    const int32_t* pairs;        /* device [n_pairs][2]: (source i, target j), i != j */
+    const float* pair_dist_um;   /* device [n_pairs] |x_i - x_j| */
+    float gain, offset, gamma;   /* observation model n, b, gamma (Section 3.3) */
+    double dt_ms;
+    float tau_c_ms;
+    int32_t frame_num, frame_den;  /* frame(t) = floor(t*num/den) */
+    const float* drive_rate_hz;  /* host [n_nodes] control pulse rates, or NULL */
+    float drive_amp;
+    uint64_t control_seed;       /* Philox key of the control pulses (output 0 only) */
+    /* vertex model assumed by the simulation-based fit */
+    float tau_ms, v_rest, v_reset, v_th, noise_sigma, w_assumed;
+    int32_t n_ref;
+} net_obs_desc;
+
+/*
+ * Pair features (device [n_pairs][64], FP32) from the observations: per
+ * vertex, activity e(f) = max(0, (F(f+1)-b) - rho (F(f)-b)) with
+ * rho = (1 - dt/tau_c)^(den/num) (the calcium model sampled per frame) and
+ * standardised e, F; per pair, lagged correlations of e and F, responses to
+ * the other vertex's control pulses, activity levels and distance.  Waits
+ * for completion.
+ */
+net_status net_features(const net_obs_desc* obs, float* features_dev, void* stream);
+const char* net_estimate_last_error(void);
 
 /* Release the handle and its device memory (waits for the handle's stream). */
 void net_free(net_t* h);

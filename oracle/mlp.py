@@ -35,9 +35,13 @@ def unpack(p):
     return p[W1].reshape(IN, H), p[B1], p[W2].reshape(H, H), p[B2], p[W3], p[B3][0]
 
 
-def forward(p, X, bf=True):
+def forward(p, X, bf=True, shift=None, scale=None):
+    """shift/scale: optional input standardisation x' = (x - shift) * scale."""
     w1, b1, w2, b2, w3, b3 = unpack(p)
     r = bf16 if bf else (lambda a: np.asarray(a, dtype=np.float64))
+    X = np.asarray(X, dtype=np.float64)
+    if shift is not None:
+        X = (X - shift) * scale
     Xb, w1b, w2b = r(X), r(w1), r(w2)
     H1 = r(np.maximum(Xb @ w1b + b1, 0.0))
     H2 = r(np.maximum(H1 @ w2b + b2, 0.0))
@@ -50,11 +54,11 @@ def bce(z, y):
     return float(np.mean(np.log1p(np.exp(-np.abs(z))) + np.maximum(z, 0.0) - z * y))
 
 
-def grad(p, X, y, bf=True):
+def grad(p, X, y, bf=True, shift=None, scale=None):
     """Gradient of the mean BCE with respect to the flat parameters, and the loss."""
     w1, b1, w2, b2, w3, b3 = unpack(p)
     r = bf16 if bf else (lambda a: np.asarray(a, dtype=np.float64))
-    z, (Xb, w1b, w2b, H1, H2) = forward(p, X, bf)
+    z, (Xb, w1b, w2b, H1, H2) = forward(p, X, bf, shift, scale)
     B = X.shape[0]
     dz = (1.0 / (1.0 + np.exp(-z)) - y) / B
     g = np.zeros(N_PARAMS)

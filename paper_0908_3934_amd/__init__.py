@@ -254,6 +254,12 @@ class Mlp:
         a = np.ascontiguousarray(params, dtype=np.float32)
         self._check(library().net_mlp_set_params(self.h, a.ctypes.data, a.size), "net_mlp_set_params")
 
+    def set_input_norm(self, shift, scale):
+        a = np.ascontiguousarray(shift, dtype=np.float32)
+        b = np.ascontiguousarray(scale, dtype=np.float32)
+        assert a.size == _abi.MLP_IN and b.size == _abi.MLP_IN
+        self._check(library().net_mlp_set_input_norm(self.h, a.ctypes.data, b.ctypes.data), "net_mlp_set_input_norm")
+
     def get_params(self) -> np.ndarray:
         out = np.zeros(_abi.MLP_PARAMS, dtype=np.float32)
         self._check(library().net_mlp_get_params(self.h, out.ctypes.data, out.size), "net_mlp_get_params")

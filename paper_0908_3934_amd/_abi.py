@@ -71,6 +71,17 @@ class FluorParams(C.Structure):
     _fields_ = [("gain", C.c_float), ("offset", C.c_float), ("gamma", C.c_float), ("pad", C.c_int32)]
 
 
+class ObsDesc(C.Structure):
+    _fields_ = [
+        ("n_nodes", C.c_int32), ("n_frames", C.c_int32), ("fluor", _vp), ("n_pairs", C.c_int64),
+        ("pairs", _vp), ("pair_dist_um", _vp), ("gain", C.c_float), ("offset", C.c_float), ("gamma", C.c_float),
+        ("dt_ms", C.c_double), ("tau_c_ms", C.c_float), ("frame_num", C.c_int32), ("frame_den", C.c_int32),
+        ("drive_rate_hz", _vp), ("drive_amp", C.c_float), ("control_seed", C.c_uint64),
+        ("tau_ms", C.c_float), ("v_rest", C.c_float), ("v_reset", C.c_float), ("v_th", C.c_float),
+        ("noise_sigma", C.c_float), ("w_assumed", C.c_float), ("n_ref", C.c_int32),
+    ]
+
+
 ALLOC_FN = C.CFUNCTYPE(_vp, C.c_size_t, _vp, _vp)
 RELEASE_FN = C.CFUNCTYPE(None, _vp, _vp, _vp)
 
@@ -89,6 +100,9 @@ SIGNATURES = {
     "net_mlp_create": (C.c_int, [C.POINTER(_vp)]),
     "net_mlp_set_params": (C.c_int, [_vp, _vp, C.c_int64]),
     "net_mlp_get_params": (C.c_int, [_vp, _vp, C.c_int64]),
+    "net_mlp_set_input_norm": (C.c_int, [_vp, _vp, _vp]),
+    "net_features": (C.c_int, [_vp, _vp, _vp]),
+    "net_estimate_last_error": (C.c_char_p, []),
     "net_mlp_forward": (C.c_int, [_vp, _vp, C.c_int64, _vp, _vp]),
     "net_mlp_grad": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, _vp, _vp]),
     "net_mlp_train_step": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_float, _vp, _vp]),

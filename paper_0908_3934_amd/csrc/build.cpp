@@ -53,14 +53,15 @@ int32_t delay_from_geometry(const double* xi, const double* xj, int dims, double
     return steps < 1.0 ? 1 : static_cast<int32_t>(steps);
 }
 
+}  // namespace
+
+// Control pulse threshold: a pulse when a 32-bit draw is below floor(p * 2^32).
 uint32_t pulse_threshold(double rate_hz, double dt_ms) {
     const double thr = std::floor(rate_hz * (dt_ms * 1e-3) * 4294967296.0);
     if (!(thr > 0.0)) return 0u;
     if (thr >= 4294967295.0) return 0xFFFFFFFFu;
     return static_cast<uint32_t>(thr);
 }
-
-}  // namespace
 
 net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g, std::string& err) {
     if (!descs || n_nets < 1) {

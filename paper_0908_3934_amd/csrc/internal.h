@@ -161,8 +161,28 @@ struct MlpDevice {
     uint16_t* dH2 = nullptr;
     float* logits = nullptr;      // [cap]
     float* loss = nullptr;        // [1]
+    float* in_shift = nullptr;    // [64] input standardisation: x' = (x - shift) * scale
+    float* in_scale = nullptr;    // [64]
     int64_t cap = 0;
 };
+
+// Observation-side inputs of the feature extractor.
+struct FeatureInputs {
+    const float* F;             // device [nf][n] fluorescence
+    const uint32_t* drive_thr;  // device [n] control pulse thresholds, or null
+    const int32_t* pairs;       // device [P][2]
+    const float* dist;          // device [P]
+    int32_t n, nf;
+    int64_t P;
+    float rho, offset;          // frame-to-frame calcium decay, observation offset
+    int64_t frame_num, frame_den;
+    uint32_t key_lo, key_hi;    // control schedule key
+};
+struct FeatureWork {
+    float *en, *zn, *rn, *dc, *stats, *pm;
+};
+hipError_t launch_features(const FeatureInputs& in, const FeatureWork& w, float* out, hipStream_t s);
+uint32_t pulse_threshold(double rate_hz, double dt_ms);
 
 hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const float* y, bool backward, hipStream_t s);
 hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, hipStream_t s);

@@ -42,6 +42,9 @@ enum Epilogue { kBiasReluBf16 = 0, kMaskBf16 = 1, kAtomicF32 = 2 };
 
 struct GemmArgs {
     const void* A;
+    const float* a_shift;     // FP32 A only: A is staged as (A - shift[f]) * scale[f] (null: as is),
+    const float* a_scale;     // f = k, or f = m when shift_on_m (A is a transposed feature matrix)
+    int32_t shift_on_m;
     const uint16_t* B;
     int64_t M, N, K, k_chunk;
     int64_t a_rs, a_cs, b_rs, b_cs;
@@ -73,8 +76,16 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
             uint16_t av = 0;
             if (m < g.M && k < k_hi) {
                 const int64_t off = m * g.a_rs + k * g.a_cs;
-                av = kAF32 ? f32_to_bf16_bits(static_cast<const float*>(g.A)[off])
-                           : static_cast<const uint16_t*>(g.A)[off];
+                if (kAF32) {
+                    float x = static_cast<const float*>(g.A)[off];
+                    if (g.a_shift) {
+                        const int64_t fi = g.shift_on_m ? m : k;
+                        x = (x - g.a_shift[fi]) * g.a_scale[fi];
+                    }
+                    av = f32_to_bf16_bits(x);
+                } else {
+                    av = static_cast<const uint16_t*>(g.A)[off];
+                }
             }
             As[i][kk] = av;
             const int jn = e % kTile, kb = e / kTile;   // B: column jn, row kb
@@ -218,6 +229,8 @@ hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const floa
     const float* p = d.params;
     GemmArgs g1{};
     g1.A = X;
+    g1.a_shift = d.in_shift;
+    g1.a_scale = d.in_scale;
     g1.B = d.w1b;
     g1.M = B;
     g1.N = kMlpH;
@@ -233,6 +246,8 @@ hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const floa
     if (e != hipSuccess) return e;
     GemmArgs g2 = g1;
     g2.A = d.H1;
+    g2.a_shift = nullptr;
+    g2.a_scale = nullptr;
     g2.B = d.w2b;
     g2.K = kMlpH;
     g2.k_chunk = kMlpH;
@@ -295,6 +310,9 @@ hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, hipStream
     // dW1 = X^T dH1  (M = 64, N = 256, K = B), X rounded to BF16 on staging
     GemmArgs w1{};
     w1.A = X;
+    w1.a_shift = d.in_shift;
+    w1.a_scale = d.in_scale;
+    w1.shift_on_m = 1;
     w1.B = d.dH1;
     w1.M = kMlpIn;
     w1.N = kMlpH;

@@ -33,7 +33,8 @@ hipError_t alloc(T** p, size_t n) {
 }
 
 void release(MlpDevice& d) {
-    void* ps[] = {d.params, d.adam_m, d.adam_v, d.grad, d.w1b, d.w2b, d.H1, d.H2, d.dH1, d.dH2, d.logits, d.loss};
+    void* ps[] = {d.params, d.adam_m, d.adam_v, d.grad,   d.w1b,  d.w2b,      d.H1,
+                  d.H2,     d.dH1,    d.dH2,    d.logits, d.loss, d.in_shift, d.in_scale};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     d = MlpDevice{};
@@ -78,7 +79,8 @@ net_status net_mlp_create(net_mlp_t** out) {
     MlpDevice& d = m->d;
     if (alloc(&d.params, kMlpParams) != hipSuccess || alloc(&d.adam_m, kMlpParams) != hipSuccess ||
         alloc(&d.adam_v, kMlpParams) != hipSuccess || alloc(&d.grad, kMlpParams) != hipSuccess ||
-        alloc(&d.w1b, kMlpW1) != hipSuccess || alloc(&d.w2b, kMlpW2) != hipSuccess || alloc(&d.loss, 1) != hipSuccess) {
+        alloc(&d.w1b, kMlpW1) != hipSuccess || alloc(&d.w2b, kMlpW2) != hipSuccess || alloc(&d.loss, 1) != hipSuccess ||
+        alloc(&d.in_shift, kMlpIn) != hipSuccess || alloc(&d.in_scale, kMlpIn) != hipSuccess) {
         release(d);
         delete m;
         return mfail(NET_E_OOM, "net_mlp_create: device allocation failed");
@@ -87,6 +89,11 @@ net_status net_mlp_create(net_mlp_t** out) {
     if (e == hipSuccess) e = hipMemset(d.adam_m, 0, kMlpParams * sizeof(float));
     if (e == hipSuccess) e = hipMemset(d.adam_v, 0, kMlpParams * sizeof(float));
     if (e == hipSuccess) e = mlp_refresh_bf16(d, nullptr);
+    if (e == hipSuccess) {
+        const std::vector<float> zero(kMlpIn, 0.0f), one(kMlpIn, 1.0f);
+        e = hipMemcpy(d.in_shift, zero.data(), kMlpIn * sizeof(float), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d.in_scale, one.data(), kMlpIn * sizeof(float), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         release(d);
@@ -108,6 +115,15 @@ net_status net_mlp_set_params(net_mlp_t* m, const float* host_params, int64_t n)
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) return mdev(m, e, "net_mlp_set_params");
     m->adam_t = 0;
+    return NET_OK;
+}
+
+net_status net_mlp_set_input_norm(net_mlp_t* m, const float* shift, const float* scale) {
+    if (!m || !shift || !scale) return mfail(NET_E_ARG, "net_mlp_set_input_norm: NULL argument");
+    if (m->broken) return mfail(NET_E_STATE, "net_mlp_set_input_norm: handle unusable");
+    hipError_t e = hipMemcpy(m->d.in_shift, shift, kMlpIn * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->d.in_scale, scale, kMlpIn * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return mdev(m, e, "net_mlp_set_input_norm");
     return NET_OK;
 }
 

@@ -1,0 +1,191 @@
+"""The inverse problem on the GPU (Sections 1 and 4 of the paper): estimate
+which candidate pairs i -> j carry a functional edge from calcium-like
+observations of a simulated network.
+
+Argument marshalling around the C-ABI only: the simulation, the
+observation, the pair features, the MLP (forward, backward, Adam) and the
+simulation-based fit all run in the library's HIP kernels; PyTorch holds
+device buffers.
+
+* ``observe``          simulate networks (one ensemble launch) and record
+                       fluorescence F = n*cbar + b + gamma*xi per 30 Hz frame.
+* ``candidate_pairs``  ordered pairs closer than 150 um and their labels.
+* ``features``         64 pair features (``net_features``).
+* ``EdgeScorer``       the learned scorer: trained on simulated networks.
+* ``auc``              area under the ROC curve (Mann-Whitney, ties 1/2).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import _abi
+from . import GeonetError, Mlp, Net, NET_OBS_FLUOR, library, _stream_handle, NET_OK
+
+SNR = 5.0
+CANDIDATE_RADIUS_UM = 150.0
+
+
+def observation_gamma(spec, gain: float = 1.0, snr: float = SNR) -> float:
+    """Noise level for a given SNR: one spike raises calcium by dt (the
+    calcium transition of Section 3.3), observed as gain*dt; gamma is that
+    jump divided by the SNR."""
+    return gain * spec.dt_ms / snr
+
+
+def frames_in(n_steps: int, num: int, den: int) -> int:
+    """Number of complete frames in steps [0, n_steps)."""
+    return (n_steps * num) // den
+
+
+def candidate_pairs(spec, radius_um: float = CANDIDATE_RADIUS_UM):
+    """All ordered pairs (i, j), i != j, with |x_i - x_j| < radius; labels
+    mark the pairs that are edges of the network."""
+    pos = np.asarray(spec.pos_um, dtype=np.float64)
+    d = np.sqrt(((pos[:, None, :] - pos[None, :, :]) ** 2).sum(-1))
+    np.fill_diagonal(d, np.inf)
+    i, j = np.nonzero(d < radius_um)
+    pairs = np.stack([i, j], 1).astype(np.int32)
+    dist = d[i, j].astype(np.float32)
+    edge = np.zeros((spec.n, spec.n), dtype=bool)
+    edge[spec.src, spec.dst] = True
+    return pairs, dist, edge[i, j]
+
+
+@dataclass
+class Observed:
+    spec: object
+    F: object               # torch float32 [n_frames][n] on the GPU
+    pairs: object           # torch int32 [P][2]
+    dist: object            # torch float32 [P]
+    labels: np.ndarray      # bool [P]
+    gain: float
+    offset: float
+    gamma: float
+
+    @property
+    def n_frames(self) -> int:
+        return int(self.F.shape[0])
+
+
+def observe(specs: Sequence, n_steps: int, gain: float = 1.0, offset: float = 0.0,
+            gamma: Optional[float] = None) -> List[Observed]:
+    """Simulate every network for n_steps (one ensemble) and observe it."""
+    import torch
+    specs = list(specs)
+    nf = frames_in(n_steps, specs[0].frame_num, specs[0].frame_den)
+    if gamma is None:
+        gamma = observation_gamma(specs[0], gain)
+    net = Net(specs, frame_capacity=nf)
+    net.step(n_steps)
+    F_all = net.observe(NET_OBS_FLUOR, frames=nf, gain=gain, offset=offset, gamma=gamma)
+    offs = net.node_offsets()
+    out = []
+    for k, s in enumerate(specs):
+        pairs, dist, labels = candidate_pairs(s)
+        out.append(Observed(spec=s, F=F_all[:, offs[k]:offs[k + 1]].contiguous(),
+                            pairs=torch.tensor(pairs, device=F_all.device),
+                            dist=torch.tensor(dist, device=F_all.device), labels=labels,
+                            gain=gain, offset=offset, gamma=gamma))
+    torch.cuda.synchronize()
+    net.close()
+    return out
+
+
+def obs_desc(o: Observed, keep: list, w_assumed: float = 0.0) -> _abi.ObsDesc:
+    s = o.spec
+    d = _abi.ObsDesc()
+    d.n_nodes = s.n
+    d.n_frames = o.n_frames
+    d.fluor = o.F.data_ptr()
+    d.n_pairs = int(o.pairs.shape[0])
+    d.pairs = o.pairs.data_ptr()
+    d.pair_dist_um = o.dist.data_ptr()
+    d.gain, d.offset, d.gamma = o.gain, o.offset, o.gamma
+    d.dt_ms = s.dt_ms
+    d.tau_c_ms = s.tau_c_ms
+    d.frame_num, d.frame_den = s.frame_num, s.frame_den
+    if s.drive_rate_hz is not None:
+        rate = np.ascontiguousarray(s.drive_rate_hz, dtype=np.float32)
+        keep.append(rate)
+        d.drive_rate_hz = rate.ctypes.data
+    d.drive_amp = s.drive_amp
+    d.control_seed = s.seed
+    d.tau_ms, d.v_rest, d.v_reset, d.v_th = s.tau_ms, s.v_rest, s.v_reset, s.v_th
+    d.noise_sigma = s.noise_sigma
+    d.w_assumed = w_assumed
+    d.n_ref = s.n_ref
+    return d
+
+
+def _echeck(st, where):
+    if st != NET_OK:
+        raise GeonetError(st, where, library().net_estimate_last_error().decode())
+
+
+def features(o: Observed, stream=None):
+    """64 features per candidate pair (torch float32 [P][64] on the GPU)."""
+    import torch
+    out = torch.empty((int(o.pairs.shape[0]), 64), dtype=torch.float32, device=o.F.device)
+    keep = []
+    d = obs_desc(o, keep)
+    _echeck(library().net_features(C.byref(d), out.data_ptr(), _stream_handle(stream)), "net_features")
+    return out
+
+
+def auc(scores, labels) -> float:
+    """Mann-Whitney area under the ROC curve, ties counted 1/2."""
+    s = np.asarray(scores, dtype=np.float64)
+    y = np.asarray(labels).astype(bool)
+    n1, n0 = int(y.sum()), int((~y).sum())
+    if n1 == 0 or n0 == 0:
+        return float("nan")
+    order = np.argsort(s, kind="mergesort")
+    sv = s[order]
+    ranks = np.empty(s.size)
+    # average rank of each run of equal scores
+    starts = np.r_[0, np.nonzero(np.diff(sv))[0] + 1]
+    ends = np.r_[starts[1:], s.size]
+    for a, b in zip(starts, ends):
+        ranks[order[a:b]] = 0.5 * (a + b - 1) + 1.0
+    return float((ranks[y].sum() - n1 * (n1 + 1) / 2.0) / (n1 * n0))
+
+
+class EdgeScorer:
+    """Learned edge scorer: 64 pair features -> MLP 256 -> 256 -> 1 (GPU)."""
+
+    def __init__(self, seed: int = 0):
+        self.mlp = Mlp(Mlp.init_params(seed))
+        self.seed = seed
+        self.history = []
+
+    def fit(self, train: Sequence[Observed], epochs: int = 4, batch: int = 16384, lr: float = 1e-3,
+            feats: Optional[list] = None):
+        import torch
+        X = torch.cat(feats if feats is not None else [features(o) for o in train])
+        y = torch.tensor(np.concatenate([o.labels for o in train]).astype(np.float32), device=X.device)
+        mean = X.mean(0)
+        std = X.std(0)
+        scale = torch.where(std > 1e-6, 1.0 / std, torch.zeros_like(std))
+        self.mlp.set_input_norm(mean.cpu().numpy(), scale.cpu().numpy())
+        g = torch.Generator(device="cpu").manual_seed(self.seed)
+        n = X.shape[0]
+        loss = torch.zeros(1, dtype=torch.float32, device=X.device)
+        for ep in range(epochs):
+            perm = torch.randperm(n, generator=g).to(X.device)
+            Xs, ys = X[perm].contiguous(), y[perm].contiguous()
+            tot, steps = 0.0, 0
+            for a in range(0, n - batch + 1, batch):
+                self.mlp.train_step(Xs[a:a + batch], ys[a:a + batch], lr, loss=loss)
+                tot += float(loss.item()) if (steps % 50 == 0) else 0.0
+                steps += 1
+            self.history.append(tot)
+        return self
+
+    def score(self, o: Observed, feats=None):
+        f = features(o) if feats is None else feats
+        return self.mlp.forward(f)
