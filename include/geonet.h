@@ -288,6 +288,39 @@ typedef struct {
  * for completion.
  */
 net_status net_features(const net_obs_desc* obs, float* features_dev, void* stream);
+
+/* Options of the simulation-based fit (zeroed struct or NULL: defaults). */
+typedef struct {
+    int32_t realisations;   /* K noise realisations per hypothesis, divides 64 (default 8) */
+    int32_t sweeps;         /* toggle sweeps (default 0 with a zeroed struct: pass 2 for the usual fit) */
+    float init_fraction;    /* initial in-neighbours per target: top fraction by correlation (0.3) */
+    int32_t pad;
+    uint64_t fit_seed;      /* Philox key of the fit's own noise (never the data's) */
+} net_simfit_opts;
+
+enum { NET_EST_SCORER = 1, NET_EST_SIMFIT = 2 };
+
+/*
+ * Scores of the candidate pairs (device [n_pairs] FP32; higher = more likely
+ * an edge i -> j), from the observations only (the inverse problem of
+ * Sections 1 and 4):
+ *   NET_EST_SCORER  features (net_features) through the trained MLP `scorer`;
+ *                   scores are logits.
+ *   NET_EST_SIMFIT  simulation-based fit.  Each target j is simulated with the
+ *                   vertex model of the forward path, teacher-forced by the
+ *                   deconvolved activity of a hypothesised in-neighbour set G
+ *                   (input w_assumed * e_i(f) spread over frame f), its own
+ *                   control pulses and K noise realisations (fit_seed); the
+ *                   observed trace is scored with the Gaussian observation
+ *                   model using the realisations' mean and variance.  G starts
+ *                   as the top init_fraction by lag-0 plus lag-1 correlation;
+ *                   each sweep evaluates every single toggle and, per target,
+ *                   applies the one that raises the likelihood most (if any).
+ *                   Score = LL(G + e) - LL(G - e) at the final G.
+ * Waits for completion.
+ */
+net_status net_estimate(const net_obs_desc* obs, int32_t method, net_mlp_t* scorer, const net_simfit_opts* opts,
+                        float* scores_dev, void* stream);
 const char* net_estimate_last_error(void);
 
 /* Release the handle and its device memory (waits for the handle's stream). */

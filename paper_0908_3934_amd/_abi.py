@@ -82,6 +82,14 @@ class ObsDesc(C.Structure):
     ]
 
 
+class SimfitOpts(C.Structure):
+    _fields_ = [("realisations", C.c_int32), ("sweeps", C.c_int32), ("init_fraction", C.c_float),
+                ("pad", C.c_int32), ("fit_seed", C.c_uint64)]
+
+
+NET_EST_SCORER = 1
+NET_EST_SIMFIT = 2
+
 ALLOC_FN = C.CFUNCTYPE(_vp, C.c_size_t, _vp, _vp)
 RELEASE_FN = C.CFUNCTYPE(None, _vp, _vp, _vp)
 
@@ -102,6 +110,7 @@ SIGNATURES = {
     "net_mlp_get_params": (C.c_int, [_vp, _vp, C.c_int64]),
     "net_mlp_set_input_norm": (C.c_int, [_vp, _vp, _vp]),
     "net_features": (C.c_int, [_vp, _vp, _vp]),
+    "net_estimate": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp]),
     "net_estimate_last_error": (C.c_char_p, []),
     "net_mlp_forward": (C.c_int, [_vp, _vp, C.c_int64, _vp, _vp]),
     "net_mlp_grad": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, _vp, _vp]),

@@ -184,6 +184,29 @@ struct FeatureWork {
 hipError_t launch_features(const FeatureInputs& in, const FeatureWork& w, float* out, hipStream_t s);
 uint32_t pulse_threshold(double rate_hz, double dt_ms);
 
+// Simulation-based fit.
+struct FitInputs {
+    const float* F;             // device [nf][n]
+    const uint32_t* drive_thr;  // device [n] or null
+    const int32_t* pairs;       // device [P][2], sorted by target
+    int32_t n, nf, K, n_ref;
+    int64_t P, t_end, frame_num, frame_den;
+    float rho, offset, inv_jump, w, decay, v_rest, v_reset, v_th, sigma, drive_amp, gamma;
+    double dt, tau_c, gain;
+    uint32_t ctl_lo, ctl_hi, fit_lo, fit_hi;
+};
+struct FitWork {
+    float* e;          // [n][nf]
+    uint32_t* pulses;  // [n][words]
+    float* base;       // [n][nf]
+    uint8_t* member;   // [P]
+    int64_t* row;      // [n+1]
+    double* ll;        // [P + n]
+    int32_t words;
+};
+hipError_t fit_prep(const FitInputs& in, const FitWork& w, hipStream_t s);
+hipError_t fit_eval(const FitInputs& in, const FitWork& w, hipStream_t s);
+
 hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const float* y, bool backward, hipStream_t s);
 hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, hipStream_t s);
 hipError_t mlp_adam(const MlpDevice& d, float lr, float beta1, float beta2, float eps, int64_t t, hipStream_t s);

@@ -137,6 +137,30 @@ def features(o: Observed, stream=None):
     return out
 
 
+def simfit(o: Observed, w_assumed: float, realisations: int = 8, sweeps: int = 2, init_fraction: float = 0.3,
+           fit_seed: int = 0x5EEDF17, stream=None):
+    """Simulation-based fit scores LL(G + e) - LL(G - e) per candidate pair."""
+    import torch
+    out = torch.empty(int(o.pairs.shape[0]), dtype=torch.float32, device=o.F.device)
+    keep = []
+    d = obs_desc(o, keep, w_assumed=w_assumed)
+    opts = _abi.SimfitOpts(realisations, sweeps, init_fraction, 0, fit_seed)
+    _echeck(library().net_estimate(C.byref(d), _abi.NET_EST_SIMFIT, None, C.byref(opts), out.data_ptr(),
+                                   _stream_handle(stream)), "net_estimate")
+    return out
+
+
+def scorer_scores(o: Observed, scorer: "EdgeScorer", stream=None):
+    """Learned scores through the library's single SCORER entry point."""
+    import torch
+    out = torch.empty(int(o.pairs.shape[0]), dtype=torch.float32, device=o.F.device)
+    keep = []
+    d = obs_desc(o, keep)
+    _echeck(library().net_estimate(C.byref(d), _abi.NET_EST_SCORER, scorer.mlp.h, None, out.data_ptr(),
+                                   _stream_handle(stream)), "net_estimate")
+    return out
+
+
 def auc(scores, labels) -> float:
     """Mann-Whitney area under the ROC curve, ties counted 1/2."""
     s = np.asarray(scores, dtype=np.float64)
