@@ -111,12 +111,23 @@ typedef struct {
 
 /* Build flags (variants that compute the same result; for tuning/measurement). */
 #define NET_BUILD_NO_LDS_SUMMARY 1        /* keep the recent-spike summary in global memory */
-#define NET_BUILD_DELIVER_PREFETCH 2      /* delivery: prefetch the next edge chunks */
+#define NET_BUILD_DELIVER_STREAM_WEIGHTS 2 /* delivery: stream every weight with its edge
+                                             (default: load a weight only when its edge
+                                             delivers a spike) */
 #define NET_BUILD_DELIVER_NONTEMPORAL 4   /* delivery: non-temporal edge loads */
 #define NET_BUILD_PER_STEP 8              /* ensembles: per-step kernels instead of the
                                              single-launch ensemble kernel */
 #define NET_BUILD_DELIVER_UNROLL2 16      /* delivery: two 512-edge chunks per wave iteration
                                              (default one) */
+#define NET_BUILD_SINGLE_LAUNCH 32        /* one network: run all steps of a call in one launch of
+                                             the LDS-resident kernel ensembles use, when the
+                                             network fits one workgroup's LDS */
+#define NET_BUILD_AUTOTUNE 64             /* time the candidate launch shapes on this graph at
+                                             build (a few steps from the initial state, which is
+                                             then restored) and keep the fastest: delivery
+                                             variants for the per-step kernels, workgroup size and
+                                             workgroups per CU for the single-launch kernel.
+                                             Every candidate computes the same bits. */
 
 /*
  * Optional per-step records for net_step_n (device pointers, may be NULL).
@@ -143,6 +154,9 @@ typedef struct {
     int32_t lds_summary;    /* 1 if the delivery kernel stages the summary in LDS */
     int32_t deliver_blocks, deliver_threads;
     int64_t device_bytes;   /* device memory held by the handle */
+    int32_t deliver_flags;  /* NET_BUILD_DELIVER_* bits of the delivery variant in use */
+    int32_t ensemble_blocks, ensemble_threads;   /* single-launch kernel shape (0: per-step kernels) */
+    int32_t autotuned;      /* 1 if the launch shape was chosen by timing at build */
 } net_info_t;
 
 /*
@@ -294,7 +308,8 @@ typedef struct {
     int32_t realisations;   /* K noise realisations per hypothesis, divides 64 (default 8) */
     int32_t sweeps;         /* toggle sweeps (default 0 with a zeroed struct: pass 2 for the usual fit) */
     float init_fraction;    /* initial in-neighbours per target: top fraction by correlation (0.3) */
-    int32_t pad;
+    float min_gain;         /* smallest log-likelihood gain (nats) for which a toggle is applied
+                               (<= 0: 1e-3) */
     uint64_t fit_seed;      /* Philox key of the fit's own noise (never the data's) */
 } net_simfit_opts;
 
@@ -315,7 +330,8 @@ enum { NET_EST_SCORER = 1, NET_EST_SIMFIT = 2 };
  *                   model using the realisations' mean and variance.  G starts
  *                   as the top init_fraction by lag-0 plus lag-1 correlation;
  *                   each sweep evaluates every single toggle and, per target,
- *                   applies the one that raises the likelihood most (if any).
+ *                   applies the one that raises the likelihood most, if by more
+ *                   than min_gain.
  *                   Score = LL(G + e) - LL(G - e) at the final G.
  * Waits for completion.
  */

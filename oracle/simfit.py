@@ -14,8 +14,8 @@ is defined here, in the steps the GPU path follows:
    Gaussian log-likelihood of the observed trace with the realisations'
    frame-mean calcium mean and variance;
 4. each sweep evaluates every single toggle and, per target, applies the
-   one that raises its likelihood most (if any); the score of a candidate
-   is LL(G + e) - LL(G - e) at the final G.
+   one that raises its likelihood most, if by more than min_gain nats; the
+   score of a candidate is LL(G + e) - LL(G - e) at the final G.
 
 Everything is float64 and vectorised over all hypotheses and realisations.
 """
@@ -98,7 +98,8 @@ def loglik(cbar, Fj, gain, offset, gamma):
 
 
 def fit(F, pairs, *, drive_thr, control_seed, gain, offset, gamma, dt, tau, v_rest, v_reset, v_th, n_ref, sigma,
-        drive_amp, tau_c, frame_num, frame_den, w, K=8, sweeps=2, init_fraction=0.3, fit_seed=0x5EEDF17):
+        drive_amp, tau_c, frame_num, frame_den, w, K=8, sweeps=2, init_fraction=0.3, fit_seed=0x5EEDF17,
+        min_gain=1e-3):
     """Scores LL(G + e) - LL(G - e) per pair (in the given order)."""
     F = np.asarray(F, dtype=np.float64)
     nf, n = F.shape
@@ -138,7 +139,7 @@ def fit(F, pairs, *, drive_thr, control_seed, gain, offset, gamma, dt, tau, v_re
         for j in np.unique(targets):
             idx = np.nonzero(targets == j)[0]          # candidates of j in pair order
             k = idx[np.argmax(delta[idx])]             # first maximum, as the library's scan
-            if delta[k] > 0.0:
+            if delta[k] > min_gain:
                 member[k] = ~member[k]
     cur, tog = ll[P + targets], ll[:P]
     return np.where(member, cur - tog, tog - cur), member, ll

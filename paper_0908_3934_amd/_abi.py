@@ -17,10 +17,12 @@ NET_E_STATE = -5
 NET_E_UNSUPPORTED = -6
 
 NET_BUILD_NO_LDS_SUMMARY = 1
-NET_BUILD_DELIVER_PREFETCH = 2
+NET_BUILD_DELIVER_STREAM_WEIGHTS = 2
 NET_BUILD_DELIVER_NONTEMPORAL = 4
 NET_BUILD_PER_STEP = 8
 NET_BUILD_DELIVER_UNROLL2 = 16
+NET_BUILD_SINGLE_LAUNCH = 32
+NET_BUILD_AUTOTUNE = 64
 
 NET_OBS_V = 1
 NET_OBS_REF = 2
@@ -58,6 +60,8 @@ class Info(C.Structure):
         ("n_nets", C.c_int32), ("max_delay", C.c_int32), ("raster_words", C.c_int64), ("t", C.c_int64),
         ("frames_done", C.c_int64), ("exact", C.c_int32), ("summary_window", C.c_int32), ("lds_summary", C.c_int32),
         ("deliver_blocks", C.c_int32), ("deliver_threads", C.c_int32), ("device_bytes", C.c_int64),
+        ("deliver_flags", C.c_int32), ("ensemble_blocks", C.c_int32), ("ensemble_threads", C.c_int32),
+        ("autotuned", C.c_int32),
     ]
 
 
@@ -84,7 +88,7 @@ class ObsDesc(C.Structure):
 
 class SimfitOpts(C.Structure):
     _fields_ = [("realisations", C.c_int32), ("sweeps", C.c_int32), ("init_fraction", C.c_float),
-                ("pad", C.c_int32), ("fit_seed", C.c_uint64)]
+                ("min_gain", C.c_float), ("fit_seed", C.c_uint64)]
 
 
 NET_EST_SCORER = 1

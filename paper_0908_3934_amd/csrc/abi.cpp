@@ -32,6 +32,7 @@ struct net {
     std::vector<int64_t> tsteps;
     int64_t t_cap = 0, t_used = 0;
     EnsemblePlan plan;
+    bool autotuned = false;
 };
 
 namespace {
@@ -167,6 +168,81 @@ bool plan_ensemble(net* h, const HostGraph& hg, int n_cu, int wgs_per_cu, int th
     return true;
 }
 
+// Plans the single-launch kernel for one shape and uploads the plan into the
+// handle's plan buffers (allocated once, for the largest shape).
+bool load_plan(net* h, const HostGraph& hg, int n_cu, int per_cu, int threads, bool observe, hipStream_t s) {
+    std::vector<NetMeta> meta;
+    std::vector<int32_t> wg_nets, wg_off;
+    size_t lds_max = 0;
+    if (!plan_ensemble(h, hg, n_cu, per_cu, threads, observe, meta, wg_nets, wg_off, lds_max)) return false;
+    EnsemblePlan& pl = h->plan;
+    if (hipMemcpyAsync(pl.meta, meta.data(), meta.size() * sizeof(NetMeta), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(pl.wg_nets, wg_nets.data(), wg_nets.size() * sizeof(int32_t), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(pl.wg_off, wg_off.data(), wg_off.size() * sizeof(int32_t), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return false;
+    pl.blocks = static_cast<int>(wg_off.size()) - 1;
+    pl.threads = threads;
+    pl.lds_bytes = lds_max;
+    return enable_ensemble_lds(lds_max) == hipSuccess;
+}
+
+// Back to the state right after build: V = v0, every other state array zero
+// (age = never fired).
+net_status reset_state(net* h, const HostGraph& hg, hipStream_t s) {
+    DeviceGraph& g = h->g;
+    const size_t np = static_cast<size_t>(g.n_pad);
+    hipError_t e = hipMemcpyAsync(g.V, hg.v0.data(), std::min(hg.v0.size(), np) * sizeof(float),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(g.age, kAgeNever, np, s);
+    if (e == hipSuccess) e = hipMemsetAsync(g.I, 0, np * sizeof(float), s);
+    if (e == hipSuccess) e = hipMemsetAsync(g.ring, 0, np * kRingWords * sizeof(uint32_t), s);
+    if (e == hipSuccess) e = hipMemsetAsync(g.summary, 0, np / 32 * sizeof(uint32_t), s);
+    if (e == hipSuccess && g.calcium) e = hipMemsetAsync(g.calcium, 0, np * sizeof(double), s);
+    if (e == hipSuccess && g.frame_acc) e = hipMemsetAsync(g.frame_acc, 0, np * sizeof(double), s);
+    if (e == hipSuccess && g.frames)
+        e = hipMemsetAsync(g.frames, 0, np * static_cast<size_t>(g.frame_cap) * sizeof(float), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? NET_OK : device_fail(h, e, "net_build: state reset");
+}
+
+// Milliseconds of `steps` steps from the current state with the handle's
+// current launch shape: the single-launch kernel if planned, else the sum of
+// the per-step delivery kernels (the part the variants change).
+bool trial_ms(net* h, int64_t t0, int32_t steps, hipStream_t s, double* ms) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return false;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return false;
+    }
+    bool ok = true;
+    double total = 0.0;
+    if (h->plan.enabled) {
+        ok = launch_ensemble(h->g, h->plan, t0, steps, nullptr, h->frame_num, h->frame_den, s, e0, e1) == hipSuccess &&
+             hipEventSynchronize(e1) == hipSuccess;
+        float m = 0.0f;
+        ok = ok && hipEventElapsedTime(&m, e0, e1) == hipSuccess;
+        total = m;
+    } else {
+        for (int32_t k = 0; ok && k < steps; ++k) {
+            ok = launch_deliver(h->g, h->lc, t0 + k, s, e0, e1) == hipSuccess &&
+                 launch_node_update(h->g, t0 + k, 0, nullptr, 0, 0, 0, s, nullptr, nullptr) == hipSuccess &&
+                 hipEventSynchronize(e1) == hipSuccess;
+            float m = 0.0f;
+            ok = ok && hipEventElapsedTime(&m, e0, e1) == hipSuccess;
+            total += m;
+        }
+    }
+    ok = ok && hipStreamSynchronize(s) == hipSuccess;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = total;
+    return ok;
+}
+
 }  // namespace
 
 extern "C" {
@@ -274,39 +350,102 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
         device_fail(h, e, "net_build: configure");
         return bail(NET_E_DEVICE);
     }
-    if (n_nets > 1 && !(opts && (opts->flags & NET_BUILD_PER_STEP))) {
+    const int flags = opts ? opts->flags : 0;
+    const bool autotune = (flags & NET_BUILD_AUTOTUNE) != 0;
+    const bool single = n_nets > 1 || (flags & NET_BUILD_SINGLE_LAUNCH);
+    if (single && !(flags & NET_BUILD_PER_STEP)) {
         int dev = 0, n_cu = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
-            std::vector<NetMeta> meta;
-            std::vector<int32_t> wg_nets, wg_off;
-            size_t lds_max = 0;
             const bool observe = frame_cap > 0 && hg.frame_num > 0;
-            int per_cu = (opts && opts->blocks_per_cu) ? opts->blocks_per_cu : 2;
-            int threads = (opts && opts->block_threads) ? opts->block_threads : (per_cu >= 2 ? 512 : 1024);
-            bool ok = plan_ensemble(h, hg, n_cu, per_cu, threads, observe, meta, wg_nets, wg_off, lds_max);
-            if (!ok && per_cu > 1 && !(opts && opts->blocks_per_cu)) {
-                per_cu = 1;
-                threads = (opts && opts->block_threads) ? opts->block_threads : 1024;
-                ok = plan_ensemble(h, hg, n_cu, per_cu, threads, observe, meta, wg_nets, wg_off, lds_max);
+            // candidate shapes (workgroups per CU, threads); explicit options pin them
+            std::vector<std::pair<int, int>> shapes;
+            const int opt_cu = opts ? opts->blocks_per_cu : 0, opt_thr = opts ? opts->block_threads : 0;
+            if (opt_cu || opt_thr) {
+                const int pc = opt_cu ? opt_cu : 2;
+                shapes.push_back({pc, opt_thr ? opt_thr : (pc >= 2 ? 512 : 1024)});
+            } else if (autotune) {
+                shapes = {{2, 512}, {1, 1024}, {1, 512}, {2, 256}, {4, 256}};
+            } else {
+                shapes = {{2, 512}, {1, 1024}};      // the first that fits
             }
-            if (ok) {
-                EnsemblePlan& pl = h->plan;
-                std::vector<NetMeta> mv(meta.begin(), meta.end());
-                if ((st = upload(h, &pl.meta, mv, mv.size(), s, "ensemble plan")) != NET_OK) return bail(st);
-                if ((st = upload(h, &pl.wg_nets, wg_nets, wg_nets.size(), s, "ensemble plan")) != NET_OK) return bail(st);
-                if ((st = upload(h, &pl.wg_off, wg_off, wg_off.size(), s, "ensemble plan")) != NET_OK) return bail(st);
-                pl.blocks = static_cast<int>(wg_off.size()) - 1;
-                pl.threads = threads;
-                pl.lds_bytes = lds_max;
-                e = enable_ensemble_lds(lds_max);
-                if (e != hipSuccess) {
-                    device_fail(h, e, "net_build: ensemble LDS");
+            int max_cu = 1;
+            for (auto& sh : shapes) max_cu = std::max(max_cu, sh.first);
+            EnsemblePlan& pl = h->plan;
+            const size_t nn = static_cast<size_t>(n_nets);
+            const size_t nwg = static_cast<size_t>(n_cu) * static_cast<size_t>(max_cu) + 1;
+            std::vector<NetMeta> meta0(nn);
+            std::vector<int32_t> zi(std::max(nn, nwg), 0);
+            if ((st = upload(h, &pl.meta, meta0, nn, s, "ensemble plan")) != NET_OK) return bail(st);
+            if ((st = upload(h, &pl.wg_nets, zi, nn, s, "ensemble plan")) != NET_OK) return bail(st);
+            if ((st = upload(h, &pl.wg_off, zi, nwg, s, "ensemble plan")) != NET_OK) return bail(st);
+            int best = -1;
+            double best_ms = 0.0;
+            for (size_t k = 0; k < shapes.size(); ++k) {
+                if (!load_plan(h, hg, n_cu, shapes[k].first, shapes[k].second, observe, s)) continue;
+                if (!autotune || shapes.size() == 1) {
+                    best = static_cast<int>(k);
+                    break;
+                }
+                pl.enabled = true;
+                double ms = 0.0;
+                const bool ok = trial_ms(h, 0, 8, s, &ms) && trial_ms(h, 8, 64, s, &ms);
+                pl.enabled = false;
+                if ((st = reset_state(h, hg, s)) != NET_OK) return bail(st);
+                if (!ok) {
+                    (void)hipGetLastError();
+                    continue;
+                }
+                if (best < 0 || ms < best_ms) {
+                    best = static_cast<int>(k);
+                    best_ms = ms;
+                }
+            }
+            if (best >= 0) {
+                if (!load_plan(h, hg, n_cu, shapes[best].first, shapes[best].second, observe, s)) {
+                    device_fail(h, hipErrorUnknown, "net_build: ensemble plan");
                     return bail(NET_E_DEVICE);
                 }
                 pl.enabled = true;
+                h->autotuned = autotune && shapes.size() > 1;
             }
         }
+    }
+    if (autotune && !h->plan.enabled) {
+        // delivery variants of the per-step kernels (identical results)
+        const int variants[] = {0,
+                                NET_BUILD_DELIVER_UNROLL2,
+                                NET_BUILD_DELIVER_NONTEMPORAL,
+                                NET_BUILD_DELIVER_UNROLL2 | NET_BUILD_DELIVER_NONTEMPORAL,
+                                NET_BUILD_DELIVER_STREAM_WEIGHTS,
+                                NET_BUILD_DELIVER_STREAM_WEIGHTS | NET_BUILD_DELIVER_UNROLL2};
+        net_build_opts o = opts ? *opts : net_build_opts{};
+        const int keep = o.flags & ~(NET_BUILD_DELIVER_UNROLL2 | NET_BUILD_DELIVER_NONTEMPORAL |
+                                     NET_BUILD_DELIVER_STREAM_WEIGHTS);
+        int best = -1;
+        double best_ms = 0.0;
+        for (int k = 0; k < static_cast<int>(sizeof(variants) / sizeof(variants[0])); ++k) {
+            o.flags = keep | variants[k];
+            if (configure_deliver(g, &o, h->lc) != hipSuccess) continue;
+            double ms = 0.0;
+            const bool ok = trial_ms(h, 0, 4, s, &ms) && trial_ms(h, 4, 16, s, &ms);
+            if ((st = reset_state(h, hg, s)) != NET_OK) return bail(st);
+            if (!ok) {
+                (void)hipGetLastError();
+                continue;
+            }
+            if (best < 0 || ms < best_ms) {
+                best = k;
+                best_ms = ms;
+            }
+        }
+        o.flags = keep | (best >= 0 ? variants[best] : 0);
+        e = configure_deliver(g, &o, h->lc);
+        if (e != hipSuccess) {
+            device_fail(h, e, "net_build: configure");
+            return bail(NET_E_DEVICE);
+        }
+        h->autotuned = best >= 0;
     }
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -440,6 +579,12 @@ net_status net_info(const net_t* h, net_info_t* out) {
     out->deliver_blocks = h->lc.deliver_blocks;
     out->deliver_threads = h->lc.deliver_threads;
     out->device_bytes = h->device_bytes;
+    out->deliver_flags = (h->lc.unroll == 2 ? NET_BUILD_DELIVER_UNROLL2 : 0) |
+                         (h->lc.nontemporal ? NET_BUILD_DELIVER_NONTEMPORAL : 0) |
+                         (h->lc.stream_weights ? NET_BUILD_DELIVER_STREAM_WEIGHTS : 0);
+    out->ensemble_blocks = h->plan.enabled ? h->plan.blocks : 0;
+    out->ensemble_threads = h->plan.enabled ? h->plan.threads : 0;
+    out->autotuned = h->autotuned ? 1 : 0;
     return NET_OK;
 }
 

@@ -100,6 +100,7 @@ net_status simfit(const net_obs_desc* o, const net_simfit_opts* opts, float* out
     const int K = opts && opts->realisations ? opts->realisations : 8;
     const int sweeps = opts ? opts->sweeps : 2;
     const double init_frac = opts && opts->init_fraction > 0.0f ? opts->init_fraction : 0.3;
+    const double min_gain = opts && opts->min_gain > 0.0f ? opts->min_gain : 1e-3;
     if (K < 1 || K > 64 || (64 % K) != 0) return efail(NET_E_ARG, "simfit: realisations must divide 64");
     if (sweeps < 0 || sweeps > 64) return efail(NET_E_ARG, "simfit: sweeps in 0..64");
     const int64_t P = o->n_pairs, n = o->n_nodes, nf = o->n_frames;
@@ -132,7 +133,7 @@ net_status simfit(const net_obs_desc* o, const net_simfit_opts* opts, float* out
     w.words = static_cast<int32_t>((t_end + 31) / 32);
     w.e = sc.get<float>(n * nf);
     w.pulses = sc.get<uint32_t>(n * static_cast<int64_t>(w.words));
-    w.base = sc.get<float>(n * nf);
+    w.base = sc.get<double>(n * nf);
     w.member = sc.get<uint8_t>(P);
     w.row = sc.get<int64_t>(n + 1);
     w.ll = sc.get<double>(P + n);
@@ -184,7 +185,7 @@ net_status simfit(const net_obs_desc* o, const net_simfit_opts* opts, float* out
     in.offset = o->offset;
     in.inv_jump = static_cast<float>(1.0 / (static_cast<double>(o->gain) * o->dt_ms));
     in.w = o->w_assumed;
-    in.decay = static_cast<float>(o->dt_ms / static_cast<double>(o->tau_ms));
+    in.decay = o->dt_ms / static_cast<double>(o->tau_ms);
     in.v_rest = o->v_rest;
     in.v_reset = o->v_reset;
     in.v_th = o->v_th;
@@ -208,11 +209,13 @@ net_status simfit(const net_obs_desc* o, const net_simfit_opts* opts, float* out
         if (e != hipSuccess) return efail(NET_E_DEVICE, std::string("simfit: ") + hipGetErrorString(e));
         if (!to_host(ll, w.ll, static_cast<size_t>(P + n), s)) return efail(NET_E_DEVICE, "simfit: evaluation");
         if (sw == sweeps) break;
-        // per target, apply the single toggle that raises its likelihood most
-        // (coordinate ascent: every sweep improves each target or leaves it)
+        // per target, apply the single toggle that raises its likelihood most,
+        // if by more than min_gain (coordinate ascent: every sweep improves
+        // each target or leaves it; gains below min_gain are noise of the
+        // K-realisation estimate)
         for (int64_t j = 0; j < n; ++j) {
             int64_t best = -1;
-            double gain = 0.0;
+            double gain = min_gain;
             for (int64_t q = row[j]; q < row[j + 1]; ++q)
                 if (ll[q] - ll[P + j] > gain) {
                     gain = ll[q] - ll[P + j];

@@ -99,9 +99,9 @@ struct LaunchConfig {
     int deliver_blocks = 0;
     int deliver_threads = 0;
     bool lds_summary = false;
-    bool prefetch = false;
+    bool stream_weights = false;
     bool nontemporal = false;
-    int unroll = 2;
+    int unroll = 1;
     size_t lds_bytes = 0;
 };
 
@@ -191,14 +191,15 @@ struct FitInputs {
     const int32_t* pairs;       // device [P][2], sorted by target
     int32_t n, nf, K, n_ref;
     int64_t P, t_end, frame_num, frame_den;
-    float rho, offset, inv_jump, w, decay, v_rest, v_reset, v_th, sigma, drive_amp, gamma;
+    float rho, offset, inv_jump, sigma, gamma;
+    double w, decay, v_rest, v_reset, v_th, drive_amp;   // the fit's vertex model runs in FP64
     double dt, tau_c, gain;
     uint32_t ctl_lo, ctl_hi, fit_lo, fit_hi;
 };
 struct FitWork {
     float* e;          // [n][nf]
     uint32_t* pulses;  // [n][words]
-    float* base;       // [n][nf]
+    double* base;      // [n][nf]
     uint8_t* member;   // [P]
     int64_t* row;      // [n+1]
     double* ll;        // [P + n]

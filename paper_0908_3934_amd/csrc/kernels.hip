@@ -78,12 +78,16 @@ struct DeliverArgs {
 };
 
 // One wave handles 512 consecutive slots per iteration: lane L owns slots
-// 8L .. 8L+7 of the chunk, loaded as 2x16 B (sources), 16 B (weights) and
-// 8 B (delays).  Workgroups take contiguous chunk ranges; ranges of the
-// workgroups that share an XCD (blockIdx % 8) are adjacent, so the history
-// words they gather for neighbouring targets meet in that XCD's L2.
-// The next chunk's stream loads are issued right after the current chunk's
-// history gathers, so they are in flight while the gathers are consumed.
+// 8L .. 8L+7 of the chunk, loaded as 2x16 B (sources) and 8 B (delays).
+// Workgroups take contiguous chunk ranges; ranges of the workgroups that
+// share an XCD (blockIdx % 8) are adjacent, so the history words they gather
+// for neighbouring targets meet in that XCD's L2.
+//
+// A weight is needed only when its edge delivers a spike (a few in 10^4
+// edges at physiological rates), so by default weights are not streamed:
+// each arrival loads its own 2 B weight, and the stream is 5 B per edge
+// instead of 7.  kWStream = true streams the weights with the chunk (16 B per
+// lane) instead.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
@@ -94,21 +98,19 @@ struct ChunkRegs {
     uint32_t rs;
 };
 
-// Stream loads of one chunk.  The edge list is read once per step and is
-// larger than the last-level cache, so it is loaded non-temporally to leave
-// the caches to the history ring and the summary.
-template <bool kNT>
+// Stream loads of one chunk (optionally non-temporal).
+template <bool kWStream, bool kNT>
 __device__ __forceinline__ void load_chunk(ChunkRegs& x, const DeliverArgs& a, int64_t c, int lane) {
     const int64_t e0 = c * kChunkEdges + lane * kEdgesPerLane;
     if (kNT) {
         x.s_lo = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(a.src + e0));
         x.s_hi = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(a.src + e0 + 4));
-        x.wq = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(a.w + e0));
+        if (kWStream) x.wq = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(a.w + e0));
         x.dq = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(a.d + e0));
     } else {
         x.s_lo = *reinterpret_cast<const u32x4*>(a.src + e0);
         x.s_hi = *reinterpret_cast<const u32x4*>(a.src + e0 + 4);
-        x.wq = *reinterpret_cast<const u32x4*>(a.w + e0);
+        if (kWStream) x.wq = *reinterpret_cast<const u32x4*>(a.w + e0);
         x.dq = *reinterpret_cast<const u32x2*>(a.d + e0);
     }
     x.rs = a.rowstart[c * 64 + lane];
@@ -118,17 +120,27 @@ __device__ __forceinline__ void load_chunk(ChunkRegs& x, const DeliverArgs& a, i
 // belongs to chunk_row0 whether or not it opens a row), then one exact FP32
 // atomic add per arrival.  All partial sums of a row are exact in FP32, so
 // the order of these additions does not change the result.
+template <bool kWStream>
 __device__ __forceinline__ void deliver_fired(const DeliverArgs& a, int64_t c, int lane, uint32_t fired, uint32_t rs,
                                               const u32x4& wq) {
     const uint32_t bits = lane == 0 ? (rs & ~1u) : rs;
     const uint32_t before = wave_exclusive_sum(__popc(bits), lane);
     const int32_t row0 = a.chunk_row0[c] + static_cast<int32_t>(before);
+    const int64_t e0 = c * kChunkEdges + lane * kEdgesPerLane;
     const uint32_t wv[4] = {wq.x, wq.y, wq.z, wq.w};
+    uint32_t wb[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {   // all weight loads first, then the adds
+        if (kWStream)
+            wb[k] = (wv[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+        else
+            wb[k] = ((fired >> k) & 1u) ? a.w[e0 + k] : 0u;
+    }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         if ((fired >> k) & 1u) {
             const int32_t row = row0 + __popc(bits & ((2u << k) - 1u));
-            unsafeAtomicAdd(a.I + row, half_bits_to_float((wv[k >> 1] >> (16 * (k & 1))) & 0xFFFFu));
+            unsafeAtomicAdd(a.I + row, half_bits_to_float(wb[k]));
         }
     }
 }
@@ -136,7 +148,7 @@ __device__ __forceinline__ void deliver_fired(const DeliverArgs& a, int64_t c, i
 // kUnroll chunks per wave iteration: all their stream loads are issued
 // before the first wait, and all their history gathers before the second,
 // so a wave keeps kUnroll chunks of loads in flight.
-template <bool kLdsSummary, bool kPrefetch, bool kNT, int kUnroll>
+template <bool kLdsSummary, bool kWStream, bool kNT, int kUnroll>
 __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
     extern __shared__ uint4 lds_summary4[];
     const uint32_t* lds_summary = reinterpret_cast<const uint32_t*>(lds_summary4);
@@ -151,27 +163,18 @@ __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
     const uint32_t t = a.t;
     const int64_t stride = static_cast<int64_t>(nwaves) * kUnroll;
 
-    int64_t c = c_begin + static_cast<int64_t>(wave) * kUnroll;
-    ChunkRegs cur[kUnroll];
-    if (kPrefetch) {
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int64_t cu = c + u < c_end ? c + u : c_end - 1;
-            if (c < c_end) load_chunk<kNT>(cur[u], a, cu, lane);
-        }
-    }
     if (kLdsSummary) {
         const uint4* g = reinterpret_cast<const uint4*>(a.summary);
         for (int i = threadIdx.x; i < a.summary_vec4; i += blockDim.x) lds_summary4[i] = g[i];
         __syncthreads();
     }
 
-    for (; c < c_end; c += stride) {
+    for (int64_t c = c_begin + static_cast<int64_t>(wave) * kUnroll; c < c_end; c += stride) {
         // chunks beyond the range repeat the last one and are masked below
-        if (!kPrefetch) {
+        ChunkRegs cur[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) load_chunk<kNT>(cur[u], a, c + u < c_end ? c + u : c_end - 1, lane);
-        }
+        for (int u = 0; u < kUnroll; ++u)
+            load_chunk<kWStream, kNT>(cur[u], a, c + u < c_end ? c + u : c_end - 1, lane);
         uint32_t slot[kUnroll][8], word[kUnroll][8], cand[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
@@ -191,28 +194,13 @@ __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
                 cand[u] |= hit << k;
             }
         }
-        u32x4 wq[kUnroll];
-        uint32_t rs[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            wq[u] = cur[u].wq;
-            rs[u] = cur[u].rs;
-        }
-        if (kPrefetch) {
-            // unconditional, so consuming the gathers never waits for these loads
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const int64_t cn = c + stride + u;
-                load_chunk<kNT>(cur[u], a, cn < c_end ? cn : c_end - 1, lane);
-            }
-        }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             uint32_t fired = 0;
 #pragma unroll
             for (int k = 0; k < 8; ++k) fired |= (((cand[u] >> k) & (word[u][k] >> (slot[u][k] & 31))) & 1u) << k;
             if (c + u >= c_end) fired = 0;
-            if (wave_ballot(fired != 0)) deliver_fired(a, c + u, lane, fired, rs[u], wq[u]);
+            if (wave_ballot(fired != 0)) deliver_fired<kWStream>(a, c + u, lane, fired, cur[u].rs, cur[u].wq);
         }
     }
 }
@@ -431,7 +419,6 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
                 const int64_t e0 = static_cast<int64_t>(c) * kChunkEdges + lane * kEdgesPerLane;
                 const u32x4 s_lo = *reinterpret_cast<const u32x4*>(a.src + e0);
                 const u32x4 s_hi = *reinterpret_cast<const u32x4*>(a.src + e0 + 4);
-                const u32x4 wq = *reinterpret_cast<const u32x4*>(a.w + e0);
                 const u32x2 dq = *reinterpret_cast<const u32x2*>(a.d + e0);
                 const uint32_t sv[8] = {s_lo.x, s_lo.y, s_lo.z, s_lo.w, s_hi.x, s_hi.y, s_hi.z, s_hi.w};
                 uint32_t fired = 0;
@@ -448,12 +435,14 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
                     const uint32_t bits = lane == 0 ? (rs & ~1u) : rs;
                     const uint32_t before = wave_exclusive_sum(__popc(bits), lane);
                     const int32_t row0 = a.chunk_row0[c] - nm.node_off + static_cast<int32_t>(before);
-                    const uint32_t wv[4] = {wq.x, wq.y, wq.z, wq.w};
+                    uint32_t wb[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) wb[k] = ((fired >> k) & 1u) ? a.w[e0 + k] : 0u;   // arrivals only
 #pragma unroll
                     for (int k = 0; k < 8; ++k) {
                         if ((fired >> k) & 1u) {
                             const int32_t row = row0 + __popc(bits & ((2u << k) - 1u));
-                            atomicAdd(L.I + row, half_bits_to_float((wv[k >> 1] >> (16 * (k & 1))) & 0xFFFFu));
+                            atomicAdd(L.I + row, half_bits_to_float(wb[k]));
                         }
                     }
                 }
@@ -639,7 +628,7 @@ hipError_t configure_deliver(const DeviceGraph& g, const net_build_opts* opts, L
     const bool want_lds = !(flags & NET_BUILD_NO_LDS_SUMMARY);
     lc.lds_summary = want_lds && summary_bytes <= static_cast<size_t>(lds_max);
     lc.lds_bytes = lc.lds_summary ? summary_bytes : 0;
-    lc.prefetch = (flags & NET_BUILD_DELIVER_PREFETCH) != 0;
+    lc.stream_weights = (flags & NET_BUILD_DELIVER_STREAM_WEIGHTS) != 0;
     lc.nontemporal = (flags & NET_BUILD_DELIVER_NONTEMPORAL) != 0;
     lc.unroll = (flags & NET_BUILD_DELIVER_UNROLL2) ? 2 : 1;
     if (lc.lds_summary) {
@@ -692,11 +681,12 @@ hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t 
     a.n_pad = static_cast<uint32_t>(g.n_pad);
     a.window = static_cast<uint32_t>(g.d_sum);
     const dim3 grid(lc.deliver_blocks), block(lc.deliver_threads);
-    const int v = (lc.unroll == 2 ? 8 : 0) | (lc.lds_summary ? 4 : 0) | (lc.prefetch ? 2 : 0) | (lc.nontemporal ? 1 : 0);
+    const int v = (lc.unroll == 2 ? 8 : 0) | (lc.lds_summary ? 4 : 0) | (lc.stream_weights ? 2 : 0) |
+                  (lc.nontemporal ? 1 : 0);
     switch (v) {
-#define GEONET_DELIVER_CASE(U, L, P, N)                                                            \
-    case (U == 2 ? 8 : 0) | (L ? 4 : 0) | (P ? 2 : 0) | (N ? 1 : 0):                               \
-        hipExtLaunchKernelGGL((deliver_kernel<L, P, N, U>), grid, block, L ? lc.lds_bytes : 0, s, ev0, ev1, 0, \
+#define GEONET_DELIVER_CASE(U, L, W, N)                                                            \
+    case (U == 2 ? 8 : 0) | (L ? 4 : 0) | (W ? 2 : 0) | (N ? 1 : 0):                               \
+        hipExtLaunchKernelGGL((deliver_kernel<L, W, N, U>), grid, block, L ? lc.lds_bytes : 0, s, ev0, ev1, 0, \
                               a);                                                                  \
         break;
 #define GEONET_DELIVER_CASES(U)              \

@@ -98,9 +98,9 @@ struct FitBaseArgs {
     const int32_t* pairs;     // [P][2]
     const int64_t* row;       // [n+1] pairs of target j are [row[j], row[j+1]) (pairs sorted by target)
     const uint8_t* member;    // [P] 1 if the pair is in G
-    float* base;              // [n][nf]
+    double* base;             // [n][nf]
     int32_t n, nf;
-    float w;
+    double w;
     int64_t frame_num, frame_den;
 };
 
@@ -108,25 +108,26 @@ __global__ void __launch_bounds__(256) fitbase_kernel(FitBaseArgs a) {
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= static_cast<int64_t>(a.n) * a.nf) return;
     const int j = static_cast<int>(idx / a.nf), f = static_cast<int>(idx % a.nf);
-    float s = 0.0f;
+    double s = 0.0;
     for (int64_t p = a.row[j]; p < a.row[j + 1]; ++p)
         if (a.member[p]) s += a.e[static_cast<int64_t>(a.pairs[2 * p]) * a.nf + f];
-    const float steps = static_cast<float>(first_step(f + 1, a.frame_num, a.frame_den) -
-                                           first_step(f, a.frame_num, a.frame_den));
+    const double steps = static_cast<double>(first_step(f + 1, a.frame_num, a.frame_den) -
+                                             first_step(f, a.frame_num, a.frame_den));
     a.base[idx] = a.w * s / steps;
 }
 
 struct FitEvalArgs {
     const float* F;           // [nf][n] observed
     const float* e;           // [n][nf]
-    const float* base;        // [n][nf]
+    const double* base;       // [n][nf]
     const uint32_t* pulses;   // [n][words]
     const int32_t* pairs;     // [P][2]
     const uint8_t* member;    // [P]
     double* ll;               // [P + n]: variant v < P toggles pair v; v = P + j is G_j itself
     int64_t P;
     int32_t n, nf, words, K;
-    float w, decay, v_rest, v_reset, v_th, sigma, drive_amp;
+    float sigma;
+    double w, decay, v_rest, v_reset, v_th, drive_amp;
     int32_t n_ref;
     double dt, tau_c, gain, offset, gamma2;
     int64_t frame_num, frame_den;
@@ -143,29 +144,31 @@ __global__ void __launch_bounds__(256) fiteval_kernel(FitEvalArgs a) {
     const bool valid = v < nvar;
     int j = 0;
     int src = -1;
-    float sign = 0.0f;
+    double sign = 0.0;
     if (valid) {
         if (v < a.P) {
             j = a.pairs[2 * v + 1];
             src = a.pairs[2 * v];
-            sign = a.member[v] ? -1.0f : 1.0f;
+            sign = a.member[v] ? -1.0 : 1.0;
         } else {
             j = static_cast<int>(v - a.P);
         }
     }
-    const float* bj = a.base + static_cast<int64_t>(j) * a.nf;
+    const double* bj = a.base + static_cast<int64_t>(j) * a.nf;
     const float* es = src >= 0 ? a.e + static_cast<int64_t>(src) * a.nf : nullptr;
     const uint32_t* pj = a.pulses + static_cast<int64_t>(j) * a.words;
-    float V = a.v_rest;
+    // V in FP64: the likelihood depends on V only through spike times, and
+    // FP64 keeps threshold decisions aligned with the FP64 reference
+    double V = a.v_rest;
     uint32_t age = 255u;
     double c = 0.0, acc = 0.0, ll = 0.0;
     const int group = lane - (lane % K);      // first lane of this variant's realisations
     int64_t t = 0;
     for (int f = 0; f < a.nf; ++f) {
         const int64_t t1 = first_step(f + 1, a.frame_num, a.frame_den);
-        const float steps = static_cast<float>(t1 - t);
-        float u = bj[f];
-        if (es) u += sign * a.w * es[f] / steps;
+        const double steps = static_cast<double>(t1 - t);
+        double u = bj[f];
+        if (es) u += sign * a.w * static_cast<double>(es[f]) / steps;
         uint32_t pw = pj[t >> 5];
         for (; t < t1; ++t) {
             if ((t & 31) == 0) pw = pj[t >> 5];
@@ -183,18 +186,18 @@ __global__ void __launch_bounds__(256) fiteval_kernel(FitEvalArgs a) {
                 V = a.v_reset;
                 continue;
             }
-            float in = u + (((pw >> (t & 31)) & 1u) ? a.drive_amp : 0.0f);
+            double in = u + (((pw >> (t & 31)) & 1u) ? a.drive_amp : 0.0);
             if (a.sigma != 0.0f) {
                 const uint4 q = philox_fit(make_uint4(static_cast<uint32_t>(j), static_cast<uint32_t>(t),
                                                       static_cast<uint32_t>(static_cast<uint64_t>(t) >> 32),
                                                       2u + static_cast<uint32_t>(k)),
                                            a.key_lo, a.key_hi);
-                in += a.sigma * gauss_fit(q.y, q.z);
+                in += static_cast<double>(a.sigma) * static_cast<double>(gauss_fit(q.y, q.z));
             }
             V = V + a.decay * (a.v_rest - V) + in;
         }
         // frame mean of this realisation, then mean/variance over the K lanes
-        const double cbar = acc / static_cast<double>(steps);
+        const double cbar = acc / steps;
         acc = 0.0;
         double s1 = 0.0, s2 = 0.0;
         for (int q = 0; q < K; ++q) {

@@ -138,13 +138,13 @@ def features(o: Observed, stream=None):
 
 
 def simfit(o: Observed, w_assumed: float, realisations: int = 8, sweeps: int = 2, init_fraction: float = 0.3,
-           fit_seed: int = 0x5EEDF17, stream=None):
+           fit_seed: int = 0x5EEDF17, min_gain: float = 1e-3, stream=None):
     """Simulation-based fit scores LL(G + e) - LL(G - e) per candidate pair."""
     import torch
     out = torch.empty(int(o.pairs.shape[0]), dtype=torch.float32, device=o.F.device)
     keep = []
     d = obs_desc(o, keep, w_assumed=w_assumed)
-    opts = _abi.SimfitOpts(realisations, sweeps, init_fraction, 0, fit_seed)
+    opts = _abi.SimfitOpts(realisations, sweeps, init_fraction, min_gain, fit_seed)
     _echeck(library().net_estimate(C.byref(d), _abi.NET_EST_SIMFIT, None, C.byref(opts), out.data_ptr(),
                                    _stream_handle(stream)), "net_estimate")
     return out

@@ -252,3 +252,56 @@ def test_ensemble_observation_matches_per_step():
         outs.append(net.observe(gn.NET_OBS_FRAMES, frames=nf).cpu().numpy())
     assert outs[0].shape[0] == 6
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_single_network_single_launch_matches_oracle():
+    """One network through the single-launch LDS-resident kernel."""
+    gn, torch = _gn()
+    spec = synth.config0_like(256, synth.config_seed(0), w0=0.36)
+    spec.noise_sigma = 0.05
+    T = 4000
+    g = run_gpu(spec, T, flags=gn.NET_BUILD_SINGLE_LAUNCH)
+    inf = g["net"].info()
+    assert inf["ensemble_blocks"] == 1 and inf["ensemble_threads"] > 0
+    o = oracle.OracleNet(spec).step(T, v=True, inp=True)
+    check_parity(g, o)
+    p = run_gpu(spec, T)                      # per-step kernels
+    assert p["net"].info()["ensemble_blocks"] == 0
+    for key in ("raster", "v", "input"):
+        assert np.array_equal(g[key], p[key]), key
+
+
+def test_autotuned_ensemble_equals_default():
+    gn, torch = _gn()
+    specs = _ensemble_specs([64, 90, 1500, 300, 2048, 700, 128, 77, 1024, 400])
+    T = 1200
+    a = run_gpu(specs, T)
+    b = run_gpu(specs, T, flags=gn.NET_BUILD_AUTOTUNE)
+    inf = b["net"].info()
+    assert inf["autotuned"] == 1 and inf["ensemble_blocks"] > 0 and inf["t"] == T
+    for key in ("raster", "v", "input"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_autotuned_per_step_equals_default():
+    gn, torch = _gn()
+    spec = synth.config1(n=8192)
+    T = 600
+    a = run_gpu(spec, T)
+    b = run_gpu(spec, T, flags=gn.NET_BUILD_AUTOTUNE)
+    inf = b["net"].info()
+    assert inf["autotuned"] == 1 and inf["ensemble_blocks"] == 0 and inf["t"] == T
+    for key in ("raster", "v", "input"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+@pytest.mark.parametrize("flags", ["DELIVER_STREAM_WEIGHTS", "DELIVER_UNROLL2", "DELIVER_NONTEMPORAL"])
+def test_delivery_variants_identical(flags):
+    gn, torch = _gn()
+    spec = synth.config1(n=8192)
+    T = 600
+    a = run_gpu(spec, T)
+    b = run_gpu(spec, T, flags=getattr(gn, "NET_BUILD_" + flags))
+    assert b["net"].info()["deliver_flags"] == getattr(gn, "NET_BUILD_" + flags)
+    for key in ("raster", "v", "input"):
+        assert np.array_equal(a[key], b[key]), key

@@ -1,9 +1,10 @@
 """GPU simulation-based fit against the FP64 fit reference on the same
 observation (simulated and observed by the CPU oracle), plus its argument
-checks.  The library's vertex state is FP32 (calcium and likelihood FP64), so
-a realisation can cross threshold one step apart from the reference; the bar
-is that almost every score agrees to 1e-3 and the few that do not leave the
-ranking quality unchanged."""
+checks.  The fit's vertex model is FP64 on both sides but the library draws
+its state noise with FP32 Box-Muller, so a realisation can, rarely, cross
+threshold one step apart from the reference; the bar is that almost every
+score agrees to 1e-3, the median to 1e-5, and the ranking quality is
+unchanged."""
 import numpy as np
 import pytest
 
@@ -64,6 +65,7 @@ def test_simfit_matches_reference(sweeps):
     assert np.isfinite(g).all()
     close = np.abs(g - ref) <= 1e-3 + 1e-3 * np.abs(ref)
     assert close.mean() >= 0.95, (close.mean(), np.abs(g - ref).max())
+    assert np.median(np.abs(g - ref)) <= 1e-5
     assert abs(metrics.auc(g, labels) - metrics.auc(ref, labels)) <= 0.02
     assert np.abs(ref).max() > 1e-3                     # the toggles do change the likelihood
 
