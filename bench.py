@@ -27,17 +27,21 @@ BYTES_PER_ARRIVAL = 2   # FP16 weight, loaded only when its edge delivers a spik
 BYTES_PER_EDGE_STREAMED_W = 7   # with --stream-weights: the weight is streamed with its edge
 
 
-def measured_traffic():
+def measured_traffic(deliver_flags):
     """HBM bytes per delivery launch from the committed rocprofv3 counter
-    summary, if it was taken on the kernel source as it is now (else None)."""
+    summary, if it was taken on the kernel source as it is now and on the
+    same delivery variant (else None)."""
     import hashlib
     prof = os.path.join(ROOT, "profiles", "deliver_config2.md")
     src = os.path.join(ROOT, "paper_0908_3934_amd", "csrc", "kernels.hip")
     try:
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
         fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines()
-                      if line.startswith(("traffic_bytes_per_launch:", "kernels_hip_sha256_16:")))
+                      if line.startswith(("traffic_bytes_per_launch:", "kernels_hip_sha256_16:",
+                                          "deliver_flags:")))
         if fields.get("kernels_hip_sha256_16", "").strip() != sha:
+            return None
+        if int(fields.get("deliver_flags", "-1")) != deliver_flags:
             return None
         return int(fields["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -154,6 +158,85 @@ def bench_ensemble(args, torch, synth, gn):
     }
 
 
+def bench_estimate(args, torch, synth):
+    """Functional-topology estimation on N = 1024 networks observed for
+    obs-steps at 30 Hz with SNR 5: the learned scorer (64 pair features ->
+    MLP, trained on the GPU on train-nets simulated networks) against the
+    simulation-based fit, both scoring every candidate pair (< 150 um) of the
+    same held-out networks.  value = the scorer's AUC; the fit's AUC and both
+    wall times (features + MLP vs fit, per network, after observation) are
+    reported beside it."""
+    import numpy as np
+    from paper_0908_3934_amd import estimate as est
+    t0 = time.perf_counter()
+    train, feats = [], []
+    for b in range(0, args.train_nets, 128):
+        obs = est.observe([synth.config4_net(m) for m in range(b, min(args.train_nets, b + 128))], args.obs_steps)
+        for o in obs:
+            feats.append(est.features(o))
+            o.F = None                                  # keep features, free the traces
+        train += obs
+        log("training data: %d networks simulated and featurised (%.1f s)" % (len(train), time.perf_counter() - t0))
+    n_pairs = sum(len(o.labels) for o in train)
+    t1 = time.perf_counter()
+    sc = est.EdgeScorer(seed=0).fit(train, epochs=args.epochs, batch=16384, lr=1e-3, feats=feats)
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t1
+    log("scorer trained on %d pairs in %.2f s (loss history %s)" % (n_pairs, fit_s, ["%.3f" % h for h in sc.history]))
+    del feats
+    test = est.observe([synth.config4_net(90000 + m) for m in range(args.test_nets)], args.obs_steps)
+    S, F, C, Y = [], [], [], []
+    t_sc = t_sf = 0.0
+    for k, o in enumerate(test):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        s_sc = est.scorer_scores(o, sc)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        s_sf = est.simfit(o, w_assumed=synth.W0, realisations=8, sweeps=2)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        t_sc += b - a
+        t_sf += c - b
+        f = est.features(o).cpu().numpy()
+        S.append(s_sc.cpu().numpy())
+        F.append(s_sf.cpu().numpy())
+        C.append(f[:, 8] + f[:, 9])                    # lag-0 + lag-1 activity correlation
+        Y.append(o.labels)
+        log("held-out net %d: %d pairs, scorer %.4f s AUC %.4f | fit %.2f s AUC %.4f"
+            % (k, len(o.labels), b - a, est.auc(S[-1], o.labels), c - b, est.auc(F[-1], o.labels)))
+    S, F, C, Y = map(np.concatenate, (S, F, C, Y))
+    auc_sc, auc_sf, auc_c = est.auc(S, Y), est.auc(F, Y), est.auc(C, Y)
+    nf = args.obs_steps * 3 // 1000
+    return {
+        "metric": "AUC",
+        "value": auc_sc,
+        "unit": "area under the ROC curve over all candidate pairs of the held-out networks",
+        "n_gpus": 1,
+        "steps": args.obs_steps,
+        "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 (MLP), f32/f64 (simulation and fit)",
+        "data": "synthetic",
+        "config": {
+            "workload": "%d training and %d held-out LIF networks of 1024 vertices (1 mm square, p = 0.3 "
+                        "within 150 um, 10 %% driven, noise 0.05), %d frames at 30 Hz, SNR 5, candidates "
+                        "< 150 um" % (args.train_nets, args.test_nets, nf),
+            "train_pairs": n_pairs,
+            "test_pairs": int(Y.size),
+            "positive_fraction": float(Y.mean()),
+        },
+        "scorer": {"auc": auc_sc, "wall_s": t_sc, "train_s": fit_s, "epochs": args.epochs},
+        "simfit": {"auc": auc_sf, "wall_s": t_sf, "realisations": 8, "sweeps": 2},
+        "correlation_baseline_auc": auc_c,
+        "auc_gap": auc_sf - auc_sc,
+        "wall_ratio_simfit_over_scorer": t_sf / max(t_sc, 1e-12),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,12 +245,19 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--stream-weights", action="store_true",
-                    help="delivery variant that streams every weight (7 B per edge) instead of loading "
-                         "weights only for arrivals")
-    ap.add_argument("--workload", choices=["step", "ensemble"], default="step",
+    ap.add_argument("--deliver-flags", type=int, default=16,
+                    help="NET_BUILD_DELIVER_* bits of the delivery variant (default 16: two chunks per wave "
+                         "iteration, the fastest measured; 2 streams every weight, 7 B per edge)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library time the delivery variants at build instead of --deliver-flags")
+    ap.add_argument("--workload", choices=["step", "ensemble", "estimate"], default="step",
                     help="step: the N = 2^20 network (default); ensemble: 512 uneven networks in one launch "
-                         "against each network run alone")
+                         "against each network run alone; estimate: learned edge scorer against the "
+                         "simulation-based fit on held-out N = 1024 networks")
+    ap.add_argument("--train-nets", type=int, default=256, help="estimate workload: training networks")
+    ap.add_argument("--test-nets", type=int, default=16, help="estimate workload: held-out networks")
+    ap.add_argument("--obs-steps", type=int, default=200000, help="estimate workload: observed steps (20 s)")
+    ap.add_argument("--epochs", type=int, default=4, help="estimate workload: scorer training epochs")
     ap.add_argument("--seq-sample", type=int, default=8,
                     help="ensemble workload: time every k-th network alone and scale to all")
     ap.add_argument("--rate-steps", type=int, default=500,
@@ -188,6 +278,9 @@ def main():
     if args.workload == "ensemble":
         print(json.dumps(bench_ensemble(args, torch, synth, gn)), flush=True)
         return
+    if args.workload == "estimate":
+        print(json.dumps(bench_estimate(args, torch, synth)), flush=True)
+        return
     if args.copy_calibration:
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
@@ -199,7 +292,7 @@ def main():
     spec = synth.config2(n=args.n)
     log("generated N=%d E=%d in %.1f s" % (spec.n, spec.n_edges, time.perf_counter() - t0))
     t0 = time.perf_counter()
-    net = gn.Net(spec, flags=gn.NET_BUILD_DELIVER_STREAM_WEIGHTS if args.stream_weights else 0)
+    net = gn.Net(spec, flags=gn.NET_BUILD_AUTOTUNE if args.autotune else args.deliver_flags)
     info = net.info()
     log("built in %.1f s: %s" % (time.perf_counter() - t0, info))
 
@@ -219,7 +312,8 @@ def main():
     value = E * args.steps / wall
     avg_deliver_s = tm["deliver_ms"] / tm["deliver_launches"] / 1e3
     arrivals = arrivals_per_step(net, spec, args.rate_steps)
-    if args.stream_weights:
+    streamed_w = bool(info["deliver_flags"] & gn.NET_BUILD_DELIVER_STREAM_WEIGHTS)
+    if streamed_w:
         alg_bytes = BYTES_PER_EDGE_STREAMED_W * E
     else:
         alg_bytes = BYTES_PER_EDGE * E + BYTES_PER_ARRIVAL * arrivals
@@ -249,9 +343,11 @@ def main():
             "n_vertices": spec.n,
             "n_edges": E,
             "max_delay_steps": info["max_delay"],
+            "deliver_flags": info["deliver_flags"],
             "real_time_factor": sim_s / wall,
-            "deliver_launch": "%d blocks x %d threads, summary in %s" % (
-                info["deliver_blocks"], info["deliver_threads"], "LDS" if info["lds_summary"] else "global"),
+            "deliver_launch": "%d blocks x %d threads, summary in %s, variant flags %d%s" % (
+                info["deliver_blocks"], info["deliver_threads"], "LDS" if info["lds_summary"] else "global",
+                info["deliver_flags"], " (autotuned at build)" if info["autotuned"] else ""),
         },
         "roofline": {
             "bound": "hbm",
@@ -260,7 +356,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None if args.stream_weights else measured_traffic(),
+            "traffic": measured_traffic(info["deliver_flags"]),
             "algorithmic_bytes_per_launch": alg_bytes,
             "arrivals_per_step": arrivals,
             "avg_launch_us": avg_deliver_s * 1e6,

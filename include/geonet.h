@@ -119,6 +119,8 @@ typedef struct {
                                              single-launch ensemble kernel */
 #define NET_BUILD_DELIVER_UNROLL2 16      /* delivery: two 512-edge chunks per wave iteration
                                              (default one) */
+#define NET_BUILD_DELIVER_PIPELINE 128   /* delivery: issue the next chunk's edge loads while
+                                             this chunk's history gathers are in flight */
 #define NET_BUILD_SINGLE_LAUNCH 32        /* one network: run all steps of a call in one launch of
                                              the LDS-resident kernel ensembles use, when the
                                              network fits one workgroup's LDS */
@@ -307,7 +309,8 @@ net_status net_features(const net_obs_desc* obs, float* features_dev, void* stre
 typedef struct {
     int32_t realisations;   /* K noise realisations per hypothesis, divides 64 (default 8) */
     int32_t sweeps;         /* toggle sweeps (default 0 with a zeroed struct: pass 2 for the usual fit) */
-    float init_fraction;    /* initial in-neighbours per target: top fraction by correlation (0.3) */
+    float init_fraction;    /* initial in-neighbours per target: the top ceil(f n - 1e-6) of its n
+                               candidates by correlation (f = 0.3) */
     float min_gain;         /* smallest log-likelihood gain (nats) for which a toggle is applied
                                (<= 0: 1e-3) */
     uint64_t fit_seed;      /* Philox key of the fit's own noise (never the data's) */

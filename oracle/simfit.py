@@ -43,7 +43,7 @@ def initial_members(en, pairs, frac):
     for j in np.unique(targets):
         idx = np.nonzero(targets == j)[0]
         order = idx[np.argsort(-score[idx], kind="stable")]
-        member[order[:math.ceil(frac * idx.size)]] = True
+        member[order[:math.ceil(frac * idx.size - 1e-6)]] = True     # ceil(f n), f n integral counts exactly
     return member
 
 

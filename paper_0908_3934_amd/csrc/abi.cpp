@@ -196,7 +196,7 @@ net_status reset_state(net* h, const HostGraph& hg, hipStream_t s) {
     const size_t np = static_cast<size_t>(g.n_pad);
     hipError_t e = hipMemcpyAsync(g.V, hg.v0.data(), std::min(hg.v0.size(), np) * sizeof(float),
                                   hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemsetAsync(g.age, kAgeNever, np, s);
+    if (e == hipSuccess) e = hipMemsetAsync(g.age, kAgeNever, np * sizeof(uint16_t), s);
     if (e == hipSuccess) e = hipMemsetAsync(g.I, 0, np * sizeof(float), s);
     if (e == hipSuccess) e = hipMemsetAsync(g.ring, 0, np * kRingWords * sizeof(uint32_t), s);
     if (e == hipSuccess) e = hipMemsetAsync(g.summary, 0, np / 32 * sizeof(uint32_t), s);
@@ -389,7 +389,7 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
                 }
                 pl.enabled = true;
                 double ms = 0.0;
-                const bool ok = trial_ms(h, 0, 8, s, &ms) && trial_ms(h, 8, 64, s, &ms);
+                const bool ok = trial_ms(h, 0, 200, s, &ms) && trial_ms(h, 200, 200, s, &ms);
                 pl.enabled = false;
                 if ((st = reset_state(h, hg, s)) != NET_OK) return bail(st);
                 if (!ok) {
@@ -414,21 +414,25 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
     if (autotune && !h->plan.enabled) {
         // delivery variants of the per-step kernels (identical results)
         const int variants[] = {0,
+                                NET_BUILD_DELIVER_PIPELINE,
                                 NET_BUILD_DELIVER_UNROLL2,
                                 NET_BUILD_DELIVER_NONTEMPORAL,
-                                NET_BUILD_DELIVER_UNROLL2 | NET_BUILD_DELIVER_NONTEMPORAL,
+                                NET_BUILD_DELIVER_PIPELINE | NET_BUILD_DELIVER_NONTEMPORAL,
                                 NET_BUILD_DELIVER_STREAM_WEIGHTS,
-                                NET_BUILD_DELIVER_STREAM_WEIGHTS | NET_BUILD_DELIVER_UNROLL2};
+                                NET_BUILD_DELIVER_STREAM_WEIGHTS | NET_BUILD_DELIVER_PIPELINE};
         net_build_opts o = opts ? *opts : net_build_opts{};
         const int keep = o.flags & ~(NET_BUILD_DELIVER_UNROLL2 | NET_BUILD_DELIVER_NONTEMPORAL |
-                                     NET_BUILD_DELIVER_STREAM_WEIGHTS);
+                                     NET_BUILD_DELIVER_STREAM_WEIGHTS | NET_BUILD_DELIVER_PIPELINE);
         int best = -1;
         double best_ms = 0.0;
         for (int k = 0; k < static_cast<int>(sizeof(variants) / sizeof(variants[0])); ++k) {
             o.flags = keep | variants[k];
             if (configure_deliver(g, &o, h->lc) != hipSuccess) continue;
+            // warm up into spiking activity (the initial state is silent, so
+            // the history gathers, which the variants handle differently,
+            // would be missing from the trial), then time
             double ms = 0.0;
-            const bool ok = trial_ms(h, 0, 4, s, &ms) && trial_ms(h, 4, 16, s, &ms);
+            const bool ok = trial_ms(h, 0, 200, s, &ms) && trial_ms(h, 200, 64, s, &ms);
             if ((st = reset_state(h, hg, s)) != NET_OK) return bail(st);
             if (!ok) {
                 (void)hipGetLastError();
@@ -579,7 +583,8 @@ net_status net_info(const net_t* h, net_info_t* out) {
     out->deliver_blocks = h->lc.deliver_blocks;
     out->deliver_threads = h->lc.deliver_threads;
     out->device_bytes = h->device_bytes;
-    out->deliver_flags = (h->lc.unroll == 2 ? NET_BUILD_DELIVER_UNROLL2 : 0) |
+    out->deliver_flags = (h->lc.mode == 1 ? NET_BUILD_DELIVER_UNROLL2 : 0) |
+                         (h->lc.mode == 2 ? NET_BUILD_DELIVER_PIPELINE : 0) |
                          (h->lc.nontemporal ? NET_BUILD_DELIVER_NONTEMPORAL : 0) |
                          (h->lc.stream_weights ? NET_BUILD_DELIVER_STREAM_WEIGHTS : 0);
     out->ensemble_blocks = h->plan.enabled ? h->plan.blocks : 0;

@@ -158,7 +158,9 @@ net_status simfit(const net_obs_desc* o, const net_simfit_opts* opts, float* out
         std::stable_sort(c.begin(), c.end(), [&](int64_t a, int64_t b) {
             return hf[64 * a + 8] + hf[64 * a + 9] > hf[64 * b + 8] + hf[64 * b + 9];
         });
-        const size_t take = static_cast<size_t>(std::ceil(init_frac * static_cast<double>(c.size())));
+        // ceil(f n); the margin keeps f = 0.3 given as a float (0.30000001)
+        // from taking an extra candidate when f n is an integer
+        const size_t take = static_cast<size_t>(std::ceil(init_frac * static_cast<double>(c.size()) - 1e-6));
         for (size_t k = 0; k < take && k < c.size(); ++k) member[c[k]] = 1;
     }
     FitInputs in{};

@@ -84,7 +84,8 @@ struct DeviceGraph {
     const uint32_t* drive_thr;    // null when no vertex is driven
     const float* i_ext;           // null when all zero
     float* V;
-    uint8_t* age;
+    uint16_t* age;     // low byte: steps since the last spike, high byte: steps since the one
+                       // before it (both saturate at 255; delivery at step t reads t - t_spike)
     float* I;
     uint32_t* ring;               // [kRingWords][n_pad]: bit (s mod 32) of word (s mod 256)/32 = spike at step s
     uint32_t* summary;            // [n_pad / 32]
@@ -101,7 +102,7 @@ struct LaunchConfig {
     bool lds_summary = false;
     bool stream_weights = false;
     bool nontemporal = false;
-    int unroll = 1;
+    int mode = 0;                  // delivery loop: 0 one chunk, 1 two chunks, 2 pipelined
     size_t lds_bytes = 0;
 };
 

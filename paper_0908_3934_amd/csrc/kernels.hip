@@ -51,14 +51,18 @@ __device__ __forceinline__ float half_bits_to_float(uint32_t bits) {
 
 __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
 
-__device__ __forceinline__ uint32_t wave_exclusive_sum(uint32_t v, int lane) {
-    uint32_t x = v;
+// Number of set bits of `bits` (8 per lane) in all lanes below this one:
+// one ballot per bit position, counted below the lane with mbcnt, so no
+// cross-lane data movement through LDS.
+__device__ __forceinline__ uint32_t wave_bits_before(uint32_t bits) {
+    uint32_t n = 0;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
+    for (int b = 0; b < 8; ++b) {
+        const uint64_t m = __ballot((bits >> b) & 1u);
+        n += __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                       __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
     }
-    return x - v;
+    return n;
 }
 
 struct DeliverArgs {
@@ -69,6 +73,7 @@ struct DeliverArgs {
     const int32_t* __restrict__ chunk_row0;
     const uint32_t* __restrict__ summary;
     const uint32_t* __restrict__ ring;
+    const uint16_t* __restrict__ ages;   // per vertex: steps since its last spike | since the one before << 8
     float* __restrict__ I;
     int64_t n_chunks;
     int32_t summary_vec4;   // summary size in 16-byte units
@@ -84,10 +89,16 @@ struct DeliverArgs {
 // for neighbouring targets meet in that XCD's L2.
 //
 // A weight is needed only when its edge delivers a spike (a few in 10^4
-// edges at physiological rates), so by default weights are not streamed:
-// each arrival loads its own 2 B weight, and the stream is 5 B per edge
-// instead of 7.  kWStream = true streams the weights with the chunk (16 B per
-// lane) instead.
+// edges at physiological rates), so by default weights are not streamed: a
+// wave that has an arrival loads the 16 B of weights of each lane then, and
+// the stream is 5 B per edge instead of 7.  kWStream = true streams the
+// weights with the chunk instead.
+//
+// Each iteration is a chain of dependent memory phases (edge stream, LDS
+// summary, history gathers), and the 128 KiB summary leaves room for one
+// workgroup per CU, so the loop is latency-bound.  kMode 2 pipelines it: the
+// next chunk's stream loads are issued right after this chunk's gathers.
+// kMode 1 handles two chunks per iteration instead; kMode 0 one.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
@@ -95,7 +106,6 @@ struct ChunkRegs {
     u32x4 s_lo, s_hi;
     u32x4 wq;
     u32x2 dq;
-    uint32_t rs;
 };
 
 // Stream loads of one chunk (optionally non-temporal).
@@ -113,42 +123,94 @@ __device__ __forceinline__ void load_chunk(ChunkRegs& x, const DeliverArgs& a, i
         if (kWStream) x.wq = *reinterpret_cast<const u32x4*>(a.w + e0);
         x.dq = *reinterpret_cast<const u32x2*>(a.d + e0);
     }
-    x.rs = a.rowstart[c * 64 + lane];
 }
 
+// Summary test of one chunk and, for each candidate edge, a gather of its
+// source's two most recent spike ages (a 2 B word per vertex, 2 MiB at
+// N = 2^20, which stays in L2).  Bit k of *cand is set if edge k must be
+// resolved.
+template <bool kLdsSummary>
+__device__ __forceinline__ void gather_chunk(const ChunkRegs& x, const DeliverArgs& a, const uint32_t* lds_summary,
+                                             uint32_t* aw, uint32_t* cand) {
+    const uint32_t sv[8] = {x.s_lo.x, x.s_lo.y, x.s_lo.z, x.s_lo.w, x.s_hi.x, x.s_hi.y, x.s_hi.z, x.s_hi.w};
+    uint32_t cm = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t s = sv[k];
+        const uint32_t sw = kLdsSummary ? lds_summary[s >> 5] : a.summary[s >> 5];
+        const uint32_t dk = ((k < 4 ? x.dq.x : x.dq.y) >> (8 * (k & 3))) & 0xFFu;
+        // edges longer than the summary window are always resolved
+        const uint32_t hit = ((sw >> (s & 31)) & 1u) | (dk > a.window ? 1u : 0u);
+        aw[k] = a.ages[hit ? s : 0u];
+        cm |= hit << k;
+    }
+    *cand = cm;
+}
+
+// Exact arrival test.  With a1 < a2 the ages of the source's last two spikes,
+// the source fired at t - d iff d == a1 or d == a2, or d > a2 and an older
+// spike sits at t - d; only that last case (three spikes within d steps, or
+// d = 255 where a saturated age is ambiguous) reads the history ring.
+__device__ __forceinline__ uint32_t fired_bits(const ChunkRegs& x, const DeliverArgs& a, uint32_t t,
+                                               const uint32_t* aw, uint32_t cand) {
+    uint32_t fired = 0, need = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t dk = ((k < 4 ? x.dq.x : x.dq.y) >> (8 * (k & 3))) & 0xFFu;
+        const uint32_t a1 = aw[k] & 0xFFu, a2 = aw[k] >> 8;
+        const bool c = (cand >> k) & 1u;
+        const bool hit = dk < 255u && (dk == a1 || dk == a2);
+        const bool ring = dk == 255u || (dk > a2 && dk != a1);
+        fired |= (c && hit ? 1u : 0u) << k;
+        need |= (c && !hit && ring ? 1u : 0u) << k;
+    }
+    if (wave_ballot(need != 0)) {
+        const uint32_t sv[8] = {x.s_lo.x, x.s_lo.y, x.s_lo.z, x.s_lo.w, x.s_hi.x, x.s_hi.y, x.s_hi.z, x.s_hi.w};
+        uint32_t slot[8], word[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t dk = ((k < 4 ? x.dq.x : x.dq.y) >> (8 * (k & 3))) & 0xFFu;
+            slot[k] = (t - dk) & 0xFFu;
+            word[k] = a.ring[((need >> k) & 1u) ? (slot[k] >> 5) * a.n_pad + sv[k] : 0u];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) fired |= (((need >> k) & (word[k] >> (slot[k] & 31))) & 1u) << k;
+    }
+    return fired;
+}
+
+// Arrivals of one chunk (called by the whole wave when any lane has one).
 // Row of each fired slot from the row-start bits (position 0 of the chunk
 // belongs to chunk_row0 whether or not it opens a row), then one exact FP32
 // atomic add per arrival.  All partial sums of a row are exact in FP32, so
-// the order of these additions does not change the result.
+// the order of these additions does not change the result.  The row-start
+// byte, the chunk's first row and (unless streamed) the weights are loaded
+// together, and the prefix count of row starts needs no LDS round trip.
 template <bool kWStream>
-__device__ __forceinline__ void deliver_fired(const DeliverArgs& a, int64_t c, int lane, uint32_t fired, uint32_t rs,
-                                              const u32x4& wq) {
-    const uint32_t bits = lane == 0 ? (rs & ~1u) : rs;
-    const uint32_t before = wave_exclusive_sum(__popc(bits), lane);
-    const int32_t row0 = a.chunk_row0[c] + static_cast<int32_t>(before);
+__device__ __forceinline__ void deliver_fired(const DeliverArgs& a, int64_t c, int lane, uint32_t fired,
+                                              const u32x4& wq_stream) {
     const int64_t e0 = c * kChunkEdges + lane * kEdgesPerLane;
-    const uint32_t wv[4] = {wq.x, wq.y, wq.z, wq.w};
-    uint32_t wb[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {   // all weight loads first, then the adds
-        if (kWStream)
-            wb[k] = (wv[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
-        else
-            wb[k] = ((fired >> k) & 1u) ? a.w[e0 + k] : 0u;
+    const uint32_t rs = a.rowstart[c * 64 + lane];
+    const int32_t first_row = a.chunk_row0[c];
+    u32x4 wq = wq_stream;
+    if (!kWStream) {
+        // only lanes with an arrival load their 16 B of weights
+        wq = u32x4{0u, 0u, 0u, 0u};
+        if (fired) wq = *reinterpret_cast<const u32x4*>(a.w + e0);
     }
+    const uint32_t bits = lane == 0 ? (rs & ~1u) : rs;
+    const int32_t row0 = first_row + static_cast<int32_t>(wave_bits_before(bits));
+    const uint32_t wv[4] = {wq.x, wq.y, wq.z, wq.w};
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         if ((fired >> k) & 1u) {
             const int32_t row = row0 + __popc(bits & ((2u << k) - 1u));
-            unsafeAtomicAdd(a.I + row, half_bits_to_float(wb[k]));
+            unsafeAtomicAdd(a.I + row, half_bits_to_float((wv[k >> 1] >> (16 * (k & 1))) & 0xFFFFu));
         }
     }
 }
 
-// kUnroll chunks per wave iteration: all their stream loads are issued
-// before the first wait, and all their history gathers before the second,
-// so a wave keeps kUnroll chunks of loads in flight.
-template <bool kLdsSummary, bool kWStream, bool kNT, int kUnroll>
+template <bool kLdsSummary, bool kWStream, bool kNT, int kMode>
 __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
     extern __shared__ uint4 lds_summary4[];
     const uint32_t* lds_summary = reinterpret_cast<const uint32_t*>(lds_summary4);
@@ -161,7 +223,8 @@ __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
     const int64_t c_begin = static_cast<int64_t>(lb) * a.n_chunks / nb;
     const int64_t c_end = static_cast<int64_t>(lb + 1) * a.n_chunks / nb;
     const uint32_t t = a.t;
-    const int64_t stride = static_cast<int64_t>(nwaves) * kUnroll;
+    constexpr int kPer = kMode == 1 ? 2 : 1;             // chunks per iteration
+    const int64_t stride = static_cast<int64_t>(nwaves) * kPer;
 
     if (kLdsSummary) {
         const uint4* g = reinterpret_cast<const uint4*>(a.summary);
@@ -169,45 +232,44 @@ __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
         __syncthreads();
     }
 
-    for (int64_t c = c_begin + static_cast<int64_t>(wave) * kUnroll; c < c_end; c += stride) {
-        // chunks beyond the range repeat the last one and are masked below
-        ChunkRegs cur[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-            load_chunk<kWStream, kNT>(cur[u], a, c + u < c_end ? c + u : c_end - 1, lane);
-        uint32_t slot[kUnroll][8], word[kUnroll][8], cand[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const uint32_t sv[8] = {cur[u].s_lo.x, cur[u].s_lo.y, cur[u].s_lo.z, cur[u].s_lo.w,
-                                    cur[u].s_hi.x, cur[u].s_hi.y, cur[u].s_hi.z, cur[u].s_hi.w};
-            cand[u] = 0;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const uint32_t s = sv[k];
-                const uint32_t sw = kLdsSummary ? lds_summary[s >> 5] : a.summary[s >> 5];
-                const uint32_t dk = ((k < 4 ? cur[u].dq.x : cur[u].dq.y) >> (8 * (k & 3))) & 0xFFu;
-                // edges longer than the summary window always look at the history
-                const uint32_t hit = ((sw >> (s & 31)) & 1u) | (dk > a.window ? 1u : 0u);
-                slot[u][k] = (t - dk) & 0xFFu;
-                const uint32_t widx = hit ? (slot[u][k] >> 5) * a.n_pad + s : 0u;
-                word[u][k] = a.ring[widx];
-                cand[u] |= hit << k;
-            }
+    int64_t c = c_begin + static_cast<int64_t>(wave) * kPer;
+    if (kMode == 2) {
+        ChunkRegs cur;
+        if (c < c_end) load_chunk<kWStream, kNT>(cur, a, c, lane);
+        for (; c < c_end; c += stride) {
+            uint32_t aw[8], cand;
+            gather_chunk<kLdsSummary>(cur, a, lds_summary, aw, &cand);
+            const ChunkRegs now = cur;
+            // the next chunk's stream is in flight while the gathers return
+            // (unconditional, so waiting for the gathers never waits for it;
+            // the last iteration reloads its own chunk)
+            load_chunk<kWStream, kNT>(cur, a, c + stride < c_end ? c + stride : c, lane);
+            const uint32_t fired = fired_bits(now, a, t, aw, cand);
+            if (wave_ballot(fired != 0)) deliver_fired<kWStream>(a, c, lane, fired, now.wq);
         }
+    } else {
+        for (; c < c_end; c += stride) {
+            // chunks beyond the range repeat the last one and are masked below
+            ChunkRegs cur[kPer];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            uint32_t fired = 0;
+            for (int u = 0; u < kPer; ++u)
+                load_chunk<kWStream, kNT>(cur[u], a, c + u < c_end ? c + u : c_end - 1, lane);
+            uint32_t aw[kPer][8], cand[kPer];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) fired |= (((cand[u] >> k) & (word[u][k] >> (slot[u][k] & 31))) & 1u) << k;
-            if (c + u >= c_end) fired = 0;
-            if (wave_ballot(fired != 0)) deliver_fired<kWStream>(a, c + u, lane, fired, cur[u].rs, cur[u].wq);
+            for (int u = 0; u < kPer; ++u) gather_chunk<kLdsSummary>(cur[u], a, lds_summary, aw[u], &cand[u]);
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                uint32_t fired = fired_bits(cur[u], a, t, aw[u], cand[u]);
+                if (c + u >= c_end) fired = 0;
+                if (wave_ballot(fired != 0)) deliver_fired<kWStream>(a, c + u, lane, fired, cur[u].wq);
+            }
         }
     }
 }
 
 struct NodeArgs {
     float* __restrict__ V;
-    uint8_t* __restrict__ age;
+    uint16_t* __restrict__ age;
     float* __restrict__ I;
     uint32_t* __restrict__ ring;
     uint32_t* __restrict__ summary;
@@ -235,7 +297,8 @@ __global__ void __launch_bounds__(256) node_update_kernel(NodeArgs a) {
     const int64_t jj = valid ? j : 0;
     const NetParams p = kMulti ? a.params[a.net_id[jj]] : a.p0;
     const float v = a.V[jj];
-    const uint32_t age = a.age[jj];
+    const uint32_t ages = a.age[jj];
+    const uint32_t age = ages & 0xFFu, age2 = ages >> 8;
     const float in = a.I[jj];
     const bool spike = valid && v >= p.v_th;
 
@@ -281,7 +344,10 @@ __global__ void __launch_bounds__(256) node_update_kernel(NodeArgs a) {
 
     if (valid) {
         a.V[j] = vn;
-        a.age[j] = static_cast<uint8_t>(age_n);
+        // the previous last spike becomes the one before the last
+        const uint32_t older = spike ? age : age2;
+        const uint32_t age2_n = older >= static_cast<uint32_t>(kAgeNever) ? kAgeNever : older + 1u;
+        a.age[j] = static_cast<uint16_t>(age_n | (age2_n << 8));
         if (a.calcium) {
             // calcium and its frame sum in FP64: tau_c / dt is thousands of steps
             const double c = a.calcium[j];
@@ -321,7 +387,7 @@ struct EnsembleArgs {
     const uint32_t* __restrict__ drive_thr;
     const float* __restrict__ i_ext;
     float* __restrict__ V;
-    uint8_t* __restrict__ age;
+    uint16_t* __restrict__ age;
     uint32_t* __restrict__ ring;
     uint32_t* __restrict__ summary;
     double* __restrict__ calcium;
@@ -387,7 +453,7 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
             const int64_t u = nm.node_off + j;
             L.V[j] = a.V[u];
             L.I[j] = 0.0f;
-            L.age[j] = a.age[u];
+            L.age[j] = a.age[u] & 0xFFu;
             if (obs) {
                 L.c[j] = a.calcium[u];
                 L.acc[j] = a.frame_acc[u];
@@ -433,8 +499,7 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
                 if (wave_ballot(fired != 0)) {
                     const uint32_t rs = a.rowstart[static_cast<int64_t>(c) * 64 + lane];
                     const uint32_t bits = lane == 0 ? (rs & ~1u) : rs;
-                    const uint32_t before = wave_exclusive_sum(__popc(bits), lane);
-                    const int32_t row0 = a.chunk_row0[c] - nm.node_off + static_cast<int32_t>(before);
+                    const int32_t row0 = a.chunk_row0[c] - nm.node_off + static_cast<int32_t>(wave_bits_before(bits));
                     uint32_t wb[8];
 #pragma unroll
                     for (int k = 0; k < 8; ++k) wb[k] = ((fired >> k) & 1u) ? a.w[e0 + k] : 0u;   // arrivals only
@@ -540,7 +605,9 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
                 put_bits_shared(reinterpret_cast<uint64_t*>(a.summary), nm.node_off + base + wave * 64, recent, alive);
             if (!valid) continue;
             a.V[u] = L.V[j];
-            a.age[u] = static_cast<uint8_t>(age);
+            // the single-launch kernel keeps no second age: 0 sends every
+            // per-step delivery of these sources to the history ring
+            a.age[u] = static_cast<uint16_t>(age);
             if (obs) {
                 a.calcium[u] = L.c[j];
                 a.frame_acc[u] = L.acc[j];
@@ -568,7 +635,7 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
 
 struct ObserveArgs {
     const float* __restrict__ V;
-    const uint8_t* __restrict__ age;
+    const uint16_t* __restrict__ age;
     const double* __restrict__ calcium;
     const float* __restrict__ frames;
     const NetParams* __restrict__ params;
@@ -590,7 +657,7 @@ __global__ void __launch_bounds__(256) observe_kernel(ObserveArgs a) {
             static_cast<float*>(a.out)[j] = a.V[j];
             break;
         case NET_OBS_REF: {
-            const int32_t age = a.age[j];
+            const int32_t age = a.age[j] & 0xFF;
             static_cast<int32_t*>(a.out)[j] = (age >= 1 && age <= p.n_ref) ? p.n_ref + 1 - age : 0;
             break;
         }
@@ -630,16 +697,16 @@ hipError_t configure_deliver(const DeviceGraph& g, const net_build_opts* opts, L
     lc.lds_bytes = lc.lds_summary ? summary_bytes : 0;
     lc.stream_weights = (flags & NET_BUILD_DELIVER_STREAM_WEIGHTS) != 0;
     lc.nontemporal = (flags & NET_BUILD_DELIVER_NONTEMPORAL) != 0;
-    lc.unroll = (flags & NET_BUILD_DELIVER_UNROLL2) ? 2 : 1;
+    lc.mode = (flags & NET_BUILD_DELIVER_UNROLL2) ? 1 : ((flags & NET_BUILD_DELIVER_PIPELINE) ? 2 : 0);
     if (lc.lds_summary) {
-        const void* fns[8] = {reinterpret_cast<const void*>(&deliver_kernel<true, false, false, 1>),
-                              reinterpret_cast<const void*>(&deliver_kernel<true, false, true, 1>),
-                              reinterpret_cast<const void*>(&deliver_kernel<true, true, false, 1>),
-                              reinterpret_cast<const void*>(&deliver_kernel<true, true, true, 1>),
-                              reinterpret_cast<const void*>(&deliver_kernel<true, false, false, 2>),
-                              reinterpret_cast<const void*>(&deliver_kernel<true, false, true, 2>),
-                              reinterpret_cast<const void*>(&deliver_kernel<true, true, false, 2>),
-                              reinterpret_cast<const void*>(&deliver_kernel<true, true, true, 2>)};
+        const void* fns[] = {
+#define GEONET_DELIVER_FN(W, N, M) reinterpret_cast<const void*>(&deliver_kernel<true, W, N, M>),
+#define GEONET_DELIVER_FNS(M) GEONET_DELIVER_FN(false, false, M) GEONET_DELIVER_FN(false, true, M) \
+                              GEONET_DELIVER_FN(true, false, M) GEONET_DELIVER_FN(true, true, M)
+            GEONET_DELIVER_FNS(0) GEONET_DELIVER_FNS(1) GEONET_DELIVER_FNS(2)
+#undef GEONET_DELIVER_FNS
+#undef GEONET_DELIVER_FN
+        };
         for (const void* f : fns) {
             e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(summary_bytes));
             if (e != hipSuccess) return e;
@@ -674,6 +741,7 @@ hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t 
     a.chunk_row0 = g.chunk_row0;
     a.summary = g.summary;
     a.ring = g.ring;
+    a.ages = g.age;
     a.I = g.I;
     a.n_chunks = g.n_chunks;
     a.summary_vec4 = static_cast<int32_t>(g.n_pad / 128);
@@ -681,27 +749,29 @@ hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t 
     a.n_pad = static_cast<uint32_t>(g.n_pad);
     a.window = static_cast<uint32_t>(g.d_sum);
     const dim3 grid(lc.deliver_blocks), block(lc.deliver_threads);
-    const int v = (lc.unroll == 2 ? 8 : 0) | (lc.lds_summary ? 4 : 0) | (lc.stream_weights ? 2 : 0) |
-                  (lc.nontemporal ? 1 : 0);
+    const int v = lc.mode * 8 + (lc.lds_summary ? 4 : 0) + (lc.stream_weights ? 2 : 0) + (lc.nontemporal ? 1 : 0);
     switch (v) {
-#define GEONET_DELIVER_CASE(U, L, W, N)                                                            \
-    case (U == 2 ? 8 : 0) | (L ? 4 : 0) | (W ? 2 : 0) | (N ? 1 : 0):                               \
-        hipExtLaunchKernelGGL((deliver_kernel<L, W, N, U>), grid, block, L ? lc.lds_bytes : 0, s, ev0, ev1, 0, \
+#define GEONET_DELIVER_CASE(M, L, W, N)                                                            \
+    case M * 8 + (L ? 4 : 0) + (W ? 2 : 0) + (N ? 1 : 0):                                          \
+        hipExtLaunchKernelGGL((deliver_kernel<L, W, N, M>), grid, block, L ? lc.lds_bytes : 0, s, ev0, ev1, 0, \
                               a);                                                                  \
         break;
-#define GEONET_DELIVER_CASES(U)              \
-    GEONET_DELIVER_CASE(U, false, false, false) \
-    GEONET_DELIVER_CASE(U, false, false, true)  \
-    GEONET_DELIVER_CASE(U, false, true, false)  \
-    GEONET_DELIVER_CASE(U, false, true, true)   \
-    GEONET_DELIVER_CASE(U, true, false, false)  \
-    GEONET_DELIVER_CASE(U, true, false, true)   \
-    GEONET_DELIVER_CASE(U, true, true, false)   \
-    GEONET_DELIVER_CASE(U, true, true, true)
+#define GEONET_DELIVER_CASES(M)              \
+    GEONET_DELIVER_CASE(M, false, false, false) \
+    GEONET_DELIVER_CASE(M, false, false, true)  \
+    GEONET_DELIVER_CASE(M, false, true, false)  \
+    GEONET_DELIVER_CASE(M, false, true, true)   \
+    GEONET_DELIVER_CASE(M, true, false, false)  \
+    GEONET_DELIVER_CASE(M, true, false, true)   \
+    GEONET_DELIVER_CASE(M, true, true, false)   \
+    GEONET_DELIVER_CASE(M, true, true, true)
+        GEONET_DELIVER_CASES(0)
         GEONET_DELIVER_CASES(1)
         GEONET_DELIVER_CASES(2)
 #undef GEONET_DELIVER_CASES
 #undef GEONET_DELIVER_CASE
+        default:
+            return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -96,3 +96,13 @@ def test_search_reaches_the_best_subset_on_a_small_target():
         flip = list(subsets[k_final])
         flip[k] ^= 1
         assert lls[subsets.index(tuple(flip))] <= final + 1e-9
+
+
+@pytest.mark.parametrize("frac", [0.3, float(np.float32(0.3))])
+def test_initial_member_count(frac):
+    """ceil(f n) initial members per target, also for f given in FP32."""
+    rng = np.random.default_rng(1)
+    en = FE.standardise(rng.random((12, 40)))
+    pairs = np.array([[i, 0] for i in range(1, 11)] + [[i, 11] for i in range(1, 8)])
+    m = SF.initial_members(en, pairs, frac)
+    assert m[:10].sum() == 3 and m[10:].sum() == 3        # ceil(3.0) and ceil(2.1)
