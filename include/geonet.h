@@ -121,6 +121,9 @@ typedef struct {
                                              (default one) */
 #define NET_BUILD_DELIVER_PIPELINE 128   /* delivery: issue the next chunk's edge loads while
                                              this chunk's history gathers are in flight */
+#define NET_BUILD_SUMMARY_HALF 256        /* delivery: one recent-spike summary bit per vertex pair
+                                             (half the LDS, twice the workgroups per CU; more
+                                             candidates, resolved exactly) */
 #define NET_BUILD_SINGLE_LAUNCH 32        /* one network: run all steps of a call in one launch of
                                              the LDS-resident kernel ensembles use, when the
                                              network fits one workgroup's LDS */

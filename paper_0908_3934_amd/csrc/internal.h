@@ -74,6 +74,7 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
 struct DeviceGraph {
     int64_t n_total, n_pad, e_slots, n_chunks;
     int32_t n_nets, max_delay, d_sum;   // d_sum: summary window W <= max_delay
+    int32_t sum_shift = 0;        // summary bit b covers vertices [b << sum_shift, (b + 1) << sum_shift)
     const int32_t* src;
     const uint16_t* w;
     const uint8_t* d;
@@ -88,7 +89,7 @@ struct DeviceGraph {
                        // before it (both saturate at 255; delivery at step t reads t - t_spike)
     float* I;
     uint32_t* ring;               // [kRingWords][n_pad]: bit (s mod 32) of word (s mod 256)/32 = spike at step s
-    uint32_t* summary;            // [n_pad / 32]
+    uint32_t* summary;            // [n_pad / 32] words, of which (n_pad >> sum_shift) / 32 are used
     double* calcium;              // null when observation is off
     double* frame_acc;
     float* frames;                // [frame_cap][n_pad]
@@ -131,7 +132,7 @@ hipError_t launch_node_update(const DeviceGraph& g, int64_t t, int64_t rec_row, 
                               hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_observe(const DeviceGraph& g, int32_t what, const net_fluor_params* fp, void* out,
                           int64_t n_frames, hipStream_t s);
-hipError_t configure_deliver(const DeviceGraph& g, const net_build_opts* opts, LaunchConfig& lc);
+hipError_t configure_deliver(DeviceGraph& g, const net_build_opts* opts, LaunchConfig& lc);   // sets g.sum_shift
 hipError_t enable_ensemble_lds(size_t bytes);
 hipError_t launch_ensemble(const DeviceGraph& g, const EnsemblePlan& plan, int64_t t0, int32_t n_steps,
                            const net_record* rec, int32_t frame_num, int32_t frame_den, hipStream_t s,

@@ -80,6 +80,7 @@ struct DeliverArgs {
     uint32_t t;             // step index modulo 2^32 (only t mod 256 matters)
     uint32_t n_pad;         // ring row length: word (slot/32, vertex) is at slot/32*n_pad + vertex
     uint32_t window;        // summary window W: bit set iff the vertex fired in the last W steps
+    uint32_t sum_shift;     // summary bit of vertex s: s >> sum_shift (0, or 1: one bit per vertex pair)
 };
 
 // One wave handles 512 consecutive slots per iteration: lane L owns slots
@@ -137,10 +138,11 @@ __device__ __forceinline__ void gather_chunk(const ChunkRegs& x, const DeliverAr
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const uint32_t s = sv[k];
-        const uint32_t sw = kLdsSummary ? lds_summary[s >> 5] : a.summary[s >> 5];
+        const uint32_t sb = s >> a.sum_shift;
+        const uint32_t sw = kLdsSummary ? lds_summary[sb >> 5] : a.summary[sb >> 5];
         const uint32_t dk = ((k < 4 ? x.dq.x : x.dq.y) >> (8 * (k & 3))) & 0xFFu;
         // edges longer than the summary window are always resolved
-        const uint32_t hit = ((sw >> (s & 31)) & 1u) | (dk > a.window ? 1u : 0u);
+        const uint32_t hit = ((sw >> (sb & 31)) & 1u) | (dk > a.window ? 1u : 0u);
         aw[k] = a.ages[hit ? s : 0u];
         cm |= hit << k;
     }
@@ -285,7 +287,7 @@ struct NodeArgs {
     float* __restrict__ rec_input;
     int64_t n_total, n_pad, rec_row, raster_words, frame_index;
     uint32_t t_lo, t_hi;
-    int32_t d_sum, frame_flush, frame_steps, frame_cap;
+    int32_t d_sum, frame_flush, frame_steps, frame_cap, sum_shift;
     NetParams p0;
 };
 
@@ -340,7 +342,20 @@ __global__ void __launch_bounds__(256) node_update_kernel(NodeArgs a) {
     }
     // recent-spike summary for the next step: last spike within d_sum steps
     const uint64_t recent = wave_ballot(valid && age_n <= static_cast<uint32_t>(a.d_sum));
-    if (lane == 0 && j < a.n_pad) reinterpret_cast<uint64_t*>(a.summary)[j >> 6] = recent;
+    if (lane == 0 && j < a.n_pad) {
+        if (a.sum_shift == 0) {
+            reinterpret_cast<uint64_t*>(a.summary)[j >> 6] = recent;
+        } else {
+            // one bit per vertex pair: OR the pairs, then pack the even bits
+            uint64_t x = (recent | (recent >> 1)) & 0x5555555555555555ull;
+            x = (x | (x >> 1)) & 0x3333333333333333ull;
+            x = (x | (x >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+            x = (x | (x >> 4)) & 0x00FF00FF00FF00FFull;
+            x = (x | (x >> 8)) & 0x0000FFFF0000FFFFull;
+            x = (x | (x >> 16)) & 0x00000000FFFFFFFFull;
+            a.summary[j >> 6] = static_cast<uint32_t>(x);
+        }
+    }
 
     if (valid) {
         a.V[j] = vn;
@@ -683,15 +698,16 @@ __global__ void __launch_bounds__(256) observe_kernel(ObserveArgs a) {
 
 }  // namespace
 
-hipError_t configure_deliver(const DeviceGraph& g, const net_build_opts* opts, LaunchConfig& lc) {
+hipError_t configure_deliver(DeviceGraph& g, const net_build_opts* opts, LaunchConfig& lc) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     int n_cu = 0, lds_max = 0;
     if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
-    const size_t summary_bytes = static_cast<size_t>(g.n_pad / 8);
     const int flags = opts ? opts->flags : 0;
+    g.sum_shift = (flags & NET_BUILD_SUMMARY_HALF) ? 1 : 0;
+    const size_t summary_bytes = static_cast<size_t>(g.n_pad / 8) >> g.sum_shift;
     const bool want_lds = !(flags & NET_BUILD_NO_LDS_SUMMARY);
     lc.lds_summary = want_lds && summary_bytes <= static_cast<size_t>(lds_max);
     lc.lds_bytes = lc.lds_summary ? summary_bytes : 0;
@@ -718,7 +734,8 @@ hipError_t configure_deliver(const DeviceGraph& g, const net_build_opts* opts, L
         per_cu = static_cast<int>((160 * 1024) / summary_bytes);
         per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
     }
-    int threads = per_cu <= 1 ? 1024 : (per_cu <= 2 ? 512 : 256);
+    // up to 32 waves per CU: 1024 threads for one or two workgroups per CU
+    int threads = per_cu <= 2 ? 1024 : (per_cu <= 4 ? 512 : 256);
     if (opts && opts->block_threads) threads = opts->block_threads;
     if (opts && opts->blocks_per_cu) per_cu = opts->blocks_per_cu;
     int64_t blocks = static_cast<int64_t>(n_cu) * per_cu;
@@ -744,7 +761,8 @@ hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t 
     a.ages = g.age;
     a.I = g.I;
     a.n_chunks = g.n_chunks;
-    a.summary_vec4 = static_cast<int32_t>(g.n_pad / 128);
+    a.summary_vec4 = static_cast<int32_t>((g.n_pad >> g.sum_shift) / 128);
+    a.sum_shift = static_cast<uint32_t>(g.sum_shift);
     a.t = static_cast<uint32_t>(t);
     a.n_pad = static_cast<uint32_t>(g.n_pad);
     a.window = static_cast<uint32_t>(g.d_sum);
@@ -803,6 +821,7 @@ hipError_t launch_node_update(const DeviceGraph& g, int64_t t, int64_t rec_row, 
     a.t_lo = static_cast<uint32_t>(t);
     a.t_hi = static_cast<uint32_t>(static_cast<uint64_t>(t) >> 32);
     a.d_sum = g.d_sum;
+    a.sum_shift = g.sum_shift;
     a.frame_flush = frame_flush;
     a.frame_steps = frame_steps;
     a.frame_cap = g.frame_cap;

@@ -8,6 +8,8 @@
 // binary cross-entropy with logits and all gradients are FP32.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 #include <cstdint>
 
@@ -134,52 +136,95 @@ struct HeadArgs {
     uint16_t* dH2;
     float* dw3;
     float* db3;
-    float* loss;             // sum of per-row losses / B (atomic)
+    float* db2;              // column sums of the BF16 dH2
+    float* loss;             // sum of per-row losses / B
     int64_t B;
 };
 
+// Head and loss: one wave per row, rows strided over the grid.  The w3, b3
+// and b2 gradients and the loss are summed in registers over a wave's rows,
+// then over the workgroup in LDS, and added to the gradient once per
+// workgroup (not once per row).
 __global__ void __launch_bounds__(256) head_kernel(HeadArgs a) {
+    __shared__ float red[4][2 * kMlpH + 2];
     const int lane = threadIdx.x & 63;
-    const int64_t row = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-    if (row >= a.B) return;
-    float h[4], s = 0.0f;
+    const int wave = threadIdx.x >> 6;
+    const int64_t n_waves = static_cast<int64_t>(gridDim.x) * 4;
+    float w3r[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        h[q] = bf16_bits_to_f32(a.H2[row * 256 + q * 64 + lane]);
-        s += h[q] * a.w3[q * 64 + lane];
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    const float logit = s + a.b3[0];
-    if (lane == 0) a.logits[row] = logit;
-    if (!a.y) return;
-    const float y = a.y[row];
-    const float p = 1.0f / (1.0f + expf(-logit));
+    for (int q = 0; q < 4; ++q) w3r[q] = a.w3[q * 64 + lane];
+    const float b3 = a.b3[0];
     const float inv_b = 1.0f / static_cast<float>(a.B);
-    const float dl = (p - y) * inv_b;
-    if (lane == 0) {
+    float gw3[4] = {0.0f, 0.0f, 0.0f, 0.0f}, gb2[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float gl = 0.0f, gb3 = 0.0f;
+    for (int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + wave; row < a.B; row += n_waves) {
+        float h[4], s = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            h[q] = bf16_bits_to_f32(a.H2[row * kMlpH + q * 64 + lane]);
+            s += h[q] * w3r[q];
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        const float logit = s + b3;
+        if (lane == 0) a.logits[row] = logit;
+        if (!a.y) continue;
+        const float y = a.y[row];
+        const float p = 1.0f / (1.0f + expf(-logit));
+        const float dl = (p - y) * inv_b;
         // log(1 + exp(-|z|)) + max(z, 0) - z*y
-        const float l = log1pf(expf(-fabsf(logit))) + fmaxf(logit, 0.0f) - logit * y;
-        atomicAdd(a.loss, l * inv_b);
-        atomicAdd(a.db3, dl);
+        gl += (log1pf(expf(-fabsf(logit))) + fmaxf(logit, 0.0f) - logit * y) * inv_b;
+        gb3 += dl;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint16_t g = f32_to_bf16_bits(h[q] > 0.0f ? dl * w3r[q] : 0.0f);
+            a.dH2[row * kMlpH + q * 64 + lane] = g;
+            gb2[q] += bf16_bits_to_f32(g);
+            gw3[q] += dl * h[q];
+        }
     }
+    if (!a.y) return;                        // uniform over the grid
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int n = q * 64 + lane;
-        a.dH2[row * 256 + n] = f32_to_bf16_bits(h[q] > 0.0f ? dl * a.w3[n] : 0.0f);
-        atomicAdd(a.dw3 + n, dl * h[q]);
+        red[wave][q * 64 + lane] = gw3[q];
+        red[wave][kMlpH + q * 64 + lane] = gb2[q];
+    }
+    if (lane == 0) {
+        red[wave][2 * kMlpH] = gl;           // every lane holds the same row sums
+        red[wave][2 * kMlpH + 1] = gb3;
+    }
+    __syncthreads();
+    const int n = threadIdx.x;
+    atomicAdd(a.dw3 + n, red[0][n] + red[1][n] + red[2][n] + red[3][n]);
+    atomicAdd(a.db2 + n, red[0][kMlpH + n] + red[1][kMlpH + n] + red[2][kMlpH + n] + red[3][kMlpH + n]);
+    if (n == 0) {
+        atomicAdd(a.loss, red[0][2 * kMlpH] + red[1][2 * kMlpH] + red[2][2 * kMlpH] + red[3][2 * kMlpH]);
+        atomicAdd(a.db3, red[0][2 * kMlpH + 1] + red[1][2 * kMlpH + 1] + red[2][2 * kMlpH + 1] +
+                             red[3][2 * kMlpH + 1]);
     }
 }
 
-// Column sums of a BF16 [B x 256] matrix into FP32 (bias gradients).
+// Column sums of a [B][256] BF16 matrix into out (atomic, once per
+// workgroup): each thread owns two adjacent columns of every other row of
+// its workgroup's row range.
 __global__ void __launch_bounds__(256) colsum_kernel(const uint16_t* X, int64_t B, float* out) {
-    const int n = threadIdx.x;
+    __shared__ float red[2][kMlpH];
+    const int t = threadIdx.x;
+    const int cp = t & 127, ro = t >> 7;
     const int64_t rows_per = (B + gridDim.x - 1) / gridDim.x;
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rows_per;
     const int64_t r1 = r0 + rows_per < B ? r0 + rows_per : B;
-    float s = 0.0f;
-    for (int64_t r = r0; r < r1; ++r) s += bf16_bits_to_f32(X[r * 256 + n]);
-    if (r1 > r0) atomicAdd(out + n, s);
+    const uint32_t* X32 = reinterpret_cast<const uint32_t*>(X);
+    float s0 = 0.0f, s1 = 0.0f;
+    for (int64_t r = r0 + ro; r < r1; r += 2) {
+        const uint32_t v = X32[r * (kMlpH / 2) + cp];
+        s0 += bf16_bits_to_f32(v & 0xFFFFu);
+        s1 += bf16_bits_to_f32(v >> 16);
+    }
+    red[ro][2 * cp] = s0;
+    red[ro][2 * cp + 1] = s1;
+    __syncthreads();
+    if (r1 > r0) atomicAdd(out + t, red[0][t] + red[1][t]);
 }
 
 // Adam on the flat FP32 parameter vector; refreshes the BF16 copies of W1, W2.
@@ -265,10 +310,11 @@ hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const floa
     h.dH2 = d.dH2;
     h.dw3 = d.grad + kMlpW3Off;
     h.db3 = d.grad + kMlpB3Off;
+    h.db2 = d.grad + kMlpB2Off;
     h.loss = d.loss;
     h.B = B;
-    const int64_t threads = B * 64;
-    hipLaunchKernelGGL(head_kernel, dim3(static_cast<unsigned>((threads + 255) / 256)), dim3(256), 0, s, h);
+    const int64_t hb = std::min<int64_t>(std::max<int64_t>((B + 63) / 64, 1), 512);   // ~16 rows per wave
+    hipLaunchKernelGGL(head_kernel, dim3(static_cast<unsigned>(hb)), dim3(256), 0, s, h);
     return hipGetLastError();
 }
 
@@ -324,8 +370,8 @@ hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, hipStream
     w1.b_cs = 1;
     w1.out_f32 = d.grad + kMlpW1Off;
     if ((e = gemm<true, kAtomicF32>(w1, split, s)) != hipSuccess) return e;
-    const unsigned cs_blocks = static_cast<unsigned>(B < 1024 ? 1 : (B + 1023) / 1024);
-    hipLaunchKernelGGL(colsum_kernel, dim3(cs_blocks), dim3(256), 0, s, d.dH2, B, d.grad + kMlpB2Off);
+    // b1 gradient: column sums of dH1 (b2's are summed in the head kernel)
+    const unsigned cs_blocks = static_cast<unsigned>(std::min<int64_t>(std::max<int64_t>((B + 63) / 64, 1), 1024));
     hipLaunchKernelGGL(colsum_kernel, dim3(cs_blocks), dim3(256), 0, s, d.dH1, B, d.grad + kMlpB1Off);
     return hipGetLastError();
 }

@@ -295,7 +295,8 @@ def test_autotuned_per_step_equals_default():
         assert np.array_equal(a[key], b[key]), key
 
 
-@pytest.mark.parametrize("flags", ["DELIVER_STREAM_WEIGHTS", "DELIVER_UNROLL2", "DELIVER_NONTEMPORAL"])
+@pytest.mark.parametrize("flags", ["DELIVER_STREAM_WEIGHTS", "DELIVER_UNROLL2", "DELIVER_NONTEMPORAL",
+                                   "DELIVER_PIPELINE", "SUMMARY_HALF"])
 def test_delivery_variants_identical(flags):
     gn, torch = _gn()
     spec = synth.config1(n=8192)
