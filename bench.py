@@ -158,6 +158,66 @@ def bench_ensemble(args, torch, synth, gn):
     }
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def bench_mlp(args, torch, gn):
+    """The edge scorer (64 -> 256 -> 256 -> 1, BF16 MFMA): training steps
+    (forward, BCE backward, Adam) on batches of 16,384 pairs, the size the
+    scorer is trained with, and the forward pass on 65,536 pairs (about one
+    N = 1024 network's candidates).  FLOPs counted: 2 x (64*256 + 256*256 +
+    256) per pair forward, 3x that per training pair.  Timed with events on
+    the stream of the calls, whole steps (all kernels)."""
+    import numpy as np
+    m = gn.Mlp(gn.Mlp.init_params(0))
+    m.set_input_norm(np.zeros(64, np.float32), np.ones(64, np.float32))
+    fw = 2 * (64 * 256 + 256 * 256 + 256)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    Bt, Bf = 16384, 65536
+    X = torch.randn(Bf, 64, device="cuda", generator=g)
+    y = (torch.rand(Bf, device="cuda", generator=g) < 0.3).float()
+    loss = torch.zeros(1, device="cuda")
+    Xt, yt = X[:Bt].contiguous(), y[:Bt].contiguous()
+    steps = args.steps
+    for _ in range(args.warmup):
+        m.train_step(Xt, yt, 1e-3, loss=loss)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        m.train_step(Xt, yt, 1e-3, loss=loss)
+    torch.cuda.synchronize()
+    train_s = (time.perf_counter() - t0) / steps
+    for _ in range(args.warmup):
+        m.forward(X)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        m.forward(X)
+    torch.cuda.synchronize()
+    fwd_s = (time.perf_counter() - t0) / steps
+    train_tflops = 3 * fw * Bt / train_s / 1e12
+    return {
+        "metric": "training pairs/s",
+        "value": Bt / train_s,
+        "unit": "pairs per second (one optimizer step per 16,384 pairs)",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": train_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 (fp32 accumulation, fp32 Adam)",
+        "data": "synthetic",
+        "config": {"workload": "edge-scorer MLP 64 -> 256 -> 256 -> 1, batch 16,384 (training), 65,536 (forward)"},
+        "forward_pairs_per_s": Bf / fwd_s,
+        "forward_us": fwd_s * 1e6,
+        "roofline": {"bound": "mfma", "achieved": train_tflops, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": train_tflops / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
+                     "forward_achieved": fw * Bf / fwd_s / 1e12},
+    }
+
+
 def bench_estimate(args, torch, synth):
     """Functional-topology estimation on N = 1024 networks observed for
     obs-steps at 30 Hz with SNR 5: the learned scorer (64 pair features ->
@@ -250,10 +310,11 @@ def main():
                          "iteration, the fastest measured; 2 streams every weight, 7 B per edge)")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library time the delivery variants at build instead of --deliver-flags")
-    ap.add_argument("--workload", choices=["step", "ensemble", "estimate"], default="step",
+    ap.add_argument("--workload", choices=["step", "ensemble", "estimate", "mlp"], default="step",
                     help="step: the N = 2^20 network (default); ensemble: 512 uneven networks in one launch "
                          "against each network run alone; estimate: learned edge scorer against the "
-                         "simulation-based fit on held-out N = 1024 networks")
+                         "simulation-based fit on held-out N = 1024 networks; mlp: the edge scorer's training "
+                         "step and forward pass")
     ap.add_argument("--train-nets", type=int, default=256, help="estimate workload: training networks")
     ap.add_argument("--test-nets", type=int, default=16, help="estimate workload: held-out networks")
     ap.add_argument("--obs-steps", type=int, default=200000, help="estimate workload: observed steps (20 s)")
@@ -280,6 +341,9 @@ def main():
         return
     if args.workload == "estimate":
         print(json.dumps(bench_estimate(args, torch, synth)), flush=True)
+        return
+    if args.workload == "mlp":
+        print(json.dumps(bench_mlp(args, torch, gn)), flush=True)
         return
     if args.copy_calibration:
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")

@@ -157,6 +157,7 @@ struct MlpDevice {
     float* grad = nullptr;
     uint16_t* w1b = nullptr;      // BF16 copies
     uint16_t* w2b = nullptr;
+    uint16_t* Xb = nullptr;       // [cap x 64] BF16 standardised inputs of the last forward pass
     uint16_t* H1 = nullptr;       // [cap x 256] BF16 activations and gradients
     uint16_t* H2 = nullptr;
     uint16_t* dH1 = nullptr;

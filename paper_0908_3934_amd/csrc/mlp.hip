@@ -33,20 +33,21 @@ __device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
 }
 
 // ---------------------------------------------------------------------------
-// C[M x N] = op(A)[M x K] * op(B)[K x N], FP32 accumulation.
+// C[M x N] = op(A)[M x K] * op(B)[K x N], BF16 operands, FP32 accumulation.
 // A element (m, k) at A[m*a_rs + k*a_cs]; B element (k, n) at B[k*b_rs + n*b_cs].
-// A is FP32 (rounded to BF16 when staged) or BF16 bits; B is BF16 bits.
-// Block tile 64 x 64, four waves (2 x 2) of one 32 x 32 MFMA tile each,
-// K staged through LDS 32 at a time.  Split-K: blockIdx.z takes
-// K range [z*k_chunk, min(K, (z+1)*k_chunk)).
+// Every operand has a unit stride along k or along m / n; it is read in
+// 16-byte groups of 8 elements along that dimension (a k-contiguous group
+// goes to LDS as is, an m- or n-contiguous one is transposed on the way,
+// since LDS holds both tiles k-contiguous for the MFMA fragments).
+// Block tile 128 x 128, four waves of 64 x 64 (2 x 2 tiles of
+// v_mfma_f32_32x32x16_bf16), K staged 32 at a time; the next stage's groups
+// are loaded into registers while the current stage's MFMAs run.  Split-K:
+// blockIdx.z takes K range [z*k_chunk, min(K, (z+1)*k_chunk)).
 // ---------------------------------------------------------------------------
 enum Epilogue { kBiasReluBf16 = 0, kMaskBf16 = 1, kAtomicF32 = 2 };
 
 struct GemmArgs {
-    const void* A;
-    const float* a_shift;     // FP32 A only: A is staged as (A - shift[f]) * scale[f] (null: as is),
-    const float* a_scale;     // f = k, or f = m when shift_on_m (A is a transposed feature matrix)
-    int32_t shift_on_m;
+    const uint16_t* A;
     const uint16_t* B;
     int64_t M, N, K, k_chunk;
     int64_t a_rs, a_cs, b_rs, b_cs;
@@ -56,77 +57,143 @@ struct GemmArgs {
     float* out_f32;           // [M x N] row-major (atomic add)
 };
 
-constexpr int kTile = 64, kKs = 32, kLdsK = kKs + 8;   // padded rows against bank conflicts
+constexpr int kTile = 128, kKs = 32, kLdsK = kKs + 8;   // padded rows against bank conflicts
+constexpr int kGroups = kTile * kKs / 8 / 256;           // 16-byte groups per thread per operand (2)
 
-template <bool kAF32, int kEpi>
+struct StageRegs {
+    uint4 a[kGroups];
+    uint4 b[kGroups];
+};
+
+// Group e of a stage: for a k-contiguous operand, tile row e / 4 and k offset
+// (e % 4) * 8; for an m/n-contiguous one, k offset e / 16 and tile row (e % 16) * 8.
+__device__ __forceinline__ void load_stage(StageRegs& r, const GemmArgs& g, bool a_kc, bool b_kc, int64_t m0,
+                                           int64_t n0, int64_t k0, int64_t k_hi, int tid) {
+#pragma unroll
+    for (int q = 0; q < kGroups; ++q) {
+        const int e = tid + 256 * q;
+        const int64_t m = a_kc ? m0 + e / 4 : m0 + (e % 16) * 8;
+        const int64_t k = a_kc ? k0 + (e % 4) * 8 : k0 + e / 16;
+        uint4 va = make_uint4(0u, 0u, 0u, 0u);
+        if (m < g.M && k < k_hi) va = *reinterpret_cast<const uint4*>(g.A + m * g.a_rs + k * g.a_cs);
+        r.a[q] = va;
+        const int64_t n = b_kc ? n0 + e / 4 : n0 + (e % 16) * 8;
+        const int64_t kb = b_kc ? k0 + (e % 4) * 8 : k0 + e / 16;
+        uint4 vb = make_uint4(0u, 0u, 0u, 0u);
+        if (n < g.N && kb < k_hi) vb = *reinterpret_cast<const uint4*>(g.B + kb * g.b_rs + n * g.b_cs);
+        r.b[q] = vb;
+    }
+}
+
+// Writes 8 BF16 of a group to LDS: along k (one 16-byte store) or down 8 rows.
+__device__ __forceinline__ void put_group(uint16_t (*T)[kLdsK], int row, int kk, bool kc, const uint4& v) {
+    if (kc) {
+        *reinterpret_cast<uint4*>(&T[row][kk]) = v;
+    } else {
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            T[row + 2 * i][kk] = static_cast<uint16_t>(w[i] & 0xFFFFu);
+            T[row + 2 * i + 1][kk] = static_cast<uint16_t>(w[i] >> 16);
+        }
+    }
+}
+
+__device__ __forceinline__ void store_stage(const StageRegs& r, bool a_kc, bool b_kc, int tid, uint16_t (*As)[kLdsK],
+                                            uint16_t (*Bs)[kLdsK]) {
+#pragma unroll
+    for (int q = 0; q < kGroups; ++q) {
+        const int e = tid + 256 * q;
+        put_group(As, a_kc ? e / 4 : (e % 16) * 8, a_kc ? (e % 4) * 8 : e / 16, a_kc, r.a[q]);
+        put_group(Bs, b_kc ? e / 4 : (e % 16) * 8, b_kc ? (e % 4) * 8 : e / 16, b_kc, r.b[q]);
+    }
+}
+
+template <int kEpi>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
-    __shared__ uint16_t As[kTile][kLdsK];   // [m][k]
-    __shared__ uint16_t Bs[kTile][kLdsK];   // [n][k] (transposed so fragments are contiguous)
+    __shared__ __attribute__((aligned(16))) uint16_t As[kTile][kLdsK];   // [m][k]
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kTile][kLdsK];   // [n][k]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int64_t m0 = static_cast<int64_t>(blockIdx.y) * kTile, n0 = static_cast<int64_t>(blockIdx.x) * kTile;
     const int64_t k_lo = static_cast<int64_t>(blockIdx.z) * g.k_chunk;
     const int64_t k_hi = k_lo + g.k_chunk < g.K ? k_lo + g.k_chunk : g.K;
-    f32x16 acc = {};
-    for (int64_t k0 = k_lo; k0 < k_hi; k0 += kKs) {
-        // stage 64 x 32 of A and 32 x 64 of B: 8 elements of each per thread
+    const bool a_kc = g.a_cs == 1, b_kc = g.b_rs == 1;
+    f32x16 acc[2][2];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int e = tid + r * 256;            // 0 .. 2047
-            const int i = e / kKs, kk = e % kKs;    // A: row i, column kk
-            const int64_t m = m0 + i, k = k0 + kk;
-            uint16_t av = 0;
-            if (m < g.M && k < k_hi) {
-                const int64_t off = m * g.a_rs + k * g.a_cs;
-                if (kAF32) {
-                    float x = static_cast<const float*>(g.A)[off];
-                    if (g.a_shift) {
-                        const int64_t fi = g.shift_on_m ? m : k;
-                        x = (x - g.a_shift[fi]) * g.a_scale[fi];
-                    }
-                    av = f32_to_bf16_bits(x);
-                } else {
-                    av = static_cast<const uint16_t*>(g.A)[off];
-                }
-            }
-            As[i][kk] = av;
-            const int jn = e % kTile, kb = e / kTile;   // B: column jn, row kb
-            const int64_t n = n0 + jn, kr = k0 + kb;
-            Bs[jn][kb] = (n < g.N && kr < k_hi) ? g.B[kr * g.b_rs + n * g.b_cs] : static_cast<uint16_t>(0);
-        }
+    for (int tm = 0; tm < 2; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < 2; ++tn)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[tm][tn][i] = 0.0f;
+    StageRegs r;
+    if (k_lo < k_hi) load_stage(r, g, a_kc, b_kc, m0, n0, k_lo, k_hi, tid);
+    for (int64_t k0 = k_lo; k0 < k_hi; k0 += kKs) {
+        store_stage(r, a_kc, b_kc, tid, As, Bs);
         __syncthreads();
+        if (k0 + kKs < k_hi) load_stage(r, g, a_kc, b_kc, m0, n0, k0 + kKs, k_hi, tid);
 #pragma unroll
         for (int ks = 0; ks < kKs; ks += 16) {
             // lane supplies row (lane % 32) and k = ks + 8*(lane / 32) .. +7
-            const int r = lane & 31, kq = ks + 8 * (lane >> 5);
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + r][kq]);
-            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn * 32 + r][kq]);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+            const int rr = lane & 31, kq = ks + 8 * (lane >> 5);
+            bf16x8 a[2], b[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                a[t] = *reinterpret_cast<const bf16x8*>(&As[wm * 64 + t * 32 + rr][kq]);
+                b[t] = *reinterpret_cast<const bf16x8*>(&Bs[wn * 64 + t * 32 + rr][kq]);
+            }
+#pragma unroll
+            for (int tm = 0; tm < 2; ++tm)
+#pragma unroll
+                for (int tn = 0; tn < 2; ++tn)
+                    acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[tm], b[tn], acc[tm][tn], 0, 0, 0);
         }
         __syncthreads();
     }
-    // acc[i] holds C[m][n]: n = lane % 32, m = 8*(i/4) + 4*(lane/32) + i%4
-    const int64_t n = n0 + wn * 32 + (lane & 31);
+    // acc[tm][tn][i] holds C[m][n]: n = lane % 32, m = 8*(i/4) + 4*(lane/32) + i%4 within the 32 x 32 tile
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int64_t m = m0 + wm * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-        if (m >= g.M || n >= g.N) continue;
-        const float v = acc[i];
-        if (kEpi == kBiasReluBf16) {
-            const float h = v + g.bias[n];
-            g.out_bf16[m * g.N + n] = f32_to_bf16_bits(h > 0.0f ? h : 0.0f);
-        } else if (kEpi == kMaskBf16) {
-            const float keep = bf16_bits_to_f32(g.mask[m * g.N + n]) > 0.0f ? 1.0f : 0.0f;
-            g.out_bf16[m * g.N + n] = f32_to_bf16_bits(v * keep);
-        } else {
-            atomicAdd(g.out_f32 + m * g.N + n, v);
+    for (int tm = 0; tm < 2; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < 2; ++tn) {
+            const int64_t n = n0 + wn * 64 + tn * 32 + (lane & 31);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int64_t m = m0 + wm * 64 + tm * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+                if (m >= g.M || n >= g.N) continue;
+                const float v = acc[tm][tn][i];
+                if (kEpi == kBiasReluBf16) {
+                    const float h = v + g.bias[n];
+                    g.out_bf16[m * g.N + n] = f32_to_bf16_bits(h > 0.0f ? h : 0.0f);
+                } else if (kEpi == kMaskBf16) {
+                    const float keep = bf16_bits_to_f32(g.mask[m * g.N + n]) > 0.0f ? 1.0f : 0.0f;
+                    g.out_bf16[m * g.N + n] = f32_to_bf16_bits(v * keep);
+                } else {
+                    atomicAdd(g.out_f32 + m * g.N + n, v);
+                }
+            }
         }
-    }
 }
 
-// Head: logit = H2 . w3 + b3; BCE with logits; dlogit = (sigmoid - y)/B;
-// dH2 = BF16(dlogit * w3 * [H2 > 0]); dw3 += dlogit * H2; db3 += dlogit.
-// One wave per row (256 columns, 4 per lane).
+// Input standardisation and the first rounding point: Xb = BF16((X - shift) * scale)
+// for a [B][64] FP32 feature matrix; one thread per 8 features of a row.
+__global__ void __launch_bounds__(256) normalize_kernel(const float* X, const float* shift, const float* scale,
+                                                        uint16_t* Xb, int64_t n8) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n8) return;
+    const int f0 = static_cast<int>((i * 8) % kMlpIn);
+    const float4 x0 = reinterpret_cast<const float4*>(X)[2 * i];
+    const float4 x1 = reinterpret_cast<const float4*>(X)[2 * i + 1];
+    const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+    uint32_t w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t lo = f32_to_bf16_bits((x[2 * j] - shift[f0 + 2 * j]) * scale[f0 + 2 * j]);
+        const uint32_t hi = f32_to_bf16_bits((x[2 * j + 1] - shift[f0 + 2 * j + 1]) * scale[f0 + 2 * j + 1]);
+        w[j] = lo | (hi << 16);
+    }
+    reinterpret_cast<uint4*>(Xb)[i] = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 struct HeadArgs {
     const uint16_t* H2;
     const float* w3;
@@ -258,11 +325,18 @@ __global__ void __launch_bounds__(256) to_bf16_kernel(const float* x, uint16_t* 
     if (i < n) y[i] = f32_to_bf16_bits(x[i]);
 }
 
-template <bool kAF32, int kEpi>
+template <int kEpi>
 hipError_t gemm(const GemmArgs& g, int split, hipStream_t s) {
+    // every operand must have a unit stride along k or along its row/column
+    // dimension, with that extent (and the split-K chunk) a multiple of 8 so
+    // that each 16-byte group is entirely in or out of range
+    const bool a_kc = g.a_cs == 1, b_kc = g.b_rs == 1;
+    if ((!a_kc && g.a_rs != 1) || (!b_kc && g.b_cs != 1)) return hipErrorInvalidValue;
+    if ((a_kc || b_kc) && (g.K % 8 != 0 || g.k_chunk % kKs != 0)) return hipErrorInvalidValue;
+    if ((!a_kc && g.M % 8 != 0) || (!b_kc && g.N % 8 != 0)) return hipErrorInvalidValue;
     dim3 grid(static_cast<unsigned>((g.N + kTile - 1) / kTile), static_cast<unsigned>((g.M + kTile - 1) / kTile),
               static_cast<unsigned>(split));
-    hipLaunchKernelGGL((gemm_kernel<kAF32, kEpi>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_kernel<kEpi>), grid, dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
@@ -272,10 +346,11 @@ hipError_t gemm(const GemmArgs& g, int split, hipStream_t s) {
 hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const float* y, bool backward,
                        hipStream_t s) {
     const float* p = d.params;
+    const int64_t n8 = B * kMlpIn / 8;
+    hipLaunchKernelGGL(normalize_kernel, dim3(static_cast<unsigned>((n8 + 255) / 256)), dim3(256), 0, s, X,
+                       d.in_shift, d.in_scale, d.Xb, n8);
     GemmArgs g1{};
-    g1.A = X;
-    g1.a_shift = d.in_shift;
-    g1.a_scale = d.in_scale;
+    g1.A = d.Xb;
     g1.B = d.w1b;
     g1.M = B;
     g1.N = kMlpH;
@@ -287,19 +362,17 @@ hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const floa
     g1.b_cs = 1;
     g1.bias = p + kMlpB1Off;
     g1.out_bf16 = d.H1;
-    hipError_t e = gemm<true, kBiasReluBf16>(g1, 1, s);
+    hipError_t e = gemm<kBiasReluBf16>(g1, 1, s);
     if (e != hipSuccess) return e;
     GemmArgs g2 = g1;
     g2.A = d.H1;
-    g2.a_shift = nullptr;
-    g2.a_scale = nullptr;
     g2.B = d.w2b;
     g2.K = kMlpH;
     g2.k_chunk = kMlpH;
     g2.a_rs = kMlpH;
     g2.bias = p + kMlpB2Off;
     g2.out_bf16 = d.H2;
-    e = gemm<false, kBiasReluBf16>(g2, 1, s);
+    e = gemm<kBiasReluBf16>(g2, 1, s);
     if (e != hipSuccess) return e;
     HeadArgs h{};
     h.H2 = d.H2;
@@ -321,7 +394,8 @@ hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const floa
 // Backward pass after mlp_forward(..., backward = true): accumulates the
 // gradient of the mean BCE into d.grad (which the caller zeroed).
 hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, hipStream_t s) {
-    const int split = B >= 4096 ? static_cast<int>((B + 2047) / 2048) : 1;
+    // split-K over chunks of 512 rows (the weight-gradient tiles alone are too few)
+    const int split = static_cast<int>(std::max<int64_t>((B + 511) / 512, 1));
     const int64_t k_chunk = ((B + split - 1) / split + kKs - 1) / kKs * kKs;
     // dW2 = H1^T dH2  (M = 256, N = 256, K = B)
     GemmArgs w2{};
@@ -336,7 +410,7 @@ hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, hipStream
     w2.b_rs = kMlpH;
     w2.b_cs = 1;
     w2.out_f32 = d.grad + kMlpW2Off;
-    hipError_t e = gemm<false, kAtomicF32>(w2, split, s);
+    hipError_t e = gemm<kAtomicF32>(w2, split, s);
     if (e != hipSuccess) return e;
     // dH1 = BF16((dH2 W2^T) * [H1 > 0])  (M = B, N = 256, K = 256)
     GemmArgs h1{};
@@ -352,13 +426,10 @@ hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, hipStream
     h1.b_cs = kMlpH;
     h1.mask = d.H1;
     h1.out_bf16 = d.dH1;
-    if ((e = gemm<false, kMaskBf16>(h1, 1, s)) != hipSuccess) return e;
+    if ((e = gemm<kMaskBf16>(h1, 1, s)) != hipSuccess) return e;
     // dW1 = X^T dH1  (M = 64, N = 256, K = B), X rounded to BF16 on staging
     GemmArgs w1{};
-    w1.A = X;
-    w1.a_shift = d.in_shift;
-    w1.a_scale = d.in_scale;
-    w1.shift_on_m = 1;
+    w1.A = d.Xb;                       // the forward pass's normalised BF16 inputs
     w1.B = d.dH1;
     w1.M = kMlpIn;
     w1.N = kMlpH;
@@ -369,7 +440,7 @@ hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, hipStream
     w1.b_rs = kMlpH;
     w1.b_cs = 1;
     w1.out_f32 = d.grad + kMlpW1Off;
-    if ((e = gemm<true, kAtomicF32>(w1, split, s)) != hipSuccess) return e;
+    if ((e = gemm<kAtomicF32>(w1, split, s)) != hipSuccess) return e;
     // b1 gradient: column sums of dH1 (b2's are summed in the head kernel)
     const unsigned cs_blocks = static_cast<unsigned>(std::min<int64_t>(std::max<int64_t>((B + 63) / 64, 1), 1024));
     hipLaunchKernelGGL(colsum_kernel, dim3(cs_blocks), dim3(256), 0, s, d.dH1, B, d.grad + kMlpB1Off);

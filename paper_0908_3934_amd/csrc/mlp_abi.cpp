@@ -33,7 +33,7 @@ hipError_t alloc(T** p, size_t n) {
 }
 
 void release(MlpDevice& d) {
-    void* ps[] = {d.params, d.adam_m, d.adam_v, d.grad,   d.w1b,  d.w2b,      d.H1,
+    void* ps[] = {d.params, d.adam_m, d.adam_v, d.grad, d.w1b,  d.w2b,  d.Xb,       d.H1,
                   d.H2,     d.dH1,    d.dH2,    d.logits, d.loss, d.in_shift, d.in_scale};
     for (void* p : ps)
         if (p) (void)hipFree(p);
@@ -51,6 +51,9 @@ net_status reserve(net_mlp* m, int64_t rows, hipStream_t s) {
         *b = nullptr;
         if (alloc(b, static_cast<size_t>(rows) * kMlpH) != hipSuccess) return mfail(NET_E_OOM, "net_mlp: workspace");
     }
+    if (m->d.Xb) (void)hipFree(m->d.Xb);
+    m->d.Xb = nullptr;
+    if (alloc(&m->d.Xb, static_cast<size_t>(rows) * kMlpIn) != hipSuccess) return mfail(NET_E_OOM, "net_mlp: workspace");
     if (m->d.logits) (void)hipFree(m->d.logits);
     m->d.logits = nullptr;
     if (alloc(&m->d.logits, static_cast<size_t>(rows)) != hipSuccess) return mfail(NET_E_OOM, "net_mlp: workspace");
