@@ -319,7 +319,7 @@ typedef struct {
     uint64_t fit_seed;      /* Philox key of the fit's own noise (never the data's) */
 } net_simfit_opts;
 
-enum { NET_EST_SCORER = 1, NET_EST_SIMFIT = 2 };
+enum { NET_EST_SCORER = 1, NET_EST_SIMFIT = 2, NET_EST_AUTO = 3 };
 
 /*
  * Scores of the candidate pairs (device [n_pairs] FP32; higher = more likely
@@ -339,6 +339,10 @@ enum { NET_EST_SCORER = 1, NET_EST_SIMFIT = 2 };
  *                   applies the one that raises the likelihood most, if by more
  *                   than min_gain.
  *                   Score = LL(G + e) - LL(G - e) at the final G.
+ *   NET_EST_AUTO    the scorer when `scorer` is given (the fast path, trained on
+ *                   simulated networks of the same kind), else the fit.
+ * Errors: NET_E_ARG for a bad descriptor, pair or option (message in
+ * net_estimate_last_error), NET_E_OOM, NET_E_DEVICE.
  * Waits for completion.
  */
 net_status net_estimate(const net_obs_desc* obs, int32_t method, net_mlp_t* scorer, const net_simfit_opts* opts,

@@ -95,6 +95,7 @@ class SimfitOpts(C.Structure):
 
 NET_EST_SCORER = 1
 NET_EST_SIMFIT = 2
+NET_EST_AUTO = 3
 
 ALLOC_FN = C.CFUNCTYPE(_vp, C.c_size_t, _vp, _vp)
 RELEASE_FN = C.CFUNCTYPE(None, _vp, _vp, _vp)

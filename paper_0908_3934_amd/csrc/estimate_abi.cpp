@@ -262,6 +262,7 @@ net_status net_estimate(const net_obs_desc* obs, int32_t method, net_mlp_t* scor
     if (!scores_dev && obs->n_pairs > 0) return efail(NET_E_ARG, "net_estimate: scores are NULL");
     if (obs->n_pairs == 0) return NET_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (method == NET_EST_AUTO) method = scorer ? NET_EST_SCORER : NET_EST_SIMFIT;
     if (method == NET_EST_SCORER) {
         if (!scorer) return efail(NET_E_ARG, "net_estimate: the scorer needs a trained MLP");
         DeviceScratch sc;

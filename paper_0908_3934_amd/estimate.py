@@ -161,6 +161,21 @@ def scorer_scores(o: Observed, scorer: "EdgeScorer", stream=None):
     return out
 
 
+def estimate(o: Observed, scorer: Optional["EdgeScorer"] = None, w_assumed: float = 0.0, stream=None, **fit_opts):
+    """net_estimate with NET_EST_AUTO: the learned scorer when one is given,
+    else the simulation-based fit (fit options as for simfit)."""
+    import torch
+    out = torch.empty(int(o.pairs.shape[0]), dtype=torch.float32, device=o.F.device)
+    keep = []
+    d = obs_desc(o, keep, w_assumed=w_assumed)
+    opts = _abi.SimfitOpts(fit_opts.get("realisations", 8), fit_opts.get("sweeps", 2),
+                           fit_opts.get("init_fraction", 0.3), fit_opts.get("min_gain", 1e-3),
+                           fit_opts.get("fit_seed", 0x5EEDF17))
+    _echeck(library().net_estimate(C.byref(d), _abi.NET_EST_AUTO, scorer.mlp.h if scorer is not None else None,
+                                   C.byref(opts), out.data_ptr(), _stream_handle(stream)), "net_estimate")
+    return out
+
+
 def auc(scores, labels) -> float:
     """Mann-Whitney area under the ROC curve, ties counted 1/2."""
     s = np.asarray(scores, dtype=np.float64)

@@ -89,3 +89,16 @@ def test_simfit_argument_errors():
     bad[0, 0] = bad[0, 1]
     with pytest.raises(gn.GeonetError):
         _gpu(spec, F, gamma, bad, dist, labels, w_assumed=synth.W0)                      # self pair
+
+
+def test_auto_method_dispatch():
+    """NET_EST_AUTO: the scorer's scores when a scorer is given, the fit's otherwise."""
+    import torch
+    from paper_0908_3934_amd import estimate as est
+    spec, F, gamma, pairs, dist, labels = _case(n_targets=3, seed=6)
+    ob = est.Observed(spec=spec, F=torch.tensor(F, device="cuda"), pairs=torch.tensor(pairs, device="cuda"),
+                      dist=torch.tensor(dist, device="cuda"), labels=labels, gain=1.0, offset=0.0, gamma=gamma)
+    sc = est.EdgeScorer(seed=1)
+    assert torch.equal(est.estimate(ob, scorer=sc), est.scorer_scores(ob, sc))
+    fit = dict(realisations=4, sweeps=1)
+    assert torch.equal(est.estimate(ob, w_assumed=synth.W0, **fit), est.simfit(ob, synth.W0, **fit))
