@@ -124,6 +124,9 @@ typedef struct {
 #define NET_BUILD_SUMMARY_HALF 256        /* delivery: one recent-spike summary bit per vertex pair
                                              (half the LDS, twice the workgroups per CU; more
                                              candidates, resolved exactly) */
+#define NET_BUILD_DELIVER_COMPACT 512    /* delivery: gather the candidate edges of each chunk
+                                             into an LDS stage and resolve them one per lane
+                                             (needs fewer than 2^24 vertices and room in LDS) */
 #define NET_BUILD_SINGLE_LAUNCH 32        /* one network: run all steps of a call in one launch of
                                              the LDS-resident kernel ensembles use, when the
                                              network fits one workgroup's LDS */

@@ -24,6 +24,7 @@ NET_BUILD_DELIVER_UNROLL2 = 16
 NET_BUILD_SINGLE_LAUNCH = 32
 NET_BUILD_DELIVER_PIPELINE = 128
 NET_BUILD_SUMMARY_HALF = 256
+NET_BUILD_DELIVER_COMPACT = 512
 NET_BUILD_AUTOTUNE = 64
 
 NET_OBS_V = 1

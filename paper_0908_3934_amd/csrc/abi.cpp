@@ -420,11 +420,13 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
                                 NET_BUILD_DELIVER_STREAM_WEIGHTS,
                                 NET_BUILD_SUMMARY_HALF,
                                 NET_BUILD_SUMMARY_HALF | NET_BUILD_DELIVER_PIPELINE,
-                                NET_BUILD_SUMMARY_HALF | NET_BUILD_DELIVER_UNROLL2};
+                                NET_BUILD_SUMMARY_HALF | NET_BUILD_DELIVER_UNROLL2,
+                                NET_BUILD_DELIVER_COMPACT,
+                                NET_BUILD_DELIVER_COMPACT | NET_BUILD_SUMMARY_HALF};
         net_build_opts o = opts ? *opts : net_build_opts{};
         const int keep = o.flags & ~(NET_BUILD_DELIVER_UNROLL2 | NET_BUILD_DELIVER_NONTEMPORAL |
                                      NET_BUILD_DELIVER_STREAM_WEIGHTS | NET_BUILD_DELIVER_PIPELINE |
-                                     NET_BUILD_SUMMARY_HALF);
+                                     NET_BUILD_SUMMARY_HALF | NET_BUILD_DELIVER_COMPACT);
         int best = -1;
         double best_ms = 0.0;
         for (int k = 0; k < static_cast<int>(sizeof(variants) / sizeof(variants[0])); ++k) {
@@ -587,6 +589,7 @@ net_status net_info(const net_t* h, net_info_t* out) {
     out->device_bytes = h->device_bytes;
     out->deliver_flags = (h->lc.mode == 1 ? NET_BUILD_DELIVER_UNROLL2 : 0) |
                          (h->lc.mode == 2 ? NET_BUILD_DELIVER_PIPELINE : 0) |
+                         (h->lc.mode == 3 ? NET_BUILD_DELIVER_COMPACT : 0) |
                          (h->lc.nontemporal ? NET_BUILD_DELIVER_NONTEMPORAL : 0) |
                          (h->lc.stream_weights ? NET_BUILD_DELIVER_STREAM_WEIGHTS : 0) |
                          (h->g.sum_shift ? NET_BUILD_SUMMARY_HALF : 0);

@@ -81,6 +81,7 @@ struct DeliverArgs {
     uint32_t n_pad;         // ring row length: word (slot/32, vertex) is at slot/32*n_pad + vertex
     uint32_t window;        // summary window W: bit set iff the vertex fired in the last W steps
     uint32_t sum_shift;     // summary bit of vertex s: s >> sum_shift (0, or 1: one bit per vertex pair)
+    int32_t stage_vec4;     // compacted mode: the per-wave candidate stages start here in LDS (16-byte units)
 };
 
 // One wave handles 512 consecutive slots per iteration: lane L owns slots
@@ -95,11 +96,10 @@ struct DeliverArgs {
 // the stream is 5 B per edge instead of 7.  kWStream = true streams the
 // weights with the chunk instead.
 //
-// Each iteration is a chain of dependent memory phases (edge stream, LDS
-// summary, history gathers), and the 128 KiB summary leaves room for one
-// workgroup per CU, so the loop is latency-bound.  kMode 2 pipelines it: the
-// next chunk's stream loads are issued right after this chunk's gathers.
-// kMode 1 handles two chunks per iteration instead; kMode 0 one.
+// Loop variants (same results): kMode 0 one chunk per wave iteration,
+// kMode 1 two, kMode 2 one with the next chunk's stream loads issued while
+// this chunk's gathers return, kMode 3 one with the candidates compacted
+// across the wave before they are resolved (compact_resolve).
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
@@ -181,6 +181,65 @@ __device__ __forceinline__ uint32_t fired_bits(const ChunkRegs& x, const Deliver
     return fired;
 }
 
+// Compacted resolution of one chunk (kMode 3).  The summary test marks the
+// candidates (~5 % of edges); instead of every lane resolving its 8 edges,
+// the wave writes its candidates (source | delay << 24) to its own LDS stage
+// at slots counted with one ballot per edge position, then resolves them 64
+// at a time, one candidate per lane (one age gather per lane, the ring read
+// for the rare three-spike case), and returns each arrival to the lane that
+// owns the edge through a ballot.  Sources must be below 2^24.
+template <bool kLdsSummary>
+__device__ __forceinline__ uint32_t compact_resolve(const ChunkRegs& x, const DeliverArgs& a,
+                                                    const uint32_t* lds_summary, uint32_t t, uint32_t* stage,
+                                                    int lane) {
+    const uint32_t sv[8] = {x.s_lo.x, x.s_lo.y, x.s_lo.z, x.s_lo.w, x.s_hi.x, x.s_hi.y, x.s_hi.z, x.s_hi.w};
+    uint32_t dv[8], cand = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t s = sv[k];
+        const uint32_t sb = s >> a.sum_shift;
+        const uint32_t sw = kLdsSummary ? lds_summary[sb >> 5] : a.summary[sb >> 5];
+        dv[k] = ((k < 4 ? x.dq.x : x.dq.y) >> (8 * (k & 3))) & 0xFFu;
+        cand |= (((sw >> (sb & 31)) & 1u) | (dv[k] > a.window ? 1u : 0u)) << k;
+    }
+    uint32_t slot[8], total = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint64_t m = wave_ballot((cand >> k) & 1u);
+        slot[k] = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                            __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), total));
+        total += static_cast<uint32_t>(__builtin_popcountll(m));
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if ((cand >> k) & 1u) stage[slot[k]] = sv[k] | (dv[k] << 24);
+    uint32_t fired = 0;
+    for (uint32_t r = 0; r < total; r += 64) {
+        const uint32_t q = r + static_cast<uint32_t>(lane);
+        const bool valid = q < total;
+        const uint32_t e = valid ? stage[q] : 0u;
+        const uint32_t s = e & 0xFFFFFFu, d = e >> 24;
+        const uint32_t aw = a.ages[s];
+        const uint32_t a1 = aw & 0xFFu, a2 = aw >> 8;
+        bool f = valid && d < 255u && (d == a1 || d == a2);
+        const bool need = valid && !f && (d == 255u || d > a2);
+        if (wave_ballot(need)) {
+            const uint32_t sl = (t - d) & 0xFFu;
+            const uint32_t w = a.ring[need ? (sl >> 5) * a.n_pad + s : 0u];
+            f = f || (need && ((w >> (sl & 31u)) & 1u));
+        }
+        const uint64_t R = wave_ballot(f);
+        if (R != 0) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t p = slot[k] - r;
+                if (((cand >> k) & 1u) && p < 64u) fired |= static_cast<uint32_t>((R >> p) & 1u) << k;
+            }
+        }
+    }
+    return fired;
+}
+
 // Arrivals of one chunk (called by the whole wave when any lane has one).
 // Row of each fired slot from the row-start bits (position 0 of the chunk
 // belongs to chunk_row0 whether or not it opens a row), then one exact FP32
@@ -235,7 +294,15 @@ __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
     }
 
     int64_t c = c_begin + static_cast<int64_t>(wave) * kPer;
-    if (kMode == 2) {
+    if (kMode == 3) {
+        uint32_t* stage = reinterpret_cast<uint32_t*>(lds_summary4 + a.stage_vec4) + wave * kChunkEdges;
+        for (; c < c_end; c += stride) {
+            ChunkRegs cur;
+            load_chunk<kWStream, kNT>(cur, a, c, lane);
+            const uint32_t fired = compact_resolve<kLdsSummary>(cur, a, lds_summary, t, stage, lane);
+            if (wave_ballot(fired != 0)) deliver_fired<kWStream>(a, c, lane, fired, cur.wq);
+        }
+    } else if (kMode == 2) {
         ChunkRegs cur;
         if (c < c_end) load_chunk<kWStream, kNT>(cur, a, c, lane);
         for (; c < c_end; c += stride) {
@@ -710,34 +777,46 @@ hipError_t configure_deliver(DeviceGraph& g, const net_build_opts* opts, LaunchC
     const size_t summary_bytes = static_cast<size_t>(g.n_pad / 8) >> g.sum_shift;
     const bool want_lds = !(flags & NET_BUILD_NO_LDS_SUMMARY);
     lc.lds_summary = want_lds && summary_bytes <= static_cast<size_t>(lds_max);
-    lc.lds_bytes = lc.lds_summary ? summary_bytes : 0;
     lc.stream_weights = (flags & NET_BUILD_DELIVER_STREAM_WEIGHTS) != 0;
     lc.nontemporal = (flags & NET_BUILD_DELIVER_NONTEMPORAL) != 0;
     lc.mode = (flags & NET_BUILD_DELIVER_UNROLL2) ? 1 : ((flags & NET_BUILD_DELIVER_PIPELINE) ? 2 : 0);
-    if (lc.lds_summary) {
+    if ((flags & NET_BUILD_DELIVER_COMPACT) && g.n_pad <= (int64_t(1) << 24)) lc.mode = 3;
+    // Workgroups per CU limited by the summary (and, compacted, the per-wave
+    // candidate stages) held in LDS (160 KiB per CU).
+    int threads = 1024, per_cu = 8;
+    if (opts && opts->block_threads) threads = opts->block_threads;
+    const size_t stage_per_wave = static_cast<size_t>(kChunkEdges) * sizeof(uint32_t);
+    auto lds_need = [&](int thr) {
+        return (lc.lds_summary ? summary_bytes : 0) +
+               (lc.mode == 3 ? static_cast<size_t>(thr / 64) * stage_per_wave : 0);
+    };
+    if (lc.mode == 3 && lds_need(threads) > static_cast<size_t>(lds_max)) lc.mode = 1;   // stages do not fit
+    lc.lds_bytes = lds_need(threads);
+    if (lc.lds_bytes > 0) {
+        per_cu = static_cast<int>((160 * 1024) / lc.lds_bytes);
+        per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
+    }
+    if (!(opts && opts->block_threads)) {
+        // up to 32 waves per CU: 1024 threads for one or two workgroups per CU
+        threads = per_cu <= 2 ? 1024 : (per_cu <= 4 ? 512 : 256);
+        lc.lds_bytes = lds_need(threads);
+    }
+    if (opts && opts->blocks_per_cu) per_cu = opts->blocks_per_cu;
+    if (lc.lds_bytes > 0) {
         const void* fns[] = {
-#define GEONET_DELIVER_FN(W, N, M) reinterpret_cast<const void*>(&deliver_kernel<true, W, N, M>),
-#define GEONET_DELIVER_FNS(M) GEONET_DELIVER_FN(false, false, M) GEONET_DELIVER_FN(false, true, M) \
-                              GEONET_DELIVER_FN(true, false, M) GEONET_DELIVER_FN(true, true, M)
-            GEONET_DELIVER_FNS(0) GEONET_DELIVER_FNS(1) GEONET_DELIVER_FNS(2)
+#define GEONET_DELIVER_FN(L, W, N, M) reinterpret_cast<const void*>(&deliver_kernel<L, W, N, M>),
+#define GEONET_DELIVER_FNS(L, M) GEONET_DELIVER_FN(L, false, false, M) GEONET_DELIVER_FN(L, false, true, M) \
+                                 GEONET_DELIVER_FN(L, true, false, M) GEONET_DELIVER_FN(L, true, true, M)
+            GEONET_DELIVER_FNS(true, 0) GEONET_DELIVER_FNS(true, 1) GEONET_DELIVER_FNS(true, 2)
+            GEONET_DELIVER_FNS(true, 3) GEONET_DELIVER_FNS(false, 3)
 #undef GEONET_DELIVER_FNS
 #undef GEONET_DELIVER_FN
         };
         for (const void* f : fns) {
-            e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(summary_bytes));
+            e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lc.lds_bytes));
             if (e != hipSuccess) return e;
         }
     }
-    // Workgroups per CU limited by the summary held in LDS (160 KiB per CU).
-    int per_cu = 8;
-    if (lc.lds_summary && summary_bytes > 0) {
-        per_cu = static_cast<int>((160 * 1024) / summary_bytes);
-        per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
-    }
-    // up to 32 waves per CU: 1024 threads for one or two workgroups per CU
-    int threads = per_cu <= 2 ? 1024 : (per_cu <= 4 ? 512 : 256);
-    if (opts && opts->block_threads) threads = opts->block_threads;
-    if (opts && opts->blocks_per_cu) per_cu = opts->blocks_per_cu;
     int64_t blocks = static_cast<int64_t>(n_cu) * per_cu;
     const int64_t waves_needed = g.n_chunks;                 // at least one chunk per wave
     const int64_t max_blocks = (waves_needed + (threads / 64) - 1) / (threads / 64);
@@ -763,15 +842,17 @@ hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t 
     a.n_chunks = g.n_chunks;
     a.summary_vec4 = static_cast<int32_t>((g.n_pad >> g.sum_shift) / 128);
     a.sum_shift = static_cast<uint32_t>(g.sum_shift);
+    a.stage_vec4 = lc.lds_summary ? a.summary_vec4 : 0;
     a.t = static_cast<uint32_t>(t);
     a.n_pad = static_cast<uint32_t>(g.n_pad);
     a.window = static_cast<uint32_t>(g.d_sum);
     const dim3 grid(lc.deliver_blocks), block(lc.deliver_threads);
     const int v = lc.mode * 8 + (lc.lds_summary ? 4 : 0) + (lc.stream_weights ? 2 : 0) + (lc.nontemporal ? 1 : 0);
+    const size_t shared = lc.lds_bytes;
     switch (v) {
 #define GEONET_DELIVER_CASE(M, L, W, N)                                                            \
     case M * 8 + (L ? 4 : 0) + (W ? 2 : 0) + (N ? 1 : 0):                                          \
-        hipExtLaunchKernelGGL((deliver_kernel<L, W, N, M>), grid, block, L ? lc.lds_bytes : 0, s, ev0, ev1, 0, \
+        hipExtLaunchKernelGGL((deliver_kernel<L, W, N, M>), grid, block, shared, s, ev0, ev1, 0,          \
                               a);                                                                  \
         break;
 #define GEONET_DELIVER_CASES(M)              \
@@ -786,6 +867,7 @@ hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t 
         GEONET_DELIVER_CASES(0)
         GEONET_DELIVER_CASES(1)
         GEONET_DELIVER_CASES(2)
+        GEONET_DELIVER_CASES(3)
 #undef GEONET_DELIVER_CASES
 #undef GEONET_DELIVER_CASE
         default:

@@ -296,7 +296,7 @@ def test_autotuned_per_step_equals_default():
 
 
 @pytest.mark.parametrize("flags", ["DELIVER_STREAM_WEIGHTS", "DELIVER_UNROLL2", "DELIVER_NONTEMPORAL",
-                                   "DELIVER_PIPELINE", "SUMMARY_HALF"])
+                                   "DELIVER_PIPELINE", "SUMMARY_HALF", "DELIVER_COMPACT"])
 def test_delivery_variants_identical(flags):
     gn, torch = _gn()
     spec = synth.config1(n=8192)
