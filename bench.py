@@ -8,9 +8,13 @@ delayed-spike delivery over every edge, then the vertex update (drive,
 noise, Euler LIF, refractory hold, spike test, history ring).  Inputs are
 resident in HBM before timing starts.
 
-Prints one JSON line: edge-steps/s over the timed steps, the delivery
-kernel's roofline (algorithmic bytes / measured kernel time vs 8 TB/s) and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+By default a step is one fused kernel (each workgroup delivers into and
+then updates its own range of vertices); --deliver-flags selects the
+two-kernel variants.  Prints one JSON line: edge-steps/s over the timed
+steps, the dominant kernel's roofline (algorithmic bytes / its measured
+duration vs 8 TB/s) and the FP64 CPU oracle timed on a bounded sample of the
+same workload.  --workload selects the other measured rows (ensemble,
+estimate, mlp).
 """
 import argparse
 import json
@@ -24,28 +28,34 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_EDGE = 5      # int32 source + uint8 delay, streamed every step
 BYTES_PER_ARRIVAL = 2   # FP16 weight, loaded only when its edge delivers a spike
-BYTES_PER_EDGE_STREAMED_W = 7   # with --stream-weights: the weight is streamed with its edge
+BYTES_PER_EDGE_STREAMED_W = 7   # delivery variant that streams every weight with its edge
+# vertex update per step: V read + written (8), two-spike ages read + written
+# (4), history-ring word read + written (8), one summary bit (1/8)
+BYTES_PER_VERTEX_UPDATE = 20.125
 
 
 def measured_traffic(deliver_flags):
-    """HBM bytes per delivery launch from the committed rocprofv3 counter
-    summary, if it was taken on the kernel source as it is now and on the
-    same delivery variant (else None)."""
+    """HBM bytes per launch of the dominant kernel from a committed rocprofv3
+    counter summary under profiles/, if one was taken on the kernel source as
+    it is now and on the same delivery variant (else None)."""
+    import glob
     import hashlib
-    prof = os.path.join(ROOT, "profiles", "deliver_config2.md")
     src = os.path.join(ROOT, "paper_0908_3934_amd", "csrc", "kernels.hip")
     try:
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-        fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines()
-                      if line.startswith(("traffic_bytes_per_launch:", "kernels_hip_sha256_16:",
-                                          "deliver_flags:")))
-        if fields.get("kernels_hip_sha256_16", "").strip() != sha:
-            return None
-        if int(fields.get("deliver_flags", "-1")) != deliver_flags:
-            return None
-        return int(fields["traffic_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
+    except OSError:
         return None
+    for prof in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        try:
+            fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines()
+                          if line.startswith(("traffic_bytes_per_launch:", "kernels_hip_sha256_16:",
+                                              "deliver_flags:")))
+            if (fields.get("kernels_hip_sha256_16", "").strip() == sha
+                    and int(fields.get("deliver_flags", "-1")) == deliver_flags):
+                return int(fields["traffic_bytes_per_launch"])
+        except (OSError, KeyError, ValueError):
+            continue
+    return None
 
 
 def log(msg):
@@ -305,9 +315,10 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--deliver-flags", type=int, default=16,
-                    help="NET_BUILD_DELIVER_* bits of the delivery variant (default 16: two chunks per wave "
-                         "iteration, the fastest measured; 2 streams every weight, 7 B per edge)")
+    ap.add_argument("--deliver-flags", type=int, default=1024,
+                    help="NET_BUILD_* bits of the step variant (default 1024: one fused kernel per step, "
+                         "the fastest measured; 16: delivery and update kernels, two chunks per wave "
+                         "iteration; 2 streams every weight, 7 B per edge)")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library time the delivery variants at build instead of --deliver-flags")
     ap.add_argument("--workload", choices=["step", "ensemble", "estimate", "mlp"], default="step",
@@ -369,18 +380,25 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     tm = net.timing_end()
-    log("timed %d steps in %.3f s; kernels: deliver %.3f ms, update %.3f ms"
-        % (args.steps, wall, tm["deliver_ms"], tm["update_ms"]))
+    log("timed %d steps in %.3f s; kernels: deliver %.3f ms, update %.3f ms, fused step %.3f ms"
+        % (args.steps, wall, tm["deliver_ms"], tm["update_ms"], tm["step_ms"]))
 
     E = spec.n_edges
     value = E * args.steps / wall
-    avg_deliver_s = tm["deliver_ms"] / tm["deliver_launches"] / 1e3
+    fused = tm["step_launches"] > 0
+    kernel = "step_kernel" if fused else "deliver_kernel"
+    if fused:
+        avg_deliver_s = tm["step_ms"] / tm["step_launches"] / 1e3
+    else:
+        avg_deliver_s = tm["deliver_ms"] / tm["deliver_launches"] / 1e3
     arrivals = arrivals_per_step(net, spec, args.rate_steps)
     streamed_w = bool(info["deliver_flags"] & gn.NET_BUILD_DELIVER_STREAM_WEIGHTS)
     if streamed_w:
         alg_bytes = BYTES_PER_EDGE_STREAMED_W * E
     else:
         alg_bytes = BYTES_PER_EDGE * E + BYTES_PER_ARRIVAL * arrivals
+    if fused:
+        alg_bytes += BYTES_PER_VERTEX_UPDATE * spec.n
     achieved = alg_bytes / avg_deliver_s / 1e9
     log("arrivals per step %.0f (%.4f %% of edges); algorithmic bytes per launch %.0f"
         % (arrivals, 100.0 * arrivals / E, alg_bytes))
@@ -409,13 +427,13 @@ def main():
             "max_delay_steps": info["max_delay"],
             "deliver_flags": info["deliver_flags"],
             "real_time_factor": sim_s / wall,
-            "deliver_launch": "%d blocks x %d threads, summary in %s, variant flags %d%s" % (
+            "launch": "%d blocks x %d threads, summary in %s, variant flags %d%s" % (
                 info["deliver_blocks"], info["deliver_threads"], "LDS" if info["lds_summary"] else "global",
                 info["deliver_flags"], " (autotuned at build)" if info["autotuned"] else ""),
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "deliver_kernel",
+            "kernel": kernel,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -424,7 +442,7 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes,
             "arrivals_per_step": arrivals,
             "avg_launch_us": avg_deliver_s * 1e6,
-            "update_avg_launch_us": tm["update_ms"] / tm["update_launches"] * 1e3,
+            "update_avg_launch_us": (tm["update_ms"] / tm["update_launches"] * 1e3) if tm["update_launches"] else None,
         },
     }
     net.close()

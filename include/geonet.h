@@ -127,6 +127,11 @@ typedef struct {
 #define NET_BUILD_DELIVER_COMPACT 512    /* delivery: gather the candidate edges of each chunk
                                              into an LDS stage and resolve them one per lane
                                              (needs fewer than 2^24 vertices and room in LDS) */
+#define NET_BUILD_FUSED_STEP 1024        /* one network: one kernel per step, each workgroup
+                                             delivering into and then updating its own range of
+                                             vertices (the slot list is cut into one segment per
+                                             CU; needs room for the summary and a segment's inputs
+                                             in LDS, else the two kernels are used) */
 #define NET_BUILD_SINGLE_LAUNCH 32        /* one network: run all steps of a call in one launch of
                                              the LDS-resident kernel ensembles use, when the
                                              network fits one workgroup's LDS */
@@ -232,6 +237,8 @@ typedef struct {
     double deliver_ms, update_ms, ensemble_ms;         /* summed kernel durations */
     int64_t deliver_launches, update_launches, ensemble_launches;
     int64_t steps;                                     /* steps covered by timed launches */
+    double step_ms;                                    /* fused step kernels (NET_BUILD_FUSED_STEP) */
+    int64_t step_launches;
 } net_timing_t;
 
 net_status net_timing_begin(net_t* h, int64_t max_launches);

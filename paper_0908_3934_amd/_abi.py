@@ -25,6 +25,7 @@ NET_BUILD_SINGLE_LAUNCH = 32
 NET_BUILD_DELIVER_PIPELINE = 128
 NET_BUILD_SUMMARY_HALF = 256
 NET_BUILD_DELIVER_COMPACT = 512
+NET_BUILD_FUSED_STEP = 1024
 NET_BUILD_AUTOTUNE = 64
 
 NET_OBS_V = 1
@@ -71,7 +72,8 @@ class Info(C.Structure):
 class Timing(C.Structure):
     _fields_ = [("deliver_ms", C.c_double), ("update_ms", C.c_double), ("ensemble_ms", C.c_double),
                 ("deliver_launches", C.c_int64), ("update_launches", C.c_int64),
-                ("ensemble_launches", C.c_int64), ("steps", C.c_int64)]
+                ("ensemble_launches", C.c_int64), ("steps", C.c_int64), ("step_ms", C.c_double),
+                ("step_launches", C.c_int64)]
 
 
 class FluorParams(C.Structure):

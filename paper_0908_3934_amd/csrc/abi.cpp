@@ -26,7 +26,7 @@ struct net {
     void (*release)(void*, void*, void*) = nullptr;
     void* alloc_ctx = nullptr;
     hipStream_t last_stream = nullptr;
-    // kernel timing: events [2 * launch] = start/end; kind 0 deliver, 1 update, 2 ensemble
+    // kernel timing: events [2 * launch] = start/end; kind 0 deliver, 1 update, 2 ensemble, 3 fused step
     std::vector<hipEvent_t> tev;
     std::vector<int32_t> tkind;
     std::vector<int64_t> tsteps;
@@ -200,6 +200,8 @@ net_status reset_state(net* h, const HostGraph& hg, hipStream_t s) {
     if (e == hipSuccess) e = hipMemsetAsync(g.I, 0, np * sizeof(float), s);
     if (e == hipSuccess) e = hipMemsetAsync(g.ring, 0, np * kRingWords * sizeof(uint32_t), s);
     if (e == hipSuccess) e = hipMemsetAsync(g.summary, 0, np / 32 * sizeof(uint32_t), s);
+    if (e == hipSuccess && g.age_alt) e = hipMemsetAsync(g.age_alt, kAgeNever, np * sizeof(uint16_t), s);
+    if (e == hipSuccess && g.summary_alt) e = hipMemsetAsync(g.summary_alt, 0, np / 32 * sizeof(uint32_t), s);
     if (e == hipSuccess && g.calcium) e = hipMemsetAsync(g.calcium, 0, np * sizeof(double), s);
     if (e == hipSuccess && g.frame_acc) e = hipMemsetAsync(g.frame_acc, 0, np * sizeof(double), s);
     if (e == hipSuccess && g.frames)
@@ -267,7 +269,23 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
         return fail(NET_E_ARG, "net_build: invalid options");
     HostGraph hg;
     std::string err;
-    net_status st = build_host_graph(descs, n_nets, hg, err);
+    // fused step: one segment per CU, sized to fit next to the summary in LDS
+    int32_t seg_count = 0, seg_cap = 0;
+    if (opts && (opts->flags & NET_BUILD_FUSED_STEP) && n_nets == 1 && descs && descs[0].n_nodes > 0) {
+        int dev = 0, n_cu = 0, lds_max = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess) {
+            const int64_t n_pad = (static_cast<int64_t>(descs[0].n_nodes) + kNodeAlign - 1) / kNodeAlign * kNodeAlign;
+            const int64_t summary = (n_pad / 8) >> ((opts->flags & NET_BUILD_SUMMARY_HALF) ? 1 : 0);
+            const int64_t room = (static_cast<int64_t>(lds_max) - summary) / 4;
+            if (room >= 64) {
+                seg_count = n_cu;
+                seg_cap = static_cast<int32_t>(std::min<int64_t>(room, int64_t(1) << 30));
+            }
+        }
+    }
+    net_status st = build_host_graph(descs, n_nets, hg, err, seg_count, seg_cap);
     if (st != NET_OK) return fail(st, err);
 
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -345,6 +363,17 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
         if ((st = zeros(h, &g.frame_acc, np, s, "frame accumulator")) != NET_OK) return bail(st);
         if ((st = zeros(h, &g.frames, np * static_cast<size_t>(frame_cap), s, "frames")) != NET_OK) return bail(st);
     }
+    if (!hg.seg_vertex.empty()) {
+        int32_t *sv = nullptr, *sc = nullptr;
+        if ((st = upload(h, &sv, hg.seg_vertex, hg.seg_vertex.size(), s, "segments")) != NET_OK) return bail(st);
+        if ((st = upload(h, &sc, hg.seg_chunk, hg.seg_chunk.size(), s, "segments")) != NET_OK) return bail(st);
+        if ((st = zeros(h, &g.age_alt, np, s, "ages", kAgeNever)) != NET_OK) return bail(st);
+        if ((st = zeros(h, &g.summary_alt, np / 32, s, "summary")) != NET_OK) return bail(st);
+        g.seg_vertex = sv;
+        g.seg_chunk = sc;
+        g.n_seg = static_cast<int32_t>(hg.seg_vertex.size()) - 1;
+        g.seg_max = hg.seg_max;
+    }
     hipError_t e = configure_deliver(g, opts, h->lc);
     if (e != hipSuccess) {
         device_fail(h, e, "net_build: configure");
@@ -411,7 +440,7 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
             }
         }
     }
-    if (autotune && !h->plan.enabled) {
+    if (autotune && !h->plan.enabled && !h->lc.fused) {
         // delivery variants of the per-step kernels (identical results)
         const int variants[] = {0,
                                 NET_BUILD_DELIVER_PIPELINE,
@@ -511,9 +540,11 @@ net_status net_step_n(net_t* h, int64_t n_steps, const net_record* rec, void* st
     for (int64_t k = 0; k < n_steps; ++k) {
         const int64_t t = h->t + k;
         hipEvent_t d0, d1, u0, u1;
-        next_events(h, 0, 1, &d0, &d1);
-        hipError_t e = launch_deliver(h->g, h->lc, t, s, d0, d1);
-        if (e != hipSuccess) return device_fail(h, e, "net_step_n: delivery launch");
+        next_events(h, h->lc.fused ? 3 : 0, 1, &d0, &d1);
+        if (!h->lc.fused) {
+            hipError_t e = launch_deliver(h->g, h->lc, t, s, d0, d1);
+            if (e != hipSuccess) return device_fail(h, e, "net_step_n: delivery launch");
+        }
         int32_t flush = 0, steps = 0;
         int64_t frame = 0;
         if (observe) {
@@ -527,8 +558,15 @@ net_status net_step_n(net_t* h, int64_t n_steps, const net_record* rec, void* st
                 h->frames_done = std::max(h->frames_done, frame + 1);
             }
         }
+        if (h->lc.fused) {
+            hipError_t e = launch_step(h->g, h->lc, t, k, rec, flush, frame, steps, s, d0, d1);
+            if (e != hipSuccess) return device_fail(h, e, "net_step_n: step launch");
+            std::swap(h->g.age, h->g.age_alt);          // the step wrote the next ages and summary
+            std::swap(h->g.summary, h->g.summary_alt);
+            continue;
+        }
         next_events(h, 1, 0, &u0, &u1);
-        e = launch_node_update(h->g, t, k, rec, flush, frame, steps, s, u0, u1);
+        hipError_t e = launch_node_update(h->g, t, k, rec, flush, frame, steps, s, u0, u1);
         if (e != hipSuccess) return device_fail(h, e, "net_step_n: update launch");
     }
     h->t += n_steps;
@@ -590,6 +628,7 @@ net_status net_info(const net_t* h, net_info_t* out) {
     out->deliver_flags = (h->lc.mode == 1 ? NET_BUILD_DELIVER_UNROLL2 : 0) |
                          (h->lc.mode == 2 ? NET_BUILD_DELIVER_PIPELINE : 0) |
                          (h->lc.mode == 3 ? NET_BUILD_DELIVER_COMPACT : 0) |
+                         (h->lc.fused ? NET_BUILD_FUSED_STEP : 0) |
                          (h->lc.nontemporal ? NET_BUILD_DELIVER_NONTEMPORAL : 0) |
                          (h->lc.stream_weights ? NET_BUILD_DELIVER_STREAM_WEIGHTS : 0) |
                          (h->g.sum_shift ? NET_BUILD_SUMMARY_HALF : 0);
@@ -633,6 +672,7 @@ net_status net_timing_end(net_t* h, net_timing_t* out) {
         if (r != hipSuccess) return device_fail(h, r, "net_timing_end");
         switch (h->tkind[k]) {
             case 0: out->deliver_ms += ms; out->deliver_launches++; break;
+            case 3: out->step_ms += ms; out->step_launches++; break;
             case 1: out->update_ms += ms; out->update_launches++; break;
             default: out->ensemble_ms += ms; out->ensemble_launches++; break;
         }

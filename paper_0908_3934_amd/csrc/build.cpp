@@ -63,7 +63,8 @@ uint32_t pulse_threshold(double rate_hz, double dt_ms) {
     return static_cast<uint32_t>(thr);
 }
 
-net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g, std::string& err) {
+net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g, std::string& err, int32_t seg_count,
+                            int32_t seg_cap) {
     if (!descs || n_nets < 1) {
         err = "net_build: descs must hold n_nets >= 1 networks";
         return NET_E_ARG;
@@ -139,6 +140,43 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
     // network's slot range starts on a chunk boundary, so a chunk never mixes
     // networks (the ensemble kernel walks each network's chunks on its own).
     std::vector<int64_t> row_ptr(N + 1, 0);   // row_ptr[r] = first slot of row r
+    // Segments (fused step): balance slots plus a per-vertex update cost,
+    // cut only at multiples of 64 vertices, at most seg_cap vertices each.
+    std::vector<char> seg_start(N + 1, 0);
+    g.seg_vertex.clear();
+    g.seg_chunk.clear();
+    g.seg_max = 0;
+    if (seg_count > 0 && n_nets == 1 && seg_cap >= 64) {
+        const int64_t kVertexCost = 16;
+        int64_t total = 0;
+        for (int64_t r = 0; r < N; ++r) total += std::max<int64_t>(indeg[r], 1) + kVertexCost;
+        const int64_t cap = seg_cap / 64 * 64;
+        std::vector<int32_t> starts{0};
+        int64_t acc = 0, begin = 0;
+        for (int64_t r = 0; r < N; ++r) {
+            acc += std::max<int64_t>(indeg[r], 1) + kVertexCost;
+            const int64_t next = r + 1;
+            if (next % 64 != 0 || next == N) continue;
+            const int64_t k = static_cast<int64_t>(starts.size());
+            if (acc * seg_count >= total * k || next - begin >= cap) {
+                starts.push_back(static_cast<int32_t>(next));
+                begin = next;
+            }
+        }
+        bool ok = static_cast<int32_t>(starts.size()) <= seg_count;
+        starts.push_back(static_cast<int32_t>(N));
+        for (size_t k = 0; ok && k + 1 < starts.size(); ++k) {
+            const int32_t len = starts[k + 1] - starts[k];
+            ok = len <= cap;
+            g.seg_max = std::max(g.seg_max, len);
+        }
+        if (ok) {
+            g.seg_vertex = starts;
+            for (size_t k = 0; k + 1 < starts.size(); ++k) seg_start[starts[k]] = 1;
+        } else {
+            g.seg_max = 0;
+        }
+    }
     g.net_chunk_begin.assign(n_nets, 0);
     g.net_chunk_end.assign(n_nets, 0);
     int64_t used = 0;
@@ -146,6 +184,10 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
         if (n_nets > 1) used = (used + kChunkEdges - 1) / kChunkEdges * kChunkEdges;
         g.net_chunk_begin[m] = used / kChunkEdges;
         for (int64_t r = g.node_off[m]; r < g.node_off[m + 1]; ++r) {
+            if (seg_start[r]) {
+                used = (used + kChunkEdges - 1) / kChunkEdges * kChunkEdges;
+                g.seg_chunk.push_back(static_cast<int32_t>(used / kChunkEdges));
+            }
             row_ptr[r] = used;
             used += std::max<int64_t>(indeg[r], 1);
         }
@@ -159,6 +201,7 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
         return NET_E_RANGE;
     }
     g.n_chunks = g.e_slots / kChunkEdges;
+    if (!g.seg_vertex.empty()) g.seg_chunk.push_back(static_cast<int32_t>(g.n_chunks));
     // Every slot starts as a zero-weight placeholder owned by the preceding row
     // (its source is that row's own vertex, so it stays inside its network).
     g.src.assign(g.e_slots, 0);

@@ -54,6 +54,10 @@ struct HostGraph {
     std::vector<int32_t> chunk_row0;  // [n_chunks] row of each chunk's first slot
     std::vector<int64_t> node_off;    // [n_nets + 1]
     std::vector<int64_t> net_chunk_begin, net_chunk_end;  // [n_nets] chunk range of each network
+    // segments for the fused step (one workgroup each): first vertex (a
+    // multiple of 64) and first chunk of segment k at [k]; [n_seg] = end
+    std::vector<int32_t> seg_vertex, seg_chunk;
+    int32_t seg_max = 0;                                  // most vertices in one segment
     std::vector<int32_t> net_max_delay;                   // [n_nets]
     std::vector<NetParams> params;    // [n_nets]
     // per-vertex arrays [n_pad]
@@ -68,7 +72,12 @@ struct HostGraph {
 
 // Builds the CSR-by-target edge list and per-vertex arrays.  Returns a
 // status and fills `err` on failure.
-net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g, std::string& err);
+// seg_count > 0 (one network only): also cut the vertices into at most
+// seg_count segments of at most seg_cap vertices, each starting on a
+// 64-vertex boundary with its slots starting on a chunk boundary; leaves
+// seg_vertex empty if that is not possible.
+net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g, std::string& err,
+                            int32_t seg_count = 0, int32_t seg_cap = 0);
 
 // Device-side handle contents.
 struct DeviceGraph {
@@ -90,6 +99,13 @@ struct DeviceGraph {
     float* I;
     uint32_t* ring;               // [kRingWords][n_pad]: bit (s mod 32) of word (s mod 256)/32 = spike at step s
     uint32_t* summary;            // [n_pad / 32] words, of which (n_pad >> sum_shift) / 32 are used
+    // fused step: second buffers (the step reads age/summary and writes
+    // these; the host swaps them after each step) and the segments
+    uint16_t* age_alt = nullptr;
+    uint32_t* summary_alt = nullptr;
+    const int32_t* seg_vertex = nullptr;   // [n_seg + 1]
+    const int32_t* seg_chunk = nullptr;    // [n_seg + 1]
+    int32_t n_seg = 0, seg_max = 0;
     double* calcium;              // null when observation is off
     double* frame_acc;
     float* frames;                // [frame_cap][n_pad]
@@ -103,7 +119,8 @@ struct LaunchConfig {
     bool lds_summary = false;
     bool stream_weights = false;
     bool nontemporal = false;
-    int mode = 0;                  // delivery loop: 0 one chunk, 1 two chunks, 2 pipelined
+    int mode = 0;                  // delivery loop: 0 one chunk, 1 two chunks, 2 pipelined, 3 compacted
+    bool fused = false;            // one kernel per step (delivery + vertex update), see launch_step
     size_t lds_bytes = 0;
 };
 
@@ -130,6 +147,11 @@ hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t 
 hipError_t launch_node_update(const DeviceGraph& g, int64_t t, int64_t rec_row, const net_record* rec,
                               int32_t frame_flush, int64_t frame_index, int32_t frame_steps,
                               hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Fused step (lc.fused): delivery and vertex update of step t in one launch;
+// reads g.age / g.summary and writes g.age_alt / g.summary_alt (swap after).
+hipError_t launch_step(const DeviceGraph& g, const LaunchConfig& lc, int64_t t, int64_t rec_row, const net_record* rec,
+                       int32_t frame_flush, int64_t frame_index, int32_t frame_steps, hipStream_t s,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_observe(const DeviceGraph& g, int32_t what, const net_fluor_params* fp, void* out,
                           int64_t n_frames, hipStream_t s);
 hipError_t configure_deliver(DeviceGraph& g, const net_build_opts* opts, LaunchConfig& lc);   // sets g.sum_shift

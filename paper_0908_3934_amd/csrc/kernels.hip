@@ -338,7 +338,8 @@ __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
 
 struct NodeArgs {
     float* __restrict__ V;
-    uint16_t* __restrict__ age;
+    const uint16_t* __restrict__ age;    // ages read (step t)
+    uint16_t* __restrict__ age_out;      // ages written (for step t + 1); may equal age
     float* __restrict__ I;
     uint32_t* __restrict__ ring;
     uint32_t* __restrict__ summary;
@@ -358,25 +359,30 @@ struct NodeArgs {
     NetParams p0;
 };
 
+// Vertex update of step t for vertex j with delivered input `in` (all lanes
+// of a wave call it together, on 64 consecutive vertices starting at a
+// multiple of 64).  Vertices j >= j_end are not this caller's; the wave's
+// raster and summary words are written only when their first vertex is below
+// word_end.
 template <bool kMulti>
-__global__ void __launch_bounds__(256) node_update_kernel(NodeArgs a) {
-    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int64_t j_end, int64_t word_end, float in,
+                                              bool clear_input) {
     const int lane = threadIdx.x & 63;
-    const bool valid = j < a.n_total;
+    const bool valid = j < j_end;
     const int64_t jj = valid ? j : 0;
     const NetParams p = kMulti ? a.params[a.net_id[jj]] : a.p0;
     const float v = a.V[jj];
     const uint32_t ages = a.age[jj];
     const uint32_t age = ages & 0xFFu, age2 = ages >> 8;
-    const float in = a.I[jj];
     const bool spike = valid && v >= p.v_th;
 
     const uint64_t spikes = wave_ballot(spike);
-    if (a.rec_raster && lane == 0 && j < a.n_total) a.rec_raster[a.rec_row * a.raster_words + (j >> 6)] = spikes;
+    if (a.rec_raster && lane == 0 && j < word_end && j < a.n_total)
+        a.rec_raster[a.rec_row * a.raster_words + (j >> 6)] = spikes;
     if (valid) {
         if (a.rec_v) a.rec_v[a.rec_row * a.n_total + j] = v;
         if (a.rec_input) a.rec_input[a.rec_row * a.n_total + j] = in;
-        a.I[j] = 0.0f;
+        if (clear_input) a.I[j] = 0.0f;
         // spike-history ring: bit (t mod 256) of vertex j
         const uint32_t slot = a.t_lo & 0xFFu;
         uint32_t* wp = a.ring + (slot >> 5) * a.n_pad + j;
@@ -409,7 +415,7 @@ __global__ void __launch_bounds__(256) node_update_kernel(NodeArgs a) {
     }
     // recent-spike summary for the next step: last spike within d_sum steps
     const uint64_t recent = wave_ballot(valid && age_n <= static_cast<uint32_t>(a.d_sum));
-    if (lane == 0 && j < a.n_pad) {
+    if (lane == 0 && j < word_end) {
         if (a.sum_shift == 0) {
             reinterpret_cast<uint64_t*>(a.summary)[j >> 6] = recent;
         } else {
@@ -429,7 +435,7 @@ __global__ void __launch_bounds__(256) node_update_kernel(NodeArgs a) {
         // the previous last spike becomes the one before the last
         const uint32_t older = spike ? age : age2;
         const uint32_t age2_n = older >= static_cast<uint32_t>(kAgeNever) ? kAgeNever : older + 1u;
-        a.age[j] = static_cast<uint16_t>(age_n | (age2_n << 8));
+        a.age_out[j] = static_cast<uint16_t>(age_n | (age2_n << 8));
         if (a.calcium) {
             // calcium and its frame sum in FP64: tau_c / dt is thousands of steps
             const double c = a.calcium[j];
@@ -443,6 +449,13 @@ __global__ void __launch_bounds__(256) node_update_kernel(NodeArgs a) {
             a.calcium[j] = c + p.dt_d * (-c / p.tau_c_d + (spike ? 1.0 : 0.0));
         }
     }
+}
+
+template <bool kMulti>
+__global__ void __launch_bounds__(256) node_update_kernel(NodeArgs a) {
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const float in = a.I[j < a.n_total ? j : 0];
+    vertex_update<kMulti>(a, j, a.n_total, a.n_pad, in, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -763,6 +776,83 @@ __global__ void __launch_bounds__(256) observe_kernel(ObserveArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fused step: one workgroup per segment (a 64-aligned vertex range whose
+// slots start on a chunk boundary, so the workgroup owns whole rows).  The
+// workgroup delivers its chunks into an input array in LDS (two chunks per
+// wave iteration, as deliver_kernel), waits for its own waves, then updates
+// its vertices.  Other workgroups still read this step's ages and summary as
+// sources, so the update writes the next step's copies (age_out, summary);
+// the ring is written in place: step t sets only bit t, which no delivery of
+// step t reads (delays are >= 1).
+// ---------------------------------------------------------------------------
+struct StepArgs {
+    DeliverArgs d;
+    NodeArgs n;
+    const int32_t* seg_vertex;
+    const int32_t* seg_chunk;
+};
+
+__device__ __forceinline__ void deliver_fired_lds(const DeliverArgs& a, int64_t c, int lane, uint32_t fired,
+                                                  float* lds_in, int32_t v0) {
+    const int64_t e0 = c * kChunkEdges + lane * kEdgesPerLane;
+    const uint32_t rs = a.rowstart[c * 64 + lane];
+    const int32_t first_row = a.chunk_row0[c];
+    u32x4 wq = u32x4{0u, 0u, 0u, 0u};
+    if (fired) wq = *reinterpret_cast<const u32x4*>(a.w + e0);
+    const uint32_t bits = lane == 0 ? (rs & ~1u) : rs;
+    const int32_t row0 = first_row + static_cast<int32_t>(wave_bits_before(bits)) - v0;
+    const uint32_t wv[4] = {wq.x, wq.y, wq.z, wq.w};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if ((fired >> k) & 1u) {
+            const int32_t row = row0 + __popc(bits & ((2u << k) - 1u));
+            atomicAdd(lds_in + row, half_bits_to_float((wv[k >> 1] >> (16 * (k & 1))) & 0xFFFFu));
+        }
+    }
+}
+
+__global__ void __launch_bounds__(1024) step_kernel(StepArgs s) {
+    extern __shared__ uint4 lds4[];
+    const uint32_t* lds_summary = reinterpret_cast<const uint32_t*>(lds4);
+    float* lds_in = reinterpret_cast<float*>(lds4 + s.d.summary_vec4);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nwaves = blockDim.x >> 6;
+    const int nb = gridDim.x;
+    const int b = blockIdx.x;
+    const int lb = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+    const int32_t v0 = s.seg_vertex[lb], v1 = s.seg_vertex[lb + 1];
+    const int64_t c_begin = s.seg_chunk[lb], c_end = s.seg_chunk[lb + 1];
+    const uint32_t t = s.d.t;
+    const uint4* g = reinterpret_cast<const uint4*>(s.d.summary);
+    for (int i = threadIdx.x; i < s.d.summary_vec4; i += blockDim.x) lds4[i] = g[i];
+    for (int i = threadIdx.x; i < v1 - v0; i += blockDim.x) lds_in[i] = 0.0f;
+    __syncthreads();
+
+    const int64_t stride = static_cast<int64_t>(nwaves) * 2;
+    for (int64_t c = c_begin + static_cast<int64_t>(wave) * 2; c < c_end; c += stride) {
+        ChunkRegs cur[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) load_chunk<false, false>(cur[u], s.d, c + u < c_end ? c + u : c_end - 1, lane);
+        uint32_t aw[2][8], cand[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) gather_chunk<true>(cur[u], s.d, lds_summary, aw[u], &cand[u]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            uint32_t fired = fired_bits(cur[u], s.d, t, aw[u], cand[u]);
+            if (c + u >= c_end) fired = 0;
+            if (wave_ballot(fired != 0)) deliver_fired_lds(s.d, c + u, lane, fired, lds_in, v0);
+        }
+    }
+    __syncthreads();
+    for (int64_t base = v0; base < v1; base += blockDim.x) {
+        const int64_t j = base + threadIdx.x;
+        const float in = j < v1 ? lds_in[j - v0] : 0.0f;
+        vertex_update<false>(s.n, j, v1, v1, in, false);
+    }
+}
+
 }  // namespace
 
 hipError_t configure_deliver(DeviceGraph& g, const net_build_opts* opts, LaunchConfig& lc) {
@@ -824,11 +914,28 @@ hipError_t configure_deliver(DeviceGraph& g, const net_build_opts* opts, LaunchC
     if (blocks >= 8) blocks = blocks / 8 * 8;
     lc.deliver_blocks = static_cast<int>(blocks);
     lc.deliver_threads = threads;
+    // Fused step: one 1024-thread workgroup per segment, the summary and the
+    // segment's inputs in LDS.
+    lc.fused = false;
+    if ((flags & NET_BUILD_FUSED_STEP) && g.seg_vertex && g.n_seg > 0 && lc.lds_summary) {
+        const size_t need = summary_bytes + (static_cast<size_t>(g.seg_max) * sizeof(float) + 15) / 16 * 16;
+        if (need <= static_cast<size_t>(lds_max)) {
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&step_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    static_cast<int>(need));
+            if (e != hipSuccess) return e;
+            lc.fused = true;
+            lc.mode = 1;
+            lc.stream_weights = false;
+            lc.nontemporal = false;
+            lc.lds_bytes = need;
+            lc.deliver_threads = 1024;
+            lc.deliver_blocks = g.n_seg;
+        }
+    }
     return hipSuccess;
 }
 
-hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t t, hipStream_t s, hipEvent_t ev0,
-                          hipEvent_t ev1) {
+static DeliverArgs deliver_args(const DeviceGraph& g, const LaunchConfig& lc, int64_t t) {
     DeliverArgs a;
     a.src = g.src;
     a.w = g.w;
@@ -846,6 +953,12 @@ hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t 
     a.t = static_cast<uint32_t>(t);
     a.n_pad = static_cast<uint32_t>(g.n_pad);
     a.window = static_cast<uint32_t>(g.d_sum);
+    return a;
+}
+
+hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t t, hipStream_t s, hipEvent_t ev0,
+                          hipEvent_t ev1) {
+    const DeliverArgs a = deliver_args(g, lc, t);
     const dim3 grid(lc.deliver_blocks), block(lc.deliver_threads);
     const int v = lc.mode * 8 + (lc.lds_summary ? 4 : 0) + (lc.stream_weights ? 2 : 0) + (lc.nontemporal ? 1 : 0);
     const size_t shared = lc.lds_bytes;
@@ -876,12 +989,12 @@ hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_node_update(const DeviceGraph& g, int64_t t, int64_t rec_row, const net_record* rec,
-                              int32_t frame_flush, int64_t frame_index, int32_t frame_steps, hipStream_t s,
-                              hipEvent_t ev0, hipEvent_t ev1) {
+static NodeArgs node_args(const DeviceGraph& g, int64_t t, int64_t rec_row, const net_record* rec,
+                          int32_t frame_flush, int64_t frame_index, int32_t frame_steps) {
     NodeArgs a;
     a.V = g.V;
     a.age = g.age;
+    a.age_out = g.age;
     a.I = g.I;
     a.ring = g.ring;
     a.summary = g.summary;
@@ -908,6 +1021,13 @@ hipError_t launch_node_update(const DeviceGraph& g, int64_t t, int64_t rec_row, 
     a.frame_steps = frame_steps;
     a.frame_cap = g.frame_cap;
     a.p0 = g.p0;
+    return a;
+}
+
+hipError_t launch_node_update(const DeviceGraph& g, int64_t t, int64_t rec_row, const net_record* rec,
+                              int32_t frame_flush, int64_t frame_index, int32_t frame_steps, hipStream_t s,
+                              hipEvent_t ev0, hipEvent_t ev1) {
+    const NodeArgs a = node_args(g, t, rec_row, rec, frame_flush, frame_index, frame_steps);
     const int threads = 256;
     const int64_t blocks = g.n_pad / threads + ((g.n_pad % threads) ? 1 : 0);
     if (g.n_nets > 1)
@@ -985,6 +1105,22 @@ hipError_t launch_ensemble(const DeviceGraph& g, const EnsemblePlan& plan, int64
 hipError_t enable_ensemble_lds(size_t bytes) {
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&ensemble_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+}
+
+hipError_t launch_step(const DeviceGraph& g, const LaunchConfig& lc, int64_t t, int64_t rec_row, const net_record* rec,
+                       int32_t frame_flush, int64_t frame_index, int32_t frame_steps, hipStream_t s,
+                       hipEvent_t ev0, hipEvent_t ev1) {
+    if (!lc.fused || !g.seg_vertex || !g.age_alt || !g.summary_alt) return hipErrorInvalidValue;
+    StepArgs a;
+    a.d = deliver_args(g, lc, t);
+    a.n = node_args(g, t, rec_row, rec, frame_flush, frame_index, frame_steps);
+    a.n.age_out = g.age_alt;
+    a.n.summary = g.summary_alt;
+    a.n.I = nullptr;
+    a.seg_vertex = g.seg_vertex;
+    a.seg_chunk = g.seg_chunk;
+    hipExtLaunchKernelGGL(step_kernel, dim3(g.n_seg), dim3(lc.deliver_threads), lc.lds_bytes, s, ev0, ev1, 0, a);
+    return hipGetLastError();
 }
 
 }  // namespace geonet

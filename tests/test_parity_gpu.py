@@ -306,3 +306,34 @@ def test_delivery_variants_identical(flags):
     assert b["net"].info()["deliver_flags"] == getattr(gn, "NET_BUILD_" + flags)
     for key in ("raster", "v", "input"):
         assert np.array_equal(a[key], b[key]), key
+
+
+@pytest.mark.parametrize("n,T", [(8192 + 37, 600), (65536, 300)])
+def test_fused_step_equals_two_kernels(n, T):
+    """One kernel per step (delivery into LDS, then the workgroup's own
+    vertices) gives the same bits as the delivery + update kernels, records
+    included; a ragged vertex count exercises the last segment."""
+    gn, torch = _gn()
+    spec = synth.config1(n=n)
+    a = run_gpu(spec, T)
+    b = run_gpu(spec, T, flags=gn.NET_BUILD_FUSED_STEP)
+    inf = b["net"].info()
+    assert inf["deliver_flags"] & gn.NET_BUILD_FUSED_STEP and inf["t"] == T
+    for key in ("raster", "v", "input"):
+        assert np.array_equal(a[key], b[key]), key
+    ra = a["net"].observe(gn.NET_OBS_REF).cpu().numpy()
+    rb = b["net"].observe(gn.NET_OBS_REF).cpu().numpy()
+    assert np.array_equal(ra, rb)
+
+
+def test_fused_step_with_observation():
+    gn, torch = _gn()
+    spec = synth.config0_like(4096, synth.config_seed(4, 3), w0=0.36)
+    spec.noise_sigma = 0.05
+    outs = []
+    for flags in (0, gn.NET_BUILD_FUSED_STEP):
+        net = gn.Net(spec, frame_capacity=8, flags=flags)
+        net.step(2100)
+        nf = net.info()["frames_done"]
+        outs.append(net.observe(gn.NET_OBS_FRAMES, frames=nf).cpu().numpy())
+    assert outs[0].shape[0] == 6 and np.array_equal(outs[0], outs[1])
