@@ -263,7 +263,7 @@ def bench_estimate(args, torch, synth):
         s_sc = est.scorer_scores(o, sc)
         torch.cuda.synchronize()
         b = time.perf_counter()
-        s_sf = est.simfit(o, w_assumed=synth.W0, realisations=8, sweeps=2)
+        s_sf = est.simfit(o, w_assumed=synth.W0, realisations=args.fit_realisations, sweeps=args.fit_sweeps)
         torch.cuda.synchronize()
         c = time.perf_counter()
         t_sc += b - a
@@ -300,7 +300,7 @@ def bench_estimate(args, torch, synth):
             "positive_fraction": float(Y.mean()),
         },
         "scorer": {"auc": auc_sc, "wall_s": t_sc, "train_s": fit_s, "epochs": args.epochs},
-        "simfit": {"auc": auc_sf, "wall_s": t_sf, "realisations": 8, "sweeps": 2},
+        "simfit": {"auc": auc_sf, "wall_s": t_sf, "realisations": args.fit_realisations, "sweeps": args.fit_sweeps},
         "correlation_baseline_auc": auc_c,
         "auc_gap": auc_sf - auc_sc,
         "wall_ratio_simfit_over_scorer": t_sf / max(t_sc, 1e-12),
@@ -330,6 +330,8 @@ def main():
     ap.add_argument("--test-nets", type=int, default=16, help="estimate workload: held-out networks")
     ap.add_argument("--obs-steps", type=int, default=200000, help="estimate workload: observed steps (20 s)")
     ap.add_argument("--epochs", type=int, default=4, help="estimate workload: scorer training epochs")
+    ap.add_argument("--fit-realisations", type=int, default=8, help="estimate workload: noise realisations of the fit")
+    ap.add_argument("--fit-sweeps", type=int, default=2, help="estimate workload: toggle sweeps of the fit")
     ap.add_argument("--seq-sample", type=int, default=8,
                     help="ensemble workload: time every k-th network alone and scale to all")
     ap.add_argument("--rate-steps", type=int, default=500,

@@ -337,3 +337,43 @@ def test_fused_step_with_observation():
         nf = net.info()["frames_done"]
         outs.append(net.observe(gn.NET_OBS_FRAMES, frames=nf).cpu().numpy())
     assert outs[0].shape[0] == 6 and np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("variant", ["default", "FUSED_STEP", "DELIVER_COMPACT", "DELIVER_UNROLL2"])
+def test_fast_source_long_delays(variant):
+    """A source firing every ~23 steps under a constant input, with delays of
+    1, 43, 200, 254 and 255 steps: with several of its spikes inside a delay
+    the arrival test must consult the history ring (and always at d = 255,
+    where a saturated age is ambiguous).  Inputs must match the oracle
+    exactly at every step."""
+    gn, torch = _gn()
+    delays = np.array([1, 43, 200, 254, 255], dtype=np.uint8)
+    spec = synth.NetSpec(name="fast", pos_um=np.zeros((6, 2)), src=np.zeros(5, np.int32),
+                         dst=np.arange(1, 6, dtype=np.int32), weight=synth.round_fp16(np.full(5, 0.25)),
+                         delay_steps=delays, i_ext=np.array([0.5, 0, 0, 0, 0, 0], np.float32), seed=3)
+    T = 1500
+    flags = 0 if variant == "default" else getattr(gn, "NET_BUILD_" + variant)
+    g = run_gpu(spec, T, flags=flags)
+    o = oracle.OracleNet(spec).step(T, v=True, inp=True)
+    assert o["raster"][:, 0].sum() > 50                      # the source fires fast
+    assert np.array_equal(g["raster"], o["raster"])
+    assert np.array_equal(g["input"], o["input"])
+    assert (o["input"][:, 5] != 0).sum() > 30                 # arrivals on the 255-step edge
+
+
+@pytest.mark.parametrize("variant", ["default", "FUSED_STEP"])
+@pytest.mark.parametrize("n", [1, 100])
+def test_degenerate_networks(variant, n):
+    """No edges at all (every row is a placeholder slot): a single driven
+    vertex, and 100 noisy driven vertices."""
+    gn, torch = _gn()
+    rng = np.random.default_rng(n)
+    spec = synth.NetSpec(name="empty", pos_um=rng.random((n, 2)) * 100, src=np.zeros(0, np.int32),
+                         dst=np.zeros(0, np.int32), weight=np.zeros(0, np.float32),
+                         drive_rate_hz=np.full(n, 200.0, np.float32), noise_sigma=0.05, seed=17)
+    T = 2000
+    flags = 0 if variant == "default" else getattr(gn, "NET_BUILD_" + variant)
+    g = run_gpu(spec, T, flags=flags)
+    o = oracle.OracleNet(spec).step(T, v=True, inp=True)
+    check_parity(g, o, exact_raster=True)
+    assert not g["input"].any() and o["raster"].sum() > 0
