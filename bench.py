@@ -32,6 +32,7 @@ BYTES_PER_EDGE_STREAMED_W = 7   # delivery variant that streams every weight wit
 # vertex update per step: V read + written (8), two-spike ages read + written
 # (4), history-ring word read + written (8), one summary bit (1/8)
 BYTES_PER_VERTEX_UPDATE = 20.125
+TIMING_EVERY = 16       # kernel-bound events on one launch in 16 across the timed region
 
 
 def measured_traffic(deliver_flags):
@@ -240,8 +241,9 @@ def bench_estimate(args, torch, synth):
     from paper_0908_3934_amd import estimate as est
     t0 = time.perf_counter()
     train, feats = [], []
-    for b in range(0, args.train_nets, 128):
-        obs = est.observe([synth.config4_net(m) for m in range(b, min(args.train_nets, b + 128))], args.obs_steps)
+    batch = 256                                       # one ensemble launch fills the 256 CUs
+    for b in range(0, args.train_nets, batch):
+        obs = est.observe([synth.config4_net(m) for m in range(b, min(args.train_nets, b + batch))], args.obs_steps)
         for o in obs:
             feats.append(est.features(o))
             o.F = None                                  # keep features, free the traces
@@ -375,7 +377,7 @@ def main():
 
     net.step(args.warmup)
     torch.cuda.synchronize()
-    net.timing_begin(2 * args.steps)
+    net.timing_begin(2 * args.steps // TIMING_EVERY + 4, every=TIMING_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     net.step(args.steps)
@@ -444,6 +446,8 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes,
             "arrivals_per_step": arrivals,
             "avg_launch_us": avg_deliver_s * 1e6,
+            "timed_launches": tm["step_launches"] if fused else tm["deliver_launches"],
+            "timing": "kernel-bound HIP events on one launch in %d across the timed region" % TIMING_EVERY,
             "update_avg_launch_us": (tm["update_ms"] / tm["update_launches"] * 1e3) if tm["update_launches"] else None,
         },
     }

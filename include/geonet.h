@@ -226,12 +226,14 @@ net_status net_observe(net_t* h, int32_t what, const void* params, void* out, in
                        void* stream);
 
 /*
- * Kernel timing for measurement.  After net_timing_begin(h, max_launches),
- * the next max_launches kernel launches made by net_step_n are bound to HIP
- * events (start and end of the kernel itself, on the call's stream).
- * net_timing_end waits for them, fills *out with the summed durations per
- * kernel kind and the launch and step counts, and stops recording.  Timing
- * never changes results.
+ * Kernel timing for measurement.  After net_timing_begin(h, max_launches,
+ * every), one in `every` kernel launches of each kind made by net_step_n
+ * (the first, then every every-th) is bound to HIP events (start and end of
+ * the kernel itself, on the call's stream), up to max_launches in all; a
+ * bound launch costs a few microseconds of issue time, so a sample keeps
+ * the timed run undisturbed.  net_timing_end waits for them, fills *out with
+ * the summed durations per kernel kind and the counts of timed launches and
+ * of the steps they cover, and stops recording.  Timing never changes results.
  */
 typedef struct {
     double deliver_ms, update_ms, ensemble_ms;         /* summed kernel durations */
@@ -241,7 +243,7 @@ typedef struct {
     int64_t step_launches;
 } net_timing_t;
 
-net_status net_timing_begin(net_t* h, int64_t max_launches);
+net_status net_timing_begin(net_t* h, int64_t max_launches, int32_t every);
 net_status net_timing_end(net_t* h, net_timing_t* out);
 
 /* Sizes and counters of a handle (host struct). */

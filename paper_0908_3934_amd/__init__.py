@@ -198,8 +198,10 @@ class Net:
         _check(library().net_step_n(self.h, n_steps, C.byref(rec), s), "net_step_n")
         return {"raster": r, "v": vv, "input": ii}
 
-    def timing_begin(self, max_launches: int):
-        _check(library().net_timing_begin(self.h, max_launches), "net_timing_begin")
+    def timing_begin(self, max_launches: int, every: int = 1):
+        """Bind kernel-start/end HIP events to up to max_launches launches,
+        one launch of each kernel kind in every `every`."""
+        _check(library().net_timing_begin(self.h, max_launches, every), "net_timing_begin")
 
     def timing_end(self) -> dict:
         out = _abi.Timing()

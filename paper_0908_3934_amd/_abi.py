@@ -111,7 +111,7 @@ SIGNATURES = {
     "net_observe": (C.c_int, [_vp, C.c_int32, _vp, _vp, C.c_int64, _vp]),
     "net_info": (C.c_int, [_vp, C.POINTER(Info)]),
     "net_node_offsets": (C.c_int, [_vp, _vp]),
-    "net_timing_begin": (C.c_int, [_vp, C.c_int64]),
+    "net_timing_begin": (C.c_int, [_vp, C.c_int64, C.c_int32]),
     "net_timing_end": (C.c_int, [_vp, C.POINTER(Timing)]),
     "net_free": (None, [_vp]),
     "net_last_error": (C.c_char_p, []),

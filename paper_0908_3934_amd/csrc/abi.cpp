@@ -31,6 +31,8 @@ struct net {
     std::vector<int32_t> tkind;
     std::vector<int64_t> tsteps;
     int64_t t_cap = 0, t_used = 0;
+    int64_t t_every = 1;          // time one launch of each kind in t_every
+    int64_t t_seen[4] = {0, 0, 0, 0};
     EnsemblePlan plan;
     bool autotuned = false;
 };
@@ -109,6 +111,7 @@ net_status zeros(net* h, T** dst, size_t count, hipStream_t s, const char* what,
 void next_events(net* h, int32_t kind, int64_t steps, hipEvent_t* e0, hipEvent_t* e1) {
     *e0 = *e1 = nullptr;
     if (h->t_used >= h->t_cap) return;
+    if (h->t_seen[kind & 3]++ % h->t_every != 0) return;   // a uniform sample of the launches
     const int64_t k = h->t_used++;
     *e0 = h->tev[2 * k];
     *e1 = h->tev[2 * k + 1];
@@ -644,10 +647,13 @@ net_status net_node_offsets(const net_t* h, int64_t* out) {
     return NET_OK;
 }
 
-net_status net_timing_begin(net_t* h, int64_t max_launches) {
+net_status net_timing_begin(net_t* h, int64_t max_launches, int32_t every) {
     if (!h) return fail(NET_E_ARG, "net_timing_begin: handle is NULL");
     if (max_launches < 0 || max_launches > (int64_t(1) << 22))
         return fail(NET_E_ARG, "net_timing_begin: bad max_launches");
+    if (every < 1) return fail(NET_E_ARG, "net_timing_begin: every must be >= 1");
+    h->t_every = every;
+    for (int64_t& c : h->t_seen) c = 0;
     for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
     h->tev.assign(static_cast<size_t>(2 * max_launches), nullptr);
     h->tkind.assign(static_cast<size_t>(max_launches), 0);

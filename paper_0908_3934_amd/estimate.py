@@ -73,14 +73,16 @@ class Observed:
 
 
 def observe(specs: Sequence, n_steps: int, gain: float = 1.0, offset: float = 0.0,
-            gamma: Optional[float] = None) -> List[Observed]:
-    """Simulate every network for n_steps (one ensemble) and observe it."""
+            gamma: Optional[float] = None, autotune: bool = True) -> List[Observed]:
+    """Simulate every network for n_steps (one ensemble launch, its workgroup
+    shape timed at build unless autotune is False) and observe it."""
     import torch
     specs = list(specs)
     nf = frames_in(n_steps, specs[0].frame_num, specs[0].frame_den)
     if gamma is None:
         gamma = observation_gamma(specs[0], gain)
-    net = Net(specs, frame_capacity=nf)
+    from . import NET_BUILD_AUTOTUNE
+    net = Net(specs, frame_capacity=nf, flags=NET_BUILD_AUTOTUNE if autotune and len(specs) > 1 else 0)
     net.step(n_steps)
     F_all = net.observe(NET_OBS_FLUOR, frames=nf, gain=gain, offset=offset, gamma=gamma)
     offs = net.node_offsets()
