@@ -57,30 +57,43 @@ struct GemmArgs {
     float* out_f32;           // [M x N] row-major (atomic add)
 };
 
-constexpr int kTile = 128, kKs = 32, kLdsK = kKs + 8;   // padded rows against bank conflicts
-constexpr int kGroups = kTile * kKs / 8 / 256;           // 16-byte groups per thread per operand (2)
+constexpr int kKs = 32, kLdsK = kKs + 8;   // K per stage; LDS rows padded against bank conflicts
 
+// 16-byte groups of a BM x kKs tile per thread (256 threads).
+template <int BM, int BN>
 struct StageRegs {
-    uint4 a[kGroups];
-    uint4 b[kGroups];
+    uint4 a[BM * kKs / 8 / 256];
+    uint4 b[BN * kKs / 8 / 256];
 };
 
-// Group e of a stage: for a k-contiguous operand, tile row e / 4 and k offset
-// (e % 4) * 8; for an m/n-contiguous one, k offset e / 16 and tile row (e % 16) * 8.
-__device__ __forceinline__ void load_stage(StageRegs& r, const GemmArgs& g, bool a_kc, bool b_kc, int64_t m0,
+// Group e of an R-row tile: for a k-contiguous operand, tile row e / 4 and k
+// offset (e % 4) * 8; for an m/n-contiguous one, k offset e / (R / 8) and
+// tile row (e % (R / 8)) * 8.
+template <int R>
+__device__ __forceinline__ void group_pos(int e, bool kc, int* row, int* kk) {
+    *row = kc ? e / 4 : (e % (R / 8)) * 8;
+    *kk = kc ? (e % 4) * 8 : e / (R / 8);
+}
+
+template <int BM, int BN>
+__device__ __forceinline__ void load_stage(StageRegs<BM, BN>& r, const GemmArgs& g, bool a_kc, bool b_kc, int64_t m0,
                                            int64_t n0, int64_t k0, int64_t k_hi, int tid) {
 #pragma unroll
-    for (int q = 0; q < kGroups; ++q) {
-        const int e = tid + 256 * q;
-        const int64_t m = a_kc ? m0 + e / 4 : m0 + (e % 16) * 8;
-        const int64_t k = a_kc ? k0 + (e % 4) * 8 : k0 + e / 16;
+    for (int q = 0; q < BM * kKs / 8 / 256; ++q) {
+        int row, kk;
+        group_pos<BM>(tid + 256 * q, a_kc, &row, &kk);
+        const int64_t m = m0 + row, k = k0 + kk;
         uint4 va = make_uint4(0u, 0u, 0u, 0u);
         if (m < g.M && k < k_hi) va = *reinterpret_cast<const uint4*>(g.A + m * g.a_rs + k * g.a_cs);
         r.a[q] = va;
-        const int64_t n = b_kc ? n0 + e / 4 : n0 + (e % 16) * 8;
-        const int64_t kb = b_kc ? k0 + (e % 4) * 8 : k0 + e / 16;
+    }
+#pragma unroll
+    for (int q = 0; q < BN * kKs / 8 / 256; ++q) {
+        int row, kk;
+        group_pos<BN>(tid + 256 * q, b_kc, &row, &kk);
+        const int64_t n = n0 + row, k = k0 + kk;
         uint4 vb = make_uint4(0u, 0u, 0u, 0u);
-        if (n < g.N && kb < k_hi) vb = *reinterpret_cast<const uint4*>(g.B + kb * g.b_rs + n * g.b_cs);
+        if (n < g.N && k < k_hi) vb = *reinterpret_cast<const uint4*>(g.B + k * g.b_rs + n * g.b_cs);
         r.b[q] = vb;
     }
 }
@@ -99,66 +112,75 @@ __device__ __forceinline__ void put_group(uint16_t (*T)[kLdsK], int row, int kk,
     }
 }
 
-__device__ __forceinline__ void store_stage(const StageRegs& r, bool a_kc, bool b_kc, int tid, uint16_t (*As)[kLdsK],
-                                            uint16_t (*Bs)[kLdsK]) {
+template <int BM, int BN>
+__device__ __forceinline__ void store_stage(const StageRegs<BM, BN>& r, bool a_kc, bool b_kc, int tid,
+                                            uint16_t (*As)[kLdsK], uint16_t (*Bs)[kLdsK]) {
 #pragma unroll
-    for (int q = 0; q < kGroups; ++q) {
-        const int e = tid + 256 * q;
-        put_group(As, a_kc ? e / 4 : (e % 16) * 8, a_kc ? (e % 4) * 8 : e / 16, a_kc, r.a[q]);
-        put_group(Bs, b_kc ? e / 4 : (e % 16) * 8, b_kc ? (e % 4) * 8 : e / 16, b_kc, r.b[q]);
+    for (int q = 0; q < BM * kKs / 8 / 256; ++q) {
+        int row, kk;
+        group_pos<BM>(tid + 256 * q, a_kc, &row, &kk);
+        put_group(As, row, kk, a_kc, r.a[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < BN * kKs / 8 / 256; ++q) {
+        int row, kk;
+        group_pos<BN>(tid + 256 * q, b_kc, &row, &kk);
+        put_group(Bs, row, kk, b_kc, r.b[q]);
     }
 }
 
-template <int kEpi>
+// Block tile BM x BN (64 or 128 each), four waves in a 2 x 2 arrangement,
+// each wave (BM/2) x (BN/2) = TM x TN tiles of 32 x 32.
+template <int kEpi, int BM, int BN>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[kTile][kLdsK];   // [m][k]
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[kTile][kLdsK];   // [n][k]
+    constexpr int TM = BM / 64, TN = BN / 64;
+    __shared__ __attribute__((aligned(16))) uint16_t As[BM][kLdsK];   // [m][k]
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][kLdsK];   // [n][k]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int64_t m0 = static_cast<int64_t>(blockIdx.y) * kTile, n0 = static_cast<int64_t>(blockIdx.x) * kTile;
+    const int64_t m0 = static_cast<int64_t>(blockIdx.y) * BM, n0 = static_cast<int64_t>(blockIdx.x) * BN;
     const int64_t k_lo = static_cast<int64_t>(blockIdx.z) * g.k_chunk;
     const int64_t k_hi = k_lo + g.k_chunk < g.K ? k_lo + g.k_chunk : g.K;
     const bool a_kc = g.a_cs == 1, b_kc = g.b_rs == 1;
-    f32x16 acc[2][2];
+    f32x16 acc[TM][TN];
 #pragma unroll
-    for (int tm = 0; tm < 2; ++tm)
+    for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
-        for (int tn = 0; tn < 2; ++tn)
+        for (int tn = 0; tn < TN; ++tn)
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[tm][tn][i] = 0.0f;
-    StageRegs r;
-    if (k_lo < k_hi) load_stage(r, g, a_kc, b_kc, m0, n0, k_lo, k_hi, tid);
+    StageRegs<BM, BN> r;
+    if (k_lo < k_hi) load_stage<BM, BN>(r, g, a_kc, b_kc, m0, n0, k_lo, k_hi, tid);
     for (int64_t k0 = k_lo; k0 < k_hi; k0 += kKs) {
-        store_stage(r, a_kc, b_kc, tid, As, Bs);
+        store_stage<BM, BN>(r, a_kc, b_kc, tid, As, Bs);
         __syncthreads();
-        if (k0 + kKs < k_hi) load_stage(r, g, a_kc, b_kc, m0, n0, k0 + kKs, k_hi, tid);
+        if (k0 + kKs < k_hi) load_stage<BM, BN>(r, g, a_kc, b_kc, m0, n0, k0 + kKs, k_hi, tid);
 #pragma unroll
         for (int ks = 0; ks < kKs; ks += 16) {
             // lane supplies row (lane % 32) and k = ks + 8*(lane / 32) .. +7
             const int rr = lane & 31, kq = ks + 8 * (lane >> 5);
-            bf16x8 a[2], b[2];
+            bf16x8 a[TM], b[TN];
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                a[t] = *reinterpret_cast<const bf16x8*>(&As[wm * 64 + t * 32 + rr][kq]);
-                b[t] = *reinterpret_cast<const bf16x8*>(&Bs[wn * 64 + t * 32 + rr][kq]);
-            }
+            for (int t = 0; t < TM; ++t) a[t] = *reinterpret_cast<const bf16x8*>(&As[wm * (BM / 2) + t * 32 + rr][kq]);
 #pragma unroll
-            for (int tm = 0; tm < 2; ++tm)
+            for (int t = 0; t < TN; ++t) b[t] = *reinterpret_cast<const bf16x8*>(&Bs[wn * (BN / 2) + t * 32 + rr][kq]);
 #pragma unroll
-                for (int tn = 0; tn < 2; ++tn)
+            for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+                for (int tn = 0; tn < TN; ++tn)
                     acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[tm], b[tn], acc[tm][tn], 0, 0, 0);
         }
         __syncthreads();
     }
     // acc[tm][tn][i] holds C[m][n]: n = lane % 32, m = 8*(i/4) + 4*(lane/32) + i%4 within the 32 x 32 tile
 #pragma unroll
-    for (int tm = 0; tm < 2; ++tm)
+    for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
-        for (int tn = 0; tn < 2; ++tn) {
-            const int64_t n = n0 + wn * 64 + tn * 32 + (lane & 31);
+        for (int tn = 0; tn < TN; ++tn) {
+            const int64_t n = n0 + wn * (BN / 2) + tn * 32 + (lane & 31);
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int64_t m = m0 + wm * 64 + tm * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+                const int64_t m = m0 + wm * (BM / 2) + tm * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
                 if (m >= g.M || n >= g.N) continue;
                 const float v = acc[tm][tn][i];
                 if (kEpi == kBiasReluBf16) {
@@ -325,6 +347,20 @@ __global__ void __launch_bounds__(256) to_bf16_kernel(const float* x, uint16_t* 
     if (i < n) y[i] = f32_to_bf16_bits(x[i]);
 }
 
+template <int kEpi, int BM, int BN>
+hipError_t gemm_tile(const GemmArgs& g, int split, hipStream_t s) {
+    dim3 grid(static_cast<unsigned>((g.N + BN - 1) / BN), static_cast<unsigned>((g.M + BM - 1) / BM),
+              static_cast<unsigned>(split));
+    hipLaunchKernelGGL((gemm_kernel<kEpi, BM, BN>), grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+// Tile shape: 64 x 64 unless that gives more than 8,192 workgroups.  These
+// products are small and each K stage waits for its loads, so many resident
+// workgroups per CU hide more latency than larger tiles save (measured on
+// the scorer: training step 142 us with 64 x 64, 175 us with 64 x 128, 211 us
+// with 128 x 128).  GEONET_GEMM_TILE (0: 128 x 128, 1: 64 x 128, 2: 64 x 64)
+// fixes it at compile time.
 template <int kEpi>
 hipError_t gemm(const GemmArgs& g, int split, hipStream_t s) {
     // every operand must have a unit stride along k or along its row/column
@@ -334,10 +370,15 @@ hipError_t gemm(const GemmArgs& g, int split, hipStream_t s) {
     if ((!a_kc && g.a_rs != 1) || (!b_kc && g.b_cs != 1)) return hipErrorInvalidValue;
     if ((a_kc || b_kc) && (g.K % 8 != 0 || g.k_chunk % kKs != 0)) return hipErrorInvalidValue;
     if ((!a_kc && g.M % 8 != 0) || (!b_kc && g.N % 8 != 0)) return hipErrorInvalidValue;
-    dim3 grid(static_cast<unsigned>((g.N + kTile - 1) / kTile), static_cast<unsigned>((g.M + kTile - 1) / kTile),
-              static_cast<unsigned>(split));
-    hipLaunchKernelGGL((gemm_kernel<kEpi>), grid, dim3(256), 0, s, g);
-    return hipGetLastError();
+#ifdef GEONET_GEMM_TILE
+    const int tile = GEONET_GEMM_TILE;
+#else
+    auto blocks = [&](int64_t bm, int64_t bn) { return ((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn) * split; };
+    const int tile = blocks(64, 64) > 8192 ? 0 : 2;
+#endif
+    if (tile == 0) return gemm_tile<kEpi, 128, 128>(g, split, s);
+    if (tile == 1) return gemm_tile<kEpi, 64, 128>(g, split, s);
+    return gemm_tile<kEpi, 64, 64>(g, split, s);
 }
 
 }  // namespace
