@@ -166,7 +166,34 @@ def bench_ensemble(args, torch, synth, gn):
         },
         "speedup_vs_sequential": seq_all / wall,
         "edge_steps_per_s": E * steps / wall,
+        "roofline": {
+            "bound": "hbm", "kernel": "ensemble_kernel",
+            "achieved": BYTES_PER_EDGE * E * steps / (tm["ensemble_ms"] / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": BYTES_PER_EDGE * E * steps / (tm["ensemble_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "traffic": None,
+            "note": "5 B per edge-step streamed from L2/MALL (the %.0f MB edge list stays in the 256 MB MALL); "
+                    "the bound is the per-step LDS work and two barriers of each workgroup" % (BYTES_PER_EDGE * E / 1e6),
+        },
+        "cpu_baseline": ensemble_cpu_baseline(specs, len(specs)),
     }
+
+
+def ensemble_cpu_baseline(specs, n_all, every=64, steps=2000):
+    """The FP64 oracle on every 64th network for 2,000 steps, scaled to
+    networks per second of 10,000-step runs."""
+    import oracle
+    sample = specs[::every]
+    t = 0.0
+    for s in sample:
+        net = oracle.OracleNet(s)
+        t0 = time.perf_counter()
+        net.step(steps, raster=False)
+        t += time.perf_counter() - t0
+        net.close()
+    per_net = t / len(sample) * (10000 / steps)
+    return {"value": 1.0 / per_net, "unit": "networks per second (10,000-step runs)", "cores": 1, "kind": "oracle",
+            "sample": "every %dth of the %d networks (%d), %d steps each, single-threaded FP64; %.1f s"
+                      % (every, n_all, len(sample), steps, t)}
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0
@@ -226,7 +253,22 @@ def bench_mlp(args, torch, gn):
         "roofline": {"bound": "mfma", "achieved": train_tflops, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": train_tflops / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
                      "forward_achieved": fw * Bf / fwd_s / 1e12},
+        "cpu_baseline": mlp_cpu_baseline(Xt.cpu().numpy(), yt.cpu().numpy(), m.get_params()),
     }
+
+
+def mlp_cpu_baseline(X, y, params, rows=2048):
+    """The FP64 reference (same BF16 rounding points) for one gradient of a
+    2,048-row batch, in training pairs per second."""
+    from threadpoolctl import threadpool_limits
+    from oracle import mlp as M
+    X, y = X[:rows].astype("float64"), y[:rows].astype("float64")
+    with threadpool_limits(limits=1):                  # one core, like every oracle timing
+        t0 = time.perf_counter()
+        M.grad(params.astype("float64"), X, y, bf=True)
+        t = time.perf_counter() - t0
+    return {"value": rows / t, "unit": "training pairs per second (forward + gradient)", "cores": 1,
+            "kind": "oracle", "sample": "one %d-row batch through the FP64 MLP reference (numpy); %.2f s" % (rows, t)}
 
 
 def bench_estimate(args, torch, synth):
