@@ -199,11 +199,11 @@ net_status reset_state(net* h, const HostGraph& hg, hipStream_t s) {
     const size_t np = static_cast<size_t>(g.n_pad);
     hipError_t e = hipMemcpyAsync(g.V, hg.v0.data(), std::min(hg.v0.size(), np) * sizeof(float),
                                   hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemsetAsync(g.age, kAgeNever, np * sizeof(uint16_t), s);
+    if (e == hipSuccess) e = hipMemsetAsync(g.age, kAgeNever, (np + kAgePad) * sizeof(uint16_t), s);
     if (e == hipSuccess) e = hipMemsetAsync(g.I, 0, np * sizeof(float), s);
     if (e == hipSuccess) e = hipMemsetAsync(g.ring, 0, np * kRingWords * sizeof(uint32_t), s);
     if (e == hipSuccess) e = hipMemsetAsync(g.summary, 0, np / 32 * sizeof(uint32_t), s);
-    if (e == hipSuccess && g.age_alt) e = hipMemsetAsync(g.age_alt, kAgeNever, np * sizeof(uint16_t), s);
+    if (e == hipSuccess && g.age_alt) e = hipMemsetAsync(g.age_alt, kAgeNever, (np + kAgePad) * sizeof(uint16_t), s);
     if (e == hipSuccess && g.summary_alt) e = hipMemsetAsync(g.summary_alt, 0, np / 32 * sizeof(uint32_t), s);
     if (e == hipSuccess && g.calcium) e = hipMemsetAsync(g.calcium, 0, np * sizeof(double), s);
     if (e == hipSuccess && g.frame_acc) e = hipMemsetAsync(g.frame_acc, 0, np * sizeof(double), s);
@@ -280,11 +280,10 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
             hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
             hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess) {
             const int64_t n_pad = (static_cast<int64_t>(descs[0].n_nodes) + kNodeAlign - 1) / kNodeAlign * kNodeAlign;
-            const int64_t summary = (n_pad / 8) >> ((opts->flags & NET_BUILD_SUMMARY_HALF) ? 1 : 0);
-            const int64_t room = (static_cast<int64_t>(lds_max) - summary) / 4;
-            if (room >= 64) {
+            const int64_t room = (static_cast<int64_t>(lds_max) - kStepSummaryBytes - kStepQueueBytes) / 4;
+            if (!(opts->flags & NET_BUILD_SUMMARY_HALF) && n_pad / 8 <= kStepSummaryBytes && room >= 64) {
                 seg_count = n_cu;
-                seg_cap = static_cast<int32_t>(std::min<int64_t>(room, int64_t(1) << 30));
+                seg_cap = static_cast<int32_t>(std::min<int64_t>(room, kStepMaxSegment));
             }
         }
     }
@@ -357,7 +356,7 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
         g.i_ext = ie;
     }
     if ((st = upload(h, &g.V, hg.v0, np, s, "V")) != NET_OK) return bail(st);
-    if ((st = zeros(h, &g.age, np, s, "age", kAgeNever)) != NET_OK) return bail(st);
+    if ((st = zeros(h, &g.age, np + kAgePad, s, "age", kAgeNever)) != NET_OK) return bail(st);
     if ((st = zeros(h, &g.I, np, s, "input")) != NET_OK) return bail(st);
     if ((st = zeros(h, &g.ring, np * kRingWords, s, "history ring")) != NET_OK) return bail(st);
     if ((st = zeros(h, &g.summary, np / 32, s, "summary")) != NET_OK) return bail(st);
@@ -370,7 +369,7 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
         int32_t *sv = nullptr, *sc = nullptr;
         if ((st = upload(h, &sv, hg.seg_vertex, hg.seg_vertex.size(), s, "segments")) != NET_OK) return bail(st);
         if ((st = upload(h, &sc, hg.seg_chunk, hg.seg_chunk.size(), s, "segments")) != NET_OK) return bail(st);
-        if ((st = zeros(h, &g.age_alt, np, s, "ages", kAgeNever)) != NET_OK) return bail(st);
+        if ((st = zeros(h, &g.age_alt, np + kAgePad, s, "ages", kAgeNever)) != NET_OK) return bail(st);
         if ((st = zeros(h, &g.summary_alt, np / 32, s, "summary")) != NET_OK) return bail(st);
         g.seg_vertex = sv;
         g.seg_chunk = sc;

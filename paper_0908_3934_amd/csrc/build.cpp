@@ -252,7 +252,8 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
     }
     g.max_delay = max_delay;
     // Summary window: the smallest W with at most 0.5 % of the edges longer
-    // than W (those edges bypass the recent-spike filter).
+    // than W (those edges bypass the recent-spike filter).  W <= 254, so an
+    // edge of delay 255 always bypasses it.
     {
         std::vector<int64_t> hist(256, 0);
         for (int64_t s = 0; s < g.e_slots; ++s) hist[g.d[s]]++;
@@ -264,7 +265,7 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
             above += hist[d];
             w = d - 1;
         }
-        g.window = std::max(w, 1);
+        g.window = std::min(std::max(w, 1), 254);
     }
     // Placeholders for empty rows, row-start bits, per-row order and exactness.
     const double two24 = 16777216.0;

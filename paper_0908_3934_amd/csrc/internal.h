@@ -18,6 +18,17 @@ constexpr int kRingSlots = 256;       // spike history per vertex, bits
 constexpr int kRingWords = kRingSlots / 32;
 constexpr int kNodeAlign = 256;       // vertex arrays padded to this many entries (one update workgroup)
 constexpr uint8_t kAgeNever = 255;    // "no spike within the last 254 steps"
+// The ages arrays hold this many entries past n_pad; entry n_pad stays
+// (kAgeNever, kAgeNever) and is what delivery gathers for non-candidate edges.
+constexpr int kAgePad = 64;
+// The fused step kernel keeps the recent-spike summary in a fixed 128 KiB of
+// LDS (one bit per vertex, up to 2^20 vertices) and its segment's inputs
+// after it.
+constexpr int kStepSummaryBytes = 128 * 1024;
+// ... and per wave (16 per workgroup) a queue of 128 arrival slot indices.
+constexpr int kStepQueueBytes = 16 * 128 * 4;
+// Vertices per fused-step segment at most (6 per thread of its workgroup).
+constexpr int kStepMaxSegment = 6 * 1024;
 
 // Per-network constants used by the vertex kernels.
 struct NetParams {
@@ -121,6 +132,8 @@ struct LaunchConfig {
     bool nontemporal = false;
     int mode = 0;                  // delivery loop: 0 one chunk, 1 two chunks, 2 pipelined, 3 compacted
     bool fused = false;            // one kernel per step (delivery + vertex update), see launch_step
+    int step_loop = 0;             // fused step loop shape (kStepLoops index; GEONET_STEP_LOOP overrides)
+    int32_t queue_off = 0;         // fused step: arrival queues' offset in LDS (floats after the inputs)
     size_t lds_bytes = 0;
 };
 

@@ -12,6 +12,8 @@
 //                       (Section 3.3).
 //   observe_kernel      fluorescence n*cbar + b + gamma*xi (Section 3.3) and
 //                       state read-outs.
+#include <cstdlib>
+
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -65,6 +67,20 @@ __device__ __forceinline__ uint32_t wave_bits_before(uint32_t bits) {
     return n;
 }
 
+// As wave_bits_before, also returning the wave's total (wave-uniform).
+__device__ __forceinline__ uint32_t wave_bits_before_total(uint32_t bits, uint32_t* total) {
+    uint32_t n = 0, tot = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const uint64_t m = __ballot((bits >> b) & 1u);
+        n += __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                       __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+        tot += static_cast<uint32_t>(__builtin_popcountll(m));
+    }
+    *total = tot;
+    return n;
+}
+
 struct DeliverArgs {
     const int32_t* __restrict__ src;
     const uint16_t* __restrict__ w;
@@ -82,6 +98,7 @@ struct DeliverArgs {
     uint32_t window;        // summary window W: bit set iff the vertex fired in the last W steps
     uint32_t sum_shift;     // summary bit of vertex s: s >> sum_shift (0, or 1: one bit per vertex pair)
     int32_t stage_vec4;     // compacted mode: the per-wave candidate stages start here in LDS (16-byte units)
+    uint32_t age_sentinel;  // index of the ages entry that stays (255, 255): gathered by non-candidate edges
 };
 
 // One wave handles 512 consecutive slots per iteration: lane L owns slots
@@ -126,45 +143,63 @@ __device__ __forceinline__ void load_chunk(ChunkRegs& x, const DeliverArgs& a, i
     }
 }
 
-// Summary test of one chunk and, for each candidate edge, a gather of its
-// source's two most recent spike ages (a 2 B word per vertex, 2 MiB at
-// N = 2^20, which stays in L2).  Bit k of *cand is set if edge k must be
-// resolved.
+// Summary test of one chunk and a gather of two spike ages per candidate
+// edge (a 2 B word per vertex, 2 MiB at N = 2^20, which stays in L2).  A
+// candidate edge (its source fired within the summary window, or the edge is
+// longer than the window) gathers its source's ages; every other edge takes
+// the ages (255, 255), which can match no delay of a non-candidate (those are
+// at most the window, below 255), so the resolution below needs no candidate
+// mask.  `shift` is the summary resolution (0: one bit per vertex).
 template <bool kLdsSummary>
 __device__ __forceinline__ void gather_chunk(const ChunkRegs& x, const DeliverArgs& a, const uint32_t* lds_summary,
-                                             uint32_t* aw, uint32_t* cand) {
+                                             uint32_t shift, uint32_t* aw) {
     const uint32_t sv[8] = {x.s_lo.x, x.s_lo.y, x.s_lo.z, x.s_lo.w, x.s_hi.x, x.s_hi.y, x.s_hi.z, x.s_hi.w};
-    uint32_t cm = 0;
+    const char* ages = reinterpret_cast<const char*>(a.ages);
+    uint32_t sw[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const uint32_t s = sv[k];
-        const uint32_t sb = s >> a.sum_shift;
-        const uint32_t sw = kLdsSummary ? lds_summary[sb >> 5] : a.summary[sb >> 5];
-        const uint32_t dk = ((k < 4 ? x.dq.x : x.dq.y) >> (8 * (k & 3))) & 0xFFu;
-        // edges longer than the summary window are always resolved
-        const uint32_t hit = ((sw >> (sb & 31)) & 1u) | (dk > a.window ? 1u : 0u);
-        aw[k] = a.ages[hit ? s : 0u];
-        cm |= hit << k;
+        const uint32_t sb = sv[k] >> shift;
+        sw[k] = kLdsSummary ? lds_summary[sb >> 5] : a.summary[sb >> 5];
     }
-    *cand = cm;
+    // Only candidate lanes issue the gather (the texture path's cost grows
+    // with the active lanes); the others keep the sentinel ages.
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t dk = ((k < 4 ? x.dq.x : x.dq.y) >> (8 * (k & 3))) & 0xFFu;
+        const bool cand = (__builtin_amdgcn_ubfe(sw[k], sv[k] >> shift, 1) != 0u) | (dk > a.window);   // bit mod 32
+        uint32_t v = 0xFFFFu;
+        if (cand) v = *reinterpret_cast<const uint16_t*>(ages + (sv[k] << 1));
+        aw[k] = v;
+    }
 }
 
-// Exact arrival test.  With a1 < a2 the ages of the source's last two spikes,
-// the source fired at t - d iff d == a1 or d == a2, or d > a2 and an older
-// spike sits at t - d; only that last case (three spikes within d steps, or
-// d = 255 where a saturated age is ambiguous) reads the history ring.
+// With a1 <= a2 the ages of the source's last two spikes (255 = "255 or
+// more"), the source fired at t - d only if d == a1 or d >= a2; most chunks
+// have no such edge and skip the resolution (wave-uniform).
+__device__ __forceinline__ bool chunk_may_fire(const ChunkRegs& x, const uint32_t* aw) {
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t dk = ((k < 4 ? x.dq.x : x.dq.y) >> (8 * (k & 3))) & 0xFFu;
+        any = any | (dk == (aw[k] & 0xFFu)) | (dk >= ((aw[k] >> 8) & 0xFFu));
+    }
+    return wave_ballot(any) != 0;
+}
+
+// Exact arrival test.  For d < a2 the only spike within d steps is the one at
+// a1 (exact, since a1 < a2 <= 255), so the source fired at t - d iff d == a1.
+// For d >= a2 (an older spike may sit at t - d, or a2 = d = 255 is saturated)
+// the history ring decides.
 __device__ __forceinline__ uint32_t fired_bits(const ChunkRegs& x, const DeliverArgs& a, uint32_t t,
-                                               const uint32_t* aw, uint32_t cand) {
+                                               const uint32_t* aw) {
     uint32_t fired = 0, need = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const uint32_t dk = ((k < 4 ? x.dq.x : x.dq.y) >> (8 * (k & 3))) & 0xFFu;
-        const uint32_t a1 = aw[k] & 0xFFu, a2 = aw[k] >> 8;
-        const bool c = (cand >> k) & 1u;
-        const bool hit = dk < 255u && (dk == a1 || dk == a2);
-        const bool ring = dk == 255u || (dk > a2 && dk != a1);
-        fired |= (c && hit ? 1u : 0u) << k;
-        need |= (c && !hit && ring ? 1u : 0u) << k;
+        const uint32_t a1 = aw[k] & 0xFFu, a2 = (aw[k] >> 8) & 0xFFu;
+        const bool ring = dk >= a2;
+        fired |= (!ring && dk == a1 ? 1u : 0u) << k;
+        need |= (ring ? 1u : 0u) << k;
     }
     if (wave_ballot(need != 0)) {
         const uint32_t sv[8] = {x.s_lo.x, x.s_lo.y, x.s_lo.z, x.s_lo.w, x.s_hi.x, x.s_hi.y, x.s_hi.z, x.s_hi.w};
@@ -306,15 +341,17 @@ __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
         ChunkRegs cur;
         if (c < c_end) load_chunk<kWStream, kNT>(cur, a, c, lane);
         for (; c < c_end; c += stride) {
-            uint32_t aw[8], cand;
-            gather_chunk<kLdsSummary>(cur, a, lds_summary, aw, &cand);
+            uint32_t aw[8];
+            gather_chunk<kLdsSummary>(cur, a, lds_summary, a.sum_shift, aw);
             const ChunkRegs now = cur;
             // the next chunk's stream is in flight while the gathers return
             // (unconditional, so waiting for the gathers never waits for it;
             // the last iteration reloads its own chunk)
             load_chunk<kWStream, kNT>(cur, a, c + stride < c_end ? c + stride : c, lane);
-            const uint32_t fired = fired_bits(now, a, t, aw, cand);
-            if (wave_ballot(fired != 0)) deliver_fired<kWStream>(a, c, lane, fired, now.wq);
+            if (chunk_may_fire(now, aw)) {
+                const uint32_t fired = fired_bits(now, a, t, aw);
+                if (wave_ballot(fired != 0)) deliver_fired<kWStream>(a, c, lane, fired, now.wq);
+            }
         }
     } else {
         for (; c < c_end; c += stride) {
@@ -323,14 +360,15 @@ __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
 #pragma unroll
             for (int u = 0; u < kPer; ++u)
                 load_chunk<kWStream, kNT>(cur[u], a, c + u < c_end ? c + u : c_end - 1, lane);
-            uint32_t aw[kPer][8], cand[kPer];
+            uint32_t aw[kPer][8];
 #pragma unroll
-            for (int u = 0; u < kPer; ++u) gather_chunk<kLdsSummary>(cur[u], a, lds_summary, aw[u], &cand[u]);
+            for (int u = 0; u < kPer; ++u) gather_chunk<kLdsSummary>(cur[u], a, lds_summary, a.sum_shift, aw[u]);
 #pragma unroll
             for (int u = 0; u < kPer; ++u) {
-                uint32_t fired = fired_bits(cur[u], a, t, aw[u], cand[u]);
-                if (c + u >= c_end) fired = 0;
-                if (wave_ballot(fired != 0)) deliver_fired<kWStream>(a, c + u, lane, fired, cur[u].wq);
+                if (c + u < c_end && chunk_may_fire(cur[u], aw[u])) {
+                    const uint32_t fired = fired_bits(cur[u], a, t, aw[u]);
+                    if (wave_ballot(fired != 0)) deliver_fired<kWStream>(a, c + u, lane, fired, cur[u].wq);
+                }
             }
         }
     }
@@ -359,20 +397,39 @@ struct NodeArgs {
     NetParams p0;
 };
 
+// State a vertex update reads from memory (besides the input), loaded ahead
+// of the update by the fused step.
+struct VertexState {
+    float v;
+    uint32_t ages;
+    uint32_t thr;    // drive threshold (0: not driven)
+    uint32_t ring;   // the history word that holds this step's bit
+};
+
+__device__ __forceinline__ VertexState load_vertex_state(const NodeArgs& a, int64_t j, int64_t j_end) {
+    const int64_t jj = j < j_end ? j : 0;
+    VertexState st;
+    st.v = a.V[jj];
+    st.ages = a.age[jj];
+    st.thr = a.drive_thr ? a.drive_thr[jj] : 0u;
+    st.ring = a.ring[((a.t_lo & 0xFFu) >> 5) * a.n_pad + jj];
+    return st;
+}
+
 // Vertex update of step t for vertex j with delivered input `in` (all lanes
 // of a wave call it together, on 64 consecutive vertices starting at a
 // multiple of 64).  Vertices j >= j_end are not this caller's; the wave's
 // raster and summary words are written only when their first vertex is below
-// word_end.
+// word_end.  `st` is the vertex's state as load_vertex_state returns it.
 template <bool kMulti>
 __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int64_t j_end, int64_t word_end, float in,
-                                              bool clear_input) {
+                                              bool clear_input, const VertexState& st) {
     const int lane = threadIdx.x & 63;
     const bool valid = j < j_end;
     const int64_t jj = valid ? j : 0;
     const NetParams p = kMulti ? a.params[a.net_id[jj]] : a.p0;
-    const float v = a.V[jj];
-    const uint32_t ages = a.age[jj];
+    const float v = st.v;
+    const uint32_t ages = st.ages;
     const uint32_t age = ages & 0xFFu, age2 = ages >> 8;
     const bool spike = valid && v >= p.v_th;
 
@@ -383,11 +440,11 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
         if (a.rec_v) a.rec_v[a.rec_row * a.n_total + j] = v;
         if (a.rec_input) a.rec_input[a.rec_row * a.n_total + j] = in;
         if (clear_input) a.I[j] = 0.0f;
-        // spike-history ring: bit (t mod 256) of vertex j
+        // spike-history ring: bit (t mod 256) of vertex j (other slots of the
+        // word are only read elsewhere in this step)
         const uint32_t slot = a.t_lo & 0xFFu;
-        uint32_t* wp = a.ring + (slot >> 5) * a.n_pad + j;
         const uint32_t m = 1u << (slot & 31);
-        *wp = spike ? (*wp | m) : (*wp & ~m);
+        a.ring[(slot >> 5) * a.n_pad + j] = spike ? (st.ring | m) : (st.ring & ~m);
     }
 
     float vn;
@@ -403,7 +460,7 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
         } else {
             float u = a.i_ext ? a.i_ext[jj] : 0.0f;
             float noise = 0.0f;
-            const uint32_t thr = a.drive_thr ? a.drive_thr[jj] : 0u;
+            const uint32_t thr = st.thr;
             if (thr != 0u || p.sigma != 0.0f) {
                 const uint32_t jl = static_cast<uint32_t>(jj - p.node_off);
                 const uint4 r = philox(make_uint4(jl, a.t_lo, a.t_hi, 0u), p.key_lo, p.key_hi);
@@ -455,7 +512,7 @@ template <bool kMulti>
 __global__ void __launch_bounds__(256) node_update_kernel(NodeArgs a) {
     const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const float in = a.I[j < a.n_total ? j : 0];
-    vertex_update<kMulti>(a, j, a.n_total, a.n_pad, in, true);
+    vertex_update<kMulti>(a, j, a.n_total, a.n_pad, in, true, load_vertex_state(a, j, a.n_total));
 }
 
 // ---------------------------------------------------------------------------
@@ -791,7 +848,44 @@ struct StepArgs {
     NodeArgs n;
     const int32_t* seg_vertex;
     const int32_t* seg_chunk;
+    int32_t queue_off;   // arrival queues start this many floats after the segment inputs' start in LDS
 };
+
+// Arrivals found in a chunk are queued in the wave's LDS queue (slot
+// indices) instead of being added at once: the row and weight of an arrival
+// need loads from memory, and a wave that issued them per chunk would wait
+// for each.  The queue is resolved in one pass when full and at the end.
+constexpr uint32_t kStepQueue = 128;   // entries per wave
+constexpr int kStepPrefetch = kStepMaxSegment / 1024;   // vertices per thread whose state the step loads ahead
+
+// Row and weight of each queued slot, then an exact FP32 add into the
+// segment's LDS inputs.  The row of slot p of chunk c is chunk_row0[c] plus
+// the row starts among positions 1..p of the chunk (64 bytes of row-start
+// bits, bit p of the chunk's 512).
+__device__ __forceinline__ void flush_arrivals(const DeliverArgs& a, const uint32_t* q, uint32_t qn, int lane,
+                                               float* lds_in, int32_t v0) {
+    for (uint32_t i = 0; i < qn; i += 64) {
+        const uint32_t k = i + static_cast<uint32_t>(lane);
+        if (k < qn) {
+            const uint32_t e = q[k];
+            const uint32_t c = e >> 9, p = e & 511u;
+            const u32x4* rs = reinterpret_cast<const u32x4*>(a.rowstart + static_cast<uint64_t>(c) * 64);
+            const u32x4 r0 = rs[0], r1 = rs[1], r2 = rs[2], r3 = rs[3];
+            const uint32_t wbits = a.w[e];
+            const int32_t row0 = a.chunk_row0[c];
+            const uint32_t words[16] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
+                                        r2.x, r2.y, r2.z, r2.w, r3.x, r3.y, r3.z, r3.w};
+            const uint32_t pw = p >> 5, pb = p & 31u;
+            int32_t cnt = -static_cast<int32_t>(r0.x & 1u);   // position 0 belongs to row0
+#pragma unroll
+            for (uint32_t j = 0; j < 16; ++j) {
+                const uint32_t m = j < pw ? 0xFFFFFFFFu : (j == pw ? (pb == 31u ? 0xFFFFFFFFu : (2u << pb) - 1u) : 0u);
+                cnt += __popc(words[j] & m);
+            }
+            atomicAdd(lds_in + (row0 + cnt - v0), half_bits_to_float(wbits));
+        }
+    }
+}
 
 __device__ __forceinline__ void deliver_fired_lds(const DeliverArgs& a, int64_t c, int lane, uint32_t fired,
                                                   float* lds_in, int32_t v0) {
@@ -812,10 +906,16 @@ __device__ __forceinline__ void deliver_fired_lds(const DeliverArgs& a, int64_t 
     }
 }
 
+// kPer chunks per wave iteration; kPipe: the next iteration's stream loads
+// are issued after this iteration's age gathers, so they are in flight while
+// the gathers return and the chunks are resolved.
+template <int kPer, bool kPipe>
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs s) {
-    extern __shared__ uint4 lds4[];
+    // the summary at a fixed LDS address (its reads need no base), the
+    // segment's inputs after it
+    __shared__ uint4 lds4[kStepSummaryBytes / 16];
+    extern __shared__ float lds_in[];
     const uint32_t* lds_summary = reinterpret_cast<const uint32_t*>(lds4);
-    float* lds_in = reinterpret_cast<float*>(lds4 + s.d.summary_vec4);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
@@ -830,28 +930,90 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs s) {
     for (int i = threadIdx.x; i < v1 - v0; i += blockDim.x) lds_in[i] = 0.0f;
     __syncthreads();
 
-    const int64_t stride = static_cast<int64_t>(nwaves) * 2;
-    for (int64_t c = c_begin + static_cast<int64_t>(wave) * 2; c < c_end; c += stride) {
-        ChunkRegs cur[2];
+    uint32_t* queue = reinterpret_cast<uint32_t*>(lds_in + s.queue_off) + wave * kStepQueue;
+    uint32_t qn = 0;   // wave-uniform
+    // the state of this workgroup's vertices is loaded now and arrives while
+    // the edges stream (segments hold at most kStepPrefetch * 1024 vertices)
+    VertexState pre[kStepPrefetch];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) load_chunk<false, false>(cur[u], s.d, c + u < c_end ? c + u : c_end - 1, lane);
-        uint32_t aw[2][8], cand[2];
+    for (int i = 0; i < kStepPrefetch; ++i) {
+        const int64_t j = v0 + static_cast<int64_t>(i) * 1024 + threadIdx.x;
+        if (v0 + i * 1024 < v1) pre[i] = load_vertex_state(s.n, j, v1);
+    }
+    const int64_t stride = static_cast<int64_t>(nwaves) * kPer;
+    int64_t c = c_begin + static_cast<int64_t>(wave) * kPer;
+    // chunks beyond the range repeat the last one and are skipped below
+    ChunkRegs cur[kPer];
+    if (kPipe && c < c_end) {
 #pragma unroll
-        for (int u = 0; u < 2; ++u) gather_chunk<true>(cur[u], s.d, lds_summary, aw[u], &cand[u]);
+        for (int u = 0; u < kPer; ++u) load_chunk<false, false>(cur[u], s.d, c + u < c_end ? c + u : c_end - 1, lane);
+    }
+    for (; c < c_end; c += stride) {
+        if (!kPipe) {
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            uint32_t fired = fired_bits(cur[u], s.d, t, aw[u], cand[u]);
-            if (c + u >= c_end) fired = 0;
-            if (wave_ballot(fired != 0)) deliver_fired_lds(s.d, c + u, lane, fired, lds_in, v0);
+            for (int u = 0; u < kPer; ++u) load_chunk<false, false>(cur[u], s.d, c + u < c_end ? c + u : c_end - 1, lane);
+        }
+        uint32_t aw[kPer][8];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) gather_chunk<true>(cur[u], s.d, lds_summary, 0u, aw[u]);
+        ChunkRegs now[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) now[u] = cur[u];
+        if (kPipe) {
+            const int64_t cn = c + stride;
+#pragma unroll
+            for (int u = 0; u < kPer; ++u)
+                load_chunk<false, false>(cur[u], s.d, cn + u < c_end ? cn + u : c_end - 1, lane);
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            if (c + u < c_end && chunk_may_fire(now[u], aw[u])) {
+                const uint32_t fired = fired_bits(now[u], s.d, t, aw[u]);
+                uint32_t total;
+                const uint32_t before = wave_bits_before_total(fired, &total);
+                if (total > kStepQueue) {
+                    deliver_fired_lds(s.d, c + u, lane, fired, lds_in, v0);
+                } else if (total > 0) {
+                    if (qn + total > kStepQueue) {
+                        flush_arrivals(s.d, queue, qn, lane, lds_in, v0);
+                        qn = 0;
+                    }
+                    uint32_t at = qn + before;
+                    const uint32_t e0 = static_cast<uint32_t>(c + u) * kChunkEdges + static_cast<uint32_t>(lane) * kEdgesPerLane;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        if ((fired >> k) & 1u) queue[at++] = e0 + static_cast<uint32_t>(k);
+                    }
+                    qn += total;
+                }
+            }
         }
     }
+    if (qn) flush_arrivals(s.d, queue, qn, lane, lds_in, v0);
     __syncthreads();
-    for (int64_t base = v0; base < v1; base += blockDim.x) {
-        const int64_t j = base + threadIdx.x;
-        const float in = j < v1 ? lds_in[j - v0] : 0.0f;
-        vertex_update<false>(s.n, j, v1, v1, in, false);
+#pragma unroll
+    for (int i = 0; i < kStepPrefetch; ++i) {
+        const int64_t base = v0 + static_cast<int64_t>(i) * 1024;
+        if (base < v1) {
+            const int64_t j = base + threadIdx.x;
+            const float in = j < v1 ? lds_in[j - v0] : 0.0f;
+            vertex_update<false>(s.n, j, v1, v1, in, false, pre[i]);
+        }
     }
 }
+
+// Step-loop shapes (chunks per iteration, pipelined stream loads).
+struct StepLoop {
+    int per;
+    bool pipe;
+    const void* fn;
+};
+const StepLoop kStepLoops[] = {
+    {2, false, reinterpret_cast<const void*>(&step_kernel<2, false>)},
+    {3, false, reinterpret_cast<const void*>(&step_kernel<3, false>)},
+    {2, true, reinterpret_cast<const void*>(&step_kernel<2, true>)},
+};
+constexpr int kStepLoopCount = sizeof(kStepLoops) / sizeof(kStepLoops[0]);
 
 }  // namespace
 
@@ -917,12 +1079,22 @@ hipError_t configure_deliver(DeviceGraph& g, const net_build_opts* opts, LaunchC
     // Fused step: one 1024-thread workgroup per segment, the summary and the
     // segment's inputs in LDS.
     lc.fused = false;
-    if ((flags & NET_BUILD_FUSED_STEP) && g.seg_vertex && g.n_seg > 0 && lc.lds_summary) {
-        const size_t need = summary_bytes + (static_cast<size_t>(g.seg_max) * sizeof(float) + 15) / 16 * 16;
-        if (need <= static_cast<size_t>(lds_max)) {
-            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&step_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    static_cast<int>(need));
-            if (e != hipSuccess) return e;
+    // (queued arrivals are 32-bit slot indices: at most 2^23 chunks)
+    if ((flags & NET_BUILD_FUSED_STEP) && g.seg_vertex && g.n_seg > 0 && lc.lds_summary && g.sum_shift == 0 &&
+        summary_bytes <= static_cast<size_t>(kStepSummaryBytes) && g.n_chunks <= (int64_t(1) << 23)) {
+        const size_t in_bytes = (static_cast<size_t>(g.seg_max) * sizeof(float) + 15) / 16 * 16;
+        const size_t need = in_bytes + kStepQueueBytes;   // beyond the summary: inputs, arrival queues
+        lc.queue_off = static_cast<int32_t>(in_bytes / sizeof(float));
+        if (need + kStepSummaryBytes <= static_cast<size_t>(lds_max) && g.seg_max <= kStepMaxSegment) {
+            for (const StepLoop& sl : kStepLoops) {
+                e = hipFuncSetAttribute(sl.fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(need));
+                if (e != hipSuccess) return e;
+            }
+            lc.step_loop = 0;
+            if (const char* env = std::getenv("GEONET_STEP_LOOP")) {
+                const int v = std::atoi(env);
+                if (v >= 0 && v < kStepLoopCount) lc.step_loop = v;
+            }
             lc.fused = true;
             lc.mode = 1;
             lc.stream_weights = false;
@@ -953,6 +1125,7 @@ static DeliverArgs deliver_args(const DeviceGraph& g, const LaunchConfig& lc, in
     a.t = static_cast<uint32_t>(t);
     a.n_pad = static_cast<uint32_t>(g.n_pad);
     a.window = static_cast<uint32_t>(g.d_sum);
+    a.age_sentinel = static_cast<uint32_t>(g.n_pad);
     return a;
 }
 
@@ -1119,7 +1292,14 @@ hipError_t launch_step(const DeviceGraph& g, const LaunchConfig& lc, int64_t t, 
     a.n.I = nullptr;
     a.seg_vertex = g.seg_vertex;
     a.seg_chunk = g.seg_chunk;
-    hipExtLaunchKernelGGL(step_kernel, dim3(g.n_seg), dim3(lc.deliver_threads), lc.lds_bytes, s, ev0, ev1, 0, a);
+    a.queue_off = lc.queue_off;
+    const dim3 grid(g.n_seg), block(lc.deliver_threads);
+    switch (lc.step_loop) {
+        case 0: hipExtLaunchKernelGGL((step_kernel<2, false>), grid, block, lc.lds_bytes, s, ev0, ev1, 0, a); break;
+        case 1: hipExtLaunchKernelGGL((step_kernel<3, false>), grid, block, lc.lds_bytes, s, ev0, ev1, 0, a); break;
+        case 2: hipExtLaunchKernelGGL((step_kernel<2, true>), grid, block, lc.lds_bytes, s, ev0, ev1, 0, a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -377,3 +377,33 @@ def test_degenerate_networks(variant, n):
     o = oracle.OracleNet(spec).step(T, v=True, inp=True)
     check_parity(g, o, exact_raster=True)
     assert not g["input"].any() and o["raster"].sum() > 0
+
+
+@pytest.mark.parametrize("spread", [1, 4, 16])
+def test_synchronous_bursts(spread):
+    """Every vertex fires in lockstep under a constant input, so a step
+    delivers whole chunks at once: with one delay for all edges each
+    512-edge chunk has 512 arrivals in one step, with `spread` delays about
+    512/spread.  The fused step handles the large cases directly and queues
+    the others; all must equal the two-kernel path bit for bit and the oracle
+    to the usual bar (inputs exact)."""
+    gn, torch = _gn()
+    rng = np.random.default_rng(spread)
+    n, k = 2048, 256
+    dst = np.repeat(np.arange(n, dtype=np.int32), k)
+    src = np.argpartition(rng.random((n, n - 1)), k, axis=1)[:, :k].reshape(-1)   # k distinct per row
+    src = np.where(src >= dst, src + 1, src).astype(np.int32)                  # no self-loops
+    delays = (5 + rng.integers(0, spread, size=n * k)).astype(np.uint8)
+    w = synth.round_fp16(np.full(n * k, 0.001))
+    spec = synth.NetSpec(name="lockstep", pos_um=np.zeros((n, 2)), src=src, dst=dst, weight=w,
+                         delay_steps=delays, i_ext=np.full(n, 0.5, np.float32), seed=11)
+    T = 400
+    a = run_gpu(spec, T)
+    b = run_gpu(spec, T, flags=gn.NET_BUILD_FUSED_STEP)
+    assert b["net"].info()["deliver_flags"] & gn.NET_BUILD_FUSED_STEP
+    for key in ("raster", "v", "input"):
+        assert np.array_equal(a[key], b[key]), key
+    o = oracle.OracleNet(spec).step(T, v=True, inp=True)
+    check_parity(b, o, v_steps=T)
+    per_step = (o["input"] != 0).sum(1)
+    assert per_step.max() == n                                      # a burst reaches every vertex
