@@ -280,7 +280,7 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
             hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
             hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess) {
             const int64_t n_pad = (static_cast<int64_t>(descs[0].n_nodes) + kNodeAlign - 1) / kNodeAlign * kNodeAlign;
-            const int64_t room = (static_cast<int64_t>(lds_max) - kStepSummaryBytes - kStepQueueBytes) / 4;
+            const int64_t room = (static_cast<int64_t>(lds_max) - kStepSummaryBytes - kStepQueueBytes - 16) / 4;
             if (!(opts->flags & NET_BUILD_SUMMARY_HALF) && n_pad / 8 <= kStepSummaryBytes && room >= 64) {
                 seg_count = n_cu;
                 seg_cap = static_cast<int32_t>(std::min<int64_t>(room, kStepMaxSegment));

@@ -140,14 +140,16 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
     // network's slot range starts on a chunk boundary, so a chunk never mixes
     // networks (the ensemble kernel walks each network's chunks on its own).
     std::vector<int64_t> row_ptr(N + 1, 0);   // row_ptr[r] = first slot of row r
-    // Segments (fused step): balance slots plus a per-vertex update cost,
-    // cut only at multiples of 64 vertices, at most seg_cap vertices each.
+    // Segments (fused step): balance slots plus a small per-vertex update
+    // cost (the update's loads overlap the delivery, so a segment's time
+    // follows its slot count), cut only at multiples of 64 vertices, at most
+    // seg_cap vertices each.
     std::vector<char> seg_start(N + 1, 0);
     g.seg_vertex.clear();
     g.seg_chunk.clear();
     g.seg_max = 0;
     if (seg_count > 0 && n_nets == 1 && seg_cap >= 64) {
-        const int64_t kVertexCost = 16;
+        const int64_t kVertexCost = 1;
         int64_t total = 0;
         for (int64_t r = 0; r < N; ++r) total += std::max<int64_t>(indeg[r], 1) + kVertexCost;
         const int64_t cap = seg_cap / 64 * 64;

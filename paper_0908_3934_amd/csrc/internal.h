@@ -25,7 +25,8 @@ constexpr int kAgePad = 64;
 // LDS (one bit per vertex, up to 2^20 vertices) and its segment's inputs
 // after it.
 constexpr int kStepSummaryBytes = 128 * 1024;
-// ... and per wave (16 per workgroup) a queue of 128 arrival slot indices.
+// ... and per wave (16 per workgroup) a queue of 128 arrival slot indices,
+// then a 16-byte work counter.
 constexpr int kStepQueueBytes = 16 * 128 * 4;
 // Vertices per fused-step segment at most (6 per thread of its workgroup).
 constexpr int kStepMaxSegment = 6 * 1024;
@@ -132,7 +133,6 @@ struct LaunchConfig {
     bool nontemporal = false;
     int mode = 0;                  // delivery loop: 0 one chunk, 1 two chunks, 2 pipelined, 3 compacted
     bool fused = false;            // one kernel per step (delivery + vertex update), see launch_step
-    int step_loop = 0;             // fused step loop shape (kStepLoops index; GEONET_STEP_LOOP overrides)
     int32_t queue_off = 0;         // fused step: arrival queues' offset in LDS (floats after the inputs)
     size_t lds_bytes = 0;
 };

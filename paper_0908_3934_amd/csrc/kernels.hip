@@ -12,8 +12,6 @@
 //                       (Section 3.3).
 //   observe_kernel      fluorescence n*cbar + b + gamma*xi (Section 3.3) and
 //                       state read-outs.
-#include <cstdlib>
-
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -399,10 +397,11 @@ struct NodeArgs {
 
 // State a vertex update reads from memory (besides the input), loaded ahead
 // of the update by the fused step.
+// (Four registers per vertex: the fused step keeps several per thread.)
 struct VertexState {
     float v;
-    uint32_t ages;
-    uint32_t thr;    // drive threshold (0: not driven)
+    uint32_t ages;   // the two spike ages; vertex_random adds the drive pulse as bit 16
+    uint32_t aux;    // the drive threshold (0: not driven); vertex_random replaces it by the noise's bits
     uint32_t ring;   // the history word that holds this step's bit
 };
 
@@ -411,16 +410,38 @@ __device__ __forceinline__ VertexState load_vertex_state(const NodeArgs& a, int6
     VertexState st;
     st.v = a.V[jj];
     st.ages = a.age[jj];
-    st.thr = a.drive_thr ? a.drive_thr[jj] : 0u;
+    st.aux = a.drive_thr ? a.drive_thr[jj] : 0u;
     st.ring = a.ring[((a.t_lo & 0xFFu) >> 5) * a.n_pad + jj];
     return st;
+}
+
+// Control input and state noise of step t for vertex j: the drive pulse is
+// an integer compare of the first Philox word with the rate threshold, the
+// noise a Box-Muller draw from the next two (Section 3.1 control and noise).
+// Used only where the vertex is neither spiking nor held.
+template <bool kMulti>
+__device__ __forceinline__ void vertex_random(const NodeArgs& a, int64_t j, int64_t j_end, VertexState& st) {
+    const int64_t jj = j < j_end ? j : 0;
+    const NetParams p = kMulti ? a.params[a.net_id[jj]] : a.p0;
+    const uint32_t thr = st.aux;
+    float noise = 0.0f;
+    uint32_t pulse = 0;
+    if (thr != 0u || p.sigma != 0.0f) {
+        const uint32_t jl = static_cast<uint32_t>(jj - p.node_off);
+        const uint4 r = philox(make_uint4(jl, a.t_lo, a.t_hi, 0u), p.key_lo, p.key_hi);
+        pulse = r.x < thr ? 1u : 0u;
+        if (p.sigma != 0.0f) noise = p.sigma * gaussian(r.y, r.z);
+    }
+    st.ages |= pulse << 16;
+    st.aux = __float_as_uint(noise);
 }
 
 // Vertex update of step t for vertex j with delivered input `in` (all lanes
 // of a wave call it together, on 64 consecutive vertices starting at a
 // multiple of 64).  Vertices j >= j_end are not this caller's; the wave's
 // raster and summary words are written only when their first vertex is below
-// word_end.  `st` is the vertex's state as load_vertex_state returns it.
+// word_end.  `st` is the vertex's state as load_vertex_state returns it,
+// completed by vertex_random.
 template <bool kMulti>
 __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int64_t j_end, int64_t word_end, float in,
                                               bool clear_input, const VertexState& st) {
@@ -429,7 +450,7 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
     const int64_t jj = valid ? j : 0;
     const NetParams p = kMulti ? a.params[a.net_id[jj]] : a.p0;
     const float v = st.v;
-    const uint32_t ages = st.ages;
+    const uint32_t ages = st.ages & 0xFFFFu;
     const uint32_t age = ages & 0xFFu, age2 = ages >> 8;
     const bool spike = valid && v >= p.v_th;
 
@@ -441,10 +462,11 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
         if (a.rec_input) a.rec_input[a.rec_row * a.n_total + j] = in;
         if (clear_input) a.I[j] = 0.0f;
         // spike-history ring: bit (t mod 256) of vertex j (other slots of the
-        // word are only read elsewhere in this step)
+        // word are only read elsewhere in this step); written only when it
+        // changes
         const uint32_t slot = a.t_lo & 0xFFu;
         const uint32_t m = 1u << (slot & 31);
-        a.ring[(slot >> 5) * a.n_pad + j] = spike ? (st.ring | m) : (st.ring & ~m);
+        if (((st.ring & m) != 0u) != spike) a.ring[(slot >> 5) * a.n_pad + j] = st.ring ^ m;
     }
 
     float vn;
@@ -459,15 +481,8 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
             vn = p.v_reset;
         } else {
             float u = a.i_ext ? a.i_ext[jj] : 0.0f;
-            float noise = 0.0f;
-            const uint32_t thr = st.thr;
-            if (thr != 0u || p.sigma != 0.0f) {
-                const uint32_t jl = static_cast<uint32_t>(jj - p.node_off);
-                const uint4 r = philox(make_uint4(jl, a.t_lo, a.t_hi, 0u), p.key_lo, p.key_hi);
-                if (r.x < thr) u += p.drive_amp;
-                if (p.sigma != 0.0f) noise = p.sigma * gaussian(r.y, r.z);
-            }
-            vn = v + p.decay * (p.v_rest - v) + in + u + noise;
+            if ((st.ages >> 16) & 1u) u += p.drive_amp;
+            vn = v + p.decay * (p.v_rest - v) + in + u + __uint_as_float(st.aux);
         }
     }
     // recent-spike summary for the next step: last spike within d_sum steps
@@ -512,7 +527,9 @@ template <bool kMulti>
 __global__ void __launch_bounds__(256) node_update_kernel(NodeArgs a) {
     const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const float in = a.I[j < a.n_total ? j : 0];
-    vertex_update<kMulti>(a, j, a.n_total, a.n_pad, in, true, load_vertex_state(a, j, a.n_total));
+    VertexState st = load_vertex_state(a, j, a.n_total);
+    vertex_random<kMulti>(a, j, a.n_total, st);
+    vertex_update<kMulti>(a, j, a.n_total, a.n_pad, in, true, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -906,16 +923,17 @@ __device__ __forceinline__ void deliver_fired_lds(const DeliverArgs& a, int64_t 
     }
 }
 
-// kPer chunks per wave iteration; kPipe: the next iteration's stream loads
-// are issued after this iteration's age gathers, so they are in flight while
-// the gathers return and the chunks are resolved.
-template <int kPer, bool kPipe>
+// One workgroup per segment.  Waves take units of two chunks: unit `wave`
+// first, then the next unclaimed one from an LDS counter (claimed one
+// iteration ahead), so that waves the hardware serves later do not hold the
+// workgroup's barrier.
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs s) {
     // the summary at a fixed LDS address (its reads need no base), the
-    // segment's inputs after it
+    // segment's inputs, the arrival queues and the unit counter after it
     __shared__ uint4 lds4[kStepSummaryBytes / 16];
     extern __shared__ float lds_in[];
     const uint32_t* lds_summary = reinterpret_cast<const uint32_t*>(lds4);
+    constexpr int kPer = 2;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
@@ -925,50 +943,54 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs s) {
     const int32_t v0 = s.seg_vertex[lb], v1 = s.seg_vertex[lb + 1];
     const int64_t c_begin = s.seg_chunk[lb], c_end = s.seg_chunk[lb + 1];
     const uint32_t t = s.d.t;
-    const uint4* g = reinterpret_cast<const uint4*>(s.d.summary);
-    for (int i = threadIdx.x; i < s.d.summary_vec4; i += blockDim.x) lds4[i] = g[i];
-    for (int i = threadIdx.x; i < v1 - v0; i += blockDim.x) lds_in[i] = 0.0f;
-    __syncthreads();
-
     uint32_t* queue = reinterpret_cast<uint32_t*>(lds_in + s.queue_off) + wave * kStepQueue;
-    uint32_t qn = 0;   // wave-uniform
-    // the state of this workgroup's vertices is loaded now and arrives while
-    // the edges stream (segments hold at most kStepPrefetch * 1024 vertices)
-    VertexState pre[kStepPrefetch];
+    uint32_t* unit_counter = reinterpret_cast<uint32_t*>(lds_in + s.queue_off) + nwaves * kStepQueue;
+    // Start-up: the summary's loads first, then the first chunks, then the
+    // vertex state, so that only the summary is waited for before the
+    // barrier (which waits for LDS, not for global loads).  Every thread
+    // stages 8 x 16 B of the summary in registers; the LDS array has room
+    // for the largest summary, so the copy needs no branch (words past a
+    // smaller summary are never read).
+    const u32x4* g = reinterpret_cast<const u32x4*>(s.d.summary);
+    constexpr int kSumPer = kStepSummaryBytes / 16 / 1024;
+    u32x4 sreg[kSumPer];
 #pragma unroll
-    for (int i = 0; i < kStepPrefetch; ++i) {
-        const int64_t j = v0 + static_cast<int64_t>(i) * 1024 + threadIdx.x;
-        if (v0 + i * 1024 < v1) pre[i] = load_vertex_state(s.n, j, v1);
+    for (int i = 0; i < kSumPer; ++i) {
+        const int idx = i * 1024 + threadIdx.x;
+        sreg[i] = g[idx < s.d.summary_vec4 ? idx : s.d.summary_vec4 - 1];
     }
-    const int64_t stride = static_cast<int64_t>(nwaves) * kPer;
+    __builtin_amdgcn_sched_barrier(0);   // issued first: waits count loads in issue order
     int64_t c = c_begin + static_cast<int64_t>(wave) * kPer;
     // chunks beyond the range repeat the last one and are skipped below
+    // (every segment holds at least one chunk)
     ChunkRegs cur[kPer];
-    if (kPipe && c < c_end) {
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) load_chunk<false, false>(cur[u], s.d, c + u < c_end ? c + u : c_end - 1, lane);
-    }
-    for (; c < c_end; c += stride) {
-        if (!kPipe) {
+    for (int u = 0; u < kPer; ++u) load_chunk<false, false>(cur[u], s.d, c + u < c_end ? c + u : c_end - 1, lane);
+    __builtin_amdgcn_sched_barrier(0);
+    // the state of this workgroup's vertices (segments hold at most
+    // kStepPrefetch * 1024) arrives while the edges stream; issued after the
+    // first chunks, which are then not kept waiting for it
+    VertexState pre[kStepPrefetch];
 #pragma unroll
-            for (int u = 0; u < kPer; ++u) load_chunk<false, false>(cur[u], s.d, c + u < c_end ? c + u : c_end - 1, lane);
-        }
+    for (int i = 0; i < kStepPrefetch; ++i)
+        pre[i] = load_vertex_state(s.n, v0 + static_cast<int64_t>(i) * 1024 + threadIdx.x, v1);
+#pragma unroll
+    for (int i = 0; i < kSumPer; ++i) reinterpret_cast<u32x4*>(lds4)[i * 1024 + threadIdx.x] = sreg[i];
+    for (int i = threadIdx.x; i < v1 - v0; i += blockDim.x) lds_in[i] = 0.0f;
+    if (threadIdx.x == 0) *unit_counter = static_cast<uint32_t>(nwaves);
+    __syncthreads();
+
+    uint32_t qn = 0;   // wave-uniform
+    while (c < c_end) {
+        uint32_t claim = 0;
+        if (lane == 0) claim = atomicAdd(unit_counter, 1u);
         uint32_t aw[kPer][8];
 #pragma unroll
         for (int u = 0; u < kPer; ++u) gather_chunk<true>(cur[u], s.d, lds_summary, 0u, aw[u]);
-        ChunkRegs now[kPer];
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) now[u] = cur[u];
-        if (kPipe) {
-            const int64_t cn = c + stride;
-#pragma unroll
-            for (int u = 0; u < kPer; ++u)
-                load_chunk<false, false>(cur[u], s.d, cn + u < c_end ? cn + u : c_end - 1, lane);
-        }
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
-            if (c + u < c_end && chunk_may_fire(now[u], aw[u])) {
-                const uint32_t fired = fired_bits(now[u], s.d, t, aw[u]);
+            if (c + u < c_end && chunk_may_fire(cur[u], aw[u])) {
+                const uint32_t fired = fired_bits(cur[u], s.d, t, aw[u]);
                 uint32_t total;
                 const uint32_t before = wave_bits_before_total(fired, &total);
                 if (total > kStepQueue) {
@@ -988,6 +1010,11 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs s) {
                 }
             }
         }
+        c = c_begin + static_cast<int64_t>(__builtin_amdgcn_readfirstlane(claim)) * kPer;
+        if (c < c_end) {
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) load_chunk<false, false>(cur[u], s.d, c + u < c_end ? c + u : c_end - 1, lane);
+        }
     }
     if (qn) flush_arrivals(s.d, queue, qn, lane, lds_in, v0);
     __syncthreads();
@@ -997,23 +1024,11 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs s) {
         if (base < v1) {
             const int64_t j = base + threadIdx.x;
             const float in = j < v1 ? lds_in[j - v0] : 0.0f;
+            vertex_random<false>(s.n, j, v1, pre[i]);
             vertex_update<false>(s.n, j, v1, v1, in, false, pre[i]);
         }
     }
 }
-
-// Step-loop shapes (chunks per iteration, pipelined stream loads).
-struct StepLoop {
-    int per;
-    bool pipe;
-    const void* fn;
-};
-const StepLoop kStepLoops[] = {
-    {2, false, reinterpret_cast<const void*>(&step_kernel<2, false>)},
-    {3, false, reinterpret_cast<const void*>(&step_kernel<3, false>)},
-    {2, true, reinterpret_cast<const void*>(&step_kernel<2, true>)},
-};
-constexpr int kStepLoopCount = sizeof(kStepLoops) / sizeof(kStepLoops[0]);
 
 }  // namespace
 
@@ -1083,18 +1098,12 @@ hipError_t configure_deliver(DeviceGraph& g, const net_build_opts* opts, LaunchC
     if ((flags & NET_BUILD_FUSED_STEP) && g.seg_vertex && g.n_seg > 0 && lc.lds_summary && g.sum_shift == 0 &&
         summary_bytes <= static_cast<size_t>(kStepSummaryBytes) && g.n_chunks <= (int64_t(1) << 23)) {
         const size_t in_bytes = (static_cast<size_t>(g.seg_max) * sizeof(float) + 15) / 16 * 16;
-        const size_t need = in_bytes + kStepQueueBytes;   // beyond the summary: inputs, arrival queues
+        const size_t need = in_bytes + kStepQueueBytes + 16;   // beyond the summary: inputs, queues, counter
         lc.queue_off = static_cast<int32_t>(in_bytes / sizeof(float));
         if (need + kStepSummaryBytes <= static_cast<size_t>(lds_max) && g.seg_max <= kStepMaxSegment) {
-            for (const StepLoop& sl : kStepLoops) {
-                e = hipFuncSetAttribute(sl.fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(need));
-                if (e != hipSuccess) return e;
-            }
-            lc.step_loop = 0;
-            if (const char* env = std::getenv("GEONET_STEP_LOOP")) {
-                const int v = std::atoi(env);
-                if (v >= 0 && v < kStepLoopCount) lc.step_loop = v;
-            }
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&step_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    static_cast<int>(need));
+            if (e != hipSuccess) return e;
             lc.fused = true;
             lc.mode = 1;
             lc.stream_weights = false;
@@ -1293,13 +1302,7 @@ hipError_t launch_step(const DeviceGraph& g, const LaunchConfig& lc, int64_t t, 
     a.seg_vertex = g.seg_vertex;
     a.seg_chunk = g.seg_chunk;
     a.queue_off = lc.queue_off;
-    const dim3 grid(g.n_seg), block(lc.deliver_threads);
-    switch (lc.step_loop) {
-        case 0: hipExtLaunchKernelGGL((step_kernel<2, false>), grid, block, lc.lds_bytes, s, ev0, ev1, 0, a); break;
-        case 1: hipExtLaunchKernelGGL((step_kernel<3, false>), grid, block, lc.lds_bytes, s, ev0, ev1, 0, a); break;
-        case 2: hipExtLaunchKernelGGL((step_kernel<2, true>), grid, block, lc.lds_bytes, s, ev0, ev1, 0, a); break;
-        default: return hipErrorInvalidValue;
-    }
+    hipExtLaunchKernelGGL(step_kernel, dim3(g.n_seg), dim3(lc.deliver_threads), lc.lds_bytes, s, ev0, ev1, 0, a);
     return hipGetLastError();
 }
 
