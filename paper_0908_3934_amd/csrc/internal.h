@@ -192,6 +192,8 @@ struct MlpDevice {
     float* grad = nullptr;
     uint16_t* w1b = nullptr;      // BF16 copies
     uint16_t* w2b = nullptr;
+    uint16_t* w1t = nullptr;      // BF16 W1 and W2 as the fused forward kernel holds them in LDS
+    uint16_t* w2p = nullptr;      // (transposed, k reordered, 16-byte groups swizzled)
     uint16_t* Xb = nullptr;       // [cap x 64] BF16 standardised inputs of the last forward pass
     uint16_t* H1 = nullptr;       // [cap x 256] BF16 activations and gradients
     uint16_t* H2 = nullptr;
@@ -250,5 +252,6 @@ hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const floa
 hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, hipStream_t s);
 hipError_t mlp_adam(const MlpDevice& d, float lr, float beta1, float beta2, float eps, int64_t t, hipStream_t s);
 hipError_t mlp_refresh_bf16(const MlpDevice& d, hipStream_t s);
+hipError_t mlp_forward_fused(const MlpDevice& d, const float* X, int64_t B, float* logits, hipStream_t s);
 
 }  // namespace geonet

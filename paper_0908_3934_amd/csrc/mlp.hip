@@ -21,15 +21,35 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+// Round to nearest, ties to even; infinities stay, NaNs become quiet NaNs.
+// Branch-free (a select), since it runs once per activation.
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float x) {
-    uint32_t u = __builtin_bit_cast(uint32_t, x);
-    if ((u & 0x7F800000u) == 0x7F800000u) return static_cast<uint16_t>((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
-    u += 0x7FFFu + ((u >> 16) & 1u);          // round to nearest, ties to even
-    return static_cast<uint16_t>(u >> 16);
+    const uint32_t u = __builtin_bit_cast(uint32_t, x);
+    const uint32_t rne = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+    const uint32_t qnan = (u >> 16) | 0x40u;
+    return static_cast<uint16_t>((u & 0x7FFFFFFFu) > 0x7F800000u ? qnan : rne);
 }
 
 __device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
     return __builtin_bit_cast(float, static_cast<uint32_t>(b) << 16);
+}
+
+// Positions of W1[k][n] and W2[k][n] in the fused forward kernel's LDS images
+// (see mlp_forward_fused_kernel): row n holds column n of the weight matrix;
+// within a row, W2's k order follows the layout of the first product's
+// accumulators (slot q of row n holds k = 32t + 16f + 8(j/4) + 4h + j%4 for
+// q = 16(2t + f) + 8h + j), and the 16-byte groups of row n are XOR-swizzled
+// with n mod 8 so that 32 lanes reading one group of 32 rows spread over the
+// LDS banks.
+__device__ __forceinline__ int w1_image_index(int k, int n) {
+    return n * kMlpIn + (((k >> 3) ^ (n & 7)) << 3) + (k & 7);
+}
+
+__device__ __forceinline__ int w2_image_index(int k, int n) {
+    const int t = k >> 5, f = (k >> 4) & 1, r2 = k & 15;
+    const int h = (r2 >> 2) & 1, j = 4 * (r2 >> 3) + (r2 & 3);
+    const int q = 16 * (2 * t + f) + 8 * h + j;
+    return n * kMlpH + (((q >> 3) ^ (n & 7)) << 3) + (q & 7);
 }
 
 // ---------------------------------------------------------------------------
@@ -324,6 +344,8 @@ struct AdamArgs {
     const float* g;
     uint16_t* w1b;
     uint16_t* w2b;
+    uint16_t* w1t;
+    uint16_t* w2p;
     int64_t n;
     float lr, b1, b2, eps, c1, c2;   // c1 = 1 - b1^t, c2 = 1 - b2^t
 };
@@ -338,13 +360,172 @@ __global__ void __launch_bounds__(256) adam_kernel(AdamArgs a) {
     a.v[i] = v;
     const float p = a.p[i] - a.lr * (m / a.c1) / (sqrtf(v / a.c2) + a.eps);
     a.p[i] = p;
-    if (i < kMlpW1) a.w1b[i] = f32_to_bf16_bits(p);
-    else if (i >= kMlpW2Off && i < kMlpW2Off + kMlpW2) a.w2b[i - kMlpW2Off] = f32_to_bf16_bits(p);
+    if (i < kMlpW1) {
+        const uint16_t b = f32_to_bf16_bits(p);
+        a.w1b[i] = b;
+        a.w1t[w1_image_index(static_cast<int>(i) / kMlpH, static_cast<int>(i) % kMlpH)] = b;
+    } else if (i >= kMlpW2Off && i < kMlpW2Off + kMlpW2) {
+        const int e = static_cast<int>(i - kMlpW2Off);
+        const uint16_t b = f32_to_bf16_bits(p);
+        a.w2b[e] = b;
+        a.w2p[w2_image_index(e / kMlpH, e % kMlpH)] = b;
+    }
 }
 
-__global__ void __launch_bounds__(256) to_bf16_kernel(const float* x, uint16_t* y, int64_t n) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = f32_to_bf16_bits(x[i]);
+// BF16 copies of W1 and W2 from the FP32 parameters, row-major and as the
+// fused forward kernel's LDS images.
+__global__ void __launch_bounds__(256) weights_bf16_kernel(const float* params, uint16_t* w1b, uint16_t* w2b,
+                                                           uint16_t* w1t, uint16_t* w2p) {
+    const int i = static_cast<int>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < kMlpW1) {
+        const uint16_t b = f32_to_bf16_bits(params[kMlpW1Off + i]);
+        w1b[i] = b;
+        w1t[w1_image_index(i / kMlpH, i % kMlpH)] = b;
+    } else if (i < kMlpW1 + kMlpW2) {
+        const int e = i - kMlpW1;
+        const uint16_t b = f32_to_bf16_bits(params[kMlpW2Off + e]);
+        w2b[e] = b;
+        w2p[w2_image_index(e / kMlpH, e % kMlpH)] = b;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused forward pass for inference: logits = head(BF16(ReLU(BF16(ReLU(Xb W1
+// + b1)) W2 + b2))) with the same rounding points as the layered path.  Both
+// products are computed transposed (H1^T = W1^T Xb^T, H2^T = W2^T H1^T) so
+// that every lane owns one row (pair) from input to logit: the MFMA B
+// fragments are the lane's own standardised features (read from memory) and
+// then its own H1 values (straight from the first product's accumulators,
+// which is why W2's image orders k as they lie there); the A fragments come
+// from the weight images in LDS (32 + 128 KiB, staged once per workgroup).
+// One wave per 32 rows, rows strided over the grid; the head's dot product
+// ends with one exchange between the two half-waves that share a row.
+// ---------------------------------------------------------------------------
+struct FwdArgs {
+    const float* X;
+    const float* shift;
+    const float* scale;
+    const uint16_t* w1t;
+    const uint16_t* w2p;
+    const float* params;
+    float* logits;
+    int64_t B;
+};
+
+__global__ void __launch_bounds__(256) mlp_forward_fused_kernel(FwdArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t W1s[kMlpH * kMlpIn];
+    __shared__ __attribute__((aligned(16))) uint16_t W2s[kMlpH * kMlpH];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, col = lane & 31;
+    for (int i = tid; i < kMlpH * kMlpIn / 8; i += 256)
+        reinterpret_cast<uint4*>(W1s)[i] = reinterpret_cast<const uint4*>(a.w1t)[i];
+    for (int i = tid; i < kMlpH * kMlpH / 8; i += 256)
+        reinterpret_cast<uint4*>(W2s)[i] = reinterpret_cast<const uint4*>(a.w2p)[i];
+    __syncthreads();
+    const float* b1 = a.params + kMlpB1Off;
+    const float* b2 = a.params + kMlpB2Off;
+    const float* w3 = a.params + kMlpW3Off;
+    const float b3 = a.params[kMlpB3Off];
+    const int64_t n_tiles = (a.B + 31) / 32;
+    for (int64_t tile = static_cast<int64_t>(blockIdx.x) * 4 + wave; tile < n_tiles;
+         tile += static_cast<int64_t>(gridDim.x) * 4) {
+        const int64_t m = tile * 32 + col;
+        const bool valid = m < a.B;
+        const float* xr = a.X + (valid ? m : 0) * kMlpIn;
+        // B fragments of Xb^T: step s takes features 16s + 8h .. 16s + 8h + 7
+        bf16x8 xb[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int f0 = 16 * s + 8 * h;
+            const float4 x0 = reinterpret_cast<const float4*>(xr + f0)[0];
+            const float4 x1 = reinterpret_cast<const float4*>(xr + f0)[1];
+            const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+            uint32_t w[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t lo = f32_to_bf16_bits((xv[2 * j] - a.shift[f0 + 2 * j]) * a.scale[f0 + 2 * j]);
+                const uint32_t hi = f32_to_bf16_bits((xv[2 * j + 1] - a.shift[f0 + 2 * j + 1]) * a.scale[f0 + 2 * j + 1]);
+                w[j] = lo | (hi << 16);
+            }
+            xb[s] = __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+        }
+        // The two products interleaved over the first's output blocks: block t
+        // of H1^T (n = 32t .. 32t + 31; acc1[i] is n = 32t + 8(i/4) + 4h + i%4
+        // of row m) becomes, after bias + ReLU + BF16, the lane's two B
+        // fragments of k step (t, f) of the second product, which go into all
+        // eight accumulators of H2^T at once (acc2[u][i] is n2 = 32u + 8(i/4)
+        // + 4h + i%4 of row m).  Only acc2 lives across the blocks.
+        f32x16 acc2[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc2[u][i] = 0.0f;
+#pragma unroll 1
+        for (int t = 0; t < 8; ++t) {
+            f32x16 acc1;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc1[i] = 0.0f;
+            const int n = 32 * t + col;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const bf16x8 av = *reinterpret_cast<const bf16x8*>(&W1s[n * kMlpIn + (((2 * s + h) ^ (n & 7)) << 3)]);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, xb[s], acc1, 0, 0, 0);
+            }
+            bf16x8 hb[2];
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                // values i = 8f .. 8f + 7: n = 32t + 16f + 4h + {0..3, 8..11};
+                // the bias words are wave-uniform loads of both half-waves' values
+                const float* bt = b1 + 32 * t + 16 * f;
+                const float4 l0 = *reinterpret_cast<const float4*>(bt), l1 = *reinterpret_cast<const float4*>(bt + 4);
+                const float4 u0 = *reinterpret_cast<const float4*>(bt + 8), u1 = *reinterpret_cast<const float4*>(bt + 12);
+                const float4 bl = h ? l1 : l0, bh = h ? u1 : u0;
+                const float bias[8] = {bl.x, bl.y, bl.z, bl.w, bh.x, bh.y, bh.z, bh.w};
+                uint32_t w[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float v0 = acc1[8 * f + 2 * j] + bias[2 * j];
+                    const float v1 = acc1[8 * f + 2 * j + 1] + bias[2 * j + 1];
+                    w[j] = static_cast<uint32_t>(f32_to_bf16_bits(v0 > 0.0f ? v0 : 0.0f)) |
+                           (static_cast<uint32_t>(f32_to_bf16_bits(v1 > 0.0f ? v1 : 0.0f)) << 16);
+                }
+                hb[f] = __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+            }
+#pragma unroll
+            for (int f = 0; f < 2; ++f)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int n2 = 32 * u + col;
+                    const int grp = 2 * (2 * t + f) + h;
+                    const bf16x8 av = *reinterpret_cast<const bf16x8*>(&W2s[n2 * kMlpH + ((grp ^ (n2 & 7)) << 3)]);
+                    acc2[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, hb[f], acc2[u], 0, 0, 0);
+                }
+        }
+        // bias + ReLU + BF16, then the head's dot product over the lane's 128
+        // values of n2 and its partner half-wave's 128
+        float part = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                // n2 = 32u + 8q + 4h + r: wave-uniform loads of both halves' words
+                const float* bu = b2 + 32 * u + 8 * q;
+                const float* wu = w3 + 32 * u + 8 * q;
+                const float4 b_0 = *reinterpret_cast<const float4*>(bu), b_1 = *reinterpret_cast<const float4*>(bu + 4);
+                const float4 w_0 = *reinterpret_cast<const float4*>(wu), w_1 = *reinterpret_cast<const float4*>(wu + 4);
+                const float4 bq = h ? b_1 : b_0, wq = h ? w_1 : w_0;
+                const float bb[4] = {bq.x, bq.y, bq.z, bq.w}, ww[4] = {wq.x, wq.y, wq.z, wq.w};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float x = acc2[u][4 * q + r] + bb[r];
+                    part += bf16_bits_to_f32(f32_to_bf16_bits(x > 0.0f ? x : 0.0f)) * ww[r];
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        part += __shfl_xor(part, 32, 64);
+        if (h == 0 && valid) a.logits[m] = part + b3;
+    }
 }
 
 template <int kEpi, int BM, int BN>
@@ -488,6 +669,26 @@ hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, hipStream
     return hipGetLastError();
 }
 
+hipError_t mlp_forward_fused(const MlpDevice& d, const float* X, int64_t B, float* logits, hipStream_t s) {
+    int dev = 0, n_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    FwdArgs a;
+    a.X = X;
+    a.shift = d.in_shift;
+    a.scale = d.in_scale;
+    a.w1t = d.w1t;
+    a.w2p = d.w2p;
+    a.params = d.params;
+    a.logits = logits;
+    a.B = B;
+    // one workgroup per CU (the weight images fill its LDS), fewer for small B
+    const int64_t blocks = std::min<int64_t>(std::max<int64_t>((B + 127) / 128, 1), n_cu);
+    hipLaunchKernelGGL(mlp_forward_fused_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t mlp_adam(const MlpDevice& d, float lr, float beta1, float beta2, float eps, int64_t t, hipStream_t s) {
     AdamArgs a;
     a.p = d.params;
@@ -496,6 +697,8 @@ hipError_t mlp_adam(const MlpDevice& d, float lr, float beta1, float beta2, floa
     a.g = d.grad;
     a.w1b = d.w1b;
     a.w2b = d.w2b;
+    a.w1t = d.w1t;
+    a.w2p = d.w2p;
     a.n = kMlpParams;
     a.lr = lr;
     a.b1 = beta1;
@@ -508,10 +711,8 @@ hipError_t mlp_adam(const MlpDevice& d, float lr, float beta1, float beta2, floa
 }
 
 hipError_t mlp_refresh_bf16(const MlpDevice& d, hipStream_t s) {
-    hipLaunchKernelGGL(to_bf16_kernel, dim3((kMlpW1 + 255) / 256), dim3(256), 0, s, d.params + kMlpW1Off, d.w1b,
-                       static_cast<int64_t>(kMlpW1));
-    hipLaunchKernelGGL(to_bf16_kernel, dim3((kMlpW2 + 255) / 256), dim3(256), 0, s, d.params + kMlpW2Off, d.w2b,
-                       static_cast<int64_t>(kMlpW2));
+    hipLaunchKernelGGL(weights_bf16_kernel, dim3((kMlpW1 + kMlpW2 + 255) / 256), dim3(256), 0, s, d.params, d.w1b,
+                       d.w2b, d.w1t, d.w2p);
     return hipGetLastError();
 }
 

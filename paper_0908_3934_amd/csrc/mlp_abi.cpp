@@ -33,8 +33,8 @@ hipError_t alloc(T** p, size_t n) {
 }
 
 void release(MlpDevice& d) {
-    void* ps[] = {d.params, d.adam_m, d.adam_v, d.grad, d.w1b,  d.w2b,  d.Xb,       d.H1,
-                  d.H2,     d.dH1,    d.dH2,    d.logits, d.loss, d.in_shift, d.in_scale};
+    void* ps[] = {d.params, d.adam_m, d.adam_v, d.grad,   d.w1b,  d.w2b,      d.w1t,      d.w2p, d.Xb,
+                  d.H1,     d.H2,     d.dH1,    d.dH2,    d.logits, d.loss, d.in_shift, d.in_scale};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     d = MlpDevice{};
@@ -82,7 +82,8 @@ net_status net_mlp_create(net_mlp_t** out) {
     MlpDevice& d = m->d;
     if (alloc(&d.params, kMlpParams) != hipSuccess || alloc(&d.adam_m, kMlpParams) != hipSuccess ||
         alloc(&d.adam_v, kMlpParams) != hipSuccess || alloc(&d.grad, kMlpParams) != hipSuccess ||
-        alloc(&d.w1b, kMlpW1) != hipSuccess || alloc(&d.w2b, kMlpW2) != hipSuccess || alloc(&d.loss, 1) != hipSuccess ||
+        alloc(&d.w1b, kMlpW1) != hipSuccess || alloc(&d.w2b, kMlpW2) != hipSuccess ||
+        alloc(&d.w1t, kMlpW1) != hipSuccess || alloc(&d.w2p, kMlpW2) != hipSuccess || alloc(&d.loss, 1) != hipSuccess ||
         alloc(&d.in_shift, kMlpIn) != hipSuccess || alloc(&d.in_scale, kMlpIn) != hipSuccess) {
         release(d);
         delete m;
@@ -144,9 +145,8 @@ net_status net_mlp_forward(net_mlp_t* m, const float* x_dev, int64_t rows, float
     if (st != NET_OK) return st;
     if (!logits_dev) return mfail(NET_E_ARG, "net_mlp_forward: logits are NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((st = reserve(m, rows, s)) != NET_OK) return st;
-    hipError_t e = mlp_forward(m->d, x_dev, rows, nullptr, false, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(logits_dev, m->d.logits, rows * sizeof(float), hipMemcpyDeviceToDevice, s);
+    // one fused kernel: no activation workspace
+    hipError_t e = mlp_forward_fused(m->d, x_dev, rows, logits_dev, s);
     if (e != hipSuccess) return mdev(m, e, "net_mlp_forward");
     return NET_OK;
 }

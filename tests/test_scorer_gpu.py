@@ -74,3 +74,36 @@ def test_training_reduces_loss():
         net.train_step(Xd, yd, 2e-3)
     _, l1 = net.grad(Xd, yd)
     assert float(l1.cpu()) < 0.25 * float(l0.cpu())
+
+
+@pytest.mark.parametrize("rows", [70001])
+def test_forward_many_tiles_with_input_norm(rows):
+    """Forward (one fused kernel) over many 32-row tiles per wave with a
+    ragged last tile, under a non-trivial input standardisation."""
+    import torch
+    net, p, X, y, Xd, yd = _setup(rows, 4)
+    rng = np.random.default_rng(8)
+    shift = rng.normal(0, 0.5, M.IN).astype(np.float32)
+    scale = rng.uniform(0.5, 2.0, M.IN).astype(np.float32)
+    net.set_input_norm(shift, scale)
+    z = net.forward(Xd).cpu().numpy().astype(np.float64)
+    zr, _ = M.forward(p.astype(np.float64), X.astype(np.float64), bf=True,
+                      shift=shift.astype(np.float64), scale=scale.astype(np.float64))
+    scale_z = max(1.0, np.abs(zr).max())
+    assert np.abs(z - zr).max() <= 2e-3 * scale_z
+    assert np.median(np.abs(z - zr)) <= 1e-4 * scale_z
+
+
+def test_forward_after_training_steps():
+    """Adam keeps every BF16 copy of the weights current, including the
+    layout the fused forward kernel stages: logits after a few steps match
+    the reference evaluated at the parameters read back."""
+    import torch
+    net, p, X, y, Xd, yd = _setup(3000, 21)
+    for _ in range(3):
+        net.train_step(Xd, yd, 1e-2)
+    p1 = net.get_params().astype(np.float64)
+    z = net.forward(Xd).cpu().numpy().astype(np.float64)
+    zr, _ = M.forward(p1, X.astype(np.float64), bf=True)
+    scale_z = max(1.0, np.abs(zr).max())
+    assert np.abs(z - zr).max() <= 2e-3 * scale_z
