@@ -412,33 +412,59 @@ struct FwdArgs {
     int64_t B;
 };
 
-__global__ void __launch_bounds__(256) mlp_forward_fused_kernel(FwdArgs a) {
+constexpr int kFwdThreads = 512;   // eight waves: two per SIMD
+
+__global__ void __launch_bounds__(kFwdThreads) mlp_forward_fused_kernel(FwdArgs a) {
     __shared__ __attribute__((aligned(16))) uint16_t W1s[kMlpH * kMlpIn];
     __shared__ __attribute__((aligned(16))) uint16_t W2s[kMlpH * kMlpH];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, col = lane & 31;
-    for (int i = tid; i < kMlpH * kMlpIn / 8; i += 256)
-        reinterpret_cast<uint4*>(W1s)[i] = reinterpret_cast<const uint4*>(a.w1t)[i];
-    for (int i = tid; i < kMlpH * kMlpH / 8; i += 256)
-        reinterpret_cast<uint4*>(W2s)[i] = reinterpret_cast<const uint4*>(a.w2p)[i];
+    constexpr int kWaves = kFwdThreads / 64;
+    const int64_t n_tiles = (a.B + 31) / 32;
+    const int64_t tile_stride = static_cast<int64_t>(gridDim.x) * kWaves;
+    // The lane's raw features of its next tile (row m, features 16s + 8h ..
+    // 16s + 8h + 7 for s = 0..3), loaded one tile ahead; the first ones are
+    // in flight while the weights are staged.
+    float4 xraw[8];
+    auto load_x = [&](int64_t tile) {
+        const int64_t m = tile * 32 + col;
+        const float* xr = a.X + (m < a.B ? m : 0) * kMlpIn;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            xraw[2 * s] = reinterpret_cast<const float4*>(xr + 16 * s + 8 * h)[0];
+            xraw[2 * s + 1] = reinterpret_cast<const float4*>(xr + 16 * s + 8 * h)[1];
+        }
+    };
+    int64_t tile = static_cast<int64_t>(blockIdx.x) * kWaves + wave;
+    if (tile < n_tiles) load_x(tile);
+    // weights: every thread issues all its 16-byte loads before its LDS
+    // writes (a fixed count per thread, so no wait sits between the loads)
+    {
+        constexpr int k1 = kMlpH * kMlpIn / 8 / kFwdThreads, k2 = kMlpH * kMlpH / 8 / kFwdThreads;
+        uint4 r1[k1], r2[k2];
+#pragma unroll
+        for (int q = 0; q < k1; ++q) r1[q] = reinterpret_cast<const uint4*>(a.w1t)[q * kFwdThreads + tid];
+#pragma unroll
+        for (int q = 0; q < k2; ++q) r2[q] = reinterpret_cast<const uint4*>(a.w2p)[q * kFwdThreads + tid];
+#pragma unroll
+        for (int q = 0; q < k1; ++q) reinterpret_cast<uint4*>(W1s)[q * kFwdThreads + tid] = r1[q];
+#pragma unroll
+        for (int q = 0; q < k2; ++q) reinterpret_cast<uint4*>(W2s)[q * kFwdThreads + tid] = r2[q];
+    }
     __syncthreads();
     const float* b1 = a.params + kMlpB1Off;
     const float* b2 = a.params + kMlpB2Off;
     const float* w3 = a.params + kMlpW3Off;
     const float b3 = a.params[kMlpB3Off];
-    const int64_t n_tiles = (a.B + 31) / 32;
-    for (int64_t tile = static_cast<int64_t>(blockIdx.x) * 4 + wave; tile < n_tiles;
-         tile += static_cast<int64_t>(gridDim.x) * 4) {
+    for (; tile < n_tiles; tile += tile_stride) {
         const int64_t m = tile * 32 + col;
         const bool valid = m < a.B;
-        const float* xr = a.X + (valid ? m : 0) * kMlpIn;
         // B fragments of Xb^T: step s takes features 16s + 8h .. 16s + 8h + 7
         bf16x8 xb[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int f0 = 16 * s + 8 * h;
-            const float4 x0 = reinterpret_cast<const float4*>(xr + f0)[0];
-            const float4 x1 = reinterpret_cast<const float4*>(xr + f0)[1];
+            const float4 x0 = xraw[2 * s], x1 = xraw[2 * s + 1];
             const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
             uint32_t w[4];
 #pragma unroll
@@ -449,6 +475,7 @@ __global__ void __launch_bounds__(256) mlp_forward_fused_kernel(FwdArgs a) {
             }
             xb[s] = __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
         }
+        if (tile + tile_stride < n_tiles) load_x(tile + tile_stride);
         // The two products interleaved over the first's output blocks: block t
         // of H1^T (n = 32t .. 32t + 31; acc1[i] is n = 32t + 8(i/4) + 4h + i%4
         // of row m) becomes, after bias + ReLU + BF16, the lane's two B
@@ -684,8 +711,8 @@ hipError_t mlp_forward_fused(const MlpDevice& d, const float* X, int64_t B, floa
     a.logits = logits;
     a.B = B;
     // one workgroup per CU (the weight images fill its LDS), fewer for small B
-    const int64_t blocks = std::min<int64_t>(std::max<int64_t>((B + 127) / 128, 1), n_cu);
-    hipLaunchKernelGGL(mlp_forward_fused_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, a);
+    const int64_t blocks = std::min<int64_t>(std::max<int64_t>((B + 32 * kFwdThreads / 64 - 1) / (32 * kFwdThreads / 64), 1), n_cu);
+    hipLaunchKernelGGL(mlp_forward_fused_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kFwdThreads), 0, s, a);
     return hipGetLastError();
 }
 
