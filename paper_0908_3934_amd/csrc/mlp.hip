@@ -266,30 +266,42 @@ __global__ void __launch_bounds__(256) head_kernel(HeadArgs a) {
     const float inv_b = 1.0f / static_cast<float>(a.B);
     float gw3[4] = {0.0f, 0.0f, 0.0f, 0.0f}, gb2[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     float gl = 0.0f, gb3 = 0.0f;
-    for (int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + wave; row < a.B; row += n_waves) {
-        float h[4], s = 0.0f;
+    // kRows rows per pass, their loads issued together
+    constexpr int kRows = 4;
+    for (int64_t row0 = static_cast<int64_t>(blockIdx.x) * 4 + wave; row0 < a.B; row0 += kRows * n_waves) {
+        float h[kRows][4], y[kRows];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            h[q] = bf16_bits_to_f32(a.H2[row * kMlpH + q * 64 + lane]);
-            s += h[q] * w3r[q];
+        for (int r = 0; r < kRows; ++r) {
+            const int64_t row = row0 + r * n_waves;
+            const int64_t rr = row < a.B ? row : row0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) h[r][q] = bf16_bits_to_f32(a.H2[rr * kMlpH + q * 64 + lane]);
+            y[r] = a.y ? a.y[rr] : 0.0f;
         }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-        const float logit = s + b3;
-        if (lane == 0) a.logits[row] = logit;
-        if (!a.y) continue;
-        const float y = a.y[row];
-        const float p = 1.0f / (1.0f + expf(-logit));
-        const float dl = (p - y) * inv_b;
-        // log(1 + exp(-|z|)) + max(z, 0) - z*y
-        gl += (log1pf(expf(-fabsf(logit))) + fmaxf(logit, 0.0f) - logit * y) * inv_b;
-        gb3 += dl;
+        for (int r = 0; r < kRows; ++r) {
+            const int64_t row = row0 + r * n_waves;
+            if (row >= a.B) break;                  // uniform over the wave
+            float s = 0.0f;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint16_t g = f32_to_bf16_bits(h[q] > 0.0f ? dl * w3r[q] : 0.0f);
-            a.dH2[row * kMlpH + q * 64 + lane] = g;
-            gb2[q] += bf16_bits_to_f32(g);
-            gw3[q] += dl * h[q];
+            for (int q = 0; q < 4; ++q) s += h[r][q] * w3r[q];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+            const float logit = s + b3;
+            if (lane == 0) a.logits[row] = logit;
+            if (!a.y) continue;
+            const float p = 1.0f / (1.0f + expf(-logit));
+            const float dl = (p - y[r]) * inv_b;
+            // log(1 + exp(-|z|)) + max(z, 0) - z*y
+            gl += (log1pf(expf(-fabsf(logit))) + fmaxf(logit, 0.0f) - logit * y[r]) * inv_b;
+            gb3 += dl;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint16_t g = f32_to_bf16_bits(h[r][q] > 0.0f ? dl * w3r[q] : 0.0f);
+                a.dH2[row * kMlpH + q * 64 + lane] = g;
+                gb2[q] += bf16_bits_to_f32(g);
+                gw3[q] += dl * h[r][q];
+            }
         }
     }
     if (!a.y) return;                        // uniform over the grid
@@ -325,10 +337,20 @@ __global__ void __launch_bounds__(256) colsum_kernel(const uint16_t* X, int64_t 
     const int64_t r1 = r0 + rows_per < B ? r0 + rows_per : B;
     const uint32_t* X32 = reinterpret_cast<const uint32_t*>(X);
     float s0 = 0.0f, s1 = 0.0f;
-    for (int64_t r = r0 + ro; r < r1; r += 2) {
-        const uint32_t v = X32[r * (kMlpH / 2) + cp];
-        s0 += bf16_bits_to_f32(v & 0xFFFFu);
-        s1 += bf16_bits_to_f32(v >> 16);
+    // eight rows' loads in flight per pass (rows past r1 read row r0 and add 0)
+    for (int64_t rb = r0 + ro; rb < r1; rb += 16) {
+        uint32_t v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t r = rb + 2 * q;
+            v[q] = X32[(r < r1 ? r : r0) * (kMlpH / 2) + cp];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const bool in = rb + 2 * q < r1;
+            s0 += in ? bf16_bits_to_f32(v[q] & 0xFFFFu) : 0.0f;
+            s1 += in ? bf16_bits_to_f32(v[q] >> 16) : 0.0f;
+        }
     }
     red[ro][2 * cp] = s0;
     red[ro][2 * cp + 1] = s1;
