@@ -130,8 +130,11 @@ typedef struct {
 #define NET_BUILD_FUSED_STEP 1024        /* one network: one kernel per step, each workgroup
                                              delivering into and then updating its own range of
                                              vertices (the slot list is cut into one segment per
-                                             CU; needs room for the summary and a segment's inputs
-                                             in LDS, else the two kernels are used) */
+                                             CU). Needs at most 2^20 vertices (the summary in a
+                                             fixed 128 KiB of LDS), segments of at most 6,080
+                                             vertices, fewer than 2^32 edge slots and the full
+                                             summary (not with NET_BUILD_SUMMARY_HALF); otherwise
+                                             the two kernels are used. net_info reports which. */
 #define NET_BUILD_SINGLE_LAUNCH 32        /* one network: run all steps of a call in one launch of
                                              the LDS-resident kernel ensembles use, when the
                                              network fits one workgroup's LDS */

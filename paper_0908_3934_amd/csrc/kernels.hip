@@ -3,15 +3,22 @@
 //   deliver_kernel      I_j(t) = sum over in-edges i -> j of w_ij * s_i(t - d_ij)
 //                       (Section 3.2, Eq. izpsc last term) over the CSR-by-target
 //                       slot list; a one-bit-per-vertex "fired within the last
-//                       D steps" summary, staged in LDS, filters the edges whose
-//                       exact history bit must be fetched.
+//                       W steps" summary, staged in LDS, filters the edges
+//                       whose sources' two last spike ages are gathered; the
+//                       ages (and, rarely, the history ring) decide exactly.
 //   node_update_kernel  spike test (Eq. spd), LIF Euler transition with the
 //                       refractory hold (Section 3.1), control and noise
 //                       (Philox4x32-10 + Box-Muller), spike-history ring,
 //                       recent-spike summary, calcium and camera frames
 //                       (Section 3.3).
+//   step_kernel         one step in one launch: each workgroup delivers the
+//                       in-edges of its own vertex segment into LDS (the
+//                       same candidate test as deliver_kernel) and then runs
+//                       the vertex update on that segment.
 //   observe_kernel      fluorescence n*cbar + b + gamma*xi (Section 3.3) and
 //                       state read-outs.
+//   ensemble_kernel     many small networks, all steps of a call in one
+//                       launch, each network's state resident in LDS.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
