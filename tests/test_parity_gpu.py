@@ -433,3 +433,31 @@ def test_full_size_fused_step_open_loop():
     own = o["v"] >= spec.v_th
     disagree = int((own != raster.astype(bool)).sum())
     assert disagree <= 0.005 * max(int(raster.sum()), 1), disagree
+
+
+@pytest.mark.timeout(900)
+def test_full_size_ensemble_sampled_networks():
+    """The benchmarked ensemble (512 networks of 64..4096 vertices, one
+    autotuned launch for all steps) against the oracle on a sample of its
+    networks, smallest and largest included: rasters of 2,000 steps to the
+    usual bar."""
+    gn, torch = _gn()
+    specs = synth.config3()
+    T = 2000
+    net = gn.Net(specs, flags=gn.NET_BUILD_AUTOTUNE)
+    assert net.info()["n_nets"] == 512
+    out = net.step(T, raster=True)
+    torch.cuda.synchronize()
+    raster = gn.unpack_raster(out["raster"], net.n_total)
+    offs = net.node_offsets()
+    net.close()
+    sizes = np.array([s.n for s in specs])
+    picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 0, 137, 301, 511})
+    fired = 0
+    for k in picks:
+        o = oracle.OracleNet(specs[k]).step(T)
+        sub = raster[:, offs[k]:offs[k + 1]].astype(bool)
+        J = jaccard(sub, o["raster"].astype(bool))
+        assert J >= JACCARD_MIN, (k, specs[k].n, J)
+        fired += int(o["raster"].sum())
+    assert fired > 100
