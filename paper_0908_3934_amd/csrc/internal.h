@@ -184,6 +184,9 @@ constexpr int kMlpB2Off = kMlpW2Off + kMlpW2;                   // b2[256]
 constexpr int kMlpW3Off = kMlpB2Off + kMlpH;                    // w3[256]
 constexpr int kMlpB3Off = kMlpW3Off + kMlpH;                    // b3
 constexpr int kMlpParams = kMlpB3Off + 1;                        // 82,689
+// The head's gradient sums (w3[256], b2[256], b3, loss) are spread over
+// replicas so that few workgroups add into any one address.
+constexpr int kHeadReplicas = 32, kHeadPart = 2 * kMlpH + 8;
 
 struct MlpDevice {
     float* params = nullptr;      // FP32 master weights
@@ -201,6 +204,7 @@ struct MlpDevice {
     uint16_t* dH2 = nullptr;
     float* logits = nullptr;      // [cap]
     float* loss = nullptr;        // [1]
+    float* head_part = nullptr;   // [kHeadReplicas][kHeadPart] head gradient partial sums (zero between steps)
     float* in_shift = nullptr;    // [64] input standardisation: x' = (x - shift) * scale
     float* in_scale = nullptr;    // [64]
     int64_t cap = 0;

@@ -59,10 +59,10 @@ __device__ __forceinline__ int w2_image_index(int k, int n) {
 // 16-byte groups of 8 elements along that dimension (a k-contiguous group
 // goes to LDS as is, an m- or n-contiguous one is transposed on the way,
 // since LDS holds both tiles k-contiguous for the MFMA fragments).
-// Block tile 128 x 128, four waves of 64 x 64 (2 x 2 tiles of
-// v_mfma_f32_32x32x16_bf16), K staged 32 at a time; the next stage's groups
-// are loaded into registers while the current stage's MFMAs run.  Split-K:
-// blockIdx.z takes K range [z*k_chunk, min(K, (z+1)*k_chunk)).
+// Block tile BM x BN, four waves of (BM/2) x (BN/2) (tiles of
+// v_mfma_f32_32x32x16_bf16), K staged KS at a time (32 or 128); the next
+// stage's groups are loaded into registers while the current stage's MFMAs
+// run.  Split-K: blockIdx.z takes K range [z*k_chunk, min(K, (z+1)*k_chunk)).
 // ---------------------------------------------------------------------------
 enum Epilogue { kBiasReluBf16 = 0, kMaskBf16 = 1, kAtomicF32 = 2 };
 
@@ -77,40 +77,42 @@ struct GemmArgs {
     float* out_f32;           // [M x N] row-major (atomic add)
 };
 
-constexpr int kKs = 32, kLdsK = kKs + 8;   // K per stage; LDS rows padded against bank conflicts
+// LDS rows hold KS + 8 elements (padded against bank conflicts).
+template <int KS>
+constexpr int lds_k() { return KS + 8; }
 
-// 16-byte groups of a BM x kKs tile per thread (256 threads).
-template <int BM, int BN>
+// 16-byte groups of a BM x KS tile per thread (256 threads).
+template <int BM, int BN, int KS>
 struct StageRegs {
-    uint4 a[BM * kKs / 8 / 256];
-    uint4 b[BN * kKs / 8 / 256];
+    uint4 a[BM * KS / 8 / 256];
+    uint4 b[BN * KS / 8 / 256];
 };
 
-// Group e of an R-row tile: for a k-contiguous operand, tile row e / 4 and k
-// offset (e % 4) * 8; for an m/n-contiguous one, k offset e / (R / 8) and
-// tile row (e % (R / 8)) * 8.
-template <int R>
+// Group e of an R-row tile: for a k-contiguous operand, tile row
+// e / (KS / 8) and k offset (e % (KS / 8)) * 8; for an m/n-contiguous one, k
+// offset e / (R / 8) and tile row (e % (R / 8)) * 8.
+template <int R, int KS>
 __device__ __forceinline__ void group_pos(int e, bool kc, int* row, int* kk) {
-    *row = kc ? e / 4 : (e % (R / 8)) * 8;
-    *kk = kc ? (e % 4) * 8 : e / (R / 8);
+    *row = kc ? e / (KS / 8) : (e % (R / 8)) * 8;
+    *kk = kc ? (e % (KS / 8)) * 8 : e / (R / 8);
 }
 
-template <int BM, int BN>
-__device__ __forceinline__ void load_stage(StageRegs<BM, BN>& r, const GemmArgs& g, bool a_kc, bool b_kc, int64_t m0,
-                                           int64_t n0, int64_t k0, int64_t k_hi, int tid) {
+template <int BM, int BN, int KS>
+__device__ __forceinline__ void load_stage(StageRegs<BM, BN, KS>& r, const GemmArgs& g, bool a_kc, bool b_kc,
+                                           int64_t m0, int64_t n0, int64_t k0, int64_t k_hi, int tid) {
 #pragma unroll
-    for (int q = 0; q < BM * kKs / 8 / 256; ++q) {
+    for (int q = 0; q < BM * KS / 8 / 256; ++q) {
         int row, kk;
-        group_pos<BM>(tid + 256 * q, a_kc, &row, &kk);
+        group_pos<BM, KS>(tid + 256 * q, a_kc, &row, &kk);
         const int64_t m = m0 + row, k = k0 + kk;
         uint4 va = make_uint4(0u, 0u, 0u, 0u);
         if (m < g.M && k < k_hi) va = *reinterpret_cast<const uint4*>(g.A + m * g.a_rs + k * g.a_cs);
         r.a[q] = va;
     }
 #pragma unroll
-    for (int q = 0; q < BN * kKs / 8 / 256; ++q) {
+    for (int q = 0; q < BN * KS / 8 / 256; ++q) {
         int row, kk;
-        group_pos<BN>(tid + 256 * q, b_kc, &row, &kk);
+        group_pos<BN, KS>(tid + 256 * q, b_kc, &row, &kk);
         const int64_t n = n0 + row, k = k0 + kk;
         uint4 vb = make_uint4(0u, 0u, 0u, 0u);
         if (n < g.N && k < k_hi) vb = *reinterpret_cast<const uint4*>(g.B + k * g.b_rs + n * g.b_cs);
@@ -119,7 +121,8 @@ __device__ __forceinline__ void load_stage(StageRegs<BM, BN>& r, const GemmArgs&
 }
 
 // Writes 8 BF16 of a group to LDS: along k (one 16-byte store) or down 8 rows.
-__device__ __forceinline__ void put_group(uint16_t (*T)[kLdsK], int row, int kk, bool kc, const uint4& v) {
+template <int KS>
+__device__ __forceinline__ void put_group(uint16_t (*T)[lds_k<KS>()], int row, int kk, bool kc, const uint4& v) {
     if (kc) {
         *reinterpret_cast<uint4*>(&T[row][kk]) = v;
     } else {
@@ -132,30 +135,30 @@ __device__ __forceinline__ void put_group(uint16_t (*T)[kLdsK], int row, int kk,
     }
 }
 
-template <int BM, int BN>
-__device__ __forceinline__ void store_stage(const StageRegs<BM, BN>& r, bool a_kc, bool b_kc, int tid,
-                                            uint16_t (*As)[kLdsK], uint16_t (*Bs)[kLdsK]) {
+template <int BM, int BN, int KS>
+__device__ __forceinline__ void store_stage(const StageRegs<BM, BN, KS>& r, bool a_kc, bool b_kc, int tid,
+                                            uint16_t (*As)[lds_k<KS>()], uint16_t (*Bs)[lds_k<KS>()]) {
 #pragma unroll
-    for (int q = 0; q < BM * kKs / 8 / 256; ++q) {
+    for (int q = 0; q < BM * KS / 8 / 256; ++q) {
         int row, kk;
-        group_pos<BM>(tid + 256 * q, a_kc, &row, &kk);
-        put_group(As, row, kk, a_kc, r.a[q]);
+        group_pos<BM, KS>(tid + 256 * q, a_kc, &row, &kk);
+        put_group<KS>(As, row, kk, a_kc, r.a[q]);
     }
 #pragma unroll
-    for (int q = 0; q < BN * kKs / 8 / 256; ++q) {
+    for (int q = 0; q < BN * KS / 8 / 256; ++q) {
         int row, kk;
-        group_pos<BN>(tid + 256 * q, b_kc, &row, &kk);
-        put_group(Bs, row, kk, b_kc, r.b[q]);
+        group_pos<BN, KS>(tid + 256 * q, b_kc, &row, &kk);
+        put_group<KS>(Bs, row, kk, b_kc, r.b[q]);
     }
 }
 
 // Block tile BM x BN (64 or 128 each), four waves in a 2 x 2 arrangement,
 // each wave (BM/2) x (BN/2) = TM x TN tiles of 32 x 32.
-template <int kEpi, int BM, int BN>
+template <int kEpi, int BM, int BN, int KS>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
     constexpr int TM = BM / 64, TN = BN / 64;
-    __shared__ __attribute__((aligned(16))) uint16_t As[BM][kLdsK];   // [m][k]
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][kLdsK];   // [n][k]
+    __shared__ __attribute__((aligned(16))) uint16_t As[BM][lds_k<KS>()];   // [m][k]
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][lds_k<KS>()];   // [n][k]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int64_t m0 = static_cast<int64_t>(blockIdx.y) * BM, n0 = static_cast<int64_t>(blockIdx.x) * BN;
@@ -169,14 +172,14 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
         for (int tn = 0; tn < TN; ++tn)
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[tm][tn][i] = 0.0f;
-    StageRegs<BM, BN> r;
-    if (k_lo < k_hi) load_stage<BM, BN>(r, g, a_kc, b_kc, m0, n0, k_lo, k_hi, tid);
-    for (int64_t k0 = k_lo; k0 < k_hi; k0 += kKs) {
-        store_stage<BM, BN>(r, a_kc, b_kc, tid, As, Bs);
+    StageRegs<BM, BN, KS> r;
+    if (k_lo < k_hi) load_stage<BM, BN, KS>(r, g, a_kc, b_kc, m0, n0, k_lo, k_hi, tid);
+    for (int64_t k0 = k_lo; k0 < k_hi; k0 += KS) {
+        store_stage<BM, BN, KS>(r, a_kc, b_kc, tid, As, Bs);
         __syncthreads();
-        if (k0 + kKs < k_hi) load_stage<BM, BN>(r, g, a_kc, b_kc, m0, n0, k0 + kKs, k_hi, tid);
+        if (k0 + KS < k_hi) load_stage<BM, BN, KS>(r, g, a_kc, b_kc, m0, n0, k0 + KS, k_hi, tid);
 #pragma unroll
-        for (int ks = 0; ks < kKs; ks += 16) {
+        for (int ks = 0; ks < KS; ks += 16) {
             // lane supplies row (lane % 32) and k = ks + 8*(lane / 32) .. +7
             const int rr = lane & 31, kq = ks + 8 * (lane >> 5);
             bf16x8 a[TM], b[TN];
@@ -243,17 +246,16 @@ struct HeadArgs {
     const float* y;          // null for inference
     float* logits;
     uint16_t* dH2;
-    float* dw3;
-    float* db3;
-    float* db2;              // column sums of the BF16 dH2
-    float* loss;             // sum of per-row losses / B
+    float* part;             // [kHeadReplicas][kHeadPart]: w3 gradient, b2 gradient (column sums of the BF16
+                             // dH2), b3 gradient, loss (sum of per-row losses / B)
     int64_t B;
 };
 
 // Head and loss: one wave per row, rows strided over the grid.  The w3, b3
 // and b2 gradients and the loss are summed in registers over a wave's rows,
-// then over the workgroup in LDS, and added to the gradient once per
-// workgroup (not once per row).
+// then over the workgroup in LDS, and added once per workgroup into replica
+// (workgroup mod kHeadReplicas) of the partial sums; head_finish adds the
+// replicas into the gradient.
 __global__ void __launch_bounds__(256) head_kernel(HeadArgs a) {
     __shared__ float red[4][2 * kMlpH + 2];
     const int lane = threadIdx.x & 63;
@@ -316,23 +318,44 @@ __global__ void __launch_bounds__(256) head_kernel(HeadArgs a) {
     }
     __syncthreads();
     const int n = threadIdx.x;
-    atomicAdd(a.dw3 + n, red[0][n] + red[1][n] + red[2][n] + red[3][n]);
-    atomicAdd(a.db2 + n, red[0][kMlpH + n] + red[1][kMlpH + n] + red[2][kMlpH + n] + red[3][kMlpH + n]);
-    if (n == 0) {
-        atomicAdd(a.loss, red[0][2 * kMlpH] + red[1][2 * kMlpH] + red[2][2 * kMlpH] + red[3][2 * kMlpH]);
-        atomicAdd(a.db3, red[0][2 * kMlpH + 1] + red[1][2 * kMlpH + 1] + red[2][2 * kMlpH + 1] +
-                             red[3][2 * kMlpH + 1]);
+    float* part = a.part + (blockIdx.x % kHeadReplicas) * kHeadPart;
+    atomicAdd(part + n, red[0][n] + red[1][n] + red[2][n] + red[3][n]);
+    atomicAdd(part + kMlpH + n, red[0][kMlpH + n] + red[1][kMlpH + n] + red[2][kMlpH + n] + red[3][kMlpH + n]);
+    if (n < 2)
+        atomicAdd(part + 2 * kMlpH + n, red[0][2 * kMlpH + n] + red[1][2 * kMlpH + n] + red[2][2 * kMlpH + n] +
+                                            red[3][2 * kMlpH + n]);
+}
+
+// The head's replicas summed in a fixed order into the gradient (w3, b2, b3)
+// and the loss, then cleared for the next step (one 256-thread workgroup).
+__device__ __forceinline__ void head_finish(float* part, float* grad, float* loss) {
+    for (int i = threadIdx.x; i < 2 * kMlpH + 2; i += blockDim.x) {
+        float acc = 0.0f;
+        for (int r = 0; r < kHeadReplicas; ++r) {
+            acc += part[r * kHeadPart + i];
+            part[r * kHeadPart + i] = 0.0f;
+        }
+        if (i < kMlpH) grad[kMlpW3Off + i] += acc;
+        else if (i < 2 * kMlpH) grad[kMlpB2Off + (i - kMlpH)] += acc;
+        else if (i == 2 * kMlpH) loss[0] = acc;
+        else grad[kMlpB3Off] += acc;
     }
 }
 
 // Column sums of a [B][256] BF16 matrix into out (atomic, once per
 // workgroup): each thread owns two adjacent columns of every other row of
 // its workgroup's row range.
-__global__ void __launch_bounds__(256) colsum_kernel(const uint16_t* X, int64_t B, float* out) {
+// The last workgroup of the launch instead finishes the head's sums.
+__global__ void __launch_bounds__(256) colsum_kernel(const uint16_t* X, int64_t B, float* out, float* head_part,
+                                                     float* grad, float* loss) {
     __shared__ float red[2][kMlpH];
+    if (blockIdx.x == gridDim.x - 1) {
+        head_finish(head_part, grad, loss);
+        return;
+    }
     const int t = threadIdx.x;
     const int cp = t & 127, ro = t >> 7;
-    const int64_t rows_per = (B + gridDim.x - 1) / gridDim.x;
+    const int64_t rows_per = (B + gridDim.x - 2) / (gridDim.x - 1);
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rows_per;
     const int64_t r1 = r0 + rows_per < B ? r0 + rows_per : B;
     const uint32_t* X32 = reinterpret_cast<const uint32_t*>(X);
@@ -577,11 +600,11 @@ __global__ void __launch_bounds__(kFwdThreads) mlp_forward_fused_kernel(FwdArgs 
     }
 }
 
-template <int kEpi, int BM, int BN>
+template <int kEpi, int BM, int BN, int KS>
 hipError_t gemm_tile(const GemmArgs& g, int split, hipStream_t s) {
     dim3 grid(static_cast<unsigned>((g.N + BN - 1) / BN), static_cast<unsigned>((g.M + BM - 1) / BM),
               static_cast<unsigned>(split));
-    hipLaunchKernelGGL((gemm_kernel<kEpi, BM, BN>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_kernel<kEpi, BM, BN, KS>), grid, dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
@@ -589,8 +612,10 @@ hipError_t gemm_tile(const GemmArgs& g, int split, hipStream_t s) {
 // products are small and each K stage waits for its loads, so many resident
 // workgroups per CU hide more latency than larger tiles save (measured on
 // the scorer: training step 142 us with 64 x 64, 175 us with 64 x 128, 211 us
-// with 128 x 128).  GEONET_GEMM_TILE (0: 128 x 128, 1: 64 x 128, 2: 64 x 64)
-// fixes it at compile time.
+// with 128 x 128).  K stages of 128 wherever a workgroup's K range is a
+// multiple of 128 (four times the bytes in flight per wait), else 32.
+// GEONET_GEMM_TILE (0: 128 x 128, 1: 64 x 128, 2: 64 x 64) fixes the tile at
+// compile time.
 template <int kEpi>
 hipError_t gemm(const GemmArgs& g, int split, hipStream_t s) {
     // every operand must have a unit stride along k or along its row/column
@@ -598,17 +623,18 @@ hipError_t gemm(const GemmArgs& g, int split, hipStream_t s) {
     // that each 16-byte group is entirely in or out of range
     const bool a_kc = g.a_cs == 1, b_kc = g.b_rs == 1;
     if ((!a_kc && g.a_rs != 1) || (!b_kc && g.b_cs != 1)) return hipErrorInvalidValue;
-    if ((a_kc || b_kc) && (g.K % 8 != 0 || g.k_chunk % kKs != 0)) return hipErrorInvalidValue;
+    if ((a_kc || b_kc) && (g.K % 8 != 0 || g.k_chunk % 32 != 0)) return hipErrorInvalidValue;
     if ((!a_kc && g.M % 8 != 0) || (!b_kc && g.N % 8 != 0)) return hipErrorInvalidValue;
+    const bool wide = g.k_chunk % 128 == 0;
 #ifdef GEONET_GEMM_TILE
     const int tile = GEONET_GEMM_TILE;
 #else
     auto blocks = [&](int64_t bm, int64_t bn) { return ((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn) * split; };
     const int tile = blocks(64, 64) > 8192 ? 0 : 2;
 #endif
-    if (tile == 0) return gemm_tile<kEpi, 128, 128>(g, split, s);
-    if (tile == 1) return gemm_tile<kEpi, 64, 128>(g, split, s);
-    return gemm_tile<kEpi, 64, 64>(g, split, s);
+    if (tile == 0) return wide ? gemm_tile<kEpi, 128, 128, 128>(g, split, s) : gemm_tile<kEpi, 128, 128, 32>(g, split, s);
+    if (tile == 1) return wide ? gemm_tile<kEpi, 64, 128, 128>(g, split, s) : gemm_tile<kEpi, 64, 128, 32>(g, split, s);
+    return wide ? gemm_tile<kEpi, 64, 64, 128>(g, split, s) : gemm_tile<kEpi, 64, 64, 32>(g, split, s);
 }
 
 }  // namespace
@@ -652,10 +678,7 @@ hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const floa
     h.y = backward ? y : nullptr;
     h.logits = d.logits;
     h.dH2 = d.dH2;
-    h.dw3 = d.grad + kMlpW3Off;
-    h.db3 = d.grad + kMlpB3Off;
-    h.db2 = d.grad + kMlpB2Off;
-    h.loss = d.loss;
+    h.part = d.head_part;
     h.B = B;
     const int64_t hb = std::min<int64_t>(std::max<int64_t>((B + 63) / 64, 1), 512);   // ~16 rows per wave
     hipLaunchKernelGGL(head_kernel, dim3(static_cast<unsigned>(hb)), dim3(256), 0, s, h);
@@ -667,7 +690,7 @@ hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const floa
 hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, hipStream_t s) {
     // split-K over chunks of 512 rows (the weight-gradient tiles alone are too few)
     const int split = static_cast<int>(std::max<int64_t>((B + 511) / 512, 1));
-    const int64_t k_chunk = ((B + split - 1) / split + kKs - 1) / kKs * kKs;
+    const int64_t k_chunk = ((B + split - 1) / split + 127) / 128 * 128;
     // dW2 = H1^T dH2  (M = 256, N = 256, K = B)
     GemmArgs w2{};
     w2.A = d.H1;
@@ -712,9 +735,10 @@ hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, hipStream
     w1.b_cs = 1;
     w1.out_f32 = d.grad + kMlpW1Off;
     if ((e = gemm<kAtomicF32>(w1, split, s)) != hipSuccess) return e;
-    // b1 gradient: column sums of dH1 (b2's are summed in the head kernel)
     const unsigned cs_blocks = static_cast<unsigned>(std::min<int64_t>(std::max<int64_t>((B + 63) / 64, 1), 1024));
-    hipLaunchKernelGGL(colsum_kernel, dim3(cs_blocks), dim3(256), 0, s, d.dH1, B, d.grad + kMlpB1Off);
+    // b1 gradient: column sums of dH1, plus one workgroup that finishes the head's sums
+    hipLaunchKernelGGL(colsum_kernel, dim3(cs_blocks + 1), dim3(256), 0, s, d.dH1, B, d.grad + kMlpB1Off,
+                       d.head_part, d.grad, d.loss);
     return hipGetLastError();
 }
 

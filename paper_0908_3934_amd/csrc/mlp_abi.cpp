@@ -34,7 +34,7 @@ hipError_t alloc(T** p, size_t n) {
 
 void release(MlpDevice& d) {
     void* ps[] = {d.params, d.adam_m, d.adam_v, d.grad,   d.w1b,  d.w2b,      d.w1t,      d.w2p, d.Xb,
-                  d.H1,     d.H2,     d.dH1,    d.dH2,    d.logits, d.loss, d.in_shift, d.in_scale};
+                  d.H1,     d.H2,     d.dH1,    d.dH2,    d.logits, d.loss, d.in_shift, d.in_scale, d.head_part};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     d = MlpDevice{};
@@ -84,12 +84,14 @@ net_status net_mlp_create(net_mlp_t** out) {
         alloc(&d.adam_v, kMlpParams) != hipSuccess || alloc(&d.grad, kMlpParams) != hipSuccess ||
         alloc(&d.w1b, kMlpW1) != hipSuccess || alloc(&d.w2b, kMlpW2) != hipSuccess ||
         alloc(&d.w1t, kMlpW1) != hipSuccess || alloc(&d.w2p, kMlpW2) != hipSuccess || alloc(&d.loss, 1) != hipSuccess ||
+        alloc(&d.head_part, kHeadReplicas * kHeadPart) != hipSuccess ||
         alloc(&d.in_shift, kMlpIn) != hipSuccess || alloc(&d.in_scale, kMlpIn) != hipSuccess) {
         release(d);
         delete m;
         return mfail(NET_E_OOM, "net_mlp_create: device allocation failed");
     }
     hipError_t e = hipMemset(d.params, 0, kMlpParams * sizeof(float));
+    if (e == hipSuccess) e = hipMemset(d.head_part, 0, kHeadReplicas * kHeadPart * sizeof(float));
     if (e == hipSuccess) e = hipMemset(d.adam_m, 0, kMlpParams * sizeof(float));
     if (e == hipSuccess) e = hipMemset(d.adam_v, 0, kMlpParams * sizeof(float));
     if (e == hipSuccess) e = mlp_refresh_bf16(d, nullptr);
@@ -157,7 +159,6 @@ static net_status grad_impl(net_mlp* m, const float* x, const float* y, int64_t 
     if (!y) return mfail(NET_E_ARG, "net_mlp: labels are NULL");
     if ((st = reserve(m, rows, s)) != NET_OK) return st;
     hipError_t e = hipMemsetAsync(m->d.grad, 0, kMlpParams * sizeof(float), s);
-    if (e == hipSuccess) e = hipMemsetAsync(m->d.loss, 0, sizeof(float), s);
     if (e == hipSuccess) e = mlp_forward(m->d, x, rows, y, true, s);
     if (e == hipSuccess) e = mlp_backward(m->d, x, rows, s);
     if (e != hipSuccess) return mdev(m, e, "net_mlp: gradient");
