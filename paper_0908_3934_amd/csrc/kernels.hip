@@ -658,11 +658,26 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
             const NetMeta nm = a.meta[a.wg_nets[q]];
             const NetLds L = carve(lds, nm, obs);
             const uint32_t rmask = 32u * static_cast<uint32_t>(nm.words) - 1u;
-            for (int c = nm.chunk_begin + wave; c < nm.chunk_end; c += nwaves) {
+            // the next chunk's edges are loaded while this chunk is resolved
+            int c = nm.chunk_begin + wave;
+            u32x4 n_lo = u32x4{0u, 0u, 0u, 0u}, n_hi = n_lo;
+            u32x2 n_d = u32x2{0u, 0u};
+            if (c < nm.chunk_end) {
+                const int64_t e = static_cast<int64_t>(c) * kChunkEdges + lane * kEdgesPerLane;
+                n_lo = *reinterpret_cast<const u32x4*>(a.src + e);
+                n_hi = *reinterpret_cast<const u32x4*>(a.src + e + 4);
+                n_d = *reinterpret_cast<const u32x2*>(a.d + e);
+            }
+            for (; c < nm.chunk_end; c += nwaves) {
                 const int64_t e0 = static_cast<int64_t>(c) * kChunkEdges + lane * kEdgesPerLane;
-                const u32x4 s_lo = *reinterpret_cast<const u32x4*>(a.src + e0);
-                const u32x4 s_hi = *reinterpret_cast<const u32x4*>(a.src + e0 + 4);
-                const u32x2 dq = *reinterpret_cast<const u32x2*>(a.d + e0);
+                const u32x4 s_lo = n_lo, s_hi = n_hi;
+                const u32x2 dq = n_d;
+                if (c + nwaves < nm.chunk_end) {
+                    const int64_t e = e0 + static_cast<int64_t>(nwaves) * kChunkEdges;
+                    n_lo = *reinterpret_cast<const u32x4*>(a.src + e);
+                    n_hi = *reinterpret_cast<const u32x4*>(a.src + e + 4);
+                    n_d = *reinterpret_cast<const u32x2*>(a.d + e);
+                }
                 const uint32_t sv[8] = {s_lo.x, s_lo.y, s_lo.z, s_lo.w, s_hi.x, s_hi.y, s_hi.z, s_hi.w};
                 uint32_t fired = 0;
 #pragma unroll
