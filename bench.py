@@ -319,6 +319,7 @@ def bench_estimate(args, torch, synth):
         Y.append(o.labels)
         log("held-out net %d: %d pairs, scorer %.4f s AUC %.4f | fit %.2f s AUC %.4f"
             % (k, len(o.labels), b - a, est.auc(S[-1], o.labels), c - b, est.auc(F[-1], o.labels)))
+    cpu = None if args.no_cpu_baseline else estimate_cpu_baseline(test[0], sc)
     S, F, C, Y = map(np.concatenate, (S, F, C, Y))
     auc_sc, auc_sf, auc_c = est.auc(S, Y), est.auc(F, Y), est.auc(C, Y)
     nf = args.obs_steps * 3 // 1000
@@ -348,7 +349,38 @@ def bench_estimate(args, torch, synth):
         "correlation_baseline_auc": auc_c,
         "auc_gap": auc_sf - auc_sc,
         "wall_ratio_simfit_over_scorer": t_sf / max(t_sc, 1e-12),
+        "scorer_pairs_per_s": float(Y.size) / max(t_sc, 1e-12),
+        "cpu_baseline": cpu,
     }
+
+
+def estimate_cpu_baseline(o, sc, pairs=8192):
+    """The scorer's pipeline as the FP64 oracle computes it (pair features,
+    then the MLP with the same BF16 rounding points and input
+    standardisation), single-threaded, on the first `pairs` candidate pairs
+    of one held-out network: pairs scored per second."""
+    import numpy as np
+    import oracle
+    from oracle import features as FE
+    from oracle import mlp as M
+    from threadpoolctl import threadpool_limits
+    spec = o.spec
+    F = o.F.cpu().numpy().astype(np.float64)
+    P = o.pairs.cpu().numpy()[:pairs]
+    D = o.dist.cpu().numpy().astype(np.float64)[:pairs]
+    thr = [oracle.drive_threshold(float(r), spec.dt_ms) for r in spec.drive_rate_hz] \
+        if spec.drive_rate_hz is not None else [0] * spec.n
+    p = sc.mlp.get_params().astype(np.float64)
+    shift, scale = (a.astype(np.float64) for a in sc.input_norm)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        X = FE.features(F, P, D, dt_ms=spec.dt_ms, tau_c_ms=spec.tau_c_ms, num=spec.frame_num, den=spec.frame_den,
+                        offset=o.offset, thr=thr, seed=spec.seed)
+        M.forward(p, X, bf=True, shift=shift, scale=scale)
+        wall = time.perf_counter() - t0
+    return {"value": len(P) / wall, "unit": "candidate pairs scored per second (features + MLP)", "cores": 1,
+            "kind": "oracle", "sample": "the first %d candidate pairs of one held-out network (FP64 oracle features "
+            "and MLP, single-threaded); %.1f s" % (len(P), wall)}
 
 
 def main():

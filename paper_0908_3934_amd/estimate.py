@@ -203,6 +203,7 @@ class EdgeScorer:
         self.mlp = Mlp(Mlp.init_params(seed))
         self.seed = seed
         self.history = []
+        self.input_norm = None     # (shift, scale) of the features, set by fit
 
     def fit(self, train: Sequence[Observed], epochs: int = 4, batch: int = 16384, lr: float = 1e-3,
             feats: Optional[list] = None):
@@ -212,7 +213,8 @@ class EdgeScorer:
         mean = X.mean(0)
         std = X.std(0)
         scale = torch.where(std > 1e-6, 1.0 / std, torch.zeros_like(std))
-        self.mlp.set_input_norm(mean.cpu().numpy(), scale.cpu().numpy())
+        self.input_norm = (mean.cpu().numpy(), scale.cpu().numpy())
+        self.mlp.set_input_norm(*self.input_norm)
         g = torch.Generator(device="cpu").manual_seed(self.seed)
         n = X.shape[0]
         loss = torch.zeros(1, dtype=torch.float32, device=X.device)
