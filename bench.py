@@ -178,8 +178,8 @@ def bench_ensemble(args, torch, synth, gn):
     }
 
 
-def ensemble_cpu_baseline(specs, n_all, every=64, steps=2000):
-    """The FP64 oracle on every 64th network for 2,000 steps, scaled to
+def ensemble_cpu_baseline(specs, n_all, every=16, steps=2000):
+    """The FP64 oracle on every 16th network for 2,000 steps, scaled to
     networks per second of 10,000-step runs."""
     import oracle
     sample = specs[::every]
@@ -257,9 +257,9 @@ def bench_mlp(args, torch, gn):
     }
 
 
-def mlp_cpu_baseline(X, y, params, rows=2048):
-    """The FP64 reference (same BF16 rounding points) for one gradient of a
-    2,048-row batch, in training pairs per second."""
+def mlp_cpu_baseline(X, y, params, rows=16384):
+    """The FP64 reference (same BF16 rounding points) for the gradient of one
+    16,384-row training batch, in training pairs per second."""
     from threadpoolctl import threadpool_limits
     from oracle import mlp as M
     X, y = X[:rows].astype("float64"), y[:rows].astype("float64")
@@ -354,7 +354,7 @@ def bench_estimate(args, torch, synth):
     }
 
 
-def estimate_cpu_baseline(o, sc, pairs=8192):
+def estimate_cpu_baseline(o, sc, pairs=32768):
     """The scorer's pipeline as the FP64 oracle computes it (pair features,
     then the MLP with the same BF16 rounding points and input
     standardisation), single-threaded, on the first `pairs` candidate pairs
@@ -389,7 +389,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--n", type=int, default=1 << 20)
-    ap.add_argument("--cpu-steps", type=int, default=150)
+    ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--deliver-flags", type=int, default=1024,
                     help="NET_BUILD_* bits of the step variant (default 1024: one fused kernel per step, "
