@@ -371,6 +371,19 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
         if ((st = upload(h, &sc, hg.seg_chunk, hg.seg_chunk.size(), s, "segments")) != NET_OK) return bail(st);
         if ((st = zeros(h, &g.age_alt, np + kAgePad, s, "ages", kAgeNever)) != NET_OK) return bail(st);
         if ((st = zeros(h, &g.summary_alt, np / 32, s, "summary")) != NET_OK) return bail(st);
+        // the fused step streams one word per slot, source | delay << 24
+        // (sources are below 2^24: a fused network has at most 2^20 vertices)
+        std::vector<uint32_t> packed(static_cast<size_t>(hg.e_slots));
+        for (int64_t k = 0; k < hg.e_slots; ++k)
+            packed[k] = static_cast<uint32_t>(hg.src[k]) | (static_cast<uint32_t>(hg.d[k]) << 24);
+        uint32_t* sd = nullptr;
+        st = upload(h, &sd, packed, packed.size(), s, "packed edges");
+        if (st == NET_OK) {
+            const hipError_t se = hipStreamSynchronize(s);   // `packed` is freed below
+            if (se != hipSuccess) st = device_fail(h, se, "net_build: upload");
+        }
+        if (st != NET_OK) return bail(st);
+        g.sd = sd;
         g.seg_vertex = sv;
         g.seg_chunk = sc;
         g.n_seg = static_cast<int32_t>(hg.seg_vertex.size()) - 1;

@@ -99,6 +99,7 @@ struct DeviceGraph {
     const int32_t* src;
     const uint16_t* w;
     const uint8_t* d;
+    const uint32_t* sd = nullptr;   // fused step only: source | delay << 24 per slot
     const uint8_t* rowstart;
     const int32_t* chunk_row0;
     const NetParams* params;

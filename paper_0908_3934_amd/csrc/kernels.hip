@@ -91,6 +91,7 @@ struct DeliverArgs {
     const int32_t* __restrict__ src;
     const uint16_t* __restrict__ w;
     const uint8_t* __restrict__ d;
+    const uint32_t* __restrict__ sd;   // source | delay << 24 per slot (fused step only)
     const uint8_t* __restrict__ rowstart;
     const int32_t* __restrict__ chunk_row0;
     const uint32_t* __restrict__ summary;
@@ -132,6 +133,34 @@ struct ChunkRegs {
     u32x2 dq;
 };
 
+// The fused step's chunk: one word per edge, source in bits 0..23 and delay
+// in bits 24..31, so that the stream is 4 B per edge (2x16 B per lane).
+struct PackedChunk {
+    u32x4 lo, hi;
+};
+
+__device__ __forceinline__ uint32_t comp4(const u32x4& v, int k) {
+    return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
+}
+__device__ __forceinline__ uint32_t edge_src(const ChunkRegs& x, int k) {
+    return k < 4 ? comp4(x.s_lo, k) : comp4(x.s_hi, k - 4);
+}
+__device__ __forceinline__ uint32_t edge_delay(const ChunkRegs& x, int k) {
+    return ((k < 4 ? x.dq.x : x.dq.y) >> (8 * (k & 3))) & 0xFFu;
+}
+__device__ __forceinline__ uint32_t edge_src(const PackedChunk& x, int k) {
+    return (k < 4 ? comp4(x.lo, k) : comp4(x.hi, k - 4)) & 0xFFFFFFu;
+}
+__device__ __forceinline__ uint32_t edge_delay(const PackedChunk& x, int k) {
+    return (k < 4 ? comp4(x.lo, k) : comp4(x.hi, k - 4)) >> 24;
+}
+
+__device__ __forceinline__ void load_packed_chunk(PackedChunk& x, const uint32_t* sd, int64_t c, int lane) {
+    const int64_t e0 = c * kChunkEdges + lane * kEdgesPerLane;
+    x.lo = *reinterpret_cast<const u32x4*>(sd + e0);
+    x.hi = *reinterpret_cast<const u32x4*>(sd + e0 + 4);
+}
+
 // Stream loads of one chunk (optionally non-temporal).
 template <bool kWStream, bool kNT>
 __device__ __forceinline__ void load_chunk(ChunkRegs& x, const DeliverArgs& a, int64_t c, int lane) {
@@ -156,10 +185,12 @@ __device__ __forceinline__ void load_chunk(ChunkRegs& x, const DeliverArgs& a, i
 // the ages (255, 255), which can match no delay of a non-candidate (those are
 // at most the window, below 255), so the resolution below needs no candidate
 // mask.  `shift` is the summary resolution (0: one bit per vertex).
-template <bool kLdsSummary>
-__device__ __forceinline__ void gather_chunk(const ChunkRegs& x, const DeliverArgs& a, const uint32_t* lds_summary,
+template <bool kLdsSummary, class Chunk>
+__device__ __forceinline__ void gather_chunk(const Chunk& x, const DeliverArgs& a, const uint32_t* lds_summary,
                                              uint32_t shift, uint32_t* aw) {
-    const uint32_t sv[8] = {x.s_lo.x, x.s_lo.y, x.s_lo.z, x.s_lo.w, x.s_hi.x, x.s_hi.y, x.s_hi.z, x.s_hi.w};
+    uint32_t sv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sv[k] = edge_src(x, k);
     const char* ages = reinterpret_cast<const char*>(a.ages);
     uint32_t sw[8];
 #pragma unroll
@@ -171,7 +202,7 @@ __device__ __forceinline__ void gather_chunk(const ChunkRegs& x, const DeliverAr
     // with the active lanes); the others keep the sentinel ages.
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const uint32_t dk = ((k < 4 ? x.dq.x : x.dq.y) >> (8 * (k & 3))) & 0xFFu;
+        const uint32_t dk = edge_delay(x, k);
         const bool cand = (__builtin_amdgcn_ubfe(sw[k], sv[k] >> shift, 1) != 0u) | (dk > a.window);   // bit mod 32
         uint32_t v = 0xFFFFu;
         if (cand) v = *reinterpret_cast<const uint16_t*>(ages + (sv[k] << 1));
@@ -182,11 +213,12 @@ __device__ __forceinline__ void gather_chunk(const ChunkRegs& x, const DeliverAr
 // With a1 <= a2 the ages of the source's last two spikes (255 = "255 or
 // more"), the source fired at t - d only if d == a1 or d >= a2; most chunks
 // have no such edge and skip the resolution (wave-uniform).
-__device__ __forceinline__ bool chunk_may_fire(const ChunkRegs& x, const uint32_t* aw) {
+template <class Chunk>
+__device__ __forceinline__ bool chunk_may_fire(const Chunk& x, const uint32_t* aw) {
     bool any = false;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const uint32_t dk = ((k < 4 ? x.dq.x : x.dq.y) >> (8 * (k & 3))) & 0xFFu;
+        const uint32_t dk = edge_delay(x, k);
         any = any | (dk == (aw[k] & 0xFFu)) | (dk >= ((aw[k] >> 8) & 0xFFu));
     }
     return wave_ballot(any) != 0;
@@ -196,25 +228,25 @@ __device__ __forceinline__ bool chunk_may_fire(const ChunkRegs& x, const uint32_
 // a1 (exact, since a1 < a2 <= 255), so the source fired at t - d iff d == a1.
 // For d >= a2 (an older spike may sit at t - d, or a2 = d = 255 is saturated)
 // the history ring decides.
-__device__ __forceinline__ uint32_t fired_bits(const ChunkRegs& x, const DeliverArgs& a, uint32_t t,
+template <class Chunk>
+__device__ __forceinline__ uint32_t fired_bits(const Chunk& x, const DeliverArgs& a, uint32_t t,
                                                const uint32_t* aw) {
     uint32_t fired = 0, need = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const uint32_t dk = ((k < 4 ? x.dq.x : x.dq.y) >> (8 * (k & 3))) & 0xFFu;
+        const uint32_t dk = edge_delay(x, k);
         const uint32_t a1 = aw[k] & 0xFFu, a2 = (aw[k] >> 8) & 0xFFu;
         const bool ring = dk >= a2;
         fired |= (!ring && dk == a1 ? 1u : 0u) << k;
         need |= (ring ? 1u : 0u) << k;
     }
     if (wave_ballot(need != 0)) {
-        const uint32_t sv[8] = {x.s_lo.x, x.s_lo.y, x.s_lo.z, x.s_lo.w, x.s_hi.x, x.s_hi.y, x.s_hi.z, x.s_hi.w};
         uint32_t slot[8], word[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const uint32_t dk = ((k < 4 ? x.dq.x : x.dq.y) >> (8 * (k & 3))) & 0xFFu;
+            const uint32_t dk = edge_delay(x, k);
             slot[k] = (t - dk) & 0xFFu;
-            word[k] = a.ring[((need >> k) & 1u) ? (slot[k] >> 5) * a.n_pad + sv[k] : 0u];
+            word[k] = a.ring[((need >> k) & 1u) ? (slot[k] >> 5) * a.n_pad + edge_src(x, k) : 0u];
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) fired |= (((need >> k) & (word[k] >> (slot[k] & 31))) & 1u) << k;
@@ -986,9 +1018,9 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs s) {
     int64_t c = c_begin + static_cast<int64_t>(wave) * kPer;
     // chunks beyond the range repeat the last one and are skipped below
     // (every segment holds at least one chunk)
-    ChunkRegs cur[kPer];
+    PackedChunk cur[kPer];
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) load_chunk<false, false>(cur[u], s.d, c + u < c_end ? c + u : c_end - 1, lane);
+    for (int u = 0; u < kPer; ++u) load_packed_chunk(cur[u], s.d.sd, c + u < c_end ? c + u : c_end - 1, lane);
     __builtin_amdgcn_sched_barrier(0);
     // the state of this workgroup's vertices (segments hold at most
     // kStepPrefetch * 1024) arrives while the edges stream; issued after the
@@ -1036,7 +1068,7 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs s) {
         c = c_begin + static_cast<int64_t>(__builtin_amdgcn_readfirstlane(claim)) * kPer;
         if (c < c_end) {
 #pragma unroll
-            for (int u = 0; u < kPer; ++u) load_chunk<false, false>(cur[u], s.d, c + u < c_end ? c + u : c_end - 1, lane);
+            for (int u = 0; u < kPer; ++u) load_packed_chunk(cur[u], s.d.sd, c + u < c_end ? c + u : c_end - 1, lane);
         }
     }
     if (qn) flush_arrivals(s.d, queue, qn, lane, lds_in, v0);
@@ -1118,7 +1150,7 @@ hipError_t configure_deliver(DeviceGraph& g, const net_build_opts* opts, LaunchC
     // segment's inputs in LDS.
     lc.fused = false;
     // (queued arrivals are 32-bit slot indices: at most 2^23 chunks)
-    if ((flags & NET_BUILD_FUSED_STEP) && g.seg_vertex && g.n_seg > 0 && lc.lds_summary && g.sum_shift == 0 &&
+    if ((flags & NET_BUILD_FUSED_STEP) && g.seg_vertex && g.sd && g.n_seg > 0 && lc.lds_summary && g.sum_shift == 0 &&
         summary_bytes <= static_cast<size_t>(kStepSummaryBytes) && g.n_chunks <= (int64_t(1) << 23)) {
         const size_t in_bytes = (static_cast<size_t>(g.seg_max) * sizeof(float) + 15) / 16 * 16;
         const size_t need = in_bytes + kStepQueueBytes + 16;   // beyond the summary: inputs, queues, counter
@@ -1144,6 +1176,7 @@ static DeliverArgs deliver_args(const DeviceGraph& g, const LaunchConfig& lc, in
     a.src = g.src;
     a.w = g.w;
     a.d = g.d;
+    a.sd = g.sd;
     a.rowstart = g.rowstart;
     a.chunk_row0 = g.chunk_row0;
     a.summary = g.summary;
