@@ -254,7 +254,8 @@ hipError_t fit_prep(const FitInputs& in, const FitWork& w, hipStream_t s);
 hipError_t fit_eval(const FitInputs& in, const FitWork& w, hipStream_t s);
 
 hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const float* y, bool backward, hipStream_t s);
-hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, hipStream_t s);
+hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, float* loss_out, hipStream_t s);
+// (also clears d.grad for the next accumulation)
 hipError_t mlp_adam(const MlpDevice& d, float lr, float beta1, float beta2, float eps, int64_t t, hipStream_t s);
 hipError_t mlp_refresh_bf16(const MlpDevice& d, hipStream_t s);
 hipError_t mlp_forward_fused(const MlpDevice& d, const float* X, int64_t B, float* logits, hipStream_t s);

@@ -1072,6 +1072,13 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs s) {
         }
     }
     if (qn) flush_arrivals(s.d, queue, qn, lane, lds_in, v0);
+    // the random draws need no input: a wave computes them while the
+    // workgroup's other waves finish their deliveries
+#pragma unroll
+    for (int i = 0; i < kStepPrefetch; ++i) {
+        const int64_t base = v0 + static_cast<int64_t>(i) * 1024;
+        if (base < v1) vertex_random<false>(s.n, base + threadIdx.x, v1, pre[i]);
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kStepPrefetch; ++i) {
@@ -1079,7 +1086,6 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs s) {
         if (base < v1) {
             const int64_t j = base + threadIdx.x;
             const float in = j < v1 ? lds_in[j - v0] : 0.0f;
-            vertex_random<false>(s.n, j, v1, pre[i]);
             vertex_update<false>(s.n, j, v1, v1, in, false, pre[i]);
         }
     }

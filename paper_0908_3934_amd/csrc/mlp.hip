@@ -327,8 +327,9 @@ __global__ void __launch_bounds__(256) head_kernel(HeadArgs a) {
 }
 
 // The head's replicas summed in a fixed order into the gradient (w3, b2, b3)
-// and the loss, then cleared for the next step (one 256-thread workgroup).
-__device__ __forceinline__ void head_finish(float* part, float* grad, float* loss) {
+// and the loss (also into loss_out when given), then cleared for the next
+// step (one 256-thread workgroup).
+__device__ __forceinline__ void head_finish(float* part, float* grad, float* loss, float* loss_out) {
     for (int i = threadIdx.x; i < 2 * kMlpH + 2; i += blockDim.x) {
         float acc = 0.0f;
         for (int r = 0; r < kHeadReplicas; ++r) {
@@ -337,7 +338,10 @@ __device__ __forceinline__ void head_finish(float* part, float* grad, float* los
         }
         if (i < kMlpH) grad[kMlpW3Off + i] += acc;
         else if (i < 2 * kMlpH) grad[kMlpB2Off + (i - kMlpH)] += acc;
-        else if (i == 2 * kMlpH) loss[0] = acc;
+        else if (i == 2 * kMlpH) {
+            loss[0] = acc;
+            if (loss_out) loss_out[0] = acc;
+        }
         else grad[kMlpB3Off] += acc;
     }
 }
@@ -347,10 +351,10 @@ __device__ __forceinline__ void head_finish(float* part, float* grad, float* los
 // its workgroup's row range.
 // The last workgroup of the launch instead finishes the head's sums.
 __global__ void __launch_bounds__(256) colsum_kernel(const uint16_t* X, int64_t B, float* out, float* head_part,
-                                                     float* grad, float* loss) {
+                                                     float* grad, float* loss, float* loss_out) {
     __shared__ float red[2][kMlpH];
     if (blockIdx.x == gridDim.x - 1) {
-        head_finish(head_part, grad, loss);
+        head_finish(head_part, grad, loss, loss_out);
         return;
     }
     const int t = threadIdx.x;
@@ -386,7 +390,7 @@ struct AdamArgs {
     float* p;
     float* m;
     float* v;
-    const float* g;
+    float* g;          // read, then cleared for the next step's accumulation
     uint16_t* w1b;
     uint16_t* w2b;
     uint16_t* w1t;
@@ -399,6 +403,7 @@ __global__ void __launch_bounds__(256) adam_kernel(AdamArgs a) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     const float gi = a.g[i];
+    a.g[i] = 0.0f;
     const float m = a.b1 * a.m[i] + (1.0f - a.b1) * gi;
     const float v = a.b2 * a.v[i] + (1.0f - a.b2) * gi * gi;
     a.m[i] = m;
@@ -680,14 +685,15 @@ hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const floa
     h.dH2 = d.dH2;
     h.part = d.head_part;
     h.B = B;
-    const int64_t hb = std::min<int64_t>(std::max<int64_t>((B + 63) / 64, 1), 512);   // ~16 rows per wave
+    // ~4 rows per wave (one pass): four workgroups per CU at 16,384 rows
+    const int64_t hb = std::min<int64_t>(std::max<int64_t>((B + 15) / 16, 1), 2048);
     hipLaunchKernelGGL(head_kernel, dim3(static_cast<unsigned>(hb)), dim3(256), 0, s, h);
     return hipGetLastError();
 }
 
 // Backward pass after mlp_forward(..., backward = true): accumulates the
 // gradient of the mean BCE into d.grad (which the caller zeroed).
-hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, hipStream_t s) {
+hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, float* loss_out, hipStream_t s) {
     // split-K over chunks of 512 rows (the weight-gradient tiles alone are too few)
     const int split = static_cast<int>(std::max<int64_t>((B + 511) / 512, 1));
     const int64_t k_chunk = ((B + split - 1) / split + 127) / 128 * 128;
@@ -738,7 +744,7 @@ hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, hipStream
     const unsigned cs_blocks = static_cast<unsigned>(std::min<int64_t>(std::max<int64_t>((B + 63) / 64, 1), 1024));
     // b1 gradient: column sums of dH1, plus one workgroup that finishes the head's sums
     hipLaunchKernelGGL(colsum_kernel, dim3(cs_blocks + 1), dim3(256), 0, s, d.dH1, B, d.grad + kMlpB1Off,
-                       d.head_part, d.grad, d.loss);
+                       d.head_part, d.grad, d.loss, loss_out);
     return hipGetLastError();
 }
 

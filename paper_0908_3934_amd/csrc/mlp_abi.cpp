@@ -11,6 +11,7 @@ struct net_mlp {
     MlpDevice d;
     int64_t adam_t = 0;
     bool broken = false;
+    bool grad_clear = false;   // d.grad is all zero (Adam clears it after use)
 };
 
 namespace {
@@ -153,14 +154,17 @@ net_status net_mlp_forward(net_mlp_t* m, const float* x_dev, int64_t rows, float
     return NET_OK;
 }
 
-static net_status grad_impl(net_mlp* m, const float* x, const float* y, int64_t rows, hipStream_t s) {
+static net_status grad_impl(net_mlp* m, const float* x, const float* y, int64_t rows, float* loss_out,
+                            hipStream_t s) {
     net_status st = check(m, rows, x);
     if (st != NET_OK) return st;
     if (!y) return mfail(NET_E_ARG, "net_mlp: labels are NULL");
     if ((st = reserve(m, rows, s)) != NET_OK) return st;
-    hipError_t e = hipMemsetAsync(m->d.grad, 0, kMlpParams * sizeof(float), s);
+    hipError_t e = hipSuccess;
+    if (!m->grad_clear) e = hipMemsetAsync(m->d.grad, 0, kMlpParams * sizeof(float), s);
+    m->grad_clear = false;
     if (e == hipSuccess) e = mlp_forward(m->d, x, rows, y, true, s);
-    if (e == hipSuccess) e = mlp_backward(m->d, x, rows, s);
+    if (e == hipSuccess) e = mlp_backward(m->d, x, rows, loss_out, s);
     if (e != hipSuccess) return mdev(m, e, "net_mlp: gradient");
     return NET_OK;
 }
@@ -168,11 +172,10 @@ static net_status grad_impl(net_mlp* m, const float* x, const float* y, int64_t 
 net_status net_mlp_grad(net_mlp_t* m, const float* x_dev, const float* y_dev, int64_t rows, float* grad_dev,
                         float* loss_dev, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    net_status st = grad_impl(m, x_dev, y_dev, rows, s);
+    net_status st = grad_impl(m, x_dev, y_dev, rows, loss_dev, s);
     if (st != NET_OK) return st;
     hipError_t e = hipSuccess;
     if (grad_dev) e = hipMemcpyAsync(grad_dev, m->d.grad, kMlpParams * sizeof(float), hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess && loss_dev) e = hipMemcpyAsync(loss_dev, m->d.loss, sizeof(float), hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return mdev(m, e, "net_mlp_grad");
     return NET_OK;
 }
@@ -181,12 +184,12 @@ net_status net_mlp_train_step(net_mlp_t* m, const float* x_dev, const float* y_d
                               float* loss_dev, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (!(lr > 0.0f)) return mfail(NET_E_ARG, "net_mlp_train_step: lr must be > 0");
-    net_status st = grad_impl(m, x_dev, y_dev, rows, s);
+    net_status st = grad_impl(m, x_dev, y_dev, rows, loss_dev, s);
     if (st != NET_OK) return st;
     m->adam_t += 1;
     hipError_t e = mlp_adam(m->d, lr, 0.9f, 0.999f, 1e-8f, m->adam_t, s);
-    if (e == hipSuccess && loss_dev) e = hipMemcpyAsync(loss_dev, m->d.loss, sizeof(float), hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return mdev(m, e, "net_mlp_train_step");
+    m->grad_clear = true;
     return NET_OK;
 }
 
