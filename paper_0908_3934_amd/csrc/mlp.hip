@@ -727,20 +727,23 @@ hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, float* lo
     h1.mask = d.H1;
     h1.out_bf16 = d.dH1;
     if ((e = gemm<kMaskBf16>(h1, 1, s)) != hipSuccess) return e;
-    // dW1 = X^T dH1  (M = 64, N = 256, K = B), X rounded to BF16 on staging
+    // dW1 = X^T dH1  (M = 64, N = 256, K = B), X rounded to BF16 on staging;
+    // only four output tiles, so split-K over chunks of 256 rows (256
+    // workgroups at 16,384 rows; 512-row chunks leave half the CUs idle)
+    const int split1 = static_cast<int>(std::max<int64_t>((B + 255) / 256, 1));
     GemmArgs w1{};
     w1.A = d.Xb;                       // the forward pass's normalised BF16 inputs
     w1.B = d.dH1;
     w1.M = kMlpIn;
     w1.N = kMlpH;
     w1.K = B;
-    w1.k_chunk = k_chunk;
+    w1.k_chunk = ((B + split1 - 1) / split1 + 127) / 128 * 128;
     w1.a_rs = 1;
     w1.a_cs = kMlpIn;
     w1.b_rs = kMlpH;
     w1.b_cs = 1;
     w1.out_f32 = d.grad + kMlpW1Off;
-    if ((e = gemm<kAtomicF32>(w1, split, s)) != hipSuccess) return e;
+    if ((e = gemm<kAtomicF32>(w1, split1, s)) != hipSuccess) return e;
     const unsigned cs_blocks = static_cast<unsigned>(std::min<int64_t>(std::max<int64_t>((B + 63) / 64, 1), 1024));
     // b1 gradient: column sums of dH1, plus one workgroup that finishes the head's sums
     hipLaunchKernelGGL(colsum_kernel, dim3(cs_blocks + 1), dim3(256), 0, s, d.dH1, B, d.grad + kMlpB1Off,
