@@ -981,7 +981,9 @@ __device__ __forceinline__ void deliver_fired_lds(const DeliverArgs& a, int64_t 
 // One workgroup per segment.  Waves take units of two chunks: unit `wave`
 // first, then the next unclaimed one from an LDS counter (claimed one
 // iteration ahead), so that waves the hardware serves later do not hold the
-// workgroup's barrier.
+// workgroup's barrier.  The next unit's stream loads are issued right after
+// this unit's age gathers, so the two latencies overlap (loads complete in
+// issue order: the resolution waits for the gathers only).
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs s) {
     // the summary at a fixed LDS address (its reads need no base), the
     // segment's inputs, the arrival queues and the unit counter after it
@@ -1042,6 +1044,14 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs s) {
         uint32_t aw[kPer][8];
 #pragma unroll
         for (int u = 0; u < kPer; ++u) gather_chunk<true>(cur[u], s.d, lds_summary, 0u, aw[u]);
+        // the next unit's stream loads go out behind this unit's gathers (past
+        // the range they re-read this unit's chunks, which L2 still holds)
+        const int64_t cn = c_begin + static_cast<int64_t>(__builtin_amdgcn_readfirstlane(claim)) * kPer;
+        PackedChunk nxt[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u)
+            load_packed_chunk(nxt[u], s.d.sd, cn + u < c_end ? cn + u : (c + u < c_end ? c + u : c_end - 1), lane);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             if (c + u < c_end && chunk_may_fire(cur[u], aw[u])) {
@@ -1065,11 +1075,9 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs s) {
                 }
             }
         }
-        c = c_begin + static_cast<int64_t>(__builtin_amdgcn_readfirstlane(claim)) * kPer;
-        if (c < c_end) {
+        c = cn;
 #pragma unroll
-            for (int u = 0; u < kPer; ++u) load_packed_chunk(cur[u], s.d.sd, c + u < c_end ? c + u : c_end - 1, lane);
-        }
+        for (int u = 0; u < kPer; ++u) cur[u] = nxt[u];
     }
     if (qn) flush_arrivals(s.d, queue, qn, lane, lds_in, v0);
     // the random draws need no input: a wave computes them while the
