@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_EDGE = 5      # int32 source + uint8 delay, streamed every step
-BYTES_PER_EDGE_PACKED = 4   # fused step: one word per edge, source | delay << 24
+BYTES_PER_EDGE_PACKED = 4   # fused step and packed delivery: one word per edge, source | delay << 24
 BYTES_PER_ARRIVAL = 2   # FP16 weight, loaded only when its edge delivers a spike
 BYTES_PER_EDGE_STREAMED_W = 7   # delivery variant that streams every weight with its edge
 # vertex update per step: V read + written (8), two-spike ages read + written
@@ -472,10 +472,11 @@ def main():
         avg_deliver_s = tm["deliver_ms"] / tm["deliver_launches"] / 1e3
     arrivals = arrivals_per_step(net, spec, args.rate_steps)
     streamed_w = bool(info["deliver_flags"] & gn.NET_BUILD_DELIVER_STREAM_WEIGHTS)
+    packed = fused or bool(info["deliver_flags"] & gn.NET_BUILD_DELIVER_PACKED)
     if streamed_w:
         alg_bytes = BYTES_PER_EDGE_STREAMED_W * E
     else:
-        alg_bytes = (BYTES_PER_EDGE_PACKED if fused else BYTES_PER_EDGE) * E + BYTES_PER_ARRIVAL * arrivals
+        alg_bytes = (BYTES_PER_EDGE_PACKED if packed else BYTES_PER_EDGE) * E + BYTES_PER_ARRIVAL * arrivals
     if fused:
         alg_bytes += BYTES_PER_VERTEX_UPDATE * spec.n
     achieved = alg_bytes / avg_deliver_s / 1e9
@@ -501,7 +502,7 @@ def main():
             "workload": "LIF geometric network, N=%d vertices in a %.0f um cube, %d edges "
                         "(%s, fp16 w), 20%% inhibitory, noise 0.05, dt 0.1 ms"
                         % (spec.n, spec.meta["extent_um"][0], E,
-                           "u32 source | u8 delay << 24" if fused else "int32 src, u8 delay"),
+                           "u32 source | u8 delay << 24" if packed else "int32 src, u8 delay"),
             "n_vertices": spec.n,
             "n_edges": E,
             "max_delay_steps": info["max_delay"],

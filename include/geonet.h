@@ -135,6 +135,12 @@ typedef struct {
                                              vertices, fewer than 2^32 edge slots and the full
                                              summary (not with NET_BUILD_SUMMARY_HALF); otherwise
                                              the two kernels are used. net_info reports which. */
+#define NET_BUILD_DELIVER_PACKED 2048    /* delivery: two chunks per wave iteration, the edges
+                                             streamed as one 32-bit word each (source | delay << 24:
+                                             4 B per edge instead of 5) and the next pair's loads
+                                             issued behind this pair's history gathers; needs fewer
+                                             than 2^24 vertices (else DELIVER_UNROLL2 is used) and
+                                             4 B per edge slot of device memory more */
 #define NET_BUILD_SINGLE_LAUNCH 32        /* one network: run all steps of a call in one launch of
                                              the LDS-resident kernel ensembles use, when the
                                              network fits one workgroup's LDS */

@@ -26,6 +26,7 @@ NET_BUILD_DELIVER_PIPELINE = 128
 NET_BUILD_SUMMARY_HALF = 256
 NET_BUILD_DELIVER_COMPACT = 512
 NET_BUILD_FUSED_STEP = 1024
+NET_BUILD_DELIVER_PACKED = 2048
 NET_BUILD_AUTOTUNE = 64
 
 NET_OBS_V = 1

@@ -371,8 +371,17 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
         if ((st = upload(h, &sc, hg.seg_chunk, hg.seg_chunk.size(), s, "segments")) != NET_OK) return bail(st);
         if ((st = zeros(h, &g.age_alt, np + kAgePad, s, "ages", kAgeNever)) != NET_OK) return bail(st);
         if ((st = zeros(h, &g.summary_alt, np / 32, s, "summary")) != NET_OK) return bail(st);
-        // the fused step streams one word per slot, source | delay << 24
-        // (sources are below 2^24: a fused network has at most 2^20 vertices)
+        g.seg_vertex = sv;
+        g.seg_chunk = sc;
+        g.n_seg = static_cast<int32_t>(hg.seg_vertex.size()) - 1;
+        g.seg_max = hg.seg_max;
+    }
+    // the fused step and the packed delivery variant stream one word per
+    // slot, source | delay << 24 (sources below 2^24; a fused network has at
+    // most 2^20 vertices)
+    const int bflags = opts ? opts->flags : 0;
+    if ((!hg.seg_vertex.empty() || (bflags & (NET_BUILD_DELIVER_PACKED | NET_BUILD_AUTOTUNE))) &&
+        g.n_pad < (int64_t(1) << 24)) {
         std::vector<uint32_t> packed(static_cast<size_t>(hg.e_slots));
         for (int64_t k = 0; k < hg.e_slots; ++k)
             packed[k] = static_cast<uint32_t>(hg.src[k]) | (static_cast<uint32_t>(hg.d[k]) << 24);
@@ -384,10 +393,6 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
         }
         if (st != NET_OK) return bail(st);
         g.sd = sd;
-        g.seg_vertex = sv;
-        g.seg_chunk = sc;
-        g.n_seg = static_cast<int32_t>(hg.seg_vertex.size()) - 1;
-        g.seg_max = hg.seg_max;
     }
     hipError_t e = configure_deliver(g, opts, h->lc);
     if (e != hipSuccess) {
@@ -466,11 +471,13 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
                                 NET_BUILD_SUMMARY_HALF | NET_BUILD_DELIVER_PIPELINE,
                                 NET_BUILD_SUMMARY_HALF | NET_BUILD_DELIVER_UNROLL2,
                                 NET_BUILD_DELIVER_COMPACT,
-                                NET_BUILD_DELIVER_COMPACT | NET_BUILD_SUMMARY_HALF};
+                                NET_BUILD_DELIVER_COMPACT | NET_BUILD_SUMMARY_HALF,
+                                NET_BUILD_DELIVER_PACKED,
+                                NET_BUILD_DELIVER_PACKED | NET_BUILD_SUMMARY_HALF};
         net_build_opts o = opts ? *opts : net_build_opts{};
         const int keep = o.flags & ~(NET_BUILD_DELIVER_UNROLL2 | NET_BUILD_DELIVER_NONTEMPORAL |
                                      NET_BUILD_DELIVER_STREAM_WEIGHTS | NET_BUILD_DELIVER_PIPELINE |
-                                     NET_BUILD_SUMMARY_HALF | NET_BUILD_DELIVER_COMPACT);
+                                     NET_BUILD_SUMMARY_HALF | NET_BUILD_DELIVER_COMPACT | NET_BUILD_DELIVER_PACKED);
         int best = -1;
         double best_ms = 0.0;
         for (int k = 0; k < static_cast<int>(sizeof(variants) / sizeof(variants[0])); ++k) {
@@ -641,6 +648,7 @@ net_status net_info(const net_t* h, net_info_t* out) {
     out->deliver_threads = h->lc.deliver_threads;
     out->device_bytes = h->device_bytes;
     out->deliver_flags = (h->lc.mode == 1 ? NET_BUILD_DELIVER_UNROLL2 : 0) |
+                         (h->lc.mode == 4 ? NET_BUILD_DELIVER_PACKED : 0) |
                          (h->lc.mode == 2 ? NET_BUILD_DELIVER_PIPELINE : 0) |
                          (h->lc.mode == 3 ? NET_BUILD_DELIVER_COMPACT : 0) |
                          (h->lc.fused ? NET_BUILD_FUSED_STEP : 0) |

@@ -132,7 +132,8 @@ struct LaunchConfig {
     bool lds_summary = false;
     bool stream_weights = false;
     bool nontemporal = false;
-    int mode = 0;                  // delivery loop: 0 one chunk, 1 two chunks, 2 pipelined, 3 compacted
+    int mode = 0;                  // delivery loop: 0 one chunk, 1 two chunks, 2 pipelined, 3 compacted,
+                                   // 4 two packed chunks with the next pair prefetched
     bool fused = false;            // one kernel per step (delivery + vertex update), see launch_step
     int32_t queue_off = 0;         // fused step: arrival queues' offset in LDS (floats after the inputs)
     size_t lds_bytes = 0;

@@ -357,7 +357,7 @@ __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
     const int64_t c_begin = static_cast<int64_t>(lb) * a.n_chunks / nb;
     const int64_t c_end = static_cast<int64_t>(lb + 1) * a.n_chunks / nb;
     const uint32_t t = a.t;
-    constexpr int kPer = kMode == 1 ? 2 : 1;             // chunks per iteration
+    constexpr int kPer = (kMode == 1 || kMode == 4) ? 2 : 1;   // chunks per iteration
     const int64_t stride = static_cast<int64_t>(nwaves) * kPer;
 
     if (kLdsSummary) {
@@ -367,7 +367,35 @@ __global__ void __launch_bounds__(1024) deliver_kernel(DeliverArgs a) {
     }
 
     int64_t c = c_begin + static_cast<int64_t>(wave) * kPer;
-    if (kMode == 3) {
+    if (kMode == 4) {
+        // two packed chunks per iteration; the next pair's stream loads are
+        // issued right after this pair's gathers (unconditional: past the
+        // range they re-read this pair, which L2 still holds), so waiting
+        // for the gathers never waits for them
+        PackedChunk cur[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) load_packed_chunk(cur[u], a.sd, c + u < c_end ? c + u : c_begin, lane);
+        for (; c < c_end; c += stride) {
+            uint32_t aw[2][8];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) gather_chunk<kLdsSummary>(cur[u], a, lds_summary, a.sum_shift, aw[u]);
+            const int64_t cn = c + stride;
+            PackedChunk nxt[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                load_packed_chunk(nxt[u], a.sd, cn + u < c_end ? cn + u : (c + u < c_end ? c + u : c), lane);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (c + u < c_end && chunk_may_fire(cur[u], aw[u])) {
+                    const uint32_t fired = fired_bits(cur[u], a, t, aw[u]);
+                    if (wave_ballot(fired != 0)) deliver_fired<false>(a, c + u, lane, fired, u32x4{0u, 0u, 0u, 0u});
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) cur[u] = nxt[u];
+        }
+    } else if (kMode == 3) {
         uint32_t* stage = reinterpret_cast<uint32_t*>(lds_summary4 + a.stage_vec4) + wave * kChunkEdges;
         for (; c < c_end; c += stride) {
             ChunkRegs cur;
@@ -1117,6 +1145,10 @@ hipError_t configure_deliver(DeviceGraph& g, const net_build_opts* opts, LaunchC
     lc.nontemporal = (flags & NET_BUILD_DELIVER_NONTEMPORAL) != 0;
     lc.mode = (flags & NET_BUILD_DELIVER_UNROLL2) ? 1 : ((flags & NET_BUILD_DELIVER_PIPELINE) ? 2 : 0);
     if ((flags & NET_BUILD_DELIVER_COMPACT) && g.n_pad <= (int64_t(1) << 24)) lc.mode = 3;
+    if ((flags & NET_BUILD_DELIVER_PACKED) && lc.mode != 3) {
+        lc.mode = g.sd ? 4 : 1;
+        if (g.sd) lc.stream_weights = lc.nontemporal = false;   // the packed loop streams neither
+    }
     // Workgroups per CU limited by the summary (and, compacted, the per-wave
     // candidate stages) held in LDS (160 KiB per CU).
     int threads = 1024, per_cu = 8;
@@ -1145,6 +1177,7 @@ hipError_t configure_deliver(DeviceGraph& g, const net_build_opts* opts, LaunchC
                                  GEONET_DELIVER_FN(L, true, false, M) GEONET_DELIVER_FN(L, true, true, M)
             GEONET_DELIVER_FNS(true, 0) GEONET_DELIVER_FNS(true, 1) GEONET_DELIVER_FNS(true, 2)
             GEONET_DELIVER_FNS(true, 3) GEONET_DELIVER_FNS(false, 3)
+            GEONET_DELIVER_FN(true, false, false, 4)
 #undef GEONET_DELIVER_FNS
 #undef GEONET_DELIVER_FN
         };
@@ -1233,6 +1266,8 @@ hipError_t launch_deliver(const DeviceGraph& g, const LaunchConfig& lc, int64_t 
         GEONET_DELIVER_CASES(1)
         GEONET_DELIVER_CASES(2)
         GEONET_DELIVER_CASES(3)
+        GEONET_DELIVER_CASE(4, false, false, false)
+        GEONET_DELIVER_CASE(4, true, false, false)
 #undef GEONET_DELIVER_CASES
 #undef GEONET_DELIVER_CASE
         default:

@@ -296,7 +296,7 @@ def test_autotuned_per_step_equals_default():
 
 
 @pytest.mark.parametrize("flags", ["DELIVER_STREAM_WEIGHTS", "DELIVER_UNROLL2", "DELIVER_NONTEMPORAL",
-                                   "DELIVER_PIPELINE", "SUMMARY_HALF", "DELIVER_COMPACT"])
+                                   "DELIVER_PIPELINE", "SUMMARY_HALF", "DELIVER_COMPACT", "DELIVER_PACKED"])
 def test_delivery_variants_identical(flags):
     gn, torch = _gn()
     spec = synth.config1(n=8192)
@@ -339,7 +339,7 @@ def test_fused_step_with_observation():
     assert outs[0].shape[0] == 6 and np.array_equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("variant", ["default", "FUSED_STEP", "DELIVER_COMPACT", "DELIVER_UNROLL2"])
+@pytest.mark.parametrize("variant", ["default", "FUSED_STEP", "DELIVER_COMPACT", "DELIVER_UNROLL2", "DELIVER_PACKED"])
 def test_fast_source_long_delays(variant):
     """A source firing every ~23 steps under a constant input, with delays of
     1, 43, 200, 254 and 255 steps: with several of its spikes inside a delay
@@ -361,7 +361,7 @@ def test_fast_source_long_delays(variant):
     assert (o["input"][:, 5] != 0).sum() > 30                 # arrivals on the 255-step edge
 
 
-@pytest.mark.parametrize("variant", ["default", "FUSED_STEP"])
+@pytest.mark.parametrize("variant", ["default", "FUSED_STEP", "DELIVER_PACKED"])
 @pytest.mark.parametrize("n", [1, 100])
 def test_degenerate_networks(variant, n):
     """No edges at all (every row is a placeholder slot): a single driven
