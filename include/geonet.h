@@ -134,7 +134,10 @@ typedef struct {
                                              fixed 128 KiB of LDS), segments of at most 6,080
                                              vertices, fewer than 2^32 edge slots and the full
                                              summary (not with NET_BUILD_SUMMARY_HALF); otherwise
-                                             the two kernels are used. net_info reports which. */
+                                             the two kernels are used. net_info reports which.
+                                             The step streams one 32-bit word per edge slot
+                                             (source | delay << 24), built at net_build: 4 B per
+                                             slot of device memory more. */
 #define NET_BUILD_DELIVER_PACKED 2048    /* delivery: two chunks per wave iteration, the edges
                                              streamed as one 32-bit word each (source | delay << 24:
                                              4 B per edge instead of 5) and the next pair's loads
