@@ -308,6 +308,25 @@ def test_delivery_variants_identical(flags):
         assert np.array_equal(a[key], b[key]), key
 
 
+@pytest.mark.parametrize("combo", [("DELIVER_PACKED", "SUMMARY_HALF"), ("DELIVER_PACKED", "NO_LDS_SUMMARY")])
+def test_packed_delivery_combinations_identical(combo):
+    """The packed loop with the half-resolution summary (an autotuner
+    candidate) and with the summary read from global memory."""
+    gn, torch = _gn()
+    spec = synth.config1(n=8192 + 37)
+    T = 600
+    a = run_gpu(spec, T)
+    flags = 0
+    for f in combo:
+        flags |= getattr(gn, "NET_BUILD_" + f)
+    b = run_gpu(spec, T, flags=flags)
+    inf = b["net"].info()
+    assert inf["deliver_flags"] & gn.NET_BUILD_DELIVER_PACKED
+    assert inf["lds_summary"] == (0 if "NO_LDS_SUMMARY" in combo else 1)
+    for key in ("raster", "v", "input"):
+        assert np.array_equal(a[key], b[key]), key
+
+
 @pytest.mark.parametrize("n,T", [(8192 + 37, 600), (65536, 300)])
 def test_fused_step_equals_two_kernels(n, T):
     """One kernel per step (delivery into LDS, then the workgroup's own
