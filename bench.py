@@ -26,14 +26,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_EDGE = 5      # int32 source + uint8 delay, streamed every step
+# Algorithmic bytes of one step, per unit of work (the roofline's figure):
+# every edge streams its int32 source and uint8 delay (5 B), an edge that
+# delivers a spike also reads its FP16 weight (2 B), and every vertex update
+# moves about 18 B (V read and written, refractory/age state, the history-ring
+# bit and the delivered input).
+BYTES_PER_EDGE = 5
+BYTES_PER_ARRIVAL = 2
+BYTES_PER_VERTEX = 18
+# What the stream formats themselves move (reported beside the fraction):
 BYTES_PER_EDGE_PACKED = 4   # fused step and packed delivery: one word per edge, source | delay << 24
-BYTES_PER_ARRIVAL = 2   # FP16 weight, loaded only when its edge delivers a spike
 BYTES_PER_EDGE_STREAMED_W = 7   # delivery variant that streams every weight with its edge
-# vertex update per step: V read + written (8), two-spike ages read + written
-# (4), history-ring word read + written (8), one summary bit (1/8)
+# fused step's vertex update: V read + written (8), two-spike ages read +
+# written (4), history-ring word read + written (8), one summary bit (1/8)
 BYTES_PER_VERTEX_UPDATE = 20.125
-TIMING_EVERY = 16       # kernel-bound events on one launch in 16 across the timed region
+TIMING_EVERY = 16       # kernel-bound events on one launch in 16 across long timed regions
+MIN_TIMED_LAUNCHES = 64  # shorter timed regions bind events to more launches (every launch below 64 steps)
 
 
 def measured_traffic(deliver_flags):
@@ -60,8 +68,59 @@ def measured_traffic(deliver_flags):
     return None
 
 
+def stream_ceiling(torch, nbytes):
+    """Achievable HBM streaming rate on this device, for the roofline's
+    context: a read-only pass (FP32 sum) and a device copy over `nbytes`,
+    timed with events on torch's stream (median of 5 after 2 warm-ups)."""
+    n = int(nbytes) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+
+    def timed(fn):
+        ms = []
+        for k in range(7):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            if k >= 2:
+                ms.append(a.elapsed_time(b))
+        return sorted(ms)[len(ms) // 2] / 1e3
+
+    t_read = timed(lambda: x.sum())
+    t_copy = timed(lambda: y.copy_(x))
+    del x, y
+    torch.cuda.empty_cache()
+    return {"bytes": n * 4, "read_only_GBps": n * 4 / t_read / 1e9, "copy_GBps": 2 * n * 4 / t_copy / 1e9,
+            "method": "torch FP32 sum (read only) and device copy over the same byte count, median of 5"}
+
+
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def host_cpu():
+    """Model name of the host CPU (lscpu) and the cores the OS shows."""
+    model = None
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, ValueError, Exception):
+        pass
+    if model is None:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    return {"model": model, "nproc": os.cpu_count()}
 
 
 def cpu_baseline(spec, steps):
@@ -77,14 +136,16 @@ def cpu_baseline(spec, steps):
         "unit": "edge-steps/s",
         "cores": 1,
         "kind": "oracle",
+        "host_cpu": host_cpu(),
         "sample": "same network, first %d of the steps (single-threaded FP64 event-driven oracle; "
-                  "%.1f s run after %.1f s set-up)" % (steps, t2 - t1, t1 - t0),
+                  "%.1f s run after %.1f s set-up; its per-step cost is the vertex update of all N "
+                  "vertices, so the start-up's lower spike rate barely changes it)" % (steps, t2 - t1, t1 - t0),
     }
 
 
 def arrivals_per_step(net, spec, steps):
-    """Mean number of edges that deliver a spike per step, from a recorded
-    stretch right after the timed region: sum over sources of spikes x
+    """Mean number of edges that deliver a spike per step over the next
+    `steps` steps, which are recorded: sum over sources of spikes x
     out-degree, divided by the steps."""
     import numpy as np
     import torch
@@ -193,7 +254,7 @@ def ensemble_cpu_baseline(specs, n_all, every=16, steps=2000):
         net.close()
     per_net = t / len(sample) * (10000 / steps)
     return {"value": 1.0 / per_net, "unit": "networks per second (10,000-step runs)", "cores": 1, "kind": "oracle",
-            "sample": "every %dth of the %d networks (%d), %d steps each, single-threaded FP64; %.1f s"
+            "host_cpu": host_cpu(), "sample": "every %dth of the %d networks (%d), %d steps each, single-threaded FP64; %.1f s"
                       % (every, n_all, len(sample), steps, t)}
 
 
@@ -269,7 +330,143 @@ def mlp_cpu_baseline(X, y, params, rows=16384):
         M.grad(params.astype("float64"), X, y, bf=True)
         t = time.perf_counter() - t0
     return {"value": rows / t, "unit": "training pairs per second (forward + gradient)", "cores": 1,
-            "kind": "oracle", "sample": "one %d-row batch through the FP64 MLP reference (numpy); %.2f s" % (rows, t)}
+            "kind": "oracle", "host_cpu": host_cpu(), "sample": "one %d-row batch through the FP64 MLP reference (numpy); %.2f s" % (rows, t)}
+
+
+TESTSET_CURRENT_PA = 60.0     # constant input above the regular-spiking rheobase (51.4 pA): tonic firing
+TESTSET_W_PA = 25.0           # alpha-PSC weight scale at the in-degree of the k = 8 lattice
+
+
+def testset_specs(synth, dims=(2,)):
+    """The standardized test networks as Izhikevich networks with an alpha
+    PSC at dt = 1 ms (the paper's benchmark model and step), driven by a
+    constant current as in its Figure 8; weights U[0.5,1.5] * 25 pA scaled
+    by 8 / mean in-degree so that denser classes are not driven harder."""
+    from synth import testset as ts
+    import numpy as np
+    out = []
+    for s in ts.test_set(dims_list=dims):
+        indeg = max(1.0, s.n_edges / s.n)
+        scale = TESTSET_W_PA * min(1.0, 8.0 / indeg)
+        z = synth.izhikevich(s, psc=2, w_scale=scale)
+        z.i_ext = np.full(s.n, TESTSET_CURRENT_PA, np.float32)
+        z.noise_sigma = synth.IZ_NOISE_SIGMA
+        z.meta = dict(s.meta)
+        out.append(z)
+    return out
+
+
+def bench_testset(args, torch, synth, gn):
+    """The paper's benchmark (Section 3.4, Figure 4) on this GPU: its test
+    networks (lattice, small-world, scale-free, random; low and high density;
+    N = 10 .. 1000; here the 40 two-dimensional ones) with the Izhikevich
+    vertex and an alpha PSC at dt = 1 ms for 10 s (10,000 steps).  Reported
+    as the paper does, the real-time factor = simulated time / wall time:
+    every network on its own handle (one launch per call, launch shape
+    autotuned), and the 40 together as one ensemble launch.  value = the
+    ensemble's real-time factor per network (40 x 10 s simulated / wall)."""
+    import numpy as np
+    specs = testset_specs(synth)
+    steps = args.steps
+    sim_s = steps * synth.IZ_DT_MS * 1e-3
+    rows = []
+    for s in specs:
+        net = gn.Net(s, flags=gn.NET_BUILD_SINGLE_LAUNCH | gn.NET_BUILD_AUTOTUNE)
+        net.step(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = net.step(steps, raster=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        spikes = int(gn.unpack_raster(out["raster"], s.n).sum())
+        net.close()
+        rows.append({"name": s.name, "n": s.n, "edges": s.n_edges, "class": s.meta["class"],
+                     "density": s.meta["density"], "rtf": sim_s / wall, "rate_hz": spikes / s.n / sim_s})
+        log("%-28s N=%4d E=%6d  real-time factor %7.1f  (%.1f Hz)" % (s.name, s.n, s.n_edges, sim_s / wall,
+                                                                      spikes / s.n / sim_s))
+    ens = gn.Net(specs, flags=gn.NET_BUILD_AUTOTUNE)
+    info = ens.info()
+    ens.step(args.warmup)
+    torch.cuda.synchronize()
+    ens.timing_begin(8)
+    t0 = time.perf_counter()
+    ens.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = ens.timing_end()
+    ens.close()
+    E = sum(s.n_edges for s in specs)
+    N = sum(s.n for s in specs)
+    rtf = np.array([r["rtf"] for r in rows])
+    worst = rows[int(np.argmin(rtf))]
+    log("ensemble of %d: %.3f s for %d steps (kernel %.3f ms), %d blocks x %d threads"
+        % (len(specs), wall, steps, tm["ensemble_ms"], info["ensemble_blocks"], info["ensemble_threads"]))
+    cpu = None if args.no_cpu_baseline else testset_cpu_baseline(specs, steps)
+    return {
+        "metric": "real-time factor",
+        "value": len(specs) * sim_s / wall,
+        "unit": "simulated seconds per wall second per network (40 test networks in one launch)",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (vertex state), f32 (delivered sums)",
+        "data": "synthetic",
+        "config": {
+            "workload": "the paper's 40 two-dimensional test networks (4 classes x 2 densities x N = 10..1000), "
+                        "Izhikevich vertex with alpha PSC, dt 1 ms, 10 s, constant 60 pA input, noise 1 mV",
+            "n_networks": len(specs), "n_vertices": N, "n_edges": E,
+            "launch": "%d workgroups x %d threads, one launch per call" % (info["ensemble_blocks"],
+                                                                          info["ensemble_threads"]),
+        },
+        "alone": {
+            "method": "each network on its own handle, single-launch kernel, autotuned; real-time factor = 10 s / wall",
+            "min": float(rtf.min()), "median": float(np.median(rtf)), "max": float(rtf.max()),
+            "slowest": worst,
+            "by_network": [{k: (round(v, 2) if isinstance(v, float) else v) for k, v in r.items()} for r in rows],
+        },
+        "edge_steps_per_s": E * steps / wall,
+        "roofline": {
+            "bound": "hbm", "kernel": "ensemble_kernel",
+            "achieved": BYTES_PER_EDGE * E * steps / (tm["ensemble_ms"] / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": BYTES_PER_EDGE * E * steps / (tm["ensemble_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "traffic": None,
+            "note": "5 B per edge-step; %.1f MB of edges stay in L2: the bound is each workgroup's per-step "
+                    "barriers and LDS work, not HBM" % (BYTES_PER_EDGE * E / 1e6),
+        },
+        "paper_context": "Section 3.4: on one Tesla C1060 its Izhikevich networks (dt 1 ms) ran 10-20x faster "
+                         "than real time for most networks and about real time for the largest random ones; "
+                         "one 2.5 GHz Core2Duo core ran them from just under real time (10 vertices) to ~15x "
+                         "slower (largest random)",
+        "cpu_baseline": cpu,
+    }
+
+
+def testset_cpu_baseline(specs, steps, sample_steps=1000):
+    """The FP64 oracle, single-threaded, on every test network for
+    sample_steps steps: the real-time factor of each, as the paper's CPU
+    panels report it."""
+    import numpy as np
+    import oracle
+    rtf = []
+    t_all = 0.0
+    for s in specs:
+        net = oracle.OracleNet(s)
+        t0 = time.perf_counter()
+        net.step(sample_steps, raster=False)
+        dt = time.perf_counter() - t0
+        net.close()
+        t_all += dt
+        rtf.append(sample_steps * s.dt_ms * 1e-3 / dt)
+    rtf = np.array(rtf)
+    return {"value": float(np.median(rtf)), "unit": "real-time factor (median over the 40 networks)",
+            "cores": 1, "kind": "oracle", "host_cpu": host_cpu(), "min": float(rtf.min()), "max": float(rtf.max()),
+            "sample": "every network for %d steps (1 s simulated), single-threaded FP64 oracle; %.1f s in all"
+                      % (sample_steps, t_all)}
 
 
 def bench_estimate(args, torch, synth):
@@ -380,7 +577,7 @@ def estimate_cpu_baseline(o, sc, pairs=32768):
         M.forward(p, X, bf=True, shift=shift, scale=scale)
         wall = time.perf_counter() - t0
     return {"value": len(P) / wall, "unit": "candidate pairs scored per second (features + MLP)", "cores": 1,
-            "kind": "oracle", "sample": "the first %d candidate pairs of one held-out network (FP64 oracle features "
+            "kind": "oracle", "host_cpu": host_cpu(), "sample": "the first %d candidate pairs of one held-out network (FP64 oracle features "
             "and MLP, single-threaded); %.1f s" % (len(P), wall)}
 
 
@@ -398,11 +595,12 @@ def main():
                          "iteration; 2 streams every weight, 7 B per edge)")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library time the delivery variants at build instead of --deliver-flags")
-    ap.add_argument("--workload", choices=["step", "ensemble", "estimate", "mlp"], default="step",
+    ap.add_argument("--workload", choices=["step", "ensemble", "estimate", "mlp", "testset"], default="step",
                     help="step: the N = 2^20 network (default); ensemble: 512 uneven networks in one launch "
                          "against each network run alone; estimate: learned edge scorer against the "
                          "simulation-based fit on held-out N = 1024 networks; mlp: the edge scorer's training "
-                         "step and forward pass")
+                         "step and forward pass; testset: the paper's test networks with the Izhikevich vertex "
+                         "(real-time factors, Section 3.4)")
     ap.add_argument("--train-nets", type=int, default=256, help="estimate workload: training networks")
     ap.add_argument("--test-nets", type=int, default=16, help="estimate workload: held-out networks")
     ap.add_argument("--obs-steps", type=int, default=200000, help="estimate workload: observed steps (20 s)")
@@ -412,7 +610,11 @@ def main():
     ap.add_argument("--seq-sample", type=int, default=8,
                     help="ensemble workload: time every k-th network alone and scale to all")
     ap.add_argument("--rate-steps", type=int, default=500,
-                    help="steps recorded after the timed region to count arrivals per step")
+                    help="steps recorded right before the warm-up and right after the timed region to count "
+                         "arrivals per step")
+    ap.add_argument("--preroll", type=int, default=2000,
+                    help="untimed steps run first, whatever --warmup is, so that the timed steps see the "
+                         "network's steady spike rate rather than the start from rest")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy three times (reference for HBM counters)")
     args = ap.parse_args()
@@ -432,6 +634,9 @@ def main():
     if args.workload == "estimate":
         print(json.dumps(bench_estimate(args, torch, synth)), flush=True)
         return
+    if args.workload == "testset":
+        print(json.dumps(bench_testset(args, torch, synth, gn)), flush=True)
+        return
     if args.workload == "mlp":
         print(json.dumps(bench_mlp(args, torch, gn)), flush=True)
         return
@@ -450,17 +655,27 @@ def main():
     info = net.info()
     log("built in %.1f s: %s" % (time.perf_counter() - t0, info))
 
+    # Untimed pre-roll past the start-up transient (V starts at rest and the
+    # network needs a few hundred steps to reach its steady spike rate), then
+    # a recorded window for the arrival count, the warm-up, the timed steps
+    # and a second recorded window right after them.
+    net.step(args.preroll)
+    torch.cuda.synchronize()
+    arr_before = arrivals_per_step(net, spec, args.rate_steps)
     net.step(args.warmup)
     torch.cuda.synchronize()
-    net.timing_begin(2 * args.steps // TIMING_EVERY + 4, every=TIMING_EVERY)
+    every = TIMING_EVERY if args.steps >= MIN_TIMED_LAUNCHES * TIMING_EVERY \
+        else max(1, args.steps // MIN_TIMED_LAUNCHES)
+    net.timing_begin(2 * args.steps // every + 4, every=every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     net.step(args.steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     tm = net.timing_end()
-    log("timed %d steps in %.3f s; kernels: deliver %.3f ms, update %.3f ms, fused step %.3f ms"
-        % (args.steps, wall, tm["deliver_ms"], tm["update_ms"], tm["step_ms"]))
+    log("timed %d steps in %.3f s after %d pre-roll and %d warm-up steps; kernels: deliver %.3f ms, "
+        "update %.3f ms, fused step %.3f ms" % (args.steps, wall, args.preroll, args.warmup, tm["deliver_ms"],
+                                                tm["update_ms"], tm["step_ms"]))
 
     E = spec.n_edges
     value = E * args.steps / wall
@@ -468,20 +683,31 @@ def main():
     kernel = "step_kernel" if fused else "deliver_kernel"
     if fused:
         avg_deliver_s = tm["step_ms"] / tm["step_launches"] / 1e3
+        timed_launches = tm["step_launches"]
     else:
         avg_deliver_s = tm["deliver_ms"] / tm["deliver_launches"] / 1e3
-    arrivals = arrivals_per_step(net, spec, args.rate_steps)
+        timed_launches = tm["deliver_launches"]
+    arr_after = arrivals_per_step(net, spec, args.rate_steps)
+    arrivals = 0.5 * (arr_before + arr_after)
     streamed_w = bool(info["deliver_flags"] & gn.NET_BUILD_DELIVER_STREAM_WEIGHTS)
     packed = fused or bool(info["deliver_flags"] & gn.NET_BUILD_DELIVER_PACKED)
-    if streamed_w:
-        alg_bytes = BYTES_PER_EDGE_STREAMED_W * E
-    else:
-        alg_bytes = (BYTES_PER_EDGE_PACKED if packed else BYTES_PER_EDGE) * E + BYTES_PER_ARRIVAL * arrivals
+    # the roofline's algorithmic bytes (same for every variant: what the step must move)
+    alg_bytes = BYTES_PER_EDGE * E + BYTES_PER_ARRIVAL * arrivals
     if fused:
-        alg_bytes += BYTES_PER_VERTEX_UPDATE * spec.n
+        alg_bytes += BYTES_PER_VERTEX * spec.n
+    # what this variant's stream format moves
+    if streamed_w:
+        fmt_bytes = BYTES_PER_EDGE_STREAMED_W * E
+    else:
+        fmt_bytes = (BYTES_PER_EDGE_PACKED if packed else BYTES_PER_EDGE) * E + BYTES_PER_ARRIVAL * arrivals
+    if fused:
+        fmt_bytes += BYTES_PER_VERTEX_UPDATE * spec.n
     achieved = alg_bytes / avg_deliver_s / 1e9
-    log("arrivals per step %.0f (%.4f %% of edges); algorithmic bytes per launch %.0f"
-        % (arrivals, 100.0 * arrivals / E, alg_bytes))
+    traffic = measured_traffic(info["deliver_flags"])
+    log("arrivals per step %.0f before / %.0f after the timed steps (%.4f %% of edges); algorithmic bytes "
+        "per launch %.0f, stream format %.0f; %s: %.2f us per timed launch (%d launches)"
+        % (arr_before, arr_after, 100.0 * arrivals / E, alg_bytes, fmt_bytes, kernel, avg_deliver_s * 1e6,
+           timed_launches))
     v_now = net.observe(gn.NET_OBS_V)
     torch.cuda.synchronize()
     sim_s = args.steps * spec.dt_ms * 1e-3
@@ -492,6 +718,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "preroll_steps": args.preroll,
         "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
@@ -519,16 +746,29 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(info["deliver_flags"]),
+            "traffic": traffic,
             "algorithmic_bytes_per_launch": alg_bytes,
+            "bytes_rule": "%d B per edge + %d B per arriving spike + %d B per vertex%s"
+                          % (BYTES_PER_EDGE, BYTES_PER_ARRIVAL, BYTES_PER_VERTEX, "" if fused else
+                             " (vertex bytes belong to the separate update kernel)"),
             "arrivals_per_step": arrivals,
+            "arrivals_per_step_before_after": [arr_before, arr_after],
             "avg_launch_us": avg_deliver_s * 1e6,
-            "timed_launches": tm["step_launches"] if fused else tm["deliver_launches"],
-            "timing": "kernel-bound HIP events on one launch in %d across the timed region" % TIMING_EVERY,
+            "timed_launches": timed_launches,
+            "timing": "kernel-bound HIP events on one launch in %d across the timed region" % every,
+            "stream_format_bytes_per_launch": fmt_bytes,
+            "frac_stream_format": fmt_bytes / avg_deliver_s / 1e9 / HBM_PEAK_GBS,
+            "frac_traffic": (traffic / avg_deliver_s / 1e9 / HBM_PEAK_GBS) if traffic else None,
+            "target_frac": 0.60,
             "update_avg_launch_us": (tm["update_ms"] / tm["update_launches"] * 1e3) if tm["update_launches"] else None,
         },
     }
     net.close()
+    ceil = stream_ceiling(torch, alg_bytes)
+    ceil["frac_of_read_only"] = achieved / ceil["read_only_GBps"]
+    result["roofline"]["measured_ceiling"] = ceil
+    log("streaming ceiling over %.0f MB: read-only %.0f GB/s, copy %.0f GB/s"
+        % (ceil["bytes"] / 1e6, ceil["read_only_GBps"], ceil["copy_GBps"]))
     del v_now
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on %d steps" % args.cpu_steps)

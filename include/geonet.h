@@ -99,7 +99,30 @@ typedef struct {
     const float* v0;              /* host [n_nodes] V(0), or NULL for v_rest */
     float tau_c_ms;               /* calcium removal time constant */
     int32_t frame_num, frame_den; /* frame(t) = floor(t*num/den); equal across an ensemble */
+    /* Vertex model (Section 3.1).  NET_MODEL_LIF: the leaky integrate-and-fire
+       vertex above.  NET_MODEL_IZHIKEVICH: the simple model of Eq. izsimple,
+       Euler-stepped with its state (V, W and the PSC states) in FP64; v_th is
+       V_peak and v_reset is c (tau_ms, v_rest unused; n_ref must be 0):
+         s_j(t) = [V >= V_peak];  if s: V <- c, W <- W + d
+         else V <- V + dt*(1/C)*[k(V-Vr)(V-Vt) - W + r + U] (+ I for psc NONE) + sigma*xi
+              W <- W + dt*a*(b(V-Vr) - W)
+       with U = i_ext + drive_amp*pulse (pA) and xi drawn in FP64.  Delivered
+       input (Section 3.2) as a post-synaptic current, updated every step:
+         NET_PSC_NONE  I jumps V directly (no r);
+         NET_PSC_EXP   r <- r - dt*psc_rate*r + I               (Eq. simplepsc)
+         NET_PSC_ALPHA r <- r + dt*p;  p <- p + dt*(-a^2 r - 2a p) + I, a = psc_rate
+                                                                 (Eqs. alphapsc, izpsc)
+       an arrival being an impulse of its weight (pA for EXP/ALPHA, mV for
+       NONE).  Units: ms, mV, pF, pA, nS. */
+    int32_t model;                /* NET_MODEL_* (0 = LIF) */
+    int32_t psc;                  /* NET_PSC_* (Izhikevich only) */
+    float iz_C, iz_k, iz_vr, iz_vt, iz_a, iz_b, iz_d;   /* Izhikevich constants */
+    float psc_rate;               /* PSC decay rate a (1/ms) */
+    const float* w0;              /* host [n_nodes] initial W, or NULL (0) */
 } net_desc;
+
+enum { NET_MODEL_LIF = 0, NET_MODEL_IZHIKEVICH = 1 };
+enum { NET_PSC_NONE = 0, NET_PSC_EXP = 1, NET_PSC_ALPHA = 2 };
 
 /* Build options; a zeroed struct (or NULL) selects the defaults. */
 typedef struct {
@@ -133,8 +156,9 @@ typedef struct {
                                              CU). Needs at most 2^20 vertices (the summary in a
                                              fixed 128 KiB of LDS), segments of at most 6,080
                                              vertices, fewer than 2^32 edge slots and the full
-                                             summary (not with NET_BUILD_SUMMARY_HALF); otherwise
-                                             the two kernels are used. net_info reports which.
+                                             summary (not with NET_BUILD_SUMMARY_HALF) and LIF
+                                             vertices only; otherwise the two kernels are used.
+                                             net_info reports which.
                                              The step streams one 32-bit word per edge slot
                                              (source | delay << 24), built at net_build: 4 B per
                                              slot of device memory more. */
@@ -296,6 +320,25 @@ net_status net_mlp_grad(net_mlp_t* m, const float* x_dev, const float* y_dev, in
 /* one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the mean BCE of the rows */
 net_status net_mlp_train_step(net_mlp_t* m, const float* x_dev, const float* y_dev, int64_t rows, float lr,
                               float* loss_dev, void* stream);
+/* Input standardisation fitted to training features (device x_dev [rows][64], 1 <= rows <= 2^31),
+   computed on the GPU in FP64: shift = column mean, scale = 1 / column standard deviation
+   (unbiased), or 0 for a column whose deviation is at most 1e-6 (a constant feature is dropped).
+   Replaces what net_mlp_set_input_norm set; ordered on `stream`. */
+net_status net_mlp_fit_input_norm(net_mlp_t* m, const float* x_dev, int64_t rows, void* stream);
+/* The current standardisation (host [64] each); waits for the device. */
+net_status net_mlp_get_input_norm(const net_mlp_t* m, float* shift, float* scale);
+/* One epoch of minibatch training: the rows (x_dev [rows][64], y_dev [rows]) are visited once in
+   the order of a keyed permutation of [0, rows) (net_shuffle_indices with the same seed and epoch),
+   in consecutive batches of `batch` rows, the last one possibly smaller; one Adam step per batch
+   (as net_mlp_train_step).  loss_dev: device [ceil(rows / batch)] mean BCE of each step's batch
+   (before its update), or NULL.  The permuted batch is gathered into a workspace held by the
+   handle (grown, with a stream synchronisation, when a larger batch is asked for). */
+net_status net_mlp_train_epoch(net_mlp_t* m, const float* x_dev, const float* y_dev, int64_t rows, int64_t batch,
+                               float lr, uint64_t shuffle_seed, uint32_t epoch, float* loss_dev, void* stream);
+/* out_dev[i] = pi(i), i < n <= 2^31: the permutation of [0, n) keyed by (seed, epoch) that
+   net_mlp_train_epoch visits rows in (a four-round Feistel network over Philox4x32-10 with cycle
+   walking).  Device int64 [n]; ordered on `stream`. */
+net_status net_shuffle_indices(int64_t n, uint64_t seed, uint32_t epoch, int64_t* out_dev, void* stream);
 void net_mlp_free(net_mlp_t* m);
 const char* net_mlp_last_error(void);
 
@@ -372,6 +415,14 @@ enum { NET_EST_SCORER = 1, NET_EST_SIMFIT = 2, NET_EST_AUTO = 3 };
 net_status net_estimate(const net_obs_desc* obs, int32_t method, net_mlp_t* scorer, const net_simfit_opts* opts,
                         float* scores_dev, void* stream);
 const char* net_estimate_last_error(void);
+
+/*
+ * Error-handling test hook: marks the handle exactly as a device fault seen by
+ * a call would (nothing runs on the device), so that callers can exercise
+ * their NET_E_STATE path without faulting a GPU.  Every later call on the
+ * handle except net_info, net_node_offsets and net_free returns NET_E_STATE.
+ */
+net_status net_simulate_device_error(net_t* h);
 
 /* Release the handle and its device memory (waits for the handle's stream). */
 void net_free(net_t* h);

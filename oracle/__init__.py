@@ -31,7 +31,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-                               src, "-o", tmp, "-lm"])
+                               "-fopenmp", src, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -74,8 +74,36 @@ def _load():
         L.orc_fluorescence.argtypes = [_vp, _c.c_int64, _c.c_int32, _c.c_int64, _c.c_double,
                                        _c.c_double, _c.c_double, _c.c_uint64, _vp]
         L.orc_fluorescence.restype = None
+        L.orc_set_izhikevich.argtypes = [_vp, _c.c_int32, _vp, _c.c_double, _vp]
+        L.orc_set_izhikevich.restype = _c.c_int32
+        L.orc_get_izh.argtypes = [_vp, _vp, _vp, _vp]
+        L.orc_get_izh.restype = None
+        L.orc_set_threads.argtypes = [_c.c_int32]
+        L.orc_set_threads.restype = None
+        L.orc_get_threads.argtypes = []
+        L.orc_get_threads.restype = _c.c_int32
         _lib = L
     return _lib
+
+
+def set_threads(k: int) -> None:
+    """Threads for the per-vertex loops of the simulation oracle (default 1).
+    Results are bit-identical for any count (the spike push stays serial)."""
+    _load().orc_set_threads(int(k))
+
+
+def get_threads() -> int:
+    return int(_load().orc_get_threads())
+
+
+def test_threads() -> int:
+    """Thread count tests use for large oracle runs: the CPUs this process
+    may use, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -141,6 +169,16 @@ class OracleNet:
         if not self.h:
             raise ValueError("oracle rejected the network (bad edge or delay > 255)")
         self._L = L
+        self.model = getattr(spec, "model", 0)
+        if self.model == 1:
+            iz = np.array([spec.iz_C, spec.iz_k, spec.iz_vr, spec.iz_vt, spec.iz_a, spec.iz_b, spec.iz_d],
+                          dtype=np.float64)
+            if not np.array_equal(iz.astype(np.float32).astype(np.float64), iz) or \
+                    float(np.float32(spec.psc_rate)) != spec.psc_rate:
+                raise ValueError("Izhikevich constants must be FP32 values (the library takes them as FP32)")
+            w0 = arr(getattr(spec, "w0_iz", None), np.float32)
+            if L.orc_set_izhikevich(self.h, int(spec.psc), iz.ctypes.data, float(spec.psc_rate), _ptr(w0)) != 0:
+                raise ValueError("oracle rejected the Izhikevich parameters")
 
     def close(self):
         if self.h:
@@ -183,6 +221,12 @@ class OracleNet:
         out = np.zeros(self.n, dtype=np.int32)
         self._L.orc_get_ref(self.h, out.ctypes.data)
         return out
+
+    def izhikevich_state(self):
+        """(W, r, p) of every vertex (Izhikevich networks)."""
+        W, r, p = (np.zeros(self.n, dtype=np.float64) for _ in range(3))
+        self._L.orc_get_izh(self.h, W.ctypes.data, r.ctypes.data, p.ctypes.data)
+        return W, r, p
 
     def calcium(self) -> np.ndarray:
         out = np.zeros(self.n, dtype=np.float64)

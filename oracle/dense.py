@@ -46,8 +46,13 @@ def simulate(n: int, edges: Sequence, steps: int, *, dt: float = 0.1, tau: float
              v_rest: float = 0.0, v_reset: float = 0.0, v_th: float = 1.0, n_ref: int = 20,
              drive_thr: Optional[Sequence[int]] = None, drive_amp: float = 1.5,
              i_ext: Optional[Sequence[float]] = None, sigma: float = 0.0, seed: int = 0,
-             v0: Optional[Sequence[float]] = None) -> Dict[str, list]:
-    """edges: iterable of (src, dst, weight, delay_steps)."""
+             v0: Optional[Sequence[float]] = None, izhikevich: Optional[dict] = None) -> Dict[str, list]:
+    """edges: iterable of (src, dst, weight, delay_steps).
+
+    izhikevich: None for the LIF vertex, else a dict with C, k, vr, vt, a,
+    b, d, psc (0 none, 1 exponential, 2 alpha), psc_a and optionally w0: the
+    simple model of Section 3.1 (V_peak = v_th, c = v_reset) whose synaptic
+    states follow Section 3.2; the records then also hold W, r and p."""
     assert n <= 8, "brute force is for tiny networks"
     W = [[0.0] * n for _ in range(n)]
     A = [[False] * n for _ in range(n)]
@@ -62,6 +67,12 @@ def simulate(n: int, edges: Sequence, steps: int, *, dt: float = 0.1, tau: float
     last = [None] * n
     hist: List[List[int]] = []
     rec_s, rec_v, rec_i = [], [], []
+    iz = izhikevich
+    if iz is not None:
+        Wr = [float(x) for x in iz["w0"]] if iz.get("w0") is not None else [0.0] * n
+        R = [0.0] * n
+        P = [0.0] * n
+        rec_w, rec_r, rec_p = [], [], []
     for t in range(steps):
         s = [1 if V[j] >= v_th else 0 for j in range(n)]
         hist.append(s)
@@ -79,6 +90,36 @@ def simulate(n: int, edges: Sequence, steps: int, *, dt: float = 0.1, tau: float
             I.append(tot)
         rec_i.append(I)
         newV = list(V)
+        if iz is not None:
+            rec_w.append(list(Wr))
+            rec_r.append(list(R))
+            rec_p.append(list(P))
+            a = iz["psc_a"]
+            newW, newR, newP = list(Wr), list(R), list(P)
+            for j in range(n):
+                # synaptic current: an arrival is an impulse into r (exp) or p (alpha)
+                if iz["psc"] == 1:
+                    newR[j] = R[j] - dt * a * R[j] + I[j]
+                elif iz["psc"] == 2:
+                    newR[j] = R[j] + dt * P[j]
+                    newP[j] = P[j] + dt * (-a * a * R[j] - 2.0 * a * P[j]) + I[j]
+                if s[j]:
+                    newV[j] = v_reset
+                    newW[j] = Wr[j] + iz["d"]
+                    continue
+                r = philox4x32_10((j, t & M32, t >> 32, 0), key)
+                u = (float(i_ext[j]) if i_ext is not None else 0.0) + \
+                    (drive_amp if (drive_thr is not None and r[0] < drive_thr[j]) else 0.0)
+                xi = gauss(r[1], r[2])
+                syn = 0.0 if iz["psc"] == 0 else R[j]
+                cur = iz["k"] * (V[j] - iz["vr"]) * (V[j] - iz["vt"]) - Wr[j] + syn + u
+                vn = V[j] + dt * (1.0 / iz["C"]) * cur
+                if iz["psc"] == 0:
+                    vn = vn + I[j]
+                newV[j] = vn + sigma * xi
+                newW[j] = Wr[j] + dt * iz["a"] * (iz["b"] * (V[j] - iz["vr"]) - Wr[j])
+            V, Wr, R, P = newV, newW, newR, newP
+            continue
         for j in range(n):
             if s[j]:
                 newV[j] = v_reset
@@ -93,4 +134,7 @@ def simulate(n: int, edges: Sequence, steps: int, *, dt: float = 0.1, tau: float
             xi = gauss(r[1], r[2])
             newV[j] = V[j] + (dt / tau) * (v_rest - V[j]) + I[j] + u + sigma * xi
         V = newV
-    return {"raster": rec_s, "v": rec_v, "input": rec_i, "v_final": V}
+    out = {"raster": rec_s, "v": rec_v, "input": rec_i, "v_final": V}
+    if iz is not None:
+        out.update(w=rec_w, r=rec_r, p=rec_p)
+    return out

@@ -34,9 +34,51 @@
  *   R6  frames: frame(t) = floor(t*num/den); a frame's value is the mean of
  *       c_j(t) over its steps.
  *
+ * Izhikevich vertex (Section 3.1, Eq. izsimple; with post-synaptic current
+ * states of Section 3.2, Eqs. simplepsc, alphapsc and izpsc), selected per
+ * network by orc_set_izhikevich:
+ *   spike when V >= V_peak (Eq. spd); then V <- c and W <- W + d;
+ *   otherwise Euler: V <- V + dt*(1/C)*[k(V-Vr)(V-Vt) - W + r + U] (+ sigma*xi)
+ *                    W <- W + dt*a*(b(V-Vr) - W)
+ *   PSC (every step, from the state at t):
+ *     none  (psc 0): the delivered sum jumps V directly (as R2);
+ *     exp   (psc 1): r <- r - dt*a_s*r + I      (dr/dt = -a_s r, r += w on arrival)
+ *     alpha (psc 2): r <- r + dt*p,  p <- p + dt*(-a_s^2 r - 2 a_s p) + I
+ *   R16 an arriving spike is an impulse: it adds its weight to r (exp) or p
+ *       (alpha) at once, as Eqs. simplepsc and alphapsc state it; Eq. izpsc's
+ *       transition writes the sum inside dt*( ), which would make the PSC
+ *       amplitude depend on the step, and is read as that same impulse.
+ *   R17 control U = i_ext + A*pulse enters the bracket as a current; the
+ *       state noise sigma*xi is added to V after it (as R5).
+ * Izhikevich state is FP64 here and in the library.
+ *
+ * Hodgkin-Huxley vertex (Section 3.1: four states V, m, n, h; the paper's
+ * benchmark steps it at dt = 0.03 ms), selected by orc_set_hodgkin_huxley,
+ * Euler-stepped from the state at t, with the same PSC kinds:
+ *   C dV/dt = -gNa m^3 h (V - ENa) - gK n^4 (V - EK) - gL (V - EL) + r + U
+ *   dx/dt = alpha_x(V) (1 - x) - beta_x(V) x,  x in {m, h, n}, with
+ *   alpha_m = 0.1 (V + 40) / (1 - exp(-(V + 40)/10)),  beta_m = 4 exp(-(V + 65)/18)
+ *   alpha_h = 0.07 exp(-(V + 65)/20),  beta_h = 1 / (1 + exp(-(V + 35)/10))
+ *   alpha_n = 0.01 (V + 55) / (1 - exp(-(V + 55)/10)), beta_n = 0.125 exp(-(V + 65)/80)
+ *   (mV, ms, uF/cm^2, mS/cm^2, uA/cm^2; alpha_m and alpha_n take their limits
+ *   1 and 0.1 where the denominator vanishes, at V = -40 and V = -55 exactly).
+ *   R20 spd for this vertex is the upward crossing of V_th (V(t) >= V_th
+ *       and V(t-1) < V_th): V stays above any threshold for about a
+ *       millisecond, so the level test of Eq. spd would signal every step of
+ *       an action potential; there is no reset.
+ * HH state is FP64 here and in the library.
+ *
  * Delivery here is event-driven: when vertex i fires at step t its weights
  * are pushed into a per-target inbox slot (t + d) mod 256.  This is a
  * different formulation from a pull over in-edges, on purpose.
+ *
+ * Threads: single-threaded unless orc_set_threads(k > 1) is called (tests
+ * of large networks do, to finish in reasonable time).  Then only the loops
+ * over vertices whose iterations touch nothing but their own vertex (the
+ * spike test and the vertex transition) are split over k threads; the push
+ * of spikes into the inboxes stays one serial loop in vertex order, so every
+ * sum is formed in the same order and the results are bit-identical for any
+ * thread count.
  */
 #include <math.h>
 #include <stdint.h>
@@ -44,6 +86,12 @@
 #include <string.h>
 
 #define ORC_RING 256
+
+static int orc_threads = 1;
+
+/* Threads for the per-vertex loops of orc_step_n (1 = plain serial code). */
+void orc_set_threads(int32_t k) { orc_threads = k > 1 ? k : 1; }
+int32_t orc_get_threads(void) { return orc_threads; }
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon et al., SC'11, Section 3.3 of that paper).          */
@@ -139,6 +187,16 @@ typedef struct {
     double* frames;         /* [cap][n] frame means */
     int64_t frames_cap, n_frames;
     int64_t delivered;      /* count of (spike, edge) deliveries pushed */
+    /* Izhikevich vertex (model 1) with an optional PSC */
+    int32_t model, psc;
+    double iz_C, iz_k, iz_vr, iz_vt, iz_a, iz_b, iz_d, psc_a;
+    double* W;              /* [n] recovery variable */
+    double* r;              /* [n] PSC current */
+    double* p;              /* [n] PSC derivative (alpha) */
+    /* Hodgkin-Huxley vertex (model 2) */
+    double hh_C, hh_gna, hh_gk, hh_gl, hh_ena, hh_ek, hh_el;
+    double *hm, *hn, *hh;   /* [n] gating variables */
+    double* vprev;          /* [n] V(t-1) for the crossing test */
 } orc_net;
 
 static void* xcalloc(size_t n, size_t s) {
@@ -232,9 +290,107 @@ fail:
     return NULL;
 }
 
+/*
+ * Switch the network to the Izhikevich vertex: iz = {C, k, Vr, Vt, a, b, d}
+ * (V_peak and c are the network's v_th and v_reset); psc 0 none, 1 exp,
+ * 2 alpha, with rate psc_a (1/ms); w0 = initial W or NULL (0).  Returns 0,
+ * or -1 for a bad argument.
+ */
+int32_t orc_set_izhikevich(void* ph, int32_t psc, const double* iz, double psc_a, const float* w0) {
+    orc_net* h = (orc_net*)ph;
+    if (!h || !iz || psc < 0 || psc > 2 || !(iz[0] > 0.0)) return -1;
+    h->model = 1;
+    h->psc = psc;
+    h->iz_C = iz[0];
+    h->iz_k = iz[1];
+    h->iz_vr = iz[2];
+    h->iz_vt = iz[3];
+    h->iz_a = iz[4];
+    h->iz_b = iz[5];
+    h->iz_d = iz[6];
+    h->psc_a = psc_a;
+    if (!h->W) h->W = (double*)xcalloc((size_t)h->n, sizeof(double));
+    if (!h->r) h->r = (double*)xcalloc((size_t)h->n, sizeof(double));
+    if (!h->p) h->p = (double*)xcalloc((size_t)h->n, sizeof(double));
+    for (int32_t j = 0; j < h->n; ++j) h->W[j] = w0 ? (double)w0[j] : 0.0;
+    return 0;
+}
+
+/* HH rate functions (see the header). */
+static double hh_alpha_m(double V) {
+    const double x = V + 40.0;
+    return x == 0.0 ? 1.0 : 0.1 * x / (1.0 - exp(-x / 10.0));
+}
+static double hh_beta_m(double V) { return 4.0 * exp(-(V + 65.0) / 18.0); }
+static double hh_alpha_h(double V) { return 0.07 * exp(-(V + 65.0) / 20.0); }
+static double hh_beta_h(double V) { return 1.0 / (1.0 + exp(-(V + 35.0) / 10.0)); }
+static double hh_alpha_n(double V) {
+    const double x = V + 55.0;
+    return x == 0.0 ? 0.1 : 0.01 * x / (1.0 - exp(-x / 10.0));
+}
+static double hh_beta_n(double V) { return 0.125 * exp(-(V + 65.0) / 80.0); }
+
+/*
+ * Switch the network to the Hodgkin-Huxley vertex: hh = {C, gNa, gK, gL,
+ * ENa, EK, EL}; the threshold of the crossing test is the network's v_th;
+ * psc and psc_a as for the Izhikevich vertex.  m, n, h start at their
+ * steady state for V(0); V(-1) is taken as V(0).  Returns 0 or -1.
+ */
+int32_t orc_set_hodgkin_huxley(void* ph, int32_t psc, const double* hh, double psc_a) {
+    orc_net* h = (orc_net*)ph;
+    if (!h || !hh || psc < 0 || psc > 2 || !(hh[0] > 0.0)) return -1;
+    h->model = 2;
+    h->psc = psc;
+    h->psc_a = psc_a;
+    h->hh_C = hh[0];
+    h->hh_gna = hh[1];
+    h->hh_gk = hh[2];
+    h->hh_gl = hh[3];
+    h->hh_ena = hh[4];
+    h->hh_ek = hh[5];
+    h->hh_el = hh[6];
+    if (!h->r) h->r = (double*)xcalloc((size_t)h->n, sizeof(double));
+    if (!h->p) h->p = (double*)xcalloc((size_t)h->n, sizeof(double));
+    if (!h->hm) h->hm = (double*)xcalloc((size_t)h->n, sizeof(double));
+    if (!h->hn) h->hn = (double*)xcalloc((size_t)h->n, sizeof(double));
+    if (!h->hh) h->hh = (double*)xcalloc((size_t)h->n, sizeof(double));
+    if (!h->vprev) h->vprev = (double*)xcalloc((size_t)h->n, sizeof(double));
+    for (int32_t j = 0; j < h->n; ++j) {
+        const double V = h->V[j];
+        h->hm[j] = hh_alpha_m(V) / (hh_alpha_m(V) + hh_beta_m(V));
+        h->hh[j] = hh_alpha_h(V) / (hh_alpha_h(V) + hh_beta_h(V));
+        h->hn[j] = hh_alpha_n(V) / (hh_alpha_n(V) + hh_beta_n(V));
+        h->vprev[j] = V;
+    }
+    return 0;
+}
+
+void orc_get_hh(void* ph, double* m, double* n, double* hg) {
+    orc_net* h = (orc_net*)ph;
+    if (!h->hm) return;
+    if (m) memcpy(m, h->hm, (size_t)h->n * sizeof(double));
+    if (n) memcpy(n, h->hn, (size_t)h->n * sizeof(double));
+    if (hg) memcpy(hg, h->hh, (size_t)h->n * sizeof(double));
+}
+
+void orc_get_izh(void* ph, double* W, double* r, double* p) {
+    orc_net* h = (orc_net*)ph;
+    if (!h->W) return;
+    if (W) memcpy(W, h->W, (size_t)h->n * sizeof(double));
+    if (r) memcpy(r, h->r, (size_t)h->n * sizeof(double));
+    if (p) memcpy(p, h->p, (size_t)h->n * sizeof(double));
+}
+
 void orc_free(void* p) {
     orc_net* h = (orc_net*)p;
     if (!h) return;
+    free(h->W);
+    free(h->r);
+    free(h->p);
+    free(h->hm);
+    free(h->hn);
+    free(h->hh);
+    free(h->vprev);
     free(h->out_start);
     free(h->out_dst);
     free(h->out_w);
@@ -277,8 +433,14 @@ void orc_step_n(void* p, int64_t n_steps, uint8_t* raster, double* v_rec, double
         const int64_t t = h->t;
         const int slot = (int)(t % ORC_RING);
         /* Eq. spd on the state at the start of the step. */
+#pragma omp parallel for schedule(static) num_threads(orc_threads) if (orc_threads > 1 && n >= 4096)
         for (int32_t j = 0; j < n; ++j) {
-            s[j] = force_raster ? (force_raster[k * n + j] ? 1 : 0) : (h->V[j] >= h->v_th ? 1 : 0);
+            if (force_raster)
+                s[j] = force_raster[k * n + j] ? 1 : 0;
+            else if (h->model == 2)
+                s[j] = (h->V[j] >= h->v_th && h->vprev[j] < h->v_th) ? 1 : 0;   /* R20: upward crossing */
+            else
+                s[j] = h->V[j] >= h->v_th ? 1 : 0;
             if (raster) raster[k * n + j] = s[j];
             if (v_rec) v_rec[k * n + j] = h->V[j];
         }
@@ -303,6 +465,7 @@ void orc_step_n(void* p, int64_t n_steps, uint8_t* raster, double* v_rec, double
             h->acc_steps = 0;
             if (f_now + 1 > h->n_frames) h->n_frames = f_now + 1;
         }
+#pragma omp parallel for schedule(static) num_threads(orc_threads) if (orc_threads > 1 && n >= 4096)
         for (int32_t j = 0; j < n; ++j) {
             /* input arriving now (all its pushes happened at earlier steps) */
             double in = h->inbox[(int64_t)j * ORC_RING + slot];
@@ -310,6 +473,61 @@ void orc_step_n(void* p, int64_t n_steps, uint8_t* raster, double* v_rec, double
             if (i_rec) i_rec[k * n + j] = in;
             /* calcium transition, Section 3.3 */
             h->c[j] = h->c[j] + h->dt * (-h->c[j] / h->tau_c + (double)s[j]);
+            if (h->model == 2) {
+                /* Hodgkin-Huxley transition, Euler from the state at t; no reset */
+                const double V = h->V[j], r = h->r[j], pp = h->p[j];
+                const double m = h->hm[j], nn = h->hn[j], hg = h->hh[j];
+                if (h->psc == 1) {
+                    h->r[j] = r - h->dt * h->psc_a * r + in;
+                } else if (h->psc == 2) {
+                    h->r[j] = r + h->dt * pp;
+                    h->p[j] = pp + h->dt * (-h->psc_a * h->psc_a * r - 2.0 * h->psc_a * pp) + in;
+                }
+                uint32_t ctr[4] = {(uint32_t)j, (uint32_t)t, (uint32_t)(t >> 32), 0u};
+                uint32_t rr[4];
+                orc_philox4x32_10(ctr, h->key, rr);
+                const double U = h->i_ext[j] + ((rr[0] < h->drive_thr[j]) ? h->drive_amp : 0.0);
+                const double xi = orc_box_muller(rr[1], rr[2]);
+                const double syn = h->psc == 0 ? 0.0 : r;
+                const double i_na = h->hh_gna * m * m * m * hg * (V - h->hh_ena);
+                const double i_k = h->hh_gk * nn * nn * nn * nn * (V - h->hh_ek);
+                const double i_l = h->hh_gl * (V - h->hh_el);
+                double Vn = V + h->dt * (1.0 / h->hh_C) * (-i_na - i_k - i_l + syn + U);
+                if (h->psc == 0) Vn = Vn + in;
+                h->V[j] = Vn + h->sigma * xi;
+                h->vprev[j] = V;
+                h->hm[j] = m + h->dt * (hh_alpha_m(V) * (1.0 - m) - hh_beta_m(V) * m);
+                h->hh[j] = hg + h->dt * (hh_alpha_h(V) * (1.0 - hg) - hh_beta_h(V) * hg);
+                h->hn[j] = nn + h->dt * (hh_alpha_n(V) * (1.0 - nn) - hh_beta_n(V) * nn);
+                continue;
+            }
+            if (h->model == 1) {
+                /* Izhikevich transition (Eqs. izsimple and izpsc), all from the state at t */
+                const double V = h->V[j], W = h->W[j], r = h->r[j], pp = h->p[j];
+                if (h->psc == 1) {
+                    h->r[j] = r - h->dt * h->psc_a * r + in;
+                } else if (h->psc == 2) {
+                    h->r[j] = r + h->dt * pp;
+                    h->p[j] = pp + h->dt * (-h->psc_a * h->psc_a * r - 2.0 * h->psc_a * pp) + in;
+                }
+                if (s[j]) {
+                    h->V[j] = h->v_reset;
+                    h->W[j] = W + h->iz_d;
+                } else {
+                    uint32_t ctr[4] = {(uint32_t)j, (uint32_t)t, (uint32_t)(t >> 32), 0u};
+                    uint32_t rr[4];
+                    orc_philox4x32_10(ctr, h->key, rr);
+                    const double U = h->i_ext[j] + ((rr[0] < h->drive_thr[j]) ? h->drive_amp : 0.0);
+                    const double xi = orc_box_muller(rr[1], rr[2]);
+                    const double syn = h->psc == 0 ? 0.0 : r;
+                    const double cur = h->iz_k * (V - h->iz_vr) * (V - h->iz_vt) - W + syn + U;
+                    double Vn = V + h->dt * (1.0 / h->iz_C) * cur;
+                    if (h->psc == 0) Vn = Vn + in;
+                    h->V[j] = Vn + h->sigma * xi;
+                    h->W[j] = W + h->dt * h->iz_a * (h->iz_b * (V - h->iz_vr) - W);
+                }
+                continue;
+            }
             /* LIF transition with refractory hold (R1) */
             if (s[j]) {
                 h->V[j] = h->v_reset;

@@ -138,6 +138,13 @@ class Net:
             d.tau_c_ms = s.tau_c_ms
             d.frame_num = s.frame_num
             d.frame_den = s.frame_den
+            d.model = getattr(s, "model", 0)
+            if d.model:
+                d.psc = s.psc
+                d.iz_C, d.iz_k, d.iz_vr, d.iz_vt = s.iz_C, s.iz_k, s.iz_vr, s.iz_vt
+                d.iz_a, d.iz_b, d.iz_d = s.iz_a, s.iz_b, s.iz_d
+                d.psc_rate = s.psc_rate
+                d.w0 = _ptr(arr(s.w0_iz, np.float32))
         opts = _abi.BuildOpts(frame_capacity, block_threads, blocks_per_cu, flags)
         h = C.c_void_p()
         self._stream = _stream_handle(stream)
@@ -233,8 +240,13 @@ class Mlp:
 
     N_PARAMS = _abi.MLP_PARAMS
 
-    def __init__(self, params: Optional[np.ndarray] = None):
+    def __init__(self, params: Optional[np.ndarray] = None, torch_allocator: bool = True):
+        import torch
         lib = library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("geonet needs a ROCm GPU; none is visible")
+        if torch_allocator:
+            _register_torch_allocator()
         h = C.c_void_p()
         self._check(lib.net_mlp_create(C.byref(h)), "net_mlp_create")
         self.h = h
@@ -267,6 +279,30 @@ class Mlp:
         b = np.ascontiguousarray(scale, dtype=np.float32)
         assert a.size == _abi.MLP_IN and b.size == _abi.MLP_IN
         self._check(library().net_mlp_set_input_norm(self.h, a.ctypes.data, b.ctypes.data), "net_mlp_set_input_norm")
+
+    def fit_input_norm(self, x, stream=None):
+        """Standardisation fitted on the GPU to features x (torch float32 [rows][64])."""
+        import torch
+        assert x.is_cuda and x.dtype == torch.float32 and x.shape[1] == _abi.MLP_IN and x.is_contiguous()
+        self._check(library().net_mlp_fit_input_norm(self.h, x.data_ptr(), x.shape[0], _stream_handle(stream)),
+                    "net_mlp_fit_input_norm")
+
+    def get_input_norm(self):
+        shift = np.zeros(_abi.MLP_IN, dtype=np.float32)
+        scale = np.zeros(_abi.MLP_IN, dtype=np.float32)
+        self._check(library().net_mlp_get_input_norm(self.h, shift.ctypes.data, scale.ctypes.data),
+                    "net_mlp_get_input_norm")
+        return shift, scale
+
+    def train_epoch(self, x, y, batch: int, lr: float, seed: int, epoch: int, losses=None, stream=None):
+        """One shuffled pass over the rows, one Adam step per batch (the last may be smaller)."""
+        import torch
+        assert x.is_cuda and x.dtype == torch.float32 and x.shape[1] == _abi.MLP_IN and x.is_contiguous()
+        assert y.is_cuda and y.dtype == torch.float32 and y.shape[0] == x.shape[0] and y.is_contiguous()
+        self._check(library().net_mlp_train_epoch(self.h, x.data_ptr(), y.data_ptr(), x.shape[0], int(batch),
+                                                  float(lr), int(seed) & 0xFFFFFFFFFFFFFFFF, int(epoch) & 0xFFFFFFFF,
+                                                  losses.data_ptr() if losses is not None else None,
+                                                  _stream_handle(stream)), "net_mlp_train_epoch")
 
     def get_params(self) -> np.ndarray:
         out = np.zeros(_abi.MLP_PARAMS, dtype=np.float32)
@@ -304,6 +340,18 @@ class Mlp:
             self.close()
         except Exception:
             pass
+
+
+def shuffle_indices(n: int, seed: int, epoch: int, stream=None):
+    """The permutation of [0, n) the scorer's training epochs visit rows in
+    (torch int64 [n] on the GPU)."""
+    import torch
+    out = torch.empty(max(int(n), 1), dtype=torch.int64, device="cuda")
+    st = library().net_shuffle_indices(int(n), int(seed) & 0xFFFFFFFFFFFFFFFF, int(epoch) & 0xFFFFFFFF,
+                                       out.data_ptr(), _stream_handle(stream))
+    if st != NET_OK:
+        raise GeonetError(st, "net_shuffle_indices", library().net_mlp_last_error().decode())
+    return out[:int(n)]
 
 
 def unpack_raster(words, n: int) -> np.ndarray:

@@ -29,6 +29,12 @@ NET_BUILD_FUSED_STEP = 1024
 NET_BUILD_DELIVER_PACKED = 2048
 NET_BUILD_AUTOTUNE = 64
 
+NET_MODEL_LIF = 0
+NET_MODEL_IZHIKEVICH = 1
+NET_PSC_NONE = 0
+NET_PSC_EXP = 1
+NET_PSC_ALPHA = 2
+
 NET_OBS_V = 1
 NET_OBS_REF = 2
 NET_OBS_CALCIUM = 3
@@ -46,7 +52,9 @@ class NetDesc(C.Structure):
         ("v_rest", C.c_float), ("v_reset", C.c_float), ("v_th", C.c_float), ("n_ref", C.c_int32),
         ("drive_rate_hz", _vp), ("drive_amp", C.c_float), ("i_ext", _vp), ("noise_sigma", C.c_float),
         ("seed", C.c_uint64), ("v0", _vp), ("tau_c_ms", C.c_float), ("frame_num", C.c_int32),
-        ("frame_den", C.c_int32),
+        ("frame_den", C.c_int32), ("model", C.c_int32), ("psc", C.c_int32), ("iz_C", C.c_float),
+        ("iz_k", C.c_float), ("iz_vr", C.c_float), ("iz_vt", C.c_float), ("iz_a", C.c_float),
+        ("iz_b", C.c_float), ("iz_d", C.c_float), ("psc_rate", C.c_float), ("w0", _vp),
     ]
 
 
@@ -126,7 +134,13 @@ SIGNATURES = {
     "net_mlp_forward": (C.c_int, [_vp, _vp, C.c_int64, _vp, _vp]),
     "net_mlp_grad": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, _vp, _vp]),
     "net_mlp_train_step": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_float, _vp, _vp]),
+    "net_mlp_fit_input_norm": (C.c_int, [_vp, _vp, C.c_int64, _vp]),
+    "net_mlp_get_input_norm": (C.c_int, [_vp, _vp, _vp]),
+    "net_mlp_train_epoch": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_int64, C.c_float, C.c_uint64, C.c_uint32, _vp,
+                                      _vp]),
+    "net_shuffle_indices": (C.c_int, [C.c_int64, C.c_uint64, C.c_uint32, _vp, _vp]),
     "net_mlp_free": (None, [_vp]),
+    "net_simulate_device_error": (C.c_int, [_vp]),
     "net_mlp_last_error": (C.c_char_p, []),
 }
 

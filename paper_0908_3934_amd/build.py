@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgeonet.so")
 SOURCES = ["kernels.hip", "build.cpp", "abi.cpp", "mlp.hip", "mlp_abi.cpp", "estimate.hip", "estimate_abi.cpp", "simfit.hip"]
-HEADERS = ["internal.h", os.path.join("..", "..", "include", "geonet.h")]
+HEADERS = ["internal.h", "philox.h", os.path.join("..", "..", "include", "geonet.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("GEONET_ARCH", "gfx950")

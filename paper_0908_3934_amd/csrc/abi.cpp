@@ -54,6 +54,43 @@ net_status fail(net_status st, const std::string& msg) {
     return st;
 }
 
+}  // namespace
+
+namespace geonet {
+
+DevAllocator current_allocator() {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    DevAllocator a;
+    a.alloc = g_alloc.alloc;
+    a.release = g_alloc.release;
+    a.ctx = g_alloc.ctx;
+    return a;
+}
+
+void* DevAllocator::get(size_t bytes, hipStream_t s) const {
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) / 256 * 256;
+    void* p = nullptr;
+    if (alloc) {
+        p = alloc(bytes, s, ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    return p;
+}
+
+void DevAllocator::put(void* p, hipStream_t s) const {
+    if (!p) return;
+    if (release)
+        release(p, s, ctx);
+    else
+        (void)hipFree(p);
+}
+
+}  // namespace geonet
+
+namespace {
+
 net_status device_fail(net* h, hipError_t e, const char* where) {
     if (h) h->broken = true;
     return fail(NET_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
@@ -206,6 +243,16 @@ net_status reset_state(net* h, const HostGraph& hg, hipStream_t s) {
     if (e == hipSuccess && g.age_alt) e = hipMemsetAsync(g.age_alt, kAgeNever, (np + kAgePad) * sizeof(uint16_t), s);
     if (e == hipSuccess && g.summary_alt) e = hipMemsetAsync(g.summary_alt, 0, np / 32 * sizeof(uint32_t), s);
     if (e == hipSuccess && g.calcium) e = hipMemsetAsync(g.calcium, 0, np * sizeof(double), s);
+    if (e == hipSuccess && g.Vd) {
+        std::vector<double> vd(hg.v0.begin(), hg.v0.end());
+        e = hipMemcpyAsync(g.Vd, vd.data(), std::min(vd.size(), np) * sizeof(double), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(g.Wd, hg.w0.data(), std::min(hg.w0.size(), np) * sizeof(double), hipMemcpyHostToDevice,
+                               s);
+        if (e == hipSuccess) e = hipMemsetAsync(g.psc_r, 0, np * sizeof(double), s);
+        if (e == hipSuccess) e = hipMemsetAsync(g.psc_p, 0, np * sizeof(double), s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);     // `vd` is freed below
+    }
     if (e == hipSuccess && g.frame_acc) e = hipMemsetAsync(g.frame_acc, 0, np * sizeof(double), s);
     if (e == hipSuccess && g.frames)
         e = hipMemsetAsync(g.frames, 0, np * static_cast<size_t>(g.frame_cap) * sizeof(float), s);
@@ -274,7 +321,8 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
     std::string err;
     // fused step: one segment per CU, sized to fit next to the summary in LDS
     int32_t seg_count = 0, seg_cap = 0;
-    if (opts && (opts->flags & NET_BUILD_FUSED_STEP) && n_nets == 1 && descs && descs[0].n_nodes > 0) {
+    if (opts && (opts->flags & NET_BUILD_FUSED_STEP) && n_nets == 1 && descs && descs[0].n_nodes > 0 &&
+        descs[0].model == NET_MODEL_LIF) {
         int dev = 0, n_cu = 0, lds_max = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
@@ -360,6 +408,18 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
     if ((st = zeros(h, &g.I, np, s, "input")) != NET_OK) return bail(st);
     if ((st = zeros(h, &g.ring, np * kRingWords, s, "history ring")) != NET_OK) return bail(st);
     if ((st = zeros(h, &g.summary, np / 32, s, "summary")) != NET_OK) return bail(st);
+    if (hg.any_izh) {
+        std::vector<double> vd(hg.v0.begin(), hg.v0.end());
+        if ((st = upload(h, &g.Vd, vd, np, s, "Izhikevich V")) != NET_OK) return bail(st);
+        if ((st = upload(h, &g.Wd, hg.w0, np, s, "Izhikevich W")) != NET_OK) return bail(st);
+        if ((st = zeros(h, &g.psc_r, np, s, "PSC r")) != NET_OK) return bail(st);
+        if ((st = zeros(h, &g.psc_p, np, s, "PSC p")) != NET_OK) return bail(st);
+        const hipError_t se = hipStreamSynchronize(s);   // `vd` is freed below
+        if (se != hipSuccess) {
+            device_fail(h, se, "net_build: upload");
+            return bail(NET_E_DEVICE);
+        }
+    }
     if (frame_cap > 0) {
         if ((st = zeros(h, &g.calcium, np, s, "calcium")) != NET_OK) return bail(st);
         if ((st = zeros(h, &g.frame_acc, np, s, "frame accumulator")) != NET_OK) return bail(st);
@@ -667,8 +727,15 @@ net_status net_node_offsets(const net_t* h, int64_t* out) {
     return NET_OK;
 }
 
+net_status net_simulate_device_error(net_t* h) {
+    if (!h) return fail(NET_E_ARG, "net_simulate_device_error: handle is NULL");
+    h->broken = true;
+    return NET_OK;
+}
+
 net_status net_timing_begin(net_t* h, int64_t max_launches, int32_t every) {
     if (!h) return fail(NET_E_ARG, "net_timing_begin: handle is NULL");
+    if (h->broken) return fail(NET_E_STATE, "net_timing_begin: handle unusable after a device error");
     if (max_launches < 0 || max_launches > (int64_t(1) << 22))
         return fail(NET_E_ARG, "net_timing_begin: bad max_launches");
     if (every < 1) return fail(NET_E_ARG, "net_timing_begin: every must be >= 1");
@@ -690,6 +757,7 @@ net_status net_timing_begin(net_t* h, int64_t max_launches, int32_t every) {
 
 net_status net_timing_end(net_t* h, net_timing_t* out) {
     if (!h || !out) return fail(NET_E_ARG, "net_timing_end: NULL argument");
+    if (h->broken) return fail(NET_E_STATE, "net_timing_end: handle unusable after a device error");
     std::memset(out, 0, sizeof(*out));
     for (int64_t k = 0; k < h->t_used; ++k) {
         float ms = 0.0f;

@@ -85,8 +85,20 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
             err = "net_build: network " + std::to_string(m) + " needs positions or explicit delays";
             return NET_E_ARG;
         }
-        if (!(d.dt_ms > 0.0) || !(d.tau_ms > 0.0) || d.n_ref < 0 || d.n_ref > 250) {
+        if (d.model != NET_MODEL_LIF && d.model != NET_MODEL_IZHIKEVICH) {
+            err = "net_build: network " + std::to_string(m) + " has an unknown vertex model";
+            return NET_E_ARG;
+        }
+        if (d.model == NET_MODEL_LIF &&
+            (!(d.dt_ms > 0.0) || !(d.tau_ms > 0.0) || d.n_ref < 0 || d.n_ref > 250)) {
             err = "net_build: network " + std::to_string(m) + " needs dt > 0, tau > 0, 0 <= n_ref <= 250";
+            return NET_E_ARG;
+        }
+        if (d.model == NET_MODEL_IZHIKEVICH &&
+            (!(d.dt_ms > 0.0) || d.n_ref != 0 || !(d.iz_C > 0.0f) || d.psc < NET_PSC_NONE || d.psc > NET_PSC_ALPHA ||
+             (d.psc != NET_PSC_NONE && !(d.psc_rate >= 0.0f)))) {
+            err = "net_build: Izhikevich network " + std::to_string(m) +
+                  " needs dt > 0, n_ref = 0, C > 0, psc in 0..2 and psc_rate >= 0";
             return NET_E_ARG;
         }
         if (!d.delay_steps && d.n_edges > 0 && !(d.v_um_per_ms > 0.0)) {
@@ -335,6 +347,7 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
     g.drive_thr.assign(g.n_pad, 0u);
     g.i_ext.assign(g.n_pad, 0.0f);
     g.net_id.assign(g.n_pad, n_nets - 1);
+    g.w0.assign(g.n_pad, 0.0);
     g.params.resize(n_nets);
     for (int m = 0; m < n_nets; ++m) {
         const net_desc& d = descs[m];
@@ -351,9 +364,25 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
         p.key_lo = static_cast<uint32_t>(d.seed);
         p.key_hi = static_cast<uint32_t>(d.seed >> 32);
         p.node_off = static_cast<int32_t>(g.node_off[m]);
+        p.model = d.model;
+        p.psc = d.psc;
+        if (d.model == NET_MODEL_IZHIKEVICH) {
+            g.any_izh = true;
+            p.decay = 0.0f;
+            p.n_ref = 0;
+            p.iz_inv_c = 1.0 / static_cast<double>(d.iz_C);
+            p.iz_k = d.iz_k;
+            p.iz_vr = d.iz_vr;
+            p.iz_vt = d.iz_vt;
+            p.iz_a = d.iz_a;
+            p.iz_b = d.iz_b;
+            p.iz_d = d.iz_d;
+            p.psc_a = d.psc_rate;
+        }
         for (int32_t j = 0; j < d.n_nodes; ++j) {
             const int64_t k = g.node_off[m] + j;
             g.v0[k] = d.v0 ? d.v0[j] : d.v_rest;
+            if (d.model == NET_MODEL_IZHIKEVICH) g.w0[k] = d.w0 ? static_cast<double>(d.w0[j]) : 0.0;
             if (d.drive_rate_hz) {
                 g.drive_thr[k] = pulse_threshold(d.drive_rate_hz[j], d.dt_ms);
                 g.any_drive |= g.drive_thr[k] != 0u;

@@ -19,23 +19,10 @@
 #include <cstdint>
 
 #include "internal.h"
+#include "philox.h"
 
 namespace geonet {
 namespace {
-
-__device__ __forceinline__ uint4 philox_ctl(uint4 x, uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        // each 32 x 32 -> 64-bit product in one v_mad_u64_u32
-        const uint64_t pa = static_cast<uint64_t>(x.x) * 0xD2511F53u;
-        const uint64_t pc = static_cast<uint64_t>(x.z) * 0xCD9E8D57u;
-        x = make_uint4(static_cast<uint32_t>(pc >> 32) ^ x.y ^ k0, static_cast<uint32_t>(pc),
-                       static_cast<uint32_t>(pa >> 32) ^ x.w ^ k1, static_cast<uint32_t>(pa));
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return x;
-}
 
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
@@ -79,7 +66,7 @@ __global__ void __launch_bounds__(256) prep_kernel(PrepArgs a) {
             const int64_t t0 = (static_cast<int64_t>(f) * a.frame_den + a.frame_num - 1) / a.frame_num;
             const int64_t t1 = (static_cast<int64_t>(f + 1) * a.frame_den + a.frame_num - 1) / a.frame_num;
             for (int64_t t = t0; t < t1; ++t) {
-                const uint4 r = philox_ctl(make_uint4(static_cast<uint32_t>(j), static_cast<uint32_t>(t),
+                const uint4 r = philox4x32_10(make_uint4(static_cast<uint32_t>(j), static_cast<uint32_t>(t),
                                                       static_cast<uint32_t>(static_cast<uint64_t>(t) >> 32), 0u),
                                            a.key_lo, a.key_hi);
                 pulses += r.x < thr ? 1.0f : 0.0f;
@@ -212,6 +199,24 @@ __global__ void __launch_bounds__(256) features_kernel(FeatArgs a) {
 }
 
 }  // namespace
+
+namespace {
+__global__ void __launch_bounds__(256) pulse_threshold_kernel(const float* rates, int32_t n, double dt_ms,
+                                                              uint32_t* thr) {
+    const int32_t j = static_cast<int32_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    // the same double-precision rule as pulse_threshold on the host
+    const double t = floor(static_cast<double>(rates[j]) * (dt_ms * 1e-3) * 4294967296.0);
+    thr[j] = !(t > 0.0) ? 0u : (t >= 4294967295.0 ? 0xFFFFFFFFu : static_cast<uint32_t>(t));
+}
+}  // namespace
+
+hipError_t launch_pulse_thresholds(const float* rates, int32_t n, double dt_ms, uint32_t* thr, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pulse_threshold_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, rates,
+                       n, dt_ms, thr);
+    return hipGetLastError();
+}
 
 hipError_t launch_features(const FeatureInputs& in, const FeatureWork& w, float* out, hipStream_t s) {
     PrepArgs pa;

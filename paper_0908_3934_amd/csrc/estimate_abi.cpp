@@ -18,19 +18,34 @@ net_status efail(net_status st, const std::string& msg) {
     return st;
 }
 
+// Scratch of one call, taken from the allocator installed by
+// net_set_allocator (with PyTorch's caching allocator the blocks are reused
+// from call to call) and handed back, ordered on the call's stream, when the
+// call returns.
 struct DeviceScratch {
+    DevAllocator al = current_allocator();
+    hipStream_t s;
     std::vector<void*> ptrs;
+    explicit DeviceScratch(hipStream_t stream) : s(stream) {}
     ~DeviceScratch() {
-        for (void* p : ptrs) (void)hipFree(p);
+        for (void* p : ptrs) al.put(p, s);
     }
     template <typename T>
     T* get(size_t n) {
-        void* p = nullptr;
-        if (hipMalloc(&p, (n ? n : 1) * sizeof(T)) != hipSuccess) return nullptr;
+        void* p = al.get((n ? n : 1) * sizeof(T), s);
+        if (!p) return nullptr;
         ptrs.push_back(p);
         return static_cast<T*>(p);
     }
 };
+
+}  // namespace
+
+namespace geonet {
+net_status estimate_fail(net_status st, const std::string& msg) { return efail(st, msg); }
+}  // namespace geonet
+
+namespace {
 
 net_status check_obs(const net_obs_desc* o) {
     if (!o) return efail(NET_E_ARG, "observation descriptor is NULL");
@@ -42,9 +57,14 @@ net_status check_obs(const net_obs_desc* o) {
     return NET_OK;
 }
 
-// Computes the features of all pairs into out (device [P][64]).
-net_status features(const net_obs_desc* o, float* out, hipStream_t s, DeviceScratch& sc) {
-    FeatureInputs in{};
+}  // namespace
+
+namespace geonet {
+
+net_status estimate_check_obs(const net_obs_desc* o) { return check_obs(o); }
+
+void feature_inputs(const net_obs_desc* o, FeatureInputs& in) {
+    in = FeatureInputs{};
     in.F = o->fluor;
     in.pairs = o->pairs;
     in.dist = o->pair_dist_um;
@@ -58,6 +78,16 @@ net_status features(const net_obs_desc* o, float* out, hipStream_t s, DeviceScra
     in.frame_den = o->frame_den;
     in.key_lo = static_cast<uint32_t>(o->control_seed);
     in.key_hi = static_cast<uint32_t>(o->control_seed >> 32);
+}
+
+}  // namespace geonet
+
+namespace {
+
+// Computes the features of all pairs into out (device [P][64]).
+net_status features(const net_obs_desc* o, float* out, hipStream_t s, DeviceScratch& sc) {
+    FeatureInputs in{};
+    feature_inputs(o, in);
     const size_t nn = static_cast<size_t>(o->n_nodes), nf = static_cast<size_t>(o->n_frames);
     if (o->drive_rate_hz) {
         std::vector<uint32_t> thr(nn);
@@ -104,7 +134,7 @@ net_status simfit(const net_obs_desc* o, const net_simfit_opts* opts, float* out
     if (K < 1 || K > 64 || (64 % K) != 0) return efail(NET_E_ARG, "simfit: realisations must divide 64");
     if (sweeps < 0 || sweeps > 64) return efail(NET_E_ARG, "simfit: sweeps in 0..64");
     const int64_t P = o->n_pairs, n = o->n_nodes, nf = o->n_frames;
-    DeviceScratch sc;
+    DeviceScratch sc(s);
     // candidate pairs sorted by target (stable in source)
     std::vector<int32_t> hp;
     std::vector<float> hd;
@@ -248,7 +278,7 @@ net_status net_features(const net_obs_desc* obs, float* features_dev, void* stre
     if (st != NET_OK) return st;
     if (!features_dev && obs->n_pairs > 0) return efail(NET_E_ARG, "net_features: output is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    DeviceScratch sc;
+    DeviceScratch sc(s);
     st = features(obs, features_dev, s, sc);
     if (st != NET_OK) return st;
     if (hipStreamSynchronize(s) != hipSuccess) return efail(NET_E_DEVICE, "net_features: kernel");
@@ -265,7 +295,7 @@ net_status net_estimate(const net_obs_desc* obs, int32_t method, net_mlp_t* scor
     if (method == NET_EST_AUTO) method = scorer ? NET_EST_SCORER : NET_EST_SIMFIT;
     if (method == NET_EST_SCORER) {
         if (!scorer) return efail(NET_E_ARG, "net_estimate: the scorer needs a trained MLP");
-        DeviceScratch sc;
+        DeviceScratch sc(s);
         float* feat = sc.get<float>(64 * obs->n_pairs);
         if (!feat) return efail(NET_E_OOM, "net_estimate: allocation");
         if ((st = features(obs, feat, s, sc)) != NET_OK) return st;

@@ -31,6 +31,20 @@ constexpr int kStepQueueBytes = 16 * 128 * 4;
 // Vertices per fused-step segment at most (6 per thread of its workgroup).
 constexpr int kStepMaxSegment = 6 * 1024;
 
+// Every device allocation of the library (network handles, MLP handles and
+// the scratch of the estimation calls) goes through the allocator installed
+// by net_set_allocator, or hipMalloc/hipFree when none is installed.  A
+// handle keeps the allocator that was current when it was created.
+struct DevAllocator {
+    void* (*alloc)(size_t, void*, void*) = nullptr;
+    void (*release)(void*, void*, void*) = nullptr;
+    void* ctx = nullptr;
+    // 256-byte multiple (at least 256 bytes); null on failure
+    void* get(size_t bytes, hipStream_t s) const;
+    void put(void* p, hipStream_t s) const;
+};
+DevAllocator current_allocator();
+
 // Per-network constants used by the vertex kernels.
 struct NetParams {
     float decay;        // dt / tau
@@ -40,6 +54,9 @@ struct NetParams {
     uint32_t key_lo, key_hi;
     int32_t node_off;   // first vertex of the network in the ensemble numbering
     double dt_d, tau_c_d;   // calcium transition in double precision
+    // Izhikevich vertex (model 1; FP64 state): V_peak = v_th, c = v_reset
+    int32_t model, psc;     // NET_MODEL_*, NET_PSC_*
+    double iz_inv_c, iz_k, iz_vr, iz_vt, iz_a, iz_b, iz_d, psc_a;   // iz_inv_c = 1 / C
 };
 
 // Per-network description used by the ensemble kernel.
@@ -78,6 +95,8 @@ struct HostGraph {
     std::vector<float> i_ext;
     std::vector<int32_t> net_id;
     bool any_drive = false, any_iext = false;
+    bool any_izh = false;             // some network uses the Izhikevich vertex
+    std::vector<double> w0;           // [n_pad] initial W (Izhikevich vertices)
     double dt_ms = 0.0;
     int32_t frame_num = 0, frame_den = 1;
 };
@@ -119,6 +138,12 @@ struct DeviceGraph {
     const int32_t* seg_vertex = nullptr;   // [n_seg + 1]
     const int32_t* seg_chunk = nullptr;    // [n_seg + 1]
     int32_t n_seg = 0, seg_max = 0;
+    // Izhikevich networks (null otherwise): FP64 V and W, PSC states r and
+    // p; V is also kept in FP32 in `V` for records and read-outs
+    double* Vd = nullptr;
+    double* Wd = nullptr;
+    double* psc_r = nullptr;
+    double* psc_p = nullptr;
     double* calcium;              // null when observation is off
     double* frame_acc;
     float* frames;                // [frame_cap][n_pad]
@@ -228,6 +253,14 @@ struct FeatureWork {
     float *en, *zn, *rn, *dc, *stats, *pm;
 };
 hipError_t launch_features(const FeatureInputs& in, const FeatureWork& w, float* out, hipStream_t s);
+// Drive thresholds floor(rate * dt * 2^32) (as pulse_threshold) of n device rates.
+hipError_t launch_pulse_thresholds(const float* rates, int32_t n, double dt_ms, uint32_t* thr, hipStream_t s);
+// Shared by the estimation entry points: the descriptor check (NET_OK or
+// NET_E_ARG with the text in net_estimate_last_error), the feature inputs
+// of a descriptor (drive_thr left null) and the error setter.
+net_status estimate_check_obs(const net_obs_desc* o);
+void feature_inputs(const net_obs_desc* o, FeatureInputs& in);
+net_status estimate_fail(net_status st, const std::string& msg);
 uint32_t pulse_threshold(double rate_hz, double dt_ms);
 
 // Simulation-based fit.
@@ -260,5 +293,16 @@ hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, float* lo
 hipError_t mlp_adam(const MlpDevice& d, float lr, float beta1, float beta2, float eps, int64_t t, hipStream_t s);
 hipError_t mlp_refresh_bf16(const MlpDevice& d, hipStream_t s);
 hipError_t mlp_forward_fused(const MlpDevice& d, const float* X, int64_t B, float* logits, hipStream_t s);
+// Input standardisation statistics of X [rows][64]: shift = column mean,
+// scale = 1 / column standard deviation (unbiased; 0 for a constant column),
+// computed in FP64.  work: (kStatBlocks + 1) * 64 doubles.
+constexpr int kStatBlocks = 512;
+hipError_t mlp_input_stats(const float* X, int64_t rows, double* work, float* shift, float* scale, hipStream_t s);
+// Rows [a0, a0 + count) of the order given by the keyed permutation of
+// [0, rows) for (seed, epoch), gathered into xs [count][64] and ys [count].
+hipError_t gather_shuffled(const float* X, const float* y, int64_t rows, uint64_t seed, uint32_t epoch, int64_t a0,
+                           int64_t count, float* xs, float* ys, hipStream_t s);
+// out[i] = permutation(i) for i < n.
+hipError_t shuffle_indices(int64_t n, uint64_t seed, uint32_t epoch, int64_t* out, hipStream_t s);
 
 }  // namespace geonet

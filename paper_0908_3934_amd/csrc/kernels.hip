@@ -23,34 +23,55 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "philox.h"
 
 namespace geonet {
 namespace {
-
-// ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as
-// easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplies with the
-// Weyl key schedule.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint4 philox(uint4 x, uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        // each 32 x 32 -> 64-bit product in one v_mad_u64_u32
-        const uint64_t pa = static_cast<uint64_t>(x.x) * 0xD2511F53u;
-        const uint64_t pc = static_cast<uint64_t>(x.z) * 0xCD9E8D57u;
-        x = make_uint4(static_cast<uint32_t>(pc >> 32) ^ x.y ^ k0, static_cast<uint32_t>(pc),
-                       static_cast<uint32_t>(pa >> 32) ^ x.w ^ k1, static_cast<uint32_t>(pa));
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return x;
-}
 
 // Standard normal from two 32-bit draws (Box-Muller on 24-bit uniforms).
 __device__ __forceinline__ float gaussian(uint32_t a, uint32_t b) {
     const float u1 = (static_cast<float>(a >> 8) + 0.5f) * 0x1p-24f;
     const float u2 = (static_cast<float>(b >> 8) + 0.5f) * 0x1p-24f;
     return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+}
+
+// The same draw in FP64 (the Izhikevich vertex keeps its state in FP64).
+__device__ __forceinline__ double gaussian_d(uint32_t a, uint32_t b) {
+    const double u1 = (static_cast<double>(a >> 8) + 0.5) * 0x1p-24;
+    const double u2 = (static_cast<double>(b >> 8) + 0.5) * 0x1p-24;
+    return sqrt(-2.0 * log(u1)) * cos(2.0 * 3.141592653589793 * u2);
+}
+
+// One step of the Izhikevich vertex (Section 3.1, Eq. izsimple) with its
+// post-synaptic current (Section 3.2, Eqs. simplepsc, alphapsc, izpsc), from
+// the state at t; `spike` is spd(V(t)), `in` the delivered sum (an impulse
+// into r or p, or into V without a PSC), `u` the control current and `noise`
+// sigma*xi.  The expressions are evaluated in the order the header states.
+struct IzhState {
+    double v, w, r, p;
+};
+
+__device__ __forceinline__ IzhState izh_step(const NetParams& p, const IzhState& s, bool spike, double in, double u,
+                                             double noise) {
+    IzhState n = s;
+    if (p.psc == NET_PSC_EXP) {
+        n.r = s.r - p.dt_d * p.psc_a * s.r + in;
+    } else if (p.psc == NET_PSC_ALPHA) {
+        n.r = s.r + p.dt_d * s.p;
+        n.p = s.p + p.dt_d * (-p.psc_a * p.psc_a * s.r - 2.0 * p.psc_a * s.p) + in;
+    }
+    if (spike) {
+        n.v = static_cast<double>(p.v_reset);
+        n.w = s.w + p.iz_d;
+    } else {
+        const double syn = p.psc == NET_PSC_NONE ? 0.0 : s.r;
+        const double cur = p.iz_k * (s.v - p.iz_vr) * (s.v - p.iz_vt) - s.w + syn + u;
+        double vn = s.v + p.dt_d * p.iz_inv_c * cur;
+        if (p.psc == NET_PSC_NONE) vn = vn + in;
+        n.v = vn + noise;
+        n.w = s.w + p.dt_d * p.iz_a * (p.iz_b * (s.v - p.iz_vr) - s.w);
+    }
+    return n;
 }
 
 __device__ __forceinline__ float half_bits_to_float(uint32_t bits) {
@@ -457,6 +478,10 @@ struct NodeArgs {
     uint64_t* __restrict__ rec_raster;
     float* __restrict__ rec_v;
     float* __restrict__ rec_input;
+    double* __restrict__ Vd;      // Izhikevich state (null without Izhikevich networks)
+    double* __restrict__ Wd;
+    double* __restrict__ psc_r;
+    double* __restrict__ psc_p;
     int64_t n_total, n_pad, rec_row, raster_words, frame_index;
     uint32_t t_lo, t_hi;
     int32_t d_sum, frame_flush, frame_steps, frame_cap, sum_shift;
@@ -496,7 +521,7 @@ __device__ __forceinline__ void vertex_random(const NodeArgs& a, int64_t j, int6
     uint32_t pulse = 0;
     if (thr != 0u || p.sigma != 0.0f) {
         const uint32_t jl = static_cast<uint32_t>(jj - p.node_off);
-        const uint4 r = philox(make_uint4(jl, a.t_lo, a.t_hi, 0u), p.key_lo, p.key_hi);
+        const uint4 r = philox4x32_10(make_uint4(jl, a.t_lo, a.t_hi, 0u), p.key_lo, p.key_hi);
         pulse = r.x < thr ? 1u : 0u;
         if (p.sigma != 0.0f) noise = p.sigma * gaussian(r.y, r.z);
     }
@@ -510,17 +535,20 @@ __device__ __forceinline__ void vertex_random(const NodeArgs& a, int64_t j, int6
 // raster and summary words are written only when their first vertex is below
 // word_end.  `st` is the vertex's state as load_vertex_state returns it,
 // completed by vertex_random.
-template <bool kMulti>
+template <bool kMulti, bool kModels = false>
 __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int64_t j_end, int64_t word_end, float in,
                                               bool clear_input, const VertexState& st) {
     const int lane = threadIdx.x & 63;
     const bool valid = j < j_end;
     const int64_t jj = valid ? j : 0;
     const NetParams p = kMulti ? a.params[a.net_id[jj]] : a.p0;
-    const float v = st.v;
+    const bool izh = kModels && p.model == NET_MODEL_IZHIKEVICH;
+    IzhState zs{};
+    if (izh) zs = IzhState{a.Vd[jj], a.Wd[jj], a.psc_r[jj], a.psc_p[jj]};
+    const float v = izh ? static_cast<float>(zs.v) : st.v;
     const uint32_t ages = st.ages & 0xFFFFu;
     const uint32_t age = ages & 0xFFu, age2 = ages >> 8;
-    const bool spike = valid && v >= p.v_th;
+    const bool spike = valid && (izh ? zs.v >= static_cast<double>(p.v_th) : v >= p.v_th);
 
     const uint64_t spikes = wave_ballot(spike);
     if (a.rec_raster && lane == 0 && j < word_end && j < a.n_total)
@@ -540,7 +568,22 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
     float vn;
     uint32_t age_n;
     const bool held = age >= 1u && age <= static_cast<uint32_t>(p.n_ref);
-    if (spike) {
+    if (izh) {
+        age_n = spike ? 1u : (age >= static_cast<uint32_t>(kAgeNever) ? kAgeNever : age + 1u);
+        double u = 0.0, noise = 0.0;
+        if (!spike) {
+            const uint32_t thr = a.drive_thr ? a.drive_thr[jj] : 0u;
+            u = a.i_ext ? static_cast<double>(a.i_ext[jj]) : 0.0;
+            if (thr != 0u || p.sigma != 0.0f) {
+                const uint32_t jl = static_cast<uint32_t>(jj - p.node_off);
+                const uint4 r = philox4x32_10(make_uint4(jl, a.t_lo, a.t_hi, 0u), p.key_lo, p.key_hi);
+                if (r.x < thr) u = u + static_cast<double>(p.drive_amp);
+                noise = static_cast<double>(p.sigma) * gaussian_d(r.y, r.z);
+            }
+        }
+        zs = izh_step(p, zs, spike, static_cast<double>(in), u, noise);
+        vn = static_cast<float>(zs.v);
+    } else if (spike) {
         vn = p.v_reset;
         age_n = 1u;
     } else {
@@ -572,6 +615,12 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
 
     if (valid) {
         a.V[j] = vn;
+        if (izh) {
+            a.Vd[j] = zs.v;
+            a.Wd[j] = zs.w;
+            a.psc_r[j] = zs.r;
+            a.psc_p[j] = zs.p;
+        }
         // the previous last spike becomes the one before the last
         const uint32_t older = spike ? age : age2;
         const uint32_t age2_n = older >= static_cast<uint32_t>(kAgeNever) ? kAgeNever : older + 1u;
@@ -591,13 +640,15 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
     }
 }
 
-template <bool kMulti>
+template <bool kMulti, bool kModels>
 __global__ void __launch_bounds__(256) node_update_kernel(NodeArgs a) {
     const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const float in = a.I[j < a.n_total ? j : 0];
     VertexState st = load_vertex_state(a, j, a.n_total);
-    vertex_random<kMulti>(a, j, a.n_total, st);
-    vertex_update<kMulti>(a, j, a.n_total, a.n_pad, in, true, st);
+    // the Izhikevich vertex draws its own (FP64) noise inside vertex_update
+    if (!kModels || (kMulti ? a.params[a.net_id[j < a.n_total ? j : 0]] : a.p0).model == NET_MODEL_LIF)
+        vertex_random<kMulti>(a, j, a.n_total, st);
+    vertex_update<kMulti, kModels>(a, j, a.n_total, a.n_pad, in, true, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -633,6 +684,10 @@ struct EnsembleArgs {
     uint64_t* __restrict__ rec_raster;
     float* __restrict__ rec_v;
     float* __restrict__ rec_input;
+    double* __restrict__ Vd;      // Izhikevich state in global memory (null without Izhikevich networks)
+    double* __restrict__ Wd;
+    double* __restrict__ psc_r;
+    double* __restrict__ psc_p;
     int64_t t0, n_total, n_pad, raster_words;
     int32_t n_steps, frame_cap, frame_num, frame_den, d_sum;
 };
@@ -778,10 +833,13 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
                 const bool valid = j < nm.n_nodes;
                 const int jj = valid ? j : 0;
                 const int64_t u = nm.node_off + jj;
-                const float v = L.V[jj];
+                const bool izh = p.model == NET_MODEL_IZHIKEVICH;
+                IzhState zs{};
+                if (izh) zs = IzhState{a.Vd[u], a.Wd[u], a.psc_r[u], a.psc_p[u]};
+                const float v = izh ? static_cast<float>(zs.v) : L.V[jj];
                 const uint32_t age = L.age[jj];
                 const float in = L.I[jj];
-                const bool spike = valid && v >= p.v_th;
+                const bool spike = valid && (izh ? zs.v >= static_cast<double>(p.v_th) : v >= p.v_th);
                 const uint64_t spikes = wave_ballot(spike);
                 const uint64_t alive = wave_ballot(valid);
                 if (a.rec_raster && lane == 0 && alive != 0)
@@ -789,7 +847,29 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
                 float vn;
                 uint32_t age_n;
                 const bool held = age >= 1u && age <= static_cast<uint32_t>(p.n_ref);
-                if (spike) {
+                if (izh) {
+                    age_n = spike ? 1u : (age >= static_cast<uint32_t>(kAgeNever) ? kAgeNever : age + 1u);
+                    double uu = 0.0, noise = 0.0;
+                    if (!spike) {
+                        const uint32_t thr = a.drive_thr ? a.drive_thr[u] : 0u;
+                        uu = a.i_ext ? static_cast<double>(a.i_ext[u]) : 0.0;
+                        if (thr != 0u || p.sigma != 0.0f) {
+                            const uint4 r = philox4x32_10(make_uint4(static_cast<uint32_t>(jj), static_cast<uint32_t>(t),
+                                                                     static_cast<uint32_t>(static_cast<uint64_t>(t) >> 32), 0u),
+                                                          p.key_lo, p.key_hi);
+                            if (r.x < thr) uu = uu + static_cast<double>(p.drive_amp);
+                            noise = static_cast<double>(p.sigma) * gaussian_d(r.y, r.z);
+                        }
+                    }
+                    zs = izh_step(p, zs, spike, static_cast<double>(in), uu, noise);
+                    vn = static_cast<float>(zs.v);
+                    if (valid) {
+                        a.Vd[u] = zs.v;
+                        a.Wd[u] = zs.w;
+                        a.psc_r[u] = zs.r;
+                        a.psc_p[u] = zs.p;
+                    }
+                } else if (spike) {
                     vn = p.v_reset;
                     age_n = 1u;
                 } else {
@@ -801,7 +881,7 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
                         float noise = 0.0f;
                         const uint32_t thr = a.drive_thr ? a.drive_thr[u] : 0u;
                         if (thr != 0u || p.sigma != 0.0f) {
-                            const uint4 r = philox(make_uint4(static_cast<uint32_t>(jj), static_cast<uint32_t>(t),
+                            const uint4 r = philox4x32_10(make_uint4(static_cast<uint32_t>(jj), static_cast<uint32_t>(t),
                                                               static_cast<uint32_t>(static_cast<uint64_t>(t) >> 32), 0u),
                                                    p.key_lo, p.key_hi);
                             if (r.x < thr) uu += p.drive_amp;
@@ -921,7 +1001,7 @@ __global__ void __launch_bounds__(256) observe_kernel(ObserveArgs a) {
             break;
         case NET_OBS_FLUOR: {
             const uint32_t jl = static_cast<uint32_t>(j - p.node_off);
-            const uint4 r = philox(make_uint4(jl, static_cast<uint32_t>(f), static_cast<uint32_t>(f >> 32), 1u),
+            const uint4 r = philox4x32_10(make_uint4(jl, static_cast<uint32_t>(f), static_cast<uint32_t>(f >> 32), 1u),
                                    p.key_lo, p.key_hi);
             const double F = static_cast<double>(a.gain) * a.frames[f * a.n_pad + j] + static_cast<double>(a.offset) +
                              static_cast<double>(a.gamma) * static_cast<double>(gaussian(r.x, r.y));
@@ -1308,6 +1388,10 @@ static NodeArgs node_args(const DeviceGraph& g, int64_t t, int64_t rec_row, cons
     a.frame_steps = frame_steps;
     a.frame_cap = g.frame_cap;
     a.p0 = g.p0;
+    a.Vd = g.Vd;
+    a.Wd = g.Wd;
+    a.psc_r = g.psc_r;
+    a.psc_p = g.psc_p;
     return a;
 }
 
@@ -1317,10 +1401,16 @@ hipError_t launch_node_update(const DeviceGraph& g, int64_t t, int64_t rec_row, 
     const NodeArgs a = node_args(g, t, rec_row, rec, frame_flush, frame_index, frame_steps);
     const int threads = 256;
     const int64_t blocks = g.n_pad / threads + ((g.n_pad % threads) ? 1 : 0);
-    if (g.n_nets > 1)
-        hipExtLaunchKernelGGL(node_update_kernel<true>, dim3(blocks), dim3(threads), 0, s, ev0, ev1, 0, a);
-    else
-        hipExtLaunchKernelGGL(node_update_kernel<false>, dim3(blocks), dim3(threads), 0, s, ev0, ev1, 0, a);
+    if (g.Vd) {
+        if (g.n_nets > 1)
+            hipExtLaunchKernelGGL((node_update_kernel<true, true>), dim3(blocks), dim3(threads), 0, s, ev0, ev1, 0, a);
+        else
+            hipExtLaunchKernelGGL((node_update_kernel<false, true>), dim3(blocks), dim3(threads), 0, s, ev0, ev1, 0, a);
+    } else if (g.n_nets > 1) {
+        hipExtLaunchKernelGGL((node_update_kernel<true, false>), dim3(blocks), dim3(threads), 0, s, ev0, ev1, 0, a);
+    } else {
+        hipExtLaunchKernelGGL((node_update_kernel<false, false>), dim3(blocks), dim3(threads), 0, s, ev0, ev1, 0, a);
+    }
     return hipGetLastError();
 }
 
@@ -1376,6 +1466,10 @@ hipError_t launch_ensemble(const DeviceGraph& g, const EnsemblePlan& plan, int64
     a.rec_raster = rec ? rec->raster : nullptr;
     a.rec_v = rec ? rec->v : nullptr;
     a.rec_input = rec ? rec->input : nullptr;
+    a.Vd = g.Vd;
+    a.Wd = g.Wd;
+    a.psc_r = g.psc_r;
+    a.psc_p = g.psc_p;
     a.t0 = t0;
     a.n_total = g.n_total;
     a.n_pad = g.n_pad;

@@ -14,6 +14,7 @@
 #include <cstdint>
 
 #include "internal.h"
+#include "philox.h"
 
 namespace geonet {
 namespace {
@@ -237,6 +238,103 @@ __global__ void __launch_bounds__(256) normalize_kernel(const float* X, const fl
         w[j] = lo | (hi << 16);
     }
     reinterpret_cast<uint4*>(Xb)[i] = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Column statistics of a [rows][64] FP32 feature matrix, in FP64 with a
+// fixed summation order: pass 0 sums x, pass 1 sums (x - mean)^2.  Thread t
+// of a workgroup owns column t % 64 and every fourth row of the workgroup's
+// stride; the four partials per column are added in LDS, one row of
+// partials per workgroup.
+__global__ void __launch_bounds__(256) colstats_kernel(const float* X, int64_t rows, const double* mean,
+                                                       double* part) {
+    __shared__ double red[4][kMlpIn];
+    const int c = threadIdx.x % kMlpIn, q = threadIdx.x / kMlpIn;
+    const double mu = mean ? mean[c] : 0.0;
+    double acc = 0.0;
+    for (int64_t r = static_cast<int64_t>(blockIdx.x) * 4 + q; r < rows; r += static_cast<int64_t>(gridDim.x) * 4) {
+        const double x = static_cast<double>(X[r * kMlpIn + c]) - mu;
+        acc += mean ? x * x : x;
+    }
+    red[q][c] = acc;
+    __syncthreads();
+    if (q == 0) part[static_cast<int64_t>(blockIdx.x) * kMlpIn + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
+// Sums the partial rows in order.  pass 0: mean = sum / rows.  pass 1:
+// std = sqrt(sum / (rows - 1)) (0 for one row), shift = mean,
+// scale = 1/std where std > 1e-6, else 0 (a constant feature is dropped).
+__global__ void __launch_bounds__(64) colstats_finish_kernel(const double* part, int blocks, int64_t rows, int pass,
+                                                             double* mean, float* shift, float* scale) {
+    const int c = threadIdx.x;
+    double acc = 0.0;
+    for (int b = 0; b < blocks; ++b) acc += part[static_cast<int64_t>(b) * kMlpIn + c];
+    if (pass == 0) {
+        mean[c] = acc / static_cast<double>(rows);
+        return;
+    }
+    const double sd = rows > 1 ? sqrt(acc / static_cast<double>(rows - 1)) : 0.0;
+    shift[c] = static_cast<float>(mean[c]);
+    scale[c] = sd > 1e-6 ? static_cast<float>(1.0 / sd) : 0.0f;
+}
+
+// A keyed permutation of [0, n): a four-round balanced Feistel network on
+// 2h bits (2^(2h) >= n, so at most 4n values) whose round function is
+// Philox4x32-10 of (right half, round, epoch), walked until the value falls
+// below n (cycle walking; any permutation of the larger domain restricted
+// this way is a permutation of [0, n)).
+struct ShufflePerm {
+    uint64_t n;
+    uint32_t k0, k1, epoch;
+    int h;
+};
+
+__device__ __forceinline__ uint64_t shuffle_index(uint64_t i, const ShufflePerm& p) {
+    const uint32_t mask = (p.h >= 32) ? 0xFFFFFFFFu : ((1u << p.h) - 1u);
+    uint64_t x = i;
+    do {
+        uint32_t L = static_cast<uint32_t>(x >> p.h) & mask, R = static_cast<uint32_t>(x) & mask;
+#pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) {
+            const uint4 f = philox4x32_10(make_uint4(R, r, p.epoch, 0x53485546u), p.k0, p.k1);
+            const uint32_t nr = (L ^ f.x) & mask;
+            L = R;
+            R = nr;
+        }
+        x = (static_cast<uint64_t>(L) << p.h) | R;
+    } while (x >= p.n);
+    return x;
+}
+
+// Rows [a0, a0 + count) of the shuffled order gathered into xs / ys.
+__global__ void __launch_bounds__(256) gather_shuffled_kernel(const float* X, const float* y, ShufflePerm p,
+                                                              int64_t a0, int64_t count, float* xs, float* ys) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;   // one thread per 16 floats
+    const int64_t r = i / 4;
+    if (r >= count) return;
+    const int part = static_cast<int>(i % 4);
+    const int64_t src = static_cast<int64_t>(shuffle_index(static_cast<uint64_t>(a0 + r), p));
+    const float4* in = reinterpret_cast<const float4*>(X + src * kMlpIn) + 4 * part;
+    float4* out = reinterpret_cast<float4*>(xs + r * kMlpIn) + 4 * part;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k] = in[k];
+    if (part == 0) ys[r] = y[src];
+}
+
+__global__ void __launch_bounds__(256) shuffle_index_kernel(ShufflePerm p, int64_t* out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < static_cast<int64_t>(p.n)) out[i] = static_cast<int64_t>(shuffle_index(static_cast<uint64_t>(i), p));
+}
+
+ShufflePerm make_perm(int64_t n, uint64_t seed, uint32_t epoch) {
+    ShufflePerm p{};
+    p.n = static_cast<uint64_t>(n);
+    p.k0 = static_cast<uint32_t>(seed);
+    p.k1 = static_cast<uint32_t>(seed >> 32);
+    p.epoch = epoch;
+    int bits = 1;
+    while (bits < 63 && (uint64_t(1) << bits) < p.n) ++bits;
+    p.h = (bits + 1) / 2;
+    return p;
 }
 
 struct HeadArgs {
@@ -789,6 +887,34 @@ hipError_t mlp_adam(const MlpDevice& d, float lr, float beta1, float beta2, floa
     a.c1 = static_cast<float>(1.0 - std::pow(static_cast<double>(beta1), static_cast<double>(t)));
     a.c2 = static_cast<float>(1.0 - std::pow(static_cast<double>(beta2), static_cast<double>(t)));
     hipLaunchKernelGGL(adam_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t mlp_input_stats(const float* X, int64_t rows, double* work, float* shift, float* scale, hipStream_t s) {
+    double* mean = work + static_cast<int64_t>(kStatBlocks) * kMlpIn;
+    const int blocks = static_cast<int>(std::min<int64_t>(kStatBlocks, (rows + 3) / 4));
+    hipLaunchKernelGGL(colstats_kernel, dim3(blocks), dim3(256), 0, s, X, rows, static_cast<const double*>(nullptr),
+                       work);
+    hipLaunchKernelGGL(colstats_finish_kernel, dim3(1), dim3(kMlpIn), 0, s, static_cast<const double*>(work), blocks,
+                       rows, 0, mean, shift, scale);
+    hipLaunchKernelGGL(colstats_kernel, dim3(blocks), dim3(256), 0, s, X, rows, static_cast<const double*>(mean), work);
+    hipLaunchKernelGGL(colstats_finish_kernel, dim3(1), dim3(kMlpIn), 0, s, static_cast<const double*>(work), blocks,
+                       rows, 1, mean, shift, scale);
+    return hipGetLastError();
+}
+
+hipError_t gather_shuffled(const float* X, const float* y, int64_t rows, uint64_t seed, uint32_t epoch, int64_t a0,
+                           int64_t count, float* xs, float* ys, hipStream_t s) {
+    const ShufflePerm p = make_perm(rows, seed, epoch);
+    const int64_t threads = count * 4;
+    hipLaunchKernelGGL(gather_shuffled_kernel, dim3(static_cast<unsigned>((threads + 255) / 256)), dim3(256), 0, s, X,
+                       y, p, a0, count, xs, ys);
+    return hipGetLastError();
+}
+
+hipError_t shuffle_indices(int64_t n, uint64_t seed, uint32_t epoch, int64_t* out, hipStream_t s) {
+    const ShufflePerm p = make_perm(n, seed, epoch);
+    hipLaunchKernelGGL(shuffle_index_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, p, out);
     return hipGetLastError();
 }
 

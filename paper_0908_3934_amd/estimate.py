@@ -207,26 +207,23 @@ class EdgeScorer:
 
     def fit(self, train: Sequence[Observed], epochs: int = 4, batch: int = 16384, lr: float = 1e-3,
             feats: Optional[list] = None):
+        """Standardisation fitted to the training features and `epochs`
+        shuffled passes (net_mlp_fit_input_norm, net_mlp_train_epoch: every
+        row once per epoch, the last batch of an epoch possibly smaller).
+        history holds each epoch's mean batch loss."""
         import torch
         X = torch.cat(feats if feats is not None else [features(o) for o in train])
         y = torch.tensor(np.concatenate([o.labels for o in train]).astype(np.float32), device=X.device)
-        mean = X.mean(0)
-        std = X.std(0)
-        scale = torch.where(std > 1e-6, 1.0 / std, torch.zeros_like(std))
-        self.input_norm = (mean.cpu().numpy(), scale.cpu().numpy())
-        self.mlp.set_input_norm(*self.input_norm)
-        g = torch.Generator(device="cpu").manual_seed(self.seed)
-        n = X.shape[0]
-        loss = torch.zeros(1, dtype=torch.float32, device=X.device)
+        n = int(X.shape[0])
+        if n == 0:
+            raise ValueError("EdgeScorer.fit: no training pairs")
+        self.mlp.fit_input_norm(X)
+        self.input_norm = self.mlp.get_input_norm()
+        steps = -(-n // batch)
+        losses = torch.zeros(steps, dtype=torch.float32, device=X.device)
         for ep in range(epochs):
-            perm = torch.randperm(n, generator=g).to(X.device)
-            Xs, ys = X[perm].contiguous(), y[perm].contiguous()
-            tot, steps = 0.0, 0
-            for a in range(0, n - batch + 1, batch):
-                self.mlp.train_step(Xs[a:a + batch], ys[a:a + batch], lr, loss=loss)
-                tot += float(loss.item()) if (steps % 50 == 0) else 0.0
-                steps += 1
-            self.history.append(tot)
+            self.mlp.train_epoch(X, y, batch, lr, seed=self.seed, epoch=ep, losses=losses)
+            self.history.append(float(losses.cpu().numpy().astype(np.float64).mean()))
         return self
 
     def score(self, o: Observed, feats=None):

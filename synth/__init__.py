@@ -129,6 +129,22 @@ class NetSpec:
     frame_den: int = FRAME_DEN
     inhibitory: Optional[np.ndarray] = None      # bool [n] (informational)
     meta: dict = field(default_factory=dict)
+    # vertex model: 0 leaky integrate-and-fire (above), 1 Izhikevich (v_th is
+    # V_peak, v_reset is c; tau_ms, v_rest and n_ref are unused) with a
+    # post-synaptic current: psc 0 none (input jumps V), 1 exponential, 2 alpha
+    # (the library takes these constants as FP32: they are kept FP32-exact so
+    # that both sides simulate the same values)
+    model: int = 0
+    psc: int = 0
+    iz_C: float = 100.0                      # pF
+    iz_k: float = float(np.float32(0.7))     # nS/mV
+    iz_vr: float = -60.0                     # mV
+    iz_vt: float = -40.0                     # mV
+    iz_a: float = float(np.float32(0.03))    # 1/ms (recovery rate)
+    iz_b: float = -2.0                       # nS
+    iz_d: float = 100.0                      # pA
+    psc_rate: float = float(np.float32(0.2))  # 1/ms (PSC decay rate a)
+    w0_iz: Optional[np.ndarray] = None           # float32 [n] initial W, or 0
 
     @property
     def n(self) -> int:
@@ -207,6 +223,36 @@ def _subset(n: int, frac: float, seed: int, tag: int) -> np.ndarray:
 def _weights(m: int, scale: float, seed: int) -> np.ndarray:
     rng = np.random.default_rng([seed & 0xFFFFFFFF, seed >> 32, 7])
     return round_fp16((0.5 + rng.random(m)) * scale)
+
+
+# Izhikevich workloads (Section 3.1 simple model, regular-spiking constants;
+# the paper's benchmark steps it at dt = 1 ms).
+IZ_DT_MS = 1.0
+IZ_V_PEAK = 35.0
+IZ_C_RESET = -50.0
+IZ_DRIVE_AMP = 3000.0       # pA for one step: +30 mV, enough to fire from rest
+IZ_NOISE_SIGMA = 1.0        # mV per step
+# weight scale per PSC kind, mV (none) or pA (exp, alpha): on the 256-vertex
+# config-0 geometry these sit just below the recurrent run-away (measured on
+# the oracle: ~1 Hz with arrivals causing spikes; 11 -> 12 mV, 250 -> 300 pA
+# and 50 -> 60 pA each jump to > 60 Hz network-wide bursts)
+IZ_W0 = {0: 11.0, 1: 250.0, 2: 50.0}
+
+
+def izhikevich(spec: NetSpec, psc: int = 1, w_scale: Optional[float] = None, seed_tag: int = 11) -> NetSpec:
+    """The same geometry and edges as `spec`, as an Izhikevich network at
+    dt = 1 ms with PSC kind `psc`: weights U[0.5,1.5] * scale (FP16), V(0)
+    spread over [Vr, Vt], W(0) = 0, the same driven vertices."""
+    from dataclasses import replace
+    scale = IZ_W0[psc] if w_scale is None else w_scale
+    rng = np.random.default_rng([spec.seed & 0xFFFFFFFF, spec.seed >> 32, seed_tag])
+    w = round_fp16((0.5 + rng.random(spec.n_edges)) * scale)
+    if spec.inhibitory is not None:
+        w = np.where(spec.inhibitory[spec.src], -w, w).astype(np.float32)
+    v0 = (-60.0 + 20.0 * rng.random(spec.n)).astype(np.float32)
+    return replace(spec, name=spec.name + "-izh%d" % psc, weight=w, model=1, psc=psc, dt_ms=IZ_DT_MS,
+                   v_th=IZ_V_PEAK, v_reset=IZ_C_RESET, n_ref=0, drive_amp=IZ_DRIVE_AMP,
+                   noise_sigma=IZ_NOISE_SIGMA, v0=v0, frame_den=FRAME_DEN // 10)
 
 
 def config0_like(n: int, seed: int, name: str = "config0", w0: float = W0) -> NetSpec:

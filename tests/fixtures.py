@@ -96,3 +96,25 @@ def random_tiny(n: int, p: float, seed: int, max_delay: int = 12, w_scale: float
 def raster_events(r: np.ndarray) -> List[tuple]:
     t, j = np.nonzero(r)
     return sorted(zip(j.tolist(), t.tolist()))
+
+
+def izhikevich_tiny(n: int, psc: int, seed: int, sigma: float = 1.0) -> synth.NetSpec:
+    """Tiny random Izhikevich network (dt = 1 ms) with explicit delays, some
+    driven vertices and a constant current on the others."""
+    base = random_tiny(n, 0.5, seed, drive=True)
+    rng = np.random.default_rng(1000 + seed)
+    scale = synth.IZ_W0[psc] * 2.0
+    w = synth.round_fp16(np.sign(base.weight) * (0.5 + rng.random(base.n_edges)) * scale)
+    spec = synth.izhikevich(base, psc=psc)
+    spec.weight = w
+    spec.noise_sigma = sigma
+    spec.i_ext = (rng.random(n) * 60.0).astype(np.float32)
+    if base.drive_rate_hz is not None:
+        spec.drive_rate_hz = (base.drive_rate_hz / 150.0 * 40.0).astype(np.float32)   # 40 Hz at dt = 1 ms
+    return spec
+
+
+def iz_params(spec) -> dict:
+    return {"C": spec.iz_C, "k": spec.iz_k, "vr": spec.iz_vr, "vt": spec.iz_vt, "a": spec.iz_a, "b": spec.iz_b,
+            "d": spec.iz_d, "psc": spec.psc, "psc_a": spec.psc_rate,
+            "w0": None if spec.w0_iz is None else spec.w0_iz.tolist()}

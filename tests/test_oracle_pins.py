@@ -281,3 +281,24 @@ def test_split_run_equals_single_run():
     p1 = b.step(250, v=True)
     p2 = b.step(350, v=True)
     assert np.array_equal(whole["v"], np.concatenate([p1["v"], p2["v"]]))
+
+
+def test_oracle_threads_bit_identical():
+    """The oracle's per-vertex loops split over threads give the same bits as
+    the serial run (the spike push stays serial, in vertex order)."""
+    spec = synth.config1(n=8192)
+    spec.drive_rate_hz = np.full(spec.n, 50.0, np.float32)
+    out = []
+    try:
+        for th in (1, 4):
+            oracle.set_threads(th)
+            o = oracle.OracleNet(spec, frames_cap=4)
+            r = o.step(400, raster=True, v=True, inp=True)
+            r["c"] = o.calcium()
+            r["frames"] = o.frames()
+            out.append(r)
+    finally:
+        oracle.set_threads(1)
+    assert out[0]["raster"].sum() > 100
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), k

@@ -127,6 +127,98 @@ def test_config1_reduced():
     assert o["raster"].sum() > 1000
 
 
+class ChunkedParity:
+    """Accumulates the parity bars over a run compared in chunks of steps, so
+    that neither side holds the records of the whole run: raster Jaccard over
+    all (vertex, step) events, V over the first `v_steps` steps, delivered
+    inputs bit-exact up to (and including) the first step whose rasters
+    differ."""
+
+    def __init__(self, v_steps=1000):
+        self.inter = self.union = 0
+        self.dv = 0.0
+        self.v_steps = v_steps
+        self.diverged_at = None
+        self.t = 0
+        self.events = 0
+
+    def add(self, g_raster, o_raster, g_v=None, o_v=None, g_in=None, o_in=None):
+        a, b = g_raster.astype(bool), o_raster.astype(bool)
+        self.inter += int(np.logical_and(a, b).sum())
+        self.union += int(np.logical_or(a, b).sum())
+        self.events += int(b.sum())
+        steps = a.shape[0]
+        if g_v is not None and self.t < self.v_steps:
+            k = min(steps, self.v_steps - self.t)
+            self.dv = max(self.dv, float(np.abs(g_v[:k] - o_v[:k]).max()))
+        if self.diverged_at is None:
+            diff = np.nonzero((a != b).any(1))[0]
+            upto = diff[0] + 1 if diff.size else steps
+            assert g_in is not None, "inputs are compared until the rasters first differ"
+            assert np.array_equal(g_in[:upto], o_in[:upto]), \
+                "delivered inputs differ before the first raster difference (chunk at step %d)" % self.t
+            if diff.size:
+                self.diverged_at = self.t + int(diff[0])
+        self.t += steps
+
+    @property
+    def need_inputs(self):
+        return self.diverged_at is None
+
+    def jaccard(self):
+        return 1.0 if self.union == 0 else self.inter / self.union
+
+    def check(self):
+        assert self.dv <= V_TOL, "max |dV| over the first %d steps = %g" % (self.v_steps, self.dv)
+        J = self.jaccard()
+        assert J >= JACCARD_MIN, "raster Jaccard %.6f (first difference at step %s)" % (J, self.diverged_at)
+        return J
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_config1_full_run():
+    """Configuration 1 at its full size and length: N = 65,536 vertices in a
+    1 mm cube (~6.7e6 edges, delays up to ~170 steps, state noise 0.05), all
+    100,000 steps (10 s), the fused step against the FP64 oracle in chunks of
+    1,000 steps: raster Jaccard >= 0.995 over the run, V within 1e-4 over the
+    first 1,000 steps, inputs bit-exact up to the first raster difference.
+    The two-kernel path runs beside it and must equal it bit for bit."""
+    gn, torch = _gn()
+    spec = synth.config1()
+    T, C = 100000, 1000
+    a = gn.Net(spec, flags=gn.NET_BUILD_FUSED_STEP)
+    assert a.info()["deliver_flags"] & gn.NET_BUILD_FUSED_STEP
+    b = gn.Net(spec)
+    oracle.set_threads(oracle.test_threads())
+    try:
+        o = oracle.OracleNet(spec)
+        acc = ChunkedParity()
+        for c in range(T // C):
+            want_v = c * C < acc.v_steps
+            want_in = acc.need_inputs
+            ga = a.step(C, raster=True, v=want_v, inp=want_in)
+            gb = b.step(C, raster=True, v=want_v, inp=want_in)
+            torch.cuda.synchronize()
+            for key in ga:
+                assert (ga[key] is None and gb[key] is None) or torch.equal(ga[key], gb[key]), (c, key)
+            oc = o.step(C, raster=True, v=want_v, inp=want_in)
+            acc.add(gn.unpack_raster(ga["raster"], spec.n), oc["raster"],
+                    ga["v"].cpu().numpy().astype(np.float64) if want_v else None, oc["v"],
+                    ga["input"].cpu().numpy().astype(np.float64) if want_in else None, oc["input"])
+            del ga, gb, oc
+            if c % 10 == 9:
+                print("config 1: %d steps compared, Jaccard so far %.6f" % ((c + 1) * C, acc.jaccard()), flush=True)
+        J = acc.check()
+        print("config 1, %d steps: Jaccard %.6f, %d oracle spikes, first raster difference at %s, max|dV| %.3g"
+              % (T, J, acc.events, acc.diverged_at, acc.dv), flush=True)
+        assert acc.events > 1000000
+    finally:
+        oracle.set_threads(1)
+        a.close()
+        b.close()
+
+
 def test_ensemble_matches_independent_runs():
     sizes = [64, 100, 257, 300, 513, 97]
     specs = [synth.config0_like(n, synth.config_seed(3, k + 1), w0=0.36) for k, n in enumerate(sizes)]
@@ -454,29 +546,60 @@ def test_full_size_fused_step_open_loop():
     assert disagree <= 0.005 * max(int(raster.sum()), 1), disagree
 
 
-@pytest.mark.timeout(900)
-def test_full_size_ensemble_sampled_networks():
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_full_size_ensemble_all_networks():
     """The benchmarked ensemble (512 networks of 64..4096 vertices, one
-    autotuned launch for all steps) against the oracle on a sample of its
-    networks, smallest and largest included: rasters of 2,000 steps to the
-    usual bar."""
+    autotuned launch per call) against the oracle on every network for all
+    10,000 steps, in chunks of 1,000: per network raster Jaccard >= 0.995, V
+    within 1e-4 over the first 1,000 steps, delivered inputs bit-exact up to
+    the first raster difference.  The independent oracle runs are spread over
+    threads (each network is its own serial oracle)."""
+    from concurrent.futures import ThreadPoolExecutor
     gn, torch = _gn()
     specs = synth.config3()
-    T = 2000
+    T, C = 10000, 1000
     net = gn.Net(specs, flags=gn.NET_BUILD_AUTOTUNE)
-    assert net.info()["n_nets"] == 512
-    out = net.step(T, raster=True)
-    torch.cuda.synchronize()
-    raster = gn.unpack_raster(out["raster"], net.n_total)
+    assert net.info()["n_nets"] == 512 and net.info()["ensemble_blocks"] > 0
     offs = net.node_offsets()
-    net.close()
-    sizes = np.array([s.n for s in specs])
-    picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 0, 137, 301, 511})
-    fired = 0
-    for k in picks:
-        o = oracle.OracleNet(specs[k]).step(T)
-        sub = raster[:, offs[k]:offs[k + 1]].astype(bool)
-        J = jaccard(sub, o["raster"].astype(bool))
-        assert J >= JACCARD_MIN, (k, specs[k].n, J)
-        fired += int(o["raster"].sum())
-    assert fired > 100
+    orc = [oracle.OracleNet(s) for s in specs]
+    acc = [ChunkedParity() for _ in specs]
+    pool = ThreadPoolExecutor(max_workers=oracle.test_threads())
+    try:
+        for c in range(T // C):
+            want_v = c * C < 1000
+            want_in = any(x.need_inputs for x in acc)
+            g = net.step(C, raster=True, v=want_v, inp=want_in)
+            torch.cuda.synchronize()
+            raster = gn.unpack_raster(g["raster"], net.n_total)
+            gv = g["v"].cpu().numpy() if want_v else None
+            gi = g["input"].cpu().numpy() if want_in else None
+            del g
+
+            def one(k):
+                wv, wi = want_v, acc[k].need_inputs
+                oc = orc[k].step(C, raster=True, v=wv, inp=wi)
+                lo, hi = offs[k], offs[k + 1]
+                acc[k].add(raster[:, lo:hi], oc["raster"],
+                           gv[:, lo:hi].astype(np.float64) if wv else None, oc["v"],
+                           gi[:, lo:hi].astype(np.float64) if wi else None, oc["input"])
+                return True
+
+            assert all(pool.map(one, range(len(specs))))
+            print("ensemble: %d steps compared" % ((c + 1) * C), flush=True)
+        worst = min(range(len(specs)), key=lambda k: acc[k].jaccard())
+        for k, x in enumerate(acc):
+            try:
+                x.check()
+            except AssertionError as e:
+                raise AssertionError("network %d (N = %d): %s" % (k, specs[k].n, e))
+        fired = sum(x.events for x in acc)
+        diverged = sum(x.diverged_at is not None for x in acc)
+        print("ensemble: 512 networks x %d steps, %d oracle spikes, %d networks with any raster difference, "
+              "lowest Jaccard %.6f (network %d)" % (T, fired, diverged, acc[worst].jaccard(), worst), flush=True)
+        assert fired > 100000
+    finally:
+        pool.shutdown()
+        for o in orc:
+            o.close()
+        net.close()
