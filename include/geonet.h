@@ -375,6 +375,25 @@ typedef struct {
  */
 net_status net_features(const net_obs_desc* obs, float* features_dev, void* stream);
 
+/*
+ * net_features for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same features (same kernels, same bits), with the
+ * scratch in a fixed 16 MiB array of device memory that the library holds on
+ * every GPU it runs on until the process ends, instead of memory taken from
+ * the allocator.  It allocates and frees nothing.  The scratch needed,
+ * net_features_noalloc_scratch_bytes(n_nodes, n_frames) (about
+ * 16 * n_nodes * n_frames bytes), must not exceed 16 MiB, else NET_E_RANGE
+ * with the sizes in net_estimate_last_error and nothing launched.  Every
+ * call on one GPU uses that GPU's one array: calls that overlap on one GPU
+ * (from several threads or streams at once) race and must be serialised by
+ * the caller; each call waits for its own completion, so successive calls
+ * from one thread are safe.  Nothing in the array needs to start at zero
+ * (every kernel writes its scratch before reading it).
+ */
+net_status net_features_noalloc(const net_obs_desc* obs, float* features_dev, void* stream);
+size_t net_features_noalloc_scratch_bytes(int32_t n_nodes, int32_t n_frames);
+
 /* Options of the simulation-based fit (zeroed struct or NULL: defaults). */
 typedef struct {
     int32_t realisations;   /* K noise realisations per hypothesis, divides 64 (default 8) */

@@ -141,6 +141,8 @@ SIGNATURES = {
     "net_shuffle_indices": (C.c_int, [C.c_int64, C.c_uint64, C.c_uint32, _vp, _vp]),
     "net_mlp_free": (None, [_vp]),
     "net_simulate_device_error": (C.c_int, [_vp]),
+    "net_features_noalloc": (C.c_int, [_vp, _vp, _vp]),
+    "net_features_noalloc_scratch_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
     "net_mlp_last_error": (C.c_char_p, []),
 }
 

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgeonet.so")
-SOURCES = ["kernels.hip", "build.cpp", "abi.cpp", "mlp.hip", "mlp_abi.cpp", "estimate.hip", "estimate_abi.cpp", "simfit.hip"]
+SOURCES = ["kernels.hip", "build.cpp", "abi.cpp", "mlp.hip", "mlp_abi.cpp", "estimate.hip", "estimate_abi.cpp", "simfit.hip",
+           "features_noalloc.hip"]
 HEADERS = ["internal.h", "philox.h", os.path.join("..", "..", "include", "geonet.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

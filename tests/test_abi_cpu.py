@@ -18,7 +18,7 @@ HEADER = os.path.join(ROOT, "include", "geonet.h")
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:net_status|void|const char\s*\*)\s*(net_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^(?:net_status|void|size_t|const char\s*\*)\s*(net_\w+)\s*\(", text, re.M)))
 
 
 @pytest.fixture(scope="module")
