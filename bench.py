@@ -337,20 +337,29 @@ TESTSET_CURRENT_PA = 60.0     # constant input above the regular-spiking rheobas
 TESTSET_W_PA = 25.0           # alpha-PSC weight scale at the in-degree of the k = 8 lattice
 
 
-def testset_specs(synth, dims=(2,)):
-    """The standardized test networks as Izhikevich networks with an alpha
-    PSC at dt = 1 ms (the paper's benchmark model and step), driven by a
-    constant current as in its Figure 8; weights U[0.5,1.5] * 25 pA scaled
-    by 8 / mean in-degree so that denser classes are not driven harder."""
+TESTSET_HH_CURRENT = 8.0      # uA/cm^2, above the HH model's onset of repetitive firing (~6.3)
+TESTSET_HH_W = 6.0            # alpha-PSC weight scale (uA/cm^2) at the in-degree of the k = 8 lattice
+
+
+def testset_specs(synth, dims=(2,), model="izhikevich"):
+    """The standardized test networks as Izhikevich networks at dt = 1 ms or
+    Hodgkin-Huxley networks at dt = 0.03 ms (the paper's two benchmark
+    models and steps), with an alpha PSC, driven by a constant current as in
+    its Figure 8; weights U[0.5,1.5] * scale, the scale multiplied by
+    8 / mean in-degree so that denser classes are not driven harder."""
     from synth import testset as ts
     import numpy as np
     out = []
     for s in ts.test_set(dims_list=dims):
         indeg = max(1.0, s.n_edges / s.n)
-        scale = TESTSET_W_PA * min(1.0, 8.0 / indeg)
-        z = synth.izhikevich(s, psc=2, w_scale=scale)
-        z.i_ext = np.full(s.n, TESTSET_CURRENT_PA, np.float32)
-        z.noise_sigma = synth.IZ_NOISE_SIGMA
+        if model == "hh":
+            z = synth.hodgkin_huxley(s, psc=2, w_scale=TESTSET_HH_W * min(1.0, 8.0 / indeg))
+            z.i_ext = np.full(s.n, TESTSET_HH_CURRENT, np.float32)
+            z.noise_sigma = synth.HH_NOISE_SIGMA
+        else:
+            z = synth.izhikevich(s, psc=2, w_scale=TESTSET_W_PA * min(1.0, 8.0 / indeg))
+            z.i_ext = np.full(s.n, TESTSET_CURRENT_PA, np.float32)
+            z.noise_sigma = synth.IZ_NOISE_SIGMA
         z.meta = dict(s.meta)
         out.append(z)
     return out
@@ -366,9 +375,12 @@ def bench_testset(args, torch, synth, gn):
     autotuned), and the 40 together as one ensemble launch.  value = the
     ensemble's real-time factor per network (40 x 10 s simulated / wall)."""
     import numpy as np
-    specs = testset_specs(synth)
-    steps = args.steps
-    sim_s = steps * synth.IZ_DT_MS * 1e-3
+    specs = testset_specs(synth, model=args.model)
+    hh = args.model == "hh"
+    dt_ms = synth.HH_DT_MS if hh else synth.IZ_DT_MS
+    # 10 s of Izhikevich time (10,000 steps) or 1 s of HH time (33,334 steps), as in the paper
+    steps = args.steps if args.steps_given else (33334 if hh else 10000)
+    sim_s = steps * dt_ms * 1e-3
     rows = []
     for s in specs:
         net = gn.Net(s, flags=gn.NET_BUILD_SINGLE_LAUNCH | gn.NET_BUILD_AUTOTUNE)
@@ -401,7 +413,7 @@ def bench_testset(args, torch, synth, gn):
     worst = rows[int(np.argmin(rtf))]
     log("ensemble of %d: %.3f s for %d steps (kernel %.3f ms), %d blocks x %d threads"
         % (len(specs), wall, steps, tm["ensemble_ms"], info["ensemble_blocks"], info["ensemble_threads"]))
-    cpu = None if args.no_cpu_baseline else testset_cpu_baseline(specs, steps)
+    cpu = None if args.no_cpu_baseline else testset_cpu_baseline(specs, steps, sample_steps=3334 if hh else 1000)
     return {
         "metric": "real-time factor",
         "value": len(specs) * sim_s / wall,
@@ -416,14 +428,19 @@ def bench_testset(args, torch, synth, gn):
         "dtype": "f64 (vertex state), f32 (delivered sums)",
         "data": "synthetic",
         "config": {
-            "workload": "the paper's 40 two-dimensional test networks (4 classes x 2 densities x N = 10..1000), "
-                        "Izhikevich vertex with alpha PSC, dt 1 ms, 10 s, constant 60 pA input, noise 1 mV",
+            "workload": ("the paper's 40 two-dimensional test networks (4 classes x 2 densities x N = 10..1000), "
+                         "Hodgkin-Huxley vertex with alpha PSC, dt 0.03 ms, 1 s, constant 8 uA/cm^2 input, "
+                         "noise 0.1 mV") if hh else
+                        ("the paper's 40 two-dimensional test networks (4 classes x 2 densities x N = 10..1000), "
+                         "Izhikevich vertex with alpha PSC, dt 1 ms, 10 s, constant 60 pA input, noise 1 mV"),
+            "model": args.model,
             "n_networks": len(specs), "n_vertices": N, "n_edges": E,
             "launch": "%d workgroups x %d threads, one launch per call" % (info["ensemble_blocks"],
                                                                           info["ensemble_threads"]),
         },
         "alone": {
-            "method": "each network on its own handle, single-launch kernel, autotuned; real-time factor = 10 s / wall",
+            "method": "each network on its own handle, single-launch kernel, autotuned; real-time factor = "
+                      "simulated time / wall",
             "min": float(rtf.min()), "median": float(np.median(rtf)), "max": float(rtf.max()),
             "slowest": worst,
             "by_network": [{k: (round(v, 2) if isinstance(v, float) else v) for k, v in r.items()} for r in rows],
@@ -438,10 +455,13 @@ def bench_testset(args, torch, synth, gn):
             "note": "5 B per edge-step; %.1f MB of edges stay in L2: the bound is each workgroup's per-step "
                     "barriers and LDS work, not HBM" % (BYTES_PER_EDGE * E / 1e6),
         },
-        "paper_context": "Section 3.4: on one Tesla C1060 its Izhikevich networks (dt 1 ms) ran 10-20x faster "
-                         "than real time for most networks and about real time for the largest random ones; "
-                         "one 2.5 GHz Core2Duo core ran them from just under real time (10 vertices) to ~15x "
-                         "slower (largest random)",
+        "paper_context": ("Section 3.4: on one Tesla C1060 its HH networks (dt 0.03 ms) ran in about real time "
+                          "except the largest random ones (10-15x slower than real time); one 2.5 GHz Core2Duo "
+                          "core was 15-800x slower than real time") if hh else
+                         ("Section 3.4: on one Tesla C1060 its Izhikevich networks (dt 1 ms) ran 10-20x faster "
+                          "than real time for most networks and about real time for the largest random ones; "
+                          "one 2.5 GHz Core2Duo core ran them from just under real time (10 vertices) to ~15x "
+                          "slower (largest random)"),
         "cpu_baseline": cpu,
     }
 
@@ -465,8 +485,8 @@ def testset_cpu_baseline(specs, steps, sample_steps=1000):
     rtf = np.array(rtf)
     return {"value": float(np.median(rtf)), "unit": "real-time factor (median over the 40 networks)",
             "cores": 1, "kind": "oracle", "host_cpu": host_cpu(), "min": float(rtf.min()), "max": float(rtf.max()),
-            "sample": "every network for %d steps (1 s simulated), single-threaded FP64 oracle; %.1f s in all"
-                      % (sample_steps, t_all)}
+            "sample": "every network for %d steps (%.2f s simulated), single-threaded FP64 oracle; %.1f s in all"
+                      % (sample_steps, sample_steps * specs[0].dt_ms * 1e-3, t_all)}
 
 
 def bench_estimate(args, torch, synth):
@@ -617,7 +637,11 @@ def main():
                          "network's steady spike rate rather than the start from rest")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy three times (reference for HBM counters)")
+    ap.add_argument("--model", choices=["izhikevich", "hh"], default="izhikevich",
+                    help="testset workload: the vertex model (Izhikevich at dt = 1 ms for 10 s, or "
+                         "Hodgkin-Huxley at dt = 0.03 ms for 1 s)")
     args = ap.parse_args()
+    args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
     if args.gpus != 1:
         print("bench.py measures one GPU only: the simulator is built and measured on a single "
               "MI355X; --gpus %d is not supported" % args.gpus, file=sys.stderr)

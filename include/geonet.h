@@ -115,13 +115,27 @@ typedef struct {
        an arrival being an impulse of its weight (pA for EXP/ALPHA, mV for
        NONE).  Units: ms, mV, pF, pA, nS. */
     int32_t model;                /* NET_MODEL_* (0 = LIF) */
-    int32_t psc;                  /* NET_PSC_* (Izhikevich only) */
+    int32_t psc;                  /* NET_PSC_* (Izhikevich and Hodgkin-Huxley) */
     float iz_C, iz_k, iz_vr, iz_vt, iz_a, iz_b, iz_d;   /* Izhikevich constants */
     float psc_rate;               /* PSC decay rate a (1/ms) */
     const float* w0;              /* host [n_nodes] initial W, or NULL (0) */
+    /* NET_MODEL_HODGKIN_HUXLEY: the four-state vertex of Section 3.1 (V and the
+       gates m, n, h, FP64), Euler-stepped (the paper uses dt = 0.03 ms):
+         V <- V + dt*(1/C)*[-gNa m^3 h (V-ENa) - gK n^4 (V-EK) - gL (V-EL) + r + U]
+              (+ I for psc NONE) + sigma*xi
+         x <- x + dt*(alpha_x(V)(1-x) - beta_x(V) x),  x in {m, n, h}
+       with alpha_m = 0.1(V+40)/(1-exp(-(V+40)/10)), beta_m = 4 exp(-(V+65)/18),
+       alpha_h = 0.07 exp(-(V+65)/20), beta_h = 1/(1+exp(-(V+35)/10)),
+       alpha_n = 0.01(V+55)/(1-exp(-(V+55)/10)), beta_n = 0.125 exp(-(V+65)/80)
+       (limits 1 and 0.1 at V = -40, -55).  The gates start at their steady
+       state for V(0).  A spike is the upward crossing s_j(t) = [V(t) >= v_th and
+       V(t-1) < v_th] (V(-1) = V(0)); there is no reset; n_ref must be 0; the
+       PSC kinds are those of the Izhikevich vertex.  Units: mV, ms, uF/cm^2,
+       mS/cm^2, uA/cm^2. */
+    float hh_C, hh_gna, hh_gk, hh_gl, hh_ena, hh_ek, hh_el;
 } net_desc;
 
-enum { NET_MODEL_LIF = 0, NET_MODEL_IZHIKEVICH = 1 };
+enum { NET_MODEL_LIF = 0, NET_MODEL_IZHIKEVICH = 1, NET_MODEL_HODGKIN_HUXLEY = 2 };
 enum { NET_PSC_NONE = 0, NET_PSC_EXP = 1, NET_PSC_ALPHA = 2 };
 
 /* Build options; a zeroed struct (or NULL) selects the defaults. */

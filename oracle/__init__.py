@@ -78,6 +78,10 @@ def _load():
         L.orc_set_izhikevich.restype = _c.c_int32
         L.orc_get_izh.argtypes = [_vp, _vp, _vp, _vp]
         L.orc_get_izh.restype = None
+        L.orc_set_hodgkin_huxley.argtypes = [_vp, _c.c_int32, _vp, _c.c_double]
+        L.orc_set_hodgkin_huxley.restype = _c.c_int32
+        L.orc_get_hh.argtypes = [_vp, _vp, _vp, _vp]
+        L.orc_get_hh.restype = None
         L.orc_set_threads.argtypes = [_c.c_int32]
         L.orc_set_threads.restype = None
         L.orc_get_threads.argtypes = []
@@ -179,6 +183,14 @@ class OracleNet:
             w0 = arr(getattr(spec, "w0_iz", None), np.float32)
             if L.orc_set_izhikevich(self.h, int(spec.psc), iz.ctypes.data, float(spec.psc_rate), _ptr(w0)) != 0:
                 raise ValueError("oracle rejected the Izhikevich parameters")
+        elif self.model == 2:
+            hh = np.array([spec.hh_C, spec.hh_gna, spec.hh_gk, spec.hh_gl, spec.hh_ena, spec.hh_ek, spec.hh_el],
+                          dtype=np.float64)
+            if not np.array_equal(hh.astype(np.float32).astype(np.float64), hh) or \
+                    float(np.float32(spec.psc_rate)) != spec.psc_rate:
+                raise ValueError("Hodgkin-Huxley constants must be FP32 values (the library takes them as FP32)")
+            if L.orc_set_hodgkin_huxley(self.h, int(spec.psc), hh.ctypes.data, float(spec.psc_rate)) != 0:
+                raise ValueError("oracle rejected the Hodgkin-Huxley parameters")
 
     def close(self):
         if self.h:
@@ -227,6 +239,12 @@ class OracleNet:
         W, r, p = (np.zeros(self.n, dtype=np.float64) for _ in range(3))
         self._L.orc_get_izh(self.h, W.ctypes.data, r.ctypes.data, p.ctypes.data)
         return W, r, p
+
+    def gates(self):
+        """(m, n, h) of every vertex (Hodgkin-Huxley networks)."""
+        m, n, h = (np.zeros(self.n, dtype=np.float64) for _ in range(3))
+        self._L.orc_get_hh(self.h, m.ctypes.data, n.ctypes.data, h.ctypes.data)
+        return m, n, h
 
     def calcium(self) -> np.ndarray:
         out = np.zeros(self.n, dtype=np.float64)

@@ -46,13 +46,19 @@ def simulate(n: int, edges: Sequence, steps: int, *, dt: float = 0.1, tau: float
              v_rest: float = 0.0, v_reset: float = 0.0, v_th: float = 1.0, n_ref: int = 20,
              drive_thr: Optional[Sequence[int]] = None, drive_amp: float = 1.5,
              i_ext: Optional[Sequence[float]] = None, sigma: float = 0.0, seed: int = 0,
-             v0: Optional[Sequence[float]] = None, izhikevich: Optional[dict] = None) -> Dict[str, list]:
+             v0: Optional[Sequence[float]] = None, izhikevich: Optional[dict] = None,
+             hodgkin_huxley: Optional[dict] = None) -> Dict[str, list]:
     """edges: iterable of (src, dst, weight, delay_steps).
 
     izhikevich: None for the LIF vertex, else a dict with C, k, vr, vt, a,
     b, d, psc (0 none, 1 exponential, 2 alpha), psc_a and optionally w0: the
     simple model of Section 3.1 (V_peak = v_th, c = v_reset) whose synaptic
-    states follow Section 3.2; the records then also hold W, r and p."""
+    states follow Section 3.2; the records then also hold W, r and p.
+
+    hodgkin_huxley: None, or a dict with C, gna, gk, gl, ena, ek, el, psc,
+    psc_a: the four-state vertex of Section 3.1 with the standard rate
+    functions (written below independently of oracle.c), spikes signalled on
+    the upward crossing of v_th, gates starting at their steady state."""
     assert n <= 8, "brute force is for tiny networks"
     W = [[0.0] * n for _ in range(n)]
     A = [[False] * n for _ in range(n)]
@@ -67,6 +73,10 @@ def simulate(n: int, edges: Sequence, steps: int, *, dt: float = 0.1, tau: float
     last = [None] * n
     hist: List[List[int]] = []
     rec_s, rec_v, rec_i = [], [], []
+    hh = hodgkin_huxley
+    if hh is not None:
+        return _simulate_hh(n, A, W, D, steps, dt, v_th, drive_thr, drive_amp, i_ext, sigma, key,
+                            [float(v) for v in v0] if v0 is not None else [v_rest] * n, hh)
     iz = izhikevich
     if iz is not None:
         Wr = [float(x) for x in iz["w0"]] if iz.get("w0") is not None else [0.0] * n
@@ -138,3 +148,68 @@ def simulate(n: int, edges: Sequence, steps: int, *, dt: float = 0.1, tau: float
     if iz is not None:
         out.update(w=rec_w, r=rec_r, p=rec_p)
     return out
+
+
+def _rates(V: float):
+    """(alpha, beta) of m, h, n at V (mV, ms), the standard squid-axon set."""
+    x = V + 40.0
+    am = 1.0 if x == 0.0 else 0.1 * x / (1.0 - math.exp(-x / 10.0))
+    bm = 4.0 * math.exp(-(V + 65.0) / 18.0)
+    ah = 0.07 * math.exp(-(V + 65.0) / 20.0)
+    bh = 1.0 / (1.0 + math.exp(-(V + 35.0) / 10.0))
+    y = V + 55.0
+    an = 0.1 if y == 0.0 else 0.01 * y / (1.0 - math.exp(-y / 10.0))
+    bn = 0.125 * math.exp(-(V + 65.0) / 80.0)
+    return (am, bm), (ah, bh), (an, bn)
+
+
+def _simulate_hh(n, A, W, D, steps, dt, v_th, drive_thr, drive_amp, i_ext, sigma, key, V, hh):
+    gates = []
+    for j in range(n):
+        (am, bm), (ah, bh), (an, bn) = _rates(V[j])
+        gates.append([am / (am + bm), ah / (ah + bh), an / (an + bn)])   # m, h, n at rest
+    Vprev = list(V)
+    R = [0.0] * n
+    P = [0.0] * n
+    hist: List[List[int]] = []
+    rec_s, rec_v, rec_i = [], [], []
+    a = hh["psc_a"]
+    for t in range(steps):
+        s = [1 if (V[j] >= v_th and Vprev[j] < v_th) else 0 for j in range(n)]
+        hist.append(s)
+        rec_s.append(s)
+        rec_v.append(list(V))
+        I = []
+        for j in range(n):
+            tot = 0.0
+            for k in range(n):
+                if k != j and A[k][j] and t - D[k][j] >= 0 and hist[t - D[k][j]][k]:
+                    tot += W[k][j]
+            I.append(tot)
+        rec_i.append(I)
+        newV, newR, newP, newG = list(V), list(R), list(P), [list(g) for g in gates]
+        for j in range(n):
+            if hh["psc"] == 1:
+                newR[j] = R[j] - dt * a * R[j] + I[j]
+            elif hh["psc"] == 2:
+                newR[j] = R[j] + dt * P[j]
+                newP[j] = P[j] + dt * (-a * a * R[j] - 2.0 * a * P[j]) + I[j]
+            r = philox4x32_10((j, t & M32, t >> 32, 0), key)
+            u = (float(i_ext[j]) if i_ext is not None else 0.0) + \
+                (drive_amp if (drive_thr is not None and r[0] < drive_thr[j]) else 0.0)
+            xi = gauss(r[1], r[2])
+            m, h, nn = gates[j]
+            syn = 0.0 if hh["psc"] == 0 else R[j]
+            i_na = hh["gna"] * m * m * m * h * (V[j] - hh["ena"])
+            i_k = hh["gk"] * nn * nn * nn * nn * (V[j] - hh["ek"])
+            i_l = hh["gl"] * (V[j] - hh["el"])
+            vn = V[j] + dt * (1.0 / hh["C"]) * (-i_na - i_k - i_l + syn + u)
+            if hh["psc"] == 0:
+                vn = vn + I[j]
+            newV[j] = vn + sigma * xi
+            (am, bm), (ah, bh), (an, bn) = _rates(V[j])
+            newG[j] = [m + dt * (am * (1.0 - m) - bm * m), h + dt * (ah * (1.0 - h) - bh * h),
+                       nn + dt * (an * (1.0 - nn) - bn * nn)]
+        Vprev = list(V)
+        V, R, P, gates = newV, newR, newP, newG
+    return {"raster": rec_s, "v": rec_v, "input": rec_i, "v_final": V}

@@ -139,6 +139,9 @@ class Net:
             d.frame_num = s.frame_num
             d.frame_den = s.frame_den
             d.model = getattr(s, "model", 0)
+            if d.model == _abi.NET_MODEL_HODGKIN_HUXLEY:
+                d.hh_C, d.hh_gna, d.hh_gk, d.hh_gl = s.hh_C, s.hh_gna, s.hh_gk, s.hh_gl
+                d.hh_ena, d.hh_ek, d.hh_el = s.hh_ena, s.hh_ek, s.hh_el
             if d.model:
                 d.psc = s.psc
                 d.iz_C, d.iz_k, d.iz_vr, d.iz_vt = s.iz_C, s.iz_k, s.iz_vr, s.iz_vt

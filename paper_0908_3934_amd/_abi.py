@@ -31,6 +31,7 @@ NET_BUILD_AUTOTUNE = 64
 
 NET_MODEL_LIF = 0
 NET_MODEL_IZHIKEVICH = 1
+NET_MODEL_HODGKIN_HUXLEY = 2
 NET_PSC_NONE = 0
 NET_PSC_EXP = 1
 NET_PSC_ALPHA = 2
@@ -55,6 +56,8 @@ class NetDesc(C.Structure):
         ("frame_den", C.c_int32), ("model", C.c_int32), ("psc", C.c_int32), ("iz_C", C.c_float),
         ("iz_k", C.c_float), ("iz_vr", C.c_float), ("iz_vt", C.c_float), ("iz_a", C.c_float),
         ("iz_b", C.c_float), ("iz_d", C.c_float), ("psc_rate", C.c_float), ("w0", _vp),
+        ("hh_C", C.c_float), ("hh_gna", C.c_float), ("hh_gk", C.c_float), ("hh_gl", C.c_float),
+        ("hh_ena", C.c_float), ("hh_ek", C.c_float), ("hh_el", C.c_float),
     ]
 
 

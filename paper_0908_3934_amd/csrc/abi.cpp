@@ -245,10 +245,13 @@ net_status reset_state(net* h, const HostGraph& hg, hipStream_t s) {
     if (e == hipSuccess && g.calcium) e = hipMemsetAsync(g.calcium, 0, np * sizeof(double), s);
     if (e == hipSuccess && g.Vd) {
         std::vector<double> vd(hg.v0.begin(), hg.v0.end());
-        e = hipMemcpyAsync(g.Vd, vd.data(), std::min(vd.size(), np) * sizeof(double), hipMemcpyHostToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(g.Wd, hg.w0.data(), std::min(hg.w0.size(), np) * sizeof(double), hipMemcpyHostToDevice,
-                               s);
+        const size_t nb = std::min(vd.size(), np) * sizeof(double);
+        e = hipMemcpyAsync(g.Vd, vd.data(), nb, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && g.Wd) e = hipMemcpyAsync(g.Wd, hg.w0.data(), nb, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && g.hh_m) e = hipMemcpyAsync(g.hh_m, hg.hh_m0.data(), nb, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && g.hh_n) e = hipMemcpyAsync(g.hh_n, hg.hh_n0.data(), nb, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && g.hh_h) e = hipMemcpyAsync(g.hh_h, hg.hh_h0.data(), nb, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && g.hh_vprev) e = hipMemcpyAsync(g.hh_vprev, vd.data(), nb, hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipMemsetAsync(g.psc_r, 0, np * sizeof(double), s);
         if (e == hipSuccess) e = hipMemsetAsync(g.psc_p, 0, np * sizeof(double), s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);     // `vd` is freed below
@@ -408,12 +411,18 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
     if ((st = zeros(h, &g.I, np, s, "input")) != NET_OK) return bail(st);
     if ((st = zeros(h, &g.ring, np * kRingWords, s, "history ring")) != NET_OK) return bail(st);
     if ((st = zeros(h, &g.summary, np / 32, s, "summary")) != NET_OK) return bail(st);
-    if (hg.any_izh) {
+    if (hg.any_izh || hg.any_hh) {
         std::vector<double> vd(hg.v0.begin(), hg.v0.end());
-        if ((st = upload(h, &g.Vd, vd, np, s, "Izhikevich V")) != NET_OK) return bail(st);
-        if ((st = upload(h, &g.Wd, hg.w0, np, s, "Izhikevich W")) != NET_OK) return bail(st);
+        if ((st = upload(h, &g.Vd, vd, np, s, "FP64 V")) != NET_OK) return bail(st);
         if ((st = zeros(h, &g.psc_r, np, s, "PSC r")) != NET_OK) return bail(st);
         if ((st = zeros(h, &g.psc_p, np, s, "PSC p")) != NET_OK) return bail(st);
+        if (hg.any_izh && (st = upload(h, &g.Wd, hg.w0, np, s, "Izhikevich W")) != NET_OK) return bail(st);
+        if (hg.any_hh) {
+            if ((st = upload(h, &g.hh_m, hg.hh_m0, np, s, "HH gates")) != NET_OK) return bail(st);
+            if ((st = upload(h, &g.hh_n, hg.hh_n0, np, s, "HH gates")) != NET_OK) return bail(st);
+            if ((st = upload(h, &g.hh_h, hg.hh_h0, np, s, "HH gates")) != NET_OK) return bail(st);
+            if ((st = upload(h, &g.hh_vprev, vd, np, s, "HH V(t-1)")) != NET_OK) return bail(st);
+        }
         const hipError_t se = hipStreamSynchronize(s);   // `vd` is freed below
         if (se != hipSuccess) {
             device_fail(h, se, "net_build: upload");

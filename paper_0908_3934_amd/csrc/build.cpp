@@ -63,6 +63,21 @@ uint32_t pulse_threshold(double rate_hz, double dt_ms) {
     return static_cast<uint32_t>(thr);
 }
 
+// Hodgkin-Huxley rate functions (the standard squid-axon set; mV, ms),
+// alpha_m and alpha_n at their limits where the denominator vanishes.
+void hh_steady_gates(double V, double* m, double* n, double* h) {
+    const double x = V + 40.0, y = V + 55.0;
+    const double am = x == 0.0 ? 1.0 : 0.1 * x / (1.0 - std::exp(-x / 10.0));
+    const double bm = 4.0 * std::exp(-(V + 65.0) / 18.0);
+    const double ah = 0.07 * std::exp(-(V + 65.0) / 20.0);
+    const double bh = 1.0 / (1.0 + std::exp(-(V + 35.0) / 10.0));
+    const double an = y == 0.0 ? 0.1 : 0.01 * y / (1.0 - std::exp(-y / 10.0));
+    const double bn = 0.125 * std::exp(-(V + 65.0) / 80.0);
+    *m = am / (am + bm);
+    *n = an / (an + bn);
+    *h = ah / (ah + bh);
+}
+
 net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g, std::string& err, int32_t seg_count,
                             int32_t seg_cap) {
     if (!descs || n_nets < 1) {
@@ -85,13 +100,20 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
             err = "net_build: network " + std::to_string(m) + " needs positions or explicit delays";
             return NET_E_ARG;
         }
-        if (d.model != NET_MODEL_LIF && d.model != NET_MODEL_IZHIKEVICH) {
+        if (d.model != NET_MODEL_LIF && d.model != NET_MODEL_IZHIKEVICH && d.model != NET_MODEL_HODGKIN_HUXLEY) {
             err = "net_build: network " + std::to_string(m) + " has an unknown vertex model";
             return NET_E_ARG;
         }
         if (d.model == NET_MODEL_LIF &&
             (!(d.dt_ms > 0.0) || !(d.tau_ms > 0.0) || d.n_ref < 0 || d.n_ref > 250)) {
             err = "net_build: network " + std::to_string(m) + " needs dt > 0, tau > 0, 0 <= n_ref <= 250";
+            return NET_E_ARG;
+        }
+        if (d.model == NET_MODEL_HODGKIN_HUXLEY &&
+            (!(d.dt_ms > 0.0) || d.n_ref != 0 || !(d.hh_C > 0.0f) || d.psc < NET_PSC_NONE || d.psc > NET_PSC_ALPHA ||
+             (d.psc != NET_PSC_NONE && !(d.psc_rate >= 0.0f)))) {
+            err = "net_build: Hodgkin-Huxley network " + std::to_string(m) +
+                  " needs dt > 0, n_ref = 0, C > 0, psc in 0..2 and psc_rate >= 0";
             return NET_E_ARG;
         }
         if (d.model == NET_MODEL_IZHIKEVICH &&
@@ -348,6 +370,9 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
     g.i_ext.assign(g.n_pad, 0.0f);
     g.net_id.assign(g.n_pad, n_nets - 1);
     g.w0.assign(g.n_pad, 0.0);
+    g.hh_m0.assign(g.n_pad, 0.0);
+    g.hh_n0.assign(g.n_pad, 0.0);
+    g.hh_h0.assign(g.n_pad, 0.0);
     g.params.resize(n_nets);
     for (int m = 0; m < n_nets; ++m) {
         const net_desc& d = descs[m];
@@ -379,10 +404,25 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
             p.iz_d = d.iz_d;
             p.psc_a = d.psc_rate;
         }
+        if (d.model == NET_MODEL_HODGKIN_HUXLEY) {
+            g.any_hh = true;
+            p.decay = 0.0f;
+            p.n_ref = 0;
+            p.hh_inv_c = 1.0 / static_cast<double>(d.hh_C);
+            p.hh_gna = d.hh_gna;
+            p.hh_gk = d.hh_gk;
+            p.hh_gl = d.hh_gl;
+            p.hh_ena = d.hh_ena;
+            p.hh_ek = d.hh_ek;
+            p.hh_el = d.hh_el;
+            p.psc_a = d.psc_rate;
+        }
         for (int32_t j = 0; j < d.n_nodes; ++j) {
             const int64_t k = g.node_off[m] + j;
             g.v0[k] = d.v0 ? d.v0[j] : d.v_rest;
             if (d.model == NET_MODEL_IZHIKEVICH) g.w0[k] = d.w0 ? static_cast<double>(d.w0[j]) : 0.0;
+            if (d.model == NET_MODEL_HODGKIN_HUXLEY)
+                hh_steady_gates(static_cast<double>(g.v0[k]), &g.hh_m0[k], &g.hh_n0[k], &g.hh_h0[k]);
             if (d.drive_rate_hz) {
                 g.drive_thr[k] = pulse_threshold(d.drive_rate_hz[j], d.dt_ms);
                 g.any_drive |= g.drive_thr[k] != 0u;

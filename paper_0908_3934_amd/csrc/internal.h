@@ -57,6 +57,8 @@ struct NetParams {
     // Izhikevich vertex (model 1; FP64 state): V_peak = v_th, c = v_reset
     int32_t model, psc;     // NET_MODEL_*, NET_PSC_*
     double iz_inv_c, iz_k, iz_vr, iz_vt, iz_a, iz_b, iz_d, psc_a;   // iz_inv_c = 1 / C
+    // Hodgkin-Huxley vertex (model 2; FP64 state): hh_inv_c = 1 / C
+    double hh_inv_c, hh_gna, hh_gk, hh_gl, hh_ena, hh_ek, hh_el;
 };
 
 // Per-network description used by the ensemble kernel.
@@ -97,6 +99,8 @@ struct HostGraph {
     bool any_drive = false, any_iext = false;
     bool any_izh = false;             // some network uses the Izhikevich vertex
     std::vector<double> w0;           // [n_pad] initial W (Izhikevich vertices)
+    bool any_hh = false;              // some network uses the Hodgkin-Huxley vertex
+    std::vector<double> hh_m0, hh_n0, hh_h0;   // [n_pad] gates at their steady state for V(0)
     double dt_ms = 0.0;
     int32_t frame_num = 0, frame_den = 1;
 };
@@ -144,6 +148,11 @@ struct DeviceGraph {
     double* Wd = nullptr;
     double* psc_r = nullptr;
     double* psc_p = nullptr;
+    // Hodgkin-Huxley networks (null otherwise): gates and V(t-1); V is in Vd
+    double* hh_m = nullptr;
+    double* hh_n = nullptr;
+    double* hh_h = nullptr;
+    double* hh_vprev = nullptr;
     double* calcium;              // null when observation is off
     double* frame_acc;
     float* frames;                // [frame_cap][n_pad]
@@ -262,6 +271,8 @@ net_status estimate_check_obs(const net_obs_desc* o);
 void feature_inputs(const net_obs_desc* o, FeatureInputs& in);
 net_status estimate_fail(net_status st, const std::string& msg);
 uint32_t pulse_threshold(double rate_hz, double dt_ms);
+// Steady-state gates (m, n, h) of the Hodgkin-Huxley vertex at V.
+void hh_steady_gates(double V, double* m, double* n, double* h);
 
 // Simulation-based fit.
 struct FitInputs {

@@ -74,6 +74,50 @@ __device__ __forceinline__ IzhState izh_step(const NetParams& p, const IzhState&
     return n;
 }
 
+// Hodgkin-Huxley vertex (Section 3.1's four-state model), one Euler step
+// from the state at t: the rate functions of the standard squid-axon set
+// (alpha_m, alpha_n at their limits where the denominator vanishes), the PSC
+// kinds as for the Izhikevich vertex.  vprev keeps V(t) for the crossing
+// test of the next step.
+struct HhState {
+    double v, vprev, m, n, h, r, p;
+};
+
+__device__ __forceinline__ double hh_am(double V) {
+    const double x = V + 40.0;
+    return x == 0.0 ? 1.0 : 0.1 * x / (1.0 - exp(-x / 10.0));
+}
+__device__ __forceinline__ double hh_bm(double V) { return 4.0 * exp(-(V + 65.0) / 18.0); }
+__device__ __forceinline__ double hh_ah(double V) { return 0.07 * exp(-(V + 65.0) / 20.0); }
+__device__ __forceinline__ double hh_bh(double V) { return 1.0 / (1.0 + exp(-(V + 35.0) / 10.0)); }
+__device__ __forceinline__ double hh_an(double V) {
+    const double x = V + 55.0;
+    return x == 0.0 ? 0.1 : 0.01 * x / (1.0 - exp(-x / 10.0));
+}
+__device__ __forceinline__ double hh_bn(double V) { return 0.125 * exp(-(V + 65.0) / 80.0); }
+
+__device__ __forceinline__ HhState hh_step(const NetParams& p, const HhState& s, double in, double u, double noise) {
+    HhState n = s;
+    if (p.psc == NET_PSC_EXP) {
+        n.r = s.r - p.dt_d * p.psc_a * s.r + in;
+    } else if (p.psc == NET_PSC_ALPHA) {
+        n.r = s.r + p.dt_d * s.p;
+        n.p = s.p + p.dt_d * (-p.psc_a * p.psc_a * s.r - 2.0 * p.psc_a * s.p) + in;
+    }
+    const double syn = p.psc == NET_PSC_NONE ? 0.0 : s.r;
+    const double i_na = p.hh_gna * s.m * s.m * s.m * s.h * (s.v - p.hh_ena);
+    const double i_k = p.hh_gk * s.n * s.n * s.n * s.n * (s.v - p.hh_ek);
+    const double i_l = p.hh_gl * (s.v - p.hh_el);
+    double vn = s.v + p.dt_d * p.hh_inv_c * (-i_na - i_k - i_l + syn + u);
+    if (p.psc == NET_PSC_NONE) vn = vn + in;
+    n.v = vn + noise;
+    n.vprev = s.v;
+    n.m = s.m + p.dt_d * (hh_am(s.v) * (1.0 - s.m) - hh_bm(s.v) * s.m);
+    n.h = s.h + p.dt_d * (hh_ah(s.v) * (1.0 - s.h) - hh_bh(s.v) * s.h);
+    n.n = s.n + p.dt_d * (hh_an(s.v) * (1.0 - s.n) - hh_bn(s.v) * s.n);
+    return n;
+}
+
 __device__ __forceinline__ float half_bits_to_float(uint32_t bits) {
     return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(bits)));
 }
@@ -482,6 +526,10 @@ struct NodeArgs {
     double* __restrict__ Wd;
     double* __restrict__ psc_r;
     double* __restrict__ psc_p;
+    double* __restrict__ hh_m;    // Hodgkin-Huxley gates and V(t-1) (null without HH networks)
+    double* __restrict__ hh_n;
+    double* __restrict__ hh_h;
+    double* __restrict__ hh_vprev;
     int64_t n_total, n_pad, rec_row, raster_words, frame_index;
     uint32_t t_lo, t_hi;
     int32_t d_sum, frame_flush, frame_steps, frame_cap, sum_shift;
@@ -543,12 +591,16 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
     const int64_t jj = valid ? j : 0;
     const NetParams p = kMulti ? a.params[a.net_id[jj]] : a.p0;
     const bool izh = kModels && p.model == NET_MODEL_IZHIKEVICH;
+    const bool hh = kModels && p.model == NET_MODEL_HODGKIN_HUXLEY;
     IzhState zs{};
+    HhState hs{};
     if (izh) zs = IzhState{a.Vd[jj], a.Wd[jj], a.psc_r[jj], a.psc_p[jj]};
-    const float v = izh ? static_cast<float>(zs.v) : st.v;
+    if (hh) hs = HhState{a.Vd[jj], a.hh_vprev[jj], a.hh_m[jj], a.hh_n[jj], a.hh_h[jj], a.psc_r[jj], a.psc_p[jj]};
+    const float v = izh ? static_cast<float>(zs.v) : (hh ? static_cast<float>(hs.v) : st.v);
     const uint32_t ages = st.ages & 0xFFFFu;
     const uint32_t age = ages & 0xFFu, age2 = ages >> 8;
-    const bool spike = valid && (izh ? zs.v >= static_cast<double>(p.v_th) : v >= p.v_th);
+    const double vth = static_cast<double>(p.v_th);
+    const bool spike = valid && (izh ? zs.v >= vth : (hh ? (hs.v >= vth && hs.vprev < vth) : v >= p.v_th));
 
     const uint64_t spikes = wave_ballot(spike);
     if (a.rec_raster && lane == 0 && j < word_end && j < a.n_total)
@@ -583,6 +635,18 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
         }
         zs = izh_step(p, zs, spike, static_cast<double>(in), u, noise);
         vn = static_cast<float>(zs.v);
+    } else if (hh) {
+        age_n = spike ? 1u : (age >= static_cast<uint32_t>(kAgeNever) ? kAgeNever : age + 1u);
+        const uint32_t thr = a.drive_thr ? a.drive_thr[jj] : 0u;
+        double u = a.i_ext ? static_cast<double>(a.i_ext[jj]) : 0.0, noise = 0.0;
+        if (thr != 0u || p.sigma != 0.0f) {
+            const uint32_t jl = static_cast<uint32_t>(jj - p.node_off);
+            const uint4 r = philox4x32_10(make_uint4(jl, a.t_lo, a.t_hi, 0u), p.key_lo, p.key_hi);
+            if (r.x < thr) u = u + static_cast<double>(p.drive_amp);
+            noise = static_cast<double>(p.sigma) * gaussian_d(r.y, r.z);
+        }
+        hs = hh_step(p, hs, static_cast<double>(in), u, noise);
+        vn = static_cast<float>(hs.v);
     } else if (spike) {
         vn = p.v_reset;
         age_n = 1u;
@@ -620,6 +684,15 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
             a.Wd[j] = zs.w;
             a.psc_r[j] = zs.r;
             a.psc_p[j] = zs.p;
+        }
+        if (hh) {
+            a.Vd[j] = hs.v;
+            a.hh_vprev[j] = hs.vprev;
+            a.hh_m[j] = hs.m;
+            a.hh_n[j] = hs.n;
+            a.hh_h[j] = hs.h;
+            a.psc_r[j] = hs.r;
+            a.psc_p[j] = hs.p;
         }
         // the previous last spike becomes the one before the last
         const uint32_t older = spike ? age : age2;
@@ -688,6 +761,10 @@ struct EnsembleArgs {
     double* __restrict__ Wd;
     double* __restrict__ psc_r;
     double* __restrict__ psc_p;
+    double* __restrict__ hh_m;    // Hodgkin-Huxley gates and V(t-1) in global memory
+    double* __restrict__ hh_n;
+    double* __restrict__ hh_h;
+    double* __restrict__ hh_vprev;
     int64_t t0, n_total, n_pad, raster_words;
     int32_t n_steps, frame_cap, frame_num, frame_den, d_sum;
 };
@@ -834,12 +911,17 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
                 const int jj = valid ? j : 0;
                 const int64_t u = nm.node_off + jj;
                 const bool izh = p.model == NET_MODEL_IZHIKEVICH;
+                const bool hh = p.model == NET_MODEL_HODGKIN_HUXLEY;
                 IzhState zs{};
+                HhState hs{};
                 if (izh) zs = IzhState{a.Vd[u], a.Wd[u], a.psc_r[u], a.psc_p[u]};
-                const float v = izh ? static_cast<float>(zs.v) : L.V[jj];
+                if (hh) hs = HhState{a.Vd[u], a.hh_vprev[u], a.hh_m[u], a.hh_n[u], a.hh_h[u], a.psc_r[u], a.psc_p[u]};
+                const float v = izh ? static_cast<float>(zs.v) : (hh ? static_cast<float>(hs.v) : L.V[jj]);
                 const uint32_t age = L.age[jj];
                 const float in = L.I[jj];
-                const bool spike = valid && (izh ? zs.v >= static_cast<double>(p.v_th) : v >= p.v_th);
+                const double vth = static_cast<double>(p.v_th);
+                const bool spike =
+                    valid && (izh ? zs.v >= vth : (hh ? (hs.v >= vth && hs.vprev < vth) : v >= p.v_th));
                 const uint64_t spikes = wave_ballot(spike);
                 const uint64_t alive = wave_ballot(valid);
                 if (a.rec_raster && lane == 0 && alive != 0)
@@ -868,6 +950,28 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
                         a.Wd[u] = zs.w;
                         a.psc_r[u] = zs.r;
                         a.psc_p[u] = zs.p;
+                    }
+                } else if (hh) {
+                    age_n = spike ? 1u : (age >= static_cast<uint32_t>(kAgeNever) ? kAgeNever : age + 1u);
+                    const uint32_t thr = a.drive_thr ? a.drive_thr[u] : 0u;
+                    double uu = a.i_ext ? static_cast<double>(a.i_ext[u]) : 0.0, noise = 0.0;
+                    if (thr != 0u || p.sigma != 0.0f) {
+                        const uint4 r = philox4x32_10(make_uint4(static_cast<uint32_t>(jj), static_cast<uint32_t>(t),
+                                                                 static_cast<uint32_t>(static_cast<uint64_t>(t) >> 32), 0u),
+                                                      p.key_lo, p.key_hi);
+                        if (r.x < thr) uu = uu + static_cast<double>(p.drive_amp);
+                        noise = static_cast<double>(p.sigma) * gaussian_d(r.y, r.z);
+                    }
+                    hs = hh_step(p, hs, static_cast<double>(in), uu, noise);
+                    vn = static_cast<float>(hs.v);
+                    if (valid) {
+                        a.Vd[u] = hs.v;
+                        a.hh_vprev[u] = hs.vprev;
+                        a.hh_m[u] = hs.m;
+                        a.hh_n[u] = hs.n;
+                        a.hh_h[u] = hs.h;
+                        a.psc_r[u] = hs.r;
+                        a.psc_p[u] = hs.p;
                     }
                 } else if (spike) {
                     vn = p.v_reset;
@@ -1392,6 +1496,10 @@ static NodeArgs node_args(const DeviceGraph& g, int64_t t, int64_t rec_row, cons
     a.Wd = g.Wd;
     a.psc_r = g.psc_r;
     a.psc_p = g.psc_p;
+    a.hh_m = g.hh_m;
+    a.hh_n = g.hh_n;
+    a.hh_h = g.hh_h;
+    a.hh_vprev = g.hh_vprev;
     return a;
 }
 
@@ -1470,6 +1578,10 @@ hipError_t launch_ensemble(const DeviceGraph& g, const EnsemblePlan& plan, int64
     a.Wd = g.Wd;
     a.psc_r = g.psc_r;
     a.psc_p = g.psc_p;
+    a.hh_m = g.hh_m;
+    a.hh_n = g.hh_n;
+    a.hh_h = g.hh_h;
+    a.hh_vprev = g.hh_vprev;
     a.t0 = t0;
     a.n_total = g.n_total;
     a.n_pad = g.n_pad;

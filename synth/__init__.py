@@ -145,6 +145,16 @@ class NetSpec:
     iz_d: float = 100.0                      # pA
     psc_rate: float = float(np.float32(0.2))  # 1/ms (PSC decay rate a)
     w0_iz: Optional[np.ndarray] = None           # float32 [n] initial W, or 0
+    # Hodgkin-Huxley vertex (model 2; v_th is the threshold of the upward
+    # crossing that signals a spike): membrane capacitance (uF/cm^2),
+    # maximal conductances (mS/cm^2) and reversal potentials (mV)
+    hh_C: float = 1.0
+    hh_gna: float = 120.0
+    hh_gk: float = 36.0
+    hh_gl: float = float(np.float32(0.3))
+    hh_ena: float = 50.0
+    hh_ek: float = -77.0
+    hh_el: float = float(np.float32(-54.387))
 
     @property
     def n(self) -> int:
@@ -253,6 +263,32 @@ def izhikevich(spec: NetSpec, psc: int = 1, w_scale: Optional[float] = None, see
     return replace(spec, name=spec.name + "-izh%d" % psc, weight=w, model=1, psc=psc, dt_ms=IZ_DT_MS,
                    v_th=IZ_V_PEAK, v_reset=IZ_C_RESET, n_ref=0, drive_amp=IZ_DRIVE_AMP,
                    noise_sigma=IZ_NOISE_SIGMA, v0=v0, frame_den=FRAME_DEN // 10)
+
+
+# Hodgkin-Huxley workloads (the paper's benchmark steps its HH model at
+# dt = 0.03 ms).
+HH_DT_MS = 0.03
+HH_V_TH = 0.0               # mV, upward crossing
+HH_V0 = -65.0
+HH_DRIVE_AMP = 1000.0       # uA/cm^2 for one step: +30 mV
+HH_NOISE_SIGMA = 0.1        # mV per step
+HH_W0 = {0: 8.0, 1: 30.0, 2: 6.0}   # mV (none) or uA/cm^2 (exp, alpha)
+
+
+def hodgkin_huxley(spec: NetSpec, psc: int = 1, w_scale: Optional[float] = None, seed_tag: int = 13) -> NetSpec:
+    """The same geometry and edges as `spec`, as a Hodgkin-Huxley network at
+    dt = 0.03 ms with PSC kind `psc`: weights U[0.5,1.5] * scale (FP16),
+    V(0) near rest (gates at their steady state), the same driven vertices."""
+    from dataclasses import replace
+    scale = HH_W0[psc] if w_scale is None else w_scale
+    rng = np.random.default_rng([spec.seed & 0xFFFFFFFF, spec.seed >> 32, seed_tag])
+    w = round_fp16((0.5 + rng.random(spec.n_edges)) * scale)
+    if spec.inhibitory is not None:
+        w = np.where(spec.inhibitory[spec.src], -w, w).astype(np.float32)
+    v0 = (HH_V0 + 4.0 * rng.random(spec.n)).astype(np.float32)
+    return replace(spec, name=spec.name + "-hh%d" % psc, weight=w, model=2, psc=psc, dt_ms=HH_DT_MS,
+                   v_th=HH_V_TH, n_ref=0, drive_amp=HH_DRIVE_AMP, noise_sigma=HH_NOISE_SIGMA, v0=v0,
+                   psc_rate=float(np.float32(0.5)), frame_num=FRAME_NUM, frame_den=FRAME_DEN * 10 // 3)
 
 
 def config0_like(n: int, seed: int, name: str = "config0", w0: float = W0) -> NetSpec:

@@ -118,3 +118,24 @@ def iz_params(spec) -> dict:
     return {"C": spec.iz_C, "k": spec.iz_k, "vr": spec.iz_vr, "vt": spec.iz_vt, "a": spec.iz_a, "b": spec.iz_b,
             "d": spec.iz_d, "psc": spec.psc, "psc_a": spec.psc_rate,
             "w0": None if spec.w0_iz is None else spec.w0_iz.tolist()}
+
+
+def hodgkin_huxley_tiny(n: int, psc: int, seed: int, sigma: float = 0.1) -> synth.NetSpec:
+    """Tiny random Hodgkin-Huxley network (dt = 0.03 ms) with explicit
+    delays, driven vertices and a constant current on the others."""
+    base = random_tiny(n, 0.5, seed, drive=True)
+    rng = np.random.default_rng(2000 + seed)
+    scale = synth.HH_W0[psc] * 2.0
+    w = synth.round_fp16(np.sign(base.weight) * (0.5 + rng.random(base.n_edges)) * scale)
+    spec = synth.hodgkin_huxley(base, psc=psc)
+    spec.weight = w
+    spec.noise_sigma = sigma
+    spec.i_ext = (rng.random(n) * 8.0).astype(np.float32)
+    if base.drive_rate_hz is not None:
+        spec.drive_rate_hz = (base.drive_rate_hz / 150.0 * 40.0).astype(np.float32)
+    return spec
+
+
+def hh_params(spec) -> dict:
+    return {"C": spec.hh_C, "gna": spec.hh_gna, "gk": spec.hh_gk, "gl": spec.hh_gl, "ena": spec.hh_ena,
+            "ek": spec.hh_ek, "el": spec.hh_el, "psc": spec.psc, "psc_a": spec.psc_rate}
