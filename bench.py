@@ -263,43 +263,55 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 def bench_mlp(args, torch, gn):
     """The edge scorer (64 -> 256 -> 256 -> 1, BF16 MFMA): training steps
-    (forward, BCE backward, Adam) on batches of 16,384 pairs, the size the
-    scorer is trained with, and the forward pass on 65,536 pairs (about one
-    N = 1024 network's candidates).  FLOPs counted: 2 x (64*256 + 256*256 +
-    256) per pair forward, 3x that per training pair.  Timed with events on
-    the stream of the calls, whole steps (all kernels)."""
+    (forward, BCE backward, Adam) on batches of --mlp-rows pairs (default
+    65,536), and the forward pass on 65,536 pairs (about one N = 1024
+    network's candidates); the training step is also timed at 16,384 and
+    262,144 rows.  FLOPs counted: 2 x (64*256 + 256*256 + 256) per pair
+    forward, 3x that per training pair.  Timed with events on the stream of
+    the calls, whole steps (all kernels)."""
     import numpy as np
     m = gn.Mlp(gn.Mlp.init_params(0))
     m.set_input_norm(np.zeros(64, np.float32), np.ones(64, np.float32))
     fw = 2 * (64 * 256 + 256 * 256 + 256)
     g = torch.Generator(device="cuda").manual_seed(0)
-    Bt, Bf = 16384, 65536
-    X = torch.randn(Bf, 64, device="cuda", generator=g)
-    y = (torch.rand(Bf, device="cuda", generator=g) < 0.3).float()
+    Bt, Bf = args.mlp_rows, 65536
+    rows_max = max(Bt, Bf, 262144)
+    X = torch.randn(rows_max, 64, device="cuda", generator=g)
+    y = (torch.rand(rows_max, device="cuda", generator=g) < 0.3).float()
     loss = torch.zeros(1, device="cuda")
-    Xt, yt = X[:Bt].contiguous(), y[:Bt].contiguous()
     steps = args.steps
+
+    def train_time(rows, n):
+        Xt, yt = X[:rows].contiguous(), y[:rows].contiguous()
+        for _ in range(args.warmup):
+            m.train_step(Xt, yt, 1e-3, loss=loss)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            m.train_step(Xt, yt, 1e-3, loss=loss)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    train_s = train_time(Bt, steps)
+    sweep = {}
+    for rows in (16384, 65536, 262144):
+        t = train_s if rows == Bt else train_time(rows, max(20, steps // 4))
+        sweep[str(rows)] = {"ms_per_step": t * 1e3, "tflops": 3 * fw * rows / t / 1e12}
+        log("training step on %d rows: %.3f ms (%.1f TFLOP/s)" % (rows, t * 1e3, sweep[str(rows)]["tflops"]))
+    Xf = X[:Bf].contiguous()
     for _ in range(args.warmup):
-        m.train_step(Xt, yt, 1e-3, loss=loss)
+        m.forward(Xf)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        m.train_step(Xt, yt, 1e-3, loss=loss)
-    torch.cuda.synchronize()
-    train_s = (time.perf_counter() - t0) / steps
-    for _ in range(args.warmup):
-        m.forward(X)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        m.forward(X)
+        m.forward(Xf)
     torch.cuda.synchronize()
     fwd_s = (time.perf_counter() - t0) / steps
     train_tflops = 3 * fw * Bt / train_s / 1e12
     return {
         "metric": "training pairs/s",
         "value": Bt / train_s,
-        "unit": "pairs per second (one optimizer step per 16,384 pairs)",
+        "unit": "pairs per second (one optimizer step per %d pairs)" % Bt,
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
@@ -309,13 +321,14 @@ def bench_mlp(args, torch, gn):
         "vs_baseline": None,
         "dtype": "bf16 (fp32 accumulation, fp32 Adam)",
         "data": "synthetic",
-        "config": {"workload": "edge-scorer MLP 64 -> 256 -> 256 -> 1, batch 16,384 (training), 65,536 (forward)"},
+        "config": {"workload": "edge-scorer MLP 64 -> 256 -> 256 -> 1, batch %d (training), 65,536 (forward)" % Bt},
+        "train_sweep": sweep,
         "forward_pairs_per_s": Bf / fwd_s,
         "forward_us": fwd_s * 1e6,
         "roofline": {"bound": "mfma", "achieved": train_tflops, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": train_tflops / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
                      "forward_achieved": fw * Bf / fwd_s / 1e12},
-        "cpu_baseline": mlp_cpu_baseline(Xt.cpu().numpy(), yt.cpu().numpy(), m.get_params()),
+        "cpu_baseline": mlp_cpu_baseline(X[:16384].cpu().numpy(), y[:16384].cpu().numpy(), m.get_params()),
     }
 
 
@@ -466,6 +479,66 @@ def bench_testset(args, torch, synth, gn):
     }
 
 
+def bench_stdp(args, torch, synth, gn):
+    """Spike-timing-dependent plasticity on a configuration-1-sized network
+    (N = 65,536 in a 1 mm cube, ~6.7e6 edges, noise 0.05, dt 0.1 ms): every
+    step delivers with the current weights and updates every edge whose spike
+    arrives or whose target fires (per-step kernels: one wave per target row,
+    then the vertex update).  value = edge-steps/s."""
+    import numpy as np
+    spec = synth.plastic(synth.config1(n=args.stdp_n))
+    E = spec.n_edges
+    net = gn.Net(spec)
+    net.step(args.preroll)
+    torch.cuda.synchronize()
+    w0 = net.observe(gn.NET_OBS_WEIGHTS).cpu().numpy()
+    net.timing_begin(2 * args.steps + 4, every=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net.step(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = net.timing_end()
+    w1 = net.observe(gn.NET_OBS_WEIGHTS).cpu().numpy()
+    rate = arrivals_per_step(net, spec, args.rate_steps)
+    net.close()
+    deliver_s = tm["deliver_ms"] / tm["deliver_launches"] / 1e3
+    alg = 9.0 * E + 18.0 * spec.n
+    log("stdp: %d steps in %.3f s; plastic delivery %.1f us, update %.1f us per step; %.0f arrivals per step"
+        % (args.steps, wall, deliver_s * 1e6, tm["update_ms"] / tm["update_launches"] * 1e3, rate))
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        o = oracle.OracleNet(spec)
+        t1 = time.perf_counter()
+        o.step(args.cpu_steps, raster=False)
+        dt = time.perf_counter() - t1
+        o.close()
+        cpu = {"value": E * args.cpu_steps / dt, "unit": "edge-steps/s", "cores": 1, "kind": "oracle",
+               "host_cpu": host_cpu(), "sample": "the same plastic network, first %d steps, single-threaded FP64 "
+               "oracle (event-driven delivery, updates on arrivals and post spikes); %.1f s" % (args.cpu_steps, dt)}
+    return {
+        "metric": "edge-steps/s",
+        "value": E * args.steps / wall,
+        "unit": "edge-steps/s (plastic weights)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.preroll, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (state), int32 x 2^-20 (plastic weights), f64 (plasticity increments)",
+        "data": "synthetic",
+        "config": {"workload": "LIF network with STDP, N=%d in a 1 mm cube, %d edges, alpha %.4g/ms, beta %.3g/ms, "
+                               "noise 0.05, dt 0.1 ms" % (spec.n, E, spec.stdp_alpha, spec.stdp_beta),
+                   "n_vertices": spec.n, "n_edges": E},
+        "weights_moved_fraction": float(np.mean(w1 != w0)),
+        "roofline": {"bound": "hbm", "kernel": "plastic_deliver_kernel",
+                     "achieved": alg / deliver_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg / deliver_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_rule": "9 B per edge (source, delay and the plastic weight read every step) + 18 B per "
+                                   "vertex; weight writes only for updated edges",
+                     "avg_launch_us": deliver_s * 1e6, "arrivals_per_step": rate},
+        "cpu_baseline": cpu,
+    }
+
+
 def testset_cpu_baseline(specs, steps, sample_steps=1000):
     """The FP64 oracle, single-threaded, on every test network for
     sample_steps steps: the real-time factor of each, as the paper's CPU
@@ -500,23 +573,36 @@ def bench_estimate(args, torch, synth):
     import numpy as np
     from paper_0908_3934_amd import estimate as est
     t0 = time.perf_counter()
-    train, feats = [], []
+    w0 = args.w0
+    feats, labels = [], []
+    n_train = 0
     batch = 256                                       # one ensemble launch fills the 256 CUs
+    gsel = torch.Generator(device="cpu").manual_seed(12345)
     for b in range(0, args.train_nets, batch):
-        obs = est.observe([synth.config4_net(m) for m in range(b, min(args.train_nets, b + batch))], args.obs_steps)
+        obs = est.observe([synth.config4_net(m, w0=w0, inhibitory=args.inhibitory, g_inh=args.g_inh) for m in range(b, min(args.train_nets, b + batch))],
+                          args.obs_steps)
         for o in obs:
-            feats.append(est.features(o))
-            o.F = None                                  # keep features, free the traces
-        train += obs
-        log("training data: %d networks simulated and featurised (%.1f s)" % (len(train), time.perf_counter() - t0))
-    n_pairs = sum(len(o.labels) for o in train)
+            f = est.features(o)
+            lab = o.labels
+            if args.pairs_per_net and f.shape[0] > args.pairs_per_net:
+                # a uniform sample of the network's candidate pairs (training data only)
+                idx = torch.randperm(f.shape[0], generator=gsel)[:args.pairs_per_net]
+                f = f[idx.to(f.device)].contiguous()
+                lab = lab[idx.numpy()]
+            feats.append(f)
+            labels.append(lab)
+        n_train += len(obs)
+        del obs
+        log("training data: %d networks simulated and featurised (%.1f s)" % (n_train, time.perf_counter() - t0))
+    sim_train_s = time.perf_counter() - t0
+    n_pairs = sum(len(l) for l in labels)
     t1 = time.perf_counter()
-    sc = est.EdgeScorer(seed=0).fit(train, epochs=args.epochs, batch=16384, lr=1e-3, feats=feats)
+    sc = est.EdgeScorer(seed=0).fit([], epochs=args.epochs, batch=16384, lr=1e-3, feats=feats, labels=labels)
     torch.cuda.synchronize()
     fit_s = time.perf_counter() - t1
     log("scorer trained on %d pairs in %.2f s (loss history %s)" % (n_pairs, fit_s, ["%.3f" % h for h in sc.history]))
     del feats
-    test = est.observe([synth.config4_net(90000 + m) for m in range(args.test_nets)], args.obs_steps)
+    test = est.observe([synth.config4_net(90000 + m, w0=w0, inhibitory=args.inhibitory, g_inh=args.g_inh) for m in range(args.test_nets)], args.obs_steps)
     S, F, C, Y = [], [], [], []
     t_sc = t_sf = 0.0
     for k, o in enumerate(test):
@@ -525,7 +611,10 @@ def bench_estimate(args, torch, synth):
         s_sc = est.scorer_scores(o, sc)
         torch.cuda.synchronize()
         b = time.perf_counter()
-        s_sf = est.simfit(o, w_assumed=synth.W0, realisations=args.fit_realisations, sweeps=args.fit_sweeps)
+        # the fit assumes w0 out of every source, -g_inh * w0 out of the
+        # inhibitory ones (cell types known) when the networks have them
+        ws = est.source_weights(o.spec, w0, args.g_inh) if args.inhibitory > 0 else None
+        s_sf = est.simfit(o, w_assumed=w0, w_source=ws, realisations=args.fit_realisations, sweeps=args.fit_sweeps)
         torch.cuda.synchronize()
         c = time.perf_counter()
         t_sc += b - a
@@ -556,8 +645,14 @@ def bench_estimate(args, torch, synth):
         "data": "synthetic",
         "config": {
             "workload": "%d training and %d held-out LIF networks of 1024 vertices (1 mm square, p = 0.3 "
-                        "within 150 um, 10 %% driven, noise 0.05), %d frames at 30 Hz, SNR 5, candidates "
-                        "< 150 um" % (args.train_nets, args.test_nets, nf),
+                        "within 150 um, weights U[0.5,1.5] x %.3g%s, 10 %% driven, noise 0.05), %d frames at 30 Hz, "
+                        "SNR 5, candidates < 150 um%s" % (
+                            args.train_nets, args.test_nets, w0,
+                            (", %.0f %% inhibitory sources at -%.3g x" % (100 * args.inhibitory, args.g_inh))
+                            if args.inhibitory > 0 else "", nf,
+                            (", %d training pairs sampled per network" % args.pairs_per_net) if args.pairs_per_net else ""),
+            "w0": w0, "inhibitory_fraction": args.inhibitory, "g_inh": args.g_inh,
+            "simulate_and_featurise_training_s": sim_train_s,
             "train_pairs": n_pairs,
             "test_pairs": int(Y.size),
             "positive_fraction": float(Y.mean()),
@@ -615,16 +710,27 @@ def main():
                          "iteration; 2 streams every weight, 7 B per edge)")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library time the delivery variants at build instead of --deliver-flags")
-    ap.add_argument("--workload", choices=["step", "ensemble", "estimate", "mlp", "testset"], default="step",
+    ap.add_argument("--workload", choices=["step", "ensemble", "estimate", "mlp", "testset", "stdp"], default="step",
                     help="step: the N = 2^20 network (default); ensemble: 512 uneven networks in one launch "
                          "against each network run alone; estimate: learned edge scorer against the "
                          "simulation-based fit on held-out N = 1024 networks; mlp: the edge scorer's training "
-                         "step and forward pass; testset: the paper's test networks with the Izhikevich vertex "
-                         "(real-time factors, Section 3.4)")
+                         "step and forward pass; testset: the paper's test networks with the Izhikevich or "
+                         "Hodgkin-Huxley vertex (real-time factors, Section 3.4); stdp: a 65,536-vertex network "
+                         "with plastic weights")
     ap.add_argument("--train-nets", type=int, default=256, help="estimate workload: training networks")
     ap.add_argument("--test-nets", type=int, default=16, help="estimate workload: held-out networks")
     ap.add_argument("--obs-steps", type=int, default=200000, help="estimate workload: observed steps (20 s)")
     ap.add_argument("--epochs", type=int, default=4, help="estimate workload: scorer training epochs")
+    ap.add_argument("--w0", type=float, default=None,
+                    help="estimate workload: weight scale of the observed networks (default the shared 0.05)")
+    ap.add_argument("--mlp-rows", type=int, default=65536,
+                    help="mlp workload: training batch rows per optimizer step")
+    ap.add_argument("--inhibitory", type=float, default=0.0,
+                    help="estimate workload: fraction of inhibitory sources in the observed networks")
+    ap.add_argument("--g-inh", type=float, default=1.0,
+                    help="estimate workload: inhibitory weights are -g_inh times the sampled ones")
+    ap.add_argument("--pairs-per-net", type=int, default=0,
+                    help="estimate workload: training pairs sampled per network (0 = all of them)")
     ap.add_argument("--fit-realisations", type=int, default=8, help="estimate workload: noise realisations of the fit")
     ap.add_argument("--fit-sweeps", type=int, default=2, help="estimate workload: toggle sweeps of the fit")
     ap.add_argument("--seq-sample", type=int, default=8,
@@ -637,11 +743,14 @@ def main():
                          "network's steady spike rate rather than the start from rest")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy three times (reference for HBM counters)")
+    ap.add_argument("--stdp-n", type=int, default=65536, help="stdp workload: vertices (1 mm cube at 65,536)")
     ap.add_argument("--model", choices=["izhikevich", "hh"], default="izhikevich",
                     help="testset workload: the vertex model (Izhikevich at dt = 1 ms for 10 s, or "
                          "Hodgkin-Huxley at dt = 0.03 ms for 1 s)")
     args = ap.parse_args()
     args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
+    if args.w0 is None:
+        args.w0 = 0.05
     if args.gpus != 1:
         print("bench.py measures one GPU only: the simulator is built and measured on a single "
               "MI355X; --gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -657,6 +766,9 @@ def main():
         return
     if args.workload == "estimate":
         print(json.dumps(bench_estimate(args, torch, synth)), flush=True)
+        return
+    if args.workload == "stdp":
+        print(json.dumps(bench_stdp(args, torch, synth, gn)), flush=True)
         return
     if args.workload == "testset":
         print(json.dumps(bench_testset(args, torch, synth, gn)), flush=True)

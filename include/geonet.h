@@ -133,6 +133,21 @@ typedef struct {
        PSC kinds are those of the Izhikevich vertex.  Units: mV, ms, uF/cm^2,
        mS/cm^2, uA/cm^2. */
     float hh_C, hh_gna, hh_gk, hh_gl, hh_ena, hh_ek, hh_el;
+    /* Spike-timing-dependent plasticity (Section 3.2 "Plasticity", Eqs.
+       omegatrans and Gparams), plastic != 0: with s_j the time since j's last
+       spike (s_j(t+1) = (1 - s_j(t) fired) * (s_j(t) + dt), s_j(0) = 0),
+         q_ij(t) = (s_i(t - d_ij) - s_j(t)) * max(spd_i(t - d_ij), spd_j(t))
+         w_ij(t+1) = w_ij(t) + dt * stdp_alpha * sign(q) * exp(-stdp_beta * |q|),
+       the increment rounded to a multiple of 2^-20 (weights are kept as such
+       multiples, so delivered sums stay exact in any order); a spike delivers
+       the weight its edge has when it arrives.  Needs the LIF vertex, one
+       network per handle, n_ref >= 17 (the last 16 spike times of a vertex
+       then cover the 255-step delay window) and weights that are multiples
+       of 2^-20 below 2048 after FP16 rounding; the per-step kernels are used
+       (build flags that select other kernels are ignored). */
+    int32_t plastic;
+    float stdp_alpha;             /* weight per ms */
+    float stdp_beta;              /* 1/ms */
 } net_desc;
 
 enum { NET_MODEL_LIF = 0, NET_MODEL_IZHIKEVICH = 1, NET_MODEL_HODGKIN_HUXLEY = 2 };
@@ -185,6 +200,20 @@ typedef struct {
 #define NET_BUILD_SINGLE_LAUNCH 32        /* one network: run all steps of a call in one launch of
                                              the LDS-resident kernel ensembles use, when the
                                              network fits one workgroup's LDS */
+#define NET_BUILD_REORDER 4096           /* renumber each network's vertices along a Morton (Z-order) curve
+                                             of their positions before building, so that vertices close in
+                                             space are close in memory (the gathers of delivery then meet in
+                                             cache); everything at the boundary keeps the caller's numbering:
+                                             records and read-outs are put back in it (records at some extra
+                                             cost) and random streams use the caller's vertex index */
+#define NET_BUILD_GRAPH 8192             /* run net_step_n calls without records or kernel timing as HIP
+                                             graph replays: the per-step kernels of 256 steps (a whole turn
+                                             of the history ring) captured once and replayed from steps that
+                                             are multiples of 256, the single-launch ensemble kernel captured
+                                             once per call length; the kernels then read the step from a
+                                             device counter the graph advances.  Same results; steps outside
+                                             whole 256-step blocks run as plain launches.  Not for plastic
+                                             networks (ignored). */
 #define NET_BUILD_AUTOTUNE 64             /* time the candidate launch shapes on this graph at
                                              build (a few steps from the initial state, which is
                                              then restored) and keep the fastest: delivery
@@ -259,7 +288,9 @@ enum {
     NET_OBS_REF = 2,      /* int32 [n_total]  remaining held steps */
     NET_OBS_CALCIUM = 3,  /* float [n_total]  current c */
     NET_OBS_FRAMES = 4,   /* float [F][n_total] mean c of frames 0..F-1, F = out_bytes/(4*n_total) */
-    NET_OBS_FLUOR = 5     /* float [F][n_total] n*cbar + b + gamma*xi, params = net_fluor_params */
+    NET_OBS_FLUOR = 5,    /* float [F][n_total] n*cbar + b + gamma*xi, params = net_fluor_params */
+    NET_OBS_WEIGHTS = 6   /* float [n_edges] current weights, in the order the edges were given
+                             (plastic networks only; NET_E_UNSUPPORTED otherwise) */
 };
 
 typedef struct {
@@ -377,6 +408,9 @@ typedef struct {
     /* vertex model assumed by the simulation-based fit */
     float tau_ms, v_rest, v_reset, v_th, noise_sigma, w_assumed;
     int32_t n_ref;
+    const float* w_source;       /* host [n_nodes]: the weight the fit assumes on every edge out of
+                                    vertex i (negative for an inhibitory cell, whose type the
+                                    experimenter knows), or NULL: w_assumed for every vertex */
 } net_obs_desc;
 
 /*
@@ -430,7 +464,8 @@ enum { NET_EST_SCORER = 1, NET_EST_SIMFIT = 2, NET_EST_AUTO = 3 };
  *   NET_EST_SIMFIT  simulation-based fit.  Each target j is simulated with the
  *                   vertex model of the forward path, teacher-forced by the
  *                   deconvolved activity of a hypothesised in-neighbour set G
- *                   (input w_assumed * e_i(f) spread over frame f), its own
+ *                   (input w_i * e_i(f) spread over frame f, w_i from w_source,
+ *                   else w_assumed), its own
  *                   control pulses and K noise realisations (fit_seed); the
  *                   observed trace is scored with the Gaussian observation
  *                   model using the realisations' mean and variance.  G starts

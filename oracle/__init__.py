@@ -82,6 +82,10 @@ def _load():
         L.orc_set_hodgkin_huxley.restype = _c.c_int32
         L.orc_get_hh.argtypes = [_vp, _vp, _vp, _vp]
         L.orc_get_hh.restype = None
+        L.orc_set_stdp.argtypes = [_vp, _c.c_double, _c.c_double]
+        L.orc_set_stdp.restype = _c.c_int32
+        L.orc_get_weights.argtypes = [_vp, _vp, _vp, _c.c_int64, _vp]
+        L.orc_get_weights.restype = None
         L.orc_set_threads.argtypes = [_c.c_int32]
         L.orc_set_threads.restype = None
         L.orc_get_threads.argtypes = []
@@ -183,7 +187,13 @@ class OracleNet:
             w0 = arr(getattr(spec, "w0_iz", None), np.float32)
             if L.orc_set_izhikevich(self.h, int(spec.psc), iz.ctypes.data, float(spec.psc_rate), _ptr(w0)) != 0:
                 raise ValueError("oracle rejected the Izhikevich parameters")
-        elif self.model == 2:
+        if getattr(spec, "plastic", 0):
+            a_, b_ = float(spec.stdp_alpha), float(spec.stdp_beta)
+            if float(np.float32(a_)) != a_ or float(np.float32(b_)) != b_:
+                raise ValueError("STDP rates must be FP32 values (the library takes them as FP32)")
+            if L.orc_set_stdp(self.h, a_, b_) != 0:
+                raise ValueError("oracle rejected STDP (LIF only, weights multiples of 2^-20)")
+        if self.model == 2:
             hh = np.array([spec.hh_C, spec.hh_gna, spec.hh_gk, spec.hh_gl, spec.hh_ena, spec.hh_ek, spec.hh_el],
                           dtype=np.float64)
             if not np.array_equal(hh.astype(np.float32).astype(np.float64), hh) or \
@@ -239,6 +249,14 @@ class OracleNet:
         W, r, p = (np.zeros(self.n, dtype=np.float64) for _ in range(3))
         self._L.orc_get_izh(self.h, W.ctypes.data, r.ctypes.data, p.ctypes.data)
         return W, r, p
+
+    def weights(self, src, dst) -> np.ndarray:
+        """Current weight of each edge (src[e] -> dst[e])."""
+        a = np.ascontiguousarray(src, dtype=np.int32)
+        b = np.ascontiguousarray(dst, dtype=np.int32)
+        out = np.zeros(a.shape[0], dtype=np.float64)
+        self._L.orc_get_weights(self.h, a.ctypes.data, b.ctypes.data, a.shape[0], out.ctypes.data)
+        return out
 
     def gates(self):
         """(m, n, h) of every vertex (Hodgkin-Huxley networks)."""

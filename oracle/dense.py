@@ -47,7 +47,7 @@ def simulate(n: int, edges: Sequence, steps: int, *, dt: float = 0.1, tau: float
              drive_thr: Optional[Sequence[int]] = None, drive_amp: float = 1.5,
              i_ext: Optional[Sequence[float]] = None, sigma: float = 0.0, seed: int = 0,
              v0: Optional[Sequence[float]] = None, izhikevich: Optional[dict] = None,
-             hodgkin_huxley: Optional[dict] = None) -> Dict[str, list]:
+             hodgkin_huxley: Optional[dict] = None, stdp: Optional[dict] = None) -> Dict[str, list]:
     """edges: iterable of (src, dst, weight, delay_steps).
 
     izhikevich: None for the LIF vertex, else a dict with C, k, vr, vt, a,
@@ -58,7 +58,13 @@ def simulate(n: int, edges: Sequence, steps: int, *, dt: float = 0.1, tau: float
     hodgkin_huxley: None, or a dict with C, gna, gk, gl, ena, ek, el, psc,
     psc_a: the four-state vertex of Section 3.1 with the standard rate
     functions (written below independently of oracle.c), spikes signalled on
-    the upward crossing of v_th, gates starting at their steady state."""
+    the upward crossing of v_th, gates starting at their steady state.
+
+    stdp: None, or a dict with alpha, beta: the weights evolve by the
+    plasticity rule of Section 3.2, evaluated from the full spike history
+    (the time since the last spike read off the history matrix), each
+    increment rounded to a multiple of 2^-20; the records then also hold the
+    weight matrix after the run ("w_final")."""
     assert n <= 8, "brute force is for tiny networks"
     W = [[0.0] * n for _ in range(n)]
     A = [[False] * n for _ in range(n)]
@@ -99,6 +105,27 @@ def simulate(n: int, edges: Sequence, steps: int, *, dt: float = 0.1, tau: float
                     tot += W[k][j]
             I.append(tot)
         rec_i.append(I)
+        if stdp is not None:
+            def since(k, u):
+                # time since k's last spike strictly before step u
+                if u <= 0:
+                    return 0.0
+                for v in range(u - 1, -1, -1):
+                    if hist[v][k]:
+                        return (u - v - 1) * dt
+                return u * dt
+            for k in range(n):
+                for j in range(n):
+                    if k == j or not A[k][j]:
+                        continue
+                    u = t - D[k][j]
+                    pre = u >= 0 and hist[u][k]
+                    if not (pre or s[j]):
+                        continue
+                    q = since(k, u) - since(j, t)
+                    sg = 1.0 if q > 0 else (-1.0 if q < 0 else 0.0)
+                    dw = dt * stdp["alpha"] * sg * math.exp(-stdp["beta"] * abs(q))
+                    W[k][j] = (round(W[k][j] * 1048576.0) + int(round(dw * 1048576.0))) / 1048576.0
         newV = list(V)
         if iz is not None:
             rec_w.append(list(Wr))
@@ -144,7 +171,7 @@ def simulate(n: int, edges: Sequence, steps: int, *, dt: float = 0.1, tau: float
             xi = gauss(r[1], r[2])
             newV[j] = V[j] + (dt / tau) * (v_rest - V[j]) + I[j] + u + sigma * xi
         V = newV
-    out = {"raster": rec_s, "v": rec_v, "input": rec_i, "v_final": V}
+    out = {"raster": rec_s, "v": rec_v, "input": rec_i, "v_final": V, "w_final": W}
     if iz is not None:
         out.update(w=rec_w, r=rec_r, p=rec_p)
     return out

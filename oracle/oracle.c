@@ -68,6 +68,22 @@
  *       an action potential; there is no reset.
  * HH state is FP64 here and in the library.
  *
+ * Spike-timing-dependent plasticity (Section 3.2, "Plasticity"; Eqs.
+ * omegatrans and Gparams), switched on per network by orc_set_stdp:
+ *   s_j, the time since j's last spike: s_j(t+1) = (1 - spd(V_j(t))) (s_j(t) + dt),
+ *       s_j(0) = 0, so s_j(u) = (u - t_last - 1) dt with t_last j's last
+ *       spike before step u (u dt without one; 0 for u <= 0);
+ *   q_ij(t) = (s_i(t - d_ij) - s_j(t)) * max(spd(V_i(t - d_ij)), spd(V_j(t)));
+ *   w_ij(t+1) = w_ij(t) + dt * alpha * sign(q) * exp(-beta |q|).
+ *   R21 weights are kept as integer multiples of Q = 2^-20 (the initial FP16
+ *       weights are such multiples); every increment is rounded to the
+ *       nearest multiple (ties to even) before it is added, so every sum of
+ *       weights is exact and the delivered input does not depend on the
+ *       order of additions.  A spike delivered at step t carries w(t), the
+ *       weight at its arrival; the update of step t follows the delivery.
+ * Delivery of a plastic network keeps per ring slot the list of edges whose
+ * spike arrives then (instead of a sum of weights).
+ *
  * Delivery here is event-driven: when vertex i fires at step t its weights
  * are pushed into a per-target inbox slot (t + d) mod 256.  This is a
  * different formulation from a pull over in-edges, on purpose.
@@ -197,7 +213,23 @@ typedef struct {
     double hh_C, hh_gna, hh_gk, hh_gl, hh_ena, hh_ek, hh_el;
     double *hm, *hn, *hh;   /* [n] gating variables */
     double* vprev;          /* [n] V(t-1) for the crossing test */
+    /* STDP */
+    int32_t plastic;
+    double stdp_alpha, stdp_beta;
+    int64_t n_edges;
+    int64_t* wq;            /* [E] weight of out-edge o, in units of 2^-20 */
+    int64_t* stamp;         /* [E] last step at which out-edge o was updated */
+    int64_t* in_start;      /* [n+1] in-edges of each target ... */
+    int64_t* in_list;       /* [E]   ... as out-edge indices */
+    int32_t* out_src;       /* [E] source of out-edge o */
+    int64_t* arr[ORC_RING]; /* out-edges whose spike arrives at slot k */
+    int64_t arr_cnt[ORC_RING], arr_cap[ORC_RING];
+    int64_t** spk;          /* [n] spike steps of each vertex (all of them) */
+    int64_t *spk_cnt, *spk_cap;
+    int64_t* qin;           /* [n] delivered sum of this step in units of 2^-20 */
 } orc_net;
+
+#define ORC_WQ 1048576.0   /* 1 / Q, Q = 2^-20 */
 
 static void* xcalloc(size_t n, size_t s) {
     void* p = calloc(n ? n : 1, s);
@@ -221,6 +253,7 @@ void* orc_create(int32_t n, int32_t dims, const double* pos, int64_t n_edges,
     if (n <= 0 || n_edges < 0 || dt_ms <= 0.0) return NULL;
     orc_net* h = (orc_net*)xcalloc(1, sizeof(orc_net));
     h->n = n;
+    h->n_edges = n_edges;
     h->out_start = (int64_t*)xcalloc((size_t)n + 1, sizeof(int64_t));
     h->out_dst = (int32_t*)xcalloc((size_t)n_edges, sizeof(int32_t));
     h->out_w = (double*)xcalloc((size_t)n_edges, sizeof(double));
@@ -373,6 +406,91 @@ void orc_get_hh(void* ph, double* m, double* n, double* hg) {
     if (hg) memcpy(hg, h->hh, (size_t)h->n * sizeof(double));
 }
 
+static void push_i64(int64_t** a, int64_t* cnt, int64_t* cap, int64_t v) {
+    if (*cnt == *cap) {
+        *cap = *cap ? 2 * *cap : 16;
+        *a = (int64_t*)realloc(*a, (size_t)*cap * sizeof(int64_t));
+    }
+    (*a)[(*cnt)++] = v;
+}
+
+/*
+ * Make the network's weights plastic (STDP above) with rates alpha (weight
+ * per ms) and beta (1/ms).  Needs the LIF vertex, no step taken yet, and
+ * every weight an integer multiple of 2^-20 below 2048 in magnitude.
+ * Returns 0 or -1.
+ */
+int32_t orc_set_stdp(void* ph, double alpha, double beta) {
+    orc_net* h = (orc_net*)ph;
+    if (!h || h->model != 0 || h->t != 0) return -1;
+    const int64_t E = h->n_edges;
+    h->wq = (int64_t*)xcalloc((size_t)E, sizeof(int64_t));
+    h->stamp = (int64_t*)xcalloc((size_t)E, sizeof(int64_t));
+    for (int64_t o = 0; o < E; ++o) {
+        const double k = h->out_w[o] * ORC_WQ;
+        if (!(fabs(h->out_w[o]) < 2048.0) || k != floor(k)) return -1;
+        h->wq[o] = (int64_t)k;
+        h->stamp[o] = -1;
+    }
+    h->out_src = (int32_t*)xcalloc((size_t)E, sizeof(int32_t));
+    for (int32_t i = 0; i < h->n; ++i)
+        for (int64_t o = h->out_start[i]; o < h->out_start[i + 1]; ++o) h->out_src[o] = i;
+    h->in_start = (int64_t*)xcalloc((size_t)h->n + 1, sizeof(int64_t));
+    h->in_list = (int64_t*)xcalloc((size_t)E, sizeof(int64_t));
+    for (int64_t o = 0; o < E; ++o) h->in_start[h->out_dst[o] + 1]++;
+    for (int32_t j = 0; j < h->n; ++j) h->in_start[j + 1] += h->in_start[j];
+    {
+        int64_t* fill = (int64_t*)xcalloc((size_t)h->n, sizeof(int64_t));
+        for (int32_t j = 0; j < h->n; ++j) fill[j] = h->in_start[j];
+        for (int64_t o = 0; o < E; ++o) h->in_list[fill[h->out_dst[o]]++] = o;
+        free(fill);
+    }
+    h->spk = (int64_t**)xcalloc((size_t)h->n, sizeof(int64_t*));
+    h->spk_cnt = (int64_t*)xcalloc((size_t)h->n, sizeof(int64_t));
+    h->spk_cap = (int64_t*)xcalloc((size_t)h->n, sizeof(int64_t));
+    h->qin = (int64_t*)xcalloc((size_t)h->n, sizeof(int64_t));
+    h->stdp_alpha = alpha;
+    h->stdp_beta = beta;
+    h->plastic = 1;
+    return 0;
+}
+
+/* s_i(u): time since i's last spike before step u (see the header). */
+static double stdp_s(const orc_net* h, int32_t i, int64_t u) {
+    if (u <= 0) return 0.0;
+    const int64_t* a = h->spk[i];
+    int64_t lo = 0, hi = h->spk_cnt[i];          /* first index with a[k] >= u */
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (a[mid] < u) lo = mid + 1; else hi = mid;
+    }
+    if (lo == 0) return (double)u * h->dt;
+    return (double)(u - a[lo - 1] - 1) * h->dt;
+}
+
+/* The STDP update of out-edge o at step t (q as in the header). */
+static void stdp_update(orc_net* h, int64_t o, int32_t i, int64_t t) {
+    const int32_t j = h->out_dst[o];
+    const double q = stdp_s(h, i, t - h->out_d[o]) - stdp_s(h, j, t);
+    const double sg = q > 0.0 ? 1.0 : (q < 0.0 ? -1.0 : 0.0);
+    const double dw = h->dt * h->stdp_alpha * sg * exp(-h->stdp_beta * fabs(q));
+    h->wq[o] += (int64_t)nearbyint(dw * ORC_WQ);
+    h->stamp[o] = t;
+}
+
+/* Current weights of the edges (src[e] -> dst[e]) (plastic networks). */
+void orc_get_weights(void* ph, const int32_t* src, const int32_t* dst, int64_t m, double* out) {
+    orc_net* h = (orc_net*)ph;
+    for (int64_t e = 0; e < m; ++e) {
+        out[e] = 0.0;
+        for (int64_t o = h->out_start[src[e]]; o < h->out_start[src[e] + 1]; ++o)
+            if (h->out_dst[o] == dst[e]) {
+                out[e] = h->plastic ? (double)h->wq[o] / ORC_WQ : h->out_w[o];
+                break;
+            }
+    }
+}
+
 void orc_get_izh(void* ph, double* W, double* r, double* p) {
     orc_net* h = (orc_net*)ph;
     if (!h->W) return;
@@ -391,6 +509,19 @@ void orc_free(void* p) {
     free(h->hn);
     free(h->hh);
     free(h->vprev);
+    if (h->plastic) {
+        for (int k = 0; k < ORC_RING; ++k) free(h->arr[k]);
+        for (int32_t j = 0; j < h->n; ++j) free(h->spk[j]);
+        free(h->spk);
+        free(h->spk_cnt);
+        free(h->spk_cap);
+        free(h->qin);
+        free(h->in_start);
+        free(h->in_list);
+        free(h->out_src);
+    }
+    free(h->wq);
+    free(h->stamp);
     free(h->out_start);
     free(h->out_dst);
     free(h->out_w);
@@ -444,6 +575,41 @@ void orc_step_n(void* p, int64_t n_steps, uint8_t* raster, double* v_rec, double
             if (raster) raster[k * n + j] = s[j];
             if (v_rec) v_rec[k * n + j] = h->V[j];
         }
+        if (h->plastic) {
+            /* arrivals of step t, with the weights they carry now */
+            int64_t* list = h->arr[slot];
+            const int64_t cnt = h->arr_cnt[slot];
+            for (int64_t a = 0; a < cnt; ++a) h->qin[h->out_dst[list[a]]] += h->wq[list[a]];
+            for (int32_t j = 0; j < n; ++j) {
+                h->inbox[(int64_t)j * ORC_RING + slot] = (double)h->qin[j] / ORC_WQ;
+                h->qin[j] = 0;
+            }
+            /* the update of step t: every edge whose spike arrives now, and every
+               in-edge of a vertex that fires now (once per edge) */
+            for (int64_t a = 0; a < cnt; ++a) {
+                const int64_t o = list[a];
+                if (h->stamp[o] != t) stdp_update(h, o, h->out_src[o], t);
+            }
+            h->arr_cnt[slot] = 0;
+            for (int32_t j = 0; j < n; ++j) {
+                if (!s[j]) continue;
+                for (int64_t k2 = h->in_start[j]; k2 < h->in_start[j + 1]; ++k2) {
+                    const int64_t o = h->in_list[k2];
+                    if (h->stamp[o] == t) continue;
+                    stdp_update(h, o, h->out_src[o], t);
+                }
+            }
+            /* this step's spikes: queued for their arrival steps, and recorded */
+            for (int32_t i = 0; i < n; ++i) {
+                if (!s[i]) continue;
+                for (int64_t o = h->out_start[i]; o < h->out_start[i + 1]; ++o) {
+                    const int dslot = (int)((t + h->out_d[o]) % ORC_RING);
+                    push_i64(&h->arr[dslot], &h->arr_cnt[dslot], &h->arr_cap[dslot], o);
+                    h->delivered++;
+                }
+                push_i64(&h->spk[i], &h->spk_cnt[i], &h->spk_cap[i], t);
+            }
+        } else {
         /* Push this step's spikes to their targets' future inbox slots. */
         for (int32_t i = 0; i < n; ++i) {
             if (!s[i]) continue;
@@ -452,6 +618,7 @@ void orc_step_n(void* p, int64_t n_steps, uint8_t* raster, double* v_rec, double
                 h->inbox[(int64_t)h->out_dst[o] * ORC_RING + dslot] += h->out_w[o];
                 h->delivered++;
             }
+        }
         }
         /* Camera integration: accumulate c_j(t) into the current frame. */
         int64_t f_now = (t * h->frame_num) / h->frame_den;

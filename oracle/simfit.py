@@ -10,7 +10,9 @@ is defined here, in the steps the GPU path follows:
 3. a hypothesis (j, G) is scored by simulating vertex j (LIF Euler step with
    refractory hold, its control pulses, K realisations of state noise from
    the fit's own Philox key, calcium transition), teacher-forced by the input
-   w * sum_{i in G} e_i(f) / S(f) in every step of frame f, and taking the
+   sum_{i in G} w_i e_i(f) / S(f) in every step of frame f (w_i the weight
+   assumed on the edges out of i: one value for all, or negative for the
+   inhibitory cells of a network whose cell types are known), and taking the
    Gaussian log-likelihood of the observed trace with the realisations'
    frame-mean calcium mean and variance;
 4. each sweep evaluates every single toggle and, per target, applies the
@@ -100,7 +102,8 @@ def loglik(cbar, Fj, gain, offset, gamma):
 def fit(F, pairs, *, drive_thr, control_seed, gain, offset, gamma, dt, tau, v_rest, v_reset, v_th, n_ref, sigma,
         drive_amp, tau_c, frame_num, frame_den, w, K=8, sweeps=2, init_fraction=0.3, fit_seed=0x5EEDF17,
         min_gain=1e-3):
-    """Scores LL(G + e) - LL(G - e) per pair (in the given order)."""
+    """Scores LL(G + e) - LL(G - e) per pair (in the given order); w is one
+    weight for every source or a length-n array of per-source weights."""
     F = np.asarray(F, dtype=np.float64)
     nf, n = F.shape
     pairs = np.asarray(pairs, dtype=np.int64)
@@ -117,6 +120,7 @@ def fit(F, pairs, *, drive_thr, control_seed, gain, offset, gamma, dt, tau, v_re
             x0 = FE.philox_np(np.uint64(j), tt & np.uint64(0xFFFFFFFF), tt >> np.uint64(32), np.uint64(0),
                               control_seed & 0xFFFFFFFF, control_seed >> 32)[0]
             pulses[j] = x0 < np.uint64(drive_thr[j])
+    wv = np.broadcast_to(np.asarray(w, dtype=np.float64), (n,))
     first = (np.arange(nf + 1) * frame_den + frame_num - 1) // frame_num
     steps = np.diff(first).astype(np.float64)
     targets = pairs[:, 1]
@@ -125,10 +129,10 @@ def fit(F, pairs, *, drive_thr, control_seed, gain, offset, gamma, dt, tau, v_re
     for sw in range(sweeps + 1):
         base = np.zeros((n, nf))
         for p in np.nonzero(member)[0]:
-            base[targets[p]] += e[pairs[p, 0]]
-        base = w * base / steps
-        u = np.concatenate([base[targets] + np.where(member, -1.0, 1.0)[:, None] * w * e[pairs[:, 0]] / steps,
-                            base])
+            base[targets[p]] += wv[pairs[p, 0]] * e[pairs[p, 0]]
+        base = base / steps
+        toggle = np.where(member, -1.0, 1.0) * wv[pairs[:, 0]]
+        u = np.concatenate([base[targets] + toggle[:, None] * e[pairs[:, 0]] / steps, base])
         cb = simulate_hypotheses(j_of, u, pulses, K=K, frame_num=frame_num, frame_den=frame_den, nf=nf, dt=dt,
                                  tau=tau, v_rest=v_rest, v_reset=v_reset, v_th=v_th, n_ref=n_ref, sigma=sigma,
                                  drive_amp=drive_amp, tau_c=tau_c, fit_seed=fit_seed)

@@ -18,16 +18,17 @@ import numpy as np
 from . import _abi
 from ._abi import (NET_BUILD_AUTOTUNE, NET_BUILD_DELIVER_NONTEMPORAL, NET_BUILD_DELIVER_PIPELINE,
                    NET_BUILD_DELIVER_STREAM_WEIGHTS, NET_BUILD_SUMMARY_HALF, NET_BUILD_DELIVER_COMPACT, NET_BUILD_FUSED_STEP,
-                   NET_BUILD_DELIVER_PACKED,
+                   NET_BUILD_DELIVER_PACKED, NET_BUILD_REORDER, NET_BUILD_GRAPH,
                    NET_BUILD_DELIVER_UNROLL2, NET_BUILD_NO_LDS_SUMMARY, NET_BUILD_PER_STEP, NET_BUILD_SINGLE_LAUNCH,
-                   NET_OBS_CALCIUM, NET_OBS_FLUOR, NET_OBS_FRAMES, NET_OBS_REF,
+                   NET_OBS_CALCIUM, NET_OBS_FLUOR, NET_OBS_FRAMES, NET_OBS_REF, NET_OBS_WEIGHTS,
                    NET_OBS_V, NET_OK, NET_W_INEXACT)
 
 __all__ = ["Net", "Mlp", "GeonetError", "NET_OBS_V", "NET_OBS_REF", "NET_OBS_CALCIUM", "NET_OBS_FRAMES",
-           "NET_OBS_FLUOR", "NET_BUILD_NO_LDS_SUMMARY", "NET_BUILD_DELIVER_STREAM_WEIGHTS",
+           "NET_OBS_FLUOR", "NET_OBS_WEIGHTS", "NET_BUILD_NO_LDS_SUMMARY", "NET_BUILD_DELIVER_STREAM_WEIGHTS",
            "NET_BUILD_DELIVER_NONTEMPORAL", "NET_BUILD_DELIVER_UNROLL2", "NET_BUILD_PER_STEP",
            "NET_BUILD_SINGLE_LAUNCH", "NET_BUILD_AUTOTUNE", "NET_BUILD_DELIVER_PIPELINE",
            "NET_BUILD_SUMMARY_HALF", "NET_BUILD_DELIVER_COMPACT", "NET_BUILD_FUSED_STEP", "NET_BUILD_DELIVER_PACKED",
+           "NET_BUILD_REORDER", "NET_BUILD_GRAPH",
            "library"]
 
 
@@ -138,6 +139,9 @@ class Net:
             d.tau_c_ms = s.tau_c_ms
             d.frame_num = s.frame_num
             d.frame_den = s.frame_den
+            if getattr(s, "plastic", 0):
+                d.plastic = 1
+                d.stdp_alpha, d.stdp_beta = s.stdp_alpha, s.stdp_beta
             d.model = getattr(s, "model", 0)
             if d.model == _abi.NET_MODEL_HODGKIN_HUXLEY:
                 d.hh_C, d.hh_gna, d.hh_gk, d.hh_gl = s.hh_C, s.hh_gna, s.hh_gk, s.hh_gl
@@ -227,6 +231,8 @@ class Net:
             out = torch.empty((frames, self.n_total), dtype=torch.float32, device=dev)
         elif what == NET_OBS_REF:
             out = torch.empty(self.n_total, dtype=torch.int32, device=dev)
+        elif what == NET_OBS_WEIGHTS:
+            out = torch.empty(max(self.info()["n_edges"], 1), dtype=torch.float32, device=dev)
         else:
             out = torch.empty(self.n_total, dtype=torch.float32, device=dev)
         params = None

@@ -28,6 +28,8 @@ NET_BUILD_DELIVER_COMPACT = 512
 NET_BUILD_FUSED_STEP = 1024
 NET_BUILD_DELIVER_PACKED = 2048
 NET_BUILD_AUTOTUNE = 64
+NET_BUILD_REORDER = 4096
+NET_BUILD_GRAPH = 8192
 
 NET_MODEL_LIF = 0
 NET_MODEL_IZHIKEVICH = 1
@@ -41,6 +43,7 @@ NET_OBS_REF = 2
 NET_OBS_CALCIUM = 3
 NET_OBS_FRAMES = 4
 NET_OBS_FLUOR = 5
+NET_OBS_WEIGHTS = 6
 
 _vp = C.c_void_p
 
@@ -58,6 +61,7 @@ class NetDesc(C.Structure):
         ("iz_b", C.c_float), ("iz_d", C.c_float), ("psc_rate", C.c_float), ("w0", _vp),
         ("hh_C", C.c_float), ("hh_gna", C.c_float), ("hh_gk", C.c_float), ("hh_gl", C.c_float),
         ("hh_ena", C.c_float), ("hh_ek", C.c_float), ("hh_el", C.c_float),
+        ("plastic", C.c_int32), ("stdp_alpha", C.c_float), ("stdp_beta", C.c_float),
     ]
 
 
@@ -99,7 +103,7 @@ class ObsDesc(C.Structure):
         ("dt_ms", C.c_double), ("tau_c_ms", C.c_float), ("frame_num", C.c_int32), ("frame_den", C.c_int32),
         ("drive_rate_hz", _vp), ("drive_amp", C.c_float), ("control_seed", C.c_uint64),
         ("tau_ms", C.c_float), ("v_rest", C.c_float), ("v_reset", C.c_float), ("v_th", C.c_float),
-        ("noise_sigma", C.c_float), ("w_assumed", C.c_float), ("n_ref", C.c_int32),
+        ("noise_sigma", C.c_float), ("w_assumed", C.c_float), ("n_ref", C.c_int32), ("w_source", _vp),
     ]
 
 

@@ -35,7 +35,19 @@ struct net {
     int64_t t_seen[4] = {0, 0, 0, 0};
     EnsemblePlan plan;
     bool autotuned = false;
+    // graph replays (NET_BUILD_GRAPH): device step counter, a private capture
+    // stream, the 256-step graph of the per-step kernels and the ensemble
+    // graphs by chunk length
+    bool graph = false;
+    uint64_t* t_dev = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t step_graph = nullptr;
+    std::vector<std::pair<int32_t, hipGraphExec_t>> ens_graphs;
 };
+
+namespace {
+constexpr int32_t kGraphSteps = 256;   // one replay: a whole turn of the history ring, an even number of steps
+}
 
 namespace {
 
@@ -229,6 +241,166 @@ bool load_plan(net* h, const HostGraph& hg, int n_cu, int per_cu, int threads, b
     return enable_ensemble_lds(lds_max) == hipSuccess;
 }
 
+// Graph replays: the executable graph of a captured launch sequence.
+// `body` enqueues the launches on the capture stream; the counter is then
+// advanced by `advance` steps inside the graph.
+template <typename F>
+hipError_t capture_graph(net* h, F body, uint64_t advance, hipGraphExec_t* out) {
+    hipError_t e = hipSuccess;
+    if (!h->cap_stream) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t eb = body(h->cap_stream);
+    if (eb == hipSuccess) eb = launch_advance_counter(h->t_dev, advance, h->cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(h->cap_stream, &g);
+    if (eb != hipSuccess) e = eb;
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
+// The 256-step graph of the per-step kernels, from a step t with t % 256 == 0.
+hipError_t step_graph(net* h, hipGraphExec_t* out) {
+    if (h->step_graph) {
+        *out = h->step_graph;
+        return hipSuccess;
+    }
+    DeviceGraph gc = h->g;
+    gc.t_dev = h->t_dev;
+    const LaunchConfig lc = h->lc;
+    auto body = [&](hipStream_t cs) -> hipError_t {
+        for (int32_t k = 0; k < kGraphSteps; ++k) {
+            hipError_t e;
+            if (lc.fused) {
+                e = launch_step(gc, lc, k, 0, nullptr, 0, 0, 0, cs);
+                std::swap(gc.age, gc.age_alt);
+                std::swap(gc.summary, gc.summary_alt);
+            } else {
+                e = launch_deliver(gc, lc, k, cs);
+                if (e == hipSuccess) e = launch_node_update(gc, k, 0, nullptr, 0, 0, 0, cs);
+            }
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    hipError_t e = capture_graph(h, body, kGraphSteps, &h->step_graph);
+    *out = h->step_graph;
+    return e;
+}
+
+hipError_t ensemble_graph(net* h, int32_t n_steps, hipGraphExec_t* out) {
+    for (auto& p : h->ens_graphs)
+        if (p.first == n_steps) {
+            *out = p.second;
+            return hipSuccess;
+        }
+    DeviceGraph gc = h->g;
+    gc.t_dev = h->t_dev;
+    hipGraphExec_t ex = nullptr;
+    auto body = [&](hipStream_t cs) -> hipError_t {
+        return launch_ensemble(gc, h->plan, 0, n_steps, nullptr, h->frame_num, h->frame_den, cs);
+    };
+    hipError_t e = capture_graph(h, body, static_cast<uint64_t>(n_steps), &ex);
+    if (e != hipSuccess) return e;
+    if (h->ens_graphs.size() >= 8) {            // keep a few lengths
+        (void)hipGraphExecDestroy(h->ens_graphs.front().second);
+        h->ens_graphs.erase(h->ens_graphs.begin());
+    }
+    h->ens_graphs.push_back({n_steps, ex});
+    *out = ex;
+    return hipSuccess;
+}
+
+// Host-side frame bookkeeping of steps t0 .. t0 + n - 1 run by a graph.
+void advance_frames(net* h, int64_t t0, int64_t n) {
+    if (!(h->g.frame_cap > 0 && h->frame_num > 0)) return;
+    for (int64_t t = t0; t < t0 + n; ++t) {
+        const int64_t frame = t * h->frame_num / h->frame_den;
+        const int64_t next = (t + 1) * h->frame_num / h->frame_den;
+        h->acc_steps += 1;
+        if (next != frame) {
+            h->acc_steps = 0;
+            h->frames_done = std::max(h->frames_done, frame + 1);
+        }
+    }
+}
+
+void release_graphs(net* h) {
+    if (h->step_graph) (void)hipGraphExecDestroy(h->step_graph);
+    h->step_graph = nullptr;
+    for (auto& p : h->ens_graphs) (void)hipGraphExecDestroy(p.second);
+    h->ens_graphs.clear();
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    h->cap_stream = nullptr;
+}
+
+// Renumbered networks: records back into the caller's numbering (a
+// temporary copy of the largest record, from the handle's allocator).
+net_status records_to_caller(net* h, const net_record* rec, int64_t rows, hipStream_t s) {
+    if (!h->g.caller_of || !rec || rows <= 0 || (!rec->raster && !rec->v && !rec->input)) return NET_OK;
+    const size_t words = static_cast<size_t>((h->g.n_total + 63) / 64);
+    size_t bytes = rec->raster ? static_cast<size_t>(rows) * words * 8 : 0;
+    if (rec->v || rec->input) bytes = std::max(bytes, static_cast<size_t>(rows) * static_cast<size_t>(h->g.n_total) * 4);
+    DevAllocator al;
+    al.alloc = h->alloc;
+    al.release = h->release;
+    al.ctx = h->alloc_ctx;
+    void* tmp = al.get(bytes, s);
+    if (!tmp) return fail(NET_E_OOM, "net_step_n: no memory to renumber the records");
+    hipError_t e = launch_records_to_caller(h->g, rec, rows, tmp, s);
+    al.put(tmp, s);
+    if (e != hipSuccess) return device_fail(h, e, "net_step_n: records");
+    return NET_OK;
+}
+
+// The per-step kernels for n_steps steps (records optional), then the
+// step counter and the records' numbering.
+net_status step_loop(net* h, int64_t n_steps, const net_record* rec, hipStream_t s, bool observe) {
+    for (int64_t k = 0; k < n_steps; ++k) {
+        const int64_t t = h->t + k;
+        hipEvent_t d0, d1, u0, u1;
+        next_events(h, h->lc.fused ? 3 : 0, 1, &d0, &d1);
+        if (h->g.wq) {
+            hipError_t e = launch_plastic_deliver(h->g, t, s, d0, d1);
+            if (e != hipSuccess) return device_fail(h, e, "net_step_n: plastic delivery launch");
+        } else if (!h->lc.fused) {
+            hipError_t e = launch_deliver(h->g, h->lc, t, s, d0, d1);
+            if (e != hipSuccess) return device_fail(h, e, "net_step_n: delivery launch");
+        }
+        int32_t flush = 0, steps = 0;
+        int64_t frame = 0;
+        if (observe) {
+            frame = t * h->frame_num / h->frame_den;
+            const int64_t next = (t + 1) * h->frame_num / h->frame_den;
+            h->acc_steps += 1;
+            if (next != frame) {
+                flush = 1;
+                steps = static_cast<int32_t>(h->acc_steps);
+                h->acc_steps = 0;
+                h->frames_done = std::max(h->frames_done, frame + 1);
+            }
+        }
+        if (h->lc.fused) {
+            hipError_t e = launch_step(h->g, h->lc, t, k, rec, flush, frame, steps, s, d0, d1);
+            if (e != hipSuccess) return device_fail(h, e, "net_step_n: step launch");
+            std::swap(h->g.age, h->g.age_alt);          // the step wrote the next ages and summary
+            std::swap(h->g.summary, h->g.summary_alt);
+            continue;
+        }
+        next_events(h, 1, 0, &u0, &u1);
+        hipError_t e = launch_node_update(h->g, t, k, rec, flush, frame, steps, s, u0, u1);
+        if (e != hipSuccess) return device_fail(h, e, "net_step_n: update launch");
+    }
+    h->t += n_steps;
+    return records_to_caller(h, rec, n_steps, s);
+}
+
+net_status step_plain(net* h, int64_t n_steps, hipStream_t s, bool observe) {
+    return n_steps > 0 ? step_loop(h, n_steps, nullptr, s, observe) : NET_OK;
+}
+
 // Back to the state right after build: V = v0, every other state array zero
 // (age = never fired).
 net_status reset_state(net* h, const HostGraph& hg, hipStream_t s) {
@@ -325,7 +497,7 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
     // fused step: one segment per CU, sized to fit next to the summary in LDS
     int32_t seg_count = 0, seg_cap = 0;
     if (opts && (opts->flags & NET_BUILD_FUSED_STEP) && n_nets == 1 && descs && descs[0].n_nodes > 0 &&
-        descs[0].model == NET_MODEL_LIF) {
+        descs[0].model == NET_MODEL_LIF && !descs[0].plastic) {
         int dev = 0, n_cu = 0, lds_max = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
@@ -338,7 +510,13 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
             }
         }
     }
-    net_status st = build_host_graph(descs, n_nets, hg, err, seg_count, seg_cap);
+    // spatial renumbering: the graph is built from renumbered copies
+    std::vector<net_desc> rdescs;
+    ReorderStore rstore;
+    std::vector<int32_t> caller_of, internal_of;
+    const bool reorder = opts && (opts->flags & NET_BUILD_REORDER) && descs && n_nets >= 1;
+    if (reorder) reorder_descs(descs, n_nets, rdescs, rstore, caller_of, internal_of);
+    net_status st = build_host_graph(reorder ? rdescs.data() : descs, n_nets, hg, err, seg_count, seg_cap);
     if (st != NET_OK) return fail(st, err);
 
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -429,6 +607,32 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
             return bail(NET_E_DEVICE);
         }
     }
+    g.frame_num = hg.frame_num;
+    g.frame_den = hg.frame_den > 0 ? hg.frame_den : 1;
+    if (opts && (opts->flags & NET_BUILD_GRAPH) && !hg.plastic) {
+        if ((st = zeros(h, &h->t_dev, 1, s, "step counter")) != NET_OK) return bail(st);
+        h->graph = true;
+    }
+    if (reorder) {
+        int32_t *co = nullptr, *io = nullptr;
+        if ((st = upload(h, &co, caller_of, caller_of.size(), s, "renumbering")) != NET_OK) return bail(st);
+        if ((st = upload(h, &io, internal_of, internal_of.size(), s, "renumbering")) != NET_OK) return bail(st);
+        g.caller_of = co;
+        g.internal_of = io;
+    }
+    if (hg.plastic) {
+        int32_t *wq = nullptr, *so = nullptr, *rf = nullptr;
+        if ((st = upload(h, &wq, hg.wq, hg.wq.size(), s, "plastic weights")) != NET_OK) return bail(st);
+        if ((st = upload(h, &so, hg.slot_orig, hg.slot_orig.size(), s, "edge order")) != NET_OK) return bail(st);
+        if ((st = upload(h, &rf, hg.row_first, hg.row_first.size(), s, "rows")) != NET_OK) return bail(st);
+        if ((st = zeros(h, &g.spk_hist, np * kStdpHist, s, "spike times")) != NET_OK) return bail(st);
+        if ((st = zeros(h, &g.spk_cnt, np, s, "spike counts")) != NET_OK) return bail(st);
+        g.wq = wq;
+        g.slot_orig = so;
+        g.row_first = rf;
+        g.stdp_alpha = hg.stdp_alpha;
+        g.stdp_beta = hg.stdp_beta;
+    }
     if (frame_cap > 0) {
         if ((st = zeros(h, &g.calcium, np, s, "calcium")) != NET_OK) return bail(st);
         if ((st = zeros(h, &g.frame_acc, np, s, "frame accumulator")) != NET_OK) return bail(st);
@@ -468,7 +672,8 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
         device_fail(h, e, "net_build: configure");
         return bail(NET_E_DEVICE);
     }
-    const int flags = opts ? opts->flags : 0;
+    // a plastic network runs the per-step kernels only (trial steps would move its weights)
+    const int flags = hg.plastic ? 0 : (opts ? opts->flags : 0);
     const bool autotune = (flags & NET_BUILD_AUTOTUNE) != 0;
     const bool single = n_nets > 1 || (flags & NET_BUILD_SINGLE_LAUNCH);
     if (single && !(flags & NET_BUILD_PER_STEP)) {
@@ -595,6 +800,42 @@ net_status net_step_n(net_t* h, int64_t n_steps, const net_record* rec, void* st
     hipStream_t s = static_cast<hipStream_t>(stream);
     h->last_stream = s;
     const bool observe = h->g.frame_cap > 0 && h->frame_num > 0;
+    // graph replays: no records, no kernel timing
+    const bool graphs = h->graph && !rec && h->t_cap == 0 && n_steps > 0;
+    if (graphs && h->plan.enabled) {
+        int64_t done = 0;
+        while (done < n_steps) {
+            const int32_t chunk = static_cast<int32_t>(std::min<int64_t>(n_steps - done, int64_t(1) << 30));
+            hipGraphExec_t ex = nullptr;
+            hipError_t e = ensemble_graph(h, chunk, &ex);
+            if (e == hipSuccess) e = launch_set_counter(h->t_dev, static_cast<uint64_t>(h->t + done), s);
+            if (e == hipSuccess) e = hipGraphLaunch(ex, s);
+            if (e != hipSuccess) return device_fail(h, e, "net_step_n: ensemble graph");
+            done += chunk;
+        }
+        advance_frames(h, h->t, n_steps);
+        h->t += n_steps;
+        return NET_OK;
+    }
+    if (graphs) {
+        // single steps up to a multiple of 256, whole 256-step graphs, single steps after
+        const int64_t head = std::min<int64_t>(n_steps, (kGraphSteps - h->t % kGraphSteps) % kGraphSteps);
+        const int64_t blocks = (n_steps - head) / kGraphSteps;
+        if (blocks > 0) {
+            if (head > 0) {
+                net_status st = step_plain(h, head, s, observe);
+                if (st != NET_OK) return st;
+            }
+            hipGraphExec_t ex = nullptr;
+            hipError_t e = step_graph(h, &ex);
+            if (e == hipSuccess) e = launch_set_counter(h->t_dev, static_cast<uint64_t>(h->t), s);
+            for (int64_t b = 0; e == hipSuccess && b < blocks; ++b) e = hipGraphLaunch(ex, s);
+            if (e != hipSuccess) return device_fail(h, e, "net_step_n: step graph");
+            advance_frames(h, h->t, blocks * kGraphSteps);
+            h->t += blocks * kGraphSteps;     // 256 swaps of the fused step's buffers: back where they were
+            return step_plain(h, n_steps - head - blocks * kGraphSteps, s, observe);
+        }
+    }
     if (h->plan.enabled) {
         // one launch per (at most 2^30) steps for the whole ensemble
         int64_t done = 0;
@@ -626,42 +867,9 @@ net_status net_step_n(net_t* h, int64_t n_steps, const net_record* rec, void* st
             }
         }
         h->t += n_steps;
-        return NET_OK;
+        return records_to_caller(h, rec, n_steps, s);
     }
-    for (int64_t k = 0; k < n_steps; ++k) {
-        const int64_t t = h->t + k;
-        hipEvent_t d0, d1, u0, u1;
-        next_events(h, h->lc.fused ? 3 : 0, 1, &d0, &d1);
-        if (!h->lc.fused) {
-            hipError_t e = launch_deliver(h->g, h->lc, t, s, d0, d1);
-            if (e != hipSuccess) return device_fail(h, e, "net_step_n: delivery launch");
-        }
-        int32_t flush = 0, steps = 0;
-        int64_t frame = 0;
-        if (observe) {
-            frame = t * h->frame_num / h->frame_den;
-            const int64_t next = (t + 1) * h->frame_num / h->frame_den;
-            h->acc_steps += 1;
-            if (next != frame) {
-                flush = 1;
-                steps = static_cast<int32_t>(h->acc_steps);
-                h->acc_steps = 0;
-                h->frames_done = std::max(h->frames_done, frame + 1);
-            }
-        }
-        if (h->lc.fused) {
-            hipError_t e = launch_step(h->g, h->lc, t, k, rec, flush, frame, steps, s, d0, d1);
-            if (e != hipSuccess) return device_fail(h, e, "net_step_n: step launch");
-            std::swap(h->g.age, h->g.age_alt);          // the step wrote the next ages and summary
-            std::swap(h->g.summary, h->g.summary_alt);
-            continue;
-        }
-        next_events(h, 1, 0, &u0, &u1);
-        hipError_t e = launch_node_update(h->g, t, k, rec, flush, frame, steps, s, u0, u1);
-        if (e != hipSuccess) return device_fail(h, e, "net_step_n: update launch");
-    }
-    h->t += n_steps;
-    return NET_OK;
+    return step_loop(h, n_steps, rec, s, observe);
 }
 
 net_status net_observe(net_t* h, int32_t what, const void* params, void* out, int64_t out_bytes, void* stream) {
@@ -688,6 +896,15 @@ net_status net_observe(net_t* h, int32_t what, const void* params, void* out, in
             if (frames > avail) return fail(NET_E_RANGE, "net_observe: more frames requested than recorded");
             if (what == NET_OBS_FLUOR && !params) return fail(NET_E_ARG, "net_observe: fluorescence needs parameters");
             break;
+        }
+        case NET_OBS_WEIGHTS: {
+            if (!h->g.wq) return fail(NET_E_UNSUPPORTED, "net_observe: weights are read out for plastic networks");
+            if (out_bytes < 4 * h->n_edges) return fail(NET_E_ARG, "net_observe: out_bytes too small");
+            hipStream_t s = static_cast<hipStream_t>(stream);
+            h->last_stream = s;
+            hipError_t e = launch_weights_out(h->g, static_cast<float*>(out), s);
+            if (e != hipSuccess) return device_fail(h, e, "net_observe");
+            return NET_OK;
         }
         default:
             return fail(NET_E_ARG, "net_observe: unknown observable");
@@ -791,6 +1008,7 @@ void net_free(net_t* h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->last_stream);
     for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
+    release_graphs(h);
     release_all(h);
     delete h;
 }

@@ -63,6 +63,86 @@ uint32_t pulse_threshold(double rate_hz, double dt_ms) {
     return static_cast<uint32_t>(thr);
 }
 
+void reorder_descs(const net_desc* in, int32_t n_nets, std::vector<net_desc>& out, ReorderStore& st,
+                   std::vector<int32_t>& caller_of, std::vector<int32_t>& internal_of) {
+    out.assign(in, in + n_nets);
+    st = ReorderStore{};
+    st.pos.resize(n_nets);
+    st.src.resize(n_nets);
+    st.dst.resize(n_nets);
+    st.rate.resize(n_nets);
+    st.iext.resize(n_nets);
+    st.v0.resize(n_nets);
+    st.w0.resize(n_nets);
+    int64_t total = 0;
+    for (int m = 0; m < n_nets; ++m) total += in[m].n_nodes;
+    caller_of.assign(total, 0);
+    internal_of.assign(total, 0);
+    int64_t off = 0;
+    for (int m = 0; m < n_nets; ++m) {
+        const net_desc& d = in[m];
+        net_desc& o = out[m];
+        const int32_t n = d.n_nodes;
+        std::vector<int32_t> order(n);   // order[k] = caller's local index of internal vertex k
+        for (int32_t j = 0; j < n; ++j) order[j] = j;
+        if (d.pos_um && d.dims >= 1 && d.dims <= 3 && n > 1) {
+            const int D = d.dims;
+            std::vector<double> lo(D, 1e308), hi(D, -1e308);
+            for (int32_t j = 0; j < n; ++j)
+                for (int k = 0; k < D; ++k) {
+                    lo[k] = std::min(lo[k], d.pos_um[int64_t(j) * D + k]);
+                    hi[k] = std::max(hi[k], d.pos_um[int64_t(j) * D + k]);
+                }
+            const int bits = D == 1 ? 63 : (D == 2 ? 31 : 21);
+            std::vector<uint64_t> code(n, 0);
+            for (int32_t j = 0; j < n; ++j) {
+                for (int k = 0; k < D; ++k) {
+                    const double span = hi[k] > lo[k] ? hi[k] - lo[k] : 1.0;
+                    double q = (d.pos_um[int64_t(j) * D + k] - lo[k]) / span * std::ldexp(1.0, bits);
+                    q = std::min(std::max(q, 0.0), std::ldexp(1.0, bits) - 1.0);
+                    const uint64_t c = static_cast<uint64_t>(q);
+                    for (int b = 0; b < bits; ++b) code[j] |= ((c >> b) & 1ull) << (b * D + k);
+                }
+            }
+            std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return code[a] < code[b]; });
+        }
+        std::vector<int32_t> newid(n);
+        for (int32_t k = 0; k < n; ++k) newid[order[k]] = k;
+        for (int32_t k = 0; k < n; ++k) {
+            caller_of[off + k] = static_cast<int32_t>(off + order[k]);
+            internal_of[off + order[k]] = static_cast<int32_t>(off + k);
+        }
+        if (d.pos_um) {
+            st.pos[m].resize(static_cast<size_t>(n) * d.dims);
+            for (int32_t k = 0; k < n; ++k)
+                for (int c = 0; c < d.dims; ++c) st.pos[m][int64_t(k) * d.dims + c] = d.pos_um[int64_t(order[k]) * d.dims + c];
+            o.pos_um = st.pos[m].data();
+        }
+        if (d.n_edges > 0 && d.src && d.dst) {
+            st.src[m].resize(d.n_edges);
+            st.dst[m].resize(d.n_edges);
+            for (int64_t e = 0; e < d.n_edges; ++e) {
+                const bool ok = d.src[e] >= 0 && d.src[e] < n && d.dst[e] >= 0 && d.dst[e] < n;
+                st.src[m][e] = ok ? newid[d.src[e]] : d.src[e];    // out-of-range indices are reported by the build
+                st.dst[m][e] = ok ? newid[d.dst[e]] : d.dst[e];
+            }
+            o.src = st.src[m].data();
+            o.dst = st.dst[m].data();
+        }
+        auto perm_f = [&](const float* a, std::vector<float>& v) -> const float* {
+            if (!a) return nullptr;
+            v.resize(n);
+            for (int32_t k = 0; k < n; ++k) v[k] = a[order[k]];
+            return v.data();
+        };
+        o.drive_rate_hz = perm_f(d.drive_rate_hz, st.rate[m]);
+        o.i_ext = perm_f(d.i_ext, st.iext[m]);
+        o.v0 = perm_f(d.v0, st.v0[m]);
+        o.w0 = perm_f(d.w0, st.w0[m]);
+        off += n;
+    }
+}
+
 // Hodgkin-Huxley rate functions (the standard squid-axon set; mV, ms),
 // alpha_m and alpha_n at their limits where the denominator vanishes.
 void hh_steady_gates(double V, double* m, double* n, double* h) {
@@ -107,6 +187,11 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
         if (d.model == NET_MODEL_LIF &&
             (!(d.dt_ms > 0.0) || !(d.tau_ms > 0.0) || d.n_ref < 0 || d.n_ref > 250)) {
             err = "net_build: network " + std::to_string(m) + " needs dt > 0, tau > 0, 0 <= n_ref <= 250";
+            return NET_E_ARG;
+        }
+        if (d.plastic && (n_nets != 1 || d.model != NET_MODEL_LIF || d.n_ref < kStdpMinRef)) {
+            err = "net_build: plasticity needs one network per handle, the LIF vertex and n_ref >= " +
+                  std::to_string(kStdpMinRef);
             return NET_E_ARG;
         }
         if (d.model == NET_MODEL_HODGKIN_HUXLEY &&
@@ -252,6 +337,9 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
 
     // Scatter edges into their rows (stable in input order).
     std::vector<int64_t> fill(row_ptr.begin(), row_ptr.end() - 1);
+    const bool track = n_nets == 1 && descs[0].plastic;   // keep each slot's edge index
+    std::vector<int32_t> orig;
+    if (track) orig.assign(g.e_slots, -1);
     int32_t max_delay = 1;
     g.net_max_delay.assign(n_nets, 1);
     for (int m = 0; m < n_nets; ++m) {
@@ -284,6 +372,7 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
             g.src[s] = static_cast<int32_t>(off + i);
             g.w[s] = wb;
             g.d[s] = static_cast<uint8_t>(dl);
+            if (track) orig[s] = static_cast<int32_t>(e);
         }
     }
     g.max_delay = max_delay;
@@ -324,18 +413,20 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
             std::vector<int64_t> idx(b - a);
             for (int64_t s = a; s < b; ++s) idx[s - a] = s;
             std::sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return g.src[x] < g.src[y]; });
-            std::vector<int32_t> ts(b - a);
+            std::vector<int32_t> ts(b - a), to(track ? b - a : 0);
             std::vector<uint16_t> tw(b - a);
             std::vector<uint8_t> td(b - a);
             for (int64_t k = 0; k < b - a; ++k) {
                 ts[k] = g.src[idx[k]];
                 tw[k] = g.w[idx[k]];
                 td[k] = g.d[idx[k]];
+                if (track) to[k] = orig[idx[k]];
             }
             for (int64_t k = 0; k < b - a; ++k) {
                 g.src[a + k] = ts[k];
                 g.w[a + k] = tw[k];
                 g.d[a + k] = td[k];
+                if (track) orig[a + k] = to[k];
             }
             for (int64_t s = a + 1; s < b; ++s)
                 if (g.src[s] == g.src[s - 1]) {
@@ -353,6 +444,26 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
             ulp_min = std::min(ulp_min, fp16_ulp_log2(g.w[s]));
         }
         if (sum_abs > 0.0 && sum_abs > std::ldexp(two24, ulp_min)) g.exact = false;
+    }
+    if (track) {
+        // plastic weights: integer multiples of 2^-20 (exact sums in any order)
+        g.plastic = true;
+        g.stdp_alpha = descs[0].stdp_alpha;
+        g.stdp_beta = descs[0].stdp_beta;
+        g.wq.assign(g.e_slots, 0);
+        for (int64_t s = 0; s < g.e_slots; ++s) {
+            if (orig[s] < 0) continue;
+            const double k = static_cast<double>(fp16_abs(g.w[s])) * 1048576.0 * ((g.w[s] & 0x8000) ? -1.0 : 1.0);
+            if (!(std::fabs(k) < 2147483648.0) || k != std::floor(k)) {
+                err = "net_build: plastic weights must be multiples of 2^-20 below 2048 (edge " +
+                      std::to_string(orig[s]) + ")";
+                return NET_E_ARG;
+            }
+            g.wq[s] = static_cast<int32_t>(k);
+        }
+        g.slot_orig = std::move(orig);
+        g.row_first.assign(N + 1, 0);
+        for (int64_t r = 0; r <= N; ++r) g.row_first[r] = static_cast<int32_t>(row_ptr[r]);
     }
     g.chunk_row0.assign(g.n_chunks, 0);
     {

@@ -216,7 +216,18 @@ net_status simfit(const net_obs_desc* o, const net_simfit_opts* opts, float* out
     in.rho = static_cast<float>(std::pow(1.0 - o->dt_ms / static_cast<double>(o->tau_c_ms), spf));
     in.offset = o->offset;
     in.inv_jump = static_cast<float>(1.0 / (static_cast<double>(o->gain) * o->dt_ms));
-    in.w = o->w_assumed;
+    {
+        std::vector<float> ws(static_cast<size_t>(n), o->w_assumed);
+        if (o->w_source)
+            for (int64_t i = 0; i < n; ++i) {
+                ws[i] = o->w_source[i];
+                if (!std::isfinite(ws[i])) return efail(NET_E_ARG, "simfit: w_source holds a non-finite weight");
+            }
+        float* dws = sc.get<float>(n);
+        if (!dws) return efail(NET_E_OOM, "simfit: allocation");
+        if (!to_dev(dws, ws, s)) return efail(NET_E_DEVICE, "simfit: upload");
+        in.w_src = dws;
+    }
     in.decay = o->dt_ms / static_cast<double>(o->tau_ms);
     in.v_rest = o->v_rest;
     in.v_reset = o->v_reset;

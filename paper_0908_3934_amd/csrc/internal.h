@@ -30,6 +30,10 @@ constexpr int kStepSummaryBytes = 128 * 1024;
 constexpr int kStepQueueBytes = 16 * 128 * 4;
 // Vertices per fused-step segment at most (6 per thread of its workgroup).
 constexpr int kStepMaxSegment = 6 * 1024;
+// Spike times kept per vertex for plasticity: with at least 17 held steps
+// after a spike, 16 spikes span more than the 255-step delay window.
+constexpr int kStdpHist = 16;
+constexpr int kStdpMinRef = 17;
 
 // Every device allocation of the library (network handles, MLP handles and
 // the scratch of the estimation calls) goes through the allocator installed
@@ -99,11 +103,30 @@ struct HostGraph {
     bool any_drive = false, any_iext = false;
     bool any_izh = false;             // some network uses the Izhikevich vertex
     std::vector<double> w0;           // [n_pad] initial W (Izhikevich vertices)
+    // plastic weights (one network): weight of each slot in units of 2^-20,
+    // the caller's index of each slot's edge (-1 for placeholders), and the
+    // first slot of every row
+    bool plastic = false;
+    double stdp_alpha = 0.0, stdp_beta = 0.0;
+    std::vector<int32_t> wq, slot_orig, row_first;
     bool any_hh = false;              // some network uses the Hodgkin-Huxley vertex
     std::vector<double> hh_m0, hh_n0, hh_h0;   // [n_pad] gates at their steady state for V(0)
     double dt_ms = 0.0;
     int32_t frame_num = 0, frame_den = 1;
 };
+
+// Spatial renumbering (NET_BUILD_REORDER): copies of the descriptors with
+// every network's vertices renumbered along a Morton (Z-order) curve of
+// their positions; caller_of[k] is the caller's global index of internal
+// vertex k and internal_of its inverse.  The store keeps the arrays the
+// copies point to.
+struct ReorderStore {
+    std::vector<std::vector<double>> pos;
+    std::vector<std::vector<int32_t>> src, dst;
+    std::vector<std::vector<float>> rate, iext, v0, w0;
+};
+void reorder_descs(const net_desc* in, int32_t n_nets, std::vector<net_desc>& out, ReorderStore& store,
+                   std::vector<int32_t>& caller_of, std::vector<int32_t>& internal_of);
 
 // Builds the CSR-by-target edge list and per-vertex arrays.  Returns a
 // status and fills `err` on failure.
@@ -153,6 +176,22 @@ struct DeviceGraph {
     double* hh_n = nullptr;
     double* hh_h = nullptr;
     double* hh_vprev = nullptr;
+    // plastic weights (null otherwise): see HostGraph; the last kStdpHist
+    // spike steps of every vertex (ring, [n_pad][kStdpHist]) and their count
+    int32_t* wq = nullptr;
+    const int32_t* slot_orig = nullptr;
+    const int32_t* row_first = nullptr;   // [n_total + 1]
+    int32_t* spk_hist = nullptr;
+    int32_t* spk_cnt = nullptr;
+    double stdp_alpha = 0.0, stdp_beta = 0.0;
+    // graph replays: the device step counter (null outside a captured
+    // graph's launches) and the frame rule for the in-kernel bookkeeping
+    const uint64_t* t_dev = nullptr;
+    int32_t frame_num = 0, frame_den = 1;
+    // spatial renumbering (null without NET_BUILD_REORDER): caller's global
+    // index of each internal vertex [n_total], and the inverse
+    const int32_t* caller_of = nullptr;
+    const int32_t* internal_of = nullptr;
     double* calcium;              // null when observation is off
     double* frame_acc;
     float* frames;                // [frame_cap][n_pad]
@@ -203,6 +242,21 @@ hipError_t launch_step(const DeviceGraph& g, const LaunchConfig& lc, int64_t t, 
                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_observe(const DeviceGraph& g, int32_t what, const net_fluor_params* fp, void* out,
                           int64_t n_frames, hipStream_t s);
+// Plastic networks: delivery of step t with the weights as they are, then
+// the plasticity update of step t (one wave per target row).
+hipError_t launch_plastic_deliver(const DeviceGraph& g, int64_t t, hipStream_t s, hipEvent_t ev0 = nullptr,
+                                  hipEvent_t ev1 = nullptr);
+// Current weights in the caller's edge order (out[orig[slot]]); FP16 weights
+// for networks that are not plastic.
+hipError_t launch_weights_out(const DeviceGraph& g, float* out, hipStream_t s);
+// Device step counter of graph replays: set it, or add k to it.
+hipError_t launch_set_counter(uint64_t* t_dev, uint64_t t, hipStream_t s);
+hipError_t launch_advance_counter(uint64_t* t_dev, uint64_t k, hipStream_t s);
+// Renumbered networks: records of `rows` steps written in the internal
+// numbering, copied to `tmp` (as large as the largest record) and put back in
+// the caller's numbering.
+hipError_t launch_records_to_caller(const DeviceGraph& g, const net_record* rec, int64_t rows, void* tmp,
+                                    hipStream_t s);
 hipError_t configure_deliver(DeviceGraph& g, const net_build_opts* opts, LaunchConfig& lc);   // sets g.sum_shift
 hipError_t enable_ensemble_lds(size_t bytes);
 hipError_t launch_ensemble(const DeviceGraph& g, const EnsemblePlan& plan, int64_t t0, int32_t n_steps,
@@ -279,10 +333,11 @@ struct FitInputs {
     const float* F;             // device [nf][n]
     const uint32_t* drive_thr;  // device [n] or null
     const int32_t* pairs;       // device [P][2], sorted by target
+    const float* w_src;         // device [n]: assumed weight of the edges out of each vertex
     int32_t n, nf, K, n_ref;
     int64_t P, t_end, frame_num, frame_den;
     float rho, offset, inv_jump, sigma, gamma;
-    double w, decay, v_rest, v_reset, v_th, drive_amp;   // the fit's vertex model runs in FP64
+    double decay, v_rest, v_reset, v_th, drive_amp;   // the fit's vertex model runs in FP64
     double dt, tau_c, gain;
     uint32_t ctl_lo, ctl_hi, fit_lo, fit_hi;
 };

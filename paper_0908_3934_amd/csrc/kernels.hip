@@ -530,6 +530,14 @@ struct NodeArgs {
     double* __restrict__ hh_n;
     double* __restrict__ hh_h;
     double* __restrict__ hh_vprev;
+    int32_t* __restrict__ spk_hist;   // plastic networks: last kStdpHist spike steps per vertex
+    int32_t* __restrict__ spk_cnt;
+    const int32_t* __restrict__ caller_of;   // renumbered networks: caller's index of each vertex (else null)
+    // graph replays (else null): the step is *t_dev + t_off, and the frame
+    // bookkeeping follows from it (frame_num > 0: observation on)
+    const uint64_t* __restrict__ t_dev;
+    uint32_t t_off;
+    int32_t frame_num, frame_den;
     int64_t n_total, n_pad, rec_row, raster_words, frame_index;
     uint32_t t_lo, t_hi;
     int32_t d_sum, frame_flush, frame_steps, frame_cap, sum_shift;
@@ -545,6 +553,25 @@ struct VertexState {
     uint32_t aux;    // the drive threshold (0: not driven); vertex_random replaces it by the noise's bits
     uint32_t ring;   // the history word that holds this step's bit
 };
+
+// In a graph replay the step comes from the device counter: its Philox
+// counter words and, with observation on, whether the camera frame closes
+// this step (frame(t) = floor(t num / den); a frame of steps first(f) ..
+// first(f+1) - 1, first(f) = ceil(f den / num)).
+__device__ __forceinline__ void apply_device_step(NodeArgs& a) {
+    if (!a.t_dev) return;
+    const uint64_t t = *a.t_dev + a.t_off;
+    a.t_lo = static_cast<uint32_t>(t);
+    a.t_hi = static_cast<uint32_t>(t >> 32);
+    if (a.frame_num > 0) {
+        const int64_t num = a.frame_num, den = a.frame_den;
+        const int64_t ti = static_cast<int64_t>(t);
+        const int64_t f = ti * num / den, f1 = (ti + 1) * num / den;
+        a.frame_index = f;
+        a.frame_flush = f1 != f ? 1 : 0;
+        a.frame_steps = static_cast<int32_t>(((f + 1) * den + num - 1) / num - (f * den + num - 1) / num);
+    }
+}
 
 __device__ __forceinline__ VertexState load_vertex_state(const NodeArgs& a, int64_t j, int64_t j_end) {
     const int64_t jj = j < j_end ? j : 0;
@@ -568,7 +595,7 @@ __device__ __forceinline__ void vertex_random(const NodeArgs& a, int64_t j, int6
     float noise = 0.0f;
     uint32_t pulse = 0;
     if (thr != 0u || p.sigma != 0.0f) {
-        const uint32_t jl = static_cast<uint32_t>(jj - p.node_off);
+        const uint32_t jl = static_cast<uint32_t>((a.caller_of ? a.caller_of[jj] : jj) - p.node_off);
         const uint4 r = philox4x32_10(make_uint4(jl, a.t_lo, a.t_hi, 0u), p.key_lo, p.key_hi);
         pulse = r.x < thr ? 1u : 0u;
         if (p.sigma != 0.0f) noise = p.sigma * gaussian(r.y, r.z);
@@ -627,7 +654,7 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
             const uint32_t thr = a.drive_thr ? a.drive_thr[jj] : 0u;
             u = a.i_ext ? static_cast<double>(a.i_ext[jj]) : 0.0;
             if (thr != 0u || p.sigma != 0.0f) {
-                const uint32_t jl = static_cast<uint32_t>(jj - p.node_off);
+                const uint32_t jl = static_cast<uint32_t>((a.caller_of ? a.caller_of[jj] : jj) - p.node_off);
                 const uint4 r = philox4x32_10(make_uint4(jl, a.t_lo, a.t_hi, 0u), p.key_lo, p.key_hi);
                 if (r.x < thr) u = u + static_cast<double>(p.drive_amp);
                 noise = static_cast<double>(p.sigma) * gaussian_d(r.y, r.z);
@@ -640,7 +667,7 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
         const uint32_t thr = a.drive_thr ? a.drive_thr[jj] : 0u;
         double u = a.i_ext ? static_cast<double>(a.i_ext[jj]) : 0.0, noise = 0.0;
         if (thr != 0u || p.sigma != 0.0f) {
-            const uint32_t jl = static_cast<uint32_t>(jj - p.node_off);
+            const uint32_t jl = static_cast<uint32_t>((a.caller_of ? a.caller_of[jj] : jj) - p.node_off);
             const uint4 r = philox4x32_10(make_uint4(jl, a.t_lo, a.t_hi, 0u), p.key_lo, p.key_hi);
             if (r.x < thr) u = u + static_cast<double>(p.drive_amp);
             noise = static_cast<double>(p.sigma) * gaussian_d(r.y, r.z);
@@ -679,6 +706,12 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
 
     if (valid) {
         a.V[j] = vn;
+        if (kModels && spike && a.spk_hist) {
+            // plasticity: the step of this spike joins the vertex's recent spike times
+            const int32_t c = a.spk_cnt[j];
+            a.spk_hist[j * kStdpHist + (c % kStdpHist)] = static_cast<int32_t>(a.t_lo);
+            a.spk_cnt[j] = c + 1;
+        }
         if (izh) {
             a.Vd[j] = zs.v;
             a.Wd[j] = zs.w;
@@ -715,6 +748,7 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
 
 template <bool kMulti, bool kModels>
 __global__ void __launch_bounds__(256) node_update_kernel(NodeArgs a) {
+    apply_device_step(a);
     const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const float in = a.I[j < a.n_total ? j : 0];
     VertexState st = load_vertex_state(a, j, a.n_total);
@@ -765,6 +799,8 @@ struct EnsembleArgs {
     double* __restrict__ hh_n;
     double* __restrict__ hh_h;
     double* __restrict__ hh_vprev;
+    const int32_t* __restrict__ caller_of;   // renumbered networks (else null)
+    const uint64_t* __restrict__ t_dev;      // graph replays: the first step (else null: t0)
     int64_t t0, n_total, n_pad, raster_words;
     int32_t n_steps, frame_cap, frame_num, frame_den, d_sum;
 };
@@ -805,6 +841,7 @@ __device__ __forceinline__ void put_bits_shared(uint64_t* words, int64_t u0, uin
 }
 
 __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
+    const int64_t t0 = a.t_dev ? static_cast<int64_t>(*a.t_dev) : a.t0;   // graph replays read the step
     extern __shared__ uint4 lds4[];
     uint8_t* lds = reinterpret_cast<uint8_t*>(lds4);
     const int tid = threadIdx.x;
@@ -833,9 +870,9 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
                 for (int k = 0; k < kRingWords; ++k) L.ring[j * kRingWords + k] = gr[k * a.n_pad];
             } else {
                 // steps t0-32 .. t0-1 into one word, bit = step mod 32
-                const uint32_t q32 = static_cast<uint32_t>(a.t0) & 31u;
-                const uint32_t hi = gr[((static_cast<uint32_t>(a.t0 - 1) & 255u) >> 5) * a.n_pad];
-                const uint32_t lo = gr[((static_cast<uint32_t>(a.t0 - 32) & 255u) >> 5) * a.n_pad];
+                const uint32_t q32 = static_cast<uint32_t>(t0) & 31u;
+                const uint32_t hi = gr[((static_cast<uint32_t>(t0 - 1) & 255u) >> 5) * a.n_pad];
+                const uint32_t lo = gr[((static_cast<uint32_t>(t0 - 32) & 255u) >> 5) * a.n_pad];
                 const uint32_t m = (1u << q32) - 1u;
                 L.ring[j] = q32 == 0 ? hi : ((hi & m) | (lo & ~m));
             }
@@ -844,7 +881,7 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
     __syncthreads();
 
     for (int s = 0; s < a.n_steps; ++s) {
-        const int64_t t = a.t0 + s;
+        const int64_t t = t0 + s;
         // ---- delivery: I_j(t) = sum of w over in-edges whose source fired at t - d
         for (int q = q_begin; q < q_end; ++q) {
             const NetMeta nm = a.meta[a.wg_nets[q]];
@@ -936,7 +973,7 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
                         const uint32_t thr = a.drive_thr ? a.drive_thr[u] : 0u;
                         uu = a.i_ext ? static_cast<double>(a.i_ext[u]) : 0.0;
                         if (thr != 0u || p.sigma != 0.0f) {
-                            const uint4 r = philox4x32_10(make_uint4(static_cast<uint32_t>(jj), static_cast<uint32_t>(t),
+                            const uint4 r = philox4x32_10(make_uint4(static_cast<uint32_t>(a.caller_of ? a.caller_of[u] - nm.node_off : jj), static_cast<uint32_t>(t),
                                                                      static_cast<uint32_t>(static_cast<uint64_t>(t) >> 32), 0u),
                                                           p.key_lo, p.key_hi);
                             if (r.x < thr) uu = uu + static_cast<double>(p.drive_amp);
@@ -956,7 +993,7 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
                     const uint32_t thr = a.drive_thr ? a.drive_thr[u] : 0u;
                     double uu = a.i_ext ? static_cast<double>(a.i_ext[u]) : 0.0, noise = 0.0;
                     if (thr != 0u || p.sigma != 0.0f) {
-                        const uint4 r = philox4x32_10(make_uint4(static_cast<uint32_t>(jj), static_cast<uint32_t>(t),
+                        const uint4 r = philox4x32_10(make_uint4(static_cast<uint32_t>(a.caller_of ? a.caller_of[u] - nm.node_off : jj), static_cast<uint32_t>(t),
                                                                  static_cast<uint32_t>(static_cast<uint64_t>(t) >> 32), 0u),
                                                       p.key_lo, p.key_hi);
                         if (r.x < thr) uu = uu + static_cast<double>(p.drive_amp);
@@ -985,7 +1022,7 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
                         float noise = 0.0f;
                         const uint32_t thr = a.drive_thr ? a.drive_thr[u] : 0u;
                         if (thr != 0u || p.sigma != 0.0f) {
-                            const uint4 r = philox4x32_10(make_uint4(static_cast<uint32_t>(jj), static_cast<uint32_t>(t),
+                            const uint4 r = philox4x32_10(make_uint4(static_cast<uint32_t>(a.caller_of ? a.caller_of[u] - nm.node_off : jj), static_cast<uint32_t>(t),
                                                               static_cast<uint32_t>(static_cast<uint64_t>(t) >> 32), 0u),
                                                    p.key_lo, p.key_hi);
                             if (r.x < thr) uu += p.drive_amp;
@@ -1026,7 +1063,7 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
     }
 
     // ---- write the state back (global ring in the 256-step layout, summary)
-    const int64_t t1 = a.t0 + a.n_steps;
+    const int64_t t1 = t0 + a.n_steps;
     for (int q = q_begin; q < q_end; ++q) {
         const NetMeta nm = a.meta[a.wg_nets[q]];
         const NetLds L = carve(lds, nm, obs);
@@ -1076,6 +1113,7 @@ struct ObserveArgs {
     const float* __restrict__ frames;
     const NetParams* __restrict__ params;
     const int32_t* __restrict__ net_id;
+    const int32_t* __restrict__ internal_of;   // renumbered networks: internal index of each caller's vertex
     void* out;
     int64_t n_total, n_pad, n_frames;
     int32_t what, multi;
@@ -1086,25 +1124,27 @@ __global__ void __launch_bounds__(256) observe_kernel(ObserveArgs a) {
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t rows = (a.what == NET_OBS_FRAMES || a.what == NET_OBS_FLUOR) ? a.n_frames : 1;
     if (idx >= rows * a.n_total) return;
-    const int64_t f = idx / a.n_total, j = idx - f * a.n_total;
+    // output element (f, jc) in the caller's numbering; j is where that vertex lives
+    const int64_t f = idx / a.n_total, jc = idx - f * a.n_total;
+    const int64_t j = a.internal_of ? a.internal_of[jc] : jc;
     const NetParams& p = a.params[a.multi ? a.net_id[j] : 0];
     switch (a.what) {
         case NET_OBS_V:
-            static_cast<float*>(a.out)[j] = a.V[j];
+            static_cast<float*>(a.out)[jc] = a.V[j];
             break;
         case NET_OBS_REF: {
             const int32_t age = a.age[j] & 0xFF;
-            static_cast<int32_t*>(a.out)[j] = (age >= 1 && age <= p.n_ref) ? p.n_ref + 1 - age : 0;
+            static_cast<int32_t*>(a.out)[jc] = (age >= 1 && age <= p.n_ref) ? p.n_ref + 1 - age : 0;
             break;
         }
         case NET_OBS_CALCIUM:
-            static_cast<float*>(a.out)[j] = static_cast<float>(a.calcium[j]);
+            static_cast<float*>(a.out)[jc] = static_cast<float>(a.calcium[j]);
             break;
         case NET_OBS_FRAMES:
             static_cast<float*>(a.out)[idx] = a.frames[f * a.n_pad + j];
             break;
         case NET_OBS_FLUOR: {
-            const uint32_t jl = static_cast<uint32_t>(j - p.node_off);
+            const uint32_t jl = static_cast<uint32_t>(jc - p.node_off);
             const uint4 r = philox4x32_10(make_uint4(jl, static_cast<uint32_t>(f), static_cast<uint32_t>(f >> 32), 1u),
                                    p.key_lo, p.key_hi);
             const double F = static_cast<double>(a.gain) * a.frames[f * a.n_pad + j] + static_cast<double>(a.offset) +
@@ -1197,6 +1237,7 @@ __device__ __forceinline__ void deliver_fired_lds(const DeliverArgs& a, int64_t 
 // this unit's age gathers, so the two latencies overlap (loads complete in
 // issue order: the resolution waits for the gathers only).
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs s) {
+    apply_device_step(s.n);
     // the summary at a fixed LDS address (its reads need no base), the
     // segment's inputs, the arrival queues and the unit counter after it
     __shared__ uint4 lds4[kStepSummaryBytes / 16];
@@ -1500,6 +1541,13 @@ static NodeArgs node_args(const DeviceGraph& g, int64_t t, int64_t rec_row, cons
     a.hh_n = g.hh_n;
     a.hh_h = g.hh_h;
     a.hh_vprev = g.hh_vprev;
+    a.spk_hist = g.spk_hist;
+    a.spk_cnt = g.spk_cnt;
+    a.caller_of = g.caller_of;
+    a.t_dev = g.t_dev;
+    a.t_off = static_cast<uint32_t>(t);
+    a.frame_num = g.t_dev ? g.frame_num : 0;
+    a.frame_den = g.frame_den;
     return a;
 }
 
@@ -1509,7 +1557,7 @@ hipError_t launch_node_update(const DeviceGraph& g, int64_t t, int64_t rec_row, 
     const NodeArgs a = node_args(g, t, rec_row, rec, frame_flush, frame_index, frame_steps);
     const int threads = 256;
     const int64_t blocks = g.n_pad / threads + ((g.n_pad % threads) ? 1 : 0);
-    if (g.Vd) {
+    if (g.Vd || g.spk_hist) {
         if (g.n_nets > 1)
             hipExtLaunchKernelGGL((node_update_kernel<true, true>), dim3(blocks), dim3(threads), 0, s, ev0, ev1, 0, a);
         else
@@ -1522,6 +1570,160 @@ hipError_t launch_node_update(const DeviceGraph& g, int64_t t, int64_t rec_row, 
     return hipGetLastError();
 }
 
+namespace {
+
+struct PlasticArgs {
+    const int32_t* __restrict__ src;
+    const uint8_t* __restrict__ d;
+    int32_t* __restrict__ wq;
+    const int32_t* __restrict__ slot_orig;
+    const int32_t* __restrict__ row_first;
+    const uint32_t* __restrict__ ring;
+    const float* __restrict__ V;
+    const int32_t* __restrict__ spk_hist;
+    const int32_t* __restrict__ spk_cnt;
+    float* __restrict__ I;
+    int64_t n_total, n_pad, t;
+    float v_th;
+    double dt, alpha, beta;
+};
+
+// s_k(u): time since vertex k's last spike before step u (0 for u <= 0,
+// u*dt before any spike), from its last kStdpHist spike steps.
+__device__ __forceinline__ double since_last(const PlasticArgs& a, int64_t k, int64_t u) {
+    if (u <= 0) return 0.0;
+    const int32_t cnt = a.spk_cnt[k];
+    const int32_t have = cnt < kStdpHist ? cnt : kStdpHist;
+    int64_t best = -1;
+    for (int q = 0; q < have; ++q) {
+        const int64_t ts = a.spk_hist[k * kStdpHist + q];
+        if (ts < u && ts > best) best = ts;
+    }
+    return best < 0 ? static_cast<double>(u) * a.dt : static_cast<double>(u - best - 1) * a.dt;
+}
+
+// One wave per target row j: the delivered sum of step t with the weights as
+// they are (integers, so the order of additions cannot change it), then the
+// plasticity update of every edge of the row whose spike arrives now or
+// whose target fires now: w += round((dt alpha sign(q) exp(-beta |q|)) / 2^-20).
+__global__ void __launch_bounds__(256) plastic_deliver_kernel(PlasticArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    if (j >= a.n_total) return;
+    const bool post = a.V[j] >= a.v_th;
+    const int64_t first = a.row_first[j], last = a.row_first[j + 1];
+    int64_t acc = 0;
+    for (int64_t e = first + lane; e < last; e += 64) {
+        const int32_t i = a.src[e];
+        const int32_t dl = a.d[e];
+        const uint32_t slot = static_cast<uint32_t>(a.t - dl) & 255u;
+        const bool arrive = a.t - dl >= 0 && ((a.ring[(slot >> 5) * a.n_pad + i] >> (slot & 31u)) & 1u);
+        const int32_t w = a.wq[e];
+        if (arrive) acc += w;
+        if ((arrive || post) && a.slot_orig[e] >= 0) {
+            const double q = since_last(a, i, a.t - dl) - since_last(a, j, a.t);
+            const double sg = q > 0.0 ? 1.0 : (q < 0.0 ? -1.0 : 0.0);
+            const double dw = a.dt * a.alpha * sg * exp(-a.beta * fabs(q));
+            a.wq[e] = w + static_cast<int32_t>(rint(dw * 1048576.0));
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) a.I[j] = static_cast<float>(static_cast<double>(acc) * (1.0 / 1048576.0));
+}
+
+__global__ void __launch_bounds__(256) weights_out_kernel(const int32_t* wq, const int32_t* slot_orig, int64_t slots,
+                                                          float* out) {
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= slots) return;
+    const int32_t o = slot_orig[s];
+    if (o >= 0) out[o] = static_cast<float>(static_cast<double>(wq[s]) * (1.0 / 1048576.0));
+}
+
+}  // namespace
+
+namespace {
+
+// dst[r][caller_of[k]] = src[r][k] for 4-byte values
+__global__ void __launch_bounds__(256) to_caller_rows_kernel(const uint32_t* src, uint32_t* dst,
+                                                             const int32_t* caller_of, int64_t n, int64_t rows) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n * rows) return;
+    const int64_t r = i / n, k = i - r * n;
+    dst[r * n + caller_of[k]] = src[i];
+}
+
+// raster word (r, w) in the caller's numbering: bit b is the internal
+// vertex internal_of[64 w + b]'s bit
+__global__ void __launch_bounds__(256) to_caller_raster_kernel(const uint64_t* src, uint64_t* dst,
+                                                               const int32_t* internal_of, int64_t n, int64_t words,
+                                                               int64_t rows) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= words * rows) return;
+    const int64_t r = i / words, w = i - r * words;
+    uint64_t out = 0;
+    for (int b = 0; b < 64; ++b) {
+        const int64_t jc = w * 64 + b;
+        if (jc >= n) break;
+        const int64_t k = internal_of[jc];
+        out |= ((src[r * words + (k >> 6)] >> (k & 63)) & 1ull) << b;
+    }
+    dst[i] = out;
+}
+
+}  // namespace
+
+hipError_t launch_records_to_caller(const DeviceGraph& g, const net_record* rec, int64_t rows, void* tmp,
+                                    hipStream_t s) {
+    const int64_t n = g.n_total, words = (n + 63) / 64;
+    if (rec->raster) {
+        hipError_t e = hipMemcpyAsync(tmp, rec->raster, static_cast<size_t>(rows * words) * 8, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(to_caller_raster_kernel, dim3(static_cast<unsigned>((rows * words + 255) / 256)), dim3(256), 0,
+                           s, static_cast<const uint64_t*>(tmp), rec->raster, g.internal_of, n, words, rows);
+    }
+    float* recs[2] = {rec->v, rec->input};
+    for (float* r : recs) {
+        if (!r) continue;
+        hipError_t e = hipMemcpyAsync(tmp, r, static_cast<size_t>(rows * n) * 4, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(to_caller_rows_kernel, dim3(static_cast<unsigned>((rows * n + 255) / 256)), dim3(256), 0, s,
+                           static_cast<const uint32_t*>(tmp), reinterpret_cast<uint32_t*>(r), g.caller_of, n, rows);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_plastic_deliver(const DeviceGraph& g, int64_t t, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    PlasticArgs a;
+    a.src = g.src;
+    a.d = g.d;
+    a.wq = g.wq;
+    a.slot_orig = g.slot_orig;
+    a.row_first = g.row_first;
+    a.ring = g.ring;
+    a.V = g.V;
+    a.spk_hist = g.spk_hist;
+    a.spk_cnt = g.spk_cnt;
+    a.I = g.I;
+    a.n_total = g.n_total;
+    a.n_pad = g.n_pad;
+    a.t = t;
+    a.v_th = g.p0.v_th;
+    a.dt = g.p0.dt_d;
+    a.alpha = g.stdp_alpha;
+    a.beta = g.stdp_beta;
+    const int64_t threads = g.n_total * 64;
+    hipExtLaunchKernelGGL(plastic_deliver_kernel, dim3(static_cast<unsigned>((threads + 255) / 256)), dim3(256), 0, s,
+                          ev0, ev1, 0, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_weights_out(const DeviceGraph& g, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(weights_out_kernel, dim3(static_cast<unsigned>((g.e_slots + 255) / 256)), dim3(256), 0, s, g.wq,
+                       g.slot_orig, g.e_slots, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_observe(const DeviceGraph& g, int32_t what, const net_fluor_params* fp, void* out, int64_t n_frames,
                           hipStream_t s) {
     ObserveArgs a;
@@ -1531,6 +1733,7 @@ hipError_t launch_observe(const DeviceGraph& g, int32_t what, const net_fluor_pa
     a.frames = g.frames;
     a.params = g.params;
     a.net_id = g.net_id;
+    a.internal_of = g.internal_of;
     a.out = out;
     a.n_total = g.n_total;
     a.n_pad = g.n_pad;
@@ -1582,6 +1785,8 @@ hipError_t launch_ensemble(const DeviceGraph& g, const EnsemblePlan& plan, int64
     a.hh_n = g.hh_n;
     a.hh_h = g.hh_h;
     a.hh_vprev = g.hh_vprev;
+    a.caller_of = g.caller_of;
+    a.t_dev = g.t_dev;
     a.t0 = t0;
     a.n_total = g.n_total;
     a.n_pad = g.n_pad;
@@ -1598,6 +1803,21 @@ hipError_t launch_ensemble(const DeviceGraph& g, const EnsemblePlan& plan, int64
 hipError_t enable_ensemble_lds(size_t bytes) {
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&ensemble_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+}
+
+namespace {
+__global__ void set_counter_kernel(uint64_t* t_dev, uint64_t t) { *t_dev = t; }
+__global__ void advance_counter_kernel(uint64_t* t_dev, uint64_t k) { *t_dev += k; }
+}  // namespace
+
+hipError_t launch_set_counter(uint64_t* t_dev, uint64_t t, hipStream_t s) {
+    hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(1), 0, s, t_dev, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_counter(uint64_t* t_dev, uint64_t k, hipStream_t s) {
+    hipLaunchKernelGGL(advance_counter_kernel, dim3(1), dim3(1), 0, s, t_dev, k);
+    return hipGetLastError();
 }
 
 hipError_t launch_step(const DeviceGraph& g, const LaunchConfig& lc, int64_t t, int64_t rec_row, const net_record* rec,

@@ -6,7 +6,7 @@
 // simulated with the model of the forward path (LIF Euler step, refractory
 // hold, control pulses, state noise, calcium transition of Section 3.3),
 // driven by its sources' activity estimated from their own observations:
-// input per step in frame f = w * sum_{i in G} e_i(f) / S(f), e_i the
+// input per step in frame f = sum_{i in G} w_i e_i(f) / S(f), e_i the
 // deconvolved activity in spikes, S(f) the steps of frame f.  K noise
 // realisations give the mean and variance of j's frame-averaged calcium,
 // and the observed fluorescence is scored with the Gaussian observation
@@ -15,7 +15,7 @@
 //   mu = n*mean_k cbar + b,  s2 = gamma^2 + n^2 var_k cbar.
 //
 //   fitprep_kernel   e_i(f) in spikes and the control-pulse bits of every vertex
-//   fitbase_kernel   per (j, f): w * sum_{i in G_j} e_i(f) / S(f)
+//   fitbase_kernel   per (j, f): sum_{i in G_j} w_i e_i(f) / S(f)
 //   fiteval_kernel   one lane per (variant, realisation); a variant is target j
 //                    with G_j, or with one candidate toggled; K adjacent lanes
 //                    hold the realisations of a variant.
@@ -90,9 +90,9 @@ struct FitBaseArgs {
     const int32_t* pairs;     // [P][2]
     const int64_t* row;       // [n+1] pairs of target j are [row[j], row[j+1]) (pairs sorted by target)
     const uint8_t* member;    // [P] 1 if the pair is in G
+    const float* w_src;       // [n] assumed weight of the edges out of each vertex
     double* base;             // [n][nf]
     int32_t n, nf;
-    double w;
     int64_t frame_num, frame_den;
 };
 
@@ -102,10 +102,13 @@ __global__ void __launch_bounds__(256) fitbase_kernel(FitBaseArgs a) {
     const int j = static_cast<int>(idx / a.nf), f = static_cast<int>(idx % a.nf);
     double s = 0.0;
     for (int64_t p = a.row[j]; p < a.row[j + 1]; ++p)
-        if (a.member[p]) s += a.e[static_cast<int64_t>(a.pairs[2 * p]) * a.nf + f];
+        if (a.member[p]) {
+            const int i = a.pairs[2 * p];
+            s += static_cast<double>(a.w_src[i]) * static_cast<double>(a.e[static_cast<int64_t>(i) * a.nf + f]);
+        }
     const double steps = static_cast<double>(first_step(f + 1, a.frame_num, a.frame_den) -
                                              first_step(f, a.frame_num, a.frame_den));
-    a.base[idx] = a.w * s / steps;
+    a.base[idx] = s / steps;
 }
 
 struct FitEvalArgs {
@@ -115,11 +118,12 @@ struct FitEvalArgs {
     const uint32_t* pulses;   // [n][words]
     const int32_t* pairs;     // [P][2]
     const uint8_t* member;    // [P]
+    const float* w_src;       // [n]
     double* ll;               // [P + n]: variant v < P toggles pair v; v = P + j is G_j itself
     int64_t P;
     int32_t n, nf, words, K;
     float sigma;
-    double w, decay, v_rest, v_reset, v_th, drive_amp;
+    double decay, v_rest, v_reset, v_th, drive_amp;
     int32_t n_ref;
     double dt, tau_c, gain, offset, gamma2;
     int64_t frame_num, frame_den;
@@ -141,7 +145,7 @@ __global__ void __launch_bounds__(256) fiteval_kernel(FitEvalArgs a) {
         if (v < a.P) {
             j = a.pairs[2 * v + 1];
             src = a.pairs[2 * v];
-            sign = a.member[v] ? -1.0 : 1.0;
+            sign = (a.member[v] ? -1.0 : 1.0) * static_cast<double>(a.w_src[src]);
         } else {
             j = static_cast<int>(v - a.P);
         }
@@ -160,7 +164,7 @@ __global__ void __launch_bounds__(256) fiteval_kernel(FitEvalArgs a) {
         const int64_t t1 = first_step(f + 1, a.frame_num, a.frame_den);
         const double steps = static_cast<double>(t1 - t);
         double u = bj[f];
-        if (es) u += sign * a.w * static_cast<double>(es[f]) / steps;
+        if (es) u += sign * static_cast<double>(es[f]) / steps;
         uint32_t pw = pj[t >> 5];
         for (; t < t1; ++t) {
             if ((t & 31) == 0) pw = pj[t >> 5];
@@ -237,10 +241,10 @@ hipError_t fit_eval(const FitInputs& in, const FitWork& w, hipStream_t s) {
     b.pairs = in.pairs;
     b.row = w.row;
     b.member = w.member;
+    b.w_src = in.w_src;
     b.base = w.base;
     b.n = in.n;
     b.nf = in.nf;
-    b.w = in.w;
     b.frame_num = in.frame_num;
     b.frame_den = in.frame_den;
     const int64_t nb = static_cast<int64_t>(in.n) * in.nf;
@@ -252,13 +256,13 @@ hipError_t fit_eval(const FitInputs& in, const FitWork& w, hipStream_t s) {
     a.pulses = w.pulses;
     a.pairs = in.pairs;
     a.member = w.member;
+    a.w_src = in.w_src;
     a.ll = w.ll;
     a.P = in.P;
     a.n = in.n;
     a.nf = in.nf;
     a.words = w.words;
     a.K = in.K;
-    a.w = in.w;
     a.decay = in.decay;
     a.v_rest = in.v_rest;
     a.v_reset = in.v_reset;

@@ -98,7 +98,7 @@ def observe(specs: Sequence, n_steps: int, gain: float = 1.0, offset: float = 0.
     return out
 
 
-def obs_desc(o: Observed, keep: list, w_assumed: float = 0.0) -> _abi.ObsDesc:
+def obs_desc(o: Observed, keep: list, w_assumed: float = 0.0, w_source=None) -> _abi.ObsDesc:
     s = o.spec
     d = _abi.ObsDesc()
     d.n_nodes = s.n
@@ -121,7 +121,22 @@ def obs_desc(o: Observed, keep: list, w_assumed: float = 0.0) -> _abi.ObsDesc:
     d.noise_sigma = s.noise_sigma
     d.w_assumed = w_assumed
     d.n_ref = s.n_ref
+    if w_source is not None:
+        ws = np.ascontiguousarray(w_source, dtype=np.float32)
+        if ws.shape != (s.n,):
+            raise ValueError("w_source must hold one weight per vertex")
+        keep.append(ws)
+        d.w_source = ws.ctypes.data
     return d
+
+
+def source_weights(spec, w0: float, g_inh: float = 1.0):
+    """The per-source weights the fit assumes when the cell types are known:
+    w0 out of excitatory vertices, -g_inh * w0 out of inhibitory ones."""
+    ws = np.full(spec.n, w0, dtype=np.float32)
+    if getattr(spec, "inhibitory", None) is not None:
+        ws[np.asarray(spec.inhibitory, dtype=bool)] = np.float32(-g_inh * w0)
+    return ws
 
 
 def _echeck(st, where):
@@ -140,12 +155,13 @@ def features(o: Observed, stream=None):
 
 
 def simfit(o: Observed, w_assumed: float, realisations: int = 8, sweeps: int = 2, init_fraction: float = 0.3,
-           fit_seed: int = 0x5EEDF17, min_gain: float = 1e-3, stream=None):
-    """Simulation-based fit scores LL(G + e) - LL(G - e) per candidate pair."""
+           fit_seed: int = 0x5EEDF17, min_gain: float = 1e-3, w_source=None, stream=None):
+    """Simulation-based fit scores LL(G + e) - LL(G - e) per candidate pair
+    (w_source: optional per-source assumed weights, else w_assumed for all)."""
     import torch
     out = torch.empty(int(o.pairs.shape[0]), dtype=torch.float32, device=o.F.device)
     keep = []
-    d = obs_desc(o, keep, w_assumed=w_assumed)
+    d = obs_desc(o, keep, w_assumed=w_assumed, w_source=w_source)
     opts = _abi.SimfitOpts(realisations, sweeps, init_fraction, min_gain, fit_seed)
     _echeck(library().net_estimate(C.byref(d), _abi.NET_EST_SIMFIT, None, C.byref(opts), out.data_ptr(),
                                    _stream_handle(stream)), "net_estimate")
@@ -163,13 +179,14 @@ def scorer_scores(o: Observed, scorer: "EdgeScorer", stream=None):
     return out
 
 
-def estimate(o: Observed, scorer: Optional["EdgeScorer"] = None, w_assumed: float = 0.0, stream=None, **fit_opts):
+def estimate(o: Observed, scorer: Optional["EdgeScorer"] = None, w_assumed: float = 0.0, w_source=None, stream=None,
+             **fit_opts):
     """net_estimate with NET_EST_AUTO: the learned scorer when one is given,
     else the simulation-based fit (fit options as for simfit)."""
     import torch
     out = torch.empty(int(o.pairs.shape[0]), dtype=torch.float32, device=o.F.device)
     keep = []
-    d = obs_desc(o, keep, w_assumed=w_assumed)
+    d = obs_desc(o, keep, w_assumed=w_assumed, w_source=w_source)
     opts = _abi.SimfitOpts(fit_opts.get("realisations", 8), fit_opts.get("sweeps", 2),
                            fit_opts.get("init_fraction", 0.3), fit_opts.get("min_gain", 1e-3),
                            fit_opts.get("fit_seed", 0x5EEDF17))
@@ -206,14 +223,15 @@ class EdgeScorer:
         self.input_norm = None     # (shift, scale) of the features, set by fit
 
     def fit(self, train: Sequence[Observed], epochs: int = 4, batch: int = 16384, lr: float = 1e-3,
-            feats: Optional[list] = None):
+            feats: Optional[list] = None, labels: Optional[list] = None):
         """Standardisation fitted to the training features and `epochs`
         shuffled passes (net_mlp_fit_input_norm, net_mlp_train_epoch: every
         row once per epoch, the last batch of an epoch possibly smaller).
         history holds each epoch's mean batch loss."""
         import torch
         X = torch.cat(feats if feats is not None else [features(o) for o in train])
-        y = torch.tensor(np.concatenate([o.labels for o in train]).astype(np.float32), device=X.device)
+        lab = labels if labels is not None else [o.labels for o in train]
+        y = torch.tensor(np.concatenate(lab).astype(np.float32), device=X.device)
         n = int(X.shape[0])
         if n == 0:
             raise ValueError("EdgeScorer.fit: no training pairs")

@@ -148,6 +148,11 @@ class NetSpec:
     # Hodgkin-Huxley vertex (model 2; v_th is the threshold of the upward
     # crossing that signals a spike): membrane capacitance (uF/cm^2),
     # maximal conductances (mS/cm^2) and reversal potentials (mV)
+    # spike-timing-dependent plasticity (LIF only): weights evolve by
+    # dw = dt * alpha * sign(q) * exp(-beta |q|) (kept as multiples of 2^-20)
+    plastic: int = 0
+    stdp_alpha: float = 0.0      # weight per ms
+    stdp_beta: float = 0.0       # 1/ms
     hh_C: float = 1.0
     hh_gna: float = 120.0
     hh_gk: float = 36.0
@@ -291,6 +296,17 @@ def hodgkin_huxley(spec: NetSpec, psc: int = 1, w_scale: Optional[float] = None,
                    psc_rate=float(np.float32(0.5)), frame_num=FRAME_NUM, frame_den=FRAME_DEN * 10 // 3)
 
 
+STDP_ALPHA = float(np.float32(0.005))    # weight per ms
+STDP_BETA = float(np.float32(0.1))       # 1/ms (a 10 ms window)
+
+
+def plastic(spec: NetSpec, alpha: float = STDP_ALPHA, beta: float = STDP_BETA) -> NetSpec:
+    """The same network with STDP on its weights (FP32-exact rates)."""
+    from dataclasses import replace
+    return replace(spec, name=spec.name + "-stdp", plastic=1, stdp_alpha=float(np.float32(alpha)),
+                   stdp_beta=float(np.float32(beta)))
+
+
 def config0_like(n: int, seed: int, name: str = "config0", w0: float = W0) -> NetSpec:
     """2D square 1 mm, p = 0.3 within 150 um, 10 % driven at 5 Hz, no noise."""
     pos = uniform_positions(n, [1000.0, 1000.0], seed)
@@ -345,12 +361,19 @@ def config3(n_nets: int = 512, sizes: Optional[List[int]] = None) -> List[NetSpe
     return [config0_like(nm, config_seed(3, m + 1), "config3_net%d" % m) for m, nm in enumerate(sizes)]
 
 
-def config4_net(m: int, noise_sigma: float = NOISE_SIGMA) -> NetSpec:
+def config4_net(m: int, noise_sigma: float = NOISE_SIGMA, w0: float = W0, inhibitory: float = 0.0,
+                g_inh: float = 1.0) -> NetSpec:
     """N = 1024 network built like config0, with state noise so that
     undriven vertices fire (without it they stay silent and no edge into them
-    is observable)."""
-    spec = config0_like(1024, config_seed(4, m), "config4_net%d" % m)
+    is observable); w0 sets the weight scale, and a fraction `inhibitory` of
+    the sources (the same subset rule as config 2) get weights -g_inh times
+    theirs."""
+    spec = config0_like(1024, config_seed(4, m), "config4_net%d" % m, w0=w0)
     spec.noise_sigma = noise_sigma
+    if inhibitory > 0.0:
+        inh = _subset(spec.n, inhibitory, spec.seed, 5)
+        spec.weight = np.where(inh[spec.src], round_fp16(-g_inh * spec.weight), spec.weight).astype(np.float32)
+        spec.inhibitory = inh
     return spec
 
 

@@ -294,3 +294,60 @@ def test_fit_identifies_true_in_set_without_noise():
         flip = list(subsets[k_end])
         flip[k] ^= 1
         assert lls[subsets.index(tuple(flip))] <= lls[k_end]
+
+
+def test_fit_per_source_weights():
+    """Per-source weights enter the fit's input as w_i * e_i(f).  Pinned by
+    a scaling identity and the brute force of the identifiability case:
+    halving a true source's calcium deviation (so its activity e halves
+    exactly) while doubling its weight leaves every likelihood bit-identical;
+    the target's own weight entry is never read; and with one false source
+    given a negative (inhibitory) weight, the true in-set still has the
+    highest likelihood over all 2^10 subsets and the search from the empty
+    set ends on it."""
+    n, nf, C = 11, 36, 10
+    gain, offset, gamma, w = 1.0, 0.0, 0.002, 4.0       # offset 0: halving a trace is exact
+    model = dict(frame_num=NUM, frame_den=DEN, dt=DT, tau=20.0, v_rest=0.0, v_reset=0.0, v_th=1.0, n_ref=20,
+                 drive_amp=1.5, tau_c=TAU_C)
+    rng = np.random.default_rng(11)
+    x = np.zeros((n, nf))
+    frames = rng.permutation(np.arange(1, nf - 2))[:3 * C].reshape(C, 3)
+    for i in range(1, n):
+        x[i, frames[i - 1]] = 1.0
+    F = np.zeros((nf, n))
+    for i in range(1, n):
+        F[:, i] = offset + _trace_from_activity(x[i] * gain * DT)
+    first = (np.arange(nf + 1) * DEN + NUM - 1) // NUM
+    steps_f = np.diff(first).astype(float)
+    e = SF.activity_spikes(F, RHO, offset, gain, DT)
+    true = (2, 5, 7, 9)
+    pulses = np.zeros((n, first[-1]), dtype=bool)
+    cb = SF.simulate_hypotheses([0], (w * sum(e[i] for i in true) / steps_f)[None, :], pulses, K=1, nf=nf,
+                                sigma=0.0, fit_seed=3, **model)
+    F[:, 0] = gain * cb[0, 0] + offset + gamma * rng.standard_normal(nf)
+    pairs = np.array([[c, 0] for c in range(1, n)])
+    common = dict(drive_thr=[0] * n, control_seed=1, gain=gain, offset=offset, gamma=gamma, sigma=0.0, K=1,
+                  sweeps=8, fit_seed=3, **model)
+    s0, m0, ll0 = SF.fit(F, pairs, init_fraction=0.0, w=w, **common)
+    # scaling identity on source 5, and a wild weight on the target itself
+    F2 = F.copy()
+    F2[:, 5] = F[:, 5] / 2.0
+    assert np.array_equal(SF.activity_spikes(F2, RHO, offset, gain, DT)[5], e[5] / 2.0)
+    ws = np.full(n, w)
+    ws[5] = 2.0 * w
+    ws[0] = -100.0
+    s1, m1, ll1 = SF.fit(F2, pairs, init_fraction=0.0, w=ws, **common)
+    # (ll[C + j] scores vertex j as a target: only target 0 is the case here)
+    assert np.array_equal(m0, m1) and np.array_equal(ll0[:C + 1], ll1[:C + 1]) and np.array_equal(s0, s1)
+    # an inhibitory false source: brute force over all subsets with the signed weights
+    ws = np.full(n, w)
+    ws[3] = -w
+    subsets = list(itertools.product([0, 1], repeat=C))
+    U = np.array([sum((ws[k + 1] * e[k + 1] for k in range(C) if s[k]), np.zeros(nf)) / steps_f for s in subsets])
+    cbs = SF.simulate_hypotheses([0] * len(subsets), U, pulses, K=1, nf=nf, sigma=0.0, fit_seed=3, **model)
+    lls = SF.loglik(cbs, np.repeat(F.T[[0]], len(subsets), 0), gain, offset, gamma)
+    k_true = subsets.index(tuple(1 if c in true else 0 for c in range(1, n)))
+    assert np.argmax(lls) == k_true
+    _, member, ll = SF.fit(F, pairs, init_fraction=0.0, w=ws, **common)
+    assert tuple(int(v) for v in member) == subsets[k_true]
+    assert ll[C] == pytest.approx(lls[k_true], rel=1e-12)

@@ -21,9 +21,15 @@ def _f32(x):
     return float(np.float32(x))
 
 
-def _case(n_targets=16, seed=3):
+def _case(n_targets=16, seed=3, signed=False):
     spec = synth.config0_like(256, synth.config_seed(4, 700 + seed), w0=synth.W0)
     spec.noise_sigma = synth.NOISE_SIGMA
+    if signed:
+        # 20 % inhibitory sources at three times the excitatory magnitude
+        inh = np.zeros(spec.n, dtype=bool)
+        inh[np.random.default_rng(seed).permutation(spec.n)[: spec.n // 5]] = True
+        spec.weight = np.where(inh[spec.src], synth.round_fp16(-3.0 * spec.weight), spec.weight).astype(np.float32)
+        spec.inhibitory = inh
     steps = (NF * spec.frame_den + spec.frame_num - 1) // spec.frame_num
     o = oracle.OracleNet(spec, frames_cap=NF)
     o.step(steps)
@@ -46,11 +52,12 @@ def _gpu(spec, F, gamma, pairs, dist, labels, **kw):
 
 
 def _ref(spec, F, gamma, pairs, *, w, K, sweeps, fit_seed):
+    w = np.asarray(w, dtype=np.float32).astype(np.float64) if np.ndim(w) else _f32(w)
     thr = [oracle.drive_threshold(float(r), spec.dt_ms) for r in spec.drive_rate_hz]
     return SF.fit(F.astype(np.float64), pairs, drive_thr=thr, control_seed=spec.seed, gain=1.0, offset=0.0,
                   gamma=gamma, dt=spec.dt_ms, tau=spec.tau_ms, v_rest=spec.v_rest, v_reset=spec.v_reset,
                   v_th=spec.v_th, n_ref=spec.n_ref, sigma=_f32(spec.noise_sigma), drive_amp=spec.drive_amp,
-                  tau_c=spec.tau_c_ms, frame_num=spec.frame_num, frame_den=spec.frame_den, w=_f32(w), K=K,
+                  tau_c=spec.tau_c_ms, frame_num=spec.frame_num, frame_den=spec.frame_den, w=w, K=K,
                   sweeps=sweeps, init_fraction=0.3, fit_seed=fit_seed)
 
 
@@ -67,6 +74,28 @@ def test_simfit_matches_reference(sweeps):
     assert close.all(), (close.mean(), np.abs(g - ref).max(), bad_targets)
     assert abs(metrics.auc(g, labels) - metrics.auc(ref, labels)) <= 1e-9
     assert np.abs(ref).max() > 1e-3                     # the toggles do change the likelihood
+
+
+def test_simfit_per_source_weights_match_reference():
+    """Per-source assumed weights (inhibitory sources negative): the same
+    fit as the reference, and a uniform w_source equals w_assumed exactly."""
+    from paper_0908_3934_amd import estimate as est
+    spec, F, gamma, pairs, dist, labels = _case(seed=5, signed=True)
+    w0 = synth.W0
+    ws = est.source_weights(spec, w0, g_inh=3.0)
+    assert (ws < 0).sum() == spec.n // 5
+    K, fs = 4, 0x5EEDF17
+    print("simfit per-source weights: P=%d" % len(pairs), flush=True)
+    g = _gpu(spec, F, gamma, pairs, dist, labels, w_assumed=w0, w_source=ws, realisations=K, sweeps=2, fit_seed=fs)
+    ref, _, _ = _ref(spec, F, gamma, pairs, w=ws, K=K, sweeps=2, fit_seed=fs)
+    close = np.abs(g - ref) <= 1e-6 * np.maximum(1.0, np.abs(ref))
+    assert close.all(), (close.mean(), np.abs(g - ref).max())
+    a = _gpu(spec, F, gamma, pairs, dist, labels, w_assumed=w0, realisations=K, sweeps=1, fit_seed=fs)
+    b = _gpu(spec, F, gamma, pairs, dist, labels, w_assumed=0.0, w_source=np.full(spec.n, _f32(w0), np.float32),
+             realisations=K, sweeps=1, fit_seed=fs)
+    assert np.array_equal(a, b)
+    with pytest.raises(ValueError):
+        _gpu(spec, F, gamma, pairs, dist, labels, w_assumed=w0, w_source=ws[:-1])
 
 
 def test_simfit_same_seed_same_scores():
