@@ -723,6 +723,10 @@ def main():
     ap.add_argument("--epochs", type=int, default=4, help="estimate workload: scorer training epochs")
     ap.add_argument("--w0", type=float, default=None,
                     help="estimate workload: weight scale of the observed networks (default the shared 0.05)")
+    ap.add_argument("--relabel", type=int, default=-1,
+                    help="default workload: number the vertices in a random order (this seed) before the build")
+    ap.add_argument("--reorder", action="store_true",
+                    help="default workload: let net_build renumber the vertices in Morton order (NET_BUILD_REORDER)")
     ap.add_argument("--mlp-rows", type=int, default=65536,
                     help="mlp workload: training batch rows per optimizer step")
     ap.add_argument("--inhibitory", type=float, default=0.0,
@@ -785,9 +789,15 @@ def main():
         del x, y
     t0 = time.perf_counter()
     spec = synth.config2(n=args.n)
+    if args.relabel >= 0:
+        # the same network with its vertices numbered in a random order
+        spec = synth.relabel(spec, args.relabel)
     log("generated N=%d E=%d in %.1f s" % (spec.n, spec.n_edges, time.perf_counter() - t0))
     t0 = time.perf_counter()
-    net = gn.Net(spec, flags=gn.NET_BUILD_AUTOTUNE if args.autotune else args.deliver_flags)
+    flags = gn.NET_BUILD_AUTOTUNE if args.autotune else args.deliver_flags
+    if args.reorder:
+        flags |= gn.NET_BUILD_REORDER
+    net = gn.Net(spec, flags=flags)
     info = net.info()
     log("built in %.1f s: %s" % (time.perf_counter() - t0, info))
 
@@ -870,6 +880,8 @@ def main():
             "n_edges": E,
             "max_delay_steps": info["max_delay"],
             "deliver_flags": info["deliver_flags"],
+            "numbering": ("random (seed %d)" % args.relabel if args.relabel >= 0 else "Morton order of the generator")
+                         + (", renumbered in Morton order at build" if args.reorder else ""),
             "real_time_factor": sim_s / wall,
             "launch": "%d blocks x %d threads, summary in %s, variant flags %d%s" % (
                 info["deliver_blocks"], info["deliver_threads"], "LDS" if info["lds_summary"] else "global",

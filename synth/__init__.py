@@ -379,3 +379,20 @@ def config4_net(m: int, noise_sigma: float = NOISE_SIGMA, w0: float = W0, inhibi
 
 def in_degree(spec: NetSpec) -> np.ndarray:
     return np.bincount(spec.dst, minlength=spec.n)
+
+
+def relabel(spec: NetSpec, seed: int) -> NetSpec:
+    """The same network with its vertices numbered in a random order (every
+    per-vertex array permuted, edges renamed, edge order kept)."""
+    from dataclasses import replace
+    rng = np.random.default_rng(seed)
+    n = spec.n
+    perm = rng.permutation(n)              # new label of old vertex i is perm[i]
+    inv = np.argsort(perm)                 # old vertex of new label k
+    def pv(a):
+        return None if a is None else np.ascontiguousarray(np.asarray(a)[inv])
+    return replace(spec, name=spec.name + "-relabel", pos_um=np.ascontiguousarray(spec.pos_um[inv]),
+                   src=perm[spec.src].astype(np.int32), dst=perm[spec.dst].astype(np.int32),
+                   drive_rate_hz=pv(spec.drive_rate_hz), i_ext=pv(spec.i_ext), v0=pv(spec.v0),
+                   w0_iz=pv(getattr(spec, "w0_iz", None)),
+                   inhibitory=pv(spec.inhibitory))

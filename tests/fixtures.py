@@ -141,18 +141,4 @@ def hh_params(spec) -> dict:
             "ek": spec.hh_ek, "el": spec.hh_el, "psc": spec.psc, "psc_a": spec.psc_rate}
 
 
-def relabel(spec: synth.NetSpec, seed: int) -> synth.NetSpec:
-    """The same network with its vertices numbered in a random order (every
-    per-vertex array permuted, edges renamed, edge order kept)."""
-    from dataclasses import replace
-    rng = np.random.default_rng(seed)
-    n = spec.n
-    perm = rng.permutation(n)              # new label of old vertex i is perm[i]
-    inv = np.argsort(perm)                 # old vertex of new label k
-    def pv(a):
-        return None if a is None else np.ascontiguousarray(np.asarray(a)[inv])
-    return replace(spec, name=spec.name + "-relabel", pos_um=np.ascontiguousarray(spec.pos_um[inv]),
-                   src=perm[spec.src].astype(np.int32), dst=perm[spec.dst].astype(np.int32),
-                   drive_rate_hz=pv(spec.drive_rate_hz), i_ext=pv(spec.i_ext), v0=pv(spec.v0),
-                   w0_iz=pv(getattr(spec, "w0_iz", None)),
-                   inhibitory=pv(spec.inhibitory))
+relabel = synth.relabel
