@@ -649,12 +649,38 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
         g.n_seg = static_cast<int32_t>(hg.seg_vertex.size()) - 1;
         g.seg_max = hg.seg_max;
     }
-    // the fused step and the packed delivery variant stream one word per
-    // slot, source | delay << 24 (sources below 2^24; a fused network has at
-    // most 2^20 vertices)
+    // the fused step streams 3.5 B per slot (16 low source bits, the delay
+    // byte, 4 high source bits; sources below 2^20, chunks in pairs)
+    if (!hg.seg_vertex.empty() && g.n_pad <= (int64_t(1) << 20) && hg.e_slots % (2 * kChunkEdges) == 0) {
+        const int64_t pairs = hg.e_slots / (2 * kChunkEdges);
+        std::vector<uint16_t> lo(static_cast<size_t>(hg.e_slots));
+        std::vector<uint32_t> dl(static_cast<size_t>(pairs) * 64 * 4, 0u), hi(static_cast<size_t>(pairs) * 64 * 2, 0u);
+        for (int64_t k = 0; k < hg.e_slots; ++k) {
+            const uint32_t src = static_cast<uint32_t>(hg.src[k]);
+            lo[k] = static_cast<uint16_t>(src & 0xFFFFu);
+            const int64_t c = k / kChunkEdges, lane = (k % kChunkEdges) / kEdgesPerLane, j = k % kEdgesPerLane;
+            const int64_t rec = (c / 2) * 64 + lane, half = c % 2;     // the lane's record in its pair
+            dl[rec * 4 + half * 2 + j / 4] |= static_cast<uint32_t>(hg.d[k]) << (8 * (j % 4));
+            hi[rec * 2 + half] |= (src >> 16) << (4 * j);
+        }
+        uint16_t* dlo = nullptr;
+        uint32_t *ddl = nullptr, *dhi = nullptr;
+        st = upload(h, &dlo, lo, lo.size(), s, "narrow edges");
+        if (st == NET_OK) st = upload(h, &ddl, dl, dl.size(), s, "narrow edges");
+        if (st == NET_OK) st = upload(h, &dhi, hi, hi.size(), s, "narrow edges");
+        if (st == NET_OK) {
+            const hipError_t se = hipStreamSynchronize(s);   // the host arrays are freed below
+            if (se != hipSuccess) st = device_fail(h, se, "net_build: upload");
+        }
+        if (st != NET_OK) return bail(st);
+        g.s_lo = dlo;
+        g.dl_pair = ddl;
+        g.hi_pair = dhi;
+    }
+    // the packed two-kernel delivery variant streams one word per slot,
+    // source | delay << 24 (sources below 2^24)
     const int bflags = opts ? opts->flags : 0;
-    if ((!hg.seg_vertex.empty() || (bflags & (NET_BUILD_DELIVER_PACKED | NET_BUILD_AUTOTUNE))) &&
-        g.n_pad < (int64_t(1) << 24)) {
+    if ((bflags & (NET_BUILD_DELIVER_PACKED | NET_BUILD_AUTOTUNE)) && g.n_pad < (int64_t(1) << 24)) {
         std::vector<uint32_t> packed(static_cast<size_t>(hg.e_slots));
         for (int64_t k = 0; k < hg.e_slots; ++k)
             packed[k] = static_cast<uint32_t>(hg.src[k]) | (static_cast<uint32_t>(hg.d[k]) << 24);

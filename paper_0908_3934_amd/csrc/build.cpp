@@ -298,6 +298,9 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
             g.seg_max = 0;
         }
     }
+    // segments start on even chunks and the slot array ends on one, so the
+    // fused step's units (chunk pairs) never straddle two segments
+    const int64_t seg_align = g.seg_vertex.empty() ? kChunkEdges : 2 * kChunkEdges;
     g.net_chunk_begin.assign(n_nets, 0);
     g.net_chunk_end.assign(n_nets, 0);
     int64_t used = 0;
@@ -306,7 +309,7 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
         g.net_chunk_begin[m] = used / kChunkEdges;
         for (int64_t r = g.node_off[m]; r < g.node_off[m + 1]; ++r) {
             if (seg_start[r]) {
-                used = (used + kChunkEdges - 1) / kChunkEdges * kChunkEdges;
+                used = (used + seg_align - 1) / seg_align * seg_align;
                 g.seg_chunk.push_back(static_cast<int32_t>(used / kChunkEdges));
             }
             row_ptr[r] = used;
@@ -315,8 +318,8 @@ net_status build_host_graph(const net_desc* descs, int32_t n_nets, HostGraph& g,
         g.net_chunk_end[m] = (used + kChunkEdges - 1) / kChunkEdges;
     }
     row_ptr[N] = used;
-    g.e_slots = (used + kChunkEdges - 1) / kChunkEdges * kChunkEdges;
-    if (g.e_slots == 0) g.e_slots = kChunkEdges;
+    g.e_slots = (used + seg_align - 1) / seg_align * seg_align;
+    if (g.e_slots == 0) g.e_slots = seg_align;
     if (g.e_slots > (int64_t(1) << 31) - kChunkEdges) {
         err = "net_build: more than 2^31 edge slots";
         return NET_E_RANGE;

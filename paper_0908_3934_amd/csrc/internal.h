@@ -145,7 +145,14 @@ struct DeviceGraph {
     const int32_t* src;
     const uint16_t* w;
     const uint8_t* d;
-    const uint32_t* sd = nullptr;   // fused step only: source | delay << 24 per slot
+    const uint32_t* sd = nullptr;   // packed two-kernel variant: source | delay << 24 per slot
+    // fused step's stream, 3.5 B per slot (sources below 2^20; chunks in
+    // pairs 2p, 2p+1): s_lo[slot] = source & 0xFFFF; per pair and lane, 16
+    // delay bytes (dl_pair, 4 words: the lane's 8 slots of chunk 2p, then of
+    // chunk 2p+1) and 16 nibbles of source >> 16 (hi_pair, 2 words, same order)
+    const uint16_t* s_lo = nullptr;
+    const uint32_t* dl_pair = nullptr;
+    const uint32_t* hi_pair = nullptr;
     const uint8_t* rowstart;
     const int32_t* chunk_row0;
     const NetParams* params;
@@ -288,10 +295,13 @@ struct MlpDevice {
     uint16_t* w1t = nullptr;      // BF16 W1 and W2 as the fused forward kernel holds them in LDS
     uint16_t* w2p = nullptr;      // (transposed, k reordered, 16-byte groups swizzled)
     uint16_t* Xb = nullptr;       // [cap x 64] BF16 standardised inputs of the last forward pass
-    uint16_t* H1 = nullptr;       // [cap x 256] BF16 activations and gradients
+    uint16_t* H1 = nullptr;       // [cap x 256] BF16 activations and gradients, row-major
     uint16_t* H2 = nullptr;
-    uint16_t* dH1 = nullptr;
     uint16_t* dH2 = nullptr;
+    uint16_t* Xbt = nullptr;      // transposed copies for the weight gradients: [64 x ldt], [256 x ldt]
+    uint16_t* H1t = nullptr;      // (ldt = the batch rows rounded up to 8, at most cap rounded up)
+    uint16_t* dH2t = nullptr;
+    uint16_t* dH1t = nullptr;
     float* logits = nullptr;      // [cap]
     float* loss = nullptr;        // [1]
     float* head_part = nullptr;   // [kHeadReplicas][kHeadPart] head gradient partial sums (zero between steps)
@@ -353,8 +363,9 @@ struct FitWork {
 hipError_t fit_prep(const FitInputs& in, const FitWork& w, hipStream_t s);
 hipError_t fit_eval(const FitInputs& in, const FitWork& w, hipStream_t s);
 
-hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const float* y, bool backward, hipStream_t s);
-hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, float* loss_out, hipStream_t s);
+int64_t mlp_ldt(int64_t B);
+hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const float* y, hipStream_t s);
+hipError_t mlp_backward(const MlpDevice& d, int64_t B, float* loss_out, hipStream_t s);
 // (also clears d.grad for the next accumulation)
 hipError_t mlp_adam(const MlpDevice& d, float lr, float beta1, float beta2, float eps, int64_t t, hipStream_t s);
 hipError_t mlp_refresh_bf16(const MlpDevice& d, hipStream_t s);

@@ -156,7 +156,10 @@ struct DeliverArgs {
     const int32_t* __restrict__ src;
     const uint16_t* __restrict__ w;
     const uint8_t* __restrict__ d;
-    const uint32_t* __restrict__ sd;   // source | delay << 24 per slot (fused step only)
+    const uint32_t* __restrict__ sd;   // source | delay << 24 per slot (packed two-kernel variant)
+    const uint16_t* __restrict__ s_lo;      // fused step: low 16 source bits per slot
+    const uint32_t* __restrict__ dl_pair;   // fused step: delays per chunk pair and lane (4 words)
+    const uint32_t* __restrict__ hi_pair;   // fused step: source >> 16 nibbles per chunk pair and lane (2 words)
     const uint8_t* __restrict__ rowstart;
     const int32_t* __restrict__ chunk_row0;
     const uint32_t* __restrict__ summary;
@@ -218,6 +221,35 @@ __device__ __forceinline__ uint32_t edge_src(const PackedChunk& x, int k) {
 }
 __device__ __forceinline__ uint32_t edge_delay(const PackedChunk& x, int k) {
     return (k < 4 ? comp4(x.lo, k) : comp4(x.hi, k - 4)) >> 24;
+}
+
+// One chunk of the fused step's 3.5 B-per-slot stream: the lane's 8 low
+// source halves, 8 delay bytes and 8 high source nibbles.
+struct NarrowChunk {
+    u32x4 lo;
+    u32x2 dl;
+    uint32_t hi;
+};
+__device__ __forceinline__ uint32_t edge_src(const NarrowChunk& x, int k) {
+    return ((comp4(x.lo, k >> 1) >> (16 * (k & 1))) & 0xFFFFu) | (((x.hi >> (4 * k)) & 0xFu) << 16);
+}
+__device__ __forceinline__ uint32_t edge_delay(const NarrowChunk& x, int k) {
+    return ((k < 4 ? x.dl.x : x.dl.y) >> (8 * (k & 3))) & 0xFFu;
+}
+
+// Chunks c and c + 1 (c even) of the narrow stream: four loads per lane
+// (16 B of low halves per chunk, 16 B of delays and 8 B of nibbles per pair).
+__device__ __forceinline__ void load_narrow_pair(NarrowChunk* x, const DeliverArgs& a, int64_t c, int lane) {
+    const int64_t e0 = c * kChunkEdges + lane * kEdgesPerLane;
+    x[0].lo = *reinterpret_cast<const u32x4*>(a.s_lo + e0);
+    x[1].lo = *reinterpret_cast<const u32x4*>(a.s_lo + e0 + kChunkEdges);
+    const int64_t rec = (c >> 1) * 64 + lane;
+    const u32x4 dl = *reinterpret_cast<const u32x4*>(a.dl_pair + rec * 4);
+    const u32x2 hi = *reinterpret_cast<const u32x2*>(a.hi_pair + rec * 2);
+    x[0].dl = u32x2{dl.x, dl.y};
+    x[1].dl = u32x2{dl.z, dl.w};
+    x[0].hi = hi.x;
+    x[1].hi = hi.y;
 }
 
 __device__ __forceinline__ void load_packed_chunk(PackedChunk& x, const uint32_t* sd, int64_t c, int lane) {
@@ -1271,11 +1303,10 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs s) {
     }
     __builtin_amdgcn_sched_barrier(0);   // issued first: waits count loads in issue order
     int64_t c = c_begin + static_cast<int64_t>(wave) * kPer;
-    // chunks beyond the range repeat the last one and are skipped below
-    // (every segment holds at least one chunk)
-    PackedChunk cur[kPer];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) load_packed_chunk(cur[u], s.d.sd, c + u < c_end ? c + u : c_end - 1, lane);
+    // a segment is a whole number of chunk pairs starting on an even chunk;
+    // units beyond it reload its last pair and are skipped below
+    NarrowChunk cur[kPer];
+    load_narrow_pair(cur, s.d, c < c_end ? c : c_end - kPer, lane);
     __builtin_amdgcn_sched_barrier(0);
     // the state of this workgroup's vertices (segments hold at most
     // kStepPrefetch * 1024) arrives while the edges stream; issued after the
@@ -1300,10 +1331,8 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs s) {
         // the next unit's stream loads go out behind this unit's gathers (past
         // the range they re-read this unit's chunks, which L2 still holds)
         const int64_t cn = c_begin + static_cast<int64_t>(__builtin_amdgcn_readfirstlane(claim)) * kPer;
-        PackedChunk nxt[kPer];
-#pragma unroll
-        for (int u = 0; u < kPer; ++u)
-            load_packed_chunk(nxt[u], s.d.sd, cn + u < c_end ? cn + u : (c + u < c_end ? c + u : c_end - 1), lane);
+        NarrowChunk nxt[kPer];
+        load_narrow_pair(nxt, s.d, cn < c_end ? cn : c, lane);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
@@ -1422,7 +1451,7 @@ hipError_t configure_deliver(DeviceGraph& g, const net_build_opts* opts, LaunchC
     // segment's inputs in LDS.
     lc.fused = false;
     // (queued arrivals are 32-bit slot indices: at most 2^23 chunks)
-    if ((flags & NET_BUILD_FUSED_STEP) && g.seg_vertex && g.sd && g.n_seg > 0 && lc.lds_summary && g.sum_shift == 0 &&
+    if ((flags & NET_BUILD_FUSED_STEP) && g.seg_vertex && g.s_lo && g.n_seg > 0 && lc.lds_summary && g.sum_shift == 0 &&
         summary_bytes <= static_cast<size_t>(kStepSummaryBytes) && g.n_chunks <= (int64_t(1) << 23)) {
         const size_t in_bytes = (static_cast<size_t>(g.seg_max) * sizeof(float) + 15) / 16 * 16;
         const size_t need = in_bytes + kStepQueueBytes + 16;   // beyond the summary: inputs, queues, counter
@@ -1449,6 +1478,9 @@ static DeliverArgs deliver_args(const DeviceGraph& g, const LaunchConfig& lc, in
     a.w = g.w;
     a.d = g.d;
     a.sd = g.sd;
+    a.s_lo = g.s_lo;
+    a.dl_pair = g.dl_pair;
+    a.hi_pair = g.hi_pair;
     a.rowstart = g.rowstart;
     a.chunk_row0 = g.chunk_row0;
     a.summary = g.summary;

@@ -64,6 +64,11 @@ __device__ __forceinline__ int w2_image_index(int k, int n) {
 // v_mfma_f32_32x32x16_bf16), K staged KS at a time (32 or 128); the next
 // stage's groups are loaded into registers while the current stage's MFMAs
 // run.  Split-K: blockIdx.z takes K range [z*k_chunk, min(K, (z+1)*k_chunk)).
+// BF16 epilogues go through LDS: the block's output tile is staged there
+// once and written with 16-byte stores, row-major into out_bf16 and/or
+// transposed into out_t ([N][ldt]: column n of C is row n of out_t, its
+// entries m0.. contiguous; entries M .. ldt-1 of every row are written as
+// zero, so that a later product may run its K over ldt, a multiple of 8).
 // ---------------------------------------------------------------------------
 enum Epilogue { kBiasReluBf16 = 0, kMaskBf16 = 1, kAtomicF32 = 2 };
 
@@ -74,7 +79,9 @@ struct GemmArgs {
     int64_t a_rs, a_cs, b_rs, b_cs;
     const float* bias;        // kBiasReluBf16: [N]
     const uint16_t* mask;     // kMaskBf16: BF16 [M x N] row-major; keep where > 0
-    uint16_t* out_bf16;       // [M x N] row-major
+    uint16_t* out_bf16;       // [M x N] row-major, or null
+    uint16_t* out_t;          // [N x ldt] transposed, or null (BF16 epilogues)
+    int64_t ldt;              // row length of out_t (>= M, a multiple of 8)
     float* out_f32;           // [M x N] row-major (atomic add)
 };
 
@@ -155,11 +162,21 @@ __device__ __forceinline__ void store_stage(const StageRegs<BM, BN, KS>& r, bool
 
 // Block tile BM x BN (64 or 128 each), four waves in a 2 x 2 arrangement,
 // each wave (BM/2) x (BN/2) = TM x TN tiles of 32 x 32.
+// LDS of a block: the A and B stages during the K loop; afterwards the
+// output tile (and for kMaskBf16 the mask tile), rows padded by 8.
+template <int kEpi, int BM, int BN, int KS>
+constexpr int gemm_lds_elems() {
+    constexpr int stage = (BM + BN) * lds_k<KS>();
+    constexpr int out = (kEpi == kMaskBf16 ? 2 : 1) * BM * (BN + 8);
+    return kEpi == kAtomicF32 ? stage : (stage > out ? stage : out);
+}
+
 template <int kEpi, int BM, int BN, int KS>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
     constexpr int TM = BM / 64, TN = BN / 64;
-    __shared__ __attribute__((aligned(16))) uint16_t As[BM][lds_k<KS>()];   // [m][k]
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][lds_k<KS>()];   // [n][k]
+    __shared__ __attribute__((aligned(16))) uint16_t lds[gemm_lds_elems<kEpi, BM, BN, KS>()];
+    uint16_t (*As)[lds_k<KS>()] = reinterpret_cast<uint16_t (*)[lds_k<KS>()]>(lds);                      // [m][k]
+    uint16_t (*Bs)[lds_k<KS>()] = reinterpret_cast<uint16_t (*)[lds_k<KS>()]>(lds + BM * lds_k<KS>());   // [n][k]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int64_t m0 = static_cast<int64_t>(blockIdx.y) * BM, n0 = static_cast<int64_t>(blockIdx.x) * BN;
@@ -197,47 +214,124 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
         __syncthreads();
     }
     // acc[tm][tn][i] holds C[m][n]: n = lane % 32, m = 8*(i/4) + 4*(lane/32) + i%4 within the 32 x 32 tile
+    if constexpr (kEpi == kAtomicF32) {
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+            for (int tn = 0; tn < TN; ++tn) {
+                const int64_t n = n0 + wn * (BN / 2) + tn * 32 + (lane & 31);
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int64_t m = m0 + wm * (BM / 2) + tm * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+                    if (m < g.M && n < g.N) atomicAdd(g.out_f32 + m * g.N + n, acc[tm][tn][i]);
+                }
+            }
+        return;
+    }
+    // (the K loop ended on a barrier: the stages' LDS is free)
+    constexpr int CW = BN + 8;
+    uint16_t (*Cs)[CW] = reinterpret_cast<uint16_t (*)[CW]>(lds);
+    uint16_t (*Ms)[CW] = reinterpret_cast<uint16_t (*)[CW]>(lds + BM * CW);
+    constexpr int groups = BM * BN / 8;          // 16-byte groups of the tile
+    if constexpr (kEpi == kMaskBf16) {
+        // the mask tile, row-major 16-byte groups (N is a multiple of 8)
+        for (int e = tid; e < groups; e += 256) {
+            const int r = e / (BN / 8), c = (e % (BN / 8)) * 8;
+            const int64_t m = m0 + r, n = n0 + c;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (m < g.M && n < g.N) v = *reinterpret_cast<const uint4*>(g.mask + m * g.N + n);
+            *reinterpret_cast<uint4*>(&Ms[r][c]) = v;
+        }
+        __syncthreads();
+    }
 #pragma unroll
     for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
         for (int tn = 0; tn < TN; ++tn) {
-            const int64_t n = n0 + wn * (BN / 2) + tn * 32 + (lane & 31);
+            const int nl = wn * (BN / 2) + tn * 32 + (lane & 31);
+            const int64_t n = n0 + nl;
+            float bn = 0.0f;
+            if (kEpi == kBiasReluBf16) bn = n < g.N ? g.bias[n] : 0.0f;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int64_t m = m0 + wm * (BM / 2) + tm * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-                if (m >= g.M || n >= g.N) continue;
+                const int ml = wm * (BM / 2) + tm * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
                 const float v = acc[tm][tn][i];
+                float o;
                 if (kEpi == kBiasReluBf16) {
-                    const float h = v + g.bias[n];
-                    g.out_bf16[m * g.N + n] = f32_to_bf16_bits(h > 0.0f ? h : 0.0f);
-                } else if (kEpi == kMaskBf16) {
-                    const float keep = bf16_bits_to_f32(g.mask[m * g.N + n]) > 0.0f ? 1.0f : 0.0f;
-                    g.out_bf16[m * g.N + n] = f32_to_bf16_bits(v * keep);
+                    const float h = v + bn;
+                    o = h > 0.0f ? h : 0.0f;
                 } else {
-                    atomicAdd(g.out_f32 + m * g.N + n, v);
+                    o = v * (bf16_bits_to_f32(Ms[ml][nl]) > 0.0f ? 1.0f : 0.0f);
                 }
+                Cs[ml][nl] = f32_to_bf16_bits(o);
             }
         }
+    __syncthreads();
+    if (g.out_bf16) {
+        for (int e = tid; e < groups; e += 256) {
+            const int r = e / (BN / 8), c = (e % (BN / 8)) * 8;
+            const int64_t m = m0 + r, n = n0 + c;
+            if (m < g.M && n < g.N)
+                *reinterpret_cast<uint4*>(g.out_bf16 + m * g.N + n) = *reinterpret_cast<const uint4*>(&Cs[r][c]);
+        }
+    }
+    if (g.out_t) {
+        // group e: column c of the tile, rows r .. r+7 (consecutive threads take
+        // consecutive row groups of one column, so their stores are contiguous)
+        for (int e = tid; e < groups; e += 256) {
+            const int c = e / (BM / 8), r = (e % (BM / 8)) * 8;
+            const int64_t m = m0 + r, n = n0 + c;
+            if (n >= g.N || m >= g.ldt) continue;
+            uint32_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t lo = m + 2 * q < g.M ? Cs[r + 2 * q][c] : 0u;
+                const uint32_t hi = m + 2 * q + 1 < g.M ? Cs[r + 2 * q + 1][c] : 0u;
+                w[q] = lo | (hi << 16);
+            }
+            *reinterpret_cast<uint4*>(g.out_t + n * g.ldt + m) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
 }
 
 // Input standardisation and the first rounding point: Xb = BF16((X - shift) * scale)
-// for a [B][64] FP32 feature matrix; one thread per 8 features of a row.
+// for a [B][64] FP32 feature matrix, written row-major (Xb) and transposed
+// (Xbt [64][ldt], rows B .. ldt-1 zero).  One workgroup per 64 rows: the
+// tile is rounded into LDS, then written with 16-byte stores both ways.
 __global__ void __launch_bounds__(256) normalize_kernel(const float* X, const float* shift, const float* scale,
-                                                        uint16_t* Xb, int64_t n8) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n8) return;
-    const int f0 = static_cast<int>((i * 8) % kMlpIn);
-    const float4 x0 = reinterpret_cast<const float4*>(X)[2 * i];
-    const float4 x1 = reinterpret_cast<const float4*>(X)[2 * i + 1];
-    const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-    uint32_t w[4];
+                                                        uint16_t* Xb, uint16_t* Xbt, int64_t B, int64_t ldt) {
+    __shared__ __attribute__((aligned(16))) uint16_t T[64][kMlpIn + 8];
+    const int tid = threadIdx.x;
+    const int64_t m0 = static_cast<int64_t>(blockIdx.x) * 64;
+    {
+        const int r = tid >> 2, f0 = (tid & 3) * 16;
+        const int64_t m = m0 + r;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t lo = f32_to_bf16_bits((x[2 * j] - shift[f0 + 2 * j]) * scale[f0 + 2 * j]);
-        const uint32_t hi = f32_to_bf16_bits((x[2 * j + 1] - shift[f0 + 2 * j + 1]) * scale[f0 + 2 * j + 1]);
-        w[j] = lo | (hi << 16);
+        for (int q = 0; q < 4; ++q) {
+            float4 x = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (m < B) x = reinterpret_cast<const float4*>(X + m * kMlpIn + f0)[q];
+            const float v[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int f = f0 + 4 * q + k;
+                T[r][f] = m < B ? f32_to_bf16_bits((v[k] - shift[f]) * scale[f]) : static_cast<uint16_t>(0);
+            }
+        }
     }
-    reinterpret_cast<uint4*>(Xb)[i] = make_uint4(w[0], w[1], w[2], w[3]);
+    __syncthreads();
+    for (int e = tid; e < 64 * kMlpIn / 8; e += 256) {
+        const int r = e / (kMlpIn / 8), c = (e % (kMlpIn / 8)) * 8;
+        if (m0 + r < B) *reinterpret_cast<uint4*>(Xb + (m0 + r) * kMlpIn + c) = *reinterpret_cast<const uint4*>(&T[r][c]);
+    }
+    for (int e = tid; e < 64 * kMlpIn / 8; e += 256) {
+        const int f = e / 8, r = (e % 8) * 8;
+        const int64_t m = m0 + r;
+        if (m >= ldt) continue;
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = static_cast<uint32_t>(T[r + 2 * q][f]) | (static_cast<uint32_t>(T[r + 2 * q + 1][f]) << 16);
+        *reinterpret_cast<uint4*>(Xbt + f * ldt + m) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
 }
 
 // Column statistics of a [rows][64] FP32 feature matrix, in FP64 with a
@@ -341,87 +435,105 @@ struct HeadArgs {
     const uint16_t* H2;
     const float* w3;
     const float* b3;
-    const float* y;          // null for inference
+    const float* y;
     float* logits;
-    uint16_t* dH2;
+    uint16_t* dH2;           // [B][256] row-major
+    uint16_t* dH2t;          // [256][ldt] transposed, rows B .. ldt-1 zero
     float* part;             // [kHeadReplicas][kHeadPart]: w3 gradient, b2 gradient (column sums of the BF16
                              // dH2), b3 gradient, loss (sum of per-row losses / B)
-    int64_t B;
+    int64_t B, ldt;
 };
 
-// Head and loss: one wave per row, rows strided over the grid.  The w3, b3
-// and b2 gradients and the loss are summed in registers over a wave's rows,
-// then over the workgroup in LDS, and added once per workgroup into replica
-// (workgroup mod kHeadReplicas) of the partial sums; head_finish adds the
-// replicas into the gradient.
+// Head, loss and dH2 for 64 rows per workgroup: the H2 tile is staged in
+// LDS with 16-byte loads; four threads per row form the logit (64 products
+// each, then two exchanges); each thread then owns one column for the dH2
+// values (rounded to BF16 in place in LDS) and that column's w3 and b2
+// gradient sums; dH2 leaves row-major and transposed with 16-byte stores.
+// The per-workgroup sums go into replica (workgroup mod kHeadReplicas) of
+// the partial sums; head_finish adds the replicas into the gradient.
 __global__ void __launch_bounds__(256) head_kernel(HeadArgs a) {
-    __shared__ float red[4][2 * kMlpH + 2];
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int64_t n_waves = static_cast<int64_t>(gridDim.x) * 4;
-    float w3r[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) w3r[q] = a.w3[q * 64 + lane];
-    const float b3 = a.b3[0];
-    const float inv_b = 1.0f / static_cast<float>(a.B);
-    float gw3[4] = {0.0f, 0.0f, 0.0f, 0.0f}, gb2[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    float gl = 0.0f, gb3 = 0.0f;
-    // kRows rows per pass, their loads issued together
-    constexpr int kRows = 4;
-    for (int64_t row0 = static_cast<int64_t>(blockIdx.x) * 4 + wave; row0 < a.B; row0 += kRows * n_waves) {
-        float h[kRows][4], y[kRows];
-#pragma unroll
-        for (int r = 0; r < kRows; ++r) {
-            const int64_t row = row0 + r * n_waves;
-            const int64_t rr = row < a.B ? row : row0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) h[r][q] = bf16_bits_to_f32(a.H2[rr * kMlpH + q * 64 + lane]);
-            y[r] = a.y ? a.y[rr] : 0.0f;
-        }
-#pragma unroll
-        for (int r = 0; r < kRows; ++r) {
-            const int64_t row = row0 + r * n_waves;
-            if (row >= a.B) break;                  // uniform over the wave
-            float s = 0.0f;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) s += h[r][q] * w3r[q];
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-            const float logit = s + b3;
-            if (lane == 0) a.logits[row] = logit;
-            if (!a.y) continue;
-            const float p = 1.0f / (1.0f + expf(-logit));
-            const float dl = (p - y[r]) * inv_b;
-            // log(1 + exp(-|z|)) + max(z, 0) - z*y
-            gl += (log1pf(expf(-fabsf(logit))) + fmaxf(logit, 0.0f) - logit * y[r]) * inv_b;
-            gb3 += dl;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint16_t g = f32_to_bf16_bits(h[r][q] > 0.0f ? dl * w3r[q] : 0.0f);
-                a.dH2[row * kMlpH + q * 64 + lane] = g;
-                gb2[q] += bf16_bits_to_f32(g);
-                gw3[q] += dl * h[r][q];
-            }
-        }
-    }
-    if (!a.y) return;                        // uniform over the grid
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        red[wave][q * 64 + lane] = gw3[q];
-        red[wave][kMlpH + q * 64 + lane] = gb2[q];
-    }
-    if (lane == 0) {
-        red[wave][2 * kMlpH] = gl;           // every lane holds the same row sums
-        red[wave][2 * kMlpH + 1] = gb3;
+    constexpr int HW = kMlpH + 8;
+    __shared__ __attribute__((aligned(16))) uint16_t Hs[64][HW];
+    __shared__ float dls[64], ls[64];
+    const int tid = threadIdx.x;
+    const int64_t m0 = static_cast<int64_t>(blockIdx.x) * 64;
+    for (int e = tid; e < 64 * kMlpH / 8; e += 256) {
+        const int r = e / (kMlpH / 8), c = (e % (kMlpH / 8)) * 8;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (m0 + r < a.B) v = *reinterpret_cast<const uint4*>(a.H2 + (m0 + r) * kMlpH + c);
+        *reinterpret_cast<uint4*>(&Hs[r][c]) = v;
     }
     __syncthreads();
-    const int n = threadIdx.x;
-    float* part = a.part + (blockIdx.x % kHeadReplicas) * kHeadPart;
-    atomicAdd(part + n, red[0][n] + red[1][n] + red[2][n] + red[3][n]);
-    atomicAdd(part + kMlpH + n, red[0][kMlpH + n] + red[1][kMlpH + n] + red[2][kMlpH + n] + red[3][kMlpH + n]);
-    if (n < 2)
-        atomicAdd(part + 2 * kMlpH + n, red[0][2 * kMlpH + n] + red[1][2 * kMlpH + n] + red[2][2 * kMlpH + n] +
-                                            red[3][2 * kMlpH + n]);
+    {
+        const int r = tid >> 2, part = tid & 3;
+        float s = 0.0f;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            const int c = part * 64 + g * 8;
+            const uint4 v = *reinterpret_cast<const uint4*>(&Hs[r][c]);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                s += bf16_bits_to_f32(static_cast<uint16_t>(w[q] & 0xFFFFu)) * a.w3[c + 2 * q];
+                s += bf16_bits_to_f32(static_cast<uint16_t>(w[q] >> 16)) * a.w3[c + 2 * q + 1];
+            }
+        }
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (part == 0) {
+            const int64_t m = m0 + r;
+            float dl = 0.0f, l = 0.0f;
+            if (m < a.B) {
+                const float logit = s + a.b3[0];
+                a.logits[m] = logit;
+                const float inv_b = 1.0f / static_cast<float>(a.B);
+                const float y = a.y[m];
+                const float p = 1.0f / (1.0f + expf(-logit));
+                dl = (p - y) * inv_b;
+                // log(1 + exp(-|z|)) + max(z, 0) - z*y
+                l = (log1pf(expf(-fabsf(logit))) + fmaxf(logit, 0.0f) - logit * y) * inv_b;
+            }
+            dls[r] = dl;
+            ls[r] = l;
+        }
+    }
+    __syncthreads();
+    {
+        const int n = tid;
+        const float w3n = a.w3[n];
+        float gw3 = 0.0f, gb2 = 0.0f;
+        for (int r = 0; r < 64; ++r) {
+            const float h = bf16_bits_to_f32(Hs[r][n]);
+            const float dl = dls[r];
+            const uint16_t g = f32_to_bf16_bits(h > 0.0f ? dl * w3n : 0.0f);
+            Hs[r][n] = g;
+            gb2 += bf16_bits_to_f32(g);
+            gw3 += dl * h;
+        }
+        float* part = a.part + (blockIdx.x % kHeadReplicas) * kHeadPart;
+        atomicAdd(part + n, gw3);
+        atomicAdd(part + kMlpH + n, gb2);
+        if (n < 2) {
+            float acc = 0.0f;
+            for (int r = 0; r < 64; ++r) acc += n == 0 ? ls[r] : dls[r];
+            atomicAdd(part + 2 * kMlpH + n, acc);
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < 64 * kMlpH / 8; e += 256) {
+        const int r = e / (kMlpH / 8), c = (e % (kMlpH / 8)) * 8;
+        if (m0 + r < a.B) *reinterpret_cast<uint4*>(a.dH2 + (m0 + r) * kMlpH + c) = *reinterpret_cast<const uint4*>(&Hs[r][c]);
+    }
+    for (int e = tid; e < 64 * kMlpH / 8; e += 256) {
+        const int n = e / 8, r = (e % 8) * 8;
+        const int64_t m = m0 + r;
+        if (m >= a.ldt) continue;
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            w[q] = static_cast<uint32_t>(Hs[r + 2 * q][n]) | (static_cast<uint32_t>(Hs[r + 2 * q + 1][n]) << 16);
+        *reinterpret_cast<uint4*>(a.dH2t + n * a.ldt + m) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
 }
 
 // The head's replicas summed in a fixed order into the gradient (w3, b2, b3)
@@ -444,43 +556,35 @@ __device__ __forceinline__ void head_finish(float* part, float* grad, float* los
     }
 }
 
-// Column sums of a [B][256] BF16 matrix into out (atomic, once per
-// workgroup): each thread owns two adjacent columns of every other row of
-// its workgroup's row range.
-// The last workgroup of the launch instead finishes the head's sums.
-__global__ void __launch_bounds__(256) colsum_kernel(const uint16_t* X, int64_t B, float* out, float* head_part,
+// b1 gradient: row sums of dH1t ([256][ldt] BF16, the transposed dH1; its
+// padding is zero), one workgroup per row, 16-byte loads, a fixed order
+// within the workgroup.  The last workgroup of the launch instead finishes
+// the head's sums.
+__global__ void __launch_bounds__(256) rowsum_kernel(const uint16_t* Xt, int64_t ldt, float* out, float* head_part,
                                                      float* grad, float* loss, float* loss_out) {
-    __shared__ float red[2][kMlpH];
+    __shared__ float red[256];
     if (blockIdx.x == gridDim.x - 1) {
         head_finish(head_part, grad, loss, loss_out);
         return;
     }
     const int t = threadIdx.x;
-    const int cp = t & 127, ro = t >> 7;
-    const int64_t rows_per = (B + gridDim.x - 2) / (gridDim.x - 1);
-    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rows_per;
-    const int64_t r1 = r0 + rows_per < B ? r0 + rows_per : B;
-    const uint32_t* X32 = reinterpret_cast<const uint32_t*>(X);
-    float s0 = 0.0f, s1 = 0.0f;
-    // eight rows' loads in flight per pass (rows past r1 read row r0 and add 0)
-    for (int64_t rb = r0 + ro; rb < r1; rb += 16) {
-        uint32_t v[8];
+    const uint4* row = reinterpret_cast<const uint4*>(Xt + static_cast<int64_t>(blockIdx.x) * ldt);
+    const int64_t groups = ldt / 8;
+    float s = 0.0f;
+    for (int64_t q = t; q < groups; q += 256) {
+        const uint4 v = row[q];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int64_t r = rb + 2 * q;
-            v[q] = X32[(r < r1 ? r : r0) * (kMlpH / 2) + cp];
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const bool in = rb + 2 * q < r1;
-            s0 += in ? bf16_bits_to_f32(v[q] & 0xFFFFu) : 0.0f;
-            s1 += in ? bf16_bits_to_f32(v[q] >> 16) : 0.0f;
-        }
+        for (int k = 0; k < 4; ++k)
+            s += bf16_bits_to_f32(static_cast<uint16_t>(w[k] & 0xFFFFu)) + bf16_bits_to_f32(static_cast<uint16_t>(w[k] >> 16));
     }
-    red[ro][2 * cp] = s0;
-    red[ro][2 * cp + 1] = s1;
+    red[t] = s;
     __syncthreads();
-    if (r1 > r0) atomicAdd(out + t, red[0][t] + red[1][t]);
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    if (t == 0) out[blockIdx.x] += red[0];
 }
 
 // Adam on the flat FP32 parameter vector; refreshes the BF16 copies of W1, W2.
@@ -742,13 +846,17 @@ hipError_t gemm(const GemmArgs& g, int split, hipStream_t s) {
 
 }  // namespace
 
-// Forward pass for B rows of features X (FP32 [B x 64]); fills H1, H2 and logits.
-hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const float* y, bool backward,
-                       hipStream_t s) {
+// Row length of the transposed activations of a B-row batch.
+int64_t mlp_ldt(int64_t B) { return (B + 7) / 8 * 8; }
+
+// Training forward pass for B rows of features X (FP32 [B x 64]) with
+// labels y: Xb (and Xbt), H1 (and H1t), H2, the logits, dH2 (and dH2t) and
+// the head's gradient sums.
+hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const float* y, hipStream_t s) {
     const float* p = d.params;
-    const int64_t n8 = B * kMlpIn / 8;
-    hipLaunchKernelGGL(normalize_kernel, dim3(static_cast<unsigned>((n8 + 255) / 256)), dim3(256), 0, s, X,
-                       d.in_shift, d.in_scale, d.Xb, n8);
+    const int64_t ldt = mlp_ldt(B);
+    const unsigned tiles = static_cast<unsigned>((B + 63) / 64);
+    hipLaunchKernelGGL(normalize_kernel, dim3(tiles), dim3(256), 0, s, X, d.in_shift, d.in_scale, d.Xb, d.Xbt, B, ldt);
     GemmArgs g1{};
     g1.A = d.Xb;
     g1.B = d.w1b;
@@ -762,6 +870,8 @@ hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const floa
     g1.b_cs = 1;
     g1.bias = p + kMlpB1Off;
     g1.out_bf16 = d.H1;
+    g1.out_t = d.H1t;
+    g1.ldt = ldt;
     hipError_t e = gemm<kBiasReluBf16>(g1, 1, s);
     if (e != hipSuccess) return e;
     GemmArgs g2 = g1;
@@ -772,45 +882,57 @@ hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const floa
     g2.a_rs = kMlpH;
     g2.bias = p + kMlpB2Off;
     g2.out_bf16 = d.H2;
+    g2.out_t = nullptr;
     e = gemm<kBiasReluBf16>(g2, 1, s);
     if (e != hipSuccess) return e;
     HeadArgs h{};
     h.H2 = d.H2;
     h.w3 = p + kMlpW3Off;
     h.b3 = p + kMlpB3Off;
-    h.y = backward ? y : nullptr;
+    h.y = y;
     h.logits = d.logits;
     h.dH2 = d.dH2;
+    h.dH2t = d.dH2t;
     h.part = d.head_part;
     h.B = B;
-    // ~4 rows per wave (one pass): four workgroups per CU at 16,384 rows
-    const int64_t hb = std::min<int64_t>(std::max<int64_t>((B + 15) / 16, 1), 2048);
-    hipLaunchKernelGGL(head_kernel, dim3(static_cast<unsigned>(hb)), dim3(256), 0, s, h);
+    h.ldt = ldt;
+    hipLaunchKernelGGL(head_kernel, dim3(tiles), dim3(256), 0, s, h);
     return hipGetLastError();
 }
 
-// Backward pass after mlp_forward(..., backward = true): accumulates the
-// gradient of the mean BCE into d.grad (which the caller zeroed).
-hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, float* loss_out, hipStream_t s) {
-    // split-K over chunks of 512 rows (the weight-gradient tiles alone are too few)
-    const int split = static_cast<int>(std::max<int64_t>((B + 511) / 512, 1));
-    const int64_t k_chunk = ((B + split - 1) / split + 127) / 128 * 128;
-    // dW2 = H1^T dH2  (M = 256, N = 256, K = B)
+// Split-K of a weight gradient (K = the batch rows, padded to ldt): chunks
+// of at least `rows` rows, in multiples of 128.
+static void weight_split(int64_t ldt, int64_t rows, int* split, int64_t* chunk) {
+    const int64_t sp = std::max<int64_t>((ldt + rows - 1) / rows, 1);
+    *chunk = ((ldt + sp - 1) / sp + 127) / 128 * 128;
+    *split = static_cast<int>((ldt + *chunk - 1) / *chunk);
+}
+
+// Backward pass after mlp_forward: accumulates the gradient of the mean BCE
+// into d.grad (which the caller zeroed).  Every product reads k-contiguous
+// operands: the weight gradients take the transposed activations.
+hipError_t mlp_backward(const MlpDevice& d, int64_t B, float* loss_out, hipStream_t s) {
+    const int64_t ldt = mlp_ldt(B);
+    // dW2 = H1^T dH2  (M = 256, N = 256, K = ldt): 16 tiles, chunks of 2,048
+    // rows (512 workgroups at 65,536 rows; fewer chunks, fewer atomics)
+    int split = 1;
+    int64_t chunk = ldt;
+    weight_split(ldt, 2048, &split, &chunk);
     GemmArgs w2{};
-    w2.A = d.H1;
-    w2.B = d.dH2;
+    w2.A = d.H1t;
+    w2.B = d.dH2t;
     w2.M = kMlpH;
     w2.N = kMlpH;
-    w2.K = B;
-    w2.k_chunk = k_chunk;
-    w2.a_rs = 1;
-    w2.a_cs = kMlpH;
-    w2.b_rs = kMlpH;
-    w2.b_cs = 1;
+    w2.K = ldt;
+    w2.k_chunk = chunk;
+    w2.a_rs = ldt;
+    w2.a_cs = 1;
+    w2.b_rs = 1;
+    w2.b_cs = ldt;
     w2.out_f32 = d.grad + kMlpW2Off;
     hipError_t e = gemm<kAtomicF32>(w2, split, s);
     if (e != hipSuccess) return e;
-    // dH1 = BF16((dH2 W2^T) * [H1 > 0])  (M = B, N = 256, K = 256)
+    // dH1 = BF16((dH2 W2^T) * [H1 > 0])  (M = B, N = 256, K = 256), written transposed
     GemmArgs h1{};
     h1.A = d.dH2;
     h1.B = d.w2b;
@@ -823,28 +945,26 @@ hipError_t mlp_backward(const MlpDevice& d, const float* X, int64_t B, float* lo
     h1.b_rs = 1;          // B(k, n) = W2(n, k)
     h1.b_cs = kMlpH;
     h1.mask = d.H1;
-    h1.out_bf16 = d.dH1;
+    h1.out_t = d.dH1t;
+    h1.ldt = ldt;
     if ((e = gemm<kMaskBf16>(h1, 1, s)) != hipSuccess) return e;
-    // dW1 = X^T dH1  (M = 64, N = 256, K = B), X rounded to BF16 on staging;
-    // only four output tiles, so split-K over chunks of 256 rows (256
-    // workgroups at 16,384 rows; 512-row chunks leave half the CUs idle)
-    const int split1 = static_cast<int>(std::max<int64_t>((B + 255) / 256, 1));
+    // dW1 = Xb^T dH1  (M = 64, N = 256, K = ldt): four tiles, chunks of 512 rows
+    weight_split(ldt, 512, &split, &chunk);
     GemmArgs w1{};
-    w1.A = d.Xb;                       // the forward pass's normalised BF16 inputs
-    w1.B = d.dH1;
+    w1.A = d.Xbt;
+    w1.B = d.dH1t;
     w1.M = kMlpIn;
     w1.N = kMlpH;
-    w1.K = B;
-    w1.k_chunk = ((B + split1 - 1) / split1 + 127) / 128 * 128;
-    w1.a_rs = 1;
-    w1.a_cs = kMlpIn;
-    w1.b_rs = kMlpH;
-    w1.b_cs = 1;
+    w1.K = ldt;
+    w1.k_chunk = chunk;
+    w1.a_rs = ldt;
+    w1.a_cs = 1;
+    w1.b_rs = 1;
+    w1.b_cs = ldt;
     w1.out_f32 = d.grad + kMlpW1Off;
-    if ((e = gemm<kAtomicF32>(w1, split1, s)) != hipSuccess) return e;
-    const unsigned cs_blocks = static_cast<unsigned>(std::min<int64_t>(std::max<int64_t>((B + 63) / 64, 1), 1024));
-    // b1 gradient: column sums of dH1, plus one workgroup that finishes the head's sums
-    hipLaunchKernelGGL(colsum_kernel, dim3(cs_blocks + 1), dim3(256), 0, s, d.dH1, B, d.grad + kMlpB1Off,
+    if ((e = gemm<kAtomicF32>(w1, split, s)) != hipSuccess) return e;
+    // b1 gradient: row sums of dH1t, plus one workgroup that finishes the head's sums
+    hipLaunchKernelGGL(rowsum_kernel, dim3(kMlpH + 1), dim3(256), 0, s, d.dH1t, ldt, d.grad + kMlpB1Off,
                        d.head_part, d.grad, d.loss, loss_out);
     return hipGetLastError();
 }

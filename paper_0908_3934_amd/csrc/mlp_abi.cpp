@@ -52,9 +52,9 @@ void drop(const net_mlp* m, T** p, hipStream_t s = nullptr) {
 
 void release(net_mlp* m) {
     MlpDevice& d = m->d;
-    void* ps[] = {d.params, d.adam_m, d.adam_v, d.grad,   d.w1b,  d.w2b,      d.w1t,      d.w2p, d.Xb,
-                  d.H1,     d.H2,     d.dH1,    d.dH2,    d.logits, d.loss, d.in_shift, d.in_scale, d.head_part,
-                  m->xs,    m->ys,    m->stat_part};
+    void* ps[] = {d.params, d.adam_m, d.adam_v, d.grad,     d.w1b,  d.w2b,      d.w1t,      d.w2p,
+                  d.Xb,     d.H1,     d.H2,     d.dH2,      d.Xbt,  d.H1t,      d.dH2t,     d.dH1t,
+                  d.logits, d.loss,   d.in_shift, d.in_scale, d.head_part, m->xs, m->ys,      m->stat_part};
     for (void* p : ps) m->al.put(p, nullptr);
     d = MlpDevice{};
     m->xs = m->ys = nullptr;
@@ -68,14 +68,17 @@ net_status reserve(net_mlp* m, int64_t rows, hipStream_t s) {
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return mdev(m, e, "net_mlp: workspace");
     m->d.cap = 0;
-    uint16_t** bufs[] = {&m->d.H1, &m->d.H2, &m->d.dH1, &m->d.dH2};
+    const size_t rp = static_cast<size_t>(mlp_ldt(rows));
+    uint16_t** bufs[] = {&m->d.H1, &m->d.H2, &m->d.dH2, &m->d.H1t, &m->d.dH2t, &m->d.dH1t};
     for (uint16_t** b : bufs) {
         drop(m, b, s);
-        if (alloc(m, b, static_cast<size_t>(rows) * kMlpH, s) != hipSuccess) return mfail(NET_E_OOM, "net_mlp: workspace");
+        if (alloc(m, b, rp * kMlpH, s) != hipSuccess) return mfail(NET_E_OOM, "net_mlp: workspace");
     }
-    drop(m, &m->d.Xb, s);
-    if (alloc(m, &m->d.Xb, static_cast<size_t>(rows) * kMlpIn, s) != hipSuccess)
-        return mfail(NET_E_OOM, "net_mlp: workspace");
+    uint16_t** ibufs[] = {&m->d.Xb, &m->d.Xbt};
+    for (uint16_t** b : ibufs) {
+        drop(m, b, s);
+        if (alloc(m, b, rp * kMlpIn, s) != hipSuccess) return mfail(NET_E_OOM, "net_mlp: workspace");
+    }
     drop(m, &m->d.logits, s);
     if (alloc(m, &m->d.logits, static_cast<size_t>(rows), s) != hipSuccess) return mfail(NET_E_OOM, "net_mlp: workspace");
     m->d.cap = rows;
@@ -184,8 +187,8 @@ static net_status grad_impl(net_mlp* m, const float* x, const float* y, int64_t 
     hipError_t e = hipSuccess;
     if (!m->grad_clear) e = hipMemsetAsync(m->d.grad, 0, kMlpParams * sizeof(float), s);
     m->grad_clear = false;
-    if (e == hipSuccess) e = mlp_forward(m->d, x, rows, y, true, s);
-    if (e == hipSuccess) e = mlp_backward(m->d, x, rows, loss_out, s);
+    if (e == hipSuccess) e = mlp_forward(m->d, x, rows, y, s);
+    if (e == hipSuccess) e = mlp_backward(m->d, rows, loss_out, s);
     if (e != hipSuccess) return mdev(m, e, "net_mlp: gradient");
     return NET_OK;
 }
