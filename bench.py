@@ -35,7 +35,8 @@ BYTES_PER_EDGE = 5
 BYTES_PER_ARRIVAL = 2
 BYTES_PER_VERTEX = 18
 # What the stream formats themselves move (reported beside the fraction):
-BYTES_PER_EDGE_PACKED = 4   # fused step and packed delivery: one word per edge, source | delay << 24
+BYTES_PER_EDGE_PACKED = 4   # packed two-kernel delivery: one word per edge, source | delay << 24
+BYTES_PER_EDGE_NARROW = 3.5  # fused step: 16 + 4 source bits and the delay byte per edge
 BYTES_PER_EDGE_STREAMED_W = 7   # delivery variant that streams every weight with its edge
 # fused step's vertex update: V read + written (8), two-spike ages read +
 # written (4), history-ring word read + written (8), one summary bit (1/8)
@@ -143,18 +144,23 @@ def cpu_baseline(spec, steps):
     }
 
 
-def arrivals_per_step(net, spec, steps):
-    """Mean number of edges that deliver a spike per step over the next
-    `steps` steps, which are recorded: sum over sources of spikes x
-    out-degree, divided by the steps."""
-    import numpy as np
+def spikes_per_vertex(net, spec, steps):
+    """Spike counts of every vertex over the next `steps` steps (recorded)."""
     import torch
     words = net.step(steps, raster=True)["raster"]
     torch.cuda.synchronize()
     counts = torch.zeros(words.shape[1], 64, dtype=torch.int64, device=words.device)
     for b in range(64):
         counts[:, b] = ((words >> b) & 1).sum(0)
-    per_vertex = counts.reshape(-1)[:spec.n].cpu().numpy()
+    return counts.reshape(-1)[:spec.n].cpu().numpy()
+
+
+def arrivals_per_step(net, spec, steps):
+    """Mean number of edges that deliver a spike per step over the next
+    `steps` steps, which are recorded: sum over sources of spikes x
+    out-degree, divided by the steps."""
+    import numpy as np
+    per_vertex = spikes_per_vertex(net, spec, steps)
     outdeg = np.bincount(np.asarray(spec.src), minlength=spec.n)
     return float((per_vertex * outdeg).sum()) / steps
 
@@ -185,20 +191,38 @@ def bench_ensemble(args, torch, synth, gn):
     tm = net.timing_end()
     net.close()
     log("ensemble: %d steps in %.3f s (kernel %.3f ms)" % (steps, wall, tm["ensemble_ms"]))
-    # sequential: every k-th network alone, scaled to all
+    # sequential: every k-th network alone with its best setting (the
+    # single-launch LDS-resident kernel, autotuned; the two per-step kernels
+    # over the whole GPU; the fused per-step kernel), scaled to all
     sample = specs[::args.seq_sample]
     seq = 0.0
-    for s in sample:
-        one = gn.Net(s, flags=gn.NET_BUILD_SINGLE_LAUNCH | gn.NET_BUILD_AUTOTUNE)
-        one.step(args.warmup)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        one.step(steps)
-        torch.cuda.synchronize()
-        seq += time.perf_counter() - t1
-        one.close()
+    variants = [("single-launch", gn.NET_BUILD_SINGLE_LAUNCH | gn.NET_BUILD_AUTOTUNE), ("per-step", 0),
+                ("fused step", gn.NET_BUILD_FUSED_STEP)]
+    wins = {name: 0 for name, _ in variants}
+    largest = max(specs, key=lambda s: s.n_edges)
+    largest_alone = {}
+    for s in sample + [largest]:
+        best = None
+        for name, flags in variants:
+            one = gn.Net(s, flags=flags)
+            one.step(args.warmup)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            one.step(steps)
+            torch.cuda.synchronize()
+            tv = time.perf_counter() - t1
+            one.close()
+            if s is largest:
+                largest_alone[name] = tv
+            if best is None or tv < best[0]:
+                best = (tv, name)
+        if s is not largest or largest in sample:
+            seq += best[0]
+            wins[best[1]] += 1
     seq_all = seq * len(specs) / len(sample)
-    log("sequential: %d of %d networks alone in %.3f s -> %.3f s for all" % (len(sample), len(specs), seq, seq_all))
+    log("sequential: %d of %d networks alone in %.3f s -> %.3f s for all (best setting counts %s); largest network "
+        "(N=%d, E=%d) alone: %s" % (len(sample), len(specs), seq, seq_all, wins, largest.n, largest.n_edges,
+                                    {k: "%.3f s" % v for k, v in largest_alone.items()}))
     value = len(specs) / wall * (steps / 10000.0)
     return {
         "metric": "nets/s",
@@ -223,9 +247,13 @@ def bench_ensemble(args, torch, synth, gn):
         "sequential": {
             "value": len(specs) / seq_all * (steps / 10000.0),
             "unit": "networks per second (10,000-step runs)",
-            "method": "each network on its own handle, single-launch LDS-resident kernel, autotuned; "
+            "method": "each network on its own handle with the fastest of three settings (single-launch "
+                      "LDS-resident kernel autotuned, the two per-step kernels, the fused per-step kernel); "
                       "%d of %d networks timed and scaled" % (len(sample), len(specs)),
+            "best_setting_counts": wins,
         },
+        "largest_network_alone_s": largest_alone,
+        "largest_network": {"n_vertices": largest.n, "n_edges": largest.n_edges},
         "speedup_vs_sequential": seq_all / wall,
         "edge_steps_per_s": E * steps / wall,
         "roofline": {
@@ -479,6 +507,53 @@ def bench_testset(args, torch, synth, gn):
     }
 
 
+def bench_graph(args, torch, synth, gn):
+    """Launch-bound single networks (N = 256, config 0; N = 8,192 and
+    65,536, config-1 density) stepped without records: plain per-step
+    launches, the same kernels replayed from a captured 256-step HIP graph
+    (NET_BUILD_GRAPH), and the single-launch kernel (NET_BUILD_SINGLE_LAUNCH,
+    one launch per call), for the two-kernel and the fused step.  value =
+    steps/s of the N = 256 network with graph replays."""
+    steps = args.graph_steps
+    rows = []
+    cases = [("config0 N=256", synth.config0(), [0, gn.NET_BUILD_GRAPH, gn.NET_BUILD_SINGLE_LAUNCH])]
+    for n in (8192, 65536):
+        cases.append(("config1-density N=%d" % n, synth.config1(n=n),
+                      [0, gn.NET_BUILD_GRAPH, gn.NET_BUILD_FUSED_STEP, gn.NET_BUILD_FUSED_STEP | gn.NET_BUILD_GRAPH]))
+    for name, spec, variants in cases:
+        for flags in variants:
+            net = gn.Net(spec, flags=flags)
+            net.step(512)                                   # captures the graphs, past the start-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            net.step(steps)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            info = net.info()
+            rows.append({"network": name, "n_vertices": spec.n, "n_edges": spec.n_edges, "flags": flags,
+                         "deliver_flags": info["deliver_flags"], "us_per_step": wall / steps * 1e6,
+                         "steps_per_s": steps / wall})
+            log("%s flags %d: %.2f us per step" % (name, flags, wall / steps * 1e6))
+            net.close()
+    head = [r for r in rows if r["n_vertices"] == 256 and r["flags"] == gn.NET_BUILD_GRAPH][0]
+    return {
+        "metric": "steps/s",
+        "value": head["steps_per_s"],
+        "unit": "simulation steps per second (N = 256 network, graph replays)",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 512,
+        "ms_per_step": head["us_per_step"] / 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "single LIF networks stepped without records, plain launches vs graph replays"},
+        "rows": rows,
+    }
+
+
 def bench_stdp(args, torch, synth, gn):
     """Spike-timing-dependent plasticity on a configuration-1-sized network
     (N = 65,536 in a 1 mm cube, ~6.7e6 edges, noise 0.05, dt 0.1 ms): every
@@ -500,10 +575,15 @@ def bench_stdp(args, torch, synth, gn):
     wall = time.perf_counter() - t0
     tm = net.timing_end()
     w1 = net.observe(gn.NET_OBS_WEIGHTS).cpu().numpy()
-    rate = arrivals_per_step(net, spec, args.rate_steps)
+    # edges touched per step: arrivals (spikes x out-degree) and the in-edges
+    # of targets that fire (spikes x in-degree)
+    spk = spikes_per_vertex(net, spec, args.rate_steps)
+    rate = float((spk * np.bincount(np.asarray(spec.src), minlength=spec.n)).sum()) / args.rate_steps
+    post = float((spk * np.bincount(np.asarray(spec.dst), minlength=spec.n)).sum()) / args.rate_steps
     net.close()
     deliver_s = tm["deliver_ms"] / tm["deliver_launches"] / 1e3
-    alg = 9.0 * E + 18.0 * spec.n
+    touched = rate + post
+    alg = 5.0 * E + 8.0 * touched + 18.0 * spec.n
     log("stdp: %d steps in %.3f s; plastic delivery %.1f us, update %.1f us per step; %.0f arrivals per step"
         % (args.steps, wall, deliver_s * 1e6, tm["update_ms"] / tm["update_launches"] * 1e3, rate))
     cpu = None
@@ -532,9 +612,10 @@ def bench_stdp(args, torch, synth, gn):
         "roofline": {"bound": "hbm", "kernel": "plastic_deliver_kernel",
                      "achieved": alg / deliver_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": alg / deliver_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_rule": "9 B per edge (source, delay and the plastic weight read every step) + 18 B per "
-                                   "vertex; weight writes only for updated edges",
-                     "avg_launch_us": deliver_s * 1e6, "arrivals_per_step": rate},
+                     "bytes_rule": "5 B per edge (source, delay) + 8 B per touched edge (its weight read and "
+                                   "written: arrivals and the in-edges of firing targets) + 18 B per vertex",
+                     "avg_launch_us": deliver_s * 1e6, "arrivals_per_step": rate,
+                     "post_touches_per_step": post},
         "cpu_baseline": cpu,
     }
 
@@ -710,7 +791,8 @@ def main():
                          "iteration; 2 streams every weight, 7 B per edge)")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library time the delivery variants at build instead of --deliver-flags")
-    ap.add_argument("--workload", choices=["step", "ensemble", "estimate", "mlp", "testset", "stdp"], default="step",
+    ap.add_argument("--workload", choices=["step", "ensemble", "estimate", "mlp", "testset", "stdp", "graph"],
+                    default="step",
                     help="step: the N = 2^20 network (default); ensemble: 512 uneven networks in one launch "
                          "against each network run alone; estimate: learned edge scorer against the "
                          "simulation-based fit on held-out N = 1024 networks; mlp: the edge scorer's training "
@@ -723,6 +805,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=4, help="estimate workload: scorer training epochs")
     ap.add_argument("--w0", type=float, default=None,
                     help="estimate workload: weight scale of the observed networks (default the shared 0.05)")
+    ap.add_argument("--graph-steps", type=int, default=25600, help="graph workload: timed steps per variant")
     ap.add_argument("--relabel", type=int, default=-1,
                     help="default workload: number the vertices in a random order (this seed) before the build")
     ap.add_argument("--reorder", action="store_true",
@@ -770,6 +853,9 @@ def main():
         return
     if args.workload == "estimate":
         print(json.dumps(bench_estimate(args, torch, synth)), flush=True)
+        return
+    if args.workload == "graph":
+        print(json.dumps(bench_graph(args, torch, synth, gn)), flush=True)
         return
     if args.workload == "stdp":
         print(json.dumps(bench_stdp(args, torch, synth, gn)), flush=True)
@@ -845,7 +931,8 @@ def main():
     if streamed_w:
         fmt_bytes = BYTES_PER_EDGE_STREAMED_W * E
     else:
-        fmt_bytes = (BYTES_PER_EDGE_PACKED if packed else BYTES_PER_EDGE) * E + BYTES_PER_ARRIVAL * arrivals
+        per_edge = BYTES_PER_EDGE_NARROW if fused else (BYTES_PER_EDGE_PACKED if packed else BYTES_PER_EDGE)
+        fmt_bytes = per_edge * E + BYTES_PER_ARRIVAL * arrivals
     if fused:
         fmt_bytes += BYTES_PER_VERTEX_UPDATE * spec.n
     achieved = alg_bytes / avg_deliver_s / 1e9
@@ -875,7 +962,8 @@ def main():
             "workload": "LIF geometric network, N=%d vertices in a %.0f um cube, %d edges "
                         "(%s, fp16 w), 20%% inhibitory, noise 0.05, dt 0.1 ms"
                         % (spec.n, spec.meta["extent_um"][0], E,
-                           "u32 source | u8 delay << 24" if packed else "int32 src, u8 delay"),
+                           "3.5 B per edge: 16 + 4 source bits and the u8 delay" if fused else
+                           ("u32 source | u8 delay << 24" if packed else "int32 src, u8 delay")),
             "n_vertices": spec.n,
             "n_edges": E,
             "max_delay_steps": info["max_delay"],

@@ -283,20 +283,19 @@ constexpr int kMlpB3Off = kMlpW3Off + kMlpH;                    // b3
 constexpr int kMlpParams = kMlpB3Off + 1;                        // 82,689
 // The head's gradient sums (w3[256], b2[256], b3, loss) are spread over
 // replicas so that few workgroups add into any one address.
-constexpr int kHeadReplicas = 32, kHeadPart = 2 * kMlpH + 8;
+constexpr int kHeadReplicas = 32, kHeadPart = 3 * kMlpH + 8;   // w3, b2 sums; loss, b3; b1 sums at 2 * kMlpH + 8
 
 struct MlpDevice {
     float* params = nullptr;      // FP32 master weights
     float* adam_m = nullptr;
     float* adam_v = nullptr;
     float* grad = nullptr;
-    uint16_t* w1b = nullptr;      // BF16 copies
+    uint16_t* w1b = nullptr;      // BF16 copies: W1 transposed ([n][k]), W2 row-major and transposed
     uint16_t* w2b = nullptr;
+    uint16_t* w2c = nullptr;
     uint16_t* w1t = nullptr;      // BF16 W1 and W2 as the fused forward kernel holds them in LDS
     uint16_t* w2p = nullptr;      // (transposed, k reordered, 16-byte groups swizzled)
-    uint16_t* Xb = nullptr;       // [cap x 64] BF16 standardised inputs of the last forward pass
-    uint16_t* H1 = nullptr;       // [cap x 256] BF16 activations and gradients, row-major
-    uint16_t* H2 = nullptr;
+    uint16_t* H1 = nullptr;       // [cap x 256] BF16 H1 and dH2, row-major
     uint16_t* dH2 = nullptr;
     uint16_t* Xbt = nullptr;      // transposed copies for the weight gradients: [64 x ldt], [256 x ldt]
     uint16_t* H1t = nullptr;      // (ldt = the batch rows rounded up to 8, at most cap rounded up)

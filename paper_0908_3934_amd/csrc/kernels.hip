@@ -1611,11 +1611,14 @@ struct PlasticArgs {
     const int32_t* __restrict__ slot_orig;
     const int32_t* __restrict__ row_first;
     const uint32_t* __restrict__ ring;
+    const uint32_t* __restrict__ summary;   // bit i: vertex i fired within the last `window` steps
+    const uint16_t* __restrict__ ages;      // steps since the last two spikes (a1 | a2 << 8, 255 saturates)
     const float* __restrict__ V;
     const int32_t* __restrict__ spk_hist;
     const int32_t* __restrict__ spk_cnt;
     float* __restrict__ I;
     int64_t n_total, n_pad, t;
+    uint32_t window;
     float v_th;
     double dt, alpha, beta;
 };
@@ -1638,6 +1641,12 @@ __device__ __forceinline__ double since_last(const PlasticArgs& a, int64_t k, in
 // they are (integers, so the order of additions cannot change it), then the
 // plasticity update of every edge of the row whose spike arrives now or
 // whose target fires now: w += round((dt alpha sign(q) exp(-beta |q|)) / 2^-20).
+// An edge's arrival is found as in the delivery kernels: a source that did
+// not fire within the summary window (one bit per vertex, a small array that
+// stays in the caches) cannot arrive over an edge no longer than the window;
+// the others gather the source's two spike ages (d == a1 fires; d >= a2 asks
+// the history ring).  A weight is read only for an edge that is delivered or
+// updated.
 __global__ void __launch_bounds__(256) plastic_deliver_kernel(PlasticArgs a) {
     const int lane = threadIdx.x & 63;
     const int64_t j = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
@@ -1647,16 +1656,28 @@ __global__ void __launch_bounds__(256) plastic_deliver_kernel(PlasticArgs a) {
     int64_t acc = 0;
     for (int64_t e = first + lane; e < last; e += 64) {
         const int32_t i = a.src[e];
-        const int32_t dl = a.d[e];
-        const uint32_t slot = static_cast<uint32_t>(a.t - dl) & 255u;
-        const bool arrive = a.t - dl >= 0 && ((a.ring[(slot >> 5) * a.n_pad + i] >> (slot & 31u)) & 1u);
-        const int32_t w = a.wq[e];
-        if (arrive) acc += w;
-        if ((arrive || post) && a.slot_orig[e] >= 0) {
-            const double q = since_last(a, i, a.t - dl) - since_last(a, j, a.t);
-            const double sg = q > 0.0 ? 1.0 : (q < 0.0 ? -1.0 : 0.0);
-            const double dw = a.dt * a.alpha * sg * exp(-a.beta * fabs(q));
-            a.wq[e] = w + static_cast<int32_t>(rint(dw * 1048576.0));
+        const uint32_t dl = a.d[e];
+        const bool cand = ((a.summary[i >> 5] >> (i & 31)) & 1u) != 0u || dl > a.window;
+        bool arrive = false;
+        if (cand && a.t - static_cast<int64_t>(dl) >= 0) {
+            const uint32_t ag = a.ages[i];
+            const uint32_t a1 = ag & 0xFFu, a2 = ag >> 8;
+            if (dl >= a2) {
+                const uint32_t slot = static_cast<uint32_t>(a.t - dl) & 255u;
+                arrive = ((a.ring[(slot >> 5) * a.n_pad + i] >> (slot & 31u)) & 1u) != 0u;
+            } else {
+                arrive = dl == a1;
+            }
+        }
+        if (arrive || post) {
+            const int32_t w = a.wq[e];
+            if (arrive) acc += w;
+            if (a.slot_orig[e] >= 0) {
+                const double q = since_last(a, i, a.t - dl) - since_last(a, j, a.t);
+                const double sg = q > 0.0 ? 1.0 : (q < 0.0 ? -1.0 : 0.0);
+                const double dw = a.dt * a.alpha * sg * exp(-a.beta * fabs(q));
+                a.wq[e] = w + static_cast<int32_t>(rint(dw * 1048576.0));
+            }
         }
     }
 #pragma unroll
@@ -1733,6 +1754,8 @@ hipError_t launch_plastic_deliver(const DeviceGraph& g, int64_t t, hipStream_t s
     a.slot_orig = g.slot_orig;
     a.row_first = g.row_first;
     a.ring = g.ring;
+    a.summary = g.summary;
+    a.ages = g.age;
     a.V = g.V;
     a.spk_hist = g.spk_hist;
     a.spk_cnt = g.spk_cnt;
@@ -1740,6 +1763,7 @@ hipError_t launch_plastic_deliver(const DeviceGraph& g, int64_t t, hipStream_t s
     a.n_total = g.n_total;
     a.n_pad = g.n_pad;
     a.t = t;
+    a.window = static_cast<uint32_t>(g.d_sum);
     a.v_th = g.p0.v_th;
     a.dt = g.p0.dt_d;
     a.alpha = g.stdp_alpha;

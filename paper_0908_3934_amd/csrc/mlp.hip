@@ -70,7 +70,20 @@ __device__ __forceinline__ int w2_image_index(int k, int n) {
 // entries m0.. contiguous; entries M .. ldt-1 of every row are written as
 // zero, so that a later product may run its K over ldt, a multiple of 8).
 // ---------------------------------------------------------------------------
-enum Epilogue { kBiasReluBf16 = 0, kMaskBf16 = 1, kAtomicF32 = 2 };
+enum Epilogue { kBiasReluBf16 = 0, kMaskBf16 = 1, kAtomicF32 = 2, kHeadBf16 = 3 };
+
+// Head-epilogue inputs and outputs (the H2 product's epilogue).
+struct HeadArgs {
+    const float* w3;
+    const float* b3;
+    const float* y;
+    float* logits;
+    uint16_t* dH2;           // [B][256] row-major
+    uint16_t* dH2t;          // [256][ldt] transposed, rows B .. ldt-1 zero
+    float* part;             // [kHeadReplicas][kHeadPart]: w3 gradient, b2 gradient (column sums of the BF16
+                             // dH2), b3 gradient, loss (sum of per-row losses / B)
+    int64_t B, ldt;
+};
 
 struct GemmArgs {
     const uint16_t* A;
@@ -83,6 +96,15 @@ struct GemmArgs {
     uint16_t* out_t;          // [N x ldt] transposed, or null (BF16 epilogues)
     int64_t ldt;              // row length of out_t (>= M, a multiple of 8)
     float* out_f32;           // [M x N] row-major (atomic add)
+    HeadArgs head;            // kHeadBf16: the head that follows the product
+    // optional: A given as FP32 rows (a32, [M][K], K <= KS), standardised and
+    // rounded on the way in: BF16((x - a_shift[k]) * a_scale[k])
+    const float* a32;
+    const float* a_shift;
+    const float* a_scale;
+    uint16_t* a_t;            // optional: that BF16 A tile written transposed ([K][ldt], rows M .. ldt-1 zero)
+    float* colsum_part;       // kMaskBf16, BN = N: BF16 column sums of the tile added into replica
+                              // (row block mod kHeadReplicas) of [kHeadReplicas][kHeadPart] at offset 2N + 8
 };
 
 // LDS rows hold KS + 8 elements (padded against bank conflicts).
@@ -114,7 +136,25 @@ __device__ __forceinline__ void load_stage(StageRegs<BM, BN, KS>& r, const GemmA
         group_pos<BM, KS>(tid + 256 * q, a_kc, &row, &kk);
         const int64_t m = m0 + row, k = k0 + kk;
         uint4 va = make_uint4(0u, 0u, 0u, 0u);
-        if (m < g.M && k < k_hi) va = *reinterpret_cast<const uint4*>(g.A + m * g.a_rs + k * g.a_cs);
+        if (m < g.M && k < k_hi) {
+            if (g.a32) {
+                // 8 FP32 features of row m (k-contiguous), the input's rounding point
+                const float4 x0 = *reinterpret_cast<const float4*>(g.a32 + m * g.a_rs + k);
+                const float4 x1 = *reinterpret_cast<const float4*>(g.a32 + m * g.a_rs + k + 4);
+                const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+                uint32_t w[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t f = k + 2 * j;
+                    const uint32_t lo = f32_to_bf16_bits((x[2 * j] - g.a_shift[f]) * g.a_scale[f]);
+                    const uint32_t hi = f32_to_bf16_bits((x[2 * j + 1] - g.a_shift[f + 1]) * g.a_scale[f + 1]);
+                    w[j] = lo | (hi << 16);
+                }
+                va = make_uint4(w[0], w[1], w[2], w[3]);
+            } else {
+                va = *reinterpret_cast<const uint4*>(g.A + m * g.a_rs + k * g.a_cs);
+            }
+        }
         r.a[q] = va;
     }
 #pragma unroll
@@ -162,6 +202,90 @@ __device__ __forceinline__ void store_stage(const StageRegs<BM, BN, KS>& r, bool
 
 // Block tile BM x BN (64 or 128 each), four waves in a 2 x 2 arrangement,
 // each wave (BM/2) x (BN/2) = TM x TN tiles of 32 x 32.
+
+// Head, loss and dH2 of the 64 rows m0.. whose H2 (BF16, after bias and
+// ReLU) a 256-thread workgroup holds in LDS: four threads per row form the
+// logit (64 products each, then two exchanges); each thread then owns one
+// column for the dH2 values (rounded to BF16 in place in LDS) and that
+// column's w3 and b2 gradient sums; dH2 leaves row-major and transposed with
+// 16-byte stores.  The workgroup's sums go into replica (workgroup mod
+// kHeadReplicas) of the partial sums; head_finish adds the replicas into
+// the gradient.
+__device__ __forceinline__ void head_rows(uint16_t (*Hs)[kMlpH + 8], const HeadArgs& a, int64_t m0) {
+    __shared__ float dls[64], ls[64];
+    const int tid = threadIdx.x;
+    {
+        const int r = tid >> 2, part = tid & 3;
+        float s = 0.0f;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            const int c = part * 64 + g * 8;
+            const uint4 v = *reinterpret_cast<const uint4*>(&Hs[r][c]);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                s += bf16_bits_to_f32(static_cast<uint16_t>(w[q] & 0xFFFFu)) * a.w3[c + 2 * q];
+                s += bf16_bits_to_f32(static_cast<uint16_t>(w[q] >> 16)) * a.w3[c + 2 * q + 1];
+            }
+        }
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (part == 0) {
+            const int64_t m = m0 + r;
+            float dl = 0.0f, l = 0.0f;
+            if (m < a.B) {
+                const float logit = s + a.b3[0];
+                a.logits[m] = logit;
+                const float inv_b = 1.0f / static_cast<float>(a.B);
+                const float y = a.y[m];
+                const float p = 1.0f / (1.0f + expf(-logit));
+                dl = (p - y) * inv_b;
+                // log(1 + exp(-|z|)) + max(z, 0) - z*y
+                l = (log1pf(expf(-fabsf(logit))) + fmaxf(logit, 0.0f) - logit * y) * inv_b;
+            }
+            dls[r] = dl;
+            ls[r] = l;
+        }
+    }
+    __syncthreads();
+    {
+        const int n = tid;
+        const float w3n = a.w3[n];
+        float gw3 = 0.0f, gb2 = 0.0f;
+        for (int r = 0; r < 64; ++r) {
+            const float h = bf16_bits_to_f32(Hs[r][n]);
+            const float dl = dls[r];
+            const uint16_t g = f32_to_bf16_bits(h > 0.0f ? dl * w3n : 0.0f);
+            Hs[r][n] = g;
+            gb2 += bf16_bits_to_f32(g);
+            gw3 += dl * h;
+        }
+        float* part = a.part + (blockIdx.y % kHeadReplicas) * kHeadPart;
+        atomicAdd(part + n, gw3);
+        atomicAdd(part + kMlpH + n, gb2);
+        if (n < 2) {
+            float acc = 0.0f;
+            for (int r = 0; r < 64; ++r) acc += n == 0 ? ls[r] : dls[r];
+            atomicAdd(part + 2 * kMlpH + n, acc);
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < 64 * kMlpH / 8; e += 256) {
+        const int r = e / (kMlpH / 8), c = (e % (kMlpH / 8)) * 8;
+        if (m0 + r < a.B) *reinterpret_cast<uint4*>(a.dH2 + (m0 + r) * kMlpH + c) = *reinterpret_cast<const uint4*>(&Hs[r][c]);
+    }
+    for (int e = tid; e < 64 * kMlpH / 8; e += 256) {
+        const int n = e / 8, r = (e % 8) * 8;
+        const int64_t m = m0 + r;
+        if (m >= a.ldt) continue;
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            w[q] = static_cast<uint32_t>(Hs[r + 2 * q][n]) | (static_cast<uint32_t>(Hs[r + 2 * q + 1][n]) << 16);
+        *reinterpret_cast<uint4*>(a.dH2t + n * a.ldt + m) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
 // LDS of a block: the A and B stages during the K loop; afterwards the
 // output tile (and for kMaskBf16 the mask tile), rows padded by 8.
 template <int kEpi, int BM, int BN, int KS>
@@ -228,6 +352,24 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
             }
         return;
     }
+    if (g.a_t && n0 == 0) {
+        // the (single-stage) A tile is still in LDS: write it transposed,
+        // column k of the tile to row k of a_t
+        for (int e = tid; e < BM * KS / 8; e += 256) {
+            const int k = e / (BM / 8), r = (e % (BM / 8)) * 8;
+            const int64_t m = m0 + r;
+            if (k >= g.K || m >= g.ldt) continue;
+            uint32_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t lo = m + 2 * q < g.M ? As[r + 2 * q][k] : 0u;
+                const uint32_t hi = m + 2 * q + 1 < g.M ? As[r + 2 * q + 1][k] : 0u;
+                w[q] = lo | (hi << 16);
+            }
+            *reinterpret_cast<uint4*>(g.a_t + k * g.ldt + m) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        __syncthreads();
+    }
     // (the K loop ended on a barrier: the stages' LDS is free)
     constexpr int CW = BN + 8;
     uint16_t (*Cs)[CW] = reinterpret_cast<uint16_t (*)[CW]>(lds);
@@ -251,13 +393,13 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
             const int nl = wn * (BN / 2) + tn * 32 + (lane & 31);
             const int64_t n = n0 + nl;
             float bn = 0.0f;
-            if (kEpi == kBiasReluBf16) bn = n < g.N ? g.bias[n] : 0.0f;
+            if (kEpi == kBiasReluBf16 || kEpi == kHeadBf16) bn = n < g.N ? g.bias[n] : 0.0f;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int ml = wm * (BM / 2) + tm * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
                 const float v = acc[tm][tn][i];
                 float o;
-                if (kEpi == kBiasReluBf16) {
+                if (kEpi == kBiasReluBf16 || kEpi == kHeadBf16) {
                     const float h = v + bn;
                     o = h > 0.0f ? h : 0.0f;
                 } else {
@@ -267,6 +409,21 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
             }
         }
     __syncthreads();
+    if constexpr (kEpi == kMaskBf16) {
+        if (g.colsum_part && BN == 256) {
+            // column sums of the BF16 tile (rows past M are zero), one column per thread
+            const int n = tid;
+            float acc = 0.0f;
+            for (int r = 0; r < BM; ++r) acc += bf16_bits_to_f32(Cs[r][n]);
+            atomicAdd(g.colsum_part + (blockIdx.y % kHeadReplicas) * kHeadPart + 2 * kMlpH + 8 + n, acc);
+        }
+    }
+    if constexpr (kEpi == kHeadBf16) {
+        // the whole row width is in the tile: the head follows in place
+        static_assert(BM == 64 && BN == kMlpH, "the head epilogue needs 64 x 256 tiles");
+        head_rows(reinterpret_cast<uint16_t (*)[kMlpH + 8]>(lds), g.head, m0);
+        return;
+    }
     if (g.out_bf16) {
         for (int e = tid; e < groups; e += 256) {
             const int r = e / (BN / 8), c = (e % (BN / 8)) * 8;
@@ -291,46 +448,6 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
             }
             *reinterpret_cast<uint4*>(g.out_t + n * g.ldt + m) = make_uint4(w[0], w[1], w[2], w[3]);
         }
-    }
-}
-
-// Input standardisation and the first rounding point: Xb = BF16((X - shift) * scale)
-// for a [B][64] FP32 feature matrix, written row-major (Xb) and transposed
-// (Xbt [64][ldt], rows B .. ldt-1 zero).  One workgroup per 64 rows: the
-// tile is rounded into LDS, then written with 16-byte stores both ways.
-__global__ void __launch_bounds__(256) normalize_kernel(const float* X, const float* shift, const float* scale,
-                                                        uint16_t* Xb, uint16_t* Xbt, int64_t B, int64_t ldt) {
-    __shared__ __attribute__((aligned(16))) uint16_t T[64][kMlpIn + 8];
-    const int tid = threadIdx.x;
-    const int64_t m0 = static_cast<int64_t>(blockIdx.x) * 64;
-    {
-        const int r = tid >> 2, f0 = (tid & 3) * 16;
-        const int64_t m = m0 + r;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            float4 x = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (m < B) x = reinterpret_cast<const float4*>(X + m * kMlpIn + f0)[q];
-            const float v[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int f = f0 + 4 * q + k;
-                T[r][f] = m < B ? f32_to_bf16_bits((v[k] - shift[f]) * scale[f]) : static_cast<uint16_t>(0);
-            }
-        }
-    }
-    __syncthreads();
-    for (int e = tid; e < 64 * kMlpIn / 8; e += 256) {
-        const int r = e / (kMlpIn / 8), c = (e % (kMlpIn / 8)) * 8;
-        if (m0 + r < B) *reinterpret_cast<uint4*>(Xb + (m0 + r) * kMlpIn + c) = *reinterpret_cast<const uint4*>(&T[r][c]);
-    }
-    for (int e = tid; e < 64 * kMlpIn / 8; e += 256) {
-        const int f = e / 8, r = (e % 8) * 8;
-        const int64_t m = m0 + r;
-        if (m >= ldt) continue;
-        uint32_t w[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) w[q] = static_cast<uint32_t>(T[r + 2 * q][f]) | (static_cast<uint32_t>(T[r + 2 * q + 1][f]) << 16);
-        *reinterpret_cast<uint4*>(Xbt + f * ldt + m) = make_uint4(w[0], w[1], w[2], w[3]);
     }
 }
 
@@ -431,116 +548,12 @@ ShufflePerm make_perm(int64_t n, uint64_t seed, uint32_t epoch) {
     return p;
 }
 
-struct HeadArgs {
-    const uint16_t* H2;
-    const float* w3;
-    const float* b3;
-    const float* y;
-    float* logits;
-    uint16_t* dH2;           // [B][256] row-major
-    uint16_t* dH2t;          // [256][ldt] transposed, rows B .. ldt-1 zero
-    float* part;             // [kHeadReplicas][kHeadPart]: w3 gradient, b2 gradient (column sums of the BF16
-                             // dH2), b3 gradient, loss (sum of per-row losses / B)
-    int64_t B, ldt;
-};
-
-// Head, loss and dH2 for 64 rows per workgroup: the H2 tile is staged in
-// LDS with 16-byte loads; four threads per row form the logit (64 products
-// each, then two exchanges); each thread then owns one column for the dH2
-// values (rounded to BF16 in place in LDS) and that column's w3 and b2
-// gradient sums; dH2 leaves row-major and transposed with 16-byte stores.
-// The per-workgroup sums go into replica (workgroup mod kHeadReplicas) of
-// the partial sums; head_finish adds the replicas into the gradient.
-__global__ void __launch_bounds__(256) head_kernel(HeadArgs a) {
-    constexpr int HW = kMlpH + 8;
-    __shared__ __attribute__((aligned(16))) uint16_t Hs[64][HW];
-    __shared__ float dls[64], ls[64];
-    const int tid = threadIdx.x;
-    const int64_t m0 = static_cast<int64_t>(blockIdx.x) * 64;
-    for (int e = tid; e < 64 * kMlpH / 8; e += 256) {
-        const int r = e / (kMlpH / 8), c = (e % (kMlpH / 8)) * 8;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (m0 + r < a.B) v = *reinterpret_cast<const uint4*>(a.H2 + (m0 + r) * kMlpH + c);
-        *reinterpret_cast<uint4*>(&Hs[r][c]) = v;
-    }
-    __syncthreads();
-    {
-        const int r = tid >> 2, part = tid & 3;
-        float s = 0.0f;
-#pragma unroll
-        for (int g = 0; g < 8; ++g) {
-            const int c = part * 64 + g * 8;
-            const uint4 v = *reinterpret_cast<const uint4*>(&Hs[r][c]);
-            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                s += bf16_bits_to_f32(static_cast<uint16_t>(w[q] & 0xFFFFu)) * a.w3[c + 2 * q];
-                s += bf16_bits_to_f32(static_cast<uint16_t>(w[q] >> 16)) * a.w3[c + 2 * q + 1];
-            }
-        }
-        s += __shfl_xor(s, 1, 64);
-        s += __shfl_xor(s, 2, 64);
-        if (part == 0) {
-            const int64_t m = m0 + r;
-            float dl = 0.0f, l = 0.0f;
-            if (m < a.B) {
-                const float logit = s + a.b3[0];
-                a.logits[m] = logit;
-                const float inv_b = 1.0f / static_cast<float>(a.B);
-                const float y = a.y[m];
-                const float p = 1.0f / (1.0f + expf(-logit));
-                dl = (p - y) * inv_b;
-                // log(1 + exp(-|z|)) + max(z, 0) - z*y
-                l = (log1pf(expf(-fabsf(logit))) + fmaxf(logit, 0.0f) - logit * y) * inv_b;
-            }
-            dls[r] = dl;
-            ls[r] = l;
-        }
-    }
-    __syncthreads();
-    {
-        const int n = tid;
-        const float w3n = a.w3[n];
-        float gw3 = 0.0f, gb2 = 0.0f;
-        for (int r = 0; r < 64; ++r) {
-            const float h = bf16_bits_to_f32(Hs[r][n]);
-            const float dl = dls[r];
-            const uint16_t g = f32_to_bf16_bits(h > 0.0f ? dl * w3n : 0.0f);
-            Hs[r][n] = g;
-            gb2 += bf16_bits_to_f32(g);
-            gw3 += dl * h;
-        }
-        float* part = a.part + (blockIdx.x % kHeadReplicas) * kHeadPart;
-        atomicAdd(part + n, gw3);
-        atomicAdd(part + kMlpH + n, gb2);
-        if (n < 2) {
-            float acc = 0.0f;
-            for (int r = 0; r < 64; ++r) acc += n == 0 ? ls[r] : dls[r];
-            atomicAdd(part + 2 * kMlpH + n, acc);
-        }
-    }
-    __syncthreads();
-    for (int e = tid; e < 64 * kMlpH / 8; e += 256) {
-        const int r = e / (kMlpH / 8), c = (e % (kMlpH / 8)) * 8;
-        if (m0 + r < a.B) *reinterpret_cast<uint4*>(a.dH2 + (m0 + r) * kMlpH + c) = *reinterpret_cast<const uint4*>(&Hs[r][c]);
-    }
-    for (int e = tid; e < 64 * kMlpH / 8; e += 256) {
-        const int n = e / 8, r = (e % 8) * 8;
-        const int64_t m = m0 + r;
-        if (m >= a.ldt) continue;
-        uint32_t w[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            w[q] = static_cast<uint32_t>(Hs[r + 2 * q][n]) | (static_cast<uint32_t>(Hs[r + 2 * q + 1][n]) << 16);
-        *reinterpret_cast<uint4*>(a.dH2t + n * a.ldt + m) = make_uint4(w[0], w[1], w[2], w[3]);
-    }
-}
-
 // The head's replicas summed in a fixed order into the gradient (w3, b2, b3)
 // and the loss (also into loss_out when given), then cleared for the next
 // step (one 256-thread workgroup).
 __device__ __forceinline__ void head_finish(float* part, float* grad, float* loss, float* loss_out) {
-    for (int i = threadIdx.x; i < 2 * kMlpH + 2; i += blockDim.x) {
+    for (int i = threadIdx.x; i < kHeadPart; i += blockDim.x) {
+        if (i >= 2 * kMlpH + 2 && i < 2 * kMlpH + 8) continue;   // unused
         float acc = 0.0f;
         for (int r = 0; r < kHeadReplicas; ++r) {
             acc += part[r * kHeadPart + i];
@@ -552,39 +565,15 @@ __device__ __forceinline__ void head_finish(float* part, float* grad, float* los
             loss[0] = acc;
             if (loss_out) loss_out[0] = acc;
         }
-        else grad[kMlpB3Off] += acc;
+        else if (i == 2 * kMlpH + 1) grad[kMlpB3Off] += acc;
+        else grad[kMlpB1Off + (i - 2 * kMlpH - 8)] += acc;
     }
 }
 
-// b1 gradient: row sums of dH1t ([256][ldt] BF16, the transposed dH1; its
-// padding is zero), one workgroup per row, 16-byte loads, a fixed order
-// within the workgroup.  The last workgroup of the launch instead finishes
-// the head's sums.
-__global__ void __launch_bounds__(256) rowsum_kernel(const uint16_t* Xt, int64_t ldt, float* out, float* head_part,
-                                                     float* grad, float* loss, float* loss_out) {
-    __shared__ float red[256];
-    if (blockIdx.x == gridDim.x - 1) {
-        head_finish(head_part, grad, loss, loss_out);
-        return;
-    }
-    const int t = threadIdx.x;
-    const uint4* row = reinterpret_cast<const uint4*>(Xt + static_cast<int64_t>(blockIdx.x) * ldt);
-    const int64_t groups = ldt / 8;
-    float s = 0.0f;
-    for (int64_t q = t; q < groups; q += 256) {
-        const uint4 v = row[q];
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            s += bf16_bits_to_f32(static_cast<uint16_t>(w[k] & 0xFFFFu)) + bf16_bits_to_f32(static_cast<uint16_t>(w[k] >> 16));
-    }
-    red[t] = s;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (t < h) red[t] += red[t + h];
-        __syncthreads();
-    }
-    if (t == 0) out[blockIdx.x] += red[0];
+// The replicas of the head's and the b1 column sums added into the gradient
+// and the loss (one workgroup).
+__global__ void __launch_bounds__(256) finish_kernel(float* part, float* grad, float* loss, float* loss_out) {
+    head_finish(part, grad, loss, loss_out);
 }
 
 // Adam on the flat FP32 parameter vector; refreshes the BF16 copies of W1, W2.
@@ -595,6 +584,7 @@ struct AdamArgs {
     float* g;          // read, then cleared for the next step's accumulation
     uint16_t* w1b;
     uint16_t* w2b;
+    uint16_t* w2c;
     uint16_t* w1t;
     uint16_t* w2p;
     int64_t n;
@@ -614,29 +604,34 @@ __global__ void __launch_bounds__(256) adam_kernel(AdamArgs a) {
     a.p[i] = p;
     if (i < kMlpW1) {
         const uint16_t b = f32_to_bf16_bits(p);
-        a.w1b[i] = b;
-        a.w1t[w1_image_index(static_cast<int>(i) / kMlpH, static_cast<int>(i) % kMlpH)] = b;
+        const int k = static_cast<int>(i) / kMlpH, n = static_cast<int>(i) % kMlpH;
+        a.w1b[n * kMlpIn + k] = b;
+        a.w1t[w1_image_index(k, n)] = b;
     } else if (i >= kMlpW2Off && i < kMlpW2Off + kMlpW2) {
         const int e = static_cast<int>(i - kMlpW2Off);
         const uint16_t b = f32_to_bf16_bits(p);
         a.w2b[e] = b;
+        a.w2c[(e % kMlpH) * kMlpH + e / kMlpH] = b;
         a.w2p[w2_image_index(e / kMlpH, e % kMlpH)] = b;
     }
 }
 
-// BF16 copies of W1 and W2 from the FP32 parameters, row-major and as the
-// fused forward kernel's LDS images.
+// BF16 copies of W1 and W2 from the FP32 parameters: W1 transposed (w1b,
+// [n][k]), W2 row-major (w2b) and transposed (w2c), and the fused forward
+// kernel's LDS images.
 __global__ void __launch_bounds__(256) weights_bf16_kernel(const float* params, uint16_t* w1b, uint16_t* w2b,
-                                                           uint16_t* w1t, uint16_t* w2p) {
+                                                           uint16_t* w2c, uint16_t* w1t, uint16_t* w2p) {
     const int i = static_cast<int>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < kMlpW1) {
         const uint16_t b = f32_to_bf16_bits(params[kMlpW1Off + i]);
-        w1b[i] = b;
-        w1t[w1_image_index(i / kMlpH, i % kMlpH)] = b;
+        const int k = i / kMlpH, n = i % kMlpH;
+        w1b[n * kMlpIn + k] = b;
+        w1t[w1_image_index(k, n)] = b;
     } else if (i < kMlpW1 + kMlpW2) {
         const int e = i - kMlpW1;
         const uint16_t b = f32_to_bf16_bits(params[kMlpW2Off + e]);
         w2b[e] = b;
+        w2c[(e % kMlpH) * kMlpH + e / kMlpH] = b;
         w2p[w2_image_index(e / kMlpH, e % kMlpH)] = b;
     }
 }
@@ -849,55 +844,69 @@ hipError_t gemm(const GemmArgs& g, int split, hipStream_t s) {
 // Row length of the transposed activations of a B-row batch.
 int64_t mlp_ldt(int64_t B) { return (B + 7) / 8 * 8; }
 
+// Products over the batch rows with the whole 256-wide output row in one
+// tile (64 x 256, K staged 64 at a time): each row tile of A is read once,
+// and the head can follow the H2 product in its epilogue.  A and B must be
+// k-contiguous and K a multiple of 64.
+template <int kEpi>
+hipError_t gemm_rows(const GemmArgs& g, hipStream_t s) {
+    if (g.N != kMlpH || g.a_cs != 1 || g.b_rs != 1 || g.K % 64 != 0 || g.k_chunk != g.K) return hipErrorInvalidValue;
+    return gemm_tile<kEpi, 64, kMlpH, 64>(g, 1, s);
+}
+
 // Training forward pass for B rows of features X (FP32 [B x 64]) with
-// labels y: Xb (and Xbt), H1 (and H1t), H2, the logits, dH2 (and dH2t) and
-// the head's gradient sums.
+// labels y: Xbt (the rounded inputs, transposed), H1 (and H1t), the logits,
+// dH2 (and dH2t) and the head's gradient sums; H2 never leaves LDS.
 hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const float* y, hipStream_t s) {
     const float* p = d.params;
     const int64_t ldt = mlp_ldt(B);
-    const unsigned tiles = static_cast<unsigned>((B + 63) / 64);
-    hipLaunchKernelGGL(normalize_kernel, dim3(tiles), dim3(256), 0, s, X, d.in_shift, d.in_scale, d.Xb, d.Xbt, B, ldt);
+    // H1 = BF16(ReLU(BF16(standardised X) W1 + b1)); the product rounds X on
+    // the way in and writes the rounded tile transposed (Xbt) for dW1
     GemmArgs g1{};
-    g1.A = d.Xb;
-    g1.B = d.w1b;
+    g1.a32 = X;
+    g1.a_shift = d.in_shift;
+    g1.a_scale = d.in_scale;
+    g1.a_t = d.Xbt;
+    g1.B = d.w1b;         // B(k, n) = W1(k, n) at w1b[n * 64 + k]
     g1.M = B;
     g1.N = kMlpH;
     g1.K = kMlpIn;
     g1.k_chunk = kMlpIn;
     g1.a_rs = kMlpIn;
     g1.a_cs = 1;
-    g1.b_rs = kMlpH;
-    g1.b_cs = 1;
+    g1.b_rs = 1;
+    g1.b_cs = kMlpIn;
     g1.bias = p + kMlpB1Off;
     g1.out_bf16 = d.H1;
     g1.out_t = d.H1t;
     g1.ldt = ldt;
-    hipError_t e = gemm<kBiasReluBf16>(g1, 1, s);
+    hipError_t e = gemm_rows<kBiasReluBf16>(g1, s);
     if (e != hipSuccess) return e;
+    // H2 = BF16(ReLU(H1 W2 + b2)) stays in LDS: the head, the loss and dH2
+    // follow in the same workgroup
     GemmArgs g2 = g1;
+    g2.a32 = nullptr;
+    g2.a_t = nullptr;
     g2.A = d.H1;
-    g2.B = d.w2b;
     g2.K = kMlpH;
     g2.k_chunk = kMlpH;
     g2.a_rs = kMlpH;
+    g2.b_rs = 1;          // B(k, n) = W2(k, n) at w2c[n * 256 + k]
+    g2.b_cs = kMlpH;
+    g2.B = d.w2c;
     g2.bias = p + kMlpB2Off;
-    g2.out_bf16 = d.H2;
+    g2.out_bf16 = nullptr;
     g2.out_t = nullptr;
-    e = gemm<kBiasReluBf16>(g2, 1, s);
-    if (e != hipSuccess) return e;
-    HeadArgs h{};
-    h.H2 = d.H2;
-    h.w3 = p + kMlpW3Off;
-    h.b3 = p + kMlpB3Off;
-    h.y = y;
-    h.logits = d.logits;
-    h.dH2 = d.dH2;
-    h.dH2t = d.dH2t;
-    h.part = d.head_part;
-    h.B = B;
-    h.ldt = ldt;
-    hipLaunchKernelGGL(head_kernel, dim3(tiles), dim3(256), 0, s, h);
-    return hipGetLastError();
+    g2.head.w3 = p + kMlpW3Off;
+    g2.head.b3 = p + kMlpB3Off;
+    g2.head.y = y;
+    g2.head.logits = d.logits;
+    g2.head.dH2 = d.dH2;
+    g2.head.dH2t = d.dH2t;
+    g2.head.part = d.head_part;
+    g2.head.B = B;
+    g2.head.ldt = ldt;
+    return gemm_rows<kHeadBf16>(g2, s);
 }
 
 // Split-K of a weight gradient (K = the batch rows, padded to ldt): chunks
@@ -947,7 +956,8 @@ hipError_t mlp_backward(const MlpDevice& d, int64_t B, float* loss_out, hipStrea
     h1.mask = d.H1;
     h1.out_t = d.dH1t;
     h1.ldt = ldt;
-    if ((e = gemm<kMaskBf16>(h1, 1, s)) != hipSuccess) return e;
+    h1.colsum_part = d.head_part;      // b1 gradient: column sums of dH1
+    if ((e = gemm_rows<kMaskBf16>(h1, s)) != hipSuccess) return e;
     // dW1 = Xb^T dH1  (M = 64, N = 256, K = ldt): four tiles, chunks of 512 rows
     weight_split(ldt, 512, &split, &chunk);
     GemmArgs w1{};
@@ -963,9 +973,8 @@ hipError_t mlp_backward(const MlpDevice& d, int64_t B, float* loss_out, hipStrea
     w1.b_cs = ldt;
     w1.out_f32 = d.grad + kMlpW1Off;
     if ((e = gemm<kAtomicF32>(w1, split, s)) != hipSuccess) return e;
-    // b1 gradient: row sums of dH1t, plus one workgroup that finishes the head's sums
-    hipLaunchKernelGGL(rowsum_kernel, dim3(kMlpH + 1), dim3(256), 0, s, d.dH1t, ldt, d.grad + kMlpB1Off,
-                       d.head_part, d.grad, d.loss, loss_out);
+    // the head's and the b1 sums into the gradient
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, d.head_part, d.grad, d.loss, loss_out);
     return hipGetLastError();
 }
 
@@ -997,6 +1006,7 @@ hipError_t mlp_adam(const MlpDevice& d, float lr, float beta1, float beta2, floa
     a.g = d.grad;
     a.w1b = d.w1b;
     a.w2b = d.w2b;
+    a.w2c = d.w2c;
     a.w1t = d.w1t;
     a.w2p = d.w2p;
     a.n = kMlpParams;
@@ -1040,7 +1050,7 @@ hipError_t shuffle_indices(int64_t n, uint64_t seed, uint32_t epoch, int64_t* ou
 
 hipError_t mlp_refresh_bf16(const MlpDevice& d, hipStream_t s) {
     hipLaunchKernelGGL(weights_bf16_kernel, dim3((kMlpW1 + kMlpW2 + 255) / 256), dim3(256), 0, s, d.params, d.w1b,
-                       d.w2b, d.w1t, d.w2p);
+                       d.w2b, d.w2c, d.w1t, d.w2p);
     return hipGetLastError();
 }
 

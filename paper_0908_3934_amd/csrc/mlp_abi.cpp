@@ -52,8 +52,8 @@ void drop(const net_mlp* m, T** p, hipStream_t s = nullptr) {
 
 void release(net_mlp* m) {
     MlpDevice& d = m->d;
-    void* ps[] = {d.params, d.adam_m, d.adam_v, d.grad,     d.w1b,  d.w2b,      d.w1t,      d.w2p,
-                  d.Xb,     d.H1,     d.H2,     d.dH2,      d.Xbt,  d.H1t,      d.dH2t,     d.dH1t,
+    void* ps[] = {d.params, d.adam_m, d.adam_v, d.grad,     d.w1b,  d.w2b,      d.w2c,      d.w1t,      d.w2p,
+                  d.H1,     d.dH2,    d.Xbt,    d.H1t,      d.dH2t, d.dH1t,
                   d.logits, d.loss,   d.in_shift, d.in_scale, d.head_part, m->xs, m->ys,      m->stat_part};
     for (void* p : ps) m->al.put(p, nullptr);
     d = MlpDevice{};
@@ -69,12 +69,12 @@ net_status reserve(net_mlp* m, int64_t rows, hipStream_t s) {
     if (e != hipSuccess) return mdev(m, e, "net_mlp: workspace");
     m->d.cap = 0;
     const size_t rp = static_cast<size_t>(mlp_ldt(rows));
-    uint16_t** bufs[] = {&m->d.H1, &m->d.H2, &m->d.dH2, &m->d.H1t, &m->d.dH2t, &m->d.dH1t};
+    uint16_t** bufs[] = {&m->d.H1, &m->d.dH2, &m->d.H1t, &m->d.dH2t, &m->d.dH1t};
     for (uint16_t** b : bufs) {
         drop(m, b, s);
         if (alloc(m, b, rp * kMlpH, s) != hipSuccess) return mfail(NET_E_OOM, "net_mlp: workspace");
     }
-    uint16_t** ibufs[] = {&m->d.Xb, &m->d.Xbt};
+    uint16_t** ibufs[] = {&m->d.Xbt};
     for (uint16_t** b : ibufs) {
         drop(m, b, s);
         if (alloc(m, b, rp * kMlpIn, s) != hipSuccess) return mfail(NET_E_OOM, "net_mlp: workspace");
@@ -109,6 +109,7 @@ net_status net_mlp_create(net_mlp_t** out) {
         alloc(m, &d.adam_v, kMlpParams) != hipSuccess || alloc(m, &d.grad, kMlpParams) != hipSuccess ||
         alloc(m, &d.w1b, kMlpW1) != hipSuccess || alloc(m, &d.w2b, kMlpW2) != hipSuccess ||
         alloc(m, &d.w1t, kMlpW1) != hipSuccess || alloc(m, &d.w2p, kMlpW2) != hipSuccess ||
+        alloc(m, &d.w2c, kMlpW2) != hipSuccess ||
         alloc(m, &d.loss, 1) != hipSuccess || alloc(m, &d.head_part, kHeadReplicas * kHeadPart) != hipSuccess ||
         alloc(m, &d.in_shift, kMlpIn) != hipSuccess || alloc(m, &d.in_scale, kMlpIn) != hipSuccess) {
         release(m);
