@@ -264,7 +264,7 @@ def bench_ensemble(args, torch, synth, gn):
             "note": "5 B per edge-step streamed from L2/MALL (the %.0f MB edge list stays in the 256 MB MALL); "
                     "the bound is the per-step LDS work and two barriers of each workgroup" % (BYTES_PER_EDGE * E / 1e6),
         },
-        "cpu_baseline": ensemble_cpu_baseline(specs, len(specs)),
+        "cpu_baseline": None if args.no_cpu_baseline else ensemble_cpu_baseline(specs, len(specs)),
     }
 
 

@@ -872,6 +872,10 @@ __device__ __forceinline__ void put_bits_shared(uint64_t* words, int64_t u0, uin
     }
 }
 
+// kModels: 0 for LIF networks only, 1 with Izhikevich networks, 2 with
+// Hodgkin-Huxley networks too (the FP64 branches a kernel cannot meet are
+// compiled out: the LIF kernel needs no register spills).
+template <int kModels>
 __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
     const int64_t t0 = a.t_dev ? static_cast<int64_t>(*a.t_dev) : a.t0;   // graph replays read the step
     extern __shared__ uint4 lds4[];
@@ -919,25 +923,34 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
             const NetMeta nm = a.meta[a.wg_nets[q]];
             const NetLds L = carve(lds, nm, obs);
             const uint32_t rmask = 32u * static_cast<uint32_t>(nm.words) - 1u;
-            // the next chunk's edges are loaded while this chunk is resolved
+            // the next two chunks' edges are in flight while this chunk is resolved
             int c = nm.chunk_begin + wave;
-            u32x4 n_lo = u32x4{0u, 0u, 0u, 0u}, n_hi = n_lo;
-            u32x2 n_d = u32x2{0u, 0u};
+            u32x4 n_lo = u32x4{0u, 0u, 0u, 0u}, n_hi = n_lo, m_lo = n_lo, m_hi = n_lo;
+            u32x2 n_d = u32x2{0u, 0u}, m_d = n_d;
             if (c < nm.chunk_end) {
                 const int64_t e = static_cast<int64_t>(c) * kChunkEdges + lane * kEdgesPerLane;
                 n_lo = *reinterpret_cast<const u32x4*>(a.src + e);
                 n_hi = *reinterpret_cast<const u32x4*>(a.src + e + 4);
                 n_d = *reinterpret_cast<const u32x2*>(a.d + e);
             }
+            if (c + nwaves < nm.chunk_end) {
+                const int64_t e = static_cast<int64_t>(c + nwaves) * kChunkEdges + lane * kEdgesPerLane;
+                m_lo = *reinterpret_cast<const u32x4*>(a.src + e);
+                m_hi = *reinterpret_cast<const u32x4*>(a.src + e + 4);
+                m_d = *reinterpret_cast<const u32x2*>(a.d + e);
+            }
             for (; c < nm.chunk_end; c += nwaves) {
                 const int64_t e0 = static_cast<int64_t>(c) * kChunkEdges + lane * kEdgesPerLane;
                 const u32x4 s_lo = n_lo, s_hi = n_hi;
                 const u32x2 dq = n_d;
-                if (c + nwaves < nm.chunk_end) {
-                    const int64_t e = e0 + static_cast<int64_t>(nwaves) * kChunkEdges;
-                    n_lo = *reinterpret_cast<const u32x4*>(a.src + e);
-                    n_hi = *reinterpret_cast<const u32x4*>(a.src + e + 4);
-                    n_d = *reinterpret_cast<const u32x2*>(a.d + e);
+                n_lo = m_lo;
+                n_hi = m_hi;
+                n_d = m_d;
+                if (c + 2 * nwaves < nm.chunk_end) {
+                    const int64_t e = e0 + static_cast<int64_t>(2 * nwaves) * kChunkEdges;
+                    m_lo = *reinterpret_cast<const u32x4*>(a.src + e);
+                    m_hi = *reinterpret_cast<const u32x4*>(a.src + e + 4);
+                    m_d = *reinterpret_cast<const u32x2*>(a.d + e);
                 }
                 const uint32_t sv[8] = {s_lo.x, s_lo.y, s_lo.z, s_lo.w, s_hi.x, s_hi.y, s_hi.z, s_hi.w};
                 uint32_t fired = 0;
@@ -979,8 +992,8 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
                 const bool valid = j < nm.n_nodes;
                 const int jj = valid ? j : 0;
                 const int64_t u = nm.node_off + jj;
-                const bool izh = p.model == NET_MODEL_IZHIKEVICH;
-                const bool hh = p.model == NET_MODEL_HODGKIN_HUXLEY;
+                const bool izh = kModels >= 1 && p.model == NET_MODEL_IZHIKEVICH;
+                const bool hh = kModels >= 2 && p.model == NET_MODEL_HODGKIN_HUXLEY;
                 IzhState zs{};
                 HhState hs{};
                 if (izh) zs = IzhState{a.Vd[u], a.Wd[u], a.psc_r[u], a.psc_p[u]};
@@ -1852,13 +1865,27 @@ hipError_t launch_ensemble(const DeviceGraph& g, const EnsemblePlan& plan, int64
     a.frame_num = frame_num > 0 ? frame_num : 1;
     a.frame_den = frame_den > 0 ? frame_den : 1;
     a.d_sum = g.d_sum;
-    hipExtLaunchKernelGGL(ensemble_kernel, dim3(plan.blocks), dim3(plan.threads), plan.lds_bytes, s, ev0, ev1, 0, a);
+    if (g.hh_m)
+        hipExtLaunchKernelGGL(ensemble_kernel<2>, dim3(plan.blocks), dim3(plan.threads), plan.lds_bytes, s, ev0, ev1, 0,
+                              a);
+    else if (g.Vd)
+        hipExtLaunchKernelGGL(ensemble_kernel<1>, dim3(plan.blocks), dim3(plan.threads), plan.lds_bytes, s, ev0, ev1, 0,
+                              a);
+    else
+        hipExtLaunchKernelGGL(ensemble_kernel<0>, dim3(plan.blocks), dim3(plan.threads), plan.lds_bytes, s, ev0, ev1, 0,
+                              a);
     return hipGetLastError();
 }
 
 hipError_t enable_ensemble_lds(size_t bytes) {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&ensemble_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+    const void* fns[] = {reinterpret_cast<const void*>(&ensemble_kernel<0>),
+                         reinterpret_cast<const void*>(&ensemble_kernel<1>),
+                         reinterpret_cast<const void*>(&ensemble_kernel<2>)};
+    for (const void* f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 namespace {
