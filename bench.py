@@ -804,7 +804,7 @@ def main():
     ap.add_argument("--obs-steps", type=int, default=200000, help="estimate workload: observed steps (20 s)")
     ap.add_argument("--epochs", type=int, default=4, help="estimate workload: scorer training epochs")
     ap.add_argument("--w0", type=float, default=None,
-                    help="estimate workload: weight scale of the observed networks (default the shared 0.05)")
+                    help="estimate workload: weight scale of the observed networks (default config 4's 0.065)")
     ap.add_argument("--graph-steps", type=int, default=25600, help="graph workload: timed steps per variant")
     ap.add_argument("--relabel", type=int, default=-1,
                     help="default workload: number the vertices in a random order (this seed) before the build")
@@ -836,8 +836,6 @@ def main():
                          "Hodgkin-Huxley at dt = 0.03 ms for 1 s)")
     args = ap.parse_args()
     args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
-    if args.w0 is None:
-        args.w0 = 0.05
     if args.gpus != 1:
         print("bench.py measures one GPU only: the simulator is built and measured on a single "
               "MI355X; --gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -846,6 +844,8 @@ def main():
     import torch
     import synth
     import paper_0908_3934_amd as gn
+    if args.w0 is None:
+        args.w0 = synth.CONFIG4_W0
 
     torch.cuda.set_device(0)
     if args.workload == "ensemble":

@@ -552,11 +552,15 @@ ShufflePerm make_perm(int64_t n, uint64_t seed, uint32_t epoch) {
 // and the loss (also into loss_out when given), then cleared for the next
 // step (one 256-thread workgroup).
 __device__ __forceinline__ void head_finish(float* part, float* grad, float* loss, float* loss_out) {
-    for (int i = threadIdx.x; i < kHeadPart; i += blockDim.x) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kHeadPart; i += gridDim.x * blockDim.x) {
         if (i >= 2 * kMlpH + 2 && i < 2 * kMlpH + 8) continue;   // unused
+        float v[kHeadReplicas];
+#pragma unroll
+        for (int r = 0; r < kHeadReplicas; ++r) v[r] = part[r * kHeadPart + i];   // all loads in flight
         float acc = 0.0f;
+#pragma unroll
         for (int r = 0; r < kHeadReplicas; ++r) {
-            acc += part[r * kHeadPart + i];
+            acc += v[r];
             part[r * kHeadPart + i] = 0.0f;
         }
         if (i < kMlpH) grad[kMlpW3Off + i] += acc;
@@ -571,8 +575,8 @@ __device__ __forceinline__ void head_finish(float* part, float* grad, float* los
 }
 
 // The replicas of the head's and the b1 column sums added into the gradient
-// and the loss (one workgroup).
-__global__ void __launch_bounds__(256) finish_kernel(float* part, float* grad, float* loss, float* loss_out) {
+// and the loss (one thread per entry).
+__global__ void __launch_bounds__(64) finish_kernel(float* part, float* grad, float* loss, float* loss_out) {
     head_finish(part, grad, loss, loss_out);
 }
 
@@ -974,7 +978,7 @@ hipError_t mlp_backward(const MlpDevice& d, int64_t B, float* loss_out, hipStrea
     w1.out_f32 = d.grad + kMlpW1Off;
     if ((e = gemm<kAtomicF32>(w1, split, s)) != hipSuccess) return e;
     // the head's and the b1 sums into the gradient
-    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, d.head_part, d.grad, d.loss, loss_out);
+    hipLaunchKernelGGL(finish_kernel, dim3((kHeadPart + 63) / 64), dim3(64), 0, s, d.head_part, d.grad, d.loss, loss_out);
     return hipGetLastError();
 }
 

@@ -83,4 +83,4 @@ def test_trained_scorer_gains_over_activity_correlation():
     S, C, Y = map(np.concatenate, (S, C, Y))
     a_s, a_c = est.auc(S, Y), est.auc(C, Y)
     print("held-out AUC: scorer %.4f, activity correlation %.4f" % (a_s, a_c), flush=True)
-    assert a_s > a_c + 0.005
+    assert a_s > a_c + 0.015
