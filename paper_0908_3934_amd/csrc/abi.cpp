@@ -238,6 +238,13 @@ bool load_plan(net* h, const HostGraph& hg, int n_cu, int per_cu, int threads, b
     pl.blocks = static_cast<int>(wg_off.size()) - 1;
     pl.threads = threads;
     pl.lds_bytes = lds_max;
+    // every workgroup one network of at most one chunk per wave: the kernel
+    // that keeps the chunks in registers
+    pl.held = true;
+    for (int b = 0; b < pl.blocks && pl.held; ++b) {
+        const int q = wg_off[b];
+        pl.held = wg_off[b + 1] - q == 1 && meta[wg_nets[q]].chunk_end - meta[wg_nets[q]].chunk_begin <= threads / 64;
+    }
     return enable_ensemble_lds(lds_max) == hipSuccess;
 }
 
@@ -433,6 +440,35 @@ net_status reset_state(net* h, const HostGraph& hg, hipStream_t s) {
         e = hipMemsetAsync(g.frames, 0, np * static_cast<size_t>(g.frame_cap) * sizeof(float), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return e == hipSuccess ? NET_OK : device_fail(h, e, "net_build: state reset");
+}
+
+// Autotuning results of this process, keyed by a fingerprint of what the
+// timing depends on: a later build of an ensemble with the same networks
+// (sizes, edge chunks, ring words, models, observation) on a device with the
+// same CU count reuses the chosen shape instead of timing the trials again.
+std::mutex g_tune_mutex;
+std::vector<std::pair<uint64_t, std::pair<int, int>>> g_tune_cache;
+
+uint64_t fnv(uint64_t h, uint64_t v) {
+    for (int b = 0; b < 8; ++b) {
+        h ^= (v >> (8 * b)) & 0xFFu;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+uint64_t ensemble_fingerprint(const HostGraph& hg, const net_desc* descs, int32_t n_nets, int n_cu, bool observe) {
+    uint64_t h = 14695981039346656037ull;
+    h = fnv(h, static_cast<uint64_t>(n_cu));
+    h = fnv(h, observe ? 1u : 0u);
+    h = fnv(h, static_cast<uint64_t>(hg.node_off.size()));
+    for (size_t m = 0; m + 1 < hg.node_off.size(); ++m) {
+        h = fnv(h, static_cast<uint64_t>(hg.node_off[m + 1] - hg.node_off[m]));
+        h = fnv(h, static_cast<uint64_t>(hg.net_chunk_end[m] - hg.net_chunk_begin[m]));
+        h = fnv(h, static_cast<uint64_t>(hg.net_max_delay[m]));
+        h = fnv(h, static_cast<uint64_t>(static_cast<int32_t>(m) < n_nets ? descs[m].model : 0));
+    }
+    return h;
 }
 
 // Milliseconds of `steps` steps from the current state with the handle's
@@ -709,12 +745,21 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
             const bool observe = frame_cap > 0 && hg.frame_num > 0;
             // candidate shapes (workgroups per CU, threads); explicit options pin them
             std::vector<std::pair<int, int>> shapes;
+            uint64_t tune_key = 0;
+            bool cached = false;
             const int opt_cu = opts ? opts->blocks_per_cu : 0, opt_thr = opts ? opts->block_threads : 0;
             if (opt_cu || opt_thr) {
                 const int pc = opt_cu ? opt_cu : 2;
                 shapes.push_back({pc, opt_thr ? opt_thr : (pc >= 2 ? 512 : 1024)});
             } else if (autotune) {
                 shapes = {{2, 512}, {1, 1024}, {1, 512}, {2, 256}, {4, 256}};
+                tune_key = ensemble_fingerprint(hg, descs, n_nets, n_cu, observe);
+                std::lock_guard<std::mutex> lock(g_tune_mutex);
+                for (const auto& c : g_tune_cache)
+                    if (c.first == tune_key) {
+                        shapes = {c.second};       // tuned before in this process
+                        cached = true;
+                    }
             } else {
                 shapes = {{2, 512}, {1, 1024}};      // the first that fits
             }
@@ -732,6 +777,10 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
             double best_ms = 0.0;
             for (size_t k = 0; k < shapes.size(); ++k) {
                 if (!load_plan(h, hg, n_cu, shapes[k].first, shapes[k].second, observe, s)) continue;
+                if (cached) {
+                    best = static_cast<int>(k);
+                    break;
+                }
                 if (!autotune || shapes.size() == 1) {
                     best = static_cast<int>(k);
                     break;
@@ -756,7 +805,12 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
                     return bail(NET_E_DEVICE);
                 }
                 pl.enabled = true;
-                h->autotuned = autotune && shapes.size() > 1;
+                h->autotuned = autotune && (shapes.size() > 1 || cached);
+                if (autotune && !cached && shapes.size() > 1) {
+                    std::lock_guard<std::mutex> lock(g_tune_mutex);
+                    if (g_tune_cache.size() >= 64) g_tune_cache.erase(g_tune_cache.begin());
+                    g_tune_cache.push_back({tune_key, shapes[best]});
+                }
             }
         }
     }

@@ -227,6 +227,7 @@ struct EnsemblePlan {
     NetMeta* meta = nullptr;        // device [n_nets] (lds_off filled per network)
     int32_t* wg_nets = nullptr;     // device: networks of workgroup b at [wg_off[b], wg_off[b+1])
     int32_t* wg_off = nullptr;      // device [blocks + 1]
+    bool held = false;              // every workgroup holds one network of at most one chunk per wave
 };
 
 // LDS bytes one network needs in the ensemble kernel.

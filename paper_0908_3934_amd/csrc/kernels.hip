@@ -872,10 +872,56 @@ __device__ __forceinline__ void put_bits_shared(uint64_t* words, int64_t u0, uin
     }
 }
 
+// Delivery of one chunk of a network held in LDS: arrival test against the
+// LDS history ring, then each arrival's FP16 weight added into the LDS
+// input of its row.  With `held`, the chunk's weights, row-start bits and
+// first row come from registers (loaded once for all steps), else they are
+// loaded when the chunk has an arrival.
+__device__ __forceinline__ void ens_deliver_chunk(const EnsembleArgs& a, const NetMeta& nm, const NetLds& L,
+                                                  uint32_t rmask, int64_t t, int c, int lane, const u32x4& s_lo,
+                                                  const u32x4& s_hi, const u32x2& dq, bool held, const u32x4& h_w,
+                                                  uint32_t h_rs, int32_t h_row0) {
+    const int64_t e0 = static_cast<int64_t>(c) * kChunkEdges + lane * kEdgesPerLane;
+    const uint32_t sv[8] = {s_lo.x, s_lo.y, s_lo.z, s_lo.w, s_hi.x, s_hi.y, s_hi.z, s_hi.w};
+    uint32_t fired = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t sl = sv[k] - static_cast<uint32_t>(nm.node_off);
+        const uint32_t dk = ((k < 4 ? dq.x : dq.y) >> (8 * (k & 3))) & 0xFFu;
+        const uint32_t slot = (static_cast<uint32_t>(t) - dk) & rmask;
+        const uint32_t word = L.ring[sl * static_cast<uint32_t>(nm.words) + (slot >> 5)];
+        fired |= ((word >> (slot & 31u)) & 1u) << k;
+    }
+    if (wave_ballot(fired != 0)) {
+        const uint32_t rs = held ? h_rs : a.rowstart[static_cast<int64_t>(c) * 64 + lane];
+        const uint32_t bits = lane == 0 ? (rs & ~1u) : rs;
+        const int32_t row0 = (held ? h_row0 : a.chunk_row0[c]) - nm.node_off + static_cast<int32_t>(wave_bits_before(bits));
+        uint32_t wb[8];
+        if (held) {
+            const uint32_t hw[4] = {h_w.x, h_w.y, h_w.z, h_w.w};
+#pragma unroll
+            for (int k = 0; k < 8; ++k) wb[k] = (hw[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) wb[k] = ((fired >> k) & 1u) ? a.w[e0 + k] : 0u;   // arrivals only
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if ((fired >> k) & 1u) {
+                const int32_t row = row0 + __popc(bits & ((2u << k) - 1u));
+                atomicAdd(L.I + row, half_bits_to_float(wb[k]));
+            }
+        }
+    }
+}
+
 // kModels: 0 for LIF networks only, 1 with Izhikevich networks, 2 with
 // Hodgkin-Huxley networks too (the FP64 branches a kernel cannot meet are
-// compiled out: the LIF kernel needs no register spills).
-template <int kModels>
+// compiled out: the LIF kernel needs no register spills).  kHeld: the plan
+// gives every workgroup one network of at most one chunk per wave, whose
+// chunk then stays in registers (a separate instantiation, so that the
+// registers it holds do not weigh on the streaming kernel).
+template <int kModels, bool kHeld>
 __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
     const int64_t t0 = a.t_dev ? static_cast<int64_t>(*a.t_dev) : a.t0;   // graph replays read the step
     extern __shared__ uint4 lds4[];
@@ -916,6 +962,28 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
     }
     __syncthreads();
 
+    // A workgroup that holds one network of at most one chunk per wave keeps
+    // that chunk (sources, delays, weights, row starts) in registers for all
+    // its steps: no load on the per-step path.
+    constexpr bool held = kHeld;
+    u32x4 h_lo = u32x4{0u, 0u, 0u, 0u}, h_hi = h_lo, h_w = h_lo;
+    u32x2 h_d = u32x2{0u, 0u};
+    uint32_t h_rs = 0u;
+    int32_t h_row0 = 0;
+    if (held) {
+        const NetMeta nm = a.meta[a.wg_nets[q_begin]];
+        const int c = nm.chunk_begin + wave;
+        if (c < nm.chunk_end) {
+            const int64_t e = static_cast<int64_t>(c) * kChunkEdges + lane * kEdgesPerLane;
+            h_lo = *reinterpret_cast<const u32x4*>(a.src + e);
+            h_hi = *reinterpret_cast<const u32x4*>(a.src + e + 4);
+            h_d = *reinterpret_cast<const u32x2*>(a.d + e);
+            h_w = *reinterpret_cast<const u32x4*>(a.w + e);
+            h_rs = a.rowstart[static_cast<int64_t>(c) * 64 + lane];
+            h_row0 = a.chunk_row0[c];
+        }
+    }
+
     for (int s = 0; s < a.n_steps; ++s) {
         const int64_t t = t0 + s;
         // ---- delivery: I_j(t) = sum of w over in-edges whose source fired at t - d
@@ -923,60 +991,46 @@ __global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
             const NetMeta nm = a.meta[a.wg_nets[q]];
             const NetLds L = carve(lds, nm, obs);
             const uint32_t rmask = 32u * static_cast<uint32_t>(nm.words) - 1u;
-            // the next two chunks' edges are in flight while this chunk is resolved
-            int c = nm.chunk_begin + wave;
-            u32x4 n_lo = u32x4{0u, 0u, 0u, 0u}, n_hi = n_lo, m_lo = n_lo, m_hi = n_lo;
-            u32x2 n_d = u32x2{0u, 0u}, m_d = n_d;
-            if (c < nm.chunk_end) {
-                const int64_t e = static_cast<int64_t>(c) * kChunkEdges + lane * kEdgesPerLane;
-                n_lo = *reinterpret_cast<const u32x4*>(a.src + e);
-                n_hi = *reinterpret_cast<const u32x4*>(a.src + e + 4);
-                n_d = *reinterpret_cast<const u32x2*>(a.d + e);
+            if (held) {
+                const int c = nm.chunk_begin + wave;
+                if (c < nm.chunk_end)
+                    ens_deliver_chunk(a, nm, L, rmask, t, c, lane, h_lo, h_hi, h_d, true, h_w, h_rs, h_row0);
+                continue;
             }
-            if (c + nwaves < nm.chunk_end) {
-                const int64_t e = static_cast<int64_t>(c + nwaves) * kChunkEdges + lane * kEdgesPerLane;
-                m_lo = *reinterpret_cast<const u32x4*>(a.src + e);
-                m_hi = *reinterpret_cast<const u32x4*>(a.src + e + 4);
-                m_d = *reinterpret_cast<const u32x2*>(a.d + e);
+            // the next kDepth - 1 chunks' edges are in flight while this chunk is
+            // resolved (a register ring of this wave's chunks c, c + nwaves, ...)
+            constexpr int kDepth = 2;   // (4 measured slower: more registers, fewer waves)
+            int c = nm.chunk_begin + wave;
+            u32x4 q_lo[kDepth], q_hi[kDepth];
+            u32x2 q_d[kDepth];
+#pragma unroll
+            for (int u = 0; u < kDepth; ++u) {
+                q_lo[u] = q_hi[u] = u32x4{0u, 0u, 0u, 0u};
+                q_d[u] = u32x2{0u, 0u};
+                if (c + u * nwaves < nm.chunk_end) {
+                    const int64_t e = static_cast<int64_t>(c + u * nwaves) * kChunkEdges + lane * kEdgesPerLane;
+                    q_lo[u] = *reinterpret_cast<const u32x4*>(a.src + e);
+                    q_hi[u] = *reinterpret_cast<const u32x4*>(a.src + e + 4);
+                    q_d[u] = *reinterpret_cast<const u32x2*>(a.d + e);
+                }
             }
             for (; c < nm.chunk_end; c += nwaves) {
                 const int64_t e0 = static_cast<int64_t>(c) * kChunkEdges + lane * kEdgesPerLane;
-                const u32x4 s_lo = n_lo, s_hi = n_hi;
-                const u32x2 dq = n_d;
-                n_lo = m_lo;
-                n_hi = m_hi;
-                n_d = m_d;
-                if (c + 2 * nwaves < nm.chunk_end) {
-                    const int64_t e = e0 + static_cast<int64_t>(2 * nwaves) * kChunkEdges;
-                    m_lo = *reinterpret_cast<const u32x4*>(a.src + e);
-                    m_hi = *reinterpret_cast<const u32x4*>(a.src + e + 4);
-                    m_d = *reinterpret_cast<const u32x2*>(a.d + e);
-                }
-                const uint32_t sv[8] = {s_lo.x, s_lo.y, s_lo.z, s_lo.w, s_hi.x, s_hi.y, s_hi.z, s_hi.w};
-                uint32_t fired = 0;
+                const u32x4 s_lo = q_lo[0], s_hi = q_hi[0];
+                const u32x2 dq = q_d[0];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const uint32_t sl = sv[k] - static_cast<uint32_t>(nm.node_off);
-                    const uint32_t dk = ((k < 4 ? dq.x : dq.y) >> (8 * (k & 3))) & 0xFFu;
-                    const uint32_t slot = (static_cast<uint32_t>(t) - dk) & rmask;
-                    const uint32_t word = L.ring[sl * static_cast<uint32_t>(nm.words) + (slot >> 5)];
-                    fired |= ((word >> (slot & 31u)) & 1u) << k;
+                for (int u = 0; u + 1 < kDepth; ++u) {
+                    q_lo[u] = q_lo[u + 1];
+                    q_hi[u] = q_hi[u + 1];
+                    q_d[u] = q_d[u + 1];
                 }
-                if (wave_ballot(fired != 0)) {
-                    const uint32_t rs = a.rowstart[static_cast<int64_t>(c) * 64 + lane];
-                    const uint32_t bits = lane == 0 ? (rs & ~1u) : rs;
-                    const int32_t row0 = a.chunk_row0[c] - nm.node_off + static_cast<int32_t>(wave_bits_before(bits));
-                    uint32_t wb[8];
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) wb[k] = ((fired >> k) & 1u) ? a.w[e0 + k] : 0u;   // arrivals only
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        if ((fired >> k) & 1u) {
-                            const int32_t row = row0 + __popc(bits & ((2u << k) - 1u));
-                            atomicAdd(L.I + row, half_bits_to_float(wb[k]));
-                        }
-                    }
+                if (c + kDepth * nwaves < nm.chunk_end) {
+                    const int64_t e = e0 + static_cast<int64_t>(kDepth * nwaves) * kChunkEdges;
+                    q_lo[kDepth - 1] = *reinterpret_cast<const u32x4*>(a.src + e);
+                    q_hi[kDepth - 1] = *reinterpret_cast<const u32x4*>(a.src + e + 4);
+                    q_d[kDepth - 1] = *reinterpret_cast<const u32x2*>(a.d + e);
                 }
+                ens_deliver_chunk(a, nm, L, rmask, t, c, lane, s_lo, s_hi, dq, false, h_w, 0u, 0);
             }
         }
         __syncthreads();
@@ -1865,22 +1919,27 @@ hipError_t launch_ensemble(const DeviceGraph& g, const EnsemblePlan& plan, int64
     a.frame_num = frame_num > 0 ? frame_num : 1;
     a.frame_den = frame_den > 0 ? frame_den : 1;
     a.d_sum = g.d_sum;
-    if (g.hh_m)
-        hipExtLaunchKernelGGL(ensemble_kernel<2>, dim3(plan.blocks), dim3(plan.threads), plan.lds_bytes, s, ev0, ev1, 0,
-                              a);
-    else if (g.Vd)
-        hipExtLaunchKernelGGL(ensemble_kernel<1>, dim3(plan.blocks), dim3(plan.threads), plan.lds_bytes, s, ev0, ev1, 0,
-                              a);
-    else
-        hipExtLaunchKernelGGL(ensemble_kernel<0>, dim3(plan.blocks), dim3(plan.threads), plan.lds_bytes, s, ev0, ev1, 0,
-                              a);
+    const int m = g.hh_m ? 2 : (g.Vd ? 1 : 0);
+    const dim3 grid(plan.blocks), block(plan.threads);
+    if (plan.held) {
+        if (m == 2) hipExtLaunchKernelGGL((ensemble_kernel<2, true>), grid, block, plan.lds_bytes, s, ev0, ev1, 0, a);
+        else if (m == 1) hipExtLaunchKernelGGL((ensemble_kernel<1, true>), grid, block, plan.lds_bytes, s, ev0, ev1, 0, a);
+        else hipExtLaunchKernelGGL((ensemble_kernel<0, true>), grid, block, plan.lds_bytes, s, ev0, ev1, 0, a);
+    } else {
+        if (m == 2) hipExtLaunchKernelGGL((ensemble_kernel<2, false>), grid, block, plan.lds_bytes, s, ev0, ev1, 0, a);
+        else if (m == 1) hipExtLaunchKernelGGL((ensemble_kernel<1, false>), grid, block, plan.lds_bytes, s, ev0, ev1, 0, a);
+        else hipExtLaunchKernelGGL((ensemble_kernel<0, false>), grid, block, plan.lds_bytes, s, ev0, ev1, 0, a);
+    }
     return hipGetLastError();
 }
 
 hipError_t enable_ensemble_lds(size_t bytes) {
-    const void* fns[] = {reinterpret_cast<const void*>(&ensemble_kernel<0>),
-                         reinterpret_cast<const void*>(&ensemble_kernel<1>),
-                         reinterpret_cast<const void*>(&ensemble_kernel<2>)};
+    const void* fns[] = {reinterpret_cast<const void*>(&ensemble_kernel<0, false>),
+                         reinterpret_cast<const void*>(&ensemble_kernel<1, false>),
+                         reinterpret_cast<const void*>(&ensemble_kernel<2, false>),
+                         reinterpret_cast<const void*>(&ensemble_kernel<0, true>),
+                         reinterpret_cast<const void*>(&ensemble_kernel<1, true>),
+                         reinterpret_cast<const void*>(&ensemble_kernel<2, true>)};
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
         if (e != hipSuccess) return e;

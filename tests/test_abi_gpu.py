@@ -146,3 +146,31 @@ def test_state_error_after_device_fault(lib):
     assert lib.net_info(h, C.byref(info)) == _abi.NET_OK          # still answers, still frees
     lib.net_free(h)
     assert lib.net_simulate_device_error(None) == _abi.NET_E_ARG
+
+
+def test_autotune_cache_reuses_shape():
+    """A second autotuned build of the same ensemble in this process takes the
+    shape the first one chose (the process keeps its tuning results), and
+    steps to the same bits."""
+    import torch
+    import time
+    import paper_0908_3934_amd as gn
+    specs = [synth.config0_like(n, synth.config_seed(3, 970 + k), w0=0.36) for k, n in enumerate([100, 260, 70])]
+    for s in specs:
+        s.noise_sigma = 0.05
+    t0 = time.perf_counter()
+    a = gn.Net(specs, flags=gn.NET_BUILD_AUTOTUNE)
+    t1 = time.perf_counter()
+    b = gn.Net(specs, flags=gn.NET_BUILD_AUTOTUNE)
+    t2 = time.perf_counter()
+    ia, ib = a.info(), b.info()
+    print("autotuned builds: %.3f s then %.3f s; shape %d x %d" % (t1 - t0, t2 - t1, ia["ensemble_blocks"],
+                                                                   ia["ensemble_threads"]), flush=True)
+    assert ia["autotuned"] == ib["autotuned"] == 1
+    assert (ia["ensemble_blocks"], ia["ensemble_threads"]) == (ib["ensemble_blocks"], ib["ensemble_threads"])
+    ra = a.step(500, raster=True)
+    rb = b.step(500, raster=True)
+    torch.cuda.synchronize()
+    assert torch.equal(ra["raster"], rb["raster"])
+    a.close()
+    b.close()
