@@ -239,8 +239,8 @@ bool load_plan(net* h, const HostGraph& hg, int n_cu, int per_cu, int threads, b
     pl.threads = threads;
     pl.lds_bytes = lds_max;
     // every workgroup one network of at most one chunk per wave: the kernel
-    // that keeps the chunks in registers
-    pl.held = true;
+    // that keeps the chunks in registers (for FP64 models at most 512 threads)
+    pl.held = threads <= 512 || !(hg.any_izh || hg.any_hh);
     for (int b = 0; b < pl.blocks && pl.held; ++b) {
         const int q = wg_off[b];
         pl.held = wg_off[b + 1] - q == 1 && meta[wg_nets[q]].chunk_end - meta[wg_nets[q]].chunk_begin <= threads / 64;

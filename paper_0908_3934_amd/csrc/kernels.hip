@@ -920,9 +920,12 @@ __device__ __forceinline__ void ens_deliver_chunk(const EnsembleArgs& a, const N
 // compiled out: the LIF kernel needs no register spills).  kHeld: the plan
 // gives every workgroup one network of at most one chunk per wave, whose
 // chunk then stays in registers (a separate instantiation, so that the
-// registers it holds do not weigh on the streaming kernel).
+// registers it holds do not weigh on the streaming kernel).  A held FP64
+// model kernel runs at most 512 threads per workgroup, which gives it twice
+// the registers and no spills; the streaming ones keep 1024 threads (more
+// waves for large networks' edges) at the cost of some spills.
 template <int kModels, bool kHeld>
-__global__ void __launch_bounds__(1024) ensemble_kernel(EnsembleArgs a) {
+__global__ void __launch_bounds__((kModels == 0 || !kHeld) ? 1024 : 512) ensemble_kernel(EnsembleArgs a) {
     const int64_t t0 = a.t_dev ? static_cast<int64_t>(*a.t_dev) : a.t0;   // graph replays read the step
     extern __shared__ uint4 lds4[];
     uint8_t* lds = reinterpret_cast<uint8_t*>(lds4);
