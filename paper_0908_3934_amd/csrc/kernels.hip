@@ -1724,15 +1724,14 @@ __global__ void __launch_bounds__(256) plastic_deliver_kernel(PlasticArgs a) {
     const bool post = a.V[j] >= a.v_th;
     const int64_t first = a.row_first[j], last = a.row_first[j + 1];
     int64_t acc = 0;
-    for (int64_t e = first + lane; e < last; e += 64) {
-        const int32_t i = a.src[e];
-        const uint32_t dl = a.d[e];
-        const bool cand = ((a.summary[i >> 5] >> (i & 31)) & 1u) != 0u || dl > a.window;
+    // an edge whose ages were gathered (ag = 0xFFFF for non-candidates)
+    auto edge = [&](int64_t e, int32_t i, uint32_t dl, uint32_t ag) {
         bool arrive = false;
-        if (cand && a.t - static_cast<int64_t>(dl) >= 0) {
-            const uint32_t ag = a.ages[i];
+        if (a.t - static_cast<int64_t>(dl) >= 0) {
             const uint32_t a1 = ag & 0xFFu, a2 = ag >> 8;
             if (dl >= a2) {
+                // an older spike may sit at t - d (non-candidates never get here:
+                // their delay is at most the window, below 255)
                 const uint32_t slot = static_cast<uint32_t>(a.t - dl) & 255u;
                 arrive = ((a.ring[(slot >> 5) * a.n_pad + i] >> (slot & 31u)) & 1u) != 0u;
             } else {
@@ -1749,6 +1748,20 @@ __global__ void __launch_bounds__(256) plastic_deliver_kernel(PlasticArgs a) {
                 a.wq[e] = w + static_cast<int32_t>(rint(dw * 1048576.0));
             }
         }
+    };
+    // two edges per lane per pass, their loads issued together
+    for (int64_t e = first + lane; e < last; e += 128) {
+        const int64_t e2 = e + 64;
+        const bool two = e2 < last;
+        const int32_t i0 = a.src[e], i1 = a.src[two ? e2 : e];
+        const uint32_t d0 = a.d[e], d1 = a.d[two ? e2 : e];
+        const uint32_t sw0 = a.summary[i0 >> 5], sw1 = a.summary[i1 >> 5];
+        const bool c0 = ((sw0 >> (i0 & 31)) & 1u) != 0u || d0 > a.window;
+        const bool c1 = two && (((sw1 >> (i1 & 31)) & 1u) != 0u || d1 > a.window);
+        const uint32_t ag0 = c0 ? static_cast<uint32_t>(a.ages[i0]) : 0xFFFFu;
+        const uint32_t ag1 = c1 ? static_cast<uint32_t>(a.ages[i1]) : 0xFFFFu;
+        edge(e, i0, d0, ag0);
+        if (two) edge(e2, i1, d1, ag1);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
