@@ -520,30 +520,52 @@ def test_synchronous_bursts(spread):
     assert per_step.max() == n                                      # a burst reaches every vertex
 
 
-@pytest.mark.timeout(900)
+@pytest.mark.timeout(1100)
 def test_full_size_fused_step_open_loop():
     """The benchmarked configuration (N = 2^20 vertices, 1.03e8 edges, fused
-    step) against the oracle: the GPU's own raster of 150 steps is fed to
-    the oracle as its spike decisions (open loop / teacher forcing), so every
-    delivered input must match bit for bit and V stay within 1e-4 for all
-    vertices and steps; the oracle's own threshold test may disagree with
-    the forced spikes only on near-threshold ties."""
+    step) against the oracle over its first 1,000 steps, in chunks of 250:
+    the GPU's own raster of each chunk is fed to the oracle as its spike
+    decisions (open loop / teacher forcing), so every delivered input must
+    match bit for bit and V stay within 1e-4 for all vertices and steps; the
+    oracle's own threshold test may disagree with the forced spikes only on
+    near-threshold ties."""
     gn, torch = _gn()
     spec = synth.config2()
-    T = 150
-    g = run_gpu(spec, T, flags=gn.NET_BUILD_FUSED_STEP)
-    assert g["net"].info()["deliver_flags"] & gn.NET_BUILD_FUSED_STEP
-    g["net"].close()
-    raster = g["raster"].astype(np.uint8)
-    assert raster.sum() > 10000                                   # the network is active
-    o = oracle.OracleNet(spec).step(T, v=True, inp=True, force_raster=raster)
-    assert np.array_equal(g["input"], o["input"]), "delivered inputs differ"
-    assert (o["input"] != 0).sum() > 100000
-    dv = np.abs(g["v"] - o["v"]).max()
-    assert dv <= V_TOL, "max |dV| = %g" % dv
-    own = o["v"] >= spec.v_th
-    disagree = int((own != raster.astype(bool)).sum())
-    assert disagree <= 0.005 * max(int(raster.sum()), 1), disagree
+    T, C = 1000, 250
+    net = gn.Net(spec, flags=gn.NET_BUILD_FUSED_STEP)
+    assert net.info()["deliver_flags"] & gn.NET_BUILD_FUSED_STEP
+    orc = oracle.OracleNet(spec)
+    oracle.set_threads(oracle.test_threads())      # bit-identical to the serial run
+    try:
+        _open_loop_chunks(net, orc, spec, T, C, gn, torch)
+    finally:
+        oracle.set_threads(1)
+    net.close()
+
+
+def _open_loop_chunks(net, orc, spec, T, C, gn, torch):
+    spikes = arrivals = disagree = 0
+    dv_max = 0.0
+    for c in range(T // C):
+        out = net.step(C, raster=True, v=True, inp=True)
+        torch.cuda.synchronize()
+        raster = gn.unpack_raster(out["raster"], spec.n).astype(np.uint8)
+        gv = out["v"].cpu().numpy().astype(np.float64)
+        gi = out["input"].cpu().numpy().astype(np.float64)
+        del out
+        o = orc.step(C, v=True, inp=True, force_raster=raster)
+        assert np.array_equal(gi, o["input"]), "delivered inputs differ in steps %d..%d" % (c * C, c * C + C - 1)
+        dv_max = max(dv_max, float(np.abs(gv - o["v"]).max()))
+        own = o["v"] >= spec.v_th
+        disagree += int((own != raster.astype(bool)).sum())
+        spikes += int(raster.sum())
+        arrivals += int((o["input"] != 0).sum())
+        print("open loop steps %d..%d: max |dV| %.3g, spikes %d" % (c * C, c * C + C - 1, dv_max, spikes), flush=True)
+        del gv, gi, o, raster, own
+    assert spikes > 100000                                        # the network is active
+    assert arrivals > 1000000
+    assert dv_max <= V_TOL, "max |dV| = %g" % dv_max
+    assert disagree <= 0.005 * max(spikes, 1), disagree
 
 
 @pytest.mark.slow
