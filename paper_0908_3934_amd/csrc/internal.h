@@ -296,8 +296,8 @@ struct MlpDevice {
     uint16_t* w2c = nullptr;
     uint16_t* w1t = nullptr;      // BF16 W1 and W2 as the fused forward kernel holds them in LDS
     uint16_t* w2p = nullptr;      // (transposed, k reordered, 16-byte groups swizzled)
-    uint16_t* H1 = nullptr;       // [cap x 256] BF16 H1 and dH2, row-major
-    uint16_t* dH2 = nullptr;
+    uint32_t* H1bits = nullptr;   // [cap x 8] bits of H1 > 0 (the ReLU mask of dH1)
+    uint16_t* dH2 = nullptr;      // [cap x 256] BF16, row-major
     uint16_t* Xbt = nullptr;      // transposed copies for the weight gradients: [64 x ldt], [256 x ldt]
     uint16_t* H1t = nullptr;      // (ldt = the batch rows rounded up to 8, at most cap rounded up)
     uint16_t* dH2t = nullptr;

@@ -70,7 +70,7 @@ __device__ __forceinline__ int w2_image_index(int k, int n) {
 // entries m0.. contiguous; entries M .. ldt-1 of every row are written as
 // zero, so that a later product may run its K over ldt, a multiple of 8).
 // ---------------------------------------------------------------------------
-enum Epilogue { kBiasReluBf16 = 0, kMaskBf16 = 1, kAtomicF32 = 2, kHeadBf16 = 3 };
+enum Epilogue { kBiasReluBf16 = 0, kMaskBf16 = 1, kAtomicF32 = 2, kHeadBf16 = 3, kChainBf16 = 4 };
 
 // Head-epilogue inputs and outputs (the H2 product's epilogue).
 struct HeadArgs {
@@ -91,7 +91,7 @@ struct GemmArgs {
     int64_t M, N, K, k_chunk;
     int64_t a_rs, a_cs, b_rs, b_cs;
     const float* bias;        // kBiasReluBf16: [N]
-    const uint16_t* mask;     // kMaskBf16: BF16 [M x N] row-major; keep where > 0
+    const uint32_t* mask_bits; // kMaskBf16: [M][N/32] bits, keep where set
     uint16_t* out_bf16;       // [M x N] row-major, or null
     uint16_t* out_t;          // [N x ldt] transposed, or null (BF16 epilogues)
     int64_t ldt;              // row length of out_t (>= M, a multiple of 8)
@@ -105,6 +105,14 @@ struct GemmArgs {
     uint16_t* a_t;            // optional: that BF16 A tile written transposed ([K][ldt], rows M .. ldt-1 zero)
     float* colsum_part;       // kMaskBf16, BN = N: BF16 column sums of the tile added into replica
                               // (row block mod kHeadReplicas) of [kHeadReplicas][kHeadPart] at offset 2N + 8
+    // kChainBf16 (64 x 256 tiles): the BF16 tile, after bias + ReLU and the
+    // transposed store, is the A operand of a second product with B2
+    // (k-contiguous, [N2 = 256][K2]) and bias2, followed by the head; the
+    // tile's nonzero pattern is written as bits (mask_out, [M][N/32])
+    const uint16_t* B2;
+    const float* bias2;
+    int64_t K2;
+    uint32_t* mask_out;
 };
 
 // LDS rows hold KS + 8 elements (padded against bank conflicts).
@@ -286,12 +294,44 @@ __device__ __forceinline__ void head_rows(uint16_t (*Hs)[kMlpH + 8], const HeadA
     }
 }
 
+// B stages of the chained second product: 256 columns x 32 k of the
+// k-contiguous B2 (rows of k2), four 16-byte groups per thread held in
+// registers as native vectors (copies of the uint4 class become memcpys
+// through a stack slot).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+struct StageB {
+    u32x4 b[4];
+};
+
+__device__ __forceinline__ void load_b_stage(StageB& r, const uint16_t* B2, int64_t k2, int64_t k0, int tid) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int row, kk;
+        group_pos<256, 32>(tid + 256 * q, true, &row, &kk);
+        r.b[q] = *reinterpret_cast<const u32x4*>(B2 + static_cast<int64_t>(row) * k2 + k0 + kk);
+    }
+}
+
+template <int KSL>
+__device__ __forceinline__ void store_b_stage(const StageB& r, int tid, uint16_t (*Bs)[lds_k<KSL>()]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int row, kk;
+        group_pos<256, 32>(tid + 256 * q, true, &row, &kk);
+        *reinterpret_cast<u32x4*>(&Bs[row][kk]) = r.b[q];
+    }
+}
+
 // LDS of a block: the A and B stages during the K loop; afterwards the
-// output tile (and for kMaskBf16 the mask tile), rows padded by 8.
+// output tile (and for kMaskBf16 the mask bits), rows padded by 8.  The
+// chained product keeps its first tile beside the stages (the second
+// product's B stages reuse them).
 template <int kEpi, int BM, int BN, int KS>
 constexpr int gemm_lds_elems() {
     constexpr int stage = (BM + BN) * lds_k<KS>();
-    constexpr int out = (kEpi == kMaskBf16 ? 2 : 1) * BM * (BN + 8);
+    constexpr int out = BM * (BN + 8) + (kEpi == kMaskBf16 ? BM * (BN / 16) : 0);
+    if (kEpi == kChainBf16) return stage + BM * (BN + 8);
     return kEpi == kAtomicF32 ? stage : (stage > out ? stage : out);
 }
 
@@ -372,17 +412,15 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
     }
     // (the K loop ended on a barrier: the stages' LDS is free)
     constexpr int CW = BN + 8;
-    uint16_t (*Cs)[CW] = reinterpret_cast<uint16_t (*)[CW]>(lds);
-    uint16_t (*Ms)[CW] = reinterpret_cast<uint16_t (*)[CW]>(lds + BM * CW);
+    uint16_t (*Cs)[CW] = reinterpret_cast<uint16_t (*)[CW]>(lds + (kEpi == kChainBf16 ? (BM + BN) * lds_k<KS>() : 0));
+    uint32_t* Mb = reinterpret_cast<uint32_t*>(lds + BM * CW);   // kMaskBf16: [BM][BN / 32] bits
     constexpr int groups = BM * BN / 8;          // 16-byte groups of the tile
     if constexpr (kEpi == kMaskBf16) {
-        // the mask tile, row-major 16-byte groups (N is a multiple of 8)
-        for (int e = tid; e < groups; e += 256) {
-            const int r = e / (BN / 8), c = (e % (BN / 8)) * 8;
-            const int64_t m = m0 + r, n = n0 + c;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (m < g.M && n < g.N) v = *reinterpret_cast<const uint4*>(g.mask + m * g.N + n);
-            *reinterpret_cast<uint4*>(&Ms[r][c]) = v;
+        // the tile's mask bits (N is a multiple of 32, n0 of BN)
+        for (int e = tid; e < BM * (BN / 32); e += 256) {
+            const int r = e / (BN / 32), q = e % (BN / 32);
+            const int64_t m = m0 + r;
+            Mb[e] = m < g.M ? g.mask_bits[m * (g.N / 32) + n0 / 32 + q] : 0u;
         }
         __syncthreads();
     }
@@ -393,17 +431,17 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
             const int nl = wn * (BN / 2) + tn * 32 + (lane & 31);
             const int64_t n = n0 + nl;
             float bn = 0.0f;
-            if (kEpi == kBiasReluBf16 || kEpi == kHeadBf16) bn = n < g.N ? g.bias[n] : 0.0f;
+            if (kEpi != kMaskBf16) bn = n < g.N ? g.bias[n] : 0.0f;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int ml = wm * (BM / 2) + tm * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
                 const float v = acc[tm][tn][i];
                 float o;
-                if (kEpi == kBiasReluBf16 || kEpi == kHeadBf16) {
+                if (kEpi != kMaskBf16) {
                     const float h = v + bn;
                     o = h > 0.0f ? h : 0.0f;
                 } else {
-                    o = v * (bf16_bits_to_f32(Ms[ml][nl]) > 0.0f ? 1.0f : 0.0f);
+                    o = v * (((Mb[ml * (BN / 32) + (nl >> 5)] >> (nl & 31)) & 1u) ? 1.0f : 0.0f);
                 }
                 Cs[ml][nl] = f32_to_bf16_bits(o);
             }
@@ -432,6 +470,17 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
                 *reinterpret_cast<uint4*>(g.out_bf16 + m * g.N + n) = *reinterpret_cast<const uint4*>(&Cs[r][c]);
         }
     }
+    if constexpr (kEpi == kChainBf16) {
+        static_assert(BM == 64 && BN == kMlpH, "the chained product needs 64 x 256 tiles");
+        // nonzero bits of the first tile (the ReLU mask of the later backward product)
+        for (int e = tid; e < BM * (BN / 32); e += 256) {
+            const int r = e / (BN / 32), q = e % (BN / 32);
+            uint32_t bits = 0;
+#pragma unroll 8
+            for (int b = 0; b < 32; ++b) bits |= (Cs[r][32 * q + b] != 0 ? 1u : 0u) << b;
+            if (m0 + r < g.M) g.mask_out[(m0 + r) * (BN / 32) + q] = bits;
+        }
+    }
     if (g.out_t) {
         // group e: column c of the tile, rows r .. r+7 (consecutive threads take
         // consecutive row groups of one column, so their stores are contiguous)
@@ -448,6 +497,52 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
             }
             *reinterpret_cast<uint4*>(g.out_t + n * g.ldt + m) = make_uint4(w[0], w[1], w[2], w[3]);
         }
+    }
+    if constexpr (kEpi == kChainBf16) {
+        // second product: tile = BF16(ReLU(Cs B2 + bias2)), Cs read in place as
+        // the A operand, B2 staged KS rows of k at a time (next stage in
+        // registers while the MFMAs run); then the head on the new tile
+        f32x16 acc2[TN];
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc2[tn][i] = 0.0f;
+        // (stages of 32 k in the first 32 columns of Bs: fewer registers in flight)
+        constexpr int KS2 = 32;
+        static_assert(BN == 256 && KS2 == 32, "the chained stage holds 256 x 32");
+        StageB rb;
+        load_b_stage(rb, g.B2, g.K2, 0, tid);
+        for (int64_t k0 = 0; k0 < g.K2; k0 += KS2) {
+            store_b_stage<KS>(rb, tid, Bs);
+            __syncthreads();
+            // (the last pass reloads its own stage: an unconditional load keeps rb in registers)
+            load_b_stage(rb, g.B2, g.K2, k0 + KS2 < g.K2 ? k0 + KS2 : k0, tid);
+#pragma unroll
+            for (int ks = 0; ks < KS2; ks += 16) {
+                const int rr = lane & 31, kq = ks + 8 * (lane >> 5);
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(&Cs[wm * (BM / 2) + rr][k0 + kq]);
+#pragma unroll
+                for (int tn = 0; tn < TN; ++tn) {
+                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn * (BN / 2) + tn * 32 + rr][kq]);
+                    acc2[tn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc2[tn], 0, 0, 0);
+                }
+            }
+            __syncthreads();
+        }
+        // every read of the first tile is done: the second one replaces it
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) {
+            const int nl = wn * (BN / 2) + tn * 32 + (lane & 31);
+            const float bn = g.bias2[nl];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int ml = wm * (BM / 2) + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+                const float h = acc2[tn][i] + bn;
+                Cs[ml][nl] = f32_to_bf16_bits(h > 0.0f ? h : 0.0f);
+            }
+        }
+        __syncthreads();
+        head_rows(reinterpret_cast<uint16_t (*)[kMlpH + 8]>(&Cs[0][0]), g.head, m0);
     }
 }
 
@@ -859,8 +954,9 @@ hipError_t gemm_rows(const GemmArgs& g, hipStream_t s) {
 }
 
 // Training forward pass for B rows of features X (FP32 [B x 64]) with
-// labels y: Xbt (the rounded inputs, transposed), H1 (and H1t), the logits,
-// dH2 (and dH2t) and the head's gradient sums; H2 never leaves LDS.
+// labels y, one launch: Xbt (the rounded inputs, transposed), H1t and the
+// bits of H1 > 0, the logits, dH2 (and dH2t) and the head's gradient sums;
+// H1 and H2 stay in LDS.
 hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const float* y, hipStream_t s) {
     const float* p = d.params;
     const int64_t ldt = mlp_ldt(B);
@@ -881,36 +977,25 @@ hipError_t mlp_forward(const MlpDevice& d, const float* X, int64_t B, const floa
     g1.b_rs = 1;
     g1.b_cs = kMlpIn;
     g1.bias = p + kMlpB1Off;
-    g1.out_bf16 = d.H1;
+    g1.out_bf16 = nullptr;     // H1 stays in LDS for the second product; its ReLU mask leaves as bits
     g1.out_t = d.H1t;
     g1.ldt = ldt;
-    hipError_t e = gemm_rows<kBiasReluBf16>(g1, s);
-    if (e != hipSuccess) return e;
-    // H2 = BF16(ReLU(H1 W2 + b2)) stays in LDS: the head, the loss and dH2
-    // follow in the same workgroup
-    GemmArgs g2 = g1;
-    g2.a32 = nullptr;
-    g2.a_t = nullptr;
-    g2.A = d.H1;
-    g2.K = kMlpH;
-    g2.k_chunk = kMlpH;
-    g2.a_rs = kMlpH;
-    g2.b_rs = 1;          // B(k, n) = W2(k, n) at w2c[n * 256 + k]
-    g2.b_cs = kMlpH;
-    g2.B = d.w2c;
-    g2.bias = p + kMlpB2Off;
-    g2.out_bf16 = nullptr;
-    g2.out_t = nullptr;
-    g2.head.w3 = p + kMlpW3Off;
-    g2.head.b3 = p + kMlpB3Off;
-    g2.head.y = y;
-    g2.head.logits = d.logits;
-    g2.head.dH2 = d.dH2;
-    g2.head.dH2t = d.dH2t;
-    g2.head.part = d.head_part;
-    g2.head.B = B;
-    g2.head.ldt = ldt;
-    return gemm_rows<kHeadBf16>(g2, s);
+    g1.mask_out = d.H1bits;
+    // H2 = BF16(ReLU(H1 W2 + b2)) from the H1 tile in LDS, then the head, the
+    // loss and dH2 in the same workgroup
+    g1.B2 = d.w2c;             // B2(k, n) = W2(k, n) at w2c[n * 256 + k]
+    g1.bias2 = p + kMlpB2Off;
+    g1.K2 = kMlpH;
+    g1.head.w3 = p + kMlpW3Off;
+    g1.head.b3 = p + kMlpB3Off;
+    g1.head.y = y;
+    g1.head.logits = d.logits;
+    g1.head.dH2 = d.dH2;
+    g1.head.dH2t = d.dH2t;
+    g1.head.part = d.head_part;
+    g1.head.B = B;
+    g1.head.ldt = ldt;
+    return gemm_rows<kChainBf16>(g1, s);
 }
 
 // Split-K of a weight gradient (K = the batch rows, padded to ldt): chunks
@@ -957,7 +1042,7 @@ hipError_t mlp_backward(const MlpDevice& d, int64_t B, float* loss_out, hipStrea
     h1.a_cs = 1;
     h1.b_rs = 1;          // B(k, n) = W2(n, k)
     h1.b_cs = kMlpH;
-    h1.mask = d.H1;
+    h1.mask_bits = d.H1bits;
     h1.out_t = d.dH1t;
     h1.ldt = ldt;
     h1.colsum_part = d.head_part;      // b1 gradient: column sums of dH1

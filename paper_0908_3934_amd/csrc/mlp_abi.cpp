@@ -53,7 +53,7 @@ void drop(const net_mlp* m, T** p, hipStream_t s = nullptr) {
 void release(net_mlp* m) {
     MlpDevice& d = m->d;
     void* ps[] = {d.params, d.adam_m, d.adam_v, d.grad,     d.w1b,  d.w2b,      d.w2c,      d.w1t,      d.w2p,
-                  d.H1,     d.dH2,    d.Xbt,    d.H1t,      d.dH2t, d.dH1t,
+                  d.H1bits, d.dH2,    d.Xbt,    d.H1t,      d.dH2t, d.dH1t,
                   d.logits, d.loss,   d.in_shift, d.in_scale, d.head_part, m->xs, m->ys,      m->stat_part};
     for (void* p : ps) m->al.put(p, nullptr);
     d = MlpDevice{};
@@ -69,7 +69,7 @@ net_status reserve(net_mlp* m, int64_t rows, hipStream_t s) {
     if (e != hipSuccess) return mdev(m, e, "net_mlp: workspace");
     m->d.cap = 0;
     const size_t rp = static_cast<size_t>(mlp_ldt(rows));
-    uint16_t** bufs[] = {&m->d.H1, &m->d.dH2, &m->d.H1t, &m->d.dH2t, &m->d.dH1t};
+    uint16_t** bufs[] = {&m->d.dH2, &m->d.H1t, &m->d.dH2t, &m->d.dH1t};
     for (uint16_t** b : bufs) {
         drop(m, b, s);
         if (alloc(m, b, rp * kMlpH, s) != hipSuccess) return mfail(NET_E_OOM, "net_mlp: workspace");
@@ -79,6 +79,8 @@ net_status reserve(net_mlp* m, int64_t rows, hipStream_t s) {
         drop(m, b, s);
         if (alloc(m, b, rp * kMlpIn, s) != hipSuccess) return mfail(NET_E_OOM, "net_mlp: workspace");
     }
+    drop(m, &m->d.H1bits, s);
+    if (alloc(m, &m->d.H1bits, rp * (kMlpH / 32), s) != hipSuccess) return mfail(NET_E_OOM, "net_mlp: workspace");
     drop(m, &m->d.logits, s);
     if (alloc(m, &m->d.logits, static_cast<size_t>(rows), s) != hipSuccess) return mfail(NET_E_OOM, "net_mlp: workspace");
     m->d.cap = rows;
