@@ -249,6 +249,11 @@ typedef struct {
     int32_t deliver_flags;  /* NET_BUILD_DELIVER_* bits of the delivery variant in use */
     int32_t ensemble_blocks, ensemble_threads;   /* single-launch kernel shape (0: per-step kernels) */
     int32_t autotuned;      /* 1 if the launch shape was chosen by timing at build */
+    int32_t ensemble_stream; /* how the single-launch kernel reads its edge slots: 0 not in use,
+                                1 held in registers for all steps, 2 streamed as 2-byte sources
+                                within the network plus the delay bytes (3 B per slot), 3 streamed
+                                as 2-byte slots packing source and delay (every network's vertex
+                                count and largest delay fit in 16 bits together) */
 } net_info_t;
 
 /*

@@ -81,7 +81,7 @@ class Info(C.Structure):
         ("frames_done", C.c_int64), ("exact", C.c_int32), ("summary_window", C.c_int32), ("lds_summary", C.c_int32),
         ("deliver_blocks", C.c_int32), ("deliver_threads", C.c_int32), ("device_bytes", C.c_int64),
         ("deliver_flags", C.c_int32), ("ensemble_blocks", C.c_int32), ("ensemble_threads", C.c_int32),
-        ("autotuned", C.c_int32),
+        ("autotuned", C.c_int32), ("ensemble_stream", C.c_int32),
     ]
 
 

@@ -34,6 +34,7 @@ struct net {
     int64_t t_every = 1;          // time one launch of each kind in t_every
     int64_t t_seen[4] = {0, 0, 0, 0};
     EnsemblePlan plan;
+    std::vector<int32_t> push_base;   // per network: first entry of its out-edge offsets, -1 if none
     bool autotuned = false;
     // graph replays (NET_BUILD_GRAPH): device step counter, a private capture
     // stream, the 256-step graph of the per-step kernels and the ensemble
@@ -185,7 +186,11 @@ bool plan_ensemble(net* h, const HostGraph& hg, int n_cu, int wgs_per_cu, int th
         nm.chunk_begin = static_cast<int32_t>(hg.net_chunk_begin[m]);
         nm.chunk_end = static_cast<int32_t>(hg.net_chunk_end[m]);
         nm.words = hg.net_max_delay[m] <= 31 ? 1 : kRingWords;
-        need[m] = ensemble_lds_bytes(nm.n_nodes, nm.words, observe);
+        nm.maxd = hg.net_max_delay[m];
+        const bool push = nm.words == 1 && m < static_cast<int>(h->push_base.size()) && h->push_base[m] >= 0;
+        nm.log_cap = push ? ens_log_cap(nm.n_nodes) : 0;
+        nm.po_base = push ? h->push_base[m] : 0;
+        need[m] = ensemble_lds_bytes(nm.n_nodes, nm.words, observe) + ens_log_bytes(nm.log_cap);
         if (need[m] > budget) return false;
         // per-step cost model: edge slots + vertices + a fixed share of the barriers
         cost[m] = int64_t(nm.chunk_end - nm.chunk_begin) * kChunkEdges + 8 * int64_t(nm.n_nodes) + 2048;
@@ -203,6 +208,7 @@ bool plan_ensemble(net* h, const HostGraph& hg, int n_cu, int wgs_per_cu, int th
             if (used[b] + need[m] <= budget && (best < 0 || load[b] < load[best])) best = b;
         if (best < 0) return false;
         meta[m].lds_off = static_cast<int32_t>(used[best]);
+        meta[m].log_off = static_cast<int32_t>(used[best] + ensemble_lds_bytes(meta[m].n_nodes, meta[m].words, observe));
         used[best] += need[m];
         load[best] += cost[m];
         lists[best].push_back(m);
@@ -245,6 +251,7 @@ bool load_plan(net* h, const HostGraph& hg, int n_cu, int per_cu, int threads, b
         const int q = wg_off[b];
         pl.held = wg_off[b + 1] - q == 1 && meta[wg_nets[q]].chunk_end - meta[wg_nets[q]].chunk_begin <= threads / 64;
     }
+    if (!pl.held && !h->g.ens_ls) return false;   // the streaming kernels read the 2-byte stream
     return enable_ensemble_lds(lds_max) == hipSuccess;
 }
 
@@ -739,6 +746,97 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
     const bool autotune = (flags & NET_BUILD_AUTOTUNE) != 0;
     const bool single = n_nets > 1 || (flags & NET_BUILD_SINGLE_LAUNCH);
     if (single && !(flags & NET_BUILD_PER_STEP)) {
+        // the single-launch kernel's 2-byte stream: sources within their
+        // network, packed with the delay when both fit in 16 bits
+        int64_t max_n = 1;
+        for (int m = 0; m < n_nets; ++m) max_n = std::max(max_n, hg.node_off[m + 1] - hg.node_off[m]);
+        if (max_n <= 65536) {
+            int sb = 1;
+            while ((int64_t(1) << sb) < max_n) ++sb;
+            if (sb >= 16 || int64_t(hg.max_delay) >= (int64_t(1) << (16 - sb))) sb = 16;
+            std::vector<uint16_t> ls(static_cast<size_t>(hg.e_slots), 0);
+            for (int m = 0; m < n_nets; ++m) {
+                const int64_t off = hg.node_off[m];
+                for (int64_t k = hg.net_chunk_begin[m] * kChunkEdges; k < hg.net_chunk_end[m] * kChunkEdges; ++k) {
+                    const uint32_t local = static_cast<uint32_t>(hg.src[k] - off);
+                    ls[k] = static_cast<uint16_t>(sb < 16 ? (local | (static_cast<uint32_t>(hg.d[k]) << sb)) : local);
+                }
+            }
+            uint16_t* dls = nullptr;
+            st = upload(h, &dls, ls, ls.size(), s, "ensemble edges");
+            if (st == NET_OK) {
+                const hipError_t se = hipStreamSynchronize(s);   // `ls` is freed below
+                if (se != hipSuccess) st = device_fail(h, se, "net_build: upload");
+            }
+            if (st != NET_OK) return bail(st);
+            g.ens_ls = dls;
+            g.ens_sbits = sb;
+        }
+        // out-edge tables for the networks whose delays fit the 32-step LDS ring:
+        // each source's out-edges grouped by delay (zero weights, the empty
+        // rows' placeholders among them, add nothing and are left out)
+        {
+            std::vector<uint32_t> po, pe;
+            h->push_base.assign(n_nets, -1);
+            bool fits = true;
+            for (int m = 0; m < n_nets && fits; ++m) {
+                const int32_t D = hg.net_max_delay[m];
+                const int64_t off = hg.node_off[m], n = hg.node_off[m + 1] - off;
+                if (D > 31 || n > 65536) continue;   // (targets are 16-bit in the table)
+                if (static_cast<int64_t>(po.size()) + n * D + 1 > (int64_t(1) << 31) - 1) {
+                    fits = false;
+                    break;
+                }
+                const int64_t s0 = hg.net_chunk_begin[m] * kChunkEdges, s1 = hg.net_chunk_end[m] * kChunkEdges;
+                // target of every slot: the chunk's first row plus the row starts after it
+                std::vector<int32_t> row(static_cast<size_t>(s1 - s0));
+                for (int64_t c = hg.net_chunk_begin[m]; c < hg.net_chunk_end[m]; ++c) {
+                    int32_t r = hg.chunk_row0[c];
+                    for (int64_t k = c * kChunkEdges; k < (c + 1) * kChunkEdges; ++k) {
+                        if (k != c * kChunkEdges && ((hg.rowstart[k >> 3] >> (k & 7)) & 1u)) ++r;
+                        row[k - s0] = r;
+                    }
+                }
+                std::vector<int64_t> cnt(static_cast<size_t>(n * D) + 1, 0);
+                for (int64_t k = s0; k < s1; ++k)
+                    if ((hg.w[k] & 0x7FFFu) != 0) ++cnt[(hg.src[k] - off) * D + hg.d[k] - 1];
+                const int64_t e_base = static_cast<int64_t>(pe.size());
+                h->push_base[m] = static_cast<int32_t>(po.size());
+                int64_t run = e_base;
+                for (int64_t i = 0; i < n * D; ++i) {
+                    po.push_back(static_cast<uint32_t>(run));
+                    const int64_t c = cnt[i];
+                    cnt[i] = run;
+                    run += c;
+                }
+                po.push_back(static_cast<uint32_t>(run));
+                if (run > (int64_t(1) << 32) - 1) {
+                    fits = false;
+                    break;
+                }
+                pe.resize(static_cast<size_t>(run));
+                for (int64_t k = s0; k < s1; ++k)
+                    if ((hg.w[k] & 0x7FFFu) != 0)
+                        pe[cnt[(hg.src[k] - off) * D + hg.d[k] - 1]++] =
+                            static_cast<uint32_t>(row[k - s0] - off) | (static_cast<uint32_t>(hg.w[k]) << 16);
+            }
+            if (!fits) h->push_base.assign(n_nets, -1);
+            if (fits && !po.empty()) {
+                if (pe.empty()) pe.push_back(0u);
+                uint32_t *dpo = nullptr, *dpe = nullptr;
+                st = upload(h, &dpo, po, po.size(), s, "out-edge tables");
+                if (st == NET_OK) st = upload(h, &dpe, pe, pe.size(), s, "out-edge tables");
+                if (st == NET_OK) {
+                    const hipError_t se = hipStreamSynchronize(s);   // the host tables are freed below
+                    if (se != hipSuccess) st = device_fail(h, se, "net_build: upload");
+                }
+                if (st != NET_OK) return bail(st);
+                g.push_off = dpo;
+                g.push_edge = dpe;
+            } else {
+                h->push_base.assign(n_nets, -1);
+            }
+        }
         int dev = 0, n_cu = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
@@ -1024,6 +1122,7 @@ net_status net_info(const net_t* h, net_info_t* out) {
     out->ensemble_blocks = h->plan.enabled ? h->plan.blocks : 0;
     out->ensemble_threads = h->plan.enabled ? h->plan.threads : 0;
     out->autotuned = h->autotuned ? 1 : 0;
+    out->ensemble_stream = !h->plan.enabled ? 0 : (h->plan.held ? 1 : (h->g.ens_sbits < 16 ? 3 : 2));
     return NET_OK;
 }
 

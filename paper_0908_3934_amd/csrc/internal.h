@@ -21,6 +21,10 @@ constexpr uint8_t kAgeNever = 255;    // "no spike within the last 254 steps"
 // The ages arrays hold this many entries past n_pad; entry n_pad stays
 // (kAgeNever, kAgeNever) and is what delivery gathers for non-candidate edges.
 constexpr int kAgePad = 64;
+// How the single-launch ensemble kernel reads its chunks: held in registers
+// for all steps, or streamed each step as 2-byte sources within the network
+// plus the delay bytes, or as 2-byte slots that pack both.
+constexpr int kEnsHeld = 0, kEnsLocal = 1, kEnsPacked = 2;
 // The fused step kernel keeps the recent-spike summary in a fixed 128 KiB of
 // LDS (one bit per vertex, up to 2^20 vertices) and its segment's inputs
 // after it.
@@ -71,7 +75,20 @@ struct NetMeta {
     int32_t chunk_begin, chunk_end;
     int32_t words;      // history words per vertex in LDS: 1 (32 steps) or 8 (256 steps)
     int32_t lds_off;    // byte offset of the network's state in its workgroup's LDS
+    int32_t maxd;       // largest delay of the network
+    // spike log (networks with words == 1 and out-edge tables, else log_cap = 0):
+    // byte offset in LDS of 32 counts and 32 x log_cap vertex ids (bucket
+    // t mod 32 lists the vertices that fired at step t), and the first entry
+    // of the network's out-edge offsets
+    int32_t log_off, log_cap, po_base;
 };
+
+// Spike-log capacity per step bucket of a network of n vertices, and its LDS bytes.
+inline int ens_log_cap(int64_t n) {
+    const int64_t c = (n / 16 + 7) / 8 * 8;
+    return static_cast<int>(c < 16 ? 16 : (c > 64 ? 64 : c));
+}
+inline size_t ens_log_bytes(int cap) { return cap > 0 ? 128 + 64 * static_cast<size_t>(cap) : 0; }
 
 // Host-side result of graph construction (before upload).
 struct HostGraph {
@@ -153,6 +170,17 @@ struct DeviceGraph {
     const uint16_t* s_lo = nullptr;
     const uint32_t* dl_pair = nullptr;
     const uint32_t* hi_pair = nullptr;
+    // single-launch ensemble kernel's stream, 2 B per slot: the source's
+    // index within its network (ens_sbits = 16; delays from d), or that
+    // index | delay << ens_sbits (ens_sbits < 16)
+    const uint16_t* ens_ls = nullptr;
+    int32_t ens_sbits = 16;
+    // single-launch ensemble kernel's out-edge tables (networks with delays
+    // up to 31 steps): the out-edges of each source grouped by delay, as
+    // target within the network | FP16 weight << 16, and per network
+    // n x maxd + 1 offsets, entry s * maxd + d - 1 opening group (s, d)
+    const uint32_t* push_off = nullptr;
+    const uint32_t* push_edge = nullptr;
     const uint8_t* rowstart;
     const int32_t* chunk_row0;
     const NetParams* params;

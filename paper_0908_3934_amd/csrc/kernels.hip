@@ -833,8 +833,12 @@ struct EnsembleArgs {
     double* __restrict__ hh_vprev;
     const int32_t* __restrict__ caller_of;   // renumbered networks (else null)
     const uint64_t* __restrict__ t_dev;      // graph replays: the first step (else null: t0)
+    const uint16_t* __restrict__ ls;         // 2 B per slot: source within its network, or with
+                                             // sbits < 16 source | delay << sbits
+    const uint32_t* __restrict__ push_off;   // out-edge tables of the networks with a spike log
+    const uint32_t* __restrict__ push_edge;
     int64_t t0, n_total, n_pad, raster_words;
-    int32_t n_steps, frame_cap, frame_num, frame_den, d_sum;
+    int32_t n_steps, frame_cap, frame_num, frame_den, d_sum, sbits;
 };
 
 struct NetLds {
@@ -873,23 +877,21 @@ __device__ __forceinline__ void put_bits_shared(uint64_t* words, int64_t u0, uin
 }
 
 // Delivery of one chunk of a network held in LDS: arrival test against the
-// LDS history ring, then each arrival's FP16 weight added into the LDS
-// input of its row.  With `held`, the chunk's weights, row-start bits and
-// first row come from registers (loaded once for all steps), else they are
-// loaded when the chunk has an arrival.
+// LDS history ring (sl: each slot's source within its network, dk: its
+// delay), then each arrival's FP16 weight added into the LDS input of its
+// row.  With `held`, the chunk's weights, row-start bits and first row come
+// from registers (loaded once for all steps), else they are loaded when the
+// chunk has an arrival.
 __device__ __forceinline__ void ens_deliver_chunk(const EnsembleArgs& a, const NetMeta& nm, const NetLds& L,
-                                                  uint32_t rmask, int64_t t, int c, int lane, const u32x4& s_lo,
-                                                  const u32x4& s_hi, const u32x2& dq, bool held, const u32x4& h_w,
+                                                  uint32_t rmask, int64_t t, int c, int lane, const uint32_t (&sl)[8],
+                                                  const uint32_t (&dk)[8], bool held, const u32x4& h_w,
                                                   uint32_t h_rs, int32_t h_row0) {
     const int64_t e0 = static_cast<int64_t>(c) * kChunkEdges + lane * kEdgesPerLane;
-    const uint32_t sv[8] = {s_lo.x, s_lo.y, s_lo.z, s_lo.w, s_hi.x, s_hi.y, s_hi.z, s_hi.w};
     uint32_t fired = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const uint32_t sl = sv[k] - static_cast<uint32_t>(nm.node_off);
-        const uint32_t dk = ((k < 4 ? dq.x : dq.y) >> (8 * (k & 3))) & 0xFFu;
-        const uint32_t slot = (static_cast<uint32_t>(t) - dk) & rmask;
-        const uint32_t word = L.ring[sl * static_cast<uint32_t>(nm.words) + (slot >> 5)];
+        const uint32_t slot = (static_cast<uint32_t>(t) - dk[k]) & rmask;
+        const uint32_t word = L.ring[sl[k] * static_cast<uint32_t>(nm.words) + (slot >> 5)];
         fired |= ((word >> (slot & 31u)) & 1u) << k;
     }
     if (wave_ballot(fired != 0)) {
@@ -915,17 +917,80 @@ __device__ __forceinline__ void ens_deliver_chunk(const EnsembleArgs& a, const N
     }
 }
 
+// A network's spike log in LDS: bucket b (= step mod 32) counts the
+// vertices that fired at its step and lists the first log_cap of them.
+struct NetLog {
+    uint32_t* cnt;
+    uint16_t* ids;
+};
+
+__device__ __forceinline__ NetLog log_of(uint8_t* base, const NetMeta& nm) {
+    NetLog g;
+    g.cnt = reinterpret_cast<uint32_t*>(base + nm.log_off);
+    g.ids = reinterpret_cast<uint16_t*>(base + nm.log_off + 128);
+    return g;
+}
+
+// Wave-uniform: every spike of the last maxd steps is listed in the log
+// (else the step is delivered by the pull over the in-edges).
+__device__ __forceinline__ bool log_complete(const NetLog& g, const NetMeta& nm, int64_t t, int lane) {
+    const bool over = lane >= 1 && lane <= nm.maxd &&
+                      g.cnt[(static_cast<uint32_t>(t) - static_cast<uint32_t>(lane)) & 31u] >
+                          static_cast<uint32_t>(nm.log_cap);
+    return wave_ballot(over) == 0;
+}
+
+// Delivery of step t by one wave from the spike log: the spike of source s
+// at step t - d reaches, at step t, the out-edges of s with delay d, one
+// (s, d) group per lane, its edges read four at a time.
+__device__ __forceinline__ void ens_push(const EnsembleArgs& a, const NetMeta& nm, const NetLds& L, const NetLog& g,
+                                         int64_t t, int lane) {
+    const uint32_t cap = static_cast<uint32_t>(nm.log_cap);
+    const uint32_t tt = static_cast<uint32_t>(t);
+    uint32_t total = 0;
+    for (int d = 1; d <= nm.maxd; ++d) total += min(g.cnt[(tt - static_cast<uint32_t>(d)) & 31u], cap);
+    for (uint32_t first = 0; first < total; first += 64) {
+        const uint32_t idx = first + static_cast<uint32_t>(lane);
+        int my_d = 0;
+        uint32_t my_i = 0, pre = 0;
+        for (int d = 1; d <= nm.maxd; ++d) {
+            const uint32_t c = min(g.cnt[(tt - static_cast<uint32_t>(d)) & 31u], cap);
+            if (idx >= pre && idx < pre + c) {
+                my_d = d;
+                my_i = idx - pre;
+            }
+            pre += c;
+        }
+        if (my_d == 0) continue;
+        const uint32_t src = g.ids[((tt - static_cast<uint32_t>(my_d)) & 31u) * cap + my_i];
+        const int64_t o = static_cast<int64_t>(nm.po_base) + static_cast<int64_t>(src) * nm.maxd + my_d - 1;
+        const uint32_t e0 = a.push_off[o], e1 = a.push_off[o + 1];
+        for (uint32_t e = e0; e < e1; e += 4) {
+            uint32_t v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = e + k < e1 ? a.push_edge[e + k] : 0u;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (e + k < e1) atomicAdd(L.I + (v[k] & 0xFFFFu), half_bits_to_float(v[k] >> 16));
+        }
+    }
+}
+
 // kModels: 0 for LIF networks only, 1 with Izhikevich networks, 2 with
 // Hodgkin-Huxley networks too (the FP64 branches a kernel cannot meet are
-// compiled out: the LIF kernel needs no register spills).  kHeld: the plan
-// gives every workgroup one network of at most one chunk per wave, whose
-// chunk then stays in registers (a separate instantiation, so that the
-// registers it holds do not weigh on the streaming kernel).  A held FP64
+// compiled out: the LIF kernel needs no register spills).  kStream: how a
+// wave reads its chunks.  kEnsHeld: the plan gives every workgroup one
+// network of at most one chunk per wave, whose chunk then stays in
+// registers (a separate instantiation, so that the registers it holds do
+// not weigh on the streaming kernels).  kEnsLocal: each step streams the
+// 2-byte local sources and the delay bytes (3 B per slot); kEnsPacked: the
+// 2-byte slots carry the delay too (2 B per slot), when every network's
+// vertex count and largest delay fit in 16 bits together.  A held FP64
 // model kernel runs at most 512 threads per workgroup, which gives it twice
 // the registers and no spills; the streaming ones keep 1024 threads (more
 // waves for large networks' edges) at the cost of some spills.
-template <int kModels, bool kHeld>
-__global__ void __launch_bounds__((kModels == 0 || !kHeld) ? 1024 : 512) ensemble_kernel(EnsembleArgs a) {
+template <int kModels, int kStream>
+__global__ void __launch_bounds__((kModels == 0 || kStream != kEnsHeld) ? 1024 : 512) ensemble_kernel(EnsembleArgs a) {
     const int64_t t0 = a.t_dev ? static_cast<int64_t>(*a.t_dev) : a.t0;   // graph replays read the step
     extern __shared__ uint4 lds4[];
     uint8_t* lds = reinterpret_cast<uint8_t*>(lds4);
@@ -936,6 +1001,14 @@ __global__ void __launch_bounds__((kModels == 0 || !kHeld) ? 1024 : 512) ensembl
     const int q_begin = a.wg_off[blockIdx.x], q_end = a.wg_off[blockIdx.x + 1];
     const bool obs = a.calcium != nullptr;
 
+    // ---- spike logs: cleared, then refilled from the history ring below
+    if (kStream != kEnsHeld) {
+        for (int q = q_begin; q < q_end; ++q) {
+            const NetMeta nm = a.meta[a.wg_nets[q]];
+            if (nm.log_cap > 0 && tid < 32) log_of(lds, nm).cnt[tid] = 0u;
+        }
+        __syncthreads();
+    }
     // ---- load the state of every network of this workgroup into LDS
     for (int q = q_begin; q < q_end; ++q) {
         const NetMeta nm = a.meta[a.wg_nets[q]];
@@ -959,7 +1032,17 @@ __global__ void __launch_bounds__((kModels == 0 || !kHeld) ? 1024 : 512) ensembl
                 const uint32_t hi = gr[((static_cast<uint32_t>(t0 - 1) & 255u) >> 5) * a.n_pad];
                 const uint32_t lo = gr[((static_cast<uint32_t>(t0 - 32) & 255u) >> 5) * a.n_pad];
                 const uint32_t m = (1u << q32) - 1u;
-                L.ring[j] = q32 == 0 ? hi : ((hi & m) | (lo & ~m));
+                const uint32_t r = q32 == 0 ? hi : ((hi & m) | (lo & ~m));
+                L.ring[j] = r;
+                if (kStream != kEnsHeld && nm.log_cap > 0) {
+                    // bit b of the word is the step congruent to b mod 32: its bucket
+                    const NetLog g = log_of(lds, nm);
+                    for (uint32_t bits = r; bits != 0u; bits &= bits - 1u) {
+                        const uint32_t b = static_cast<uint32_t>(__builtin_ctz(bits));
+                        const uint32_t pos = atomicAdd(g.cnt + b, 1u);
+                        if (pos < static_cast<uint32_t>(nm.log_cap)) g.ids[b * nm.log_cap + pos] = static_cast<uint16_t>(j);
+                    }
+                }
             }
         }
     }
@@ -968,7 +1051,7 @@ __global__ void __launch_bounds__((kModels == 0 || !kHeld) ? 1024 : 512) ensembl
     // A workgroup that holds one network of at most one chunk per wave keeps
     // that chunk (sources, delays, weights, row starts) in registers for all
     // its steps: no load on the per-step path.
-    constexpr bool held = kHeld;
+    constexpr bool held = kStream == kEnsHeld;
     u32x4 h_lo = u32x4{0u, 0u, 0u, 0u}, h_hi = h_lo, h_w = h_lo;
     u32x2 h_d = u32x2{0u, 0u};
     uint32_t h_rs = 0u;
@@ -996,44 +1079,75 @@ __global__ void __launch_bounds__((kModels == 0 || !kHeld) ? 1024 : 512) ensembl
             const uint32_t rmask = 32u * static_cast<uint32_t>(nm.words) - 1u;
             if (held) {
                 const int c = nm.chunk_begin + wave;
-                if (c < nm.chunk_end)
-                    ens_deliver_chunk(a, nm, L, rmask, t, c, lane, h_lo, h_hi, h_d, true, h_w, h_rs, h_row0);
+                if (c < nm.chunk_end) {
+                    const uint32_t sv[8] = {h_lo.x, h_lo.y, h_lo.z, h_lo.w, h_hi.x, h_hi.y, h_hi.z, h_hi.w};
+                    uint32_t sl[8], dk[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        sl[k] = sv[k] - static_cast<uint32_t>(nm.node_off);
+                        dk[k] = ((k < 4 ? h_d.x : h_d.y) >> (8 * (k & 3))) & 0xFFu;
+                    }
+                    ens_deliver_chunk(a, nm, L, rmask, t, c, lane, sl, dk, true, h_w, h_rs, h_row0);
+                }
                 continue;
             }
-            // the next kDepth - 1 chunks' edges are in flight while this chunk is
-            // resolved (a register ring of this wave's chunks c, c + nwaves, ...)
-            constexpr int kDepth = 2;   // (4 measured slower: more registers, fewer waves)
+            if (nm.log_cap > 0) {
+                const NetLog g = log_of(lds, nm);
+                if (tid == 0) g.cnt[static_cast<uint32_t>(t) & 31u] = 0u;   // refilled by this step's update
+                if (log_complete(g, nm, t, lane)) continue;                    // pushed below
+            }
+            // the next kDepth - 1 chunks' slots are in flight while this chunk
+            // is resolved (a register ring of this wave's chunks c, c + nwaves,
+            // ...); weights and row starts are read only for chunks with an
+            // arrival (streaming them too measured slower)
+            constexpr bool packed = kStream == kEnsPacked;
+            constexpr int kDepth = packed ? 4 : 3;
+            const uint32_t smask = (1u << a.sbits) - 1u;
             int c = nm.chunk_begin + wave;
-            u32x4 q_lo[kDepth], q_hi[kDepth];
+            u32x4 q_s[kDepth];
             u32x2 q_d[kDepth];
 #pragma unroll
             for (int u = 0; u < kDepth; ++u) {
-                q_lo[u] = q_hi[u] = u32x4{0u, 0u, 0u, 0u};
+                q_s[u] = u32x4{0u, 0u, 0u, 0u};
                 q_d[u] = u32x2{0u, 0u};
                 if (c + u * nwaves < nm.chunk_end) {
                     const int64_t e = static_cast<int64_t>(c + u * nwaves) * kChunkEdges + lane * kEdgesPerLane;
-                    q_lo[u] = *reinterpret_cast<const u32x4*>(a.src + e);
-                    q_hi[u] = *reinterpret_cast<const u32x4*>(a.src + e + 4);
-                    q_d[u] = *reinterpret_cast<const u32x2*>(a.d + e);
+                    q_s[u] = *reinterpret_cast<const u32x4*>(a.ls + e);
+                    if (!packed) q_d[u] = *reinterpret_cast<const u32x2*>(a.d + e);
                 }
             }
             for (; c < nm.chunk_end; c += nwaves) {
                 const int64_t e0 = static_cast<int64_t>(c) * kChunkEdges + lane * kEdgesPerLane;
-                const u32x4 s_lo = q_lo[0], s_hi = q_hi[0];
+                const u32x4 sq = q_s[0];
                 const u32x2 dq = q_d[0];
 #pragma unroll
                 for (int u = 0; u + 1 < kDepth; ++u) {
-                    q_lo[u] = q_lo[u + 1];
-                    q_hi[u] = q_hi[u + 1];
+                    q_s[u] = q_s[u + 1];
                     q_d[u] = q_d[u + 1];
                 }
                 if (c + kDepth * nwaves < nm.chunk_end) {
                     const int64_t e = e0 + static_cast<int64_t>(kDepth * nwaves) * kChunkEdges;
-                    q_lo[kDepth - 1] = *reinterpret_cast<const u32x4*>(a.src + e);
-                    q_hi[kDepth - 1] = *reinterpret_cast<const u32x4*>(a.src + e + 4);
-                    q_d[kDepth - 1] = *reinterpret_cast<const u32x2*>(a.d + e);
+                    q_s[kDepth - 1] = *reinterpret_cast<const u32x4*>(a.ls + e);
+                    if (!packed) q_d[kDepth - 1] = *reinterpret_cast<const u32x2*>(a.d + e);
                 }
-                ens_deliver_chunk(a, nm, L, rmask, t, c, lane, s_lo, s_hi, dq, false, h_w, 0u, 0);
+                uint32_t sl[8], dk[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const uint32_t v = (comp4(sq, k >> 1) >> (16 * (k & 1))) & 0xFFFFu;
+                    sl[k] = packed ? (v & smask) : v;
+                    dk[k] = packed ? (v >> a.sbits) : (((k < 4 ? dq.x : dq.y) >> (8 * (k & 3))) & 0xFFu);
+                }
+                ens_deliver_chunk(a, nm, L, rmask, t, c, lane, sl, dk, false, h_w, 0u, 0);
+            }
+        }
+        // networks whose logs hold every recent spike: one wave each pushes
+        // the spikes along their out-edges
+        if (!held) {
+            for (int q = q_begin + wave; q < q_end; q += nwaves) {
+                const NetMeta nm = a.meta[a.wg_nets[q]];
+                if (nm.log_cap == 0) continue;
+                const NetLog g = log_of(lds, nm);
+                if (log_complete(g, nm, t, lane)) ens_push(a, nm, carve(lds, nm, obs), g, t, lane);
             }
         }
         __syncthreads();
@@ -1065,6 +1179,20 @@ __global__ void __launch_bounds__((kModels == 0 || !kHeld) ? 1024 : 512) ensembl
                 const uint64_t alive = wave_ballot(valid);
                 if (a.rec_raster && lane == 0 && alive != 0)
                     put_bits_shared(a.rec_raster + s * a.raster_words, nm.node_off + base + wave * 64, spikes, alive);
+                if (kStream != kEnsHeld && nm.log_cap > 0 && spikes != 0) {
+                    // this step's spikes into bucket t mod 32 (one atomic per wave)
+                    const NetLog g = log_of(lds, nm);
+                    const uint32_t b = static_cast<uint32_t>(t) & 31u;
+                    const int leader = __builtin_ctzll(spikes);
+                    uint32_t first = 0;
+                    if (lane == leader) first = atomicAdd(g.cnt + b, static_cast<uint32_t>(__popcll(spikes)));
+                    first = __shfl(first, leader, 64);
+                    if (spike) {
+                        const uint32_t pos = first + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(spikes >> 32),
+                                                                               __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(spikes), 0u));
+                        if (pos < static_cast<uint32_t>(nm.log_cap)) g.ids[b * nm.log_cap + pos] = static_cast<uint16_t>(j);
+                    }
+                }
                 float vn;
                 uint32_t age_n;
                 const bool held = age >= 1u && age <= static_cast<uint32_t>(p.n_ref);
@@ -1935,27 +2063,42 @@ hipError_t launch_ensemble(const DeviceGraph& g, const EnsemblePlan& plan, int64
     a.frame_num = frame_num > 0 ? frame_num : 1;
     a.frame_den = frame_den > 0 ? frame_den : 1;
     a.d_sum = g.d_sum;
+    a.ls = g.ens_ls;
+    a.sbits = g.ens_sbits;
+    a.push_off = g.push_off;
+    a.push_edge = g.push_edge;
     const int m = g.hh_m ? 2 : (g.Vd ? 1 : 0);
+    const int k = plan.held ? kEnsHeld : (g.ens_sbits < 16 ? kEnsPacked : kEnsLocal);
+    if (k != kEnsHeld && !g.ens_ls) return hipErrorInvalidValue;
     const dim3 grid(plan.blocks), block(plan.threads);
-    if (plan.held) {
-        if (m == 2) hipExtLaunchKernelGGL((ensemble_kernel<2, true>), grid, block, plan.lds_bytes, s, ev0, ev1, 0, a);
-        else if (m == 1) hipExtLaunchKernelGGL((ensemble_kernel<1, true>), grid, block, plan.lds_bytes, s, ev0, ev1, 0, a);
-        else hipExtLaunchKernelGGL((ensemble_kernel<0, true>), grid, block, plan.lds_bytes, s, ev0, ev1, 0, a);
+#define GEONET_ENS(M, K) hipExtLaunchKernelGGL((ensemble_kernel<M, K>), grid, block, plan.lds_bytes, s, ev0, ev1, 0, a)
+    if (k == kEnsHeld) {
+        if (m == 2) GEONET_ENS(2, kEnsHeld);
+        else if (m == 1) GEONET_ENS(1, kEnsHeld);
+        else GEONET_ENS(0, kEnsHeld);
+    } else if (k == kEnsLocal) {
+        if (m == 2) GEONET_ENS(2, kEnsLocal);
+        else if (m == 1) GEONET_ENS(1, kEnsLocal);
+        else GEONET_ENS(0, kEnsLocal);
     } else {
-        if (m == 2) hipExtLaunchKernelGGL((ensemble_kernel<2, false>), grid, block, plan.lds_bytes, s, ev0, ev1, 0, a);
-        else if (m == 1) hipExtLaunchKernelGGL((ensemble_kernel<1, false>), grid, block, plan.lds_bytes, s, ev0, ev1, 0, a);
-        else hipExtLaunchKernelGGL((ensemble_kernel<0, false>), grid, block, plan.lds_bytes, s, ev0, ev1, 0, a);
+        if (m == 2) GEONET_ENS(2, kEnsPacked);
+        else if (m == 1) GEONET_ENS(1, kEnsPacked);
+        else GEONET_ENS(0, kEnsPacked);
     }
+#undef GEONET_ENS
     return hipGetLastError();
 }
 
 hipError_t enable_ensemble_lds(size_t bytes) {
-    const void* fns[] = {reinterpret_cast<const void*>(&ensemble_kernel<0, false>),
-                         reinterpret_cast<const void*>(&ensemble_kernel<1, false>),
-                         reinterpret_cast<const void*>(&ensemble_kernel<2, false>),
-                         reinterpret_cast<const void*>(&ensemble_kernel<0, true>),
-                         reinterpret_cast<const void*>(&ensemble_kernel<1, true>),
-                         reinterpret_cast<const void*>(&ensemble_kernel<2, true>)};
+    const void* fns[] = {reinterpret_cast<const void*>(&ensemble_kernel<0, kEnsHeld>),
+                         reinterpret_cast<const void*>(&ensemble_kernel<1, kEnsHeld>),
+                         reinterpret_cast<const void*>(&ensemble_kernel<2, kEnsHeld>),
+                         reinterpret_cast<const void*>(&ensemble_kernel<0, kEnsLocal>),
+                         reinterpret_cast<const void*>(&ensemble_kernel<1, kEnsLocal>),
+                         reinterpret_cast<const void*>(&ensemble_kernel<2, kEnsLocal>),
+                         reinterpret_cast<const void*>(&ensemble_kernel<0, kEnsPacked>),
+                         reinterpret_cast<const void*>(&ensemble_kernel<1, kEnsPacked>),
+                         reinterpret_cast<const void*>(&ensemble_kernel<2, kEnsPacked>)};
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
         if (e != hipSuccess) return e;

@@ -310,6 +310,46 @@ def test_ensemble_kernel_split_calls(three_d):
         assert np.abs(v[:900, sl] - o[k]["v"]).max() <= V_TOL
 
 
+@pytest.mark.parametrize("n_big, stream", [(200, 3), (300, 2)])
+def test_ensemble_streams_long_delays(n_big, stream):
+    """The single-launch kernel's two streamed slot formats against the
+    oracle: a source firing every ~23 steps with delays of 1..255 steps, in
+    one ensemble with a noisy network of n_big vertices.  With n_big = 200
+    (8 source bits) the 255-step delay still fits beside the source in a
+    2-byte slot (format 3); with n_big = 300 (9 source bits) it does not, and
+    the kernel reads the 2-byte sources and the delay bytes (format 2).
+    Inputs and rasters must equal the oracle's at every step."""
+    gn, torch = _gn()
+    delays = np.array([1, 43, 128, 200, 254, 255], dtype=np.uint8)
+    fast = synth.NetSpec(name="fast", pos_um=np.zeros((7, 2)), src=np.zeros(6, np.int32),
+                         dst=np.arange(1, 7, dtype=np.int32), weight=synth.round_fp16(np.full(6, 0.25)),
+                         delay_steps=delays, i_ext=np.array([0.5, 0, 0, 0, 0, 0, 0], np.float32), seed=3)
+    # 60 random in-edges per vertex over a 1 mm square (delays up to 142
+    # steps): more chunks than a workgroup has waves, so every step streams them
+    base = synth.config0_like(n_big, synth.config_seed(3, 40 + n_big), w0=0.36)
+    rng = np.random.default_rng(n_big)
+    idx = rng.choice(n_big * n_big, size=60 * n_big, replace=False)
+    src, dst = (idx // n_big).astype(np.int32), (idx % n_big).astype(np.int32)
+    keep = src != dst
+    src, dst = src[keep], dst[keep]
+    big = synth.NetSpec(name="dense", pos_um=base.pos_um, src=src, dst=dst,
+                        weight=synth.round_fp16(rng.uniform(0.5, 1.5, src.size) * 0.02),
+                        drive_rate_hz=base.drive_rate_hz, noise_sigma=0.05, seed=base.seed)
+    specs = [big, fast]
+    T = 1500
+    g = run_gpu(specs, T)
+    info = g["net"].info()
+    assert info["ensemble_blocks"] > 0 and info["ensemble_stream"] == stream
+    offs = g["net"].node_offsets()
+    for k, s in enumerate(specs):
+        a, b = offs[k], offs[k + 1]
+        o = oracle.OracleNet(s).step(T, v=True, inp=True)
+        sub = {"raster": g["raster"][:, a:b], "v": g["v"][:, a:b], "input": g["input"][:, a:b]}
+        check_parity(sub, o, exact_raster=s is fast)
+    o_fast = oracle.OracleNet(fast).step(T, v=False, inp=True)
+    assert (o_fast["input"][:, 6] != 0).sum() > 30            # arrivals on the 255-step edge
+
+
 def test_observation_frames_and_fluorescence():
     gn, torch = _gn()
     spec = synth.config0_like(256, synth.config_seed(4, 0), w0=0.36)
