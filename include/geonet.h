@@ -214,6 +214,17 @@ typedef struct {
                                              device counter the graph advances.  Same results; steps outside
                                              whole 256-step blocks run as plain launches.  Not for plastic
                                              networks (ignored). */
+#define NET_BUILD_PUSH 16384             /* deliver by pushing spikes instead of testing every in-edge: each
+                                             step's update lists the vertices that fired (one atomic per wave)
+                                             and a second kernel adds the weight of every out-edge of each of
+                                             them into an input ring indexed by arrival step (one FP32 word per
+                                             vertex and ring slot, as many slots as the next power of two above
+                                             the largest delay); the update of step t reads and clears slot t.
+                                             The work per step is the spikes' out-edges, not all edges.  Used
+                                             only when every target's weights sum exactly (the order of the
+                                             additions then changes no bit), with the per-step kernels and no
+                                             graph replays; ignored for plastic networks.  net_info's
+                                             deliver_flags shows whether it is in use. */
 #define NET_BUILD_AUTOTUNE 64             /* time the candidate launch shapes on this graph at
                                              build (a few steps from the initial state, which is
                                              then restored) and keep the fastest: delivery

@@ -18,7 +18,7 @@ import numpy as np
 from . import _abi
 from ._abi import (NET_BUILD_AUTOTUNE, NET_BUILD_DELIVER_NONTEMPORAL, NET_BUILD_DELIVER_PIPELINE,
                    NET_BUILD_DELIVER_STREAM_WEIGHTS, NET_BUILD_SUMMARY_HALF, NET_BUILD_DELIVER_COMPACT, NET_BUILD_FUSED_STEP,
-                   NET_BUILD_DELIVER_PACKED, NET_BUILD_REORDER, NET_BUILD_GRAPH,
+                   NET_BUILD_DELIVER_PACKED, NET_BUILD_REORDER, NET_BUILD_GRAPH, NET_BUILD_PUSH,
                    NET_BUILD_DELIVER_UNROLL2, NET_BUILD_NO_LDS_SUMMARY, NET_BUILD_PER_STEP, NET_BUILD_SINGLE_LAUNCH,
                    NET_OBS_CALCIUM, NET_OBS_FLUOR, NET_OBS_FRAMES, NET_OBS_REF, NET_OBS_WEIGHTS,
                    NET_OBS_V, NET_OK, NET_W_INEXACT)
@@ -28,7 +28,7 @@ __all__ = ["Net", "Mlp", "GeonetError", "NET_OBS_V", "NET_OBS_REF", "NET_OBS_CAL
            "NET_BUILD_DELIVER_NONTEMPORAL", "NET_BUILD_DELIVER_UNROLL2", "NET_BUILD_PER_STEP",
            "NET_BUILD_SINGLE_LAUNCH", "NET_BUILD_AUTOTUNE", "NET_BUILD_DELIVER_PIPELINE",
            "NET_BUILD_SUMMARY_HALF", "NET_BUILD_DELIVER_COMPACT", "NET_BUILD_FUSED_STEP", "NET_BUILD_DELIVER_PACKED",
-           "NET_BUILD_REORDER", "NET_BUILD_GRAPH",
+           "NET_BUILD_REORDER", "NET_BUILD_GRAPH", "NET_BUILD_PUSH",
            "library"]
 
 

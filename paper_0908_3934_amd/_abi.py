@@ -30,6 +30,7 @@ NET_BUILD_DELIVER_PACKED = 2048
 NET_BUILD_AUTOTUNE = 64
 NET_BUILD_REORDER = 4096
 NET_BUILD_GRAPH = 8192
+NET_BUILD_PUSH = 16384
 
 NET_MODEL_LIF = 0
 NET_MODEL_IZHIKEVICH = 1

@@ -374,12 +374,12 @@ net_status records_to_caller(net* h, const net_record* rec, int64_t rows, hipStr
 net_status step_loop(net* h, int64_t n_steps, const net_record* rec, hipStream_t s, bool observe) {
     for (int64_t k = 0; k < n_steps; ++k) {
         const int64_t t = h->t + k;
-        hipEvent_t d0, d1, u0, u1;
-        next_events(h, h->lc.fused ? 3 : 0, 1, &d0, &d1);
+        hipEvent_t d0 = nullptr, d1 = nullptr, u0, u1;
+        if (!h->lc.push) next_events(h, h->lc.fused ? 3 : 0, 1, &d0, &d1);   // (push: no delivery kernel)
         if (h->g.wq) {
             hipError_t e = launch_plastic_deliver(h->g, t, s, d0, d1);
             if (e != hipSuccess) return device_fail(h, e, "net_step_n: plastic delivery launch");
-        } else if (!h->lc.fused) {
+        } else if (!h->lc.fused && !h->lc.push) {
             hipError_t e = launch_deliver(h->g, h->lc, t, s, d0, d1);
             if (e != hipSuccess) return device_fail(h, e, "net_step_n: delivery launch");
         }
@@ -652,7 +652,9 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
     }
     g.frame_num = hg.frame_num;
     g.frame_den = hg.frame_den > 0 ? hg.frame_den : 1;
-    if (opts && (opts->flags & NET_BUILD_GRAPH) && !hg.plastic) {
+    // push delivery: per-step kernels only, and only where every sum is exact
+    const bool push = opts && (opts->flags & NET_BUILD_PUSH) && !hg.plastic && hg.exact;
+    if (opts && (opts->flags & NET_BUILD_GRAPH) && !hg.plastic && !push) {
         if ((st = zeros(h, &h->t_dev, 1, s, "step counter")) != NET_OK) return bail(st);
         h->graph = true;
     }
@@ -741,10 +743,53 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
         device_fail(h, e, "net_build: configure");
         return bail(NET_E_DEVICE);
     }
+    if (push) {
+        // out-edges of every source (zero weights, the empty rows'
+        // placeholders among them, add nothing and are left out): the target
+        // of a slot is its chunk's first row plus the row starts after it
+        const int64_t nv = g.n_pad;
+        std::vector<uint32_t> off(static_cast<size_t>(nv) + 1, 0u);
+        auto each_edge = [&](auto&& f) {
+            for (int64_t c = 0; c < hg.n_chunks; ++c) {
+                int64_t r = hg.chunk_row0[c];
+                for (int64_t k = c * kChunkEdges; k < (c + 1) * kChunkEdges; ++k) {
+                    if (k != c * kChunkEdges && ((hg.rowstart[k >> 3] >> (k & 7)) & 1u)) ++r;
+                    if ((hg.w[k] & 0x7FFFu) != 0) f(k, r);
+                }
+            }
+        };
+        each_edge([&](int64_t k, int64_t) { ++off[static_cast<size_t>(hg.src[k]) + 1]; });
+        for (int64_t i = 0; i < nv; ++i) off[i + 1] += off[i];
+        std::vector<uint2> out(static_cast<size_t>(std::max<uint32_t>(off[nv], 1u)));
+        {
+            std::vector<uint32_t> fill(off.begin(), off.end() - 1);
+            each_edge([&](int64_t k, int64_t r) {
+                out[fill[hg.src[k]]++] = make_uint2(static_cast<uint32_t>(r),
+                                                    static_cast<uint32_t>(hg.w[k]) | (static_cast<uint32_t>(hg.d[k]) << 16));
+            });
+        }
+        uint32_t mask = 1;
+        while (mask <= static_cast<uint32_t>(hg.max_delay)) mask <<= 1;   // slots > largest delay
+        uint32_t* doff = nullptr;
+        uint2* dout = nullptr;
+        st = upload(h, &doff, off, off.size(), s, "out-edges");
+        if (st == NET_OK) st = upload(h, &dout, out, out.size(), s, "out-edges");
+        if (st == NET_OK) st = zeros(h, &g.in_ring, static_cast<size_t>(mask) * static_cast<size_t>(nv), s, "input ring");
+        if (st == NET_OK) {
+            const hipError_t se = hipStreamSynchronize(s);   // the host tables are freed below
+            if (se != hipSuccess) st = device_fail(h, se, "net_build: upload");
+        }
+        if (st != NET_OK) return bail(st);
+        g.out_off = doff;
+        g.out_edge = dout;
+        g.in_ring_mask = mask - 1;
+        h->lc.push = true;
+        h->lc.fused = false;
+    }
     // a plastic network runs the per-step kernels only (trial steps would move its weights)
     const int flags = hg.plastic ? 0 : (opts ? opts->flags : 0);
     const bool autotune = (flags & NET_BUILD_AUTOTUNE) != 0;
-    const bool single = n_nets > 1 || (flags & NET_BUILD_SINGLE_LAUNCH);
+    const bool single = !push && (n_nets > 1 || (flags & NET_BUILD_SINGLE_LAUNCH));
     if (single && !(flags & NET_BUILD_PER_STEP)) {
         // the single-launch kernel's 2-byte stream: sources within their
         // network, packed with the delay when both fit in 16 bits
@@ -912,7 +957,7 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
             }
         }
     }
-    if (autotune && !h->plan.enabled && !h->lc.fused) {
+    if (autotune && !h->plan.enabled && !h->lc.fused && !h->lc.push) {
         // delivery variants of the per-step kernels (identical results)
         const int variants[] = {0,
                                 NET_BUILD_DELIVER_PIPELINE,
@@ -1115,7 +1160,7 @@ net_status net_info(const net_t* h, net_info_t* out) {
                          (h->lc.mode == 4 ? NET_BUILD_DELIVER_PACKED : 0) |
                          (h->lc.mode == 2 ? NET_BUILD_DELIVER_PIPELINE : 0) |
                          (h->lc.mode == 3 ? NET_BUILD_DELIVER_COMPACT : 0) |
-                         (h->lc.fused ? NET_BUILD_FUSED_STEP : 0) |
+                         (h->lc.fused ? NET_BUILD_FUSED_STEP : 0) | (h->lc.push ? NET_BUILD_PUSH : 0) |
                          (h->lc.nontemporal ? NET_BUILD_DELIVER_NONTEMPORAL : 0) |
                          (h->lc.stream_weights ? NET_BUILD_DELIVER_STREAM_WEIGHTS : 0) |
                          (h->g.sum_shift ? NET_BUILD_SUMMARY_HALF : 0);

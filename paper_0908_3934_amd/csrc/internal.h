@@ -181,6 +181,14 @@ struct DeviceGraph {
     // n x maxd + 1 offsets, entry s * maxd + d - 1 opening group (s, d)
     const uint32_t* push_off = nullptr;
     const uint32_t* push_edge = nullptr;
+    // push delivery of the per-step update (NET_BUILD_PUSH): out-edges of
+    // each source (target, FP16 weight | delay << 16) from out_off[source];
+    // the input ring [in_ring_mask + 1][n_pad] (slot t & in_ring_mask holds
+    // the inputs arriving at step t)
+    const uint32_t* out_off = nullptr;
+    const uint2* out_edge = nullptr;
+    float* in_ring = nullptr;
+    uint32_t in_ring_mask = 0;
     const uint8_t* rowstart;
     const int32_t* chunk_row0;
     const NetParams* params;
@@ -243,6 +251,7 @@ struct LaunchConfig {
     int mode = 0;                  // delivery loop: 0 one chunk, 1 two chunks, 2 pipelined, 3 compacted,
                                    // 4 two packed chunks with the next pair prefetched
     bool fused = false;            // one kernel per step (delivery + vertex update), see launch_step
+    bool push = false;             // push delivery (NET_BUILD_PUSH): the update kernel alone, per step
     int32_t queue_off = 0;         // fused step: arrival queues' offset in LDS (floats after the inputs)
     size_t lds_bytes = 0;
 };

@@ -564,6 +564,12 @@ struct NodeArgs {
     double* __restrict__ hh_vprev;
     int32_t* __restrict__ spk_hist;   // plastic networks: last kStdpHist spike steps per vertex
     int32_t* __restrict__ spk_cnt;
+    // push delivery (else null): out-edges of each source and the input ring
+    // (slot s at push_ring + s * n_pad) the spikes of this step add into
+    const uint32_t* __restrict__ out_off;
+    const uint2* __restrict__ out_edge;
+    float* __restrict__ push_ring;
+    uint32_t push_mask;
     const int32_t* __restrict__ caller_of;   // renumbered networks: caller's index of each vertex (else null)
     // graph replays (else null): the step is *t_dev + t_off, and the frame
     // bookkeeping follows from it (frame_num > 0: observation on)
@@ -611,7 +617,7 @@ __device__ __forceinline__ VertexState load_vertex_state(const NodeArgs& a, int6
     st.v = a.V[jj];
     st.ages = a.age[jj];
     st.aux = a.drive_thr ? a.drive_thr[jj] : 0u;
-    st.ring = a.ring[((a.t_lo & 0xFFu) >> 5) * a.n_pad + jj];
+    st.ring = a.out_edge ? 0u : a.ring[((a.t_lo & 0xFFu) >> 5) * a.n_pad + jj];   // (push delivery keeps no ring)
     return st;
 }
 
@@ -664,6 +670,23 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
     const uint64_t spikes = wave_ballot(spike);
     if (a.rec_raster && lane == 0 && j < word_end && j < a.n_total)
         a.rec_raster[a.rec_row * a.raster_words + (j >> 6)] = spikes;
+    if (a.out_edge && spikes != 0) {
+        // push delivery: the wave walks the out-edges of each of its spiking
+        // vertices, 64 at a time, adding each weight into the ring slot of its
+        // arrival step t + d (never slot t, which this step reads: the ring
+        // has more slots than the largest delay).  The sums are exact, so the
+        // order of the atomics changes no bit.
+        const int64_t j0 = j - lane;
+        for (uint64_t m = spikes; m != 0; m &= m - 1) {
+            const int64_t src = j0 + __builtin_ctzll(m);
+            const uint32_t e1 = a.out_off[src + 1];
+            for (uint32_t e = a.out_off[src] + static_cast<uint32_t>(lane); e < e1; e += 64u) {
+                const uint2 ed = a.out_edge[e];
+                const uint32_t slot = (a.t_lo + (ed.y >> 16)) & a.push_mask;
+                atomicAdd(a.push_ring + static_cast<int64_t>(slot) * a.n_pad + ed.x, half_bits_to_float(ed.y & 0xFFFFu));
+            }
+        }
+    }
     if (valid) {
         if (a.rec_v) a.rec_v[a.rec_row * a.n_total + j] = v;
         if (a.rec_input) a.rec_input[a.rec_row * a.n_total + j] = in;
@@ -673,7 +696,7 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
         // changes
         const uint32_t slot = a.t_lo & 0xFFu;
         const uint32_t m = 1u << (slot & 31);
-        if (((st.ring & m) != 0u) != spike) a.ring[(slot >> 5) * a.n_pad + j] = st.ring ^ m;
+        if (!a.out_edge && ((st.ring & m) != 0u) != spike) a.ring[(slot >> 5) * a.n_pad + j] = st.ring ^ m;
     }
 
     float vn;
@@ -721,7 +744,7 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
     }
     // recent-spike summary for the next step: last spike within d_sum steps
     const uint64_t recent = wave_ballot(valid && age_n <= static_cast<uint32_t>(a.d_sum));
-    if (lane == 0 && j < word_end) {
+    if (lane == 0 && j < word_end && !a.out_edge) {   // (push delivery needs no summary)
         if (a.sum_shift == 0) {
             reinterpret_cast<uint64_t*>(a.summary)[j >> 6] = recent;
         } else {
@@ -1773,6 +1796,19 @@ static NodeArgs node_args(const DeviceGraph& g, int64_t t, int64_t rec_row, cons
     a.hh_vprev = g.hh_vprev;
     a.spk_hist = g.spk_hist;
     a.spk_cnt = g.spk_cnt;
+    a.out_off = nullptr;
+    a.out_edge = nullptr;
+    a.push_ring = nullptr;
+    a.push_mask = 0;
+    if (g.in_ring) {
+        // push delivery: the input is the ring slot of step t (read and cleared
+        // by the update), and the update pushes its own spikes
+        a.I = g.in_ring + static_cast<int64_t>(static_cast<uint64_t>(t) & g.in_ring_mask) * g.n_pad;
+        a.out_off = g.out_off;
+        a.out_edge = g.out_edge;
+        a.push_ring = g.in_ring;
+        a.push_mask = g.in_ring_mask;
+    }
     a.caller_of = g.caller_of;
     a.t_dev = g.t_dev;
     a.t_off = static_cast<uint32_t>(t);
