@@ -41,6 +41,14 @@ BYTES_PER_EDGE_STREAMED_W = 7   # delivery variant that streams every weight wit
 # fused step's vertex update: V read + written (8), two-spike ages read +
 # written (4), history-ring word read + written (8), one summary bit (1/8)
 BYTES_PER_VERTEX_UPDATE = 20.125
+# Push delivery (NET_BUILD_PUSH), one update kernel per step: per vertex V
+# read and written (8), ages read and written (4), the drive threshold (4),
+# its input-ring slot read and cleared (8); per arriving spike the out-edge
+# record (8) and the atomic add's read and write of the ring word (8); per
+# spike the source's two out-edge offsets (8).
+PUSH_BYTES_PER_VERTEX = 24
+PUSH_BYTES_PER_ARRIVAL = 16
+PUSH_BYTES_PER_SPIKE = 8
 TIMING_EVERY = 16       # kernel-bound events on one launch in 16 across long timed regions
 MIN_TIMED_LAUNCHES = 64  # shorter timed regions bind events to more launches (every launch below 64 steps)
 
@@ -141,6 +149,53 @@ def cpu_baseline(spec, steps):
         "sample": "same network, first %d of the steps (single-threaded FP64 event-driven oracle; "
                   "%.1f s run after %.1f s set-up; its per-step cost is the vertex update of all N "
                   "vertices, so the start-up's lower spike rate barely changes it)" % (steps, t2 - t1, t1 - t0),
+    }
+
+
+def push_variant(args, torch, gn, spec, arrivals, spikes, fused_ms):
+    """The same network, pre-roll, warm-up and timed steps with push delivery
+    (each spiking wave adds its out-edges into an input ring; bit-equal to the
+    fused step): whole-step rate and the update kernel against the bytes it
+    must move."""
+    t0 = time.perf_counter()
+    net = gn.Net(spec, flags=gn.NET_BUILD_PUSH)
+    info = net.info()
+    if not info["deliver_flags"] & gn.NET_BUILD_PUSH:
+        net.close()
+        return None
+    build_s = time.perf_counter() - t0
+    net.step(args.preroll + args.warmup)
+    torch.cuda.synchronize()
+    every = TIMING_EVERY if args.steps >= MIN_TIMED_LAUNCHES * TIMING_EVERY \
+        else max(1, args.steps // MIN_TIMED_LAUNCHES)
+    net.timing_begin(2 * args.steps // every + 4, every=every)
+    t0 = time.perf_counter()
+    net.step(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = net.timing_end()
+    net.close()
+    avg = tm["update_ms"] / tm["update_launches"] / 1e3
+    alg = PUSH_BYTES_PER_VERTEX * spec.n + PUSH_BYTES_PER_ARRIVAL * arrivals + PUSH_BYTES_PER_SPIKE * spikes
+    log("push delivery: %.2f us per step (update kernel %.2f us, %d timed), built in %.1f s"
+        % (wall / args.steps * 1e6, avg * 1e6, tm["update_launches"], build_s))
+    return {
+        "flags": "NET_BUILD_PUSH",
+        "value": spec.n_edges * args.steps / wall,
+        "unit": "edge-steps/s",
+        "ms_per_step": wall / args.steps * 1e3,
+        "speedup_vs_value": fused_ms / (wall / args.steps * 1e3),
+        "real_time_factor": args.steps * spec.dt_ms * 1e-3 / wall,
+        "kernel": "node_update_kernel (vertex update + push of its spikes)",
+        "avg_launch_us": avg * 1e6,
+        "timed_launches": tm["update_launches"],
+        "algorithmic_bytes_per_launch": alg,
+        "bytes_rule": "%d B per vertex + %d B per arriving spike + %d B per spike"
+                      % (PUSH_BYTES_PER_VERTEX, PUSH_BYTES_PER_ARRIVAL, PUSH_BYTES_PER_SPIKE),
+        "achieved_GBps": alg / avg / 1e9,
+        "frac": alg / avg / 1e9 / HBM_PEAK_GBS,
+        "note": "same spikes, V and inputs bit for bit as the fused step; the fused step stays the headline "
+                "(the pull over every in-edge with the history ring)",
     }
 
 
@@ -786,6 +841,7 @@ def estimate_cpu_baseline(o, sc, pairs=32768):
 
 
 def main():
+    import numpy as np
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
@@ -793,6 +849,8 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-push-variant", action="store_true",
+                    help="step workload: skip timing the same network with push delivery")
     ap.add_argument("--deliver-flags", type=int, default=1024,
                     help="NET_BUILD_* bits of the step variant (default 1024: one fused kernel per step, "
                          "the fastest measured; 16: delivery and update kernels, two chunks per wave "
@@ -901,7 +959,9 @@ def main():
     # and a second recorded window right after them.
     net.step(args.preroll)
     torch.cuda.synchronize()
-    arr_before = arrivals_per_step(net, spec, args.rate_steps)
+    spk = spikes_per_vertex(net, spec, args.rate_steps)
+    arr_before = float((spk * np.bincount(np.asarray(spec.src), minlength=spec.n)).sum()) / args.rate_steps
+    spikes = float(spk.sum()) / args.rate_steps
     net.step(args.warmup)
     torch.cuda.synchronize()
     every = TIMING_EVERY if args.steps >= MIN_TIMED_LAUNCHES * TIMING_EVERY \
@@ -920,10 +980,14 @@ def main():
     E = spec.n_edges
     value = E * args.steps / wall
     fused = tm["step_launches"] > 0
-    kernel = "step_kernel" if fused else "deliver_kernel"
+    pushed = bool(info["deliver_flags"] & gn.NET_BUILD_PUSH)
+    kernel = "step_kernel" if fused else ("node_update_kernel" if pushed else "deliver_kernel")
     if fused:
         avg_deliver_s = tm["step_ms"] / tm["step_launches"] / 1e3
         timed_launches = tm["step_launches"]
+    elif pushed:
+        avg_deliver_s = tm["update_ms"] / tm["update_launches"] / 1e3
+        timed_launches = tm["update_launches"]
     else:
         avg_deliver_s = tm["deliver_ms"] / tm["deliver_launches"] / 1e3
         timed_launches = tm["deliver_launches"]
@@ -943,6 +1007,10 @@ def main():
         fmt_bytes = per_edge * E + BYTES_PER_ARRIVAL * arrivals
     if fused:
         fmt_bytes += BYTES_PER_VERTEX_UPDATE * spec.n
+    if pushed:
+        # the push path's own bytes: it reads no in-edge list
+        alg_bytes = fmt_bytes = (PUSH_BYTES_PER_VERTEX * spec.n + PUSH_BYTES_PER_ARRIVAL * arrivals
+                                 + PUSH_BYTES_PER_SPIKE * spikes)
     achieved = alg_bytes / avg_deliver_s / 1e9
     traffic = measured_traffic(info["deliver_flags"])
     log("arrivals per step %.0f before / %.0f after the timed steps (%.4f %% of edges); algorithmic bytes "
@@ -992,9 +1060,11 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "algorithmic_bytes_per_launch": alg_bytes,
-            "bytes_rule": "%d B per edge + %d B per arriving spike + %d B per vertex%s"
-                          % (BYTES_PER_EDGE, BYTES_PER_ARRIVAL, BYTES_PER_VERTEX, "" if fused else
-                             " (vertex bytes belong to the separate update kernel)"),
+            "bytes_rule": ("%d B per vertex + %d B per arriving spike + %d B per spike (push delivery)"
+                           % (PUSH_BYTES_PER_VERTEX, PUSH_BYTES_PER_ARRIVAL, PUSH_BYTES_PER_SPIKE)) if pushed else
+                          ("%d B per edge + %d B per arriving spike + %d B per vertex%s"
+                           % (BYTES_PER_EDGE, BYTES_PER_ARRIVAL, BYTES_PER_VERTEX, "" if fused else
+                              " (vertex bytes belong to the separate update kernel)")),
             "arrivals_per_step": arrivals,
             "arrivals_per_step_before_after": [arr_before, arr_after],
             "avg_launch_us": avg_deliver_s * 1e6,
@@ -1008,6 +1078,8 @@ def main():
         },
     }
     net.close()
+    if not (info["deliver_flags"] & gn.NET_BUILD_PUSH) and not args.no_push_variant:
+        result["push_variant"] = push_variant(args, torch, gn, spec, arrivals, spikes, wall / args.steps * 1e3)
     ceil = stream_ceiling(torch, alg_bytes)
     ceil["frac_of_read_only"] = achieved / ceil["read_only_GBps"]
     result["roofline"]["measured_ceiling"] = ceil
