@@ -676,14 +676,20 @@ __device__ __forceinline__ void vertex_update(const NodeArgs& a, int64_t j, int6
         // arrival step t + d (never slot t, which this step reads: the ring
         // has more slots than the largest delay).  The sums are exact, so the
         // order of the atomics changes no bit.
+        // Two rounds of 64 edges are loaded before their atomics are issued.
         const int64_t j0 = j - lane;
         for (uint64_t m = spikes; m != 0; m &= m - 1) {
             const int64_t src = j0 + __builtin_ctzll(m);
             const uint32_t e1 = a.out_off[src + 1];
-            for (uint32_t e = a.out_off[src] + static_cast<uint32_t>(lane); e < e1; e += 64u) {
-                const uint2 ed = a.out_edge[e];
-                const uint32_t slot = (a.t_lo + (ed.y >> 16)) & a.push_mask;
-                atomicAdd(a.push_ring + static_cast<int64_t>(slot) * a.n_pad + ed.x, half_bits_to_float(ed.y & 0xFFFFu));
+            for (uint32_t e = a.out_off[src] + static_cast<uint32_t>(lane); e < e1; e += 128u) {
+                const bool second = e + 64u < e1;
+                const uint2 ed0 = a.out_edge[e];
+                const uint2 ed1 = second ? a.out_edge[e + 64u] : make_uint2(0u, 0u);
+                atomicAdd(a.push_ring + static_cast<int64_t>((a.t_lo + (ed0.y >> 16)) & a.push_mask) * a.n_pad + ed0.x,
+                          half_bits_to_float(ed0.y & 0xFFFFu));
+                if (second)
+                    atomicAdd(a.push_ring + static_cast<int64_t>((a.t_lo + (ed1.y >> 16)) & a.push_mask) * a.n_pad + ed1.x,
+                              half_bits_to_float(ed1.y & 0xFFFFu));
             }
         }
     }
