@@ -222,9 +222,9 @@ typedef struct {
                                              the largest delay); the update of step t reads and clears slot t.
                                              The work per step is the spikes' out-edges, not all edges.  Used
                                              only when every target's weights sum exactly (the order of the
-                                             additions then changes no bit), with the per-step kernels and no
-                                             graph replays; ignored for plastic networks.  net_info's
-                                             deliver_flags shows whether it is in use. */
+                                             additions then changes no bit), with the per-step update kernel
+                                             (NET_BUILD_GRAPH replays it too); ignored for plastic networks.
+                                             net_info's deliver_flags shows whether it is in use. */
 #define NET_BUILD_AUTOTUNE 64             /* time the candidate launch shapes on this graph at
                                              build (a few steps from the initial state, which is
                                              then restored) and keep the fastest: delivery

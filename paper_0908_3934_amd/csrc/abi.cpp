@@ -292,7 +292,7 @@ hipError_t step_graph(net* h, hipGraphExec_t* out) {
                 std::swap(gc.age, gc.age_alt);
                 std::swap(gc.summary, gc.summary_alt);
             } else {
-                e = launch_deliver(gc, lc, k, cs);
+                e = lc.push ? hipSuccess : launch_deliver(gc, lc, k, cs);   // (push: the update delivers)
                 if (e == hipSuccess) e = launch_node_update(gc, k, 0, nullptr, 0, 0, 0, cs);
             }
             if (e != hipSuccess) return e;
@@ -652,9 +652,9 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
     }
     g.frame_num = hg.frame_num;
     g.frame_den = hg.frame_den > 0 ? hg.frame_den : 1;
-    // push delivery: per-step kernels only, and only where every sum is exact
+    // push delivery: per-step update kernel only, and only where every sum is exact
     const bool push = opts && (opts->flags & NET_BUILD_PUSH) && !hg.plastic && hg.exact;
-    if (opts && (opts->flags & NET_BUILD_GRAPH) && !hg.plastic && !push) {
+    if (opts && (opts->flags & NET_BUILD_GRAPH) && !hg.plastic) {
         if ((st = zeros(h, &h->t_dev, 1, s, "step counter")) != NET_OK) return bail(st);
         h->graph = true;
     }

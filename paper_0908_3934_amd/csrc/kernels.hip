@@ -601,6 +601,7 @@ __device__ __forceinline__ void apply_device_step(NodeArgs& a) {
     const uint64_t t = *a.t_dev + a.t_off;
     a.t_lo = static_cast<uint32_t>(t);
     a.t_hi = static_cast<uint32_t>(t >> 32);
+    if (a.push_ring) a.I = a.push_ring + static_cast<int64_t>(a.t_lo & a.push_mask) * a.n_pad;   // this step's slot
     if (a.frame_num > 0) {
         const int64_t num = a.frame_num, den = a.frame_den;
         const int64_t ti = static_cast<int64_t>(t);

@@ -47,12 +47,14 @@ def _check_calls(a, b, calls):
     assert a.t == b.t
 
 
-@pytest.mark.parametrize("variant", ["default", "FUSED_STEP"])
+@pytest.mark.parametrize("variant", ["default", "FUSED_STEP", "PUSH"])
 def test_graph_per_step_kernels(variant):
     import paper_0908_3934_amd as gn
-    flags = 0 if variant == "default" else gn.NET_BUILD_FUSED_STEP
-    spec = _noisy(300, 0) if variant == "default" else synth.config1(n=8192)
+    flags = 0 if variant == "default" else getattr(gn, "NET_BUILD_" + variant)
+    spec = synth.config1(n=8192) if variant == "FUSED_STEP" else _noisy(300, 0)
     a, b = _pair(spec, flags)
+    if variant == "PUSH":
+        assert b.info()["deliver_flags"] & gn.NET_BUILD_PUSH
     # from 0: three whole graphs then plain steps; then a call that starts mid-block
     _check_calls(a, b, [1000, 100, 1000, 256, 513])
     a.close()
