@@ -1,5 +1,5 @@
-"""Push delivery (NET_BUILD_PUSH): each step's spikes are listed and their
-out-edges add into an input ring indexed by arrival step.  The delivered
+"""Push delivery (NET_BUILD_PUSH): the update kernel adds the out-edges of
+each vertex that fires into an input ring indexed by arrival step.  The delivered
 input of step t is still the sum over in-edges of w_ij s_i(t - d_ij)
 (Section 2, the delayed signalling), only computed from the sources' side;
 the sums are exact, so every bit must equal the oracle's and the pull
@@ -74,8 +74,8 @@ def test_no_edges_push(n):
 
 @pytest.mark.parametrize("spread", [1, 16])
 def test_synchronous_bursts_push(spread):
-    """Every vertex fires in lockstep: a step's list holds all 2,048
-    vertices and each of their 256 out-edges lands in the same slot."""
+    """Every vertex fires in lockstep: all 2,048 vertices push in one step
+    and each of their 256 out-edges lands in the slot of its delay."""
     gn, _ = _gn()
     rng = np.random.default_rng(spread)
     n, k = 2048, 256
@@ -165,3 +165,17 @@ def test_full_size_push_equals_fused():
     assert np.array_equal(va, vb)
     assert np.array_equal(ia, ib)
     assert np.count_nonzero(ia) > 10000
+
+
+def test_push_renumbered_equals_fused():
+    """A network numbered at random, renumbered in Morton order at build:
+    push delivery (out-edges in the internal numbering) and the fused step
+    give the same records in the caller's numbering."""
+    gn, _ = _gn()
+    spec = synth.relabel(synth.config1(n=8192), 5)
+    T = 800
+    a = run_gpu(spec, T, flags=gn.NET_BUILD_FUSED_STEP | gn.NET_BUILD_REORDER)
+    b = _push(spec, T, flags=gn.NET_BUILD_REORDER)
+    for key in ("raster", "v", "input"):
+        assert np.array_equal(a[key], b[key]), key
+    assert np.count_nonzero(b["input"]) > 1000
