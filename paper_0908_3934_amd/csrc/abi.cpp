@@ -35,6 +35,7 @@ struct net {
     int64_t t_seen[4] = {0, 0, 0, 0};
     EnsemblePlan plan;
     std::vector<int32_t> push_base;   // per network: first entry of its out-edge offsets, -1 if none
+    std::vector<int32_t> drv_off;     // [n_nets + 1] each network's range of the ensemble's drive list
     bool autotuned = false;
     // graph replays (NET_BUILD_GRAPH): device step counter, a private capture
     // stream, the 256-step graph of the per-step kernels and the ensemble
@@ -190,6 +191,9 @@ bool plan_ensemble(net* h, const HostGraph& hg, int n_cu, int wgs_per_cu, int th
         const bool push = nm.words == 1 && m < static_cast<int>(h->push_base.size()) && h->push_base[m] >= 0;
         nm.log_cap = push ? ens_log_cap(nm.n_nodes) : 0;
         nm.po_base = push ? h->push_base[m] : 0;
+        const bool drv = m + 1 < static_cast<int>(h->drv_off.size());
+        nm.drv_begin = drv ? h->drv_off[m] : 0;
+        nm.drv_end = drv ? h->drv_off[m + 1] : 0;
         need[m] = ensemble_lds_bytes(nm.n_nodes, nm.words, observe) + ens_log_bytes(nm.log_cap);
         if (need[m] > budget) return false;
         // per-step cost model: edge slots + vertices + a fixed share of the barriers
@@ -816,6 +820,33 @@ net_status net_build(const net_desc* descs, int32_t n_nets, const net_build_opts
             if (st != NET_OK) return bail(st);
             g.ens_ls = dls;
             g.ens_sbits = sb;
+        }
+        // the driven vertices of every network (index within the network, the
+        // caller's index for the Philox counter, the rate threshold): noise-free
+        // LIF networks draw their drive pulses for these alone
+        h->drv_off.clear();
+        if (hg.any_drive && max_n <= 65536) {
+            std::vector<uint2> drv;
+            h->drv_off.assign(n_nets + 1, 0);
+            for (int m = 0; m < n_nets; ++m) {
+                const int64_t off = hg.node_off[m];
+                h->drv_off[m] = static_cast<int32_t>(drv.size());
+                for (int64_t j = 0; j < hg.node_off[m + 1] - off; ++j) {
+                    const uint32_t thr = hg.drive_thr[off + j];
+                    if (thr == 0u) continue;
+                    const int64_t jl = reorder ? caller_of[off + j] - off : j;
+                    drv.push_back(make_uint2(static_cast<uint32_t>(j) | (static_cast<uint32_t>(jl) << 16), thr));
+                }
+            }
+            h->drv_off[n_nets] = static_cast<int32_t>(drv.size());
+            uint2* ddrv = nullptr;
+            st = upload(h, &ddrv, drv, drv.size(), s, "drive list");
+            if (st == NET_OK) {
+                const hipError_t se = hipStreamSynchronize(s);   // `drv` is freed below
+                if (se != hipSuccess) st = device_fail(h, se, "net_build: upload");
+            }
+            if (st != NET_OK) return bail(st);
+            g.ens_drv = ddrv;
         }
         // out-edge tables for the networks whose delays fit the 32-step LDS ring:
         // each source's out-edges grouped by delay (zero weights, the empty

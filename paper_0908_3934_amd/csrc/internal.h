@@ -81,6 +81,8 @@ struct NetMeta {
     // t mod 32 lists the vertices that fired at step t), and the first entry
     // of the network's out-edge offsets
     int32_t log_off, log_cap, po_base;
+    // driven vertices of the network in the ensemble's drive list [drv_begin, drv_end)
+    int32_t drv_begin, drv_end;
 };
 
 // Spike-log capacity per step bucket of a network of n vertices, and its LDS bytes.
@@ -181,6 +183,9 @@ struct DeviceGraph {
     // n x maxd + 1 offsets, entry s * maxd + d - 1 opening group (s, d)
     const uint32_t* push_off = nullptr;
     const uint32_t* push_edge = nullptr;
+    // single-launch ensemble kernel: the driven vertices of every network,
+    // (index within the network | Philox counter index << 16, threshold)
+    const uint2* ens_drv = nullptr;
     // push delivery of the per-step update (NET_BUILD_PUSH): out-edges of
     // each source (target, FP16 weight | delay << 16) from out_off[source];
     // the input ring [in_ring_mask + 1][n_pad] (slot t & in_ring_mask holds

@@ -867,6 +867,7 @@ struct EnsembleArgs {
                                              // sbits < 16 source | delay << sbits
     const uint32_t* __restrict__ push_off;   // out-edge tables of the networks with a spike log
     const uint32_t* __restrict__ push_edge;
+    const uint2* __restrict__ drv;           // driven vertices (index | counter index << 16, threshold)
     int64_t t0, n_total, n_pad, raster_words;
     int32_t n_steps, frame_cap, frame_num, frame_den, d_sum, sbits;
 };
@@ -1170,6 +1171,26 @@ __global__ void __launch_bounds__((kModels == 0 || kStream != kEnsHeld) ? 1024 :
                 ens_deliver_chunk(a, nm, L, rmask, t, c, lane, sl, dk, false, h_w, 0u, 0);
             }
         }
+        // drive pulses of noise-free LIF networks: the Philox draw only for the
+        // driven vertices, its outcome as bit 16 of the vertex's LDS age word
+        // (the update of this step reads and clears it)
+        if (a.drv) {
+            for (int q = q_begin; q < q_end; ++q) {
+                const int m = a.wg_nets[q];
+                const NetMeta nm = a.meta[m];
+                if (nm.drv_end == nm.drv_begin || a.params[m].model != NET_MODEL_LIF || a.params[m].sigma != 0.0f)
+                    continue;
+                const NetLds L = carve(lds, nm, obs);
+                const uint32_t key_lo = a.params[m].key_lo, key_hi = a.params[m].key_hi;
+                for (int i = nm.drv_begin + tid; i < nm.drv_end; i += blockDim.x) {
+                    const uint2 dv = a.drv[i];
+                    const uint4 r = philox4x32_10(make_uint4(dv.x >> 16, static_cast<uint32_t>(t),
+                                                             static_cast<uint32_t>(static_cast<uint64_t>(t) >> 32), 0u),
+                                                  key_lo, key_hi);
+                    if (r.x < dv.y) L.age[dv.x & 0xFFFFu] |= 1u << 16;
+                }
+            }
+        }
         // networks whose logs hold every recent spike: one wave each pushes
         // the spikes along their out-edges
         if (!held) {
@@ -1200,7 +1221,8 @@ __global__ void __launch_bounds__((kModels == 0 || kStream != kEnsHeld) ? 1024 :
                 if (izh) zs = IzhState{a.Vd[u], a.Wd[u], a.psc_r[u], a.psc_p[u]};
                 if (hh) hs = HhState{a.Vd[u], a.hh_vprev[u], a.hh_m[u], a.hh_n[u], a.hh_h[u], a.psc_r[u], a.psc_p[u]};
                 const float v = izh ? static_cast<float>(zs.v) : (hh ? static_cast<float>(hs.v) : L.V[jj]);
-                const uint32_t age = L.age[jj];
+                const uint32_t age_word = L.age[jj];   // bit 16: a precomputed drive pulse
+                const uint32_t age = age_word & 0xFFFFu;
                 const float in = L.I[jj];
                 const double vth = static_cast<double>(p.v_th);
                 const bool spike =
@@ -1280,13 +1302,17 @@ __global__ void __launch_bounds__((kModels == 0 || kStream != kEnsHeld) ? 1024 :
                     } else {
                         float uu = a.i_ext ? a.i_ext[u] : 0.0f;
                         float noise = 0.0f;
-                        const uint32_t thr = a.drive_thr ? a.drive_thr[u] : 0u;
-                        if (thr != 0u || p.sigma != 0.0f) {
-                            const uint4 r = philox4x32_10(make_uint4(static_cast<uint32_t>(a.caller_of ? a.caller_of[u] - nm.node_off : jj), static_cast<uint32_t>(t),
-                                                              static_cast<uint32_t>(static_cast<uint64_t>(t) >> 32), 0u),
-                                                   p.key_lo, p.key_hi);
-                            if (r.x < thr) uu += p.drive_amp;
-                            if (p.sigma != 0.0f) noise = p.sigma * gaussian(r.y, r.z);
+                        if (a.drv && p.sigma == 0.0f) {
+                            if ((age_word >> 16) & 1u) uu += p.drive_amp;   // drawn in the delivery phase
+                        } else {
+                            const uint32_t thr = a.drive_thr ? a.drive_thr[u] : 0u;
+                            if (thr != 0u || p.sigma != 0.0f) {
+                                const uint4 r = philox4x32_10(make_uint4(static_cast<uint32_t>(a.caller_of ? a.caller_of[u] - nm.node_off : jj), static_cast<uint32_t>(t),
+                                                                  static_cast<uint32_t>(static_cast<uint64_t>(t) >> 32), 0u),
+                                                       p.key_lo, p.key_hi);
+                                if (r.x < thr) uu += p.drive_amp;
+                                if (p.sigma != 0.0f) noise = p.sigma * gaussian(r.y, r.z);
+                            }
                         }
                         vn = v + p.decay * (p.v_rest - v) + in + uu + noise;
                     }
@@ -2110,6 +2136,7 @@ hipError_t launch_ensemble(const DeviceGraph& g, const EnsemblePlan& plan, int64
     a.sbits = g.ens_sbits;
     a.push_off = g.push_off;
     a.push_edge = g.push_edge;
+    a.drv = g.ens_drv;
     const int m = g.hh_m ? 2 : (g.Vd ? 1 : 0);
     const int k = plan.held ? kEnsHeld : (g.ens_sbits < 16 ? kEnsPacked : kEnsLocal);
     if (k != kEnsHeld && !g.ens_ls) return hipErrorInvalidValue;
