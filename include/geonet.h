@@ -67,7 +67,7 @@ typedef enum {
     NET_E_OOM = -3,         /* device allocation failed */
     NET_E_DEVICE = -4,      /* HIP runtime or kernel error */
     NET_E_STATE = -5,       /* handle unusable after an earlier device error */
-    NET_E_UNSUPPORTED = -6  /* request outside what this build supports */
+    NET_E_UNSUPPORTED = -6  /* request outside what the library supports */
 } net_status;
 
 /*
