@@ -81,3 +81,29 @@ def test_reorder_izhikevich():
     _same(a, b)
     a["net"].close()
     b["net"].close()
+
+
+def test_reorder_noise_free_driven_ensemble():
+    """Noise-free LIF networks draw their drive pulses for the driven
+    vertices alone, keyed by the caller's vertex index: renumbered and plain
+    builds of the same ensemble give the same records, and each network
+    matches its oracle run."""
+    import paper_0908_3934_amd as gn
+    specs = []
+    for k, n in enumerate([64, 1500, 257]):
+        s = synth.config0_like(n, synth.config_seed(0, 930 + k), w0=0.36)
+        s.drive_rate_hz = np.where(np.asarray(s.drive_rate_hz) > 0, 200.0, 0.0).astype(np.float32)
+        specs.append(fx.relabel(s, 91 + k))
+    T = 2000
+    a = run_gpu(specs, T)
+    b = run_gpu(specs, T, flags=gn.NET_BUILD_REORDER)
+    assert a["net"].info()["ensemble_blocks"] > 0 and b["net"].info()["ensemble_blocks"] > 0
+    _same(a, b)
+    offs = a["net"].node_offsets()
+    for k, s in enumerate(specs):
+        lo, hi = offs[k], offs[k + 1]
+        o = oracle.OracleNet(s).step(T, v=True, inp=True)
+        check_parity({"raster": a["raster"][:, lo:hi], "v": a["v"][:, lo:hi], "input": a["input"][:, lo:hi]}, o)
+        assert o["raster"].sum() > 100
+    a["net"].close()
+    b["net"].close()
